@@ -1,0 +1,220 @@
+/*
+ * ebsd.h -- C ABI of the MI355X (gfx950) demons-based HR-EBSD remapping library.
+ *
+ * Method: Zhu, Kaufmann & Vecchio, "Novel Remapping Approach for HR-EBSD based
+ * on Demons Registration" (arXiv:1907.05993).  For every scan point a test
+ * pattern is registered against its reference pattern by multi-resolution
+ * demons (section 1, Eq. (1)); the displacement field sampled at the ROI
+ * centres gives shifts q (section 2), from which the deformation gradient F is
+ * solved through the projective model of Eq. (2) by minimising Eq. (3); its
+ * rotation R_finite = P Q^T (Eq. (4)-(5)) remaps the reference, a second-pass
+ * ROI cross-correlation (section 2) measures the residual shifts, and
+ * F = F_inf R_finite (Eq. (12)).  The rotation is reported as a rotation vector
+ * (the axis-angle form after Eq. (5), Eq. (6)).
+ *
+ * Conventions
+ *   - Patterns are H x W fp32, row-major, x = column, y = row, pixel centres
+ *     at integers.  Pattern centre: x* = pc_x W - 0.5, y* = pc_y H - 0.5,
+ *     detector distance Z* = pc_z W (px); r(x) = (x - x*, y - y*, Z*),
+ *     k = (0, 0, 1).
+ *   - Displacement field: [2][H][W] fp32 on the reference grid, channel 0
+ *     along x, channel 1 along y, in full-resolution px, defined by
+ *     test(x + u(x)) ~ ref(x); u at a ROI centre is the shift q of Eq. (2).
+ *   - F, R: 3 x 3 row-major fp64 in the detector frame above; det F = 1
+ *     (the shifts fix F only up to scale; the isochoric normalisation stands in
+ *     for the traction-free condition).
+ *
+ * Memory and streams
+ *   - Every pattern, field and result pointer is HIP device memory owned by the
+ *     caller.  The pair array itself is host memory, read during the call.
+ *   - The handle owns its workspace (device memory it allocates and grows on
+ *     demand) and a small pinned staging buffer.  Growing the workspace
+ *     synchronises the device first.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *     stream): outputs are valid once the stream has completed.  A handle is
+ *     used by one host thread at a time.
+ *   - Errors: every call validates all of its arguments before anything is
+ *     enqueued and returns a negative EBSD_E* code (outputs untouched).
+ *     Numerical outcomes never fail a batch: they are reported per pair in
+ *     the status bits.  No exception or abort crosses the ABI.
+ */
+#ifndef EBSD_H
+#define EBSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EBSD_ABI_VERSION 1
+#define EBSD_MAX_LEVELS 8
+
+/* return codes */
+enum {
+    EBSD_OK = 0,
+    EBSD_EINVAL = -1,   /* bad argument (NULL pointer, n < 0, bad parameter value) */
+    EBSD_ESHAPE = -2,   /* pattern size not supported (too small, not divisible by 2^(levels-1)) */
+    EBSD_EROI = -3,     /* a ROI falls outside the pattern, or ROI size is not 32/64/128 */
+    EBSD_ENOMEM = -4,   /* device or pinned allocation failed */
+    EBSD_EDEVICE = -5,  /* a HIP runtime call failed */
+    EBSD_ENOTSUP = -6,  /* feature not available in this build */
+    EBSD_EVERSION = -8  /* ebsd_params.struct_size does not match this library */
+};
+
+/* per-pair status bits */
+enum {
+    EBSD_CONVERGED = 1,         /* tol > 0 and every level stopped on the tolerance */
+    EBSD_HIT_CAP = 2,           /* tol > 0 and some level ran to its iteration cap */
+    EBSD_SOLVE_ILLCOND = 16,    /* an Eq. (3) solve was ill-conditioned (cond(J^T J) > 1e12) */
+    EBSD_NONFINITE_INPUT = 32,  /* a pattern held NaN/Inf (treated as all-zero) */
+    EBSD_DEGENERATE_INPUT = 64  /* a pattern had no contrast (treated as all-zero) */
+};
+
+typedef struct ebsd_params {
+    uint32_t struct_size;                 /* sizeof(ebsd_params) */
+    int32_t levels;                       /* pyramid levels, 1..8 (multi-resolution demons) */
+    int32_t max_iters[EBSD_MAX_LEVELS];   /* demons iterations per level, [0] = finest */
+    float sigma_px;                       /* Gaussian smoothing of the accumulated field, 0 <= sigma <= 1.3 */
+    float tol_px;                         /* stop a level when 2^l RMS|u_new - u| < tol (full-res px); 0 = fixed count */
+    float pc_x, pc_y, pc_z;               /* pattern centre fractions */
+    int32_t n_roi;                        /* ROIs: 1 at the pattern centre + (n_roi - 1) on a ring, 5..256 */
+    int32_t roi_size;                     /* 32, 64 or 128 */
+    float roi_radius_frac;                /* ring radius / W */
+    int32_t window;                       /* 1 = Hann window on each ROI (section 2), 0 = none */
+    int32_t second_pass;                  /* 1 = remap + XCF second pass (Eq. (12)); 0 = demons only */
+} ebsd_params;
+
+/* One scan point.  ref/test: device pointers to H x W fp32 patterns.  Pairs
+ * with the same ref_id >= 0 share one reference (same pointer and size) whose
+ * pyramid is built once; ref_id < 0 means "not shared". */
+typedef struct ebsd_pair {
+    const float* ref;
+    const float* test;
+    int32_t H, W;
+    int32_t ref_id;
+} ebsd_pair;
+
+/* Outputs (device memory, caller-allocated; any pointer may be NULL). */
+typedef struct ebsd_outputs {
+    float* field;               /* final displacement field, [2][H][W] per pair, full-res px */
+    const int64_t* field_offset;/* HOST array [n]: float offset of pair i's field; NULL = i*2*H*W */
+    double* F;                  /* [n][9] total deformation gradient, det F = 1 (Eq. (12)) */
+    double* R;                  /* [n][9] rotation of F (Eq. (4)-(5)) */
+    double* rotvec;             /* [n][3] rotation vector theta*m, rad */
+    double* R_finite;           /* [n][9] first-pass rotation used for the remap */
+    double* F_first;            /* [n][9] first-pass deformation gradient (det 1) */
+    float* q1;                  /* [n][n_roi][2] first-pass shifts (field at ROI centres) */
+    float* q2;                  /* [n][n_roi][2] second-pass XCF shifts */
+    float* peak_height;         /* [n][n_roi] normalised XCF peak height */
+    int32_t* iters;             /* [n][levels] demons iterations run per level */
+    uint32_t* status;           /* [n] status bits */
+} ebsd_outputs;
+
+/* Library ABI version (EBSD_ABI_VERSION). */
+int ebsd_version(void);
+
+/* Fill *p with the defaults: 3 levels x 150 iterations, sigma 1 px, tol 0,
+ * pattern centre (0.5, 0.5, 0.7), 20 ROIs of 64 px on a ring of 0.3 W, Hann
+ * window, second pass on.  Returns EBSD_OK or EBSD_EINVAL (p == NULL). */
+int ebsd_params_default(ebsd_params* p);
+
+/* Human-readable text of a return code (static storage). */
+const char* ebsd_strerror(int code);
+
+typedef struct ebsd_handle ebsd_handle;
+
+/* Create a handle bound to HIP device `device` with parameters *p (copied).
+ * Returns EBSD_EVERSION if p->struct_size != sizeof(ebsd_params),
+ * EBSD_EINVAL for an invalid parameter, EBSD_EDEVICE if the device cannot be
+ * selected.  On success *out receives the handle (no device memory yet). */
+int ebsd_create(const ebsd_params* p, int device, ebsd_handle** out);
+
+/* Release the handle, its workspace and staging buffers after synchronising
+ * the device.  NULL is accepted. */
+int ebsd_destroy(ebsd_handle* h);
+
+/* Copy the handle's parameters into *out. */
+int ebsd_get_params(const ebsd_handle* h, ebsd_params* out);
+
+/* ROI layout used by the handle's parameters for an H x W pattern (section 2:
+ * ROIs evenly spaced on a ring around the pattern centre plus one at the
+ * centre).  ROI 0 is at the pattern centre, ROI j >= 1 at angle
+ * 2 pi (j-1)/(n_roi-1) from +x toward +y on a ring of radius frac W; top-left
+ * x0 = floor(c - (N-1)/2 + 0.5); the centre used in Eq. (2) is x0 + (N-1)/2.
+ * cx, cy (double) and x0, y0 are HOST arrays of n_roi entries (any may be
+ * NULL).  Returns EBSD_EROI if a ROI leaves the pattern. */
+int ebsd_roi_layout(const ebsd_params* p, int32_t H, int32_t W, double* cx, double* cy,
+                    int32_t* x0, int32_t* y0);
+
+/* The whole path for n pairs: per-pattern normalisation, pyramids, demons
+ * (Eq. (1)) coarse to fine, q1 at the ROI centres, F_first by Eq. (3),
+ * R_finite = polar(F_first) (Eq. (4)-(5)), remap + ROI XCF (section 2), F_inf
+ * by Eq. (3), F = F_inf R_finite (Eq. (12)), R = polar(F), rotation vector.
+ * pairs: HOST array of n descriptors (device pattern pointers); pairs of
+ * different sizes are processed in size buckets, in order of first
+ * appearance.  n == 0 is a no-op.  stream: hipStream_t or NULL. */
+int ebsd_register_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
+                        const ebsd_outputs* out, void* stream);
+
+/* Same as ebsd_register_batch, but demons starts on the coarsest level from
+ * the caller's field u_init (device, [n][2][H/2^(L-1)][W/2^(L-1)] fp32, in
+ * full-resolution px) instead of zero: the warm start.  All pairs must have
+ * the same size.  u_init == NULL behaves as ebsd_register_batch. */
+int ebsd_register_batch_init(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
+                             const float* u_init, const ebsd_outputs* out, void* stream);
+
+/* Second pass only (section 2, Eq. (12)): remap each reference by the
+ * caller's R_finite (device, [n][9] fp64, row-major), ROI XCF against the
+ * test, F_inf by Eq. (3), F = F_inf R_finite, det F = 1, R, rotation vector.
+ * Fills F, R, rotvec, q2, peak_height, status (and copies R_finite) of out. */
+int ebsd_second_pass_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
+                           const double* R_finite, const ebsd_outputs* out, void* stream);
+
+/* ---- single-stage entry points (one kernel each; device pointers) ------- */
+
+/* z-score each of n contiguous patterns of `elems` fp32 values:
+ * out = (in - mean) / std (population std, FP64 statistics).  flags (device,
+ * [n] uint32, may be NULL) receive EBSD_DEGENERATE_INPUT / EBSD_NONFINITE_INPUT;
+ * such patterns are written as zeros. */
+int ebsd_stage_normalize(const float* in, int32_t n, int64_t elems, float* out, uint32_t* flags,
+                         void* stream);
+
+/* Factor-2 restriction of n images [n][H][W] -> [n][H/2][W/2] with the
+ * separable [1,3,3,1]/8 filter, clamped borders (H, W even). */
+int ebsd_stage_restrict(const float* in, int32_t n, int32_t H, int32_t W, float* out, void* stream);
+
+/* One demons iteration (Eq. (1) force with the reference gradient, then
+ * Gaussian smoothing of the accumulated field with sigma_px) for n image
+ * pairs at one level: R, T [n][H][W] (normalised), u_in, u_out [n][2][H][W]
+ * in px of this level (u_in != u_out).  rms (device, [n] fp64, may be NULL)
+ * receives RMS|u_out - u_in| per pair. */
+int ebsd_stage_demons_iter(const float* R, const float* T, int32_t n, int32_t H, int32_t W,
+                           const float* u_in, float sigma_px, float* u_out, double* rms,
+                           void* stream);
+
+/* Field prolongation [n][2][h][w] -> [n][2][2h][2w]: bilinear with the
+ * half-pixel-centre map, values doubled. */
+int ebsd_stage_prolong(const float* u, int32_t n, int32_t h, int32_t w, float* out, void* stream);
+
+/* ROI cross-correlation of n ROI pairs (section 2): A (reference) and B
+ * (test), [n][N][N] fp32, N in {32, 64, 128}; per-ROI zero mean, optional
+ * Hann window, C = IFFT(FFT(B w) conj FFT(A w)), integer peak (ties to the
+ * lowest row-major index), 2-D quadratic sub-pixel fit.  q: [n][2] (x, y)
+ * shift of B relative to A; ph: [n] normalised peak height (may be NULL). */
+int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t window, float* q,
+                   float* ph, void* stream);
+
+/* Eq. (3) solve for n shift sets: q [n][n_roi][2] fp32 at ROI centres
+ * cx, cy (device, [n_roi] fp64), pattern centre (xs, ys, zs) in px.
+ * Writes F [n][9] (det 1) and, if R != NULL, R = polar(F) [n][9] (fp64);
+ * status [n] may be NULL. */
+int ebsd_stage_solve(const float* q, int32_t n, int32_t n_roi, const double* cx, const double* cy,
+                     double xs, double ys, double zs, double* F, double* R, uint32_t* status,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBSD_H */

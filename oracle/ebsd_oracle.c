@@ -1,0 +1,1005 @@
+/*
+ * ebsd_oracle.c -- plain, slow, FP64 CPU oracle for demons-based HR-EBSD
+ * remapping (Zhu, Kaufmann & Vecchio, "Novel Remapping Approach for HR-EBSD
+ * based on Demons Registration", arXiv:1907.05993).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library and its
+ * Python binding) may include, link, load or call this file.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark use it.
+ * It shares no code, header, table or constant generator with the GPU path.
+ *
+ * Everything is computed in double precision with plain loops, in the order
+ * the method states it, so that it can be checked against the paper by eye:
+ *
+ *   normalise        z-score per pattern (zero mean as in section 2)
+ *   pyramid          factor-2 restriction, [1,3,3,1]/8 separable filter
+ *   demons           Eq. (1) force, iterated per level, coarse to fine
+ *                    (multi-resolution demons, section 1)
+ *   shifts           field sampled at the ROI centres (section 2)
+ *   F solve          Eq. (2)/(3) projective model, DLT + Gauss-Newton
+ *   polar            Eq. (4)/(5): F = P D Q^T, R = P Q^T
+ *   remap            reference remapped by R_finite (section 2, before Eq. 12)
+ *   XCF              zero mean, Hann window, FFT, F_test . conj(F_ref), IFFT,
+ *                    interpolated peak (section 2)
+ *   compose          Eq. (12): F = F_inf R_finite
+ *   rotation vector  axis-angle of R (the passage after Eq. 5, Eq. 6)
+ *
+ * Readings where the paper is silent or ambiguous (sign of the force, which
+ * gradient, smoothing, ROI layout, sub-pixel estimator, determinant
+ * normalisation in place of the traction-free condition) are listed in the
+ * design notes and restated at each function below.
+ *
+ * Pins: every function here is checked by tests that do not use this file's
+ * arithmetic (numpy/scipy routines, brute-force DFT, closed forms and
+ * invariants).  The whole demons loop beyond those invariants is
+ * "parity unpinned" except through the identical-pair and known-shift cases.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_CONVERGED 1u
+#define ORC_HIT_CAP 2u
+#define ORC_SOLVE_ILLCOND 16u
+#define ORC_NONFINITE_INPUT 32u
+#define ORC_DEGENERATE_INPUT 64u
+
+#define ORC_MAX_LEVELS 8
+
+/* Parameters of one registration (mirrored by a ctypes Structure). */
+typedef struct {
+    int32_t levels;
+    int32_t max_iters[ORC_MAX_LEVELS]; /* [0] = finest level */
+    double sigma;                      /* Gaussian smoothing of the field, px; 0 = none */
+    double tol;                        /* RMS field update in full-res px; 0 = fixed count */
+    double pc_x, pc_y, pc_z;           /* pattern centre as fractions (x*, y* of W, H; Z* of W) */
+    int32_t n_roi;                     /* 1 at the pattern centre + (n_roi-1) on a ring */
+    int32_t roi_size;                  /* power of two */
+    double roi_radius_frac;            /* ring radius / W */
+    int32_t window;                    /* 1 = Hann window, 0 = none */
+    int32_t second_pass;               /* 1 = remap + XCF second pass */
+} orc_params;
+
+/* ------------------------------------------------------------------------ */
+/* small helpers                                                             */
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* ------------------------------------------------------------------------ */
+/* Normalisation.  The paper zero-means the pattern before cross-correlation
+ * (section 2); the oracle z-scores each pattern (population std) before
+ * every stage.  Returns ORC_DEGENERATE_INPUT (and writes zeros) when the
+ * pattern has no contrast, ORC_NONFINITE_INPUT when it holds NaN/Inf.      */
+uint32_t orc_normalize(const float* in, int64_t n, double* out)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double v = (double)in[i];
+        if (!isfinite(v)) {
+            for (int64_t j = 0; j < n; j++) out[j] = 0.0;
+            return ORC_NONFINITE_INPUT;
+        }
+        s += v;
+    }
+    double mean = s / (double)n;
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double d = (double)in[i] - mean;
+        ss += d * d;
+    }
+    double sd = sqrt(ss / (double)n);
+    if (!(sd > 1e-12 * (fabs(mean) + 1.0))) {
+        for (int64_t i = 0; i < n; i++) out[i] = 0.0;
+        return ORC_DEGENERATE_INPUT;
+    }
+    for (int64_t i = 0; i < n; i++) out[i] = ((double)in[i] - mean) / sd;
+    return 0u;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pyramid restriction (multi-resolution demons, section 1; the paper gives
+ * neither factor nor filter).  Factor 2, separable [1,3,3,1]/8 filter with
+ * clamped borders, so that coarse pixel i is centred on fine 2i + 0.5:
+ *   out[i] = (in[c(2i-1)] + 3 in[2i] + 3 in[2i+1] + in[c(2i+2)]) / 8.     */
+void orc_restrict(const double* in, int H, int W, double* out)
+{
+    int h = H / 2, w = W / 2;
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)H * (size_t)w);
+    for (int y = 0; y < H; y++) {
+        const double* row = in + (size_t)y * W;
+        for (int i = 0; i < w; i++) {
+            double a = row[clampi(2 * i - 1, 0, W - 1)];
+            double b = row[2 * i];
+            double c = row[2 * i + 1];
+            double d = row[clampi(2 * i + 2, 0, W - 1)];
+            tmp[(size_t)y * w + i] = (a + 3.0 * b + 3.0 * c + d) / 8.0;
+        }
+    }
+    for (int j = 0; j < h; j++) {
+        for (int x = 0; x < w; x++) {
+            double a = tmp[(size_t)clampi(2 * j - 1, 0, H - 1) * w + x];
+            double b = tmp[(size_t)(2 * j) * w + x];
+            double c = tmp[(size_t)(2 * j + 1) * w + x];
+            double d = tmp[(size_t)clampi(2 * j + 2, 0, H - 1) * w + x];
+            out[(size_t)j * w + x] = (a + 3.0 * b + 3.0 * c + d) / 8.0;
+        }
+    }
+    free(tmp);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Image gradient used by the demons force of Eq. (1): central differences in
+ * the interior, one-sided differences on the border rows/columns.          */
+void orc_gradient(const double* f, int H, int W, double* gx, double* gy)
+{
+    for (int y = 0; y < H; y++) {
+        for (int x = 0; x < W; x++) {
+            size_t i = (size_t)y * W + x;
+            double dx, dy;
+            if (W == 1) dx = 0.0;
+            else if (x == 0) dx = f[i + 1] - f[i];
+            else if (x == W - 1) dx = f[i] - f[i - 1];
+            else dx = (f[i + 1] - f[i - 1]) / 2.0;
+            if (H == 1) dy = 0.0;
+            else if (y == 0) dy = f[i + W] - f[i];
+            else if (y == H - 1) dy = f[i] - f[i - W];
+            else dy = (f[i + W] - f[i - W]) / 2.0;
+            gx[i] = dx;
+            gy[i] = dy;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bilinear sample of img (H x W, pixel centres at integers, x = column) at
+ * (x, y).  Coordinates are clamped to [0, W-1] x [0, H-1] before the floor,
+ * i.e. the image is extended by replicating its border.                    */
+double orc_bilinear(const double* img, int H, int W, double x, double y)
+{
+    double xc = clampd(x, 0.0, (double)(W - 1));
+    double yc = clampd(y, 0.0, (double)(H - 1));
+    int x0 = (int)floor(xc), y0 = (int)floor(yc);
+    double fx = xc - (double)x0, fy = yc - (double)y0;
+    int x1 = x0 + 1 < W ? x0 + 1 : W - 1;
+    int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
+    double v00 = img[(size_t)y0 * W + x0], v01 = img[(size_t)y0 * W + x1];
+    double v10 = img[(size_t)y1 * W + x0], v11 = img[(size_t)y1 * W + x1];
+    double top = (1.0 - fx) * v00 + fx * v01;
+    double bot = (1.0 - fx) * v10 + fx * v11;
+    return (1.0 - fy) * top + fy * bot;
+}
+
+void orc_bilinear_points(const double* img, int H, int W, const double* xs,
+                         const double* ys, int64_t n, double* out)
+{
+    for (int64_t i = 0; i < n; i++) out[i] = orc_bilinear(img, H, W, xs[i], ys[i]);
+}
+
+/* Warp: out(x) = img(x + u(x)), u = [2][H][W] (channel 0 along columns). */
+void orc_warp(const double* img, int H, int W, const double* u, double* out)
+{
+    size_t HW = (size_t)H * W;
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            size_t i = (size_t)y * W + x;
+            out[i] = orc_bilinear(img, H, W, (double)x + u[i], (double)y + u[HW + i]);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gaussian smoothing of one field channel: separable taps
+ * w_j = exp(-j^2 / (2 sigma^2)), j = -r..r, r = floor(3 sigma + 0.5),
+ * normalised to unit sum; the border is replicated.  sigma <= 0 copies.    */
+void orc_smooth(const double* v, int H, int W, double sigma, double* out)
+{
+    size_t HW = (size_t)H * W;
+    if (!(sigma > 0.0)) {
+        memcpy(out, v, sizeof(double) * HW);
+        return;
+    }
+    int r = (int)floor(3.0 * sigma + 0.5);
+    double* w = (double*)malloc(sizeof(double) * (size_t)(2 * r + 1));
+    double sum = 0.0;
+    for (int j = -r; j <= r; j++) {
+        w[j + r] = exp(-(double)(j * j) / (2.0 * sigma * sigma));
+        sum += w[j + r];
+    }
+    for (int j = 0; j <= 2 * r; j++) w[j] /= sum;
+    double* tmp = (double*)malloc(sizeof(double) * HW);
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            double acc = 0.0;
+            for (int j = -r; j <= r; j++)
+                acc += w[j + r] * v[(size_t)y * W + clampi(x + j, 0, W - 1)];
+            tmp[(size_t)y * W + x] = acc;
+        }
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            double acc = 0.0;
+            for (int j = -r; j <= r; j++)
+                acc += w[j + r] * tmp[(size_t)clampi(y + j, 0, H - 1) * W + x];
+            out[(size_t)y * W + x] = acc;
+        }
+    free(tmp);
+    free(w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One demons iteration at one pyramid level (Eq. (1), Thirion's force).
+ *
+ * Field convention: u lives on the reference grid and T(x + u(x)) ~ R(x),
+ * so that u at a ROI centre is the shift q of Eq. (2).  With a = R - T(x+u)
+ * the update is du = a grad(R) / (|grad R|^2 + a^2), the Eq. (1) force with
+ * the intensity difference taken reference-minus-warped-test (the opposite
+ * order to the printed Eq. (1), which belongs to the opposite field
+ * direction), and the gradient taken on the fixed reference image as
+ * Eq. (1)'s symbol says.  0/0 (den <= 1e-9) gives du = 0.
+ *
+ * The accumulated field is then smoothed (the paper applies none; sigma = 0
+ * reproduces that).  Returns RMS over pixels of |u_new - u| in level px.  */
+double orc_demons_iter(const double* R, const double* T, const double* gx,
+                       const double* gy, int H, int W, const double* u,
+                       double sigma, double* u_new)
+{
+    size_t HW = (size_t)H * W;
+    double* v = (double*)malloc(sizeof(double) * 2 * HW);
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            size_t i = (size_t)y * W + x;
+            double wv = orc_bilinear(T, H, W, (double)x + u[i], (double)y + u[HW + i]);
+            double a = R[i] - wv;
+            double den = gx[i] * gx[i] + gy[i] * gy[i] + a * a;
+            double dux = 0.0, duy = 0.0;
+            if (den > 1e-9) {
+                dux = a * gx[i] / den;
+                duy = a * gy[i] / den;
+            }
+            v[i] = u[i] + dux;
+            v[HW + i] = u[HW + i] + duy;
+        }
+    orc_smooth(v, H, W, sigma, u_new);
+    orc_smooth(v + HW, H, W, sigma, u_new + HW);
+    double ss = 0.0;
+    for (size_t i = 0; i < HW; i++) {
+        double dx = u_new[i] - u[i], dy = u_new[HW + i] - u[HW + i];
+        ss += dx * dx + dy * dy;
+    }
+    free(v);
+    return sqrt(ss / (double)HW);
+}
+
+/* Prolongation of the field to the next finer level: bilinear with the
+ * half-pixel-centre map (fine i -> coarse (i - 0.5)/2), values doubled
+ * because the field is measured in the pixels of its level.               */
+void orc_prolong(const double* u, int h, int w, double* out)
+{
+    int H = 2 * h, W = 2 * w;
+    size_t hw = (size_t)h * w, HW = (size_t)H * W;
+    for (int c = 0; c < 2; c++)
+        for (int y = 0; y < H; y++)
+            for (int x = 0; x < W; x++)
+                out[(size_t)c * HW + (size_t)y * W + x] =
+                    2.0 * orc_bilinear(u + (size_t)c * hw, h, w, ((double)x - 0.5) / 2.0,
+                                       ((double)y - 0.5) / 2.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multi-resolution demons (section 1): the field found on the coarser level
+ * initialises the next finer level.  Rn/Tn are the normalised full-res
+ * images.  u_init, if not NULL, is the initial field on the coarsest level
+ * (in that level's px).  Writes the finest field [2][H][W] and per-level
+ * iteration counts.  Returns ORC_CONVERGED when every level stopped on the
+ * tolerance, ORC_HIT_CAP when a level ran to its cap with tol > 0.       */
+uint32_t orc_demons(const double* Rn, const double* Tn, int H, int W, const orc_params* p,
+                    const double* u_init, double* field, int32_t* iters)
+{
+    int L = p->levels;
+    const double* Rl[ORC_MAX_LEVELS];
+    const double* Tl[ORC_MAX_LEVELS];
+    double* own[2 * ORC_MAX_LEVELS];
+    int nown = 0;
+    int Hs[ORC_MAX_LEVELS], Ws[ORC_MAX_LEVELS];
+    Rl[0] = Rn;
+    Tl[0] = Tn;
+    Hs[0] = H;
+    Ws[0] = W;
+    for (int l = 1; l < L; l++) {
+        Hs[l] = Hs[l - 1] / 2;
+        Ws[l] = Ws[l - 1] / 2;
+        double* r = (double*)malloc(sizeof(double) * (size_t)Hs[l] * Ws[l]);
+        double* t = (double*)malloc(sizeof(double) * (size_t)Hs[l] * Ws[l]);
+        orc_restrict(Rl[l - 1], Hs[l - 1], Ws[l - 1], r);
+        orc_restrict(Tl[l - 1], Hs[l - 1], Ws[l - 1], t);
+        Rl[l] = r;
+        Tl[l] = t;
+        own[nown++] = r;
+        own[nown++] = t;
+    }
+    size_t HW0 = (size_t)H * W;
+    double* ua = (double*)calloc(2 * HW0, sizeof(double));
+    double* ub = (double*)calloc(2 * HW0, sizeof(double));
+    double* gx = (double*)malloc(sizeof(double) * HW0);
+    double* gy = (double*)malloc(sizeof(double) * HW0);
+    {
+        size_t n = 2 * (size_t)Hs[L - 1] * Ws[L - 1];
+        if (u_init)
+            memcpy(ua, u_init, sizeof(double) * n);
+    }
+    uint32_t status = 0;
+    int all_conv = 1, any_cap = 0;
+    for (int l = L - 1; l >= 0; l--) {
+        int h = Hs[l], w = Ws[l];
+        orc_gradient(Rl[l], h, w, gx, gy);
+        double scale = (double)(1 << l);
+        int k = 0, conv = 0;
+        while (k < p->max_iters[l]) {
+            double rms = orc_demons_iter(Rl[l], Tl[l], gx, gy, h, w, ua, p->sigma, ub);
+            double* t = ua;
+            ua = ub;
+            ub = t;
+            k++;
+            if (p->tol > 0.0 && scale * rms < p->tol) {
+                conv = 1;
+                break;
+            }
+        }
+        iters[l] = k;
+        if (!conv) all_conv = 0;
+        if (!conv && p->tol > 0.0) any_cap = 1;
+        if (l > 0) {
+            orc_prolong(ua, h, w, ub);
+            double* t = ua;
+            ua = ub;
+            ub = t;
+        }
+    }
+    memcpy(field, ua, sizeof(double) * 2 * HW0);
+    if (p->tol > 0.0 && all_conv) status |= ORC_CONVERGED;
+    if (any_cap) status |= ORC_HIT_CAP;
+    free(ua);
+    free(ub);
+    free(gx);
+    free(gy);
+    for (int i = 0; i < nown; i++) free(own[i]);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ROI layout (section 2: ROIs evenly spaced around the pattern centre plus
+ * one at the centre).  ROI 0 sits at the pattern centre, ROIs 1..n-1 on a
+ * ring of radius frac*W at angles 2 pi j/(n-1), measured from +x toward +y.
+ * Top-left corner x0 = floor(cx - (N-1)/2 + 0.5); the actual centre used in
+ * Eq. (2) is x0 + (N-1)/2.  Returns 0 if all ROIs are inside the pattern. */
+int orc_roi_layout(int H, int W, const orc_params* p, double* cx, double* cy,
+                   int32_t* x0, int32_t* y0)
+{
+    const double pi = 3.14159265358979323846;
+    double xs = p->pc_x * W - 0.5, ys = p->pc_y * H - 0.5;
+    double rho = p->roi_radius_frac * W;
+    int N = p->roi_size;
+    int bad = 0;
+    for (int j = 0; j < p->n_roi; j++) {
+        double px = xs, py = ys;
+        if (j > 0) {
+            double ang = 2.0 * pi * (double)(j - 1) / (double)(p->n_roi - 1);
+            px = xs + rho * cos(ang);
+            py = ys + rho * sin(ang);
+        }
+        int ix = (int)floor(px - (N - 1) / 2.0 + 0.5);
+        int iy = (int)floor(py - (N - 1) / 2.0 + 0.5);
+        x0[j] = ix;
+        y0[j] = iy;
+        cx[j] = ix + (N - 1) / 2.0;
+        cy[j] = iy + (N - 1) / 2.0;
+        if (ix < 0 || iy < 0 || ix + N > W || iy + N > H) bad = 1;
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense linear algebra for the small solves (textbook methods).            */
+
+/* Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix A (row-major,
+ * destroyed).  On exit evals[i] are the eigenvalues and column i of V
+ * (row-major n x n) the matching unit eigenvector.  Golub & Van Loan,
+ * "Matrix Computations", symmetric Schur rotations.                         */
+void orc_jacobi_eig(double* A, int n, double* evals, double* V)
+{
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; sweep++) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) {
+                tot += A[i * n + j] * A[i * n + j];
+                if (i != j) off += A[i * n + j] * A[i * n + j];
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n - 1; p++)
+            for (int q = p + 1; q < n; q++) {
+                double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                /* A <- J^T A J with J the (p,q) rotation [c s; -s c] */
+                for (int k = 0; k < n; k++) {
+                    double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; k++) {
+                    double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; k++) {
+                    double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - s * vkq;
+                    V[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < n; i++) evals[i] = A[i * n + i];
+}
+
+/* Solve A x = b (n x n, row-major, both destroyed) by Gaussian elimination
+ * with partial pivoting.  Returns 0 on success, 1 if a pivot is zero.     */
+static int orc_gauss_solve(double* A, double* b, int n, double* x)
+{
+    for (int k = 0; k < n; k++) {
+        int piv = k;
+        for (int i = k + 1; i < n; i++)
+            if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+        if (A[piv * n + k] == 0.0) return 1;
+        if (piv != k) {
+            for (int j = 0; j < n; j++) {
+                double t = A[k * n + j];
+                A[k * n + j] = A[piv * n + j];
+                A[piv * n + j] = t;
+            }
+            double t = b[k];
+            b[k] = b[piv];
+            b[piv] = t;
+        }
+        for (int i = k + 1; i < n; i++) {
+            double m = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; j++) A[i * n + j] -= m * A[k * n + j];
+            b[i] -= m * b[k];
+        }
+    }
+    for (int i = n - 1; i >= 0; i--) {
+        double s = b[i];
+        for (int j = i + 1; j < n; j++) s -= A[i * n + j] * x[j];
+        x[i] = s / A[i * n + i];
+    }
+    return 0;
+}
+
+static double det3(const double* F)
+{
+    return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+           F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+static void matmul3(const double* A, const double* B, double* C)
+{
+    double t[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += A[i * 3 + k] * B[k * 3 + j];
+            t[i * 3 + j] = s;
+        }
+    memcpy(C, t, sizeof t);
+}
+
+/* F <- F / cbrt(det F): the isochoric normalisation that stands in for the
+ * traction-free condition (the shifts fix F only up to scale).             */
+void orc_det_normalize(double* F)
+{
+    double d = det3(F);
+    double s = cbrt(d);
+    for (int i = 0; i < 9; i++) F[i] /= s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Deformation gradient from ROI shifts: the minimiser of Eq. (3) for the
+ * projective model of Eq. (2),  r' = r + q = Z* F r / ((F r) . k).
+ * r_i = (cx_i - x*, cy_i - y*, Z*), k = (0,0,1); positions in units of Z*.
+ *   1. DLT start: smallest right singular vector of the 2n x 9 system
+ *      F1.r - p_x F3.r = 0, F2.r - p_y F3.r = 0 (via eigen of A^T A),
+ *      scaled to F33 = 1;
+ *   2. Gauss-Newton on the 8 free entries (F33 = 1) with Eq. (3)'s
+ *      residuals, stop when |step| < 1e-14 or after 100 steps;
+ *   3. det F = 1.
+ * Returns ORC_SOLVE_ILLCOND when cond(J^T J) > 1e12 or a step fails.       */
+uint32_t orc_solve_F(const double* q, const double* cx, const double* cy, int n,
+                     double xs, double ys, double zs, double* F)
+{
+    uint32_t st = 0;
+    double* rx = (double*)malloc(sizeof(double) * n);
+    double* ry = (double*)malloc(sizeof(double) * n);
+    double* px = (double*)malloc(sizeof(double) * n);
+    double* py = (double*)malloc(sizeof(double) * n);
+    for (int i = 0; i < n; i++) {
+        rx[i] = (cx[i] - xs) / zs;
+        ry[i] = (cy[i] - ys) / zs;
+        px[i] = (cx[i] - xs + q[2 * i]) / zs;
+        py[i] = (cy[i] - ys + q[2 * i + 1]) / zs;
+    }
+    /* 1. DLT */
+    double AtA[81];
+    memset(AtA, 0, sizeof AtA);
+    for (int i = 0; i < n; i++) {
+        double r[3] = {rx[i], ry[i], 1.0};
+        double row1[9] = {r[0], r[1], r[2], 0, 0, 0, -px[i] * r[0], -px[i] * r[1], -px[i] * r[2]};
+        double row2[9] = {0, 0, 0, r[0], r[1], r[2], -py[i] * r[0], -py[i] * r[1], -py[i] * r[2]};
+        for (int a = 0; a < 9; a++)
+            for (int b = 0; b < 9; b++) AtA[a * 9 + b] += row1[a] * row1[b] + row2[a] * row2[b];
+    }
+    double ev[9], V[81];
+    orc_jacobi_eig(AtA, 9, ev, V);
+    int imin = 0;
+    for (int i = 1; i < 9; i++)
+        if (ev[i] < ev[imin]) imin = i;
+    double f[9];
+    for (int i = 0; i < 9; i++) f[i] = V[i * 9 + imin];
+    double s33 = f[8];
+    if (s33 == 0.0) {
+        st |= ORC_SOLVE_ILLCOND;
+        s33 = 1.0;
+    }
+    for (int i = 0; i < 9; i++) f[i] /= s33;
+
+    /* 2. Gauss-Newton on theta = (F11,F12,F13,F21,F22,F23,F31,F32), F33 = 1 */
+    double JtJ[64], Jte[8];
+    for (int it = 0; it < 100; it++) {
+        memset(JtJ, 0, sizeof JtJ);
+        memset(Jte, 0, sizeof Jte);
+        for (int i = 0; i < n; i++) {
+            double r[3] = {rx[i], ry[i], 1.0};
+            double n1 = f[0] * r[0] + f[1] * r[1] + f[2] * r[2];
+            double n2 = f[3] * r[0] + f[4] * r[1] + f[5] * r[2];
+            double d = f[6] * r[0] + f[7] * r[1] + f[8] * r[2];
+            double ex = n1 / d - px[i], ey = n2 / d - py[i];
+            double jx[8] = {r[0] / d, r[1] / d, r[2] / d, 0, 0, 0, -n1 * r[0] / (d * d), -n1 * r[1] / (d * d)};
+            double jy[8] = {0, 0, 0, r[0] / d, r[1] / d, r[2] / d, -n2 * r[0] / (d * d), -n2 * r[1] / (d * d)};
+            for (int a = 0; a < 8; a++) {
+                Jte[a] += jx[a] * ex + jy[a] * ey;
+                for (int b = 0; b < 8; b++) JtJ[a * 8 + b] += jx[a] * jx[b] + jy[a] * jy[b];
+            }
+        }
+        double A[64], rhs[8], step[8];
+        memcpy(A, JtJ, sizeof A);
+        for (int a = 0; a < 8; a++) rhs[a] = -Jte[a];
+        if (orc_gauss_solve(A, rhs, 8, step)) {
+            st |= ORC_SOLVE_ILLCOND;
+            break;
+        }
+        double nrm = 0.0;
+        for (int a = 0; a < 8; a++) {
+            f[a] += step[a];
+            nrm += step[a] * step[a];
+        }
+        if (!isfinite(nrm)) {
+            st |= ORC_SOLVE_ILLCOND;
+            break;
+        }
+        if (sqrt(nrm) < 1e-14) break;
+    }
+    /* conditioning at the solution */
+    {
+        memset(JtJ, 0, sizeof JtJ);
+        for (int i = 0; i < n; i++) {
+            double r[3] = {rx[i], ry[i], 1.0};
+            double n1 = f[0] * r[0] + f[1] * r[1] + f[2] * r[2];
+            double n2 = f[3] * r[0] + f[4] * r[1] + f[5] * r[2];
+            double d = f[6] * r[0] + f[7] * r[1] + f[8] * r[2];
+            double jx[8] = {r[0] / d, r[1] / d, r[2] / d, 0, 0, 0, -n1 * r[0] / (d * d), -n1 * r[1] / (d * d)};
+            double jy[8] = {0, 0, 0, r[0] / d, r[1] / d, r[2] / d, -n2 * r[0] / (d * d), -n2 * r[1] / (d * d)};
+            for (int a = 0; a < 8; a++)
+                for (int b = 0; b < 8; b++) JtJ[a * 8 + b] += jx[a] * jx[b] + jy[a] * jy[b];
+        }
+        double e8[8], V8[64];
+        orc_jacobi_eig(JtJ, 8, e8, V8);
+        double lo = e8[0], hi = e8[0];
+        for (int a = 1; a < 8; a++) {
+            if (e8[a] < lo) lo = e8[a];
+            if (e8[a] > hi) hi = e8[a];
+        }
+        if (!(lo > 0.0) || hi / lo > 1e12) st |= ORC_SOLVE_ILLCOND;
+    }
+    memcpy(F, f, sizeof f);
+    if (!(det3(F) > 0.0)) st |= ORC_SOLVE_ILLCOND;
+    else orc_det_normalize(F);
+    free(rx);
+    free(ry);
+    free(px);
+    free(py);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Polar rotation, Eq. (4)-(5): F = P D Q^T (SVD), R = P Q^T.  With the
+ * eigen-decomposition F^T F = Q D^2 Q^T, P = F Q D^-1 and so
+ * R = F Q D^-1 Q^T.  If det R < 0 the last column of P is negated.        */
+void orc_polar(const double* F, double* R)
+{
+    double C[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += F[k * 3 + i] * F[k * 3 + j];
+            C[i * 3 + j] = s;
+        }
+    double ev[3], Q[9];
+    orc_jacobi_eig(C, 3, ev, Q);
+    double P[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += F[i * 3 + k] * Q[k * 3 + j];
+            P[i * 3 + j] = s / sqrt(ev[j]);
+        }
+    /* R = P Q^T */
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += P[i * 3 + k] * Q[j * 3 + k];
+            R[i * 3 + j] = s;
+        }
+    if (det3(R) < 0.0) {
+        /* pick the column of P belonging to the smallest singular value */
+        int kmin = 0;
+        for (int k = 1; k < 3; k++)
+            if (ev[k] < ev[kmin]) kmin = k;
+        for (int i = 0; i < 3; i++) P[i * 3 + kmin] = -P[i * 3 + kmin];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                double s = 0.0;
+                for (int k = 0; k < 3; k++) s += P[i * 3 + k] * Q[j * 3 + k];
+                R[i * 3 + j] = s;
+            }
+    }
+}
+
+/* Axis-angle of R (the passage after Eq. (5)), written with atan2 so small
+ * angles keep their digits: w = (R32-R23, R13-R31, R21-R12)/2 = sin(theta) m,
+ * theta = atan2(|w|, (tr R - 1)/2), rotation vector theta_k = theta m_k.   */
+void orc_rotvec(const double* R, double* rv)
+{
+    double w0 = 0.5 * (R[7] - R[5]);
+    double w1 = 0.5 * (R[2] - R[6]);
+    double w2 = 0.5 * (R[3] - R[1]);
+    double s = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    double th = atan2(s, c);
+    if (s == 0.0) {
+        rv[0] = rv[1] = rv[2] = 0.0;
+        return;
+    }
+    rv[0] = th * w0 / s;
+    rv[1] = th * w1 / s;
+    rv[2] = th * w2 / s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Remap of the reference by R_finite (section 2, before Eq. (12)):
+ * Rm(x') = R0( pi( R_finite^T r(x') ) ), r(x') = (x'-x*, y'-y*, Z*),
+ * pi(v) = (x* + Z* v_x/v_z, y* + Z* v_y/v_z); bilinear with clamping (the
+ * paper remaps with cubic interpolation; bilinear is this build's reading). */
+void orc_remap(const double* ref, int H, int W, const double* Rf, double xs, double ys,
+               double zs, double* out)
+{
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            double r0 = x - xs, r1 = y - ys, r2 = zs;
+            double v0 = Rf[0] * r0 + Rf[3] * r1 + Rf[6] * r2;
+            double v1 = Rf[1] * r0 + Rf[4] * r1 + Rf[7] * r2;
+            double v2 = Rf[2] * r0 + Rf[5] * r1 + Rf[8] * r2;
+            double sx = xs + zs * v0 / v2, sy = ys + zs * v1 / v2;
+            out[(size_t)y * W + x] = orc_bilinear(ref, H, W, sx, sy);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Radix-2 Cooley-Tukey FFT (decimation in time, bit-reversed input order),
+ * forward kernel exp(-2 pi i k n / N); the inverse uses exp(+...) and
+ * divides by N.  N must be a power of two.                                 */
+void orc_fft1(double* re, double* im, int N, int inverse)
+{
+    const double pi = 3.14159265358979323846;
+    for (int i = 1, j = 0; i < N; i++) {
+        int bit = N >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            double t = re[i];
+            re[i] = re[j];
+            re[j] = t;
+            t = im[i];
+            im[i] = im[j];
+            im[j] = t;
+        }
+    }
+    for (int len = 2; len <= N; len <<= 1) {
+        double ang = (inverse ? 2.0 : -2.0) * pi / (double)len;
+        for (int i = 0; i < N; i += len)
+            for (int k = 0; k < len / 2; k++) {
+                double wr = cos(ang * k), wi = sin(ang * k);
+                int a = i + k, b = i + k + len / 2;
+                double xr = re[b] * wr - im[b] * wi;
+                double xi = re[b] * wi + im[b] * wr;
+                re[b] = re[a] - xr;
+                im[b] = im[a] - xi;
+                re[a] += xr;
+                im[a] += xi;
+            }
+    }
+    if (inverse)
+        for (int i = 0; i < N; i++) {
+            re[i] /= (double)N;
+            im[i] /= (double)N;
+        }
+}
+
+/* 2-D FFT of an N x N row-major array: rows, then columns. */
+void orc_fft2(double* re, double* im, int N, int inverse)
+{
+    double* cr = (double*)malloc(sizeof(double) * N);
+    double* ci = (double*)malloc(sizeof(double) * N);
+    for (int y = 0; y < N; y++) orc_fft1(re + (size_t)y * N, im + (size_t)y * N, N, inverse);
+    for (int x = 0; x < N; x++) {
+        for (int y = 0; y < N; y++) {
+            cr[y] = re[(size_t)y * N + x];
+            ci[y] = im[(size_t)y * N + x];
+        }
+        orc_fft1(cr, ci, N, inverse);
+        for (int y = 0; y < N; y++) {
+            re[(size_t)y * N + x] = cr[y];
+            im[(size_t)y * N + x] = ci[y];
+        }
+    }
+    free(cr);
+    free(ci);
+}
+
+/* ------------------------------------------------------------------------ */
+/* ROI cross-correlation and its peak (section 2).
+ *   A = reference ROI, B = test ROI (N x N); each loses its own mean, is
+ *   multiplied by the symmetric Hann window h (x) h, h[n] = 0.5 - 0.5
+ *   cos(2 pi n/(N-1)) (window = 0: no window);
+ *   C = Re IFFT2( FFT2(B w) . conj(FFT2(A w)) ), so B(x) = A(x - s) puts the
+ *   peak at +s;
+ *   integer peak = argmax C, ties to the lowest row-major index; index
+ *   k >= N/2 means k - N;
+ *   sub-pixel ("interpolating the XCF peak"): the 2-D quadratic through the
+ *   3 x 3 circular neighbourhood of the integer peak, with central
+ *   differences g = (dC/dx, dC/dy) and Hessian Hs = [[Cxx, Cxy], [Cxy, Cyy]];
+ *   d = -Hs^-1 g when Hs is negative definite (Cxx < 0, det > 0), each
+ *   component clamped to +-1, else d = 0.  Band-pattern correlation peaks
+ *   are tilted ridges, which per-axis fits mislocate;
+ *   peak height PH = C_max / sqrt(sum (A w)^2 sum (B w)^2).
+ * C (optional) receives the N x N correlation.  q = (x shift, y shift).   */
+void orc_xcf(const double* A, const double* B, int N, int window, double* C, double* q,
+             double* ph)
+{
+    const double pi = 3.14159265358979323846;
+    size_t NN = (size_t)N * N;
+    double* ar = (double*)malloc(sizeof(double) * NN);
+    double* ai = (double*)calloc(NN, sizeof(double));
+    double* br = (double*)malloc(sizeof(double) * NN);
+    double* bi = (double*)calloc(NN, sizeof(double));
+    double* h = (double*)malloc(sizeof(double) * N);
+    for (int n = 0; n < N; n++) h[n] = window ? 0.5 - 0.5 * cos(2.0 * pi * n / (double)(N - 1)) : 1.0;
+    double ma = 0.0, mb = 0.0;
+    for (size_t i = 0; i < NN; i++) {
+        ma += A[i];
+        mb += B[i];
+    }
+    ma /= (double)NN;
+    mb /= (double)NN;
+    double ea = 0.0, eb = 0.0;
+    for (int y = 0; y < N; y++)
+        for (int x = 0; x < N; x++) {
+            size_t i = (size_t)y * N + x;
+            double w = h[y] * h[x];
+            ar[i] = (A[i] - ma) * w;
+            br[i] = (B[i] - mb) * w;
+            ea += ar[i] * ar[i];
+            eb += br[i] * br[i];
+        }
+    orc_fft2(ar, ai, N, 0);
+    orc_fft2(br, bi, N, 0);
+    /* P = FB . conj(FA) */
+    for (size_t i = 0; i < NN; i++) {
+        double pr = br[i] * ar[i] + bi[i] * ai[i];
+        double pi_ = bi[i] * ar[i] - br[i] * ai[i];
+        br[i] = pr;
+        bi[i] = pi_;
+    }
+    orc_fft2(br, bi, N, 1);
+    size_t best = 0;
+    for (size_t i = 1; i < NN; i++)
+        if (br[i] > br[best]) best = i;
+    int ky = (int)(best / N), kx = (int)(best % N);
+    double c0 = br[best];
+#define CAT(dy, dx) br[(size_t)((ky + (dy) + N) % N) * N + (size_t)((kx + (dx) + N) % N)]
+    double gx = 0.5 * (CAT(0, 1) - CAT(0, -1));
+    double gy = 0.5 * (CAT(1, 0) - CAT(-1, 0));
+    double hxx = CAT(0, 1) - 2.0 * c0 + CAT(0, -1);
+    double hyy = CAT(1, 0) - 2.0 * c0 + CAT(-1, 0);
+    double hxy = 0.25 * (CAT(1, 1) - CAT(1, -1) - CAT(-1, 1) + CAT(-1, -1));
+#undef CAT
+    double det = hxx * hyy - hxy * hxy;
+    double dx = 0.0, dy = 0.0;
+    if (hxx < 0.0 && det > 0.0) {
+        dx = clampd(-(hyy * gx - hxy * gy) / det, -1.0, 1.0);
+        dy = clampd(-(hxx * gy - hxy * gx) / det, -1.0, 1.0);
+    }
+    int sx = kx < N / 2 ? kx : kx - N;
+    int sy = ky < N / 2 ? ky : ky - N;
+    q[0] = sx + dx;
+    q[1] = sy + dy;
+    double nrm = sqrt(ea * eb);
+    *ph = nrm > 0.0 ? c0 / nrm : 0.0;
+    if (C) memcpy(C, br, sizeof(double) * NN);
+    free(ar);
+    free(ai);
+    free(br);
+    free(bi);
+    free(h);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole pipeline for one pair.
+ *   demons (first pass) -> q1 at the ROI centres -> F1 (Eq. 3) ->
+ *   R_finite = polar(F1) (Eq. 4-5) -> remap the reference by R_finite ->
+ *   XCF per ROI -> q2 -> F_inf (Eq. 3) -> F = F_inf R_finite (Eq. 12),
+ *   det F = 1 -> R = polar(F) -> rotation vector.
+ * rfin_in (optional) replaces the first pass's R_finite: it lets the second
+ * pass be checked in isolation against another implementation's R_finite.
+ * Any output pointer may be NULL.                                         */
+typedef struct {
+    double* field;   /* [2][H][W] full-res px */
+    double* q1;      /* [n_roi][2] */
+    double* F1;      /* [9] */
+    double* Rfin;    /* [9] */
+    double* q2;      /* [n_roi][2] */
+    double* ph;      /* [n_roi] */
+    double* F;       /* [9] */
+    double* R;       /* [9] */
+    double* rotvec;  /* [3] */
+    int32_t* iters;  /* [levels] */
+    uint32_t* status;
+} orc_outputs;
+
+static void store(double* dst, const double* src, size_t n)
+{
+    if (dst) memcpy(dst, src, sizeof(double) * n);
+}
+
+int orc_register_pair(const float* ref, const float* test, int H, int W, const orc_params* p,
+                      const double* u_init, const double* rfin_in, const orc_outputs* o)
+{
+    size_t HW = (size_t)H * W;
+    int nr = p->n_roi, N = p->roi_size;
+    double* Rn = (double*)malloc(sizeof(double) * HW);
+    double* Tn = (double*)malloc(sizeof(double) * HW);
+    double* field = (double*)malloc(sizeof(double) * 2 * HW);
+    double* cx = (double*)malloc(sizeof(double) * nr);
+    double* cy = (double*)malloc(sizeof(double) * nr);
+    int32_t* x0 = (int32_t*)malloc(sizeof(int32_t) * nr);
+    int32_t* y0 = (int32_t*)malloc(sizeof(int32_t) * nr);
+    double* q1 = (double*)malloc(sizeof(double) * 2 * nr);
+    double* q2 = (double*)calloc(2 * (size_t)nr, sizeof(double));
+    double* ph = (double*)calloc((size_t)nr, sizeof(double));
+    int32_t its[ORC_MAX_LEVELS] = {0};
+    uint32_t st = 0;
+    st |= orc_normalize(ref, (int64_t)HW, Rn);
+    st |= orc_normalize(test, (int64_t)HW, Tn);
+    st |= orc_demons(Rn, Tn, H, W, p, u_init, field, its);
+    orc_roi_layout(H, W, p, cx, cy, x0, y0);
+    double* ux = field;
+    double* uy = field + HW;
+    for (int j = 0; j < nr; j++) {
+        q1[2 * j] = orc_bilinear(ux, H, W, cx[j], cy[j]);
+        q1[2 * j + 1] = orc_bilinear(uy, H, W, cx[j], cy[j]);
+    }
+    double xs = p->pc_x * W - 0.5, ys = p->pc_y * H - 0.5, zs = p->pc_z * W;
+    double F1[9], Rfin[9], F[9], R[9], rv[3];
+    st |= orc_solve_F(q1, cx, cy, nr, xs, ys, zs, F1);
+    orc_polar(F1, Rfin);
+    if (rfin_in) memcpy(Rfin, rfin_in, sizeof Rfin);
+    if (p->second_pass) {
+        double* Rm = (double*)malloc(sizeof(double) * HW);
+        orc_remap(Rn, H, W, Rfin, xs, ys, zs, Rm);
+        double* a = (double*)malloc(sizeof(double) * N * N);
+        double* b = (double*)malloc(sizeof(double) * N * N);
+        for (int j = 0; j < nr; j++) {
+            for (int y = 0; y < N; y++)
+                for (int x = 0; x < N; x++) {
+                    a[y * N + x] = Rm[(size_t)(y0[j] + y) * W + x0[j] + x];
+                    b[y * N + x] = Tn[(size_t)(y0[j] + y) * W + x0[j] + x];
+                }
+            orc_xcf(a, b, N, p->window, NULL, q2 + 2 * j, ph + j);
+        }
+        double Finf[9];
+        st |= orc_solve_F(q2, cx, cy, nr, xs, ys, zs, Finf);
+        matmul3(Finf, Rfin, F);
+        if (det3(F) > 0.0) orc_det_normalize(F);
+        free(Rm);
+        free(a);
+        free(b);
+    } else {
+        memcpy(F, F1, sizeof F);
+    }
+    orc_polar(F, R);
+    orc_rotvec(R, rv);
+    store(o->field, field, 2 * HW);
+    store(o->q1, q1, 2 * (size_t)nr);
+    store(o->F1, F1, 9);
+    store(o->Rfin, Rfin, 9);
+    store(o->q2, q2, 2 * (size_t)nr);
+    store(o->ph, ph, (size_t)nr);
+    store(o->F, F, 9);
+    store(o->R, R, 9);
+    store(o->rotvec, rv, 3);
+    if (o->iters) memcpy(o->iters, its, sizeof(int32_t) * p->levels);
+    if (o->status) *o->status = st;
+    free(Rn);
+    free(Tn);
+    free(field);
+    free(cx);
+    free(cy);
+    free(x0);
+    free(y0);
+    free(q1);
+    free(q2);
+    free(ph);
+    return 0;
+}
+
+/* Batch over pairs (independent scan points), one pair per OpenMP thread.
+ * refs/tests: [n][H][W] float; outputs are strided per pair like the
+ * single-pair call (field [n][2][H][W], q [n][n_roi][2], F/R [n][9], ...).
+ * rfin_in, if not NULL, is [n][9].  Returns the number of threads used.   */
+int orc_register_batch(const float* refs, const float* tests, int n, int H, int W,
+                       const orc_params* p, const double* rfin_in, const orc_outputs* o)
+{
+    size_t HW = (size_t)H * W;
+    int nr = p->n_roi;
+    int used = 1;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        used = omp_get_num_threads();
+#endif
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < n; i++) {
+            orc_outputs oi;
+            oi.field = o->field ? o->field + (size_t)i * 2 * HW : NULL;
+            oi.q1 = o->q1 ? o->q1 + (size_t)i * 2 * nr : NULL;
+            oi.F1 = o->F1 ? o->F1 + (size_t)i * 9 : NULL;
+            oi.Rfin = o->Rfin ? o->Rfin + (size_t)i * 9 : NULL;
+            oi.q2 = o->q2 ? o->q2 + (size_t)i * 2 * nr : NULL;
+            oi.ph = o->ph ? o->ph + (size_t)i * nr : NULL;
+            oi.F = o->F ? o->F + (size_t)i * 9 : NULL;
+            oi.R = o->R ? o->R + (size_t)i * 9 : NULL;
+            oi.rotvec = o->rotvec ? o->rotvec + (size_t)i * 3 : NULL;
+            oi.iters = o->iters ? o->iters + (size_t)i * p->levels : NULL;
+            oi.status = o->status ? o->status + i : NULL;
+            orc_register_pair(refs + (size_t)i * HW, tests + (size_t)i * HW, H, W, p, NULL,
+                              rfin_in ? rfin_in + (size_t)i * 9 : NULL, &oi);
+        }
+    }
+    return used;
+}

@@ -1,0 +1,405 @@
+"""Pins of the FP64 CPU oracle against things that do not use its arithmetic:
+numpy/scipy/torch library routines, brute force on tiny inputs, closed forms,
+invariants and the values the paper prints (tests/golden/).  CPU only.
+
+Each stage is pinned so that a plausible slip (dropped term, wrong sign or
+index, transposed operand, wrong normalisation) fails at least one test.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.ndimage as ndi
+import scipy.optimize
+from scipy.spatial.transform import Rotation
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# -- normalisation (section 2: zero mean) -------------------------------------------------
+
+def test_normalize_matches_numpy(orc):
+    x = rng(1).normal(5.0, 3.0, size=(17, 23)).astype(np.float32)
+    out, st = orc.normalize(x)
+    ref = (x.astype(np.float64) - x.astype(np.float64).mean()) / x.astype(np.float64).std()
+    assert st == 0
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-13)
+
+
+def test_normalize_degenerate_and_nonfinite(orc):
+    out, st = orc.normalize(np.full((8, 8), 7.0, np.float32))
+    assert st == orc.DEGENERATE_INPUT and not out.any()
+    x = np.ones((8, 8), np.float32)
+    x[3, 3] = np.nan
+    out, st = orc.normalize(x)
+    assert st == orc.NONFINITE_INPUT and not out.any()
+
+
+# -- pyramid restriction --------------------------------------------------------------------
+
+def test_restrict_matches_scipy_correlate(orc):
+    x = rng(2).normal(size=(16, 24))
+    out = orc.restrict(x)
+    w = np.array([1.0, 3.0, 3.0, 1.0]) / 8.0
+    # correlate with taps at offsets -1..+2 (origin -1 for an even kernel), clamp borders
+    t = ndi.correlate1d(x, w, axis=1, mode="nearest", origin=-1)
+    t = ndi.correlate1d(t, w, axis=0, mode="nearest", origin=-1)
+    np.testing.assert_allclose(out, t[0::2, 0::2], atol=1e-14)
+
+
+def test_restrict_preserves_constants_and_linear_ramps(orc):
+    assert np.all(orc.restrict(np.full((8, 8), 3.25)) == 3.25)
+    y, x = np.mgrid[0:16, 0:16].astype(np.float64)
+    ramp = 0.7 * x - 1.3 * y + 2.0
+    out = orc.restrict(ramp)
+    j, i = np.mgrid[0:8, 0:8].astype(np.float64)
+    expect = 0.7 * (2 * i + 0.5) - 1.3 * (2 * j + 0.5) + 2.0  # centre of coarse pixel = 2i + 0.5
+    np.testing.assert_allclose(out[1:-1, 1:-1], expect[1:-1, 1:-1], atol=1e-12)
+
+
+# -- gradient, bilinear, warp ---------------------------------------------------------------
+
+def test_gradient_matches_numpy(orc):
+    x = rng(3).normal(size=(11, 13))
+    gx, gy = orc.gradient(x)
+    ny, nx = np.gradient(x)
+    np.testing.assert_allclose(gx, nx, atol=1e-14)
+    np.testing.assert_allclose(gy, ny, atol=1e-14)
+
+
+def test_bilinear_matches_map_coordinates(orc):
+    img = rng(4).normal(size=(20, 30))
+    xs = rng(5).uniform(-3, 33, size=500)
+    ys = rng(6).uniform(-3, 23, size=500)
+    out = orc.bilinear_points(img, xs, ys)
+    ref = ndi.map_coordinates(img, [ys, xs], order=1, mode="nearest")
+    np.testing.assert_allclose(out, ref, atol=1e-12)
+
+
+def test_warp_zero_field_is_exact_copy(orc):
+    img = rng(7).normal(size=(12, 9))
+    assert np.array_equal(orc.warp(img, np.zeros((2, 12, 9))), img)
+
+
+def test_warp_integer_shift(orc):
+    img = rng(8).normal(size=(16, 16))
+    u = np.zeros((2, 16, 16))
+    u[0] = 2.0
+    u[1] = -1.0
+    out = orc.warp(img, u)  # out(x, y) = img(x + 2, y - 1)
+    np.testing.assert_array_equal(out[1:, :-2], img[:-1, 2:])
+
+
+# -- smoothing --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sigma", [0.5, 1.0, 1.3])
+def test_smooth_matches_gaussian_filter(orc, sigma):
+    x = rng(9).normal(size=(19, 27))
+    out = orc.smooth(x, sigma)
+    r = int(math.floor(3 * sigma + 0.5))
+    ref = ndi.gaussian_filter(x, sigma=sigma, truncate=r / sigma, mode="nearest")
+    np.testing.assert_allclose(out, ref, atol=1e-13)
+
+
+def test_smooth_preserves_constant_and_zero_sigma_copies(orc):
+    assert np.allclose(orc.smooth(np.full((9, 9), 2.5), 1.0), 2.5, atol=1e-15)
+    x = rng(10).normal(size=(5, 6))
+    assert np.array_equal(orc.smooth(x, 0.0), x)
+
+
+# -- demons force (Eq. 1) ---------------------------------------------------------------------
+
+def test_demons_identical_images_no_update(orc):
+    R = rng(11).normal(size=(24, 24))
+    u_new, rms = orc.demons_iter(R, R, np.zeros((2, 24, 24)), 1.0)
+    assert rms == 0.0 and not u_new.any()
+
+
+def test_demons_update_bounded_by_half_pixel(orc):
+    R = rng(12).normal(size=(32, 32))
+    T = rng(13).normal(size=(32, 32))
+    u = rng(14).normal(scale=0.7, size=(2, 32, 32))
+    u_new, _ = orc.demons_iter(R, T, u, 0.0)  # no smoothing: u_new = u + du
+    du = np.sqrt(((u_new - u) ** 2).sum(0))
+    assert du.max() <= 0.5 + 1e-12
+
+
+def test_demons_1d_ramp_closed_form(orc):
+    # R(x) = x, T(x) = x - s  =>  T(x + s) = R(x); first step du = s / (1 + s^2)
+    s = 0.8
+    y, x = np.mgrid[0:8, 0:40].astype(np.float64)
+    R = x.copy()
+    T = x - s
+    u_new, _ = orc.demons_iter(R, T, np.zeros((2, 8, 40)), 0.0)
+    np.testing.assert_allclose(u_new[0][:, 2:-2], s / (1 + s * s), atol=1e-14)
+    assert not u_new[1].any()
+
+
+def test_demons_force_sign_drives_toward_shift(orc):
+    # T(x) = R(x - s) with a smooth R: after iterations u -> s in the interior
+    y, x = np.mgrid[0:64, 0:64].astype(np.float64)
+    R = np.sin(x / 5.0) + np.cos(y / 7.0) + 0.3 * np.sin((x + y) / 3.0)
+    s = (1.5, -1.0)
+    T = np.sin((x - s[0]) / 5.0) + np.cos((y - s[1]) / 7.0) + 0.3 * np.sin(((x - s[0]) + (y - s[1])) / 3.0)
+    p = orc.make_params(levels=2, iters=200, sigma=1.0)
+    f, its, st = orc.demons(R, T, p)
+    c = f[:, 16:48, 16:48]
+    assert abs(c[0].mean() - s[0]) < 0.02 and abs(c[1].mean() - s[1]) < 0.02
+
+
+def test_demons_invariant_to_common_affine_intensity(orc):
+    R = rng(15).normal(size=(20, 20))
+    T = np.roll(R, 1, axis=1) + 0.1 * rng(16).normal(size=(20, 20))
+    u = np.zeros((2, 20, 20))
+    a, _ = orc.demons_iter(R, T, u, 1.0)
+    b, _ = orc.demons_iter(3.0 * R + 5.0, 3.0 * T + 5.0, u, 1.0)
+    np.testing.assert_allclose(a, b, atol=1e-12)
+
+
+# -- prolongation ---------------------------------------------------------------------------
+
+def test_prolong_matches_torch_interpolate(orc):
+    import torch
+    u = rng(17).normal(size=(2, 7, 9))
+    out = orc.prolong(u)
+    ref = 2.0 * torch.nn.functional.interpolate(torch.from_numpy(u)[None], scale_factor=2,
+                                                mode="bilinear", align_corners=False)[0].numpy()
+    np.testing.assert_allclose(out, ref, atol=1e-13)
+
+
+# -- whole demons loop ----------------------------------------------------------------------
+
+def test_demons_identical_pair_zero_field(orc):
+    from paper_1907_05993_amd import synth as S
+    spec = S.make_spec(99, 0, 64, 64, exact_angle=0.0, strain=0.0)
+    ref, _ = S.render_pair(spec)
+    Rn, _ = orc.normalize(ref)
+    f, its, st = orc.demons(Rn, Rn, orc.make_params(levels=3, iters=20))
+    assert not f.any()
+
+
+# -- ROI layout (section 2) ---------------------------------------------------------------------
+
+def test_roi_layout_ring_and_centre(orc):
+    p = orc.make_params(n_roi=20, roi_size=64, roi_radius_frac=0.3)
+    cx, cy, x0, y0, bad = orc.roi_layout(256, 256, p)
+    assert not bad and len(cx) == 20
+    assert cx[0] == 127.5 and cy[0] == 127.5
+    r = np.hypot(cx[1:] - 127.5, cy[1:] - 127.5)
+    assert np.all(np.abs(r - 76.8) <= 0.75)  # ring radius up to the integer snapping
+    ang = np.unwrap(np.arctan2(cy[1:] - 127.5, cx[1:] - 127.5))
+    np.testing.assert_allclose(np.diff(ang), 2 * np.pi / 19, atol=0.02)
+    assert np.all(x0 >= 0) and np.all(x0 + 64 <= 256) and np.all(y0 >= 0) and np.all(y0 + 64 <= 256)
+    assert orc.roi_layout(128, 128, orc.make_params(roi_size=128))[4]  # out of bounds flagged
+
+
+# -- FFT and XCF (section 2) ------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [2, 4, 8, 16])
+def test_fft_brute_force_dft(orc, N):
+    x = rng(N).normal(size=N) + 1j * rng(N + 1).normal(size=N)
+    k = np.arange(N)
+    dft = np.array([np.sum(x * np.exp(-2j * np.pi * kk * k / N)) for kk in k])
+    np.testing.assert_allclose(orc.fft1(x), dft, atol=1e-12)
+    np.testing.assert_allclose(orc.fft1(dft, inverse=True), x, atol=1e-12)
+
+
+def test_fft2_matches_numpy(orc):
+    x = rng(20).normal(size=(64, 64)) + 1j * rng(21).normal(size=(64, 64))
+    np.testing.assert_allclose(orc.fft2(x), np.fft.fft2(x), atol=1e-10)
+    np.testing.assert_allclose(orc.fft2(x, inverse=True), np.fft.ifft2(x), atol=1e-13)
+
+
+def test_xcf_correlation_matches_numpy(orc):
+    A = rng(22).normal(size=(32, 32))
+    B = rng(23).normal(size=(32, 32))
+    q, ph, C = orc.xcf(A, B, 1)
+    h = np.hanning(32)
+    w = np.outer(h, h)
+    a = (A - A.mean()) * w
+    b = (B - B.mean()) * w
+    ref = np.real(np.fft.ifft2(np.fft.fft2(b) * np.conj(np.fft.fft2(a))))
+    np.testing.assert_allclose(C, ref, atol=1e-12)
+
+
+def test_xcf_identical_rois(orc):
+    A = ndi.gaussian_filter(rng(24).normal(size=(64, 64)), 2.0)
+    q, ph, _ = orc.xcf(A, A, 1)
+    assert np.all(np.abs(q) < 1e-12) and abs(ph - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("s", [(3, -5), (-7, 2), (0, 9), (12, 11)])
+def test_xcf_integer_shift_exact_without_window(orc, s):
+    A = ndi.gaussian_filter(rng(25).normal(size=(64, 64)), 1.5, mode="wrap")
+    B = np.roll(A, shift=(s[1], s[0]), axis=(0, 1))  # B(x) = A(x - s)
+    q, ph, _ = orc.xcf(A, B, 0)
+    np.testing.assert_allclose(q, s, atol=1e-9)
+
+
+@pytest.mark.parametrize("s", [(3, -5), (-7, 2)])
+def test_xcf_integer_shift_with_window(orc, s):
+    A = ndi.gaussian_filter(rng(26).normal(size=(64, 64)), 1.5, mode="wrap")
+    B = np.roll(A, shift=(s[1], s[0]), axis=(0, 1))
+    q, ph, _ = orc.xcf(A, B, 1)
+    assert np.all(np.round(q) == s)
+    assert np.all(np.abs(q - s) < 0.15)
+
+
+def test_xcf_subpixel_shift_of_smooth_texture(orc):
+    big = ndi.gaussian_filter(rng(27).normal(size=(128, 128)), 3.0)
+    s = (0.37, -0.21)
+    B = ndi.shift(big, (s[1], s[0]), order=3, mode="nearest")
+    q, _, _ = orc.xcf(big[32:96, 32:96], B[32:96, 32:96], 1)
+    assert np.all(np.abs(q - s) < 0.05)
+
+
+# -- F solve (Eq. 2-3), polar (Eq. 4-5), rotation vector -------------------------------------
+
+def _project(F, cx, cy, xs, ys, zs):
+    r = np.stack([cx - xs, cy - ys, np.full_like(cx, zs)])
+    v = F @ r
+    return np.stack([xs + zs * v[0] / v[2] - cx, ys + zs * v[1] / v[2] - cy], axis=1)
+
+
+def _layout():
+    import oracle
+    p = oracle.make_params(n_roi=20, roi_size=64)
+    cx, cy, _, _, _ = oracle.roi_layout(256, 256, p)
+    return cx, cy, (127.5, 127.5, 0.7 * 256)
+
+
+def test_solve_F_recovers_known_F_from_exact_shifts(orc):
+    cx, cy, pcs = _layout()
+    Ftrue = (np.eye(3) + np.array([[1e-3, -5e-4, 2e-4], [-5e-4, -2e-3, 7e-4], [2e-4, 7e-4, 1e-3]])) \
+        @ Rotation.from_rotvec([0.05, -0.08, 0.03]).as_matrix()
+    q = _project(Ftrue, cx, cy, *pcs)
+    F, st = orc.solve_F(q, cx, cy, pcs)
+    Fn = Ftrue / np.cbrt(np.linalg.det(Ftrue))
+    assert st == 0
+    np.testing.assert_allclose(F, Fn, atol=1e-12)
+    assert abs(np.linalg.det(F) - 1.0) < 1e-13
+
+
+def test_solve_F_matches_scipy_least_squares_on_noisy_shifts(orc):
+    cx, cy, pcs = _layout()
+    xs, ys, zs = pcs
+    Ftrue = Rotation.from_rotvec([0.02, 0.03, -0.04]).as_matrix()
+    q = _project(Ftrue, cx, cy, *pcs) + rng(30).normal(scale=0.3, size=(20, 2))
+    F, st = orc.solve_F(q, cx, cy, pcs)
+
+    def resid(th):
+        Fm = np.append(th, 1.0).reshape(3, 3)
+        return (_project(Fm, cx, cy, xs, ys, zs) - q).ravel()
+
+    th0 = (Ftrue / Ftrue[2, 2]).ravel()[:8]
+    sol = scipy.optimize.least_squares(resid, th0, xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    Fs = np.append(sol.x, 1.0).reshape(3, 3)
+    Fs /= np.cbrt(np.linalg.det(Fs))
+    np.testing.assert_allclose(F, Fs, atol=1e-10)
+
+
+def test_solve_F_pure_pattern_shift(orc):
+    # a uniform pattern translation (sx, sy) is F = I + (sx/Z*) e1 (x) e3 + (sy/Z*) e2 (x) e3
+    cx, cy, pcs = _layout()
+    sx, sy = 1.7, -0.9
+    F, st = orc.solve_F(np.tile([sx, sy], (20, 1)), cx, cy, pcs)
+    Fe = np.eye(3)
+    Fe[0, 2] = sx / pcs[2]
+    Fe[1, 2] = sy / pcs[2]
+    np.testing.assert_allclose(F, Fe, atol=1e-13)
+
+
+def test_solve_F_in_plane_rotation_about_pc(orc):
+    cx, cy, pcs = _layout()
+    th = math.radians(3.0)
+    c, s = math.cos(th), math.sin(th)
+    dx, dy = cx - pcs[0], cy - pcs[1]
+    q = np.stack([c * dx - s * dy - dx, s * dx + c * dy - dy], axis=1)
+    F, _ = orc.solve_F(q, cx, cy, pcs)
+    np.testing.assert_allclose(F, Rotation.from_rotvec([0, 0, th]).as_matrix(), atol=1e-13)
+
+
+def test_polar_matches_scipy(orc):
+    F = np.eye(3) + rng(31).normal(scale=0.05, size=(3, 3))
+    R = orc.polar(F)
+    Rs, Ps = scipy.linalg.polar(F)  # F = Rs Ps (right polar)
+    np.testing.assert_allclose(R, Rs, atol=1e-13)
+    np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-14)
+    assert abs(np.linalg.det(R) - 1) < 1e-14
+
+
+def test_polar_of_stretched_rotation_is_exact(orc):
+    Rt = Rotation.from_rotvec([0.1, -0.2, 0.05]).as_matrix()
+    eps = np.array([[2e-3, 1e-3, 0], [1e-3, -1e-3, 5e-4], [0, 5e-4, 3e-4]])
+    R = orc.polar((np.eye(3) + eps) @ Rt)  # left and right polar factors share R
+    np.testing.assert_allclose(R, Rt, atol=1e-14)
+
+
+@pytest.mark.parametrize("rv", [[0, 0, 0], [1e-7, -2e-7, 3e-7], [0.01, 0.02, -0.03], [0.5, -1.0, 1.2],
+                                [0, 0, 3.1]])
+def test_rotvec_matches_scipy(orc, rv):
+    R = Rotation.from_rotvec(rv).as_matrix()
+    np.testing.assert_allclose(orc.rotvec(R), Rotation.from_matrix(R).as_rotvec(), atol=1e-14)
+
+
+def test_det_normalize(orc):
+    F = np.diag([1.1, 0.9, 1.05])
+    Fn = orc.det_normalize(F)
+    assert abs(np.linalg.det(Fn) - 1) < 1e-15
+    np.testing.assert_allclose(Fn * np.cbrt(np.linalg.det(F)), F, atol=1e-15)
+
+
+# -- remap ------------------------------------------------------------------------------------
+
+def test_remap_identity_is_exact_copy(orc):
+    img = rng(40).normal(size=(32, 32))
+    # pi(r(x)) = x up to the rounding of Z* (x - x*)/Z*
+    np.testing.assert_allclose(orc.remap(img, np.eye(3), (15.5, 15.5, 22.4)), img, atol=1e-13)
+
+
+def test_remap_in_plane_rotation_matches_affine_transform(orc):
+    img = ndi.gaussian_filter(rng(41).normal(size=(64, 64)), 1.0)
+    th = math.radians(4.0)
+    Rz = Rotation.from_rotvec([0, 0, th]).as_matrix()
+    pcs = (31.5, 31.5, 44.8)
+    out = orc.remap(img, Rz, pcs)
+    # out(x') = img(R^T (x' - pc) + pc) in the (x, y) plane; scipy works in (row, col)
+    c, s = math.cos(th), math.sin(th)
+    Mxy = np.array([[c, s], [-s, c]])  # R_z^T restricted to the plane
+    M = Mxy[::-1, ::-1]
+    off = np.array([pcs[1], pcs[0]]) - M @ np.array([pcs[1], pcs[0]])
+    ref = ndi.affine_transform(img, M, offset=off, order=1, mode="nearest")
+    np.testing.assert_allclose(out, ref, atol=1e-10)
+
+
+# -- the paper's printed values (test set 2) ----------------------------------------------------
+
+def test_paper_test_set_2_misorientation(orc):
+    g = json.load(open(os.path.join(GOLDEN, "paper_test_set_2.json")))
+    np.testing.assert_allclose(np.radians(g["reference_euler_deg"]), g["reference_euler_rad"], atol=6e-5)
+    np.testing.assert_allclose(np.radians(g["test_euler_deg"]), g["test_euler_rad"], atol=6e-5)
+    g1 = Rotation.from_euler("ZXZ", g["reference_euler_deg"], degrees=True).as_matrix()
+    g2 = Rotation.from_euler("ZXZ", g["test_euler_deg"], degrees=True).as_matrix()
+    ang = np.degrees(np.linalg.norm(orc.rotvec(g1.T @ g2)))
+    assert abs(ang - g["misorientation_deg_approx"]) < 0.5  # printed as "~8"
+    np.testing.assert_allclose(ang, 8.0908, atol=2e-4)  # Bunge ZXZ; also scipy Rotation.magnitude
+
+
+# -- whole pipeline ---------------------------------------------------------------------------
+
+def test_pipeline_identical_pair(orc):
+    from paper_1907_05993_amd import synth as S
+    spec = S.make_spec(98, 0, 128, 128, exact_angle=0.0, strain=0.0)
+    ref, _ = S.render_pair(spec)
+    out = orc.register_batch(ref, ref, orc.make_params(levels=3, iters=10, roi_size=32))
+    assert not out["field"].any()
+    np.testing.assert_allclose(out["F"][0], np.eye(3), atol=1e-13)
+    assert np.all(out["rotvec"][0] == 0) or np.abs(out["rotvec"][0]).max() < 1e-13
+    np.testing.assert_allclose(out["ph"][0], 1.0, atol=1e-12)
