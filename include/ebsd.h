@@ -77,10 +77,10 @@ typedef struct ebsd_params {
     int32_t max_iters[EBSD_MAX_LEVELS];   /* demons iterations per level, [0] = finest */
     float sigma_px;                       /* Gaussian smoothing of the accumulated field, 0 <= sigma <= 1.3 */
     float tol_px;                         /* stop a level when 2^l RMS|u_new - u| < tol (full-res px); 0 = fixed count */
-    float pc_x, pc_y, pc_z;               /* pattern centre fractions */
+    double pc_x, pc_y, pc_z;              /* pattern centre fractions */
     int32_t n_roi;                        /* ROIs: 1 at the pattern centre + (n_roi - 1) on a ring, 5..256 */
     int32_t roi_size;                     /* 32, 64 or 128 */
-    float roi_radius_frac;                /* ring radius / W */
+    double roi_radius_frac;               /* ring radius / W */
     int32_t window;                       /* 1 = Hann window on each ROI (section 2), 0 = none */
     int32_t second_pass;                  /* 1 = remap + XCF second pass (Eq. (12)); 0 = demons only */
 } ebsd_params;
@@ -170,6 +170,16 @@ int ebsd_register_batch_init(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
  * Fills F, R, rotvec, q2, peak_height, status (and copies R_finite) of out. */
 int ebsd_second_pass_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
                            const double* R_finite, const ebsd_outputs* out, void* stream);
+
+/* Timing of the demons iterations, for measurement tools.  enable != 0 makes
+ * later calls record HIP events on their stream around each pyramid level's
+ * demons launches and around the whole call (of its last size bucket). */
+int ebsd_set_timing(ebsd_handle* h, int enable);
+
+/* Waits for the last timed call to complete and reports level_ms[l] (host,
+ * [levels]): the time of level l's demons launches, and *total_ms: the whole
+ * call.  EBSD_EINVAL if no timed call has been made. */
+int ebsd_get_timing(ebsd_handle* h, double* level_ms, double* total_ms);
 
 /* ---- single-stage entry points (one kernel each; device pointers) ------- */
 

@@ -1,0 +1,704 @@
+// C ABI of the gfx950 demons-based HR-EBSD library (declared in include/ebsd.h).
+//
+// Host side: argument validation (before anything is enqueued), size
+// bucketing, workspace management and the launch sequence of the whole path
+// (arXiv:1907.05993: multi-resolution demons of section 1 / Eq. (1), shifts at
+// the ROI centres and the Eq. (2)-(3) solve of section 2, polar rotation of
+// Eq. (4)-(5), remap and second-pass cross-correlation, Eq. (12)).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <map>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "../../include/ebsd.h"
+#include "ebsd_internal.h"
+
+using namespace ebsd;
+
+struct ebsd_handle {
+    ebsd_params p;
+    int device;
+    float taps[2 * kMaxRadius + 1];
+    int radius;
+    char* ws = nullptr;  // device workspace
+    size_t ws_bytes = 0;
+    char* pin = nullptr;  // pinned staging for descriptors
+    size_t pin_bytes = 0;
+    hipEvent_t pin_free = nullptr;  // recorded after the last upload from `pin`
+    bool pin_pending = false;
+    // timing: ev[0] call start, ev[1] call end, ev[2 + 2l] / ev[3 + 2l] level l
+    bool timing = false;
+    bool timed_call = false;
+    int timed_levels = 0;
+    hipEvent_t ev[2 + 2 * EBSD_MAX_LEVELS] = {};
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Sub-allocation plan inside one buffer.
+struct Plan {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    }
+};
+
+int check_params(const ebsd_params* p)
+{
+    if (!p) return EBSD_EINVAL;
+    if (p->struct_size != sizeof(ebsd_params)) return EBSD_EVERSION;
+    if (p->levels < 1 || p->levels > EBSD_MAX_LEVELS) return EBSD_EINVAL;
+    for (int l = 0; l < p->levels; l++)
+        if (p->max_iters[l] < 0 || p->max_iters[l] > 1000000) return EBSD_EINVAL;
+    if (!(p->sigma_px >= 0.0f) || !(p->sigma_px <= 1.3f)) return EBSD_EINVAL;
+    if (!(p->tol_px >= 0.0f) || !std::isfinite(p->tol_px)) return EBSD_EINVAL;
+    if (!std::isfinite(p->pc_x) || !std::isfinite(p->pc_y) || !(p->pc_z > 0.0) ||
+        !std::isfinite(p->pc_z))
+        return EBSD_EINVAL;
+    if (p->n_roi < 5 || p->n_roi > 256) return EBSD_EINVAL;
+    if (p->roi_size != 32 && p->roi_size != 64 && p->roi_size != 128) return EBSD_EROI;
+    if (!(p->roi_radius_frac >= 0.0) || !std::isfinite(p->roi_radius_frac)) return EBSD_EINVAL;
+    if (p->window != 0 && p->window != 1) return EBSD_EINVAL;
+    if (p->second_pass != 0 && p->second_pass != 1) return EBSD_EINVAL;
+    return EBSD_OK;
+}
+
+// ROI layout for an H x W pattern (see ebsd_roi_layout in the header).
+int roi_layout(const ebsd_params& p, int H, int W, double* cx, double* cy, int32_t* x0, int32_t* y0)
+{
+    const double xs = p.pc_x * W - 0.5, ys = p.pc_y * H - 0.5;
+    const double rho = p.roi_radius_frac * W;
+    const int N = p.roi_size;
+    const double pi = 3.14159265358979323846;
+    int bad = 0;
+    for (int j = 0; j < p.n_roi; j++) {
+        double px = xs, py = ys;
+        if (j > 0) {
+            const double a = 2.0 * pi * (double)(j - 1) / (double)(p.n_roi - 1);
+            px += rho * std::cos(a);
+            py += rho * std::sin(a);
+        }
+        const int ix = (int)std::floor(px - (N - 1) / 2.0 + 0.5);
+        const int iy = (int)std::floor(py - (N - 1) / 2.0 + 0.5);
+        if (x0) x0[j] = ix;
+        if (y0) y0[j] = iy;
+        if (cx) cx[j] = ix + (N - 1) / 2.0;
+        if (cy) cy[j] = iy + (N - 1) / 2.0;
+        if (ix < 0 || iy < 0 || ix + N > W || iy + N > H) bad = 1;
+    }
+    return bad ? EBSD_EROI : EBSD_OK;
+}
+
+int check_shape(const ebsd_params& p, int H, int W)
+{
+    const int f = 1 << (p.levels - 1);
+    if (H <= 0 || W <= 0 || H > 16384 || W > 16384) return EBSD_ESHAPE;
+    if (H % f != 0 || W % f != 0) return EBSD_ESHAPE;
+    if (H / f < 4 || W / f < 4) return EBSD_ESHAPE;
+    if (H < p.roi_size || W < p.roi_size) return EBSD_EROI;
+    return roi_layout(p, H, W, nullptr, nullptr, nullptr, nullptr);
+}
+
+int check_pairs(const ebsd_params& p, const ebsd_pair* pairs, int n)
+{
+    if (n < 0 || n > (1 << 24)) return EBSD_EINVAL;
+    if (n > 0 && !pairs) return EBSD_EINVAL;
+    std::map<int, std::pair<const float*, std::pair<int, int>>> refs;
+    for (int i = 0; i < n; i++) {
+        const ebsd_pair& q = pairs[i];
+        if (!q.ref || !q.test) return EBSD_EINVAL;
+        int e = check_shape(p, q.H, q.W);
+        if (e) return e;
+        if (q.ref_id >= 0) {
+            auto it = refs.find(q.ref_id);
+            if (it == refs.end())
+                refs[q.ref_id] = {q.ref, {q.H, q.W}};
+            else if (it->second.first != q.ref || it->second.second.first != q.H ||
+                     it->second.second.second != q.W)
+                return EBSD_EINVAL;
+        }
+    }
+    return EBSD_OK;
+}
+
+int map_err(hipError_t e)
+{
+    if (e == hipSuccess) return EBSD_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return EBSD_ENOMEM;
+    return EBSD_EDEVICE;
+}
+
+// Make sure the handle's workspace holds `bytes`.  Growing waits for all
+// work on the device, since earlier calls may still be using the old buffer.
+int ensure_ws(ebsd_handle* h, size_t bytes)
+{
+    if (bytes <= h->ws_bytes) return EBSD_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return EBSD_EDEVICE;
+    if (h->ws) (void)hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+    size_t want = align_up(bytes + bytes / 8, 1 << 20);
+    if (hipMalloc(&h->ws, want) != hipSuccess) {
+        h->ws = nullptr;
+        (void)hipGetLastError();
+        return EBSD_ENOMEM;
+    }
+    h->ws_bytes = want;
+    return EBSD_OK;
+}
+
+// Pinned staging for descriptor uploads; waits until the previous upload has
+// been consumed before the buffer is rewritten.
+int ensure_pin(ebsd_handle* h, size_t bytes)
+{
+    if (h->pin_pending) {
+        if (hipEventSynchronize(h->pin_free) != hipSuccess) return EBSD_EDEVICE;
+        h->pin_pending = false;
+    }
+    if (bytes <= h->pin_bytes) return EBSD_OK;
+    if (h->pin) (void)hipHostFree(h->pin);
+    h->pin = nullptr;
+    h->pin_bytes = 0;
+    size_t want = align_up(bytes * 2, 1 << 16);
+    if (hipHostMalloc((void**)&h->pin, want, hipHostMallocDefault) != hipSuccess) {
+        h->pin = nullptr;
+        (void)hipGetLastError();
+        return EBSD_ENOMEM;
+    }
+    h->pin_bytes = want;
+    return EBSD_OK;
+}
+
+// Host-side description of one size bucket.
+struct HostBucket {
+    int H, W;
+    std::vector<int> idx;        // caller pair indices
+    std::vector<const float*> test_in, ref_in;
+    std::vector<int32_t> ref_slot, pair_index;
+};
+
+std::vector<HostBucket> make_buckets(const ebsd_pair* pairs, int n)
+{
+    std::vector<HostBucket> out;
+    std::map<std::pair<int, int>, size_t> where;
+    for (int i = 0; i < n; i++) {
+        auto key = std::make_pair(pairs[i].H, pairs[i].W);
+        auto it = where.find(key);
+        size_t k;
+        if (it == where.end() || out[it->second].idx.size() >= 32000) {
+            k = out.size();
+            where[key] = k;
+            HostBucket hb;
+            hb.H = pairs[i].H;
+            hb.W = pairs[i].W;
+            out.push_back(hb);
+        } else {
+            k = it->second;
+        }
+        out[k].idx.push_back(i);
+    }
+    for (auto& hb : out) {
+        std::map<int, int> slot_of_id;
+        for (int i : hb.idx) {
+            const ebsd_pair& q = pairs[i];
+            int slot;
+            if (q.ref_id >= 0) {
+                auto it = slot_of_id.find(q.ref_id);
+                if (it == slot_of_id.end()) {
+                    slot = (int)hb.ref_in.size();
+                    slot_of_id[q.ref_id] = slot;
+                    hb.ref_in.push_back(q.ref);
+                } else {
+                    slot = it->second;
+                }
+            } else {
+                slot = (int)hb.ref_in.size();
+                hb.ref_in.push_back(q.ref);
+            }
+            hb.test_in.push_back(q.test);
+            hb.ref_slot.push_back(slot);
+            hb.pair_index.push_back(i);
+        }
+    }
+    return out;
+}
+
+enum class Mode { Full, SecondPassOnly };
+
+// Lay out, upload and run one bucket.  `pin_off` is this bucket's slice of
+// the pinned staging buffer.
+int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_init,
+               const double* rfin_in, const ebsd_outputs* out, hipStream_t s, size_t pin_off,
+               size_t* pin_used)
+{
+    const ebsd_params& p = h->p;
+    const int nb = (int)hbk.idx.size();
+    const int nref = (int)hbk.ref_in.size();
+    const int L = mode == Mode::Full ? p.levels : 1;
+    const int H = hbk.H, W = hbk.W;
+    const int nr = p.n_roi;
+
+    Bucket b;
+    std::memset(&b, 0, sizeof b);
+    b.nb = nb;
+    b.nref = nref;
+    b.H = H;
+    b.W = W;
+    b.L = L;
+    int64_t pe = 0;
+    int max_units = 1;
+    for (int l = 0; l < L; l++) {
+        b.lvl_off[l] = (int32_t)pe;
+        pe += (int64_t)(H >> l) * (W >> l);
+        max_units = std::max(max_units, demons_units(H >> l, W >> l));
+    }
+    pe = (pe + 63) / 64 * 64;  // 256 B aligned pyramids (vector loads)
+    b.pyr_elems = pe;
+    b.max_tiles = max_units;
+    b.n_roi = nr;
+    b.roi_N = p.roi_size;
+    b.xs = p.pc_x * W - 0.5;
+    b.ys = p.pc_y * H - 0.5;
+    b.zs = p.pc_z * W;
+
+    // workspace plan
+    const int max_tiles = b.max_tiles;
+    Plan w;
+    const size_t o_desc = w.take(sizeof(Bucket));
+    const size_t o_test_in = w.take(sizeof(void*) * nb);
+    const size_t o_ref_in = w.take(sizeof(void*) * nref);
+    const size_t o_ref_slot = w.take(sizeof(int32_t) * nb);
+    const size_t o_pair_index = w.take(sizeof(int32_t) * nb);
+    const size_t o_roi_c = w.take(sizeof(double) * 2 * nr);
+    const size_t o_roi_xy = w.take(sizeof(int32_t) * 2 * nr);
+    const size_t o_dst = w.take(sizeof(float*) * nb);
+    const size_t desc_bytes = w.off;
+    const size_t o_test_pyr = w.take(sizeof(float) * (size_t)nb * pe);
+    const size_t o_ref_pyr = w.take(sizeof(float) * (size_t)nref * pe);
+    const size_t o_tstat = w.take(sizeof(PatStat) * nb);
+    const size_t o_rstat = w.take(sizeof(PatStat) * nref);
+    const size_t field_bytes = mode == Mode::Full ? sizeof(float) * 2 * (size_t)nb * H * W : 0;
+    const size_t o_f0 = w.take(field_bytes);
+    const size_t o_f1 = w.take(field_bytes);
+    const size_t o_state = w.take(sizeof(PairState) * nb);
+    const size_t o_partial = w.take(sizeof(float) * 2 * (size_t)nb * max_tiles);
+    const size_t o_iters = w.take(sizeof(int32_t) * (size_t)nb * L);
+    const size_t o_q1 = w.take(sizeof(float) * 2 * (size_t)nb * nr);
+    const size_t o_q2 = w.take(sizeof(float) * 2 * (size_t)nb * nr);
+    const size_t o_ph = w.take(sizeof(float) * (size_t)nb * nr);
+    const size_t o_F1 = w.take(sizeof(double) * 9 * nb);
+    const size_t o_Rfin = w.take(sizeof(double) * 9 * nb);
+    const size_t o_F = w.take(sizeof(double) * 9 * nb);
+    const size_t o_R = w.take(sizeof(double) * 9 * nb);
+    const size_t o_rv = w.take(sizeof(double) * 3 * nb);
+    const size_t o_st = w.take(sizeof(uint32_t) * nb);
+    int e = ensure_ws(h, w.off);
+    if (e) return e;
+    char* base = h->ws;
+
+    b.test_in = reinterpret_cast<const float* const*>(base + o_test_in);
+    b.ref_in = reinterpret_cast<const float* const*>(base + o_ref_in);
+    b.ref_slot = reinterpret_cast<const int32_t*>(base + o_ref_slot);
+    b.pair_index = reinterpret_cast<const int32_t*>(base + o_pair_index);
+    b.roi_c = reinterpret_cast<const double*>(base + o_roi_c);
+    b.roi_xy = reinterpret_cast<const int32_t*>(base + o_roi_xy);
+    b.test_pyr = reinterpret_cast<float*>(base + o_test_pyr);
+    b.ref_pyr = reinterpret_cast<float*>(base + o_ref_pyr);
+    b.test_stat = reinterpret_cast<PatStat*>(base + o_tstat);
+    b.ref_stat = reinterpret_cast<PatStat*>(base + o_rstat);
+    b.field[0] = reinterpret_cast<float*>(base + o_f0);
+    b.field[1] = reinterpret_cast<float*>(base + o_f1);
+    b.state = reinterpret_cast<PairState*>(base + o_state);
+    b.partial = reinterpret_cast<float*>(base + o_partial);
+    b.iters = reinterpret_cast<int32_t*>(base + o_iters);
+    b.q1 = reinterpret_cast<float*>(base + o_q1);
+    b.q2 = reinterpret_cast<float*>(base + o_q2);
+    b.ph = reinterpret_cast<float*>(base + o_ph);
+    b.F1 = reinterpret_cast<double*>(base + o_F1);
+    b.Rfin = reinterpret_cast<double*>(base + o_Rfin);
+    b.F = reinterpret_cast<double*>(base + o_F);
+    b.R = reinterpret_cast<double*>(base + o_R);
+    b.rotvec = reinterpret_cast<double*>(base + o_rv);
+    b.status = reinterpret_cast<uint32_t*>(base + o_st);
+
+    // descriptor blob in pinned memory
+    char* pin = h->pin + pin_off;
+    std::memset(pin, 0, desc_bytes);
+    std::memcpy(pin + o_desc, &b, sizeof b);
+    std::memcpy(pin + o_test_in, hbk.test_in.data(), sizeof(void*) * nb);
+    std::memcpy(pin + o_ref_in, hbk.ref_in.data(), sizeof(void*) * nref);
+    std::memcpy(pin + o_ref_slot, hbk.ref_slot.data(), sizeof(int32_t) * nb);
+    std::memcpy(pin + o_pair_index, hbk.pair_index.data(), sizeof(int32_t) * nb);
+    {
+        std::vector<double> cx(nr), cy(nr), c2(2 * nr);
+        std::vector<int32_t> x0(nr), y0(nr), xy(2 * nr);
+        roi_layout(p, H, W, cx.data(), cy.data(), x0.data(), y0.data());
+        for (int j = 0; j < nr; j++) {
+            c2[2 * j] = cx[j];
+            c2[2 * j + 1] = cy[j];
+            xy[2 * j] = x0[j];
+            xy[2 * j + 1] = y0[j];
+        }
+        std::memcpy(pin + o_roi_c, c2.data(), sizeof(double) * 2 * nr);
+        std::memcpy(pin + o_roi_xy, xy.data(), sizeof(int32_t) * 2 * nr);
+    }
+    bool want_field = mode == Mode::Full && out->field;
+    if (want_field) {
+        float** dst = reinterpret_cast<float**>(pin + o_dst);
+        for (int k = 0; k < nb; k++) {
+            const int i = hbk.idx[k];
+            const int64_t off = out->field_offset ? out->field_offset[i] : (int64_t)i * 2 * H * W;
+            dst[k] = out->field + off;
+        }
+    }
+    *pin_used = desc_bytes;
+    hipError_t he = hipMemcpyAsync(base, pin, desc_bytes, hipMemcpyHostToDevice, s);
+    if (he != hipSuccess) return map_err(he);
+    const Bucket* d_bk = reinterpret_cast<const Bucket*>(base + o_desc);
+
+#define EBSD_TRY(x)                       \
+    do {                                  \
+        hipError_t err_ = (x);            \
+        if (err_ != hipSuccess) return map_err(err_); \
+    } while (0)
+
+    const bool tm = h->timing && mode == Mode::Full;
+    if (tm) EBSD_TRY(hipEventRecord(h->ev[0], s));
+    EBSD_TRY(launch_stats(d_bk, nb, nref, s));
+    EBSD_TRY(launch_pyramids(d_bk, b, s));
+    if (mode == Mode::Full) {
+        EBSD_TRY(launch_demons_init(d_bk, b, u_init, s));
+        for (int l = L - 1; l >= 0; l--) {
+            if (tm) EBSD_TRY(hipEventRecord(h->ev[2 + 2 * l], s));
+            for (int it = 0; it < p.max_iters[l]; it++)
+                EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, p.tol_px, s));
+            if (tm) EBSD_TRY(hipEventRecord(h->ev[3 + 2 * l], s));
+            EBSD_TRY(launch_level_end(d_bk, b, l, p.max_iters[l], p.tol_px, s));
+            if (l > 0) EBSD_TRY(launch_prolong_level(d_bk, b, l, s));
+        }
+        EBSD_TRY(launch_sample_q1(d_bk, b, s));
+        if (want_field)
+            EBSD_TRY(launch_copy_field(d_bk, b, reinterpret_cast<float* const*>(base + o_dst), s));
+        EBSD_TRY(launch_solve_first(d_bk, b, p.tol_px, s));
+        if (p.second_pass) EBSD_TRY(launch_xcf_pairs(d_bk, b, p.window, s));
+        EBSD_TRY(launch_solve_second(d_bk, b, p.second_pass, s));
+    } else {
+        EBSD_TRY(launch_gather_rfin(d_bk, b, rfin_in, s));
+        EBSD_TRY(launch_status_inputs(d_bk, b, s));
+        EBSD_TRY(launch_xcf_pairs(d_bk, b, p.window, s));
+        EBSD_TRY(launch_solve_second(d_bk, b, 1, s));
+    }
+    OutPtrs o;
+    o.F = out->F;
+    o.R = out->R;
+    o.rotvec = out->rotvec;
+    o.Rfin = out->R_finite;
+    o.F1 = mode == Mode::Full ? out->F_first : nullptr;
+    o.q1 = mode == Mode::Full ? out->q1 : nullptr;
+    o.q2 = out->q2;
+    o.ph = out->peak_height;
+    o.iters = mode == Mode::Full ? out->iters : nullptr;
+    o.status = out->status;
+    EBSD_TRY(launch_scatter(d_bk, b, o, s));
+    if (tm) {
+        EBSD_TRY(hipEventRecord(h->ev[1], s));
+        h->timed_call = true;
+        h->timed_levels = L;
+    }
+#undef EBSD_TRY
+    return EBSD_OK;
+}
+
+size_t desc_upper_bound(const HostBucket& hb, int nr)
+{
+    const size_t nb = hb.idx.size(), nref = hb.ref_in.size();
+    return align_up(sizeof(Bucket), 256) + 8 * 256 + sizeof(void*) * (2 * nb + nref) +
+           sizeof(int32_t) * 2 * nb + sizeof(double) * 2 * nr + sizeof(int32_t) * 2 * nr;
+}
+
+int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u_init,
+        const double* rfin_in, const ebsd_outputs* out, void* stream)
+{
+    if (!h || !out) return EBSD_EINVAL;
+    int e = check_pairs(h->p, pairs, n);
+    if (e) return e;
+    if (n == 0) return EBSD_OK;
+    if (mode == Mode::SecondPassOnly && !rfin_in) return EBSD_EINVAL;
+    std::vector<HostBucket> buckets = make_buckets(pairs, n);
+    if (u_init && buckets.size() != 1) return EBSD_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return EBSD_EDEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    size_t need = 0;
+    for (auto& hb : buckets) need += desc_upper_bound(hb, h->p.n_roi);
+    e = ensure_pin(h, need);
+    if (e) return e;
+    size_t off = 0;
+    for (auto& hb : buckets) {
+        size_t used = 0;
+        e = run_bucket(h, hb, mode, u_init, rfin_in, out, s, off, &used);
+        if (e) return e;
+        off = align_up(off + used, 256);
+    }
+    if (hipEventRecord(h->pin_free, s) != hipSuccess) return EBSD_EDEVICE;
+    h->pin_pending = true;
+    return EBSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ebsd_version(void) { return EBSD_ABI_VERSION; }
+
+int ebsd_params_default(ebsd_params* p)
+{
+    if (!p) return EBSD_EINVAL;
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(ebsd_params);
+    p->levels = 3;
+    for (int l = 0; l < EBSD_MAX_LEVELS; l++) p->max_iters[l] = 150;
+    p->sigma_px = 1.0f;
+    p->tol_px = 0.0f;
+    p->pc_x = 0.5f;
+    p->pc_y = 0.5f;
+    p->pc_z = 0.7f;
+    p->n_roi = 20;
+    p->roi_size = 64;
+    p->roi_radius_frac = 0.3f;
+    p->window = 1;
+    p->second_pass = 1;
+    return EBSD_OK;
+}
+
+const char* ebsd_strerror(int code)
+{
+    switch (code) {
+    case EBSD_OK: return "ok";
+    case EBSD_EINVAL: return "invalid argument";
+    case EBSD_ESHAPE: return "unsupported pattern size";
+    case EBSD_EROI: return "ROI outside the pattern or unsupported ROI size";
+    case EBSD_ENOMEM: return "out of memory";
+    case EBSD_EDEVICE: return "HIP runtime error";
+    case EBSD_ENOTSUP: return "not supported";
+    case EBSD_EVERSION: return "ebsd_params.struct_size mismatch";
+    default: return "unknown error";
+    }
+}
+
+int ebsd_create(const ebsd_params* p, int device, ebsd_handle** out)
+{
+    if (!out) return EBSD_EINVAL;
+    *out = nullptr;
+    int e = check_params(p);
+    if (e) return e;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return EBSD_EDEVICE;
+    ebsd_handle* h = new (std::nothrow) ebsd_handle();
+    if (!h) return EBSD_ENOMEM;
+    h->p = *p;
+    h->device = device;
+    // Gaussian taps w_j ~ exp(-j^2 / (2 sigma^2)), j = -r..r, r = floor(3 sigma + 0.5)
+    for (float& t : h->taps) t = 0.0f;
+    if (p->sigma_px > 0.0f) {
+        const double sg = p->sigma_px;
+        h->radius = (int)std::floor(3.0 * sg + 0.5);
+        if (h->radius > kMaxRadius) h->radius = kMaxRadius;
+        double wsum = 0.0, wv[2 * kMaxRadius + 1];
+        for (int j = -h->radius; j <= h->radius; j++) {
+            wv[j + h->radius] = std::exp(-(double)(j * j) / (2.0 * sg * sg));
+            wsum += wv[j + h->radius];
+        }
+        for (int j = 0; j <= 2 * h->radius; j++) h->taps[j] = (float)(wv[j] / wsum);
+    } else {
+        h->radius = 0;
+        h->taps[0] = 1.0f;
+    }
+    DeviceGuard g(device);
+    if (!g.ok || hipEventCreateWithFlags(&h->pin_free, hipEventDisableTiming) != hipSuccess) {
+        delete h;
+        return EBSD_EDEVICE;
+    }
+    *out = h;
+    return EBSD_OK;
+}
+
+int ebsd_destroy(ebsd_handle* h)
+{
+    if (!h) return EBSD_OK;
+    {
+        DeviceGuard g(h->device);
+        (void)hipDeviceSynchronize();
+        if (h->ws) (void)hipFree(h->ws);
+        if (h->pin) (void)hipHostFree(h->pin);
+        if (h->pin_free) (void)hipEventDestroy(h->pin_free);
+        for (auto& e : h->ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    delete h;
+    return EBSD_OK;
+}
+
+int ebsd_set_timing(ebsd_handle* h, int enable)
+{
+    if (!h) return EBSD_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return EBSD_EDEVICE;
+    if (enable && !h->ev[0]) {
+        for (auto& e : h->ev)
+            if (hipEventCreate(&e) != hipSuccess) return EBSD_EDEVICE;
+    }
+    h->timing = enable != 0;
+    return EBSD_OK;
+}
+
+int ebsd_get_timing(ebsd_handle* h, double* level_ms, double* total_ms)
+{
+    if (!h || !h->timed_call) return EBSD_EINVAL;
+    DeviceGuard g(h->device);
+    if (hipEventSynchronize(h->ev[1]) != hipSuccess) return EBSD_EDEVICE;
+    float ms = 0.0f;
+    if (total_ms) {
+        if (hipEventElapsedTime(&ms, h->ev[0], h->ev[1]) != hipSuccess) return EBSD_EDEVICE;
+        *total_ms = ms;
+    }
+    if (level_ms)
+        for (int l = 0; l < h->timed_levels; l++) {
+            if (hipEventElapsedTime(&ms, h->ev[2 + 2 * l], h->ev[3 + 2 * l]) != hipSuccess)
+                return EBSD_EDEVICE;
+            level_ms[l] = ms;
+        }
+    return EBSD_OK;
+}
+
+int ebsd_get_params(const ebsd_handle* h, ebsd_params* out)
+{
+    if (!h || !out) return EBSD_EINVAL;
+    *out = h->p;
+    return EBSD_OK;
+}
+
+int ebsd_roi_layout(const ebsd_params* p, int32_t H, int32_t W, double* cx, double* cy,
+                    int32_t* x0, int32_t* y0)
+{
+    int e = check_params(p);
+    if (e) return e;
+    if (H <= 0 || W <= 0) return EBSD_ESHAPE;
+    return roi_layout(*p, H, W, cx, cy, x0, y0);
+}
+
+int ebsd_register_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
+                        const ebsd_outputs* out, void* stream)
+{
+    return run(h, pairs, n, Mode::Full, nullptr, nullptr, out, stream);
+}
+
+int ebsd_register_batch_init(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
+                             const float* u_init, const ebsd_outputs* out, void* stream)
+{
+    return run(h, pairs, n, Mode::Full, u_init, nullptr, out, stream);
+}
+
+int ebsd_second_pass_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
+                           const double* R_finite, const ebsd_outputs* out, void* stream)
+{
+    if (!R_finite && n > 0) return EBSD_EINVAL;
+    return run(h, pairs, n, Mode::SecondPassOnly, nullptr, R_finite, out, stream);
+}
+
+int ebsd_stage_normalize(const float* in, int32_t n, int64_t elems, float* out, uint32_t* flags,
+                         void* stream)
+{
+    if (n < 0 || elems <= 0 || (n > 0 && (!in || !out))) return EBSD_EINVAL;
+    if (n == 0) return EBSD_OK;
+    return map_err(launch_stage_normalize(in, n, elems, out, flags, (hipStream_t)stream));
+}
+
+int ebsd_stage_restrict(const float* in, int32_t n, int32_t H, int32_t W, float* out, void* stream)
+{
+    if (n < 0 || (n > 0 && (!in || !out))) return EBSD_EINVAL;
+    if (H < 2 || W < 2 || (H & 1) || (W & 1) || n > 65535) return EBSD_ESHAPE;
+    if (n == 0) return EBSD_OK;
+    return map_err(launch_stage_restrict(in, n, H, W, out, (hipStream_t)stream));
+}
+
+int ebsd_stage_demons_iter(const float* R, const float* T, int32_t n, int32_t H, int32_t W,
+                           const float* u_in, float sigma_px, float* u_out, double* rms,
+                           void* stream)
+{
+    if (n < 0 || (n > 0 && (!R || !T || !u_in || !u_out)) || u_in == u_out) return EBSD_EINVAL;
+    if (!(sigma_px >= 0.0f) || !(sigma_px <= 1.3f)) return EBSD_EINVAL;
+    if (H < 1 || W < 1 || H > 16384 || W > 16384) return EBSD_ESHAPE;
+    if (n == 0) return EBSD_OK;
+    float taps[2 * kMaxRadius + 1] = {0};
+    int radius = 0;
+    if (sigma_px > 0.0f) {
+        radius = (int)std::floor(3.0 * sigma_px + 0.5);
+        double wsum = 0.0, wv[2 * kMaxRadius + 1];
+        for (int j = -radius; j <= radius; j++) {
+            wv[j + radius] = std::exp(-(double)(j * j) / (2.0 * (double)sigma_px * sigma_px));
+            wsum += wv[j + radius];
+        }
+        for (int j = 0; j <= 2 * radius; j++) taps[j] = (float)(wv[j] / wsum);
+    } else {
+        taps[0] = 1.0f;
+    }
+    return map_err(launch_stage_demons_iter(R, T, n, H, W, u_in, taps, radius, u_out, rms,
+                                            (hipStream_t)stream));
+}
+
+int ebsd_stage_prolong(const float* u, int32_t n, int32_t h, int32_t w, float* out, void* stream)
+{
+    if (n < 0 || (n > 0 && (!u || !out))) return EBSD_EINVAL;
+    if (h < 1 || w < 1 || n > 65535) return EBSD_ESHAPE;
+    if (n == 0) return EBSD_OK;
+    return map_err(launch_stage_prolong(u, n, h, w, out, (hipStream_t)stream));
+}
+
+int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t window, float* q,
+                   float* ph, void* stream)
+{
+    if (n < 0 || (n > 0 && (!A || !B || !q))) return EBSD_EINVAL;
+    if (N != 32 && N != 64 && N != 128) return EBSD_EROI;
+    if (window != 0 && window != 1) return EBSD_EINVAL;
+    if (n == 0) return EBSD_OK;
+    return map_err(launch_stage_xcf(A, B, n, N, window, q, ph, (hipStream_t)stream));
+}
+
+int ebsd_stage_solve(const float* q, int32_t n, int32_t n_roi, const double* cx, const double* cy,
+                     double xs, double ys, double zs, double* F, double* R, uint32_t* status,
+                     void* stream)
+{
+    if (n < 0 || (n > 0 && (!q || !cx || !cy || !F))) return EBSD_EINVAL;
+    if (n_roi < 5 || n_roi > 256 || !(zs > 0.0)) return EBSD_EINVAL;
+    if (n == 0) return EBSD_OK;
+    return map_err(launch_stage_solve(q, n, n_roi, cx, cy, xs, ys, zs, F, R, status,
+                                      (hipStream_t)stream));
+}
+
+}  // extern "C"

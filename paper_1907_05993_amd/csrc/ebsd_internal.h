@@ -1,0 +1,158 @@
+// Internal declarations of the gfx950 demons/XCF library: per-bucket device
+// descriptors and the host launchers that each kernel file exports.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ebsd {
+
+constexpr int kMaxLevels = 8;
+constexpr int kMaxRadius = 4;     // Gaussian half-width supported by the demons kernel
+constexpr int kDemonsTX = 64;     // demons output tile: 64 columns (one wavefront per row)
+constexpr int kDemonsTY = 16;     // ... x 16 rows
+constexpr int kDemonsThreads = 256;
+
+// Normalised Gaussian taps w[0..2r] for offsets -r..r.
+struct Taps {
+    float w[2 * kMaxRadius + 1];
+};
+
+// Per-pattern statistics from the normalisation pass.
+struct PatStat {
+    double mean;
+    double inv_std;
+    uint32_t flags;  // EBSD_DEGENERATE_INPUT / EBSD_NONFINITE_INPUT
+    uint32_t pad;
+};
+
+// Per-pair demons state (one entry per pair of a bucket).  No kernel
+// synchronises across workgroups: within a level, iteration k reads the field
+// from buffer (base + k) & 1, and every workgroup of a pair derives the stop
+// decision for iteration k from the per-tile sums of iteration k - 1 itself.
+struct PairState {
+    int32_t base;       // buffer holding the field at iteration 0 of the current level
+    int32_t stop;       // -1 while iterating, else the iteration count at which it stopped
+    int32_t cur;        // buffer holding the pair's field after the level ended
+    uint32_t convmask;  // bit l set when level l stopped on the tolerance
+};
+
+// Everything a bucket's kernels need, in device memory (one copy per bucket).
+struct Bucket {
+    int32_t nb;                 // pairs in the bucket
+    int32_t nref;               // distinct reference patterns
+    int32_t H, W, L;            // finest size and number of levels
+    int32_t lvl_off[kMaxLevels];// float offset of level l inside one pyramid
+    int64_t pyr_elems;          // floats per pyramid (all levels)
+    const float* const* test_in;// [nb] caller test patterns
+    const float* const* ref_in; // [nref] caller reference patterns
+    const int32_t* ref_slot;    // [nb] reference slot of each pair
+    const int32_t* pair_index;  // [nb] index of the pair in the caller's arrays
+    float* test_pyr;            // [nb][pyr_elems]
+    float* ref_pyr;             // [nref][pyr_elems]
+    PatStat* test_stat;         // [nb]
+    PatStat* ref_stat;          // [nref]
+    float* field[2];            // [nb][2][H][W] each (level l uses the leading 2 h w)
+    PairState* state;           // [nb]
+    float* partial;             // [2][nb][max tiles] per-tile sums of squared updates (by iteration parity)
+    int32_t max_tiles;          // tiles of the finest level
+    int32_t* iters;             // [nb][L]
+    int32_t n_roi, roi_N;
+    const double* roi_c;        // [n_roi][2] ROI centres (x, y)
+    const int32_t* roi_xy;      // [n_roi][2] ROI top-left (x0, y0)
+    double xs, ys, zs;          // pattern centre and detector distance, px
+    float* q1;                  // [nb][n_roi][2]
+    float* q2;                  // [nb][n_roi][2]
+    float* ph;                  // [nb][n_roi]
+    double* F1;                 // [nb][9]
+    double* Rfin;               // [nb][9]
+    double* F;                  // [nb][9]
+    double* R;                  // [nb][9]
+    double* rotvec;             // [nb][3]
+    uint32_t* status;           // [nb]
+};
+
+// ---- launchers (defined next to their kernels) -------------------------------
+
+// Normalisation statistics for nb test patterns and nref reference patterns.
+hipError_t launch_stats(const Bucket* d_bk, int nb, int nref, hipStream_t s);
+// Normalise level 0 of every pyramid and build levels 1..L-1.
+hipError_t launch_pyramids(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
+// Reset per-pair state and set the coarsest-level initial field
+// (u_init [nb][2][h][w] in full-res px, or zero).
+hipError_t launch_demons_init(const Bucket* d_bk, const Bucket& hb, const float* u_init,
+                              hipStream_t s);
+// Iteration k (0-based) of level l for every pair that has not stopped.
+hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, int k,
+                              const float* taps, int radius, float tol, hipStream_t s);
+// Close level l: iteration counts, convergence of the last iteration, final buffer.
+hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int cap, float tol,
+                            hipStream_t s);
+// Prolong the field of every pair from level l to level l-1 and re-arm the pairs.
+hipError_t launch_prolong_level(const Bucket* d_bk, const Bucket& hb, int level, hipStream_t s);
+// Sample the finest field at the ROI centres -> q1.
+hipError_t launch_sample_q1(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
+// Copy the finest field to the caller (field_ptr[i] = destination of pair i or NULL).
+hipError_t launch_copy_field(const Bucket* d_bk, const Bucket& hb, float* const* d_dst,
+                             hipStream_t s);
+// First-pass solve: F1 from q1 (Eq. (3)), Rfin = polar(F1); status from the
+// input flags and, when tol > 0, the per-level convergence.
+hipError_t launch_solve_first(const Bucket* d_bk, const Bucket& hb, float tol, hipStream_t s);
+// Status from the input flags only (second-pass-only entry).
+hipError_t launch_status_inputs(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
+// Remap + ROI XCF for every (pair, ROI) -> q2, ph.
+hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, hipStream_t s);
+// Rfin[b] = R_finite_in[pair_index[b]] (second-pass-only entry).
+hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, const double* rfin_in,
+                              hipStream_t s);
+// Caller output pointers (any may be NULL), indexed by the caller's pair index.
+struct OutPtrs {
+    double* F;
+    double* R;
+    double* rotvec;
+    double* Rfin;
+    double* F1;
+    float* q1;
+    float* q2;
+    float* ph;
+    int32_t* iters;
+    uint32_t* status;
+};
+hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, const OutPtrs& o, hipStream_t s);
+// Second-pass solve: F_inf from q2, F = F_inf Rfin, det 1, R, rotvec.
+hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass,
+                               hipStream_t s);
+
+// ---- stage launchers -----------------------------------------------------------
+hipError_t launch_stage_normalize(const float* in, int n, int64_t elems, float* out,
+                                  uint32_t* flags, hipStream_t s);
+hipError_t launch_stage_restrict(const float* in, int n, int H, int W, float* out, hipStream_t s);
+hipError_t launch_stage_demons_iter(const float* R, const float* T, int n, int H, int W,
+                                    const float* u_in, const float* taps, int radius,
+                                    float* u_out, double* rms, hipStream_t s);
+hipError_t launch_stage_prolong(const float* u, int n, int h, int w, float* out, hipStream_t s);
+hipError_t launch_stage_xcf(const float* A, const float* B, int n, int N, int window, float* q,
+                            float* ph, hipStream_t s);
+hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx,
+                              const double* cy, double xs, double ys, double zs, double* F,
+                              double* R, uint32_t* status, hipStream_t s);
+
+// Number of demons tiles of an h x w level (2-D tile kernel).
+inline int demons_tiles(int h, int w)
+{
+    return ((w + kDemonsTX - 1) / kDemonsTX) * ((h + kDemonsTY - 1) / kDemonsTY);
+}
+
+// Row-marching kernel (levels up to 256 px wide): columns per lane (0 = not
+// applicable), number of row strips, and its launchers (false if not applicable).
+int rows_cpl(int w);
+int rows_units(int h);
+bool launch_demons_rows(const Bucket* d_bk, const Bucket& hb, int level, int k, const Taps& tp,
+                        int radius, float tol, hipStream_t s);
+bool launch_demons_rows_stage(const float* R, const float* T, int n, int h, int w, const float* u,
+                              const Taps& tp, int radius, float* un, double* rms, hipStream_t s);
+
+// Work units (and per-pair partial sums) of one demons iteration at h x w.
+inline int demons_units(int h, int w) { return rows_cpl(w) ? rows_units(h) : demons_tiles(h, w); }
+
+}  // namespace ebsd

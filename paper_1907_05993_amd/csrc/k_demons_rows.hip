@@ -1,0 +1,302 @@
+// Row-marching demons iteration for gfx950 (multi-resolution demons of
+// arXiv:1907.05993 section 1, Eq. (1) force), used for levels up to 256 px wide.
+//
+// One workgroup of 64 NW threads (NW = 4 wavefronts for 256 px, 2 for 128 px,
+// 1 for 64 px) owns a strip of TY output rows of one pair; thread t owns column
+// t, so a workgroup spans a whole row and every memory instruction is
+// contiguous across the lanes.
+// Marching down the strip, for each row y = y0 - r .. y0 + TY - 1 + r:
+//   v = u + a grad R / (|grad R|^2 + a^2),  a = R - T(x + u)  (bilinear, clamped;
+//       central differences inside, one-sided on the border);
+//   horizontal Gaussian taps from a per-wavefront LDS row (border replicated);
+//   the filtered row enters a ring of 2r + 1 rows held in registers, and the
+//   vertical taps over the ring give u_new of row y - r.
+// Two workgroup barriers per row, no 2-D tiles; the redundant work is the 2r halo
+// rows per strip, (TY + 2r) / TY.  Per pixel: u (8 B) + R (4 B) + T (4 B gather)
+// read, u_new (8 B) written = 24 B from HBM; the other R rows and the halo hit
+// the caches.  Strips of one pair are placed on one XCD.
+#include "dev_util.h"
+
+namespace ebsd {
+
+namespace {
+
+// One demons iteration over output rows [y0, y0 + TY) of one image pair by a
+// workgroup of 64 NW threads; thread t owns column t (w <= 64 NW), so every
+// load, gather and store instruction touches consecutive addresses.
+//
+// Software pipeline per row step: issue the row's T gathers, then prefetch the
+// next row's u and its one new R row; the gradient's x-neighbours come from the
+// workgroup's LDS copy of the R row, the horizontal taps from its LDS copy of v
+// (both double-buffered by row parity, so one barrier per row suffices).  The
+// two other R rows and the u rows of the last 2r + 1 steps stay in registers.
+// Returns the workgroup's sum of |u_new - u|^2 (all threads) when want_ss.
+template <int NW, int RAD, int TY>
+__device__ float demons_strip(const float* __restrict__ Rg, const float* __restrict__ Tg,
+                              const float* __restrict__ ug, float* __restrict__ ung, int h, int w,
+                              int y0, const Taps& tp, bool want_ss)
+{
+    const EBSD_GLOBAL float* __restrict__ R = gptr(Rg);
+    const EBSD_GLOBAL float* __restrict__ T = gptr(Tg);
+    const EBSD_GLOBAL float* __restrict__ u = gptr(ug);
+    EBSD_GLOBAL float* __restrict__ un = gptr(ung);
+    constexpr int NR = 2 * RAD + 1;  // ring rows
+    constexpr int STEPS = TY + 2 * RAD;
+    constexpr int RW = 64 * NW;      // LDS row length
+    __shared__ float lds_v[2][2][RW];  // [parity][channel][column]
+    __shared__ float lds_r[2][RW];     // [parity][column]
+    __shared__ float red[NW];
+    const int c = threadIdx.x;
+    const bool in = c < w;
+    const int x = in ? c : w - 1;
+    const int xm = max(x - 1, 0), xp = min(x + 1, w - 1);
+    const float sx = (xp - xm == 2) ? 0.5f : 1.0f;
+    int tap_col[2 * RAD + 1];
+#pragma unroll
+    for (int j = 0; j <= 2 * RAD; j++) tap_col[j] = clampi(x + j - RAD, 0, w - 1);
+    const int64_t hw = (int64_t)h * w;
+    const EBSD_GLOBAL float* __restrict__ uy_src = u + hw;
+
+    // rows of step 0 (y = y0 - RAD)
+    int yc = clampi(y0 - RAD, 0, h - 1);
+    int ym = max(yc - 1, 0), yp = min(yc + 1, h - 1);
+    float r_m = R[(int64_t)ym * w + x];
+    float r_c = R[(int64_t)yc * w + x];
+    float r_p = R[(int64_t)yp * w + x];
+    float ux = u[(int64_t)yc * w + x];
+    float uy = uy_src[(int64_t)yc * w + x];
+    lds_r[0][c] = r_c;
+    __syncthreads();
+
+    float ring_x[NR], ring_y[NR], ring_ux[NR], ring_uy[NR];
+    float ss = 0.0f;
+
+#pragma unroll 1
+    for (int base = 0; base < STEPS; base += NR) {
+#pragma unroll
+        for (int s = 0; s < NR; s++) {
+            const int step = base + s;
+            if (step >= STEPS) break;  // uniform
+            const int par = step & 1;
+            const int y = y0 - RAD + step;
+            // 1. gathers of this row
+            const float wv = bilinear_clamped(T, h, w, (float)x + ux, (float)yc + uy);
+            // 2. prefetch the next row (rows ym/yc of the next step are this
+            //    step's yc/yp, or repeat at a clamped border)
+            const bool more = step + 1 < STEPS;
+            const int nyc = clampi(y + 1, 0, h - 1);
+            const int nym = max(nyc - 1, 0), nyp = min(nyc + 1, h - 1);
+            float n_rp = 0.0f, n_ux = 0.0f, n_uy = 0.0f;
+            if (more) {
+                n_rp = R[(int64_t)nyp * w + x];
+                n_ux = u[(int64_t)nyc * w + x];
+                n_uy = uy_src[(int64_t)nyc * w + x];
+            }
+            const float n_rm = (nym == yc) ? r_c : (nym == yp ? r_p : r_m);
+            const float n_rc = (nyc == yp) ? r_p : r_c;
+            // 3. force
+            const float sy = (yp - ym == 2) ? 0.5f : 1.0f;
+            const float gyr = (r_p - r_m) * sy;
+            const float gxr = (lds_r[par][xp] - lds_r[par][xm]) * sx;
+            const float a = r_c - wv;
+            const float den = gxr * gxr + gyr * gyr + a * a;
+            float dux = 0.0f, duy = 0.0f;
+            if (den > 1e-9f) {
+                const float q = a * __builtin_amdgcn_rcpf(den);
+                dux = q * gxr;
+                duy = q * gyr;
+            }
+            lds_v[par][0][c] = ux + dux;
+            lds_v[par][1][c] = uy + duy;
+            if (more) lds_r[par ^ 1][c] = n_rc;
+            ring_ux[s] = ux;
+            ring_uy[s] = uy;
+            __syncthreads();
+            // 4. horizontal taps at clamped columns
+            float ax = 0.0f, ay = 0.0f;
+#pragma unroll
+            for (int j = 0; j <= 2 * RAD; j++) {
+                ax += tp.w[j] * lds_v[par][0][tap_col[j]];
+                ay += tp.w[j] * lds_v[par][1][tap_col[j]];
+            }
+            ring_x[s] = ax;
+            ring_y[s] = ay;
+            // 5. vertical taps over the ring: output row y - RAD
+            if (step >= 2 * RAD) {
+                const int yo = y - RAD;
+                if (yo < h && in) {
+                    float ox = 0.0f, oy = 0.0f;
+#pragma unroll
+                    for (int j = 0; j <= 2 * RAD; j++) {
+                        // row yo - RAD + j was computed at step (step - 2 RAD + j)
+                        const int slot = (s + 1 + j) % NR;
+                        ox += tp.w[j] * ring_x[slot];
+                        oy += tp.w[j] * ring_y[slot];
+                    }
+                    if (want_ss) {
+                        // u of row yo was read at step (step - RAD)
+                        const int us = (s + RAD + 1) % NR;
+                        const float dx = ox - ring_ux[us], dy = oy - ring_uy[us];
+                        ss += dx * dx + dy * dy;
+                    }
+                    const int64_t o = (int64_t)yo * w + c;
+                    un[o] = ox;
+                    un[hw + o] = oy;
+                }
+            }
+            // 6. rotate
+            r_m = n_rm;
+            r_c = n_rc;
+            r_p = n_rp;
+            ux = n_ux;
+            uy = n_uy;
+            ym = nym;
+            yc = nyc;
+            yp = nyp;
+        }
+    }
+    if (!want_ss) return 0.0f;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if ((c & 63) == 0) red[c >> 6] = ss;
+    __syncthreads();
+    float tot = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NW; i++) tot += red[i];
+    __syncthreads();
+    return tot;
+}
+
+template <int NW, int RAD, int TY>
+__global__ void __launch_bounds__(64 * NW)
+    k_demons_rows(const Bucket* __restrict__ bk, int level, int k, Taps tp, float tol, int nstrips)
+{
+    __shared__ double sh_sum;
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int b = lb / nstrips;
+    const int strip = lb - b * nstrips;
+    const PairState st = bk->state[b];
+    if (st.stop >= 0) return;  // uniform
+    const int h = bk->H >> level, w = bk->W >> level;
+    const int64_t npart = (int64_t)bk->nb * bk->max_tiles;
+    if (tol > 0.0f && k > 0) {
+        const float* prev = bk->partial + ((k - 1) & 1) * npart + (int64_t)b * bk->max_tiles;
+        const double ss = pair_sum(prev, nstrips, &sh_sum);
+        const double delta = sqrt(ss / ((double)h * (double)w)) * (double)(1 << level);
+        if (delta < (double)tol) {
+            if (strip == 0 && threadIdx.x == 0) {
+                bk->state[b].stop = k;
+                bk->state[b].convmask = st.convmask | (1u << level);
+            }
+            return;
+        }
+    }
+    const int64_t slot = (int64_t)b * 2 * bk->H * bk->W;
+    const float* R = bk->ref_pyr + (int64_t)bk->ref_slot[b] * bk->pyr_elems + bk->lvl_off[level];
+    const float* T = bk->test_pyr + (int64_t)b * bk->pyr_elems + bk->lvl_off[level];
+    const float* u = bk->field[(st.base + k) & 1] + slot;
+    float* un = bk->field[(st.base + k + 1) & 1] + slot;
+    const float ss = demons_strip<NW, RAD, TY>(R, T, u, un, h, w, strip * TY, tp, tol > 0.0f);
+    if (tol > 0.0f && threadIdx.x == 0)
+        bk->partial[(k & 1) * npart + (int64_t)b * bk->max_tiles + strip] = ss;
+}
+
+// Stand-alone variant: one workgroup per pair walks its strips in order.
+template <int NW, int RAD, int TY>
+__global__ void __launch_bounds__(64 * NW)
+    k_demons_rows_stage(const float* __restrict__ R, const float* __restrict__ T, int h, int w,
+                        const float* __restrict__ u, Taps tp, float* __restrict__ un,
+                        double* __restrict__ rms)
+{
+    const int b = blockIdx.x;
+    const int64_t hw = (int64_t)h * w;
+    double acc = 0.0;
+    for (int y0 = 0; y0 < h; y0 += TY)
+        acc += (double)demons_strip<NW, RAD, TY>(R + b * hw, T + b * hw, u + 2 * b * hw,
+                                                  un + 2 * b * hw, h, w, y0, tp, true);
+    if (rms && threadIdx.x == 0) rms[b] = sqrt(acc / (double)hw);
+}
+
+constexpr int kRowsTY = 32;
+
+template <int CPL, int RAD>
+void launch_rows(const Bucket* d_bk, int nb, int h, int level, int k, const Taps& tp, float tol,
+                 hipStream_t s)
+{
+    const int nstrips = (h + kRowsTY - 1) / kRowsTY;
+    hipLaunchKernelGGL((k_demons_rows<CPL, RAD, kRowsTY>), dim3(nb * nstrips), dim3(64 * CPL), 0, s, d_bk,
+                       level, k, tp, tol, nstrips);
+}
+
+template <int CPL>
+bool dispatch_rad(const Bucket* d_bk, int nb, int h, int level, int k, const Taps& tp, int radius,
+                  float tol, hipStream_t s)
+{
+    switch (radius) {
+    case 0: launch_rows<CPL, 0>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    case 1: launch_rows<CPL, 1>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    case 2: launch_rows<CPL, 2>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    case 3: launch_rows<CPL, 3>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    case 4: launch_rows<CPL, 4>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    default: return false;
+    }
+}
+
+template <int CPL, int RAD>
+void launch_rows_stage(const float* R, const float* T, int n, int h, int w, const float* u,
+                       const Taps& tp, float* un, double* rms, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_demons_rows_stage<CPL, RAD, kRowsTY>), dim3(n), dim3(64 * CPL), 0, s, R, T, h, w,
+                       u, tp, un, rms);
+}
+
+template <int CPL>
+bool dispatch_rad_stage(const float* R, const float* T, int n, int h, int w, const float* u,
+                        const Taps& tp, int radius, float* un, double* rms, hipStream_t s)
+{
+    switch (radius) {
+    case 0: launch_rows_stage<CPL, 0>(R, T, n, h, w, u, tp, un, rms, s); return true;
+    case 1: launch_rows_stage<CPL, 1>(R, T, n, h, w, u, tp, un, rms, s); return true;
+    case 2: launch_rows_stage<CPL, 2>(R, T, n, h, w, u, tp, un, rms, s); return true;
+    case 3: launch_rows_stage<CPL, 3>(R, T, n, h, w, u, tp, un, rms, s); return true;
+    case 4: launch_rows_stage<CPL, 4>(R, T, n, h, w, u, tp, un, rms, s); return true;
+    default: return false;
+    }
+}
+
+}  // namespace
+
+int rows_cpl(int w)
+{
+    if (w <= 64) return 1;
+    if (w <= 128) return 2;
+    if (w <= 256) return 4;
+    return 0;
+}
+
+int rows_units(int h) { return (h + kRowsTY - 1) / kRowsTY; }
+
+bool launch_demons_rows(const Bucket* d_bk, const Bucket& hb, int level, int k, const Taps& tp,
+                        int radius, float tol, hipStream_t s)
+{
+    const int h = hb.H >> level, w = hb.W >> level;
+    switch (rows_cpl(w)) {
+    case 1: return dispatch_rad<1>(d_bk, hb.nb, h, level, k, tp, radius, tol, s);
+    case 2: return dispatch_rad<2>(d_bk, hb.nb, h, level, k, tp, radius, tol, s);
+    case 4: return dispatch_rad<4>(d_bk, hb.nb, h, level, k, tp, radius, tol, s);
+    default: return false;
+    }
+}
+
+bool launch_demons_rows_stage(const float* R, const float* T, int n, int h, int w, const float* u,
+                              const Taps& tp, int radius, float* un, double* rms, hipStream_t s)
+{
+    switch (rows_cpl(w)) {
+    case 1: return dispatch_rad_stage<1>(R, T, n, h, w, u, tp, radius, un, rms, s);
+    case 2: return dispatch_rad_stage<2>(R, T, n, h, w, u, tp, radius, un, rms, s);
+    case 4: return dispatch_rad_stage<4>(R, T, n, h, w, u, tp, radius, un, rms, s);
+    default: return false;
+    }
+}
+
+}  // namespace ebsd

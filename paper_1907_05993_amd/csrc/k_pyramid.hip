@@ -1,0 +1,361 @@
+// Normalisation, pyramid restriction / prolongation and field bookkeeping
+// kernels (multi-resolution demons, section 1 of arXiv:1907.05993).
+//
+// All of these are HBM-streaming passes that touch each pattern a few times per
+// batch; they are far from the hot loop and are written for coalesced access
+// rather than for peak bandwidth.
+#include "dev_util.h"
+
+#include "../../include/ebsd.h"
+
+namespace ebsd {
+
+namespace {
+
+constexpr int kStatThreads = 256;
+
+// Deterministic block sum of one double per thread (fixed tree order).
+__device__ double block_sum(double v, double* sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = kStatThreads / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Mean and 1/std of one pattern in FP64 (two passes: mean, then centred sum
+// of squares).  Non-finite values or zero contrast are flagged.
+__device__ void pattern_stats(const float* __restrict__ p, int64_t n, PatStat* out, double* sh)
+{
+    double s = 0.0;
+    int bad = 0;
+    for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
+        float v = p[i];
+        if (!isfinite(v)) bad = 1;
+        s += (double)v;
+    }
+    double badsum = block_sum((double)bad, sh);
+    double tot = block_sum(s, sh);
+    double mean = tot / (double)n;
+    double ss = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
+        double d = (double)p[i] - mean;
+        ss += d * d;
+    }
+    double var = block_sum(ss, sh) / (double)n;
+    if (threadIdx.x == 0) {
+        PatStat st;
+        st.pad = 0;
+        if (badsum > 0.0) {
+            st.mean = 0.0;
+            st.inv_std = 0.0;
+            st.flags = EBSD_NONFINITE_INPUT;
+        } else {
+            double sd = sqrt(var);
+            if (!(sd > 1e-12 * (fabs(mean) + 1.0))) {
+                st.mean = 0.0;
+                st.inv_std = 0.0;
+                st.flags = EBSD_DEGENERATE_INPUT;
+            } else {
+                st.mean = mean;
+                st.inv_std = 1.0 / sd;
+                st.flags = 0;
+            }
+        }
+        *out = st;
+    }
+}
+
+__global__ void __launch_bounds__(kStatThreads) k_stats(const Bucket* __restrict__ bk)
+{
+    __shared__ double sh[kStatThreads];
+    const int i = blockIdx.x;
+    const int64_t n = (int64_t)bk->H * bk->W;
+    if (i < bk->nb)
+        pattern_stats(bk->test_in[i], n, &bk->test_stat[i], sh);
+    else
+        pattern_stats(bk->ref_in[i - bk->nb], n, &bk->ref_stat[i - bk->nb], sh);
+}
+
+// Level 0 of every pyramid: (p - mean) / std, zeros for flagged patterns.
+__global__ void k_normalize_l0(const Bucket* __restrict__ bk)
+{
+    const int pat = blockIdx.y;
+    const int64_t n = (int64_t)bk->H * bk->W;
+    const float* src;
+    float* dst;
+    PatStat st;
+    if (pat < bk->nb) {
+        src = bk->test_in[pat];
+        dst = bk->test_pyr + (int64_t)pat * bk->pyr_elems;
+        st = bk->test_stat[pat];
+    } else {
+        int r = pat - bk->nb;
+        src = bk->ref_in[r];
+        dst = bk->ref_pyr + (int64_t)r * bk->pyr_elems;
+        st = bk->ref_stat[r];
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.0f;
+        if (st.flags == 0) v = (float)(((double)src[i] - st.mean) * st.inv_std);
+        dst[i] = v;
+    }
+}
+
+// Factor-2 restriction, separable [1,3,3,1]/8 with clamped borders:
+// coarse pixel i is centred on fine 2i + 0.5.  Horizontal pass first.
+__device__ inline float restrict_at(const float* __restrict__ in, int H, int W, int j, int i)
+{
+    float h[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const float* row = in + (int64_t)clampi(2 * j - 1 + k, 0, H - 1) * W;
+        float a = row[clampi(2 * i - 1, 0, W - 1)];
+        float b = row[2 * i];
+        float c = row[2 * i + 1];
+        float d = row[clampi(2 * i + 2, 0, W - 1)];
+        h[k] = (a + 3.0f * b + 3.0f * c + d) / 8.0f;
+    }
+    return (h[0] + 3.0f * h[1] + 3.0f * h[2] + h[3]) / 8.0f;
+}
+
+__global__ void k_restrict_level(const Bucket* __restrict__ bk, int level)
+{
+    const int pat = blockIdx.y;
+    float* base = pat < bk->nb ? bk->test_pyr + (int64_t)pat * bk->pyr_elems
+                               : bk->ref_pyr + (int64_t)(pat - bk->nb) * bk->pyr_elems;
+    const int Hi = bk->H >> (level - 1), Wi = bk->W >> (level - 1);
+    const int h = Hi / 2, w = Wi / 2;
+    const float* in = base + bk->lvl_off[level - 1];
+    float* out = base + bk->lvl_off[level];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)h * w;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int j = (int)(t / w), i = (int)(t % w);
+        out[t] = restrict_at(in, Hi, Wi, j, i);
+    }
+}
+
+__global__ void k_restrict_plain(const float* __restrict__ in, int H, int W,
+                                 float* __restrict__ out)
+{
+    const int pat = blockIdx.y;
+    const int h = H / 2, w = W / 2;
+    const float* src = in + (int64_t)pat * H * W;
+    float* dst = out + (int64_t)pat * h * w;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)h * w;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int j = (int)(t / w), i = (int)(t % w);
+        dst[t] = restrict_at(src, H, W, j, i);
+    }
+}
+
+// Prolongation u_{l-1}(x) = 2 bilinear(u_l, (x - 0.5)/2): half-pixel centres.
+__device__ inline void prolong_one(const float* __restrict__ src, int h, int w,
+                                   float* __restrict__ dst, int64_t t)
+{
+    const int H2 = 2 * h, W2 = 2 * w;
+    const int64_t hw2 = (int64_t)H2 * W2;
+    int c = (int)(t / hw2);
+    int64_t r = t - (int64_t)c * hw2;
+    int y = (int)(r / W2), x = (int)(r % W2);
+    float sx = ((float)x - 0.5f) * 0.5f, sy = ((float)y - 0.5f) * 0.5f;
+    dst[t] = 2.0f * bilinear_clamped(src + (int64_t)c * h * w, h, w, sx, sy);
+}
+
+__global__ void k_prolong_level(const Bucket* __restrict__ bk, int level)
+{
+    const int b = blockIdx.y;
+    const int h = bk->H >> level, w = bk->W >> level;
+    const int cur = bk->state[b].cur;
+    const int64_t slot = (int64_t)b * 2 * bk->H * bk->W;
+    const float* src = bk->field[cur] + slot;
+    float* dst = bk->field[cur ^ 1] + slot;
+    const int64_t n = (int64_t)2 * (2 * h) * (2 * w);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        prolong_one(src, h, w, dst, t);
+}
+
+__global__ void k_rearm(const Bucket* __restrict__ bk)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bk->nb) return;
+    PairState st = bk->state[b];
+    st.base = st.cur ^ 1;  // the prolonged field was written to the other buffer
+    st.stop = -1;
+    bk->state[b] = st;
+}
+
+__global__ void k_prolong_plain(const float* __restrict__ u, int h, int w, float* __restrict__ out)
+{
+    const int b = blockIdx.y;
+    const float* src = u + (int64_t)b * 2 * h * w;
+    float* dst = out + (int64_t)b * 2 * 4 * h * w;
+    const int64_t n = (int64_t)2 * 4 * h * w;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        prolong_one(src, h, w, dst, t);
+}
+
+// Reset demons state; coarsest-level field = u_init / 2^(L-1) or zero.
+__global__ void k_demons_init(const Bucket* __restrict__ bk, const float* __restrict__ u_init)
+{
+    const int b = blockIdx.y;
+    const int L = bk->L;
+    const int h = bk->H >> (L - 1), w = bk->W >> (L - 1);
+    const int64_t n = (int64_t)2 * h * w;
+    float* dst = bk->field[0] + (int64_t)b * 2 * bk->H * bk->W;
+    const float scale = 1.0f / (float)(1 << (L - 1));
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        dst[t] = u_init ? u_init[(int64_t)b * n + t] * scale : 0.0f;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        PairState st;
+        st.base = 0;
+        st.stop = -1;
+        st.cur = 0;
+        st.convmask = 0;
+        bk->state[b] = st;
+        for (int l = 0; l < L; l++) bk->iters[(int64_t)b * L + l] = 0;
+    }
+}
+
+__global__ void k_sample_q1(const Bucket* __restrict__ bk)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= bk->nb * bk->n_roi) return;
+    int b = t / bk->n_roi, j = t % bk->n_roi;
+    const int H = bk->H, W = bk->W;
+    const float* f = bk->field[bk->state[b].cur] + (int64_t)b * 2 * H * W;
+    float cx = (float)bk->roi_c[2 * j], cy = (float)bk->roi_c[2 * j + 1];
+    bk->q1[2 * t] = bilinear_clamped(f, H, W, cx, cy);
+    bk->q1[2 * t + 1] = bilinear_clamped(f + (int64_t)H * W, H, W, cx, cy);
+}
+
+__global__ void k_copy_field(const Bucket* __restrict__ bk, float* const* __restrict__ dsts)
+{
+    const int b = blockIdx.y;
+    float* dst = dsts[b];
+    if (!dst) return;
+    const int64_t n = (int64_t)2 * bk->H * bk->W;
+    const float4* src = reinterpret_cast<const float4*>(bk->field[bk->state[b].cur] + (int64_t)b * n);
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0 && (n & 3) == 0) {
+        float4* d4 = reinterpret_cast<float4*>(dst);
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n / 4;
+             t += (int64_t)gridDim.x * blockDim.x)
+            d4[t] = src[t];
+    } else {
+        const float* s1 = reinterpret_cast<const float*>(src);
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+             t += (int64_t)gridDim.x * blockDim.x)
+            dst[t] = s1[t];
+    }
+}
+
+// Stand-alone normalisation: one block per pattern computes the statistics
+// and writes the normalised pattern.
+__global__ void __launch_bounds__(kStatThreads)
+    k_stage_norm(const float* __restrict__ in, int64_t elems, float* __restrict__ out,
+                 uint32_t* __restrict__ flags)
+{
+    __shared__ double sh[kStatThreads];
+    __shared__ PatStat st;
+    const int p = blockIdx.x;
+    const float* src = in + (int64_t)p * elems;
+    float* dst = out + (int64_t)p * elems;
+    pattern_stats(src, elems, &st, sh);
+    __syncthreads();
+    const PatStat s = st;
+    for (int64_t i = threadIdx.x; i < elems; i += kStatThreads)
+        dst[i] = s.flags ? 0.0f : (float)(((double)src[i] - s.mean) * s.inv_std);
+    if (flags && threadIdx.x == 0) flags[p] = s.flags;
+}
+
+inline unsigned grid_for(int64_t n, int per_pattern_max = 1024)
+{
+    int64_t g = (n + 255) / 256;
+    if (g > per_pattern_max) g = per_pattern_max;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_stats(const Bucket* d_bk, int nb, int nref, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stats, dim3(nb + nref), dim3(kStatThreads), 0, s, d_bk);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramids(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
+{
+    const int npat = hb.nb + hb.nref;
+    int64_t n0 = (int64_t)hb.H * hb.W;
+    hipLaunchKernelGGL(k_normalize_l0, dim3(grid_for(n0, 64), npat), dim3(256), 0, s, d_bk);
+    for (int l = 1; l < hb.L; l++) {
+        int64_t n = (int64_t)(hb.H >> l) * (hb.W >> l);
+        hipLaunchKernelGGL(k_restrict_level, dim3(grid_for(n, 64), npat), dim3(256), 0, s, d_bk, l);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_demons_init(const Bucket* d_bk, const Bucket& hb, const float* u_init,
+                              hipStream_t s)
+{
+    int64_t n = (int64_t)2 * (hb.H >> (hb.L - 1)) * (hb.W >> (hb.L - 1));
+    hipLaunchKernelGGL(k_demons_init, dim3(grid_for(n, 64), hb.nb), dim3(256), 0, s, d_bk, u_init);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_level(const Bucket* d_bk, const Bucket& hb, int level, hipStream_t s)
+{
+    int64_t n = (int64_t)2 * (hb.H >> (level - 1)) * (hb.W >> (level - 1));
+    hipLaunchKernelGGL(k_prolong_level, dim3(grid_for(n, 128), hb.nb), dim3(256), 0, s, d_bk, level);
+    hipLaunchKernelGGL(k_rearm, dim3((hb.nb + 255) / 256), dim3(256), 0, s, d_bk);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_q1(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
+{
+    int n = hb.nb * hb.n_roi;
+    hipLaunchKernelGGL(k_sample_q1, dim3((n + 255) / 256), dim3(256), 0, s, d_bk);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_field(const Bucket* d_bk, const Bucket& hb, float* const* d_dst,
+                             hipStream_t s)
+{
+    int64_t n = (int64_t)2 * hb.H * hb.W / 4;
+    hipLaunchKernelGGL(k_copy_field, dim3(grid_for(n, 64), hb.nb), dim3(256), 0, s, d_bk, d_dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_normalize(const float* in, int n, int64_t elems, float* out,
+                                  uint32_t* flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage_norm, dim3(n), dim3(kStatThreads), 0, s, in, elems, out, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_restrict(const float* in, int n, int H, int W, float* out, hipStream_t s)
+{
+    int64_t m = (int64_t)(H / 2) * (W / 2);
+    hipLaunchKernelGGL(k_restrict_plain, dim3(grid_for(m, 64), n), dim3(256), 0, s, in, H, W, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_prolong(const float* u, int n, int h, int w, float* out, hipStream_t s)
+{
+    int64_t m = (int64_t)2 * 4 * h * w;
+    hipLaunchKernelGGL(k_prolong_plain, dim3(grid_for(m, 128), n), dim3(256), 0, s, u, h, w, out);
+    return hipGetLastError();
+}
+
+}  // namespace ebsd

@@ -1,0 +1,416 @@
+// Per-pair FP64 solves for gfx950 (arXiv:1907.05993 section 2):
+//   Eq. (2) projective model r' = r + q = Z* F r / ((F r) . k), Eq. (3) least
+//   squares over the ROI shifts (direct linear start, then Gauss-Newton on the
+//   8 entries left free by F33 = 1), det F = 1 normalisation (the shifts fix F
+//   only up to scale), rotation R = P Q^T of F = P D Q^T (Eq. (4)-(5)) written as
+//   R = F (F^T F)^(-1/2), composition F = F_inf R_finite (Eq. (12)) and the
+//   rotation vector theta m (axis-angle after Eq. (5)) with theta from atan2 so
+//   small angles keep their digits.
+// One thread per pair: this is a few microseconds of FP64 work per batch.
+#include "ebsd_internal.h"
+
+#include "../../include/ebsd.h"
+
+namespace ebsd {
+
+namespace {
+
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (destroyed);
+// columns of V are the eigenvectors.
+template <int n>
+__device__ void jacobi_eigen(double (&A)[n][n], double (&ev)[n], double (&V)[n][n])
+{
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) V[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; sweep++) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; i++) {
+            diag += A[i][i] * A[i][i];
+            for (int j = i + 1; j < n; j++) off += 2.0 * A[i][j] * A[i][j];
+        }
+        if (off == 0.0 || off <= 1e-30 * (off + diag)) break;
+        for (int p = 0; p < n - 1; p++)
+            for (int q = p + 1; q < n; q++) {
+                const double apq = A[p][q];
+                if (apq == 0.0) continue;
+                const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = rsqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < n; k++) {
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; k++) {
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; k++) {
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = c * vkp - s * vkq;
+                    V[k][q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < n; i++) ev[i] = A[i][i];
+}
+
+__device__ inline double det3(const double* F)
+{
+    return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+           F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+// ROI geometry in units of Z*: r = ((c - x*)/Z*, 1) and p = (c - x* + q)/Z*.
+struct RoiSet {
+    const float* q;      // [n][2] shifts
+    const double* cx;    // centres, element i at cx[i * cs]
+    const double* cy;
+    int cs;
+    int n;
+    double xs, ys, iz;
+    __device__ void get(int i, double& r0, double& r1, double& p0, double& p1) const
+    {
+        const double ax = cx[i * cs] - xs, ay = cy[i * cs] - ys;
+        r0 = ax * iz;
+        r1 = ay * iz;
+        p0 = (ax + (double)q[2 * i]) * iz;
+        p1 = (ay + (double)q[2 * i + 1]) * iz;
+    }
+};
+
+// Normal-equation terms of Eq. (3) at f (F33 = 1) for the ROI set.
+__device__ void gn_terms(const double* f, const RoiSet& rs, double (&JtJ)[8][8], double (&Jte)[8])
+{
+    const int n = rs.n;
+    for (int a = 0; a < 8; a++) {
+        Jte[a] = 0.0;
+        for (int b = 0; b < 8; b++) JtJ[a][b] = 0.0;
+    }
+    for (int i = 0; i < n; i++) {
+        double r0, r1, pxi, pyi;
+        rs.get(i, r0, r1, pxi, pyi);
+        const double n1 = f[0] * r0 + f[1] * r1 + f[2];
+        const double n2 = f[3] * r0 + f[4] * r1 + f[5];
+        const double d = f[6] * r0 + f[7] * r1 + f[8];
+        const double id = 1.0 / d;
+        const double u = n1 * id, v = n2 * id;
+        const double ex = u - pxi, ey = v - pyi;
+        // d(u)/d theta and d(v)/d theta, theta = (F11..F23, F31, F32)
+        double ju[8] = {r0 * id, r1 * id, id, 0.0, 0.0, 0.0, -u * r0 * id, -u * r1 * id};
+        double jv[8] = {0.0, 0.0, 0.0, r0 * id, r1 * id, id, -v * r0 * id, -v * r1 * id};
+        for (int a = 0; a < 8; a++) {
+            Jte[a] += ju[a] * ex + jv[a] * ey;
+            for (int b = a; b < 8; b++) JtJ[a][b] += ju[a] * ju[b] + jv[a] * jv[b];
+        }
+    }
+    for (int a = 0; a < 8; a++)
+        for (int b = 0; b < a; b++) JtJ[a][b] = JtJ[b][a];
+}
+
+// Cholesky solve of the SPD system M x = rhs; false if M is not positive definite.
+__device__ bool cholesky_solve8(double (&M)[8][8], const double (&rhs)[8], double (&x)[8])
+{
+    double Lm[8][8];
+    for (int i = 0; i < 8; i++)
+        for (int j = 0; j <= i; j++) {
+            double s = M[i][j];
+            for (int k = 0; k < j; k++) s -= Lm[i][k] * Lm[j][k];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                Lm[i][i] = sqrt(s);
+            } else {
+                Lm[i][j] = s / Lm[j][j];
+            }
+        }
+    double y[8];
+    for (int i = 0; i < 8; i++) {
+        double s = rhs[i];
+        for (int k = 0; k < i; k++) s -= Lm[i][k] * y[k];
+        y[i] = s / Lm[i][i];
+    }
+    for (int i = 7; i >= 0; i--) {
+        double s = y[i];
+        for (int k = i + 1; k < 8; k++) s -= Lm[k][i] * x[k];
+        x[i] = s / Lm[i][i];
+    }
+    return true;
+}
+
+// Eq. (3) for one shift set.  Writes det-1 F (row-major), returns status bits.
+__device__ uint32_t solve_F(const RoiSet& rs, double* F)
+{
+    const int n = rs.n;
+    uint32_t st = 0;
+    // direct linear start: null vector of the stacked constraints
+    double M[9][9];
+    for (int a = 0; a < 9; a++)
+        for (int b = 0; b < 9; b++) M[a][b] = 0.0;
+    for (int i = 0; i < n; i++) {
+        double rx, ry, px, py;
+        rs.get(i, rx, ry, px, py);
+        const double ra[9] = {rx, ry, 1.0, 0.0, 0.0, 0.0, -px * rx, -px * ry, -px};
+        const double rb[9] = {0.0, 0.0, 0.0, rx, ry, 1.0, -py * rx, -py * ry, -py};
+        for (int a = 0; a < 9; a++)
+            for (int b = a; b < 9; b++) M[a][b] += ra[a] * ra[b] + rb[a] * rb[b];
+    }
+    for (int a = 0; a < 9; a++)
+        for (int b = 0; b < a; b++) M[a][b] = M[b][a];
+    double ev[9], V[9][9];
+    jacobi_eigen<9>(M, ev, V);
+    int k = 0;
+    for (int i = 1; i < 9; i++)
+        if (ev[i] < ev[k]) k = i;
+    double f[9];
+    for (int i = 0; i < 9; i++) f[i] = V[i][k];
+    if (f[8] == 0.0) {
+        st |= EBSD_SOLVE_ILLCOND;
+        f[8] = 1.0;
+    }
+    const double s8 = f[8];
+    for (int i = 0; i < 9; i++) f[i] /= s8;
+    f[8] = 1.0;
+
+    double JtJ[8][8], Jte[8];
+    for (int it = 0; it < 100; it++) {
+        gn_terms(f, rs, JtJ, Jte);
+        double rhs[8], dlt[8];
+        for (int a = 0; a < 8; a++) rhs[a] = -Jte[a];
+        if (!cholesky_solve8(JtJ, rhs, dlt)) {
+            st |= EBSD_SOLVE_ILLCOND;
+            break;
+        }
+        double nrm = 0.0;
+        for (int a = 0; a < 8; a++) {
+            f[a] += dlt[a];
+            nrm += dlt[a] * dlt[a];
+        }
+        if (!isfinite(nrm)) {
+            st |= EBSD_SOLVE_ILLCOND;
+            break;
+        }
+        if (sqrt(nrm) < 1e-14) break;
+    }
+    gn_terms(f, rs, JtJ, Jte);
+    double e8[8], V8[8][8];
+    jacobi_eigen<8>(JtJ, e8, V8);
+    double lo = e8[0], hi = e8[0];
+    for (int a = 1; a < 8; a++) {
+        lo = fmin(lo, e8[a]);
+        hi = fmax(hi, e8[a]);
+    }
+    if (!(lo > 0.0) || hi > 1e12 * lo) st |= EBSD_SOLVE_ILLCOND;
+    const double d = det3(f);
+    if (d > 0.0) {
+        const double s = cbrt(d);
+        for (int i = 0; i < 9; i++) f[i] /= s;
+    } else {
+        st |= EBSD_SOLVE_ILLCOND;
+    }
+    for (int i = 0; i < 9; i++) F[i] = f[i];
+    return st;
+}
+
+// R = F (F^T F)^(-1/2): the rotation of the polar decomposition.
+__device__ void polar_rot(const double* F, double* R)
+{
+    double C[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            C[i][j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+    double ev[3], Q[3][3];
+    jacobi_eigen<3>(C, ev, Q);
+    double Ui[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += Q[i][k] * Q[j][k] / sqrt(ev[k]);
+            Ui[i][j] = s;
+        }
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            R[3 * i + j] = F[3 * i] * Ui[0][j] + F[3 * i + 1] * Ui[1][j] + F[3 * i + 2] * Ui[2][j];
+}
+
+__device__ void rotation_vector(const double* R, double* rv)
+{
+    const double w0 = 0.5 * (R[7] - R[5]), w1 = 0.5 * (R[2] - R[6]), w2 = 0.5 * (R[3] - R[1]);
+    const double s = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    const double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    if (s == 0.0) {
+        rv[0] = rv[1] = rv[2] = 0.0;
+        return;
+    }
+    const double th = atan2(s, c) / s;
+    rv[0] = th * w0;
+    rv[1] = th * w1;
+    rv[2] = th * w2;
+}
+
+__device__ RoiSet bucket_rois(const Bucket* bk, const float* q)
+{
+    RoiSet rs;
+    rs.q = q;
+    rs.cx = bk->roi_c;
+    rs.cy = bk->roi_c + 1;
+    rs.cs = 2;
+    rs.n = bk->n_roi;
+    rs.xs = bk->xs;
+    rs.ys = bk->ys;
+    rs.iz = 1.0 / bk->zs;
+    return rs;
+}
+
+__global__ void k_solve_first(const Bucket* __restrict__ bk, float tol)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bk->nb) return;
+    uint32_t st = bk->test_stat[b].flags | bk->ref_stat[bk->ref_slot[b]].flags;
+    if (tol > 0.0f) {
+        const uint32_t all = (bk->L >= 32) ? 0xffffffffu : ((1u << bk->L) - 1u);
+        if ((bk->state[b].convmask & all) == all) st |= EBSD_CONVERGED;
+        else st |= EBSD_HIT_CAP;
+    }
+    double* F1 = bk->F1 + 9 * (int64_t)b;
+    st |= solve_F(bucket_rois(bk, bk->q1 + 2 * (int64_t)b * bk->n_roi), F1);
+    polar_rot(F1, bk->Rfin + 9 * (int64_t)b);
+    bk->status[b] = st;
+}
+
+// Status for the second-pass-only entry: input flags only.
+__global__ void k_status_inputs(const Bucket* __restrict__ bk)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bk->nb) return;
+    bk->status[b] = bk->test_stat[b].flags | bk->ref_stat[bk->ref_slot[b]].flags;
+}
+
+__global__ void k_solve_second(const Bucket* __restrict__ bk, int second_pass)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bk->nb) return;
+    const double* Rf = bk->Rfin + 9 * (int64_t)b;
+    double* F = bk->F + 9 * (int64_t)b;
+    uint32_t st = bk->status[b];
+    if (second_pass) {
+        double Fi[9];
+        st |= solve_F(bucket_rois(bk, bk->q2 + 2 * (int64_t)b * bk->n_roi), Fi);
+        double Ft[9];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++)
+                Ft[3 * i + j] = Fi[3 * i] * Rf[j] + Fi[3 * i + 1] * Rf[3 + j] + Fi[3 * i + 2] * Rf[6 + j];
+        const double d = det3(Ft);
+        if (d > 0.0) {
+            const double s = cbrt(d);
+            for (int i = 0; i < 9; i++) Ft[i] /= s;
+        }
+        for (int i = 0; i < 9; i++) F[i] = Ft[i];
+    } else {
+        const double* F1 = bk->F1 + 9 * (int64_t)b;
+        for (int i = 0; i < 9; i++) F[i] = F1[i];
+    }
+    double* R = bk->R + 9 * (int64_t)b;
+    polar_rot(F, R);
+    rotation_vector(R, bk->rotvec + 3 * (int64_t)b);
+    bk->status[b] = st;
+}
+
+__global__ void k_stage_solve(const float* __restrict__ q, int n, int n_roi,
+                              const double* __restrict__ cx, const double* __restrict__ cy,
+                              double xs, double ys, double zs, double* __restrict__ F,
+                              double* __restrict__ R, uint32_t* __restrict__ status)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    RoiSet rs;
+    rs.q = q + 2 * (int64_t)b * n_roi;
+    rs.cx = cx;
+    rs.cy = cy;
+    rs.cs = 1;
+    rs.n = n_roi;
+    rs.xs = xs;
+    rs.ys = ys;
+    rs.iz = 1.0 / zs;
+    uint32_t st = solve_F(rs, F + 9 * (int64_t)b);
+    if (R) polar_rot(F + 9 * (int64_t)b, R + 9 * (int64_t)b);
+    if (status) status[b] = st;
+}
+
+__global__ void k_gather_rfin(const Bucket* __restrict__ bk, const double* __restrict__ rin)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bk->nb) return;
+    const int64_t src = 9 * (int64_t)bk->pair_index[b];
+    for (int i = 0; i < 9; i++) bk->Rfin[9 * (int64_t)b + i] = rin[src + i];
+}
+
+__global__ void k_scatter(const Bucket* __restrict__ bk, OutPtrs o)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bk->nb) return;
+    const int64_t g = bk->pair_index[b];
+    const int nr = bk->n_roi;
+    for (int i = 0; i < 9; i++) {
+        if (o.F) o.F[9 * g + i] = bk->F[9 * (int64_t)b + i];
+        if (o.R) o.R[9 * g + i] = bk->R[9 * (int64_t)b + i];
+        if (o.Rfin) o.Rfin[9 * g + i] = bk->Rfin[9 * (int64_t)b + i];
+        if (o.F1) o.F1[9 * g + i] = bk->F1[9 * (int64_t)b + i];
+    }
+    if (o.rotvec)
+        for (int i = 0; i < 3; i++) o.rotvec[3 * g + i] = bk->rotvec[3 * (int64_t)b + i];
+    for (int j = 0; j < 2 * nr; j++) {
+        if (o.q1) o.q1[2 * nr * g + j] = bk->q1[2 * nr * (int64_t)b + j];
+        if (o.q2) o.q2[2 * nr * g + j] = bk->q2[2 * nr * (int64_t)b + j];
+    }
+    if (o.ph)
+        for (int j = 0; j < nr; j++) o.ph[nr * g + j] = bk->ph[nr * (int64_t)b + j];
+    if (o.iters)
+        for (int l = 0; l < bk->L; l++) o.iters[bk->L * g + l] = bk->iters[bk->L * (int64_t)b + l];
+    if (o.status) o.status[g] = bk->status[b];
+}
+
+}  // namespace
+
+hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, const double* rfin_in,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_rfin, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, rfin_in);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, const OutPtrs& o, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_first(const Bucket* d_bk, const Bucket& hb, float tol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_solve_first, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_inputs(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_status_inputs, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_solve_second, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, second_pass);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx, const double* cy,
+                              double xs, double ys, double zs, double* F, double* R,
+                              uint32_t* status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage_solve, dim3((n + 63) / 64), dim3(64), 0, s, q, n, n_roi, cx, cy, xs,
+                       ys, zs, F, R, status);
+    return hipGetLastError();
+}
+
+}  // namespace ebsd

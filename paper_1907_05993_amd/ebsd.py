@@ -1,0 +1,392 @@
+"""Python binding of the gfx950 HIP library (``lib/libebsd.so``, C ABI in ``include/ebsd.h``).
+
+Argument marshalling only: every step of the registration runs in the library's
+HIP kernels.  PyTorch provides device memory and the current stream.  If the
+library has not been built this module raises instead of falling back to
+anything else.
+
+Method: Zhu, Kaufmann & Vecchio, arXiv:1907.05993 -- multi-resolution demons
+(section 1, Eq. (1)), shifts at ROI centres and the Eq. (2)-(3) solve for F
+(section 2), R = P Q^T (Eq. (4)-(5)), remap + second-pass cross-correlation,
+F = F_inf R_finite (Eq. (12)).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libebsd.so")
+
+EBSD_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "EROI", -4: "ENOMEM", -5: "EDEVICE", -6: "ENOTSUP",
+          -8: "EVERSION"}
+CONVERGED, HIT_CAP, SOLVE_ILLCOND, NONFINITE_INPUT, DEGENERATE_INPUT = 1, 2, 16, 32, 64
+MAX_LEVELS = 8
+
+
+class EbsdError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {ERRORS.get(code, code)} ({_strerror(code)})")
+
+
+class CParams(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("levels", C.c_int32),
+        ("max_iters", C.c_int32 * MAX_LEVELS),
+        ("sigma_px", C.c_float),
+        ("tol_px", C.c_float),
+        ("pc_x", C.c_double),
+        ("pc_y", C.c_double),
+        ("pc_z", C.c_double),
+        ("n_roi", C.c_int32),
+        ("roi_size", C.c_int32),
+        ("roi_radius_frac", C.c_double),
+        ("window", C.c_int32),
+        ("second_pass", C.c_int32),
+    ]
+
+
+class CPair(C.Structure):
+    _fields_ = [("ref", C.c_void_p), ("test", C.c_void_p), ("H", C.c_int32), ("W", C.c_int32),
+                ("ref_id", C.c_int32)]
+
+
+class COutputs(C.Structure):
+    _fields_ = [
+        ("field", C.c_void_p),
+        ("field_offset", C.c_void_p),
+        ("F", C.c_void_p),
+        ("R", C.c_void_p),
+        ("rotvec", C.c_void_p),
+        ("R_finite", C.c_void_p),
+        ("F_first", C.c_void_p),
+        ("q1", C.c_void_p),
+        ("q2", C.c_void_p),
+        ("peak_height", C.c_void_p),
+        ("iters", C.c_void_p),
+        ("status", C.c_void_p),
+    ]
+
+
+_lib = None
+
+EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create", "ebsd_destroy",
+            "ebsd_get_params", "ebsd_roi_layout", "ebsd_register_batch",
+            "ebsd_register_batch_init", "ebsd_second_pass_batch", "ebsd_stage_normalize",
+            "ebsd_stage_restrict", "ebsd_stage_demons_iter", "ebsd_stage_prolong",
+            "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_set_timing", "ebsd_get_timing"]
+
+
+def lib():
+    """Load libebsd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run paper_1907_05993_amd/build.py or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.ebsd_version.restype = C.c_int
+        L.ebsd_params_default.argtypes = [C.POINTER(CParams)]
+        L.ebsd_strerror.restype = C.c_char_p
+        L.ebsd_strerror.argtypes = [C.c_int]
+        L.ebsd_create.argtypes = [C.POINTER(CParams), C.c_int, C.POINTER(vp)]
+        L.ebsd_destroy.argtypes = [vp]
+        L.ebsd_get_params.argtypes = [vp, C.POINTER(CParams)]
+        L.ebsd_roi_layout.argtypes = [C.POINTER(CParams), i32, i32, vp, vp, vp, vp]
+        L.ebsd_register_batch.argtypes = [vp, C.POINTER(CPair), i32, C.POINTER(COutputs), vp]
+        L.ebsd_register_batch_init.argtypes = [vp, C.POINTER(CPair), i32, vp, C.POINTER(COutputs), vp]
+        L.ebsd_second_pass_batch.argtypes = [vp, C.POINTER(CPair), i32, vp, C.POINTER(COutputs), vp]
+        L.ebsd_set_timing.argtypes = [vp, C.c_int]
+        L.ebsd_get_timing.argtypes = [vp, vp, vp]
+        L.ebsd_stage_normalize.argtypes = [vp, i32, i64, vp, vp, vp]
+        L.ebsd_stage_restrict.argtypes = [vp, i32, i32, i32, vp, vp]
+        L.ebsd_stage_demons_iter.argtypes = [vp, vp, i32, i32, i32, vp, C.c_float, vp, vp, vp]
+        L.ebsd_stage_prolong.argtypes = [vp, i32, i32, i32, vp, vp]
+        L.ebsd_stage_xcf.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
+        L.ebsd_stage_solve.argtypes = [vp, i32, i32, vp, vp, C.c_double, C.c_double, C.c_double,
+                                       vp, vp, vp, vp]
+        for name in EXPORTED:
+            if name != "ebsd_strerror" and name != "ebsd_version":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _strerror(code):
+    try:
+        return lib().ebsd_strerror(int(code)).decode()
+    except Exception:  # library missing: no text available
+        return "?"
+
+
+def _check(code, what):
+    if code != EBSD_OK:
+        raise EbsdError(code, what)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Params:
+    """Mirror of ebsd_params with the library defaults."""
+    levels: int = 3
+    iters: tuple = (150, 150, 150)
+    sigma_px: float = 1.0
+    tol_px: float = 0.0
+    pc: tuple = (0.5, 0.5, 0.7)
+    n_roi: int = 20
+    roi_size: int = 64
+    roi_radius_frac: float = 0.3
+    window: int = 1
+    second_pass: int = 1
+
+    def to_c(self):
+        p = CParams()
+        p.struct_size = C.sizeof(CParams)
+        p.levels = self.levels
+        its = list(self.iters) if not isinstance(self.iters, int) else [self.iters] * self.levels
+        its = its + [0] * (MAX_LEVELS - len(its))
+        for i in range(MAX_LEVELS):
+            p.max_iters[i] = int(its[i])
+        p.sigma_px = self.sigma_px
+        p.tol_px = self.tol_px
+        p.pc_x, p.pc_y, p.pc_z = self.pc
+        p.n_roi = self.n_roi
+        p.roi_size = self.roi_size
+        p.roi_radius_frac = self.roi_radius_frac
+        p.window = self.window
+        p.second_pass = self.second_pass
+        return p
+
+
+def roi_layout(params: Params, H, W):
+    """ROI centres (cx, cy) and corners (x0, y0) as computed by the library."""
+    import numpy as np
+    n = params.n_roi
+    cx = np.empty(n, np.float64)
+    cy = np.empty(n, np.float64)
+    x0 = np.empty(n, np.int32)
+    y0 = np.empty(n, np.int32)
+    p = params.to_c()
+    _check(lib().ebsd_roi_layout(C.byref(p), H, W, cx.ctypes.data, cy.ctypes.data,
+                                 x0.ctypes.data, y0.ctypes.data), "ebsd_roi_layout")
+    return cx, cy, x0, y0
+
+
+class Registrar:
+    """A library handle bound to one device with fixed parameters."""
+
+    def __init__(self, params: Params | None = None, device: int = 0):
+        self.params = params or Params()
+        self._p = self.params.to_c()
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().ebsd_create(C.byref(self._p), device, C.byref(h)), "ebsd_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebsd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _pairs(self, refs, tests, ref_ids):
+        if isinstance(refs, torch.Tensor):
+            refs = list(refs.unbind(0)) if refs.dim() == 3 else [refs]
+            tests = list(tests.unbind(0)) if tests.dim() == 3 else [tests]
+        n = len(tests)
+        arr = (CPair * max(n, 1))()
+        keep = []
+        for i in range(n):
+            r, t = refs[i], tests[i]
+            for x in (r, t):
+                if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+                    raise ValueError("patterns must be contiguous float32 device tensors")
+            arr[i].ref = r.data_ptr()
+            arr[i].test = t.data_ptr()
+            arr[i].H, arr[i].W = t.shape[-2], t.shape[-1]
+            arr[i].ref_id = -1 if ref_ids is None else int(ref_ids[i])
+            keep += [r, t]
+        return arr, n, [(t.shape[-2], t.shape[-1]) for t in tests], keep
+
+    def _outputs(self, shapes, want_field, dev):
+        n = len(shapes)
+        nr = self.params.n_roi
+        f64 = dict(dtype=torch.float64, device=dev)
+        f32 = dict(dtype=torch.float32, device=dev)
+        out = {
+            "F": torch.empty(n, 3, 3, **f64),
+            "R": torch.empty(n, 3, 3, **f64),
+            "rotvec": torch.empty(n, 3, **f64),
+            "R_finite": torch.empty(n, 3, 3, **f64),
+            "F_first": torch.empty(n, 3, 3, **f64),
+            "q1": torch.empty(n, nr, 2, **f32),
+            "q2": torch.empty(n, nr, 2, **f32),
+            "peak_height": torch.empty(n, nr, **f32),
+            "iters": torch.empty(n, self.params.levels, dtype=torch.int32, device=dev),
+            "status": torch.empty(n, dtype=torch.int32, device=dev),
+        }
+        offs = None
+        if want_field:
+            sizes = [2 * h * w for h, w in shapes]
+            import numpy as np
+            offs = np.zeros(n, np.int64)
+            if n:
+                offs[1:] = np.cumsum(sizes)[:-1]
+            flat = torch.empty(int(sum(sizes)), **f32)
+            out["_field_flat"] = flat
+            out["_field_offsets"] = offs
+        co = COutputs()
+        co.field = out["_field_flat"].data_ptr() if want_field else None
+        co.field_offset = offs.ctypes.data if want_field else None
+        for k in ("F", "R", "rotvec", "R_finite", "F_first", "q1", "q2", "peak_height", "iters",
+                  "status"):
+            setattr(co, k, out[k].data_ptr())
+        return out, co
+
+    @staticmethod
+    def _unflatten_field(out, shapes):
+        if "_field_flat" not in out:
+            return out
+        flat, offs = out.pop("_field_flat"), out.pop("_field_offsets")
+        fields = [flat[int(o):int(o) + 2 * h * w].view(2, h, w) for o, (h, w) in zip(offs, shapes)]
+        if len(set(shapes)) == 1 and fields:
+            out["field"] = flat.view(len(shapes), 2, shapes[0][0], shapes[0][1])
+        else:
+            out["field"] = fields
+        return out
+
+    def register(self, refs, tests, ref_ids=None, want_field=True, u_init=None):
+        """Register test patterns against references (the whole path).
+
+        refs, tests: float32 device tensors [n, H, W] (or lists of [H, W]
+        tensors, sizes may differ).  ref_ids: optional ints; equal ids share
+        one reference pyramid.  u_init: optional [n, 2, h, w] coarsest-level
+        initial field (full-res px).  Returns a dict of device tensors:
+        field, F, R, rotvec, R_finite, F_first, q1, q2, peak_height, iters,
+        status.  Runs on torch's current stream.
+        """
+        arr, n, shapes, keep = self._pairs(refs, tests, ref_ids)
+        dev = keep[0].device if keep else torch.device("cuda", self.device)
+        out, co = self._outputs(shapes, want_field, dev)
+        if u_init is not None:
+            if not (u_init.is_cuda and u_init.dtype == torch.float32 and u_init.is_contiguous()):
+                raise ValueError("u_init must be a contiguous float32 device tensor")
+            rc = lib().ebsd_register_batch_init(self._h, arr, n, _ptr(u_init), C.byref(co), _stream())
+        else:
+            rc = lib().ebsd_register_batch(self._h, arr, n, C.byref(co), _stream())
+        _check(rc, "ebsd_register_batch")
+        out["_keep"] = (keep, co, arr, u_init)
+        return self._unflatten_field(out, shapes)
+
+    def set_timing(self, on=True):
+        _check(lib().ebsd_set_timing(self._h, int(bool(on))), "ebsd_set_timing")
+
+    def timing(self):
+        """(level_ms [levels], total_ms) of the last timed call (waits for it)."""
+        import numpy as np
+        lv = np.zeros(MAX_LEVELS, np.float64)
+        tot = np.zeros(1, np.float64)
+        _check(lib().ebsd_get_timing(self._h, lv.ctypes.data, tot.ctypes.data), "ebsd_get_timing")
+        return lv[:self.params.levels], float(tot[0])
+
+    def second_pass(self, refs, tests, R_finite, ref_ids=None):
+        """Second pass only, with a given R_finite [n, 3, 3] (float64 device)."""
+        arr, n, shapes, keep = self._pairs(refs, tests, ref_ids)
+        dev = keep[0].device if keep else torch.device("cuda", self.device)
+        out, co = self._outputs(shapes, False, dev)
+        rf = R_finite.to(device=dev, dtype=torch.float64).contiguous()
+        _check(lib().ebsd_second_pass_batch(self._h, arr, n, _ptr(rf), C.byref(co), _stream()),
+               "ebsd_second_pass_batch")
+        out["_keep"] = (keep, co, arr, rf)
+        for k in ("F_first", "q1", "iters"):
+            out.pop(k)
+        return out
+
+
+# -- single-stage entry points -------------------------------------------------------
+
+def _dev_f32(x):
+    if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+        raise ValueError("expected a contiguous float32 device tensor")
+    return x
+
+
+def stage_normalize(p):
+    """z-score each pattern of p [n, ...]; returns (out, flags)."""
+    p = _dev_f32(p)
+    n = p.shape[0]
+    out = torch.empty_like(p)
+    flags = torch.empty(n, dtype=torch.int32, device=p.device)
+    _check(lib().ebsd_stage_normalize(_ptr(p), n, p[0].numel() if n else 1, _ptr(out), _ptr(flags),
+                                      _stream()), "ebsd_stage_normalize")
+    return out, flags
+
+
+def stage_restrict(img):
+    img = _dev_f32(img)
+    n, H, W = img.shape
+    out = torch.empty(n, H // 2, W // 2, dtype=torch.float32, device=img.device)
+    _check(lib().ebsd_stage_restrict(_ptr(img), n, H, W, _ptr(out), _stream()), "ebsd_stage_restrict")
+    return out
+
+
+def stage_demons_iter(R, T, u, sigma):
+    R, T, u = _dev_f32(R), _dev_f32(T), _dev_f32(u)
+    n, H, W = R.shape
+    out = torch.empty_like(u)
+    rms = torch.empty(n, dtype=torch.float64, device=R.device)
+    _check(lib().ebsd_stage_demons_iter(_ptr(R), _ptr(T), n, H, W, _ptr(u), float(sigma), _ptr(out),
+                                        _ptr(rms), _stream()), "ebsd_stage_demons_iter")
+    return out, rms
+
+
+def stage_prolong(u):
+    u = _dev_f32(u)
+    n, _, h, w = u.shape
+    out = torch.empty(n, 2, 2 * h, 2 * w, dtype=torch.float32, device=u.device)
+    _check(lib().ebsd_stage_prolong(_ptr(u), n, h, w, _ptr(out), _stream()), "ebsd_stage_prolong")
+    return out
+
+
+def stage_xcf(A, B, window=1):
+    A, B = _dev_f32(A), _dev_f32(B)
+    n, N, _ = A.shape
+    q = torch.empty(n, 2, dtype=torch.float32, device=A.device)
+    ph = torch.empty(n, dtype=torch.float32, device=A.device)
+    _check(lib().ebsd_stage_xcf(_ptr(A), _ptr(B), n, N, window, _ptr(q), _ptr(ph), _stream()),
+           "ebsd_stage_xcf")
+    return q, ph
+
+
+def stage_solve(q, cx, cy, pcs):
+    """Eq. (3) solve: q [n, n_roi, 2] float32 device; cx, cy [n_roi] float64."""
+    q = _dev_f32(q)
+    n, nr, _ = q.shape
+    cx = torch.as_tensor(cx, dtype=torch.float64).to(q.device).contiguous()
+    cy = torch.as_tensor(cy, dtype=torch.float64).to(q.device).contiguous()
+    F = torch.empty(n, 3, 3, dtype=torch.float64, device=q.device)
+    R = torch.empty(n, 3, 3, dtype=torch.float64, device=q.device)
+    st = torch.empty(n, dtype=torch.int32, device=q.device)
+    _check(lib().ebsd_stage_solve(_ptr(q), n, nr, _ptr(cx), _ptr(cy), float(pcs[0]), float(pcs[1]),
+                                  float(pcs[2]), _ptr(F), _ptr(R), _ptr(st), _stream()),
+           "ebsd_stage_solve")
+    return F, R, st

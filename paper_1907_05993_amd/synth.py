@@ -241,32 +241,27 @@ def make_spec(config_id, pair_index, H, W, mis_deg=(0.0, 10.0), strain=2e-3, exa
                     extra={"axis": axis, "angle_deg": ang, "eps": eps, "Rmis": Rm})
 
 
-def _render_many(args):
-    return [render_pair(s) for s in args]
-
-
 def render_batch(specs, workers=None):
-    """Render a list of PairSpec into (refs, tests) float32 [n, H, W] arrays,
-    with a process pool for large batches."""
+    """Render a list of PairSpec into (refs, tests) float32 [n, H, W] arrays.
+    Serial by default (about 17 ms per 256^2 pair); workers > 1 uses a thread
+    pool.  No processes are forked or spawned."""
     n = len(specs)
     H, W = specs[0].H, specs[0].W
     refs = np.empty((n, H, W), np.float32)
     tests = np.empty((n, H, W), np.float32)
     if workers is None:
-        workers = min(16, os.cpu_count() or 1)
-    if n >= 16 and workers > 1:
-        import multiprocessing as mp
-        chunks = [specs[i::workers] for i in range(workers)]
-        ctx = mp.get_context("fork")
-        with ctx.Pool(workers) as pool:
-            res = pool.map(_render_many, chunks)
-        for w, chunk in enumerate(res):
-            for j, (r, t) in enumerate(chunk):
-                refs[w + j * workers] = r
-                tests[w + j * workers] = t
+        workers = 1
+
+    def one(i):
+        refs[i], tests[i] = render_pair(specs[i])
+
+    if n >= 4 and workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, range(n)))
     else:
-        for i, s in enumerate(specs):
-            refs[i], tests[i] = render_pair(s)
+        for i in range(n):
+            one(i)
     return refs, tests
 
 

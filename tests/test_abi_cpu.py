@@ -1,0 +1,99 @@
+"""CPU-only checks of the C ABI: the library loads, exports every entry point
+that include/ebsd.h declares, and its host-side logic (defaults, error codes,
+argument validation, ROI layout) behaves as documented.  No kernel runs."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ebsd.h")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1907_05993_amd import build, ebsd
+    if not os.path.exists(ebsd.LIB_PATH):
+        build.build()
+    ebsd.lib()
+    return ebsd
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\**\s*(ebsd_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(E):
+    names = declared_functions()
+    assert len(names) >= 16
+    lib = C.CDLL(E.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(E.EXPORTED)
+
+
+def test_version_defaults_strerror(E):
+    L = E.lib()
+    assert L.ebsd_version() == 1
+    p = E.CParams()
+    assert L.ebsd_params_default(C.byref(p)) == 0
+    assert p.struct_size == C.sizeof(E.CParams)
+    assert p.levels == 3 and list(p.max_iters)[:3] == [150, 150, 150]
+    assert abs(p.sigma_px - 1.0) < 1e-7 and p.n_roi == 20 and p.roi_size == 64
+    assert p.window == 1 and p.second_pass == 1
+    for code in (0, -1, -2, -3, -4, -5, -6, -8, -99):
+        assert len(L.ebsd_strerror(code)) > 0
+
+
+def test_create_validates_before_touching_the_device(E):
+    L = E.lib()
+    h = C.c_void_p()
+    p = E.Params().to_c()
+    p.struct_size = 4
+    assert L.ebsd_create(C.byref(p), 0, C.byref(h)) == -8
+    for field, val, code in [("sigma_px", -1.0, -1), ("sigma_px", 2.0, -1), ("levels", 0, -1),
+                             ("levels", 9, -1), ("n_roi", 3, -1), ("roi_size", 48, -3),
+                             ("window", 2, -1), ("pc_z", 0.0, -1), ("tol_px", float("nan"), -1)]:
+        p = E.Params().to_c()
+        setattr(p, field, val)
+        assert L.ebsd_create(C.byref(p), 0, C.byref(h)) == code, field
+    assert L.ebsd_create(C.byref(E.Params().to_c()), 0, None) == -1
+
+
+def test_create_without_gpu_reports_device_error(E):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert E.lib().ebsd_create(C.byref(E.Params().to_c()), 0, C.byref(h)) == -5
+
+
+@pytest.mark.parametrize("HW,roi", [((256, 256), 64), ((128, 128), 32), ((400, 400), 128),
+                                    ((512, 512), 128), ((160, 96), 32)])
+def test_roi_layout_equals_oracle(E, orc, HW, roi):
+    H, W = HW
+    gp = E.Params(roi_size=roi)
+    cx, cy, x0, y0 = E.roi_layout(gp, H, W)
+    ocx, ocy, ox0, oy0, bad = orc.roi_layout(H, W, orc.make_params(roi_size=roi))
+    assert not bad
+    assert np.array_equal(x0, ox0) and np.array_equal(y0, oy0)
+    assert np.array_equal(cx, ocx) and np.array_equal(cy, ocy)
+
+
+def test_roi_layout_out_of_bounds(E):
+    with pytest.raises(E.EbsdError) as ei:
+        E.roi_layout(E.Params(roi_size=128), 128, 128)
+    assert ei.value.code == -3
+
+
+def test_null_arguments_rejected(E):
+    L = E.lib()
+    assert L.ebsd_register_batch(None, None, 0, None, None) == -1
+    assert L.ebsd_stage_xcf(None, None, 1, 64, 1, None, None, None) == -1
+    assert L.ebsd_stage_xcf(None, None, 0, 48, 1, None, None, None) == -3
+    assert L.ebsd_stage_restrict(None, 0, 5, 8, None, None) == -2
+    assert L.ebsd_destroy(None) == 0

@@ -1,0 +1,264 @@
+"""Whole-path parity of the HIP library (through the C ABI) against the FP64
+oracle, plus the edge cases of the path.  Needs an MI355X; run with -m gpu.
+
+Bars (FP32 GPU vs FP64 oracle):
+  * displacement field: RMS over all pixels <= 1e-3 px while the iteration is
+    stable (3 levels x 20-30 iterations).  Deeper, Eq. (1) is chaotic in the
+    noise-dominated pixels where |a| ~ |grad R| is small: two FP64 builds of
+    the oracle that differ only in FMA contraction already disagree by ~5e-4 px
+    RMS and 0.1 px max after 3 x 150 iterations at 256^2.  At full depth the
+    tests therefore check (i) that every single step equals the oracle's step
+    from the same state (test_gpu_stages.py, teacher forcing), (ii) robust
+    field statistics (median and 95th percentile of |du|), and (iii) the
+    unique downstream result;
+  * deformation gradient: |dF_ij| <= 1e-6 when both second passes start from
+    the same R_finite (the GPU's); end to end the difference is bounded by
+    1e-4;
+  * integer outputs (iteration counts, status bits) exact in fixed-count mode.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1907_05993_amd import ebsd
+    ebsd.lib()
+    return ebsd
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def gen(name, n, start=0):
+    from paper_1907_05993_amd import synth as S
+    specs = S.workload_specs(name, n=n, start=start)
+    refs, tests = S.render_batch(specs)
+    return refs, tests, specs
+
+
+def params_pair(E, orc, levels=3, iters=100, sigma=1.0, roi=32, tol=0.0, n_roi=20):
+    gp = E.Params(levels=levels, iters=(iters,) * levels, sigma_px=sigma, tol_px=tol, roi_size=roi,
+                  n_roi=n_roi)
+    op = orc.make_params(levels=levels, iters=iters, sigma=sigma, tol=tol, roi_size=roi, n_roi=n_roi)
+    return gp, op
+
+
+def field_rms(a, b):
+    return float(np.sqrt(((np.asarray(a, np.float64) - b) ** 2).mean()))
+
+
+def field_stats(a, b):
+    d = np.sqrt(((np.asarray(a, np.float64) - b) ** 2).sum(0))
+    return float(np.sqrt((d ** 2).mean())), float(np.median(d)), float(np.percentile(d, 95)), float(d.max())
+
+
+def compare(E, orc, refs, tests, gp, op, strict=True, F_tol=1e-6):
+    """strict: field RMS <= 1e-3 px; otherwise (chaotic depth) median <= 2e-3
+    px and 95th percentile <= 0.05 px."""
+    reg = E.Registrar(gp)
+    g = reg.register(cuda(refs), cuda(tests))
+    torch.cuda.synchronize()
+    o = orc.register_batch(refs, tests, op)
+    n = refs.shape[0]
+    gf = g["field"].cpu().numpy()
+    stats = [field_stats(gf[i], o["field"][i]) for i in range(n)]
+    print("field |du| (rms, median, p95, max) per pair:", [tuple("%.1e" % v for v in st) for st in stats])
+    for rms, med, p95, mx in stats:
+        if strict:
+            assert rms <= 1e-3
+        else:
+            assert med <= 2e-3 and p95 <= 0.05
+    assert np.array_equal(g["iters"].cpu().numpy(), o["iters"])
+    # second pass from the same R_finite (the GPU's)
+    rf = g["R_finite"].cpu().numpy()
+    o2 = orc.register_batch(refs, tests, op, rfin=rf, want_field=False)
+    dF = np.abs(g["F"].cpu().numpy() - o2["F"]).max()
+    dq2 = np.abs(g["q2"].cpu().numpy() - o2["q2"]).max()
+    print("second pass from GPU R_finite: max |dF| %.2e, max |dq2| %.2e px" % (dF, dq2))
+    assert dF <= F_tol
+    # end to end
+    dF_e2e = np.abs(g["F"].cpu().numpy() - o["F"]).max()
+    dR = np.abs(g["R_finite"].cpu().numpy() - o["Rfin"]).max()
+    print("end to end: max |dF| %.2e, max |dR_finite| %.2e" % (dF_e2e, dR))
+    assert dF_e2e <= 1e-4
+    assert np.array_equal(g["status"].cpu().numpy().astype(np.uint32), o["status"])
+    return g, o
+
+
+def test_single_pair_128_stable_depth(E, orc):
+    """Single pair, 128^2, 3 levels x 20 iterations, sigma 1, 20 ROIs of 32^2: strict bar."""
+    refs, tests, _ = gen("single_128", 1)
+    gp, op = params_pair(E, orc, iters=20, roi=32)
+    compare(E, orc, refs, tests, gp, op, strict=True)
+
+
+def test_single_pair_128_full_depth(E, orc):
+    """The single-pair workload as configured: 3 x 100 iterations."""
+    refs, tests, _ = gen("single_128", 1)
+    gp, op = params_pair(E, orc, iters=100, roi=32)
+    compare(E, orc, refs, tests, gp, op, strict=False)
+
+
+def test_batch_256_stable_depth(E, orc):
+    """256^2 pairs (the batch workload's inputs), 3 x 15 iterations, ROIs of 64^2: strict bar."""
+    refs, tests, _ = gen("batch_256", 4)
+    gp, op = params_pair(E, orc, iters=15, roi=64)
+    compare(E, orc, refs, tests, gp, op, strict=True)
+
+
+def test_batch_256_full_depth(E, orc):
+    """256^2 pairs, 3 x 150 (the batch workload's settings) on 4 pairs."""
+    refs, tests, _ = gen("batch_256", 4)
+    gp, op = params_pair(E, orc, iters=150, roi=64)
+    compare(E, orc, refs, tests, gp, op, strict=False)
+
+
+def test_full_batch_1024_sampled(E, orc):
+    """The full 1024-pair 256^2 batch in one call (the benchmark's launch
+    configuration); 3 sampled pairs are checked against the oracle."""
+    refs, tests, _ = gen("batch_256", 1024)
+    gp, op = params_pair(E, orc, iters=150, roi=64)
+    reg = E.Registrar(gp)
+    g = reg.register(cuda(refs), cuda(tests))
+    torch.cuda.synchronize()
+    idx = [0, 517, 1023]
+    o = orc.register_batch(refs[idx], tests[idx], op)
+    gf = g["field"][idx].cpu().numpy()
+    for k in range(3):
+        rms, med, p95, mx = field_stats(gf[k], o["field"][k])
+        print("pair", idx[k], "field |du| rms %.1e median %.1e p95 %.1e max %.1e" % (rms, med, p95, mx))
+        assert med <= 2e-3 and p95 <= 0.05
+    rf = g["R_finite"][idx].cpu().numpy()
+    o2 = orc.register_batch(refs[idx], tests[idx], op, rfin=rf, want_field=False)
+    assert np.abs(g["F"][idx].cpu().numpy() - o2["F"]).max() <= 1e-6
+    # properties that hold for every pair
+    F = g["F"].cpu().numpy()
+    assert np.allclose(np.linalg.det(F), 1.0, atol=1e-12)
+    R = g["R"].cpu().numpy()
+    assert np.allclose(np.einsum("nji,njk->nik", R, R), np.eye(3), atol=1e-12)
+    assert np.all(g["iters"].cpu().numpy() == 150)
+
+
+def test_identical_pair_is_exactly_zero(E, orc):
+    refs, _, _ = gen("single_128", 2)
+    gp, _ = params_pair(E, orc, iters=20)
+    g = E.Registrar(gp).register(cuda(refs), cuda(refs))
+    torch.cuda.synchronize()
+    assert not g["field"].any().item()
+    assert not g["q1"].any().item()
+    eye = np.broadcast_to(np.eye(3), (2, 3, 3))
+    np.testing.assert_allclose(g["F_first"].cpu().numpy(), eye, atol=1e-13)
+    # the second pass sees FP32 FFT round-off (|q2| ~ 1e-6 px), i.e. F ~ I + 1e-8
+    np.testing.assert_allclose(g["F"].cpu().numpy(), eye, atol=1e-7)
+    assert np.abs(g["q2"].cpu().numpy()).max() < 1e-4
+    assert np.abs(g["rotvec"].cpu().numpy()).max() < 1e-7
+    np.testing.assert_allclose(g["peak_height"].cpu().numpy(), 1.0, atol=1e-5)
+
+
+def test_degenerate_and_nonfinite_inputs(E, orc):
+    refs, tests, _ = gen("single_128", 3)
+    tests[1] = 5.0
+    tests[2, 10, 10] = np.nan
+    gp, _ = params_pair(E, orc, iters=5)
+    g = E.Registrar(gp).register(cuda(refs), cuda(tests))
+    st = g["status"].cpu().numpy()
+    assert st[0] & (orc.DEGENERATE_INPUT | orc.NONFINITE_INPUT) == 0
+    assert st[1] & orc.DEGENERATE_INPUT
+    assert st[2] & orc.NONFINITE_INPUT
+    assert torch.isfinite(g["field"]).all().item()
+
+
+def test_mixed_sizes_match_separate_calls(E, orc):
+    from paper_1907_05993_amd import synth as S
+    a = [S.render_pair(S.make_spec(21, i, 128, 128, exact_angle=1.5)) for i in range(2)]
+    b = [S.render_pair(S.make_spec(22, i, 160, 96, exact_angle=1.5)) for i in range(2)]
+    gp, _ = params_pair(E, orc, iters=30, roi=32)
+    reg = E.Registrar(gp)
+    order = [a[0], b[0], a[1], b[1]]
+    g = reg.register([cuda(p[0]) for p in order], [cuda(p[1]) for p in order])
+    ga = reg.register(cuda(np.stack([p[0] for p in a])), cuda(np.stack([p[1] for p in a])))
+    gb = reg.register(cuda(np.stack([p[0] for p in b])), cuda(np.stack([p[1] for p in b])))
+    torch.cuda.synchronize()
+    for k, (src, j) in enumerate([(ga, 0), (gb, 0), (ga, 1), (gb, 1)]):
+        assert torch.equal(g["F"][k], src["F"][j])
+        assert torch.equal(g["field"][k], src["field"][j])
+
+
+def test_shared_reference_matches_unshared(E, orc):
+    from paper_1907_05993_amd import synth as S
+    spec0 = S.make_spec(23, 0, 128, 128, exact_angle=1.0)
+    ref, _ = S.render_pair(spec0)
+    tests = np.stack([S.render_pair(S.make_spec(23, i, 128, 128, exact_angle=1.0))[1] for i in range(3)])
+    refs = np.stack([ref] * 3)
+    gp, _ = params_pair(E, orc, iters=30, roi=32)
+    reg = E.Registrar(gp)
+    r_one = cuda(ref)
+    shared = reg.register([r_one] * 3, list(cuda(tests).unbind(0)), ref_ids=[7, 7, 7])
+    plain = reg.register(cuda(refs), cuda(tests))
+    torch.cuda.synchronize()
+    assert torch.equal(shared["field"], plain["field"])
+    assert torch.equal(shared["F"], plain["F"])
+
+
+def test_deterministic(E, orc):
+    refs, tests, _ = gen("single_128", 4)
+    gp, _ = params_pair(E, orc, iters=40, roi=32, tol=1e-4)
+    reg = E.Registrar(gp)
+    a = reg.register(cuda(refs), cuda(tests))
+    b = reg.register(cuda(refs), cuda(tests))
+    torch.cuda.synchronize()
+    for k in ("field", "F", "q2", "iters", "status"):
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_tolerance_mode(E, orc):
+    """Per-pair convergence: iteration counts within one of the oracle's, status
+    bits consistent, field parity."""
+    refs, tests, _ = gen("batch_256", 3)
+    gp, op = params_pair(E, orc, iters=150, roi=64, tol=1e-3)
+    g = E.Registrar(gp).register(cuda(refs), cuda(tests))
+    torch.cuda.synchronize()
+    o = orc.register_batch(refs, tests, op)
+    gi = g["iters"].cpu().numpy()
+    assert np.abs(gi - o["iters"]).max() <= 1
+    st = g["status"].cpu().numpy().astype(np.uint32)
+    for i in range(3):
+        conv = np.all(gi[i] < 150)
+        assert bool(st[i] & orc.CONVERGED) == conv
+        assert bool(st[i] & orc.HIT_CAP) == (not conv)
+    if np.array_equal(gi, o["iters"]):
+        gf = g["field"].cpu().numpy()
+        for i in range(3):
+            rms, med, p95, mx = field_stats(gf[i], o["field"][i])
+            assert med <= 2e-3 and p95 <= 0.05
+
+
+def test_second_pass_only_entry(E, orc):
+    refs, tests, specs = gen("batch_256", 2)
+    _, op = params_pair(E, orc, iters=150, roi=64)
+    rf = np.stack([orc.polar(s.F) for s in specs])
+    gp, _ = params_pair(E, orc, iters=150, roi=64)
+    g = E.Registrar(gp).second_pass(cuda(refs), cuda(tests), torch.from_numpy(rf))
+    torch.cuda.synchronize()
+    o = orc.register_batch(refs, tests, op, rfin=rf, want_field=False)
+    assert np.abs(g["F"].cpu().numpy() - o["F"]).max() <= 1e-6
+    np.testing.assert_allclose(g["R_finite"].cpu().numpy(), rf, atol=0)
+
+
+def test_zero_pairs_and_validation(E, orc):
+    gp, _ = params_pair(E, orc, iters=5)
+    reg = E.Registrar(gp)
+    out = reg.register(torch.empty(0, 128, 128, device="cuda"), torch.empty(0, 128, 128, device="cuda"))
+    assert out["F"].shape[0] == 0
+    with pytest.raises(E.EbsdError) as ei:
+        reg.register(cuda(np.zeros((1, 130, 128))), cuda(np.zeros((1, 130, 128))))
+    assert ei.value.code == -2  # 130 not divisible by 4 at 3 levels
+    with pytest.raises(E.EbsdError) as ei:
+        E.Registrar(E.Params(roi_size=128)).register(cuda(np.zeros((1, 128, 128))),
+                                                     cuda(np.zeros((1, 128, 128))))
+    assert ei.value.code == -3
