@@ -42,7 +42,21 @@ def main():
     ap.add_argument("--cap", type=int, default=150)
     ap.add_argument("--cpu-sample", type=int, default=32, help="pairs timed on the CPU oracle (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "demons_traffic.json"))
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device (counter calibration) and exit")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        n = 1 << 28  # 2^28 floats = 1 GiB
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "launches": 3}))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -68,6 +82,8 @@ def main():
     params = ebsd.Params(levels=3, iters=(args.cap,) * 3, sigma_px=1.0, tol_px=args.tol,
                          roi_size=w["roi"], n_roi=20)
     reg = ebsd.Registrar(params, device=0)
+    tuned = reg.autotune(d_refs, d_tests)  # strip heights per level, outside the timed region
+    log(f"[bench] autotuned strip heights: {tuned}")
     reg.set_timing(True)
 
     for i in range(args.warmup):
@@ -123,6 +139,7 @@ def main():
             "strain": w["strain"], "counts": 1e4,
             "levels": 3, "iters_cap": args.cap, "tol_px": args.tol, "sigma_px": 1.0,
             "n_roi": 20, "roi": w["roi"], "mode": "plain",
+            "strip_rows": {f"{k[0]}x{k[1]}": v for k, v in tuned.items()},
             "parallelism": "single GPU, batch of independent pairs",
         },
         "roofline": {

@@ -171,6 +171,24 @@ int ebsd_register_batch_init(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
 int ebsd_second_pass_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
                            const double* R_finite, const ebsd_outputs* out, void* stream);
 
+/* Autotuner for the demons kernel: on this batch (same validation as
+ * ebsd_register_batch), times every supported strip height (rows per
+ * workgroup: 16, 32, 64, 128) of the row-marching demons kernel for each
+ * pyramid level up to 256 px wide, and keeps the fastest per level size for
+ * later calls of this handle.  If the environment variable EBSD_TUNE_CACHE
+ * named a file when the handle was created, the table is read from it then
+ * and written back here (lines "gfx950 <h> <w> <rows>").  Synchronises
+ * `stream`.  Demons results are unaffected (the strip height only changes the
+ * work decomposition). */
+int ebsd_autotune(ebsd_handle* h, const ebsd_pair* pairs, int32_t n, void* stream);
+
+/* Strip height used for a pyramid level of level_h x level_w px (0 if that
+ * level uses the 2-D tile kernel, i.e. wider than 256 px). */
+int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w);
+
+/* Force the strip height (16, 32, 64 or 128) for a level size. */
+int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t rows);
+
 /* Timing of the demons iterations, for measurement tools.  enable != 0 makes
  * later calls record HIP events on their stream around each pyramid level's
  * demons launches and around the whole call (of its last size bucket). */

@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+         "-ffp-contract=off", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 
 def _compile(src, verbose):

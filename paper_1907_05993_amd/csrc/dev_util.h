@@ -37,6 +37,123 @@ __device__ inline float bilinear_clamped(P img, int h, int w, float x, float y)
     return (1.0f - fy) * top + fy * bot;
 }
 
+// A pointer value that is the same in every lane, made provably uniform
+// (scalar registers) for the compiler.
+template <class T>
+__device__ inline T* uniform_ptr(T* p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+__device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Raw buffer access: a uniform resource descriptor (base, size in bytes) and
+// 32-bit byte offsets; reads outside [0, bytes) return 0 instead of faulting.
+// Descriptor word 3 = 0x00020000 (32-bit data, gfx9 family).
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<void*>(p)), (short)0,
+                                             (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+__device__ inline float bload(__amdgpu_buffer_rsrc_t r, unsigned byte_off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
+}
+
+// Bilinear sample through a buffer descriptor (image of h x w floats).
+// xc, yc are clamped to the image by fminf/fmaxf (NaN -> the bound), so the
+// floors need no further clamping.
+__device__ inline float bilinear_buf(__amdgpu_buffer_rsrc_t img, int h, int w, float x, float y)
+{
+    const float xc = fminf(fmaxf(x, 0.0f), (float)(w - 1));
+    const float yc = fminf(fmaxf(y, 0.0f), (float)(h - 1));
+    const float xf = floorf(xc), yf = floorf(yc);
+    const unsigned x0 = (unsigned)xf, y0 = (unsigned)yf;
+    const float fx = xc - xf, fy = yc - yf;
+    const unsigned dx = x0 + 1 < (unsigned)w ? 4u : 0u;
+    const unsigned dy = y0 + 1 < (unsigned)h ? 4u * (unsigned)w : 0u;
+    const unsigned o = 4u * (y0 * (unsigned)w + x0);
+    const float v00 = bload(img, o), v01 = bload(img, o + dx);
+    const float v10 = bload(img, o + dy), v11 = bload(img, o + dy + dx);
+    const float top = (1.0f - fx) * v00 + fx * v01;
+    const float bot = (1.0f - fx) * v10 + fx * v11;
+    return (1.0f - fy) * top + fy * bot;
+}
+
+// Two halves of bilinear_buf, so that the loads of one row can be in flight
+// while the previous row is processed.
+struct Bilin {
+    float v00, v01, v10, v11, fx, fy;
+};
+__device__ inline Bilin bilinear_issue(__amdgpu_buffer_rsrc_t img, int h, int w, float x, float y)
+{
+    Bilin b;
+    const float xc = fminf(fmaxf(x, 0.0f), (float)(w - 1));
+    const float yc = fminf(fmaxf(y, 0.0f), (float)(h - 1));
+    const float xf = floorf(xc), yf = floorf(yc);
+    const unsigned x0 = (unsigned)xf, y0 = (unsigned)yf;
+    b.fx = xc - xf;
+    b.fy = yc - yf;
+    const unsigned dx = x0 + 1 < (unsigned)w ? 4u : 0u;
+    const unsigned dy = y0 + 1 < (unsigned)h ? 4u * (unsigned)w : 0u;
+    const unsigned o = 4u * (y0 * (unsigned)w + x0);
+    b.v00 = bload(img, o);
+    b.v01 = bload(img, o + dx);
+    b.v10 = bload(img, o + dy);
+    b.v11 = bload(img, o + dy + dx);
+    return b;
+}
+// Lerps as a + f (b - a) with one rounding for the product-sum (fmaf): exact
+// for f = 0, and the same instruction sequence in every kernel variant (the
+// library is built without automatic contraction).
+__device__ inline float lerpf(float a, float b, float f) { return fmaf(f, b - a, a); }
+__device__ inline float bilinear_blend(const Bilin& b)
+{
+    return lerpf(lerpf(b.v00, b.v01, b.fx), lerpf(b.v10, b.v11, b.fx), b.fy);
+}
+
+// Bilinear sample (lerp form, see lerpf) through a plain pointer.
+template <class P>
+__device__ inline float bilinear_lerp(P img, int h, int w, float x, float y)
+{
+    const float xc = fminf(fmaxf(x, 0.0f), (float)(w - 1));
+    const float yc = fminf(fmaxf(y, 0.0f), (float)(h - 1));
+    const float xf = floorf(xc), yf = floorf(yc);
+    const int x0 = (int)xf, y0 = (int)yf;
+    const int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
+    auto r0 = img + (int64_t)y0 * w;
+    auto r1 = img + (int64_t)y1 * w;
+    return lerpf(lerpf(r0[x0], r0[x1], xc - xf), lerpf(r1[x0], r1[x1], xc - xf), yc - yf);
+}
+
+// Same sample for a global image of fewer than 2^30 pixels, with 32-bit
+// unsigned offsets from a uniform base (lets the compiler use the
+// scalar-base + 32-bit vector-offset addressing form).  xc, yc are already
+// clamped to [0, w-1] x [0, h-1] by fminf/fmaxf (NaN -> the bound), so the
+// floors need no further clamping.
+__device__ inline float bilinear_g32(const EBSD_GLOBAL float* __restrict__ img, int h, int w,
+                                     float x, float y)
+{
+    const float xc = fminf(fmaxf(x, 0.0f), (float)(w - 1));
+    const float yc = fminf(fmaxf(y, 0.0f), (float)(h - 1));
+    const float xf = floorf(xc), yf = floorf(yc);
+    const unsigned x0 = (unsigned)xf, y0 = (unsigned)yf;
+    const float fx = xc - xf, fy = yc - yf;
+    const unsigned dx = x0 + 1 < (unsigned)w ? 1u : 0u;
+    const unsigned dy = y0 + 1 < (unsigned)h ? (unsigned)w : 0u;
+    const unsigned o = y0 * (unsigned)w + x0;
+    const float v00 = img[o], v01 = img[o + dx], v10 = img[o + dy], v11 = img[o + dy + dx];
+    const float top = (1.0f - fx) * v00 + fx * v01;
+    const float bot = (1.0f - fx) * v10 + fx * v11;
+    return (1.0f - fy) * top + fy * bot;
+}
+
 // Map the hardware workgroup id so that each XCD (workgroups are dealt
 // round-robin to the 8 XCDs) receives a contiguous range of logical units.
 __device__ inline int xcd_logical_block(int hw_id, int G)

@@ -9,9 +9,13 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <new>
 #include <utility>
 #include <vector>
@@ -37,9 +41,38 @@ struct ebsd_handle {
     bool timed_call = false;
     int timed_levels = 0;
     hipEvent_t ev[2 + 2 * EBSD_MAX_LEVELS] = {};
+    // strip height of the row-marching demons kernel per level size (h, w),
+    // from ebsd_autotune or the tuning cache file; default kDefaultStripTY
+    std::map<std::pair<int, int>, int> strip_ty;
+    std::string tune_cache;  // EBSD_TUNE_CACHE at create time (may be empty)
 };
 
 namespace {
+
+int strip_ty_for(const ebsd_handle* h, int lh, int lw)
+{
+    auto it = h->strip_ty.find(std::make_pair(lh, lw));
+    return it == h->strip_ty.end() ? kDefaultStripTY : it->second;
+}
+
+// Tuning cache: one line "gfx950 <level h> <level w> <strip height>" per entry.
+void load_tune_cache(ebsd_handle* h)
+{
+    if (h->tune_cache.empty()) return;
+    std::ifstream f(h->tune_cache);
+    std::string arch;
+    int lh, lw, ty;
+    while (f >> arch >> lh >> lw >> ty)
+        if (arch == "gfx950" && rows_ty_supported(ty)) h->strip_ty[std::make_pair(lh, lw)] = ty;
+}
+
+void save_tune_cache(const ebsd_handle* h)
+{
+    if (h->tune_cache.empty()) return;
+    std::ofstream f(h->tune_cache, std::ios::trunc);
+    for (auto& kv : h->strip_ty)
+        f << "gfx950 " << kv.first.first << " " << kv.first.second << " " << kv.second << "\n";
+}
 
 struct DeviceGuard {
     int prev = -1;
@@ -254,7 +287,7 @@ enum class Mode { Full, SecondPassOnly };
 // the pinned staging buffer.
 int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_init,
                const double* rfin_in, const ebsd_outputs* out, hipStream_t s, size_t pin_off,
-               size_t* pin_used)
+               size_t* pin_used, bool tune_only = false)
 {
     const ebsd_params& p = h->p;
     const int nb = (int)hbk.idx.size();
@@ -275,7 +308,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     for (int l = 0; l < L; l++) {
         b.lvl_off[l] = (int32_t)pe;
         pe += (int64_t)(H >> l) * (W >> l);
-        max_units = std::max(max_units, demons_units(H >> l, W >> l));
+        max_units = std::max(max_units, demons_units(H >> l, W >> l, kMinStripTY));
     }
     pe = (pe + 63) / 64 * 64;  // 256 B aligned pyramids (vector loads)
     b.pyr_elems = pe;
@@ -391,14 +424,47 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     if (tm) EBSD_TRY(hipEventRecord(h->ev[0], s));
     EBSD_TRY(launch_stats(d_bk, nb, nref, s));
     EBSD_TRY(launch_pyramids(d_bk, b, s));
+    if (tune_only) {
+        // time each supported strip height for every row-marching level
+        EBSD_TRY(launch_demons_init(d_bk, b, nullptr, s));
+        hipEvent_t e0, e1;
+        EBSD_TRY(hipEventCreate(&e0));
+        EBSD_TRY(hipEventCreate(&e1));
+        for (int l = L - 1; l >= 0; l--) {
+            const int lh = H >> l, lw = W >> l;
+            if (!rows_cpl(lw)) continue;
+            float best = 1e30f;
+            int best_ty = kDefaultStripTY;
+            for (int ty : {16, 32, 64, 128}) {
+                for (int it = 0; it < 2; it++)
+                    EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, 0.0f, ty, s));
+                EBSD_TRY(hipEventRecord(e0, s));
+                for (int it = 0; it < 6; it++)
+                    EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, 0.0f, ty, s));
+                EBSD_TRY(hipEventRecord(e1, s));
+                EBSD_TRY(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                EBSD_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    best_ty = ty;
+                }
+            }
+            h->strip_ty[std::make_pair(lh, lw)] = best_ty;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return EBSD_OK;
+    }
     if (mode == Mode::Full) {
         EBSD_TRY(launch_demons_init(d_bk, b, u_init, s));
         for (int l = L - 1; l >= 0; l--) {
+            const int ty = strip_ty_for(h, H >> l, W >> l);
             if (tm) EBSD_TRY(hipEventRecord(h->ev[2 + 2 * l], s));
             for (int it = 0; it < p.max_iters[l]; it++)
-                EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, p.tol_px, s));
+                EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, p.tol_px, ty, s));
             if (tm) EBSD_TRY(hipEventRecord(h->ev[3 + 2 * l], s));
-            EBSD_TRY(launch_level_end(d_bk, b, l, p.max_iters[l], p.tol_px, s));
+            EBSD_TRY(launch_level_end(d_bk, b, l, p.max_iters[l], p.tol_px, ty, s));
             if (l > 0) EBSD_TRY(launch_prolong_level(d_bk, b, l, s));
         }
         EBSD_TRY(launch_sample_q1(d_bk, b, s));
@@ -442,7 +508,7 @@ size_t desc_upper_bound(const HostBucket& hb, int nr)
 }
 
 int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u_init,
-        const double* rfin_in, const ebsd_outputs* out, void* stream)
+        const double* rfin_in, const ebsd_outputs* out, void* stream, bool tune_only = false)
 {
     if (!h || !out) return EBSD_EINVAL;
     int e = check_pairs(h->p, pairs, n);
@@ -461,12 +527,13 @@ int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u
     size_t off = 0;
     for (auto& hb : buckets) {
         size_t used = 0;
-        e = run_bucket(h, hb, mode, u_init, rfin_in, out, s, off, &used);
+        e = run_bucket(h, hb, mode, u_init, rfin_in, out, s, off, &used, tune_only);
         if (e) return e;
         off = align_up(off + used, 256);
     }
     if (hipEventRecord(h->pin_free, s) != hipSuccess) return EBSD_EDEVICE;
     h->pin_pending = true;
+    if (tune_only) save_tune_cache(h);
     return EBSD_OK;
 }
 
@@ -544,7 +611,35 @@ int ebsd_create(const ebsd_params* p, int device, ebsd_handle** out)
         delete h;
         return EBSD_EDEVICE;
     }
+    if (const char* c = std::getenv("EBSD_TUNE_CACHE")) h->tune_cache = c;
+    load_tune_cache(h);
     *out = h;
+    return EBSD_OK;
+}
+
+int ebsd_autotune(ebsd_handle* h, const ebsd_pair* pairs, int32_t n, void* stream)
+{
+    if (!h) return EBSD_EINVAL;
+    ebsd_outputs none;
+    std::memset(&none, 0, sizeof none);
+    int e = run(h, pairs, n, Mode::Full, nullptr, nullptr, &none, stream, true);
+    if (e) return e;
+    DeviceGuard g(h->device);
+    return hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? EBSD_OK
+                                                                                   : EBSD_EDEVICE;
+}
+
+int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w)
+{
+    if (!h || level_h <= 0 || level_w <= 0) return EBSD_EINVAL;
+    if (!rows_cpl(level_w)) return 0;
+    return strip_ty_for(h, level_h, level_w);
+}
+
+int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t ty)
+{
+    if (!h || level_h <= 0 || level_w <= 0 || !rows_ty_supported(ty)) return EBSD_EINVAL;
+    h->strip_ty[std::make_pair((int)level_h, (int)level_w)] = ty;
     return EBSD_OK;
 }
 

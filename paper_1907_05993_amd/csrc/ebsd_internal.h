@@ -82,12 +82,13 @@ hipError_t launch_pyramids(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // (u_init [nb][2][h][w] in full-res px, or zero).
 hipError_t launch_demons_init(const Bucket* d_bk, const Bucket& hb, const float* u_init,
                               hipStream_t s);
-// Iteration k (0-based) of level l for every pair that has not stopped.
+// Iteration k (0-based) of level l for every pair that has not stopped; ty =
+// strip height of the row-marching kernel.
 hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, int k,
-                              const float* taps, int radius, float tol, hipStream_t s);
+                              const float* taps, int radius, float tol, int ty, hipStream_t s);
 // Close level l: iteration counts, convergence of the last iteration, final buffer.
 hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int cap, float tol,
-                            hipStream_t s);
+                            int ty, hipStream_t s);
 // Prolong the field of every pair from level l to level l-1 and re-arm the pairs.
 hipError_t launch_prolong_level(const Bucket* d_bk, const Bucket& hb, int level, hipStream_t s);
 // Sample the finest field at the ROI centres -> q1.
@@ -143,16 +144,25 @@ inline int demons_tiles(int h, int w)
     return ((w + kDemonsTX - 1) / kDemonsTX) * ((h + kDemonsTY - 1) / kDemonsTY);
 }
 
-// Row-marching kernel (levels up to 256 px wide): columns per lane (0 = not
-// applicable), number of row strips, and its launchers (false if not applicable).
+// Row-marching kernel (levels up to 256 px wide): wavefronts per row (0 = not
+// applicable), supported strip heights, number of strips, and its launchers
+// (false if not applicable).
 int rows_cpl(int w);
-int rows_units(int h);
+bool rows_ty_supported(int ty);
+int rows_units(int h, int ty);
 bool launch_demons_rows(const Bucket* d_bk, const Bucket& hb, int level, int k, const Taps& tp,
-                        int radius, float tol, hipStream_t s);
+                        int radius, float tol, int ty, hipStream_t s);
 bool launch_demons_rows_stage(const float* R, const float* T, int n, int h, int w, const float* u,
                               const Taps& tp, int radius, float* un, double* rms, hipStream_t s);
 
-// Work units (and per-pair partial sums) of one demons iteration at h x w.
-inline int demons_units(int h, int w) { return rows_cpl(w) ? rows_units(h) : demons_tiles(h, w); }
+constexpr int kDefaultStripTY = 64;
+constexpr int kMinStripTY = 16;
+
+// Work units (and per-pair partial sums) of one demons iteration at h x w
+// with strip height ty (row-marching kernel) or 2-D tiles.
+inline int demons_units(int h, int w, int ty)
+{
+    return rows_cpl(w) ? rows_units(h, ty) : demons_tiles(h, w);
+}
 
 }  // namespace ebsd

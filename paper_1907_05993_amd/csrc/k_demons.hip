@@ -88,17 +88,17 @@ __device__ float demons_tile(const float* __restrict__ Rg, const float* __restri
         const int64_t row = (int64_t)yy * w;
         const float gxr = (R[row + xp] - R[row + xm]) * sx;
         const float gyr = (R[(int64_t)yp * w + xx] - R[(int64_t)ym * w + xx]) * sy;
-        const float wv = bilinear_clamped(T, h, w, (float)xx + ux, (float)yy + uy);
+        const float wv = bilinear_lerp(T, h, w, (float)xx + ux, (float)yy + uy);
         const float a = r - wv;
-        const float den = gxr * gxr + gyr * gyr + a * a;
-        float dux = 0.0f, duy = 0.0f;
+        const float den = fmaf(gxr, gxr, fmaf(gyr, gyr, a * a));
+        float vxx = ux, vyy = uy;
         if (den > 1e-9f) {
             const float s = a * __builtin_amdgcn_rcpf(den);
-            dux = s * gxr;
-            duy = s * gyr;
+            vxx = fmaf(s, gxr, ux);
+            vyy = fmaf(s, gyr, uy);
         }
-        vx[gy][gx] = ux + dux;
-        vy[gy][gx] = uy + duy;
+        vx[gy][gx] = vxx;
+        vy[gy][gx] = vyy;
     }
     __syncthreads();
 
@@ -108,8 +108,8 @@ __device__ float demons_tile(const float* __restrict__ Rg, const float* __restri
         float ax = 0.0f, ay = 0.0f;
 #pragma unroll
         for (int j = 0; j <= 2 * RAD; j++) {
-            ax += tp.w[j] * vx[gy][x + j];
-            ay += tp.w[j] * vy[gy][x + j];
+            ax = fmaf(tp.w[j], vx[gy][x + j], ax);
+            ay = fmaf(tp.w[j], vy[gy][x + j], ay);
         }
         hx[gy][x] = ax;
         hy[gy][x] = ay;
@@ -123,14 +123,14 @@ __device__ float demons_tile(const float* __restrict__ Rg, const float* __restri
         float ax = 0.0f, ay = 0.0f;
 #pragma unroll
         for (int j = 0; j <= 2 * RAD; j++) {
-            ax += tp.w[j] * hx[y + j][x];
-            ay += tp.w[j] * hy[y + j][x];
+            ax = fmaf(tp.w[j], hx[y + j][x], ax);
+            ay = fmaf(tp.w[j], hy[y + j][x], ay);
         }
         const int gy = y0 + y, gx = x0 + x;
         if (gy < h && gx < w) {
             const int64_t i = (int64_t)gy * w + gx;
             const float dx = ax - u[i], dy = ay - uy_src[i];
-            ss += dx * dx + dy * dy;
+            ss = fmaf(dx, dx, fmaf(dy, dy, ss));
             un[i] = ax;
             un[hw + i] = ay;
         }
@@ -254,10 +254,10 @@ void launch_iter_rad(const Bucket* d_bk, const Bucket& hb, int level, int k, con
 }  // namespace
 
 hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, int k,
-                              const float* taps, int radius, float tol, hipStream_t s)
+                              const float* taps, int radius, float tol, int ty, hipStream_t s)
 {
     const Taps tp = make_taps(taps, radius);
-    if (launch_demons_rows(d_bk, hb, level, k, tp, radius, tol, s)) return hipGetLastError();
+    if (launch_demons_rows(d_bk, hb, level, k, tp, radius, tol, ty, s)) return hipGetLastError();
     switch (radius) {
     case 0: launch_iter_rad<0>(d_bk, hb, level, k, tp, tol, s); break;
     case 1: launch_iter_rad<1>(d_bk, hb, level, k, tp, tol, s); break;
@@ -270,9 +270,9 @@ hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, i
 }
 
 hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int cap, float tol,
-                            hipStream_t s)
+                            int ty, hipStream_t s)
 {
-    const int ntiles = demons_units(hb.H >> level, hb.W >> level);
+    const int ntiles = demons_units(hb.H >> level, hb.W >> level, ty);
     hipLaunchKernelGGL(k_level_end, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, level, cap, tol,
                        ntiles);
     return hipGetLastError();

@@ -36,10 +36,11 @@ __device__ float demons_strip(const float* __restrict__ Rg, const float* __restr
                               const float* __restrict__ ug, float* __restrict__ ung, int h, int w,
                               int y0, const Taps& tp, bool want_ss)
 {
-    const EBSD_GLOBAL float* __restrict__ R = gptr(Rg);
-    const EBSD_GLOBAL float* __restrict__ T = gptr(Tg);
-    const EBSD_GLOBAL float* __restrict__ u = gptr(ug);
-    EBSD_GLOBAL float* __restrict__ un = gptr(ung);
+    const unsigned img_bytes = 4u * (unsigned)h * (unsigned)w;
+    const __amdgpu_buffer_rsrc_t R = make_rsrc(Rg, img_bytes);
+    const __amdgpu_buffer_rsrc_t T = make_rsrc(Tg, img_bytes);
+    const __amdgpu_buffer_rsrc_t U = make_rsrc(ug, 2u * img_bytes);
+    const __amdgpu_buffer_rsrc_t UN = make_rsrc(ung, 2u * img_bytes);
     constexpr int NR = 2 * RAD + 1;  // ring rows
     constexpr int STEPS = TY + 2 * RAD;
     constexpr int RW = 64 * NW;      // LDS row length
@@ -54,17 +55,27 @@ __device__ float demons_strip(const float* __restrict__ Rg, const float* __restr
     int tap_col[2 * RAD + 1];
 #pragma unroll
     for (int j = 0; j <= 2 * RAD; j++) tap_col[j] = clampi(x + j - RAD, 0, w - 1);
-    const int64_t hw = (int64_t)h * w;
-    const EBSD_GLOBAL float* __restrict__ uy_src = u + hw;
+    const unsigned uw4 = 4u * (unsigned)w;
+    const unsigned x4 = 4u * (unsigned)x;
+    // byte offset of channel 1 of the field
+    const unsigned ch1 = img_bytes;
 
-    // rows of step 0 (y = y0 - RAD)
-    int yc = clampi(y0 - RAD, 0, h - 1);
+    // Pipeline state at the start of step s (row y = y0 - RAD + s):
+    //   r_m, r_c, r_p   R rows ym, yc, yp of row y (registers)
+    //   ux, uy          field of row y;  g = T gathers of row y (in flight)
+    //   ux1, uy1        field of row y + 1 (in flight)
+    auto rowc = [&](int yy) { return clampi(yy, 0, h - 1); };
+    int yc = rowc(y0 - RAD);
     int ym = max(yc - 1, 0), yp = min(yc + 1, h - 1);
-    float r_m = R[(int64_t)ym * w + x];
-    float r_c = R[(int64_t)yc * w + x];
-    float r_p = R[(int64_t)yp * w + x];
-    float ux = u[(int64_t)yc * w + x];
-    float uy = uy_src[(int64_t)yc * w + x];
+    float r_m = bload(R, (unsigned)ym * uw4 + x4);
+    float r_c = bload(R, (unsigned)yc * uw4 + x4);
+    float r_p = bload(R, (unsigned)yp * uw4 + x4);
+    float ux = bload(U, (unsigned)yc * uw4 + x4);
+    float uy = bload(U, ch1 + (unsigned)yc * uw4 + x4);
+    const int yc1 = rowc(y0 - RAD + 1);
+    float ux1 = bload(U, (unsigned)yc1 * uw4 + x4);
+    float uy1 = bload(U, ch1 + (unsigned)yc1 * uw4 + x4);
+    Bilin g = bilinear_issue(T, h, w, (float)x + ux, (float)yc + uy);
     lds_r[0][c] = r_c;
     __syncthreads();
 
@@ -79,35 +90,39 @@ __device__ float demons_strip(const float* __restrict__ Rg, const float* __restr
             if (step >= STEPS) break;  // uniform
             const int par = step & 1;
             const int y = y0 - RAD + step;
-            // 1. gathers of this row
-            const float wv = bilinear_clamped(T, h, w, (float)x + ux, (float)yc + uy);
-            // 2. prefetch the next row (rows ym/yc of the next step are this
-            //    step's yc/yp, or repeat at a clamped border)
             const bool more = step + 1 < STEPS;
-            const int nyc = clampi(y + 1, 0, h - 1);
+            const bool more2 = step + 2 < STEPS;
+            // 1. prefetch: field of row y + 2, the one new R row of row y + 1
+            const int nyc = rowc(y + 1);
             const int nym = max(nyc - 1, 0), nyp = min(nyc + 1, h - 1);
-            float n_rp = 0.0f, n_ux = 0.0f, n_uy = 0.0f;
-            if (more) {
-                n_rp = R[(int64_t)nyp * w + x];
-                n_ux = u[(int64_t)nyc * w + x];
-                n_uy = uy_src[(int64_t)nyc * w + x];
+            const int yc2 = rowc(y + 2);
+            float n_rp = 0.0f, ux2 = 0.0f, uy2 = 0.0f;
+            if (more) n_rp = bload(R, (unsigned)nyp * uw4 + x4);
+            if (more2) {
+                ux2 = bload(U, (unsigned)yc2 * uw4 + x4);
+                uy2 = bload(U, ch1 + (unsigned)yc2 * uw4 + x4);
             }
+            // 2. gathers of row y + 1 (its field was requested one step ago)
+            Bilin g1 = g;
+            if (more) g1 = bilinear_issue(T, h, w, (float)x + ux1, (float)nyc + uy1);
+            // rows ym/yc of the next step are this step's yc/yp, or repeat at a clamped border
             const float n_rm = (nym == yc) ? r_c : (nym == yp ? r_p : r_m);
             const float n_rc = (nyc == yp) ? r_p : r_c;
-            // 3. force
+            // 3. force of row y (its gathers were requested one step ago)
+            const float wv = bilinear_blend(g);
             const float sy = (yp - ym == 2) ? 0.5f : 1.0f;
             const float gyr = (r_p - r_m) * sy;
             const float gxr = (lds_r[par][xp] - lds_r[par][xm]) * sx;
             const float a = r_c - wv;
-            const float den = gxr * gxr + gyr * gyr + a * a;
-            float dux = 0.0f, duy = 0.0f;
+            const float den = fmaf(gxr, gxr, fmaf(gyr, gyr, a * a));
+            float vx = ux, vy = uy;
             if (den > 1e-9f) {
                 const float q = a * __builtin_amdgcn_rcpf(den);
-                dux = q * gxr;
-                duy = q * gyr;
+                vx = fmaf(q, gxr, ux);
+                vy = fmaf(q, gyr, uy);
             }
-            lds_v[par][0][c] = ux + dux;
-            lds_v[par][1][c] = uy + duy;
+            lds_v[par][0][c] = vx;
+            lds_v[par][1][c] = vy;
             if (more) lds_r[par ^ 1][c] = n_rc;
             ring_ux[s] = ux;
             ring_uy[s] = uy;
@@ -116,8 +131,8 @@ __device__ float demons_strip(const float* __restrict__ Rg, const float* __restr
             float ax = 0.0f, ay = 0.0f;
 #pragma unroll
             for (int j = 0; j <= 2 * RAD; j++) {
-                ax += tp.w[j] * lds_v[par][0][tap_col[j]];
-                ay += tp.w[j] * lds_v[par][1][tap_col[j]];
+                ax = fmaf(tp.w[j], lds_v[par][0][tap_col[j]], ax);
+                ay = fmaf(tp.w[j], lds_v[par][1][tap_col[j]], ay);
             }
             ring_x[s] = ax;
             ring_y[s] = ay;
@@ -130,26 +145,29 @@ __device__ float demons_strip(const float* __restrict__ Rg, const float* __restr
                     for (int j = 0; j <= 2 * RAD; j++) {
                         // row yo - RAD + j was computed at step (step - 2 RAD + j)
                         const int slot = (s + 1 + j) % NR;
-                        ox += tp.w[j] * ring_x[slot];
-                        oy += tp.w[j] * ring_y[slot];
+                        ox = fmaf(tp.w[j], ring_x[slot], ox);
+                        oy = fmaf(tp.w[j], ring_y[slot], oy);
                     }
                     if (want_ss) {
                         // u of row yo was read at step (step - RAD)
                         const int us = (s + RAD + 1) % NR;
                         const float dx = ox - ring_ux[us], dy = oy - ring_uy[us];
-                        ss += dx * dx + dy * dy;
+                        ss = fmaf(dx, dx, fmaf(dy, dy, ss));
                     }
-                    const int64_t o = (int64_t)yo * w + c;
-                    un[o] = ox;
-                    un[hw + o] = oy;
+                    const unsigned o = (unsigned)yo * uw4 + 4u * (unsigned)c;
+                    bstore(UN, o, ox);
+                    bstore(UN, ch1 + o, oy);
                 }
             }
             // 6. rotate
             r_m = n_rm;
             r_c = n_rc;
             r_p = n_rp;
-            ux = n_ux;
-            uy = n_uy;
+            ux = ux1;
+            uy = uy1;
+            ux1 = ux2;
+            uy1 = uy2;
+            g = g1;
             ym = nym;
             yc = nyc;
             yp = nyp;
@@ -217,37 +235,50 @@ __global__ void __launch_bounds__(64 * NW)
     if (rms && threadIdx.x == 0) rms[b] = sqrt(acc / (double)hw);
 }
 
-constexpr int kRowsTY = 32;
-
-template <int CPL, int RAD>
+template <int CPL, int RAD, int TY>
 void launch_rows(const Bucket* d_bk, int nb, int h, int level, int k, const Taps& tp, float tol,
                  hipStream_t s)
 {
-    const int nstrips = (h + kRowsTY - 1) / kRowsTY;
-    hipLaunchKernelGGL((k_demons_rows<CPL, RAD, kRowsTY>), dim3(nb * nstrips), dim3(64 * CPL), 0, s, d_bk,
+    const int nstrips = (h + TY - 1) / TY;
+    hipLaunchKernelGGL((k_demons_rows<CPL, RAD, TY>), dim3(nb * nstrips), dim3(64 * CPL), 0, s, d_bk,
                        level, k, tp, tol, nstrips);
+}
+
+template <int CPL, int RAD>
+bool dispatch_ty(const Bucket* d_bk, int nb, int h, int level, int k, const Taps& tp, float tol,
+                 int ty, hipStream_t s)
+{
+    switch (ty) {
+    case 16: launch_rows<CPL, RAD, 16>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    case 32: launch_rows<CPL, RAD, 32>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    case 64: launch_rows<CPL, RAD, 64>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    case 128: launch_rows<CPL, RAD, 128>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    default: return false;
+    }
 }
 
 template <int CPL>
 bool dispatch_rad(const Bucket* d_bk, int nb, int h, int level, int k, const Taps& tp, int radius,
-                  float tol, hipStream_t s)
+                  float tol, int ty, hipStream_t s)
 {
     switch (radius) {
-    case 0: launch_rows<CPL, 0>(d_bk, nb, h, level, k, tp, tol, s); return true;
-    case 1: launch_rows<CPL, 1>(d_bk, nb, h, level, k, tp, tol, s); return true;
-    case 2: launch_rows<CPL, 2>(d_bk, nb, h, level, k, tp, tol, s); return true;
-    case 3: launch_rows<CPL, 3>(d_bk, nb, h, level, k, tp, tol, s); return true;
-    case 4: launch_rows<CPL, 4>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    case 0: return dispatch_ty<CPL, 0>(d_bk, nb, h, level, k, tp, tol, ty, s);
+    case 1: return dispatch_ty<CPL, 1>(d_bk, nb, h, level, k, tp, tol, ty, s);
+    case 2: return dispatch_ty<CPL, 2>(d_bk, nb, h, level, k, tp, tol, ty, s);
+    case 3: return dispatch_ty<CPL, 3>(d_bk, nb, h, level, k, tp, tol, ty, s);
+    case 4: return dispatch_ty<CPL, 4>(d_bk, nb, h, level, k, tp, tol, ty, s);
     default: return false;
     }
 }
+
+constexpr int kStageTY = 64;
 
 template <int CPL, int RAD>
 void launch_rows_stage(const float* R, const float* T, int n, int h, int w, const float* u,
                        const Taps& tp, float* un, double* rms, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_demons_rows_stage<CPL, RAD, kRowsTY>), dim3(n), dim3(64 * CPL), 0, s, R, T, h, w,
-                       u, tp, un, rms);
+    hipLaunchKernelGGL((k_demons_rows_stage<CPL, RAD, kStageTY>), dim3(n), dim3(64 * CPL), 0, s, R, T,
+                       h, w, u, tp, un, rms);
 }
 
 template <int CPL>
@@ -274,16 +305,18 @@ int rows_cpl(int w)
     return 0;
 }
 
-int rows_units(int h) { return (h + kRowsTY - 1) / kRowsTY; }
+bool rows_ty_supported(int ty) { return ty == 16 || ty == 32 || ty == 64 || ty == 128; }
+
+int rows_units(int h, int ty) { return (h + ty - 1) / ty; }
 
 bool launch_demons_rows(const Bucket* d_bk, const Bucket& hb, int level, int k, const Taps& tp,
-                        int radius, float tol, hipStream_t s)
+                        int radius, float tol, int ty, hipStream_t s)
 {
     const int h = hb.H >> level, w = hb.W >> level;
     switch (rows_cpl(w)) {
-    case 1: return dispatch_rad<1>(d_bk, hb.nb, h, level, k, tp, radius, tol, s);
-    case 2: return dispatch_rad<2>(d_bk, hb.nb, h, level, k, tp, radius, tol, s);
-    case 4: return dispatch_rad<4>(d_bk, hb.nb, h, level, k, tp, radius, tol, s);
+    case 1: return dispatch_rad<1>(d_bk, hb.nb, h, level, k, tp, radius, tol, ty, s);
+    case 2: return dispatch_rad<2>(d_bk, hb.nb, h, level, k, tp, radius, tol, ty, s);
+    case 4: return dispatch_rad<4>(d_bk, hb.nb, h, level, k, tp, radius, tol, ty, s);
     default: return false;
     }
 }

@@ -80,7 +80,8 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_get_params", "ebsd_roi_layout", "ebsd_register_batch",
             "ebsd_register_batch_init", "ebsd_second_pass_batch", "ebsd_stage_normalize",
             "ebsd_stage_restrict", "ebsd_stage_demons_iter", "ebsd_stage_prolong",
-            "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_set_timing", "ebsd_get_timing"]
+            "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_set_timing", "ebsd_get_timing",
+            "ebsd_autotune", "ebsd_get_strip_height", "ebsd_set_strip_height"]
 
 
 def lib():
@@ -103,6 +104,9 @@ def lib():
         L.ebsd_register_batch.argtypes = [vp, C.POINTER(CPair), i32, C.POINTER(COutputs), vp]
         L.ebsd_register_batch_init.argtypes = [vp, C.POINTER(CPair), i32, vp, C.POINTER(COutputs), vp]
         L.ebsd_second_pass_batch.argtypes = [vp, C.POINTER(CPair), i32, vp, C.POINTER(COutputs), vp]
+        L.ebsd_autotune.argtypes = [vp, C.POINTER(CPair), i32, vp]
+        L.ebsd_get_strip_height.argtypes = [vp, i32, i32]
+        L.ebsd_set_strip_height.argtypes = [vp, i32, i32, i32]
         L.ebsd_set_timing.argtypes = [vp, C.c_int]
         L.ebsd_get_timing.argtypes = [vp, vp, vp]
         L.ebsd_stage_normalize.argtypes = [vp, i32, i64, vp, vp, vp]
@@ -296,6 +300,21 @@ class Registrar:
         _check(rc, "ebsd_register_batch")
         out["_keep"] = (keep, co, arr, u_init)
         return self._unflatten_field(out, shapes)
+
+    def autotune(self, refs, tests, ref_ids=None):
+        """Time the demons strip heights on this batch and keep the fastest per
+        level; returns {(h, w): rows}."""
+        arr, n, shapes, keep = self._pairs(refs, tests, ref_ids)
+        _check(lib().ebsd_autotune(self._h, arr, n, _stream()), "ebsd_autotune")
+        out = {}
+        if shapes:
+            H, W = shapes[0]
+            for l in range(self.params.levels):
+                out[(H >> l, W >> l)] = lib().ebsd_get_strip_height(self._h, H >> l, W >> l)
+        return out
+
+    def set_strip_height(self, level_h, level_w, rows):
+        _check(lib().ebsd_set_strip_height(self._h, level_h, level_w, rows), "ebsd_set_strip_height")
 
     def set_timing(self, on=True):
         _check(lib().ebsd_set_timing(self._h, int(bool(on))), "ebsd_set_timing")
