@@ -42,6 +42,7 @@ def main():
     ap.add_argument("--cap", type=int, default=150)
     ap.add_argument("--cpu-sample", type=int, default=32, help="pairs timed on the CPU oracle (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "demons_traffic.json"))
+    ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (counter calibration) and exit")
     args = ap.parse_args()
@@ -82,6 +83,7 @@ def main():
     params = ebsd.Params(levels=3, iters=(args.cap,) * 3, sigma_px=1.0, tol_px=args.tol,
                          roi_size=w["roi"], n_roi=20)
     reg = ebsd.Registrar(params, device=0)
+    reg.set_graphs(not args.no_graphs)
     tuned = reg.autotune(d_refs, d_tests)  # strip heights per level, outside the timed region
     log(f"[bench] autotuned strip heights: {tuned}")
     reg.set_timing(True)
@@ -148,6 +150,7 @@ def main():
             "n_roi": 20, "roi": w["roi"], "mode": "plain",
             "strip_rows": {f"{k[0]}x{k[1]}": v for k, v in tuned.items()},
             "parallelism": "single GPU, batch of independent pairs",
+            "launch": "direct" if args.no_graphs else "hipGraph replay",
         },
         "roofline": {
             "bound": "hbm",

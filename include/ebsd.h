@@ -182,6 +182,15 @@ int ebsd_second_pass_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
  * work decomposition). */
 int ebsd_autotune(ebsd_handle* h, const ebsd_pair* pairs, int32_t n, void* stream);
 
+/* Graph replay (default on): the demons iterations of each pyramid level
+ * (one launch per iteration) form a static sequence for a given batch
+ * configuration (pair size, batch size, distinct references, parameters,
+ * strip height); it is captured once into a HIP graph and replayed on later
+ * calls, the per-call pointers travelling in a descriptor copied before the
+ * replay.  enable = 0 makes later calls launch every kernel directly.
+ * Results are identical either way. */
+int ebsd_set_graphs(ebsd_handle* h, int enable);
+
 /* Strip height used for a pyramid level of level_h x level_w px (0 if that
  * level uses the 2-D tile kernel, i.e. wider than 256 px). */
 int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w);

@@ -45,6 +45,11 @@ struct ebsd_handle {
     // from ebsd_autotune or the tuning cache file; default kDefaultStripTY
     std::map<std::pair<int, int>, int> strip_ty;
     std::string tune_cache;  // EBSD_TUNE_CACHE at create time (may be empty)
+    // captured launch sequences per bucket configuration (replayed with
+    // hipGraphLaunch); the capture itself runs on a private stream
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::string, hipGraphExec_t> graph_cache;
 };
 
 namespace {
@@ -188,10 +193,18 @@ int map_err(hipError_t e)
 
 // Make sure the handle's workspace holds `bytes`.  Growing waits for all
 // work on the device, since earlier calls may still be using the old buffer.
+void clear_graphs(ebsd_handle* h)
+{
+    for (auto& kv : h->graph_cache)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    h->graph_cache.clear();
+}
+
 int ensure_ws(ebsd_handle* h, size_t bytes)
 {
     if (bytes <= h->ws_bytes) return EBSD_OK;
     if (hipDeviceSynchronize() != hipSuccess) return EBSD_EDEVICE;
+    clear_graphs(h);  // captured kernels point into the old workspace
     if (h->ws) (void)hipFree(h->ws);
     h->ws = nullptr;
     h->ws_bytes = 0;
@@ -379,6 +392,21 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.rotvec = reinterpret_cast<double*>(base + o_rv);
     b.status = reinterpret_cast<uint32_t*>(base + o_st);
 
+    bool want_field = mode == Mode::Full && out->field;
+    b.out.F = out->F;
+    b.out.R = out->R;
+    b.out.rotvec = out->rotvec;
+    b.out.Rfin = out->R_finite;
+    b.out.F1 = mode == Mode::Full ? out->F_first : nullptr;
+    b.out.q1 = mode == Mode::Full ? out->q1 : nullptr;
+    b.out.q2 = out->q2;
+    b.out.ph = out->peak_height;
+    b.out.iters = mode == Mode::Full ? out->iters : nullptr;
+    b.out.status = out->status;
+    b.u_init = u_init;
+    b.field_dst = want_field ? reinterpret_cast<float* const*>(base + o_dst) : nullptr;
+    b.rfin_in = rfin_in;
+
     // descriptor blob in pinned memory
     char* pin = h->pin + pin_off;
     std::memset(pin, 0, desc_bytes);
@@ -400,7 +428,6 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         std::memcpy(pin + o_roi_c, c2.data(), sizeof(double) * 2 * nr);
         std::memcpy(pin + o_roi_xy, xy.data(), sizeof(int32_t) * 2 * nr);
     }
-    bool want_field = mode == Mode::Full && out->field;
     if (want_field) {
         float** dst = reinterpret_cast<float**>(pin + o_dst);
         for (int k = 0; k < nb; k++) {
@@ -426,7 +453,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     EBSD_TRY(launch_pyramids(d_bk, b, s));
     if (tune_only) {
         // time each supported strip height for every row-marching level
-        EBSD_TRY(launch_demons_init(d_bk, b, nullptr, s));
+        EBSD_TRY(launch_demons_init(d_bk, b, s));
         hipEvent_t e0, e1;
         EBSD_TRY(hipEventCreate(&e0));
         EBSD_TRY(hipEventCreate(&e1));
@@ -456,41 +483,71 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         (void)hipEventDestroy(e1);
         return EBSD_OK;
     }
+    // The demons iterations of one level (up to a few hundred launches) are a
+    // static sequence for a given configuration: captured once into a graph
+    // and replayed; the few other launches and the timing events stay on the
+    // stream.
+    auto level_iters = [&](int l, int ty, hipStream_t st) -> int {
+        for (int it = 0; it < p.max_iters[l]; it++)
+            EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, p.tol_px, ty, st));
+        return EBSD_OK;
+    };
+    auto run_level = [&](int l, int ty) -> int {
+        if (h->graphs && p.max_iters[l] > 0) {
+            std::ostringstream key;
+            key << H << ' ' << W << ' ' << nb << ' ' << nref << ' ' << l << ' ' << p.max_iters[l]
+                << ' ' << p.tol_px << ' ' << h->radius << ' ' << ty << ' ' << (void*)base;
+            auto it = h->graph_cache.find(key.str());
+            hipGraphExec_t exec = nullptr;
+            if (it != h->graph_cache.end()) {
+                exec = it->second;
+            } else {
+                if (!h->cap_stream &&
+                    hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+                    h->cap_stream = nullptr;
+                hipGraph_t graph = nullptr;
+                if (h->cap_stream &&
+                    hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+                    const int e = level_iters(l, ty, h->cap_stream);
+                    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+                    if (e == EBSD_OK && ec == hipSuccess && graph &&
+                        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                        exec = nullptr;
+                    if (graph) (void)hipGraphDestroy(graph);
+                }
+                (void)hipGetLastError();
+                h->graph_cache[key.str()] = exec;  // nullptr: this configuration runs eagerly
+            }
+            if (exec) {
+                EBSD_TRY(hipGraphLaunch(exec, s));
+                return EBSD_OK;
+            }
+        }
+        return level_iters(l, ty, s);
+    };
     if (mode == Mode::Full) {
-        EBSD_TRY(launch_demons_init(d_bk, b, u_init, s));
+        EBSD_TRY(launch_demons_init(d_bk, b, s));
         for (int l = L - 1; l >= 0; l--) {
             const int ty = strip_ty_for(h, H >> l, W >> l);
             if (tm) EBSD_TRY(hipEventRecord(h->ev[2 + 2 * l], s));
-            for (int it = 0; it < p.max_iters[l]; it++)
-                EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, p.tol_px, ty, s));
+            const int e = run_level(l, ty);
+            if (e) return e;
             if (tm) EBSD_TRY(hipEventRecord(h->ev[3 + 2 * l], s));
             EBSD_TRY(launch_level_end(d_bk, b, l, p.max_iters[l], p.tol_px, ty, s));
             if (l > 0) EBSD_TRY(launch_prolong_level(d_bk, b, l, s));
         }
         EBSD_TRY(launch_sample_q1(d_bk, b, s));
-        if (want_field)
-            EBSD_TRY(launch_copy_field(d_bk, b, reinterpret_cast<float* const*>(base + o_dst), s));
+        if (want_field) EBSD_TRY(launch_copy_field(d_bk, b, s));
         EBSD_TRY(launch_solve_first(d_bk, b, p.tol_px, s));
         if (p.second_pass) EBSD_TRY(launch_xcf_pairs(d_bk, b, p.window, s));
         EBSD_TRY(launch_solve_second(d_bk, b, p.second_pass, s));
     } else {
-        EBSD_TRY(launch_gather_rfin(d_bk, b, rfin_in, s));
+        EBSD_TRY(launch_gather_rfin(d_bk, b, s));
         EBSD_TRY(launch_status_inputs(d_bk, b, s));
         EBSD_TRY(launch_xcf_pairs(d_bk, b, p.window, s));
         EBSD_TRY(launch_solve_second(d_bk, b, 1, s));
     }
-    OutPtrs o;
-    o.F = out->F;
-    o.R = out->R;
-    o.rotvec = out->rotvec;
-    o.Rfin = out->R_finite;
-    o.F1 = mode == Mode::Full ? out->F_first : nullptr;
-    o.q1 = mode == Mode::Full ? out->q1 : nullptr;
-    o.q2 = out->q2;
-    o.ph = out->peak_height;
-    o.iters = mode == Mode::Full ? out->iters : nullptr;
-    o.status = out->status;
-    EBSD_TRY(launch_scatter(d_bk, b, o, s));
+    EBSD_TRY(launch_scatter(d_bk, b, s));
     if (tm) {
         EBSD_TRY(hipEventRecord(h->ev[1], s));
         h->timed_call = true;
@@ -629,6 +686,13 @@ int ebsd_autotune(ebsd_handle* h, const ebsd_pair* pairs, int32_t n, void* strea
                                                                                    : EBSD_EDEVICE;
 }
 
+int ebsd_set_graphs(ebsd_handle* h, int enable)
+{
+    if (!h) return EBSD_EINVAL;
+    h->graphs = enable != 0;
+    return EBSD_OK;
+}
+
 int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w)
 {
     if (!h || level_h <= 0 || level_w <= 0) return EBSD_EINVAL;
@@ -652,6 +716,8 @@ int ebsd_destroy(ebsd_handle* h)
         if (h->ws) (void)hipFree(h->ws);
         if (h->pin) (void)hipHostFree(h->pin);
         if (h->pin_free) (void)hipEventDestroy(h->pin_free);
+        clear_graphs(h);
+        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
         for (auto& e : h->ev)
             if (e) (void)hipEventDestroy(e);
     }

@@ -37,6 +37,19 @@ struct PairState {
     uint32_t convmask;  // bit l set when level l stopped on the tolerance
 };
 
+// Caller output pointers (any may be NULL), indexed by the caller's pair index.
+struct OutPtrs {
+    double* F;
+    double* R;
+    double* rotvec;
+    double* Rfin;
+    double* F1;
+    float* q1;
+    float* q2;
+    float* ph;
+    int32_t* iters;
+    uint32_t* status;
+};
 // Everything a bucket's kernels need, in device memory (one copy per bucket).
 struct Bucket {
     int32_t nb;                 // pairs in the bucket
@@ -70,6 +83,12 @@ struct Bucket {
     double* R;                  // [nb][9]
     double* rotvec;             // [nb][3]
     uint32_t* status;           // [nb]
+    // per-call caller pointers (so that a bucket's launch sequence is static
+    // and can be replayed from a captured graph)
+    OutPtrs out;                // results, scattered by pair_index
+    const float* u_init;        // [nb][2][h][w] coarsest initial field or NULL
+    float* const* field_dst;    // [nb] destination of each final field or NULL
+    const double* rfin_in;      // [caller n][9] R_finite for the second-pass-only entry
 };
 
 // ---- launchers (defined next to their kernels) -------------------------------
@@ -79,9 +98,8 @@ hipError_t launch_stats(const Bucket* d_bk, int nb, int nref, hipStream_t s);
 // Normalise level 0 of every pyramid and build levels 1..L-1.
 hipError_t launch_pyramids(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Reset per-pair state and set the coarsest-level initial field
-// (u_init [nb][2][h][w] in full-res px, or zero).
-hipError_t launch_demons_init(const Bucket* d_bk, const Bucket& hb, const float* u_init,
-                              hipStream_t s);
+// (bk->u_init [nb][2][h][w] in full-res px, or zero).
+hipError_t launch_demons_init(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Iteration k (0-based) of level l for every pair that has not stopped; ty =
 // strip height of the row-marching kernel.
 hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, int k,
@@ -93,9 +111,8 @@ hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int
 hipError_t launch_prolong_level(const Bucket* d_bk, const Bucket& hb, int level, hipStream_t s);
 // Sample the finest field at the ROI centres -> q1.
 hipError_t launch_sample_q1(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
-// Copy the finest field to the caller (field_ptr[i] = destination of pair i or NULL).
-hipError_t launch_copy_field(const Bucket* d_bk, const Bucket& hb, float* const* d_dst,
-                             hipStream_t s);
+// Copy the finest field to the caller (bk->field_dst[i] = destination of pair i or NULL).
+hipError_t launch_copy_field(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // First-pass solve: F1 from q1 (Eq. (3)), Rfin = polar(F1); status from the
 // input flags and, when tol > 0, the per-level convergence.
 hipError_t launch_solve_first(const Bucket* d_bk, const Bucket& hb, float tol, hipStream_t s);
@@ -103,23 +120,9 @@ hipError_t launch_solve_first(const Bucket* d_bk, const Bucket& hb, float tol, h
 hipError_t launch_status_inputs(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Remap + ROI XCF for every (pair, ROI) -> q2, ph.
 hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, hipStream_t s);
-// Rfin[b] = R_finite_in[pair_index[b]] (second-pass-only entry).
-hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, const double* rfin_in,
-                              hipStream_t s);
-// Caller output pointers (any may be NULL), indexed by the caller's pair index.
-struct OutPtrs {
-    double* F;
-    double* R;
-    double* rotvec;
-    double* Rfin;
-    double* F1;
-    float* q1;
-    float* q2;
-    float* ph;
-    int32_t* iters;
-    uint32_t* status;
-};
-hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, const OutPtrs& o, hipStream_t s);
+// Rfin[b] = bk->rfin_in[pair_index[b]] (second-pass-only entry).
+hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
+hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Second-pass solve: F_inf from q2, F = F_inf Rfin, det 1, R, rotvec.
 hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass,
                                hipStream_t s);

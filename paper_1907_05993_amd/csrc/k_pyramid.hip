@@ -205,8 +205,9 @@ __global__ void k_prolong_plain(const float* __restrict__ u, int h, int w, float
 }
 
 // Reset demons state; coarsest-level field = u_init / 2^(L-1) or zero.
-__global__ void k_demons_init(const Bucket* __restrict__ bk, const float* __restrict__ u_init)
+__global__ void k_demons_init(const Bucket* __restrict__ bk)
 {
+    const float* __restrict__ u_init = bk->u_init;
     const int b = blockIdx.y;
     const int L = bk->L;
     const int h = bk->H >> (L - 1), w = bk->W >> (L - 1);
@@ -239,10 +240,11 @@ __global__ void k_sample_q1(const Bucket* __restrict__ bk)
     bk->q1[2 * t + 1] = bilinear_clamped(f + (int64_t)H * W, H, W, cx, cy);
 }
 
-__global__ void k_copy_field(const Bucket* __restrict__ bk, float* const* __restrict__ dsts)
+__global__ void k_copy_field(const Bucket* __restrict__ bk)
 {
     const int b = blockIdx.y;
-    float* dst = dsts[b];
+    if (!bk->field_dst) return;
+    float* dst = bk->field_dst[b];
     if (!dst) return;
     const int64_t n = (int64_t)2 * bk->H * bk->W;
     const float4* src = reinterpret_cast<const float4*>(bk->field[bk->state[b].cur] + (int64_t)b * n);
@@ -306,11 +308,10 @@ hipError_t launch_pyramids(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_demons_init(const Bucket* d_bk, const Bucket& hb, const float* u_init,
-                              hipStream_t s)
+hipError_t launch_demons_init(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
     int64_t n = (int64_t)2 * (hb.H >> (hb.L - 1)) * (hb.W >> (hb.L - 1));
-    hipLaunchKernelGGL(k_demons_init, dim3(grid_for(n, 64), hb.nb), dim3(256), 0, s, d_bk, u_init);
+    hipLaunchKernelGGL(k_demons_init, dim3(grid_for(n, 64), hb.nb), dim3(256), 0, s, d_bk);
     return hipGetLastError();
 }
 
@@ -329,11 +330,10 @@ hipError_t launch_sample_q1(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_copy_field(const Bucket* d_bk, const Bucket& hb, float* const* d_dst,
-                             hipStream_t s)
+hipError_t launch_copy_field(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
     int64_t n = (int64_t)2 * hb.H * hb.W / 4;
-    hipLaunchKernelGGL(k_copy_field, dim3(grid_for(n, 64), hb.nb), dim3(256), 0, s, d_bk, d_dst);
+    hipLaunchKernelGGL(k_copy_field, dim3(grid_for(n, 64), hb.nb), dim3(256), 0, s, d_bk);
     return hipGetLastError();
 }
 

@@ -337,16 +337,18 @@ __global__ void k_stage_solve(const float* __restrict__ q, int n, int n_roi,
     if (status) status[b] = st;
 }
 
-__global__ void k_gather_rfin(const Bucket* __restrict__ bk, const double* __restrict__ rin)
+__global__ void k_gather_rfin(const Bucket* __restrict__ bk)
 {
+    const double* __restrict__ rin = bk->rfin_in;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= bk->nb) return;
     const int64_t src = 9 * (int64_t)bk->pair_index[b];
     for (int i = 0; i < 9; i++) bk->Rfin[9 * (int64_t)b + i] = rin[src + i];
 }
 
-__global__ void k_scatter(const Bucket* __restrict__ bk, OutPtrs o)
+__global__ void k_scatter(const Bucket* __restrict__ bk)
 {
+    const OutPtrs o = bk->out;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= bk->nb) return;
     const int64_t g = bk->pair_index[b];
@@ -372,16 +374,15 @@ __global__ void k_scatter(const Bucket* __restrict__ bk, OutPtrs o)
 
 }  // namespace
 
-hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, const double* rfin_in,
-                              hipStream_t s)
+hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_rfin, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, rfin_in);
+    hipLaunchKernelGGL(k_gather_rfin, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, const OutPtrs& o, hipStream_t s)
+hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scatter, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, o);
+    hipLaunchKernelGGL(k_scatter, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk);
     return hipGetLastError();
 }
 

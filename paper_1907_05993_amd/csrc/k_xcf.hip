@@ -347,9 +347,13 @@ template <int N>
 hipError_t launch_pairs_n(const Bucket* d_bk, int blocks, int window, hipStream_t s)
 {
     const size_t sm = sizeof(XcfShared<N>);
-    hipError_t e = hipFuncSetAttribute((const void*)k_xcf_pairs<N>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
+    static bool attr_set = false;  // a host attribute, set once (not a stream operation)
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_xcf_pairs<N>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
     hipLaunchKernelGGL(k_xcf_pairs<N>, dim3(blocks), dim3(NT), sm, s, d_bk, window);
     return hipGetLastError();
 }

@@ -81,7 +81,7 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_register_batch_init", "ebsd_second_pass_batch", "ebsd_stage_normalize",
             "ebsd_stage_restrict", "ebsd_stage_demons_iter", "ebsd_stage_prolong",
             "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_set_timing", "ebsd_get_timing",
-            "ebsd_autotune", "ebsd_get_strip_height", "ebsd_set_strip_height"]
+            "ebsd_autotune", "ebsd_get_strip_height", "ebsd_set_strip_height", "ebsd_set_graphs"]
 
 
 def lib():
@@ -105,6 +105,7 @@ def lib():
         L.ebsd_register_batch_init.argtypes = [vp, C.POINTER(CPair), i32, vp, C.POINTER(COutputs), vp]
         L.ebsd_second_pass_batch.argtypes = [vp, C.POINTER(CPair), i32, vp, C.POINTER(COutputs), vp]
         L.ebsd_autotune.argtypes = [vp, C.POINTER(CPair), i32, vp]
+        L.ebsd_set_graphs.argtypes = [vp, C.c_int]
         L.ebsd_get_strip_height.argtypes = [vp, i32, i32]
         L.ebsd_set_strip_height.argtypes = [vp, i32, i32, i32]
         L.ebsd_set_timing.argtypes = [vp, C.c_int]
@@ -312,6 +313,10 @@ class Registrar:
             for l in range(self.params.levels):
                 out[(H >> l, W >> l)] = lib().ebsd_get_strip_height(self._h, H >> l, W >> l)
         return out
+
+    def set_graphs(self, on=True):
+        """Replay captured HIP graphs (default) or launch every kernel directly."""
+        _check(lib().ebsd_set_graphs(self._h, int(bool(on))), "ebsd_set_graphs")
 
     def set_strip_height(self, level_h, level_w, rows):
         _check(lib().ebsd_set_strip_height(self._h, level_h, level_w, rows), "ebsd_set_strip_height")

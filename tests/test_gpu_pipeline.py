@@ -286,3 +286,21 @@ def test_strip_height_does_not_change_results(E, orc):
     for o in outs[1:]:
         for k in ("field", "F", "iters", "status"):
             assert torch.equal(o[k], outs[0][k]), k
+
+
+def test_graph_replay_matches_eager(E, orc):
+    """Captured-graph replays (new inputs and outputs every call, eager work and
+    synchronisations in between) equal direct launches bit for bit."""
+    sets = [gen("single_128", 2, start=2 * k) for k in range(3)]
+    gp, _ = params_pair(E, orc, iters=25, roi=32, tol=0.03)
+    eager = E.Registrar(gp)
+    eager.set_graphs(False)
+    graph = E.Registrar(gp)
+    for rep in range(2):
+        for refs, tests, _ in sets:
+            a = graph.register(cuda(refs), cuda(tests))
+            torch.cuda.synchronize()
+            b = eager.register(cuda(refs), cuda(tests))
+            torch.cuda.synchronize()
+            for k in ("field", "F", "R", "q1", "q2", "peak_height", "iters", "status"):
+                assert torch.equal(a[k], b[k]), (rep, k)
