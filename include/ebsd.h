@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define EBSD_ABI_VERSION 1
+#define EBSD_ABI_VERSION 2
 #define EBSD_MAX_LEVELS 8
 
 /* return codes */
@@ -59,13 +59,17 @@ enum {
     EBSD_ENOMEM = -4,   /* device or pinned allocation failed */
     EBSD_EDEVICE = -5,  /* a HIP runtime call failed */
     EBSD_ENOTSUP = -6,  /* feature not available in this build */
-    EBSD_EVERSION = -8  /* ebsd_params.struct_size does not match this library */
+    EBSD_ENOMODEL = -7, /* warm start requested but no network parameters loaded */
+    EBSD_EVERSION = -8, /* ebsd_params.struct_size does not match this library */
+    EBSD_EIO = -9       /* a parameter file could not be read or written */
 };
 
 /* per-pair status bits */
 enum {
     EBSD_CONVERGED = 1,         /* tol > 0 and every level stopped on the tolerance */
     EBSD_HIT_CAP = 2,           /* tol > 0 and some level ran to its iteration cap */
+    EBSD_WARM_USED = 4,         /* warm start: the network's field started demons */
+    EBSD_WARM_FALLBACK = 8,     /* warm start: the field failed the Eq. (2) fit test; demons started from zero */
     EBSD_SOLVE_ILLCOND = 16,    /* an Eq. (3) solve was ill-conditioned (cond(J^T J) > 1e12) */
     EBSD_NONFINITE_INPUT = 32,  /* a pattern held NaN/Inf (treated as all-zero) */
     EBSD_DEGENERATE_INPUT = 64  /* a pattern had no contrast (treated as all-zero) */
@@ -83,6 +87,8 @@ typedef struct ebsd_params {
     double roi_radius_frac;               /* ring radius / W */
     int32_t window;                       /* 1 = Hann window on each ROI (section 2), 0 = none */
     int32_t second_pass;                  /* 1 = remap + XCF second pass (Eq. (12)); 0 = demons only */
+    int32_t warm_start;                   /* 1 = start demons from the network's field (256 x 256, 3 levels) */
+    float fallback_residual_px;           /* warm start: largest RMS misfit of the Eq. (2) fit, full-res px */
 } ebsd_params;
 
 /* One scan point.  ref/test: device pointers to H x W fp32 patterns.  Pairs
@@ -109,6 +115,8 @@ typedef struct ebsd_outputs {
     float* peak_height;         /* [n][n_roi] normalised XCF peak height */
     int32_t* iters;             /* [n][levels] demons iterations run per level */
     uint32_t* status;           /* [n] status bits */
+    float* warm_field;          /* [n][H/4][W/4][2] network field at the coarse grid, full-res px (warm start) */
+    float* warm_misfit;         /* [n] RMS misfit of the Eq. (2) fit to warm_field, full-res px (warm start) */
 } ebsd_outputs;
 
 /* Library ABI version (EBSD_ABI_VERSION). */
@@ -116,7 +124,8 @@ int ebsd_version(void);
 
 /* Fill *p with the defaults: 3 levels x 150 iterations, sigma 1 px, tol 0,
  * pattern centre (0.5, 0.5, 0.7), 20 ROIs of 64 px on a ring of 0.3 W, Hann
- * window, second pass on.  Returns EBSD_OK or EBSD_EINVAL (p == NULL). */
+ * window, second pass on, warm start off (fallback misfit 0.5 px).  Returns
+ * EBSD_OK or EBSD_EINVAL (p == NULL). */
 int ebsd_params_default(ebsd_params* p);
 
 /* Human-readable text of a return code (static storage). */
@@ -208,6 +217,89 @@ int ebsd_set_timing(ebsd_handle* h, int enable);
  * call.  EBSD_EINVAL if no timed call has been made. */
 int ebsd_get_timing(ebsd_handle* h, double* level_ms, double* total_ms);
 
+/* ---- warm-start network ------------------------------------------------------
+ *
+ * The demons iteration of section 1 starts from zero on the coarsest level.
+ * The warm start replaces that zero by the field a convolutional network
+ * predicts from the pair: a 4-level encoder (two 3 x 3 convolutions with ReLU
+ * per level, 32/64/128/256 channels at 256/128/64/32 px, 2 x 2 max pooling
+ * between levels) and a decoder at 64 x 64 px (nearest 2x upsampling of the
+ * 32 px features, concatenation with the 64 px encoder features, two 3 x 3
+ * convolutions of 128 channels with ReLU, a 1 x 1 convolution to 2 channels).
+ * Its output is the displacement field (x, y) at the coarse grid points, whose
+ * full-resolution coordinates are 4 i + 1.5, in full-resolution px.  Inputs
+ * are the z-scored reference and test patterns (256 x 256).
+ *
+ * Arithmetic: bf16 operands on the matrix cores with fp32 accumulation;
+ * activations are stored as bf16 (round to nearest even); biases, the 1 x 1
+ * head, the loss and the optimiser are fp32.  Training minimises the mean
+ * squared endpoint error against a label field with Adam (fp32 master
+ * parameters).
+ *
+ * Parameters: a flat fp32 vector of EBSD_CNN_PARAMS values; for each 3 x 3
+ * convolution in the order c1a, c1b, c2a, c2b, c3a, c3b, c4a, c4b, d1, d2 its
+ * weights [3][3][cin][cout] then its bias [cout]; then the head weights
+ * [128][2] and bias [2].  Files written by ebsd_cnn_save hold the 8 bytes
+ * "EBSDCNN1", an int64 count and the vector (little-endian).
+ *
+ * Fallback rule (warm start inside ebsd_register_batch): the Eq. (2) model is
+ * fitted (Eq. (3): direct linear start, Gauss-Newton, det F = 1) to the
+ * predicted field at the grid points within roi_radius_frac * W of the
+ * pattern centre; if the RMS endpoint misfit exceeds fallback_residual_px the
+ * pair starts from zero (EBSD_WARM_FALLBACK), otherwise from the predicted
+ * field (EBSD_WARM_USED).
+ */
+#define EBSD_CNN_PARAMS 1762306
+
+typedef struct ebsd_cnn ebsd_cnn;
+
+/* EBSD_CNN_PARAMS. */
+int64_t ebsd_cnn_num_params(void);
+
+/* Network on HIP device `device`, for batches of at most max_batch pairs
+ * (1..4096; device buffers of about 45 MB per pair are allocated here).
+ * Parameters start at zero; set or load them before use. */
+int ebsd_cnn_create(int device, int32_t max_batch, ebsd_cnn** out);
+int ebsd_cnn_destroy(ebsd_cnn* c);
+
+/* Copy the flat fp32 parameter vector from / to HOST memory (n must equal
+ * EBSD_CNN_PARAMS).  Setting parameters also resets the optimiser state. */
+int ebsd_cnn_set_params(ebsd_cnn* c, const float* host, int64_t n);
+int ebsd_cnn_get_params(const ebsd_cnn* c, float* host, int64_t n);
+/* Gradients of the last ebsd_cnn_train_step, same layout, HOST memory. */
+int ebsd_cnn_get_grads(const ebsd_cnn* c, float* host, int64_t n);
+
+/* Parameter files (format above).  EBSD_EIO on a read/write failure or a
+ * malformed file. */
+int ebsd_cnn_load(ebsd_cnn* c, const char* path);
+int ebsd_cnn_save(const ebsd_cnn* c, const char* path);
+
+/* Forward pass for n pairs: ref, test device [n][H][W] fp32 raw patterns,
+ * z-scored here; out device [n][H/4][W/4][2] fp32 (x, y) full-res px.
+ * n <= max_batch.  The warm start uses H = W = 256; other sizes with H a
+ * multiple of 64, W a multiple of 256 and H * W <= 65536 are accepted
+ * (EBSD_ESHAPE otherwise). */
+int ebsd_cnn_forward(ebsd_cnn* c, const float* ref, const float* test, int32_t n, int32_t H,
+                     int32_t W, float* out, void* stream);
+
+/* One training step on n pairs (sizes as for ebsd_cnn_forward): forward,
+ * loss against label (device [n][H/4][W/4][2] fp32), backward and, if
+ * update != 0, one Adam step with
+ * learning rate lr (beta1 0.9, beta2 0.999, eps 1e-8).  *loss (HOST) receives
+ * the mean squared endpoint error before the update; the call synchronises
+ * `stream`. */
+int ebsd_cnn_train_step(ebsd_cnn* c, const float* ref, const float* test, const float* label,
+                        int32_t n, int32_t H, int32_t W, float lr, int32_t update, float* loss,
+                        void* stream);
+
+/* Restart Adam (moments zero, step count 0). */
+int ebsd_cnn_reset_optimizer(ebsd_cnn* c);
+
+/* Parameters used by the warm start of a registration handle: from a file
+ * (ebsd_load_model) or copied from a network object (ebsd_set_model). */
+int ebsd_load_model(ebsd_handle* h, const char* path);
+int ebsd_set_model(ebsd_handle* h, const ebsd_cnn* c);
+
 /* ---- single-stage entry points (one kernel each; device pointers) ------- */
 
 /* z-score each of n contiguous patterns of `elems` fp32 values:
@@ -249,6 +341,30 @@ int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t
 int ebsd_stage_solve(const float* q, int32_t n, int32_t n_roi, const double* cx, const double* cy,
                      double xs, double ys, double zs, double* F, double* R, uint32_t* status,
                      void* stream);
+
+/* ---- single-kernel entry points of the warm-start network -------------------
+ * bf16 tensors are uint16_t bit patterns (the upper half of an IEEE float),
+ * NHWC.  Weights are fp32 [3][3][Cin][Cout] (rounded to bf16 here).  Shapes:
+ * H % 8 == 0, W % 32 == 0, Cin % 32 == 0 or Cin == 8, Cout % 32 == 0, Cin and
+ * Cout <= 512 (EBSD_ESHAPE otherwise).  These calls allocate a temporary
+ * device buffer and synchronise `stream`; they exist to check the kernels
+ * one at a time. */
+
+/* 3 x 3 convolution with zero padding 1 of x [n][H][W][Cin]: mode 0 writes
+ * bf16 max(conv + bias, 0) to out [n][H][W][Cout] (uint16_t); mode 1 writes
+ * the fp32 convolution (bias unused). */
+int ebsd_stage_conv3x3(const uint16_t* x, int32_t n, int32_t H, int32_t W, int32_t Cin, const float* w,
+                       const float* bias, int32_t Cout, int32_t mode, void* out, void* stream);
+
+/* Input gradient of that convolution: dx [n][H][W][Cin] fp32 from the output
+ * gradient dz [n][H][W][Cout] (bf16) and w [3][3][Cin][Cout]. */
+int ebsd_stage_conv3x3_dgrad(const uint16_t* dz, int32_t n, int32_t H, int32_t W, int32_t Cout,
+                             const float* w, int32_t Cin, float* dx, void* stream);
+
+/* Weight gradient dw [3][3][Cin][Cout] fp32 = sum over pixels of
+ * x[p + tap offset][ci] dz[p][co] (x, dz bf16); also needs H % 4 == 0. */
+int ebsd_stage_conv3x3_wgrad(const uint16_t* x, const uint16_t* dz, int32_t n, int32_t H, int32_t W,
+                             int32_t Cin, int32_t Cout, float* dw, void* stream);
 
 #ifdef __cplusplus
 }

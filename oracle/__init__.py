@@ -370,7 +370,7 @@ def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None)
             oi = _Outputs()
             for k in ("field", "q1", "F1", "Rfin", "q2", "ph", "F", "R", "rotvec", "iters", "status"):
                 a = out[k]
-                setattr(oi, k, a[i].ctypes.data if a is not None else None)
+                setattr(oi, k, a[i:i + 1].ctypes.data if a is not None else None)
             r_i = np.ascontiguousarray(refs[i])
             t_i = np.ascontiguousarray(tests[i])
             u_i = np.ascontiguousarray(ui[i])

@@ -22,6 +22,7 @@
 
 #include "../../include/ebsd.h"
 #include "ebsd_internal.h"
+#include "cnn_internal.h"
 
 using namespace ebsd;
 
@@ -50,6 +51,8 @@ struct ebsd_handle {
     bool graphs = true;
     hipStream_t cap_stream = nullptr;
     std::map<std::string, hipGraphExec_t> graph_cache;
+    // warm-start network (created by ebsd_load_model / ebsd_set_model)
+    ebsd_cnn* cnn = nullptr;
 };
 
 namespace {
@@ -123,8 +126,14 @@ int check_params(const ebsd_params* p)
     if (!(p->roi_radius_frac >= 0.0) || !std::isfinite(p->roi_radius_frac)) return EBSD_EINVAL;
     if (p->window != 0 && p->window != 1) return EBSD_EINVAL;
     if (p->second_pass != 0 && p->second_pass != 1) return EBSD_EINVAL;
+    if (p->warm_start != 0 && p->warm_start != 1) return EBSD_EINVAL;
+    if (!(p->fallback_residual_px >= 0.0f) || !std::isfinite(p->fallback_residual_px)) return EBSD_EINVAL;
     return EBSD_OK;
 }
+
+// The network's input and output grid: 256 x 256 patterns, 3 pyramid levels.
+constexpr int kWarmRes = 256, kWarmLevels = 3;
+constexpr int kWarmBatch = 256;  // pairs per network launch sequence
 
 // ROI layout for an H x W pattern (see ebsd_roi_layout in the header).
 int roi_layout(const ebsd_params& p, int H, int W, double* cx, double* cy, int32_t* x0, int32_t* y0)
@@ -363,6 +372,12 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const size_t o_R = w.take(sizeof(double) * 9 * nb);
     const size_t o_rv = w.take(sizeof(double) * 3 * nb);
     const size_t o_st = w.take(sizeof(uint32_t) * nb);
+    const bool warm = mode == Mode::Full && !tune_only && !u_init && p.warm_start;
+    const int64_t gcell = (int64_t)(H >> 2) * (W >> 2);
+    const size_t o_wfield = w.take(warm ? sizeof(float) * 2 * (size_t)nb * gcell : 0);
+    const size_t o_uinit = w.take(warm ? sizeof(float) * 2 * (size_t)nb * gcell : 0);
+    const size_t o_wmis = w.take(warm ? sizeof(float) * (size_t)nb : 0);
+    const size_t o_wflag = w.take(warm ? sizeof(uint32_t) * (size_t)nb : 0);
     int e = ensure_ws(h, w.off);
     if (e) return e;
     char* base = h->ws;
@@ -403,7 +418,14 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.out.ph = out->peak_height;
     b.out.iters = mode == Mode::Full ? out->iters : nullptr;
     b.out.status = out->status;
-    b.u_init = u_init;
+    b.u_init = warm ? reinterpret_cast<const float*>(base + o_uinit) : u_init;
+    if (warm) {
+        b.warm_field = reinterpret_cast<const float*>(base + o_wfield);
+        b.warm_misfit = reinterpret_cast<const float*>(base + o_wmis);
+        b.warm_flag = reinterpret_cast<const uint32_t*>(base + o_wflag);
+        b.out.warm_field = out->warm_field;
+        b.out.warm_misfit = out->warm_misfit;
+    }
     b.field_dst = want_field ? reinterpret_cast<float* const*>(base + o_dst) : nullptr;
     b.rfin_in = rfin_in;
 
@@ -525,6 +547,22 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         }
         return level_iters(l, ty, s);
     };
+    if (warm) {
+        // network field at the coarse grid, chunk by chunk, then the Eq. (2)
+        // fit that decides between it and zero
+        float* wf = reinterpret_cast<float*>(base + o_wfield);
+        const int cm = cnn_max_batch(h->cnn);
+        for (int c0 = 0; c0 < nb; c0 += cm) {
+            const int cnt = std::min(cm, nb - c0);
+            const int ec = cnn_forward_from(h->cnn, b.ref_pyr, pe, b.ref_slot + c0, b.test_pyr + (int64_t)c0 * pe, pe,
+                                            cnt, wf + (int64_t)c0 * 2 * gcell, s);
+            if (ec) return ec;
+        }
+        EBSD_TRY(launch_warm_fit(wf, nb, H, W, b.xs, b.ys, b.zs, p.roi_radius_frac * W,
+                                 (double)p.fallback_residual_px, reinterpret_cast<float*>(base + o_uinit),
+                                 reinterpret_cast<float*>(base + o_wmis), reinterpret_cast<uint32_t*>(base + o_wflag),
+                                 s));
+    }
     if (mode == Mode::Full) {
         EBSD_TRY(launch_demons_init(d_bk, b, s));
         for (int l = L - 1; l >= 0; l--) {
@@ -548,6 +586,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         EBSD_TRY(launch_solve_second(d_bk, b, 1, s));
     }
     EBSD_TRY(launch_scatter(d_bk, b, s));
+    if (warm && out->warm_field) EBSD_TRY(launch_scatter_warm(d_bk, b, s));
     if (tm) {
         EBSD_TRY(hipEventRecord(h->ev[1], s));
         h->timed_call = true;
@@ -574,6 +613,12 @@ int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u
     if (mode == Mode::SecondPassOnly && !rfin_in) return EBSD_EINVAL;
     std::vector<HostBucket> buckets = make_buckets(pairs, n);
     if (u_init && buckets.size() != 1) return EBSD_EINVAL;
+    if (mode == Mode::Full && !tune_only && !u_init && h->p.warm_start) {
+        if (!cnn_ready(h->cnn)) return EBSD_ENOMODEL;
+        if (h->p.levels != kWarmLevels) return EBSD_ESHAPE;
+        for (auto& hb : buckets)
+            if (hb.H != kWarmRes || hb.W != kWarmRes) return EBSD_ESHAPE;
+    }
     DeviceGuard g(h->device);
     if (!g.ok) return EBSD_EDEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -617,6 +662,8 @@ int ebsd_params_default(ebsd_params* p)
     p->roi_radius_frac = 0.3f;
     p->window = 1;
     p->second_pass = 1;
+    p->warm_start = 0;
+    p->fallback_residual_px = 0.5f;
     return EBSD_OK;
 }
 
@@ -630,7 +677,9 @@ const char* ebsd_strerror(int code)
     case EBSD_ENOMEM: return "out of memory";
     case EBSD_EDEVICE: return "HIP runtime error";
     case EBSD_ENOTSUP: return "not supported";
+    case EBSD_ENOMODEL: return "warm start requested but no network parameters loaded";
     case EBSD_EVERSION: return "ebsd_params.struct_size mismatch";
+    case EBSD_EIO: return "parameter file could not be read or written";
     default: return "unknown error";
     }
 }
@@ -721,6 +770,7 @@ int ebsd_destroy(ebsd_handle* h)
         for (auto& e : h->ev)
             if (e) (void)hipEventDestroy(e);
     }
+    if (h->cnn) (void)ebsd_cnn_destroy(h->cnn);
     delete h;
     return EBSD_OK;
 }
@@ -771,6 +821,29 @@ int ebsd_roi_layout(const ebsd_params* p, int32_t H, int32_t W, double* cx, doub
     if (e) return e;
     if (H <= 0 || W <= 0) return EBSD_ESHAPE;
     return roi_layout(*p, H, W, cx, cy, x0, y0);
+}
+
+int ebsd_load_model(ebsd_handle* h, const char* path)
+{
+    if (!h || !path) return EBSD_EINVAL;
+    if (!h->cnn) {
+        const int e = ebsd_cnn_create(h->device, kWarmBatch, &h->cnn);
+        if (e) return e;
+    }
+    return ebsd_cnn_load(h->cnn, path);
+}
+
+int ebsd_set_model(ebsd_handle* h, const ebsd_cnn* c)
+{
+    if (!h || !c) return EBSD_EINVAL;
+    if (!h->cnn) {
+        const int e = ebsd_cnn_create(h->device, kWarmBatch, &h->cnn);
+        if (e) return e;
+    }
+    std::vector<float> buf((size_t)EBSD_CNN_PARAMS);
+    int e = ebsd_cnn_get_params(c, buf.data(), EBSD_CNN_PARAMS);
+    if (e) return e;
+    return ebsd_cnn_set_params(h->cnn, buf.data(), EBSD_CNN_PARAMS);
 }
 
 int ebsd_register_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,

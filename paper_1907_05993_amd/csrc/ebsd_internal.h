@@ -49,6 +49,8 @@ struct OutPtrs {
     float* ph;
     int32_t* iters;
     uint32_t* status;
+    float* warm_field;   // [n][h][w][2] network field (warm start)
+    float* warm_misfit;  // [n]
 };
 // Everything a bucket's kernels need, in device memory (one copy per bucket).
 struct Bucket {
@@ -89,6 +91,11 @@ struct Bucket {
     const float* u_init;        // [nb][2][h][w] coarsest initial field or NULL
     float* const* field_dst;    // [nb] destination of each final field or NULL
     const double* rfin_in;      // [caller n][9] R_finite for the second-pass-only entry
+    // warm start (NULL when off): network field [nb][h][w][2], fit misfit [nb],
+    // status bit (EBSD_WARM_USED / EBSD_WARM_FALLBACK) [nb]
+    const float* warm_field;
+    const float* warm_misfit;
+    const uint32_t* warm_flag;
 };
 
 // ---- launchers (defined next to their kernels) -------------------------------
@@ -123,6 +130,8 @@ hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, hi
 // Rfin[b] = bk->rfin_in[pair_index[b]] (second-pass-only entry).
 hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
+// Copy the warm-start field and misfit of every pair to the caller's outputs.
+hipError_t launch_scatter_warm(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Second-pass solve: F_inf from q2, F = F_inf Rfin, det 1, R, rotvec.
 hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass,
                                hipStream_t s);

@@ -1,0 +1,656 @@
+// Kernels of the warm-start network: 3x3 convolutions and their weight
+// gradients on the gfx950 matrix cores (bf16 operands, fp32 accumulation,
+// v_mfma_f32_32x32x16_bf16), and the element-wise passes between them.
+//
+// Matrix-core operand layout of the 32x32x16 bf16 instruction (wave64): lane l
+// supplies row l % 32 of A with the 8 consecutive k values 8 (l / 32) .. +7,
+// and column l % 32 of B with the same 8 k values; it receives the 16
+// accumulator values C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32], i = 0..15.
+#include "cnn_internal.h"
+
+#include "../../include/ebsd.h"
+
+namespace ebsd {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(uint16_t)))) uint16_t u16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+__device__ inline bf16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (bf16_t)(u >> 16);
+}
+
+__device__ inline float bf2f(bf16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ inline f32x16 mfma16(const bf16x8& a, const bf16x8& b, const f32x16& c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---- 3x3 convolution (forward and input gradient) ------------------------------
+//
+// Workgroup: 4 waves, output tile of 8 rows x 32 columns x (32 NT) channels;
+// wave w computes rows 2w, 2w+1 (one 32-pixel M tile each) for all NT N tiles.
+// For each chunk of CK input channels the (8+2) x (32+2) input halo and the
+// 9 taps of weights are staged in LDS; the K loop walks (tap, 8-channel group)
+// pairs, two per 16-wide MFMA step (one per half wave).  Pixel rows in LDS are
+// padded to 80 bytes for CK = 32 so that 8 consecutive lanes of a 16-byte read
+// cover all banks.
+constexpr int kConvTH = 8, kConvTW = 32;
+
+template <int CK, int NT>
+__global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
+{
+    constexpr int HP = kConvTH + 2, WP = kConvTW + 2;
+    constexpr int PS = (CK == 32) ? 40 : CK;
+    constexpr int BN = 32 * NT;
+    constexpr int G = CK / 8;
+    constexpr int NF = 9 * G;
+    constexpr int NS = (NF + 1) / 2;
+    __shared__ __attribute__((aligned(16))) bf16_t sA[HP * WP * PS];
+    __shared__ __attribute__((aligned(16))) bf16_t sB[9 * BN * PS];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    int b = blockIdx.x;
+    const int nbk = a.Cout / BN, txn = a.W / kConvTW, tyn = a.H / kConvTH;
+    const int nb = b % nbk;
+    b /= nbk;
+    const int tx = b % txn;
+    b /= txn;
+    const int ty = b % tyn;
+    const int img = b / tyn;
+    const int x0 = tx * kConvTW, y0 = ty * kConvTH, co0 = nb * BN;
+    const int Cin = a.Cin;
+    const bf16_t* __restrict__ xin = a.x + (int64_t)img * a.H * a.W * Cin;
+
+    f32x16 acc[2][NT];
+    for (int r = 0; r < 2; r++)
+        for (int j = 0; j < NT; j++)
+            for (int i = 0; i < 16; i++) acc[r][j][i] = 0.0f;
+
+    for (int c0 = 0; c0 < Cin; c0 += CK) {
+        for (int i = tid; i < HP * WP * G; i += 256) {
+            const int g = i % G, p = i / G;
+            const int hx = p % WP, hy = p / WP;
+            const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                v = *reinterpret_cast<const uint4*>(xin + ((int64_t)yy * a.W + xx) * Cin + c0 + 8 * g);
+            *reinterpret_cast<uint4*>(sA + p * PS + 8 * g) = v;
+        }
+        for (int i = tid; i < 9 * BN * G; i += 256) {
+            const int g = i % G, r = i / G;
+            const int co = r % BN, t = r / BN;
+            const uint4 v = *reinterpret_cast<const uint4*>(a.w + ((int64_t)(co0 + co) * 9 + t) * Cin + c0 + 8 * g);
+            *reinterpret_cast<uint4*>(sB + (t * BN + co) * PS + 8 * g) = v;
+        }
+        __syncthreads();
+        for (int s = 0; s < NS; s++) {
+            const int f = 2 * s + h;
+            const bool valid = f < NF;  // false only for the padding group of an odd group count
+            const int fc = valid ? f : 0;
+            const int t = fc / G, g = fc - G * (fc / G);
+            const int ky = t / 3, kx = t - 3 * (t / 3);
+            bf16x8 av[2], bv[NT];
+            for (int r = 0; r < 2; r++) {
+                const int row = 2 * wave + r;
+                av[r] = *reinterpret_cast<const bf16x8*>(sA + ((row + ky) * WP + l32 + kx) * PS + 8 * g);
+            }
+            for (int j = 0; j < NT; j++) {
+                u16x8 raw = *reinterpret_cast<const u16x8*>(sB + (t * BN + 32 * j + l32) * PS + 8 * g);
+                if (!valid) raw = (u16x8){0, 0, 0, 0, 0, 0, 0, 0};
+                bv[j] = __builtin_bit_cast(bf16x8, raw);
+            }
+            for (int r = 0; r < 2; r++)
+                for (int j = 0; j < NT; j++) acc[r][j] = mfma16(av[r], bv[j], acc[r][j]);
+        }
+        __syncthreads();
+    }
+
+    for (int r = 0; r < 2; r++) {
+        const int yy = y0 + 2 * wave + r;
+        for (int j = 0; j < NT; j++) {
+            const int co = co0 + 32 * j + l32;
+            const float bias = a.mode == 0 ? a.bias[co] : 0.0f;
+            for (int i = 0; i < 16; i++) {
+                const int xx = x0 + 8 * (i >> 2) + 4 * h + (i & 3);
+                const int64_t p = ((int64_t)img * a.H + yy) * a.W + xx;
+                if (a.mode == 0) {
+                    const float z = fmaxf(acc[r][j][i] + bias, 0.0f);
+                    static_cast<bf16_t*>(a.out)[p * a.out_cs + a.out_co + co] = f2bf(z);
+                } else {
+                    static_cast<float*>(a.out)[p * a.out_cs + a.out_co + co] = acc[r][j][i];
+                }
+            }
+        }
+    }
+}
+
+// ---- 3x3 weight gradient -------------------------------------------------------
+//
+// Workgroup: 3 waves; wave w owns the three taps of kernel row ky = w for a
+// block of 32 input channels x (32 NT) output channels.  GEMM view per tap:
+// M = input channel, N = output channel, K = pixel.  A k-step takes 16 pixels
+// of one output row (8 per half wave); the three taps of a wave read the input
+// at 10 consecutive halo columns, shared between them.  The workgroup walks a
+// contiguous range of 4 x 32 pixel tiles and writes its fp32 partial sums.
+constexpr int kWgTH = 4, kWgTW = 32, kWgCB = 32, kWgThreads = 192;
+
+template <int NT>
+__global__ void __launch_bounds__(kWgThreads) k_wgrad3x3(WgradArgs a)
+{
+    constexpr int HP = kWgTH + 2, WP = kWgTW + 2;
+    constexpr int BN = 32 * NT;
+    __shared__ __attribute__((aligned(16))) bf16_t sX[HP * WP * kWgCB];
+    __shared__ __attribute__((aligned(16))) bf16_t sD[kWgTH * kWgTW * BN];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    int b = blockIdx.x;
+    const int ncb = (a.Cin + kWgCB - 1) / kWgCB, nob = a.Cout / BN;
+    const int ob = b % nob;
+    b /= nob;
+    const int cb = b % ncb;
+    const int split = b / ncb;
+    const int ci0 = cb * kWgCB, co0 = ob * BN;
+    const int txn = a.W / kWgTW, tyn = a.H / kWgTH, tpi = txn * tyn;
+    const int total = a.n * tpi;
+    const int t_begin = split * a.tiles_per_split;
+    const int t_end = min(total, t_begin + a.tiles_per_split);
+    const int cvec = min(kWgCB, a.Cin - ci0) / 8;
+
+    f32x16 acc[3][NT];
+    for (int k = 0; k < 3; k++)
+        for (int j = 0; j < NT; j++)
+            for (int i = 0; i < 16; i++) acc[k][j][i] = 0.0f;
+
+    for (int tile = t_begin; tile < t_end; tile++) {
+        const int img = tile / tpi, rem = tile - tpi * img;
+        const int y0 = (rem / txn) * kWgTH, x0 = (rem - txn * (rem / txn)) * kWgTW;
+        const bf16_t* __restrict__ xin = a.x + (int64_t)img * a.H * a.W * a.Cin;
+        const bf16_t* __restrict__ din = a.dz + (int64_t)img * a.H * a.W * a.Cout;
+        for (int i = tid; i < HP * WP * 4; i += kWgThreads) {
+            const int g = i & 3, p = i >> 2;
+            const int hx = p % WP, hy = p / WP;
+            const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (g < cvec && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                v = *reinterpret_cast<const uint4*>(xin + ((int64_t)yy * a.W + xx) * a.Cin + ci0 + 8 * g);
+            *reinterpret_cast<uint4*>(sX + p * kWgCB + 8 * g) = v;
+        }
+        for (int i = tid; i < kWgTH * kWgTW * (BN / 8); i += kWgThreads) {
+            const int g = i % (BN / 8), p = i / (BN / 8);
+            const int yy = y0 + p / kWgTW, xx = x0 + p % kWgTW;
+            *reinterpret_cast<uint4*>(sD + p * BN + 8 * g) =
+                *reinterpret_cast<const uint4*>(din + ((int64_t)yy * a.W + xx) * a.Cout + co0 + 8 * g);
+        }
+        __syncthreads();
+        for (int row = 0; row < kWgTH; row++) {
+            for (int xb = 0; xb < kWgTW; xb += 16) {
+                const int px = xb + 8 * h;  // first pixel (tile column) of this half wave
+                uint16_t xv[10];
+                for (int m = 0; m < 10; m++) xv[m] = sX[((row + wave) * WP + px + m) * kWgCB + l32];
+                bf16x8 av[3];
+                for (int kx = 0; kx < 3; kx++) {
+                    u16x8 t;
+                    for (int j = 0; j < 8; j++) t[j] = xv[kx + j];
+                    av[kx] = __builtin_bit_cast(bf16x8, t);
+                }
+                for (int jn = 0; jn < NT; jn++) {
+                    u16x8 t;
+                    for (int j = 0; j < 8; j++) t[j] = sD[(row * kWgTW + px + j) * BN + 32 * jn + l32];
+                    const bf16x8 bv = __builtin_bit_cast(bf16x8, t);
+                    for (int kx = 0; kx < 3; kx++) acc[kx][jn] = mfma16(av[kx], bv, acc[kx][jn]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    const int keep = a.cin_keep;
+    for (int kx = 0; kx < 3; kx++) {
+        const int t = 3 * wave + kx;
+        for (int jn = 0; jn < NT; jn++) {
+            const int co = co0 + 32 * jn + l32;
+            for (int i = 0; i < 16; i++) {
+                const int ci = ci0 + 8 * (i >> 2) + 4 * h + (i & 3);
+                if (ci < keep)
+                    a.part[(((int64_t)split * 9 + t) * keep + ci) * a.Cout + co] = acc[kx][jn][i];
+            }
+        }
+    }
+}
+
+// ---- element-wise passes ---------------------------------------------------------
+
+__global__ void k_colsum(const float* __restrict__ part, int64_t nb, int64_t ncols, float* __restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    float s = 0.0f;
+    for (int64_t b = 0; b < nb; b++) s += part[b * ncols + c];
+    out[c] = s;
+}
+
+__global__ void k_pack_input(const float* __restrict__ rb, int64_t rs, const int32_t* __restrict__ slot,
+                             const float* __restrict__ tb, int64_t ts, int n, int64_t hw,
+                             bf16_t* __restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * hw) return;
+    const int64_t pair = i / hw, p = i - pair * hw;
+    const int64_t rsl = slot ? slot[pair] : pair;
+    const float r = rb[rsl * rs + p], t = tb[pair * ts + p];
+    uint4 v;
+    v.x = (uint32_t)f2bf(r) | ((uint32_t)f2bf(t) << 16);
+    v.y = 0u;
+    v.z = 0u;
+    v.w = 0u;
+    *reinterpret_cast<uint4*>(x + 8 * i) = v;
+}
+
+// One thread per (pooled pixel, 8-channel group).
+__global__ void k_maxpool(const bf16_t* __restrict__ in, int n, int H, int W, int C, int cs, int co,
+                          bf16_t* __restrict__ out)
+{
+    const int cg = C / 8;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int h2 = H / 2, w2 = W / 2;
+    if (i >= (int64_t)n * h2 * w2 * cg) return;
+    const int g = (int)(i % cg);
+    const int64_t q = i / cg;
+    const int x = (int)(q % w2);
+    const int64_t r = q / w2;
+    const int y = (int)(r % h2);
+    const int64_t img = r / h2;
+    const bf16_t* base = in + ((img * H + 2 * y) * W + 2 * x) * cs + co + 8 * g;
+    const u16x8 v0 = *reinterpret_cast<const u16x8*>(base);
+    const u16x8 v1 = *reinterpret_cast<const u16x8*>(base + cs);
+    const u16x8 v2 = *reinterpret_cast<const u16x8*>(base + (int64_t)W * cs);
+    const u16x8 v3 = *reinterpret_cast<const u16x8*>(base + (int64_t)W * cs + cs);
+    u16x8 o;
+    for (int j = 0; j < 8; j++) {
+        uint16_t m = v0[j];
+        if (bf2f(v1[j]) > bf2f(m)) m = v1[j];
+        if (bf2f(v2[j]) > bf2f(m)) m = v2[j];
+        if (bf2f(v3[j]) > bf2f(m)) m = v3[j];
+        o[j] = m;
+    }
+    *reinterpret_cast<u16x8*>(out + q * C + 8 * g) = o;
+}
+
+// One thread per (pooled pixel, channel): route g to the first maximum.
+__global__ void k_maxpool_back(const float* __restrict__ g, const bf16_t* __restrict__ act, int n, int H,
+                               int W, int C, int cs, int co, const float* __restrict__ add, int add_cs,
+                               int add_co, float* __restrict__ gin)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int h2 = H / 2, w2 = W / 2;
+    if (i >= (int64_t)n * h2 * w2 * C) return;
+    const int c = (int)(i % C);
+    const int64_t q = i / C;
+    const int x = (int)(q % w2);
+    const int64_t r = q / w2;
+    const int y = (int)(r % h2);
+    const int64_t img = r / h2;
+    int64_t pix[4];
+    pix[0] = (img * H + 2 * y) * W + 2 * x;
+    pix[1] = pix[0] + 1;
+    pix[2] = pix[0] + W;
+    pix[3] = pix[2] + 1;
+    int k = 0;
+    float m = bf2f(act[pix[0] * cs + co + c]);
+    for (int j = 1; j < 4; j++) {
+        const float v = bf2f(act[pix[j] * cs + co + c]);
+        if (v > m) {
+            m = v;
+            k = j;
+        }
+    }
+    const float gv = g[i];
+    for (int j = 0; j < 4; j++) {
+        float v = j == k ? gv : 0.0f;
+        if (add) v += add[pix[j] * add_cs + add_co + c];
+        gin[pix[j] * C + c] = v;
+    }
+}
+
+__global__ void k_upsample_into(const bf16_t* __restrict__ in, int n, int h, int w, int C,
+                                bf16_t* __restrict__ out, int cs)
+{
+    const int cg = C / 8;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * h * w * cg) return;
+    const int g = (int)(i % cg);
+    const int64_t q = i / cg;
+    const int x = (int)(q % w);
+    const int64_t r = q / w;
+    const int y = (int)(r % h);
+    const int64_t img = r / h;
+    const uint4 v = *reinterpret_cast<const uint4*>(in + q * C + 8 * g);
+    const int W2 = 2 * w;
+    const int64_t o = ((img * 2 * h + 2 * y) * W2 + 2 * x) * cs + 8 * g;
+    *reinterpret_cast<uint4*>(out + o) = v;
+    *reinterpret_cast<uint4*>(out + o + cs) = v;
+    *reinterpret_cast<uint4*>(out + o + (int64_t)W2 * cs) = v;
+    *reinterpret_cast<uint4*>(out + o + (int64_t)W2 * cs + cs) = v;
+}
+
+__global__ void k_upsample_back(const float* __restrict__ gout, int n, int h, int w, int C, int cs,
+                                float* __restrict__ g)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * h * w * C) return;
+    const int c = (int)(i % C);
+    const int64_t q = i / C;
+    const int x = (int)(q % w);
+    const int64_t r = q / w;
+    const int y = (int)(r % h);
+    const int64_t img = r / h;
+    const int W2 = 2 * w;
+    const int64_t o = ((img * 2 * h + 2 * y) * W2 + 2 * x) * cs + c;
+    g[i] = ((gout[o] + gout[o + cs]) + gout[o + (int64_t)W2 * cs]) + gout[o + (int64_t)W2 * cs + cs];
+}
+
+constexpr int kMaskPB = 256;  // pixels per mask block
+
+// Block b covers pixels [b kMaskPB, (b+1) kMaskPB).  Thread (sub, c): channel
+// c, pixels p0 + sub, p0 + sub + nsub, ...; the nsub partial bias sums are
+// combined in increasing sub.
+__global__ void __launch_bounds__(256) k_mask_round(const float* __restrict__ g, const bf16_t* __restrict__ act,
+                                                    int64_t P, int C, int act_cs, int act_co,
+                                                    bf16_t* __restrict__ dz, float* __restrict__ part)
+{
+    __shared__ float sh[256];
+    const int tid = threadIdx.x;
+    const int nsub = C >= 256 ? 1 : 256 / C;
+    const int64_t p0 = (int64_t)blockIdx.x * kMaskPB;
+    const int64_t p1 = min(P, p0 + kMaskPB);
+    for (int cbase = 0; cbase < C; cbase += 256 / nsub) {
+        const int sub = tid / (256 / nsub), cl = tid % (256 / nsub);
+        const int c = cbase + cl;
+        float s = 0.0f;
+        if (c < C) {
+            for (int64_t p = p0 + sub; p < p1; p += nsub) {
+                const float a = bf2f(act[p * act_cs + act_co + c]);
+                const float v = a > 0.0f ? g[p * C + c] : 0.0f;
+                dz[p * C + c] = f2bf(v);
+                s += v;
+            }
+        }
+        sh[tid] = s;
+        __syncthreads();
+        if (sub == 0 && c < C) {
+            float t = sh[cl];
+            for (int k = 1; k < nsub; k++) t += sh[k * (256 / nsub) + cl];
+            part[(int64_t)blockIdx.x * C + c] = t;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_head_fwd(const bf16_t* __restrict__ act, int64_t P, int C, const float* __restrict__ hw,
+                           const float* __restrict__ hb, float* __restrict__ out)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float s0 = 0.0f, s1 = 0.0f;
+    for (int c = 0; c < C; c++) {
+        const float a = bf2f(act[p * C + c]);
+        s0 += a * hw[2 * c];
+        s1 += a * hw[2 * c + 1];
+    }
+    out[2 * p] = s0 + hb[0];
+    out[2 * p + 1] = s1 + hb[1];
+}
+
+constexpr int kLossPB = 256;
+
+__global__ void __launch_bounds__(kLossPB) k_loss(const float* __restrict__ out, const float* __restrict__ label,
+                                                  int64_t P, float* __restrict__ gout, float* __restrict__ part)
+{
+    __shared__ float sh[kLossPB];
+    const int64_t p = (int64_t)blockIdx.x * kLossPB + threadIdx.x;
+    float e = 0.0f;
+    if (p < P) {
+        const float dx = out[2 * p] - label[2 * p], dy = out[2 * p + 1] - label[2 * p + 1];
+        const float sc = 2.0f / (float)P;
+        gout[2 * p] = sc * dx;
+        gout[2 * p + 1] = sc * dy;
+        e = dx * dx + dy * dy;
+    }
+    sh[threadIdx.x] = e;
+    __syncthreads();
+    for (int s = kLossPB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+constexpr int kHeadPB = 256;
+
+// Columns of the partial sums: dhw[c][o] at 2c + o, dhb[o] at 2C + o.
+__global__ void __launch_bounds__(256) k_head_back(const bf16_t* __restrict__ act, const float* __restrict__ gout,
+                                                   int64_t P, int C, const float* __restrict__ hw,
+                                                   float* __restrict__ gact, float* __restrict__ part)
+{
+    const int tid = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * kHeadPB;
+    const int64_t p1 = min(P, p0 + kHeadPB);
+    const int ncol = 2 * C + 2;
+    for (int col = tid; col < ncol; col += 256) {
+        float s = 0.0f;
+        if (col < 2 * C) {
+            const int c = col >> 1, o = col & 1;
+            for (int64_t p = p0; p < p1; p++) s += bf2f(act[p * C + c]) * gout[2 * p + o];
+        } else {
+            const int o = col - 2 * C;
+            for (int64_t p = p0; p < p1; p++) s += gout[2 * p + o];
+        }
+        part[(int64_t)blockIdx.x * ncol + col] = s;
+    }
+    for (int64_t i = tid; i < (p1 - p0) * C; i += 256) {
+        const int64_t p = p0 + i / C;
+        const int c = (int)(i % C);
+        gact[p * C + c] = gout[2 * p] * hw[2 * c] + gout[2 * p + 1] * hw[2 * c + 1];
+    }
+}
+
+__global__ void k_pack_weights(const float* __restrict__ w, int cin, int cin_pad, int cout,
+                               bf16_t* __restrict__ fwd, bf16_t* __restrict__ dgr)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nf = (int64_t)cout * 9 * cin_pad;
+    if (i < nf) {
+        const int ci = (int)(i % cin_pad);
+        const int64_t r = i / cin_pad;
+        const int t = (int)(r % 9);
+        const int co = (int)(r / 9);
+        fwd[i] = ci < cin ? f2bf(w[((int64_t)t * cin + ci) * cout + co]) : (bf16_t)0;
+    }
+    const int64_t nd = (int64_t)cin * 9 * cout;
+    if (dgr && i < nd) {
+        const int co = (int)(i % cout);
+        const int64_t r = i / cout;
+        const int t = (int)(r % 9);
+        const int ci = (int)(r / 9);
+        dgr[i] = f2bf(w[((int64_t)(8 - t) * cin + ci) * cout + co]);
+    }
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / bc1, vh = vi / bc2;
+    p[i] = p[i] - lr * mh / (sqrtf(vh) + eps);
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+bool conv3x3_supported(int H, int W, int Cin, int Cout)
+{
+    return H > 0 && W > 0 && H % kConvTH == 0 && W % kConvTW == 0 && (Cin % 32 == 0 || Cin == 8) &&
+           Cout > 0 && Cout % 32 == 0;
+}
+
+hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t s)
+{
+    if (!conv3x3_supported(a.H, a.W, a.Cin, a.Cout) || a.n <= 0) return hipErrorInvalidValue;
+    const int nt = a.Cout % 64 == 0 ? 2 : 1;
+    const int64_t tiles = (int64_t)a.n * (a.H / kConvTH) * (a.W / kConvTW) * (a.Cout / (32 * nt));
+    const dim3 grid((unsigned)tiles), block(256);
+    if (a.Cin == 8) {
+        if (nt == 2) hipLaunchKernelGGL((k_conv3x3<8, 2>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3<8, 1>), grid, block, 0, s, a);
+    } else {
+        if (nt == 2) hipLaunchKernelGGL((k_conv3x3<32, 2>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3<32, 1>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+int wgrad_splits(int n, int H, int W, int Cin, int Cout, int* tiles_per_split)
+{
+    const int nt = Cout % 64 == 0 ? 2 : 1;
+    const int ncb = (Cin + kWgCB - 1) / kWgCB, nob = Cout / (32 * nt);
+    const int64_t total = (int64_t)n * (H / kWgTH) * (W / kWgTW);
+    int64_t splits = 1536 / (ncb * nob);
+    if (splits < 1) splits = 1;
+    if (splits > total) splits = total;
+    const int64_t tps = (total + splits - 1) / splits;
+    *tiles_per_split = (int)tps;
+    return (int)((total + tps - 1) / tps);
+}
+
+hipError_t launch_wgrad3x3(const WgradArgs& a, hipStream_t s)
+{
+    if (a.n <= 0 || a.H % kWgTH || a.W % kWgTW || a.Cout % 32 || !(a.Cin % 32 == 0 || a.Cin == 8))
+        return hipErrorInvalidValue;
+    const int nt = a.Cout % 64 == 0 ? 2 : 1;
+    const int ncb = (a.Cin + kWgCB - 1) / kWgCB, nob = a.Cout / (32 * nt);
+    const dim3 grid((unsigned)((int64_t)a.splits * ncb * nob)), block(kWgThreads);
+    if (nt == 2) hipLaunchKernelGGL(k_wgrad3x3<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_wgrad3x3<1>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* part, int64_t nb, int64_t ncols, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_colsum, dim3(blocks_for(ncols, 256)), dim3(256), 0, s, part, nb, ncols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_input(const float* ref_base, int64_t ref_stride, const int32_t* ref_slot,
+                             const float* test_base, int64_t test_stride, int n, int H, int W,
+                             bf16_t* x, hipStream_t s)
+{
+    const int64_t hw = (int64_t)H * W;
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks_for((int64_t)n * hw, 256)), dim3(256), 0, s, ref_base,
+                       ref_stride, ref_slot, test_base, test_stride, n, hw, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpool(const bf16_t* in, int n, int H, int W, int C, int cs, int co, bf16_t* out,
+                          hipStream_t s)
+{
+    const int64_t items = (int64_t)n * (H / 2) * (W / 2) * (C / 8);
+    hipLaunchKernelGGL(k_maxpool, dim3(blocks_for(items, 256)), dim3(256), 0, s, in, n, H, W, C, cs, co, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpool_back(const float* g, const bf16_t* act, int n, int H, int W, int C, int cs,
+                               int co, const float* add, int add_cs, int add_co, float* g_in,
+                               hipStream_t s)
+{
+    const int64_t items = (int64_t)n * (H / 2) * (W / 2) * C;
+    hipLaunchKernelGGL(k_maxpool_back, dim3(blocks_for(items, 256)), dim3(256), 0, s, g, act, n, H, W, C, cs,
+                       co, add, add_cs, add_co, g_in);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample_into(const bf16_t* in, int n, int h, int w, int C, bf16_t* out, int cs,
+                                hipStream_t s)
+{
+    const int64_t items = (int64_t)n * h * w * (C / 8);
+    hipLaunchKernelGGL(k_upsample_into, dim3(blocks_for(items, 256)), dim3(256), 0, s, in, n, h, w, C, out, cs);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample_back(const float* gout, int n, int h, int w, int C, int cs, float* g,
+                                hipStream_t s)
+{
+    const int64_t items = (int64_t)n * h * w * C;
+    hipLaunchKernelGGL(k_upsample_back, dim3(blocks_for(items, 256)), dim3(256), 0, s, gout, n, h, w, C, cs, g);
+    return hipGetLastError();
+}
+
+int mask_blocks(int64_t P) { return (int)((P + kMaskPB - 1) / kMaskPB); }
+
+hipError_t launch_mask_round(const float* g, const bf16_t* act, int64_t P, int C, int act_cs,
+                             int act_co, bf16_t* dz, float* bias_part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mask_round, dim3(mask_blocks(P)), dim3(256), 0, s, g, act, P, C, act_cs, act_co, dz,
+                       bias_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_head_fwd(const bf16_t* act, int64_t P, int C, const float* hw, const float* hb,
+                           float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_head_fwd, dim3(blocks_for(P, 256)), dim3(256), 0, s, act, P, C, hw, hb, out);
+    return hipGetLastError();
+}
+
+int loss_blocks(int64_t P) { return (int)((P + kLossPB - 1) / kLossPB); }
+
+hipError_t launch_loss(const float* out, const float* label, int64_t P, float* gout, float* loss_part,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loss, dim3(loss_blocks(P)), dim3(kLossPB), 0, s, out, label, P, gout, loss_part);
+    return hipGetLastError();
+}
+
+int head_blocks(int64_t P) { return (int)((P + kHeadPB - 1) / kHeadPB); }
+
+hipError_t launch_head_back(const bf16_t* act, const float* gout, int64_t P, int C, const float* hw,
+                            float* gact, float* part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_head_back, dim3(head_blocks(P)), dim3(256), 0, s, act, gout, P, C, hw, gact, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const float* w, int cin, int cin_pad, int cout, bf16_t* fwd,
+                               bf16_t* dgr, hipStream_t s)
+{
+    const int64_t nf = (int64_t)cout * 9 * cin_pad, nd = (int64_t)cin * 9 * cout;
+    const int64_t n = nf > nd ? nf : nd;
+    hipLaunchKernelGGL(k_pack_weights, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, cin, cin_pad, cout, fwd, dgr);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, bc1,
+                       bc2);
+    return hipGetLastError();
+}
+
+}  // namespace ebsd

@@ -8,6 +8,7 @@
 //   small angles keep their digits.
 // One thread per pair: this is a few microseconds of FP64 work per batch.
 #include "ebsd_internal.h"
+#include "cnn_internal.h"
 
 #include "../../include/ebsd.h"
 
@@ -267,6 +268,7 @@ __global__ void k_solve_first(const Bucket* __restrict__ bk, float tol)
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= bk->nb) return;
     uint32_t st = bk->test_stat[b].flags | bk->ref_stat[bk->ref_slot[b]].flags;
+    if (bk->warm_flag) st |= bk->warm_flag[b];
     if (tol > 0.0f) {
         const uint32_t all = (bk->L >= 32) ? 0xffffffffu : ((1u << bk->L) - 1u);
         if ((bk->state[b].convmask & all) == all) st |= EBSD_CONVERGED;
@@ -370,6 +372,200 @@ __global__ void k_scatter(const Bucket* __restrict__ bk)
     if (o.iters)
         for (int l = 0; l < bk->L; l++) o.iters[bk->L * g + l] = bk->iters[bk->L * (int64_t)b + l];
     if (o.status) o.status[g] = bk->status[b];
+    if (o.warm_misfit && bk->warm_misfit) o.warm_misfit[g] = bk->warm_misfit[b];
+}
+
+// blockIdx.y = pair; the field of one pair is h * w * 2 floats.
+__global__ void k_scatter_warm(const Bucket* __restrict__ bk)
+{
+    const int b = blockIdx.y;
+    const int64_t n = (int64_t)(bk->H >> 2) * (bk->W >> 2) * 2;
+    const int64_t g = bk->pair_index[b];
+    float* dst = bk->out.warm_field + g * n;
+    const float* src = bk->warm_field + (int64_t)b * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+
+// ---- warm-start fallback fit ------------------------------------------------------
+// One workgroup per pair.  The Eq. (3) model is fitted to the predicted field at
+// the coarse grid points (full-resolution coordinates 4 i + 1.5) that lie within
+// `radius` of the pattern centre; each thread sums over a strided subset of the
+// points and the sums are combined in a fixed order, so the result does not
+// depend on scheduling.  All threads then run the same small dense algebra.
+constexpr int kFitThreads = 256;
+
+__device__ inline double wave_sum_d(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int NV>
+__device__ void fit_block_sum(double (&v)[NV], double* sh)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < NV; k++) {
+        const double w = wave_sum_d(v[k]);
+        if (lane == 0) sh[wave * NV + k] = w;
+    }
+    __syncthreads();
+    for (int k = 0; k < NV; k++) v[k] = ((sh[k] + sh[NV + k]) + sh[2 * NV + k]) + sh[3 * NV + k];
+    __syncthreads();
+}
+
+struct GridFit {
+    const float* q;  // [gh][gw][2]
+    int gh, gw;
+    double xs, ys, zs, iz, r2;
+    __device__ bool point(int g, double& x, double& y) const
+    {
+        x = 4.0 * (double)(g % gw) + 1.5;
+        y = 4.0 * (double)(g / gw) + 1.5;
+        const double dx = x - xs, dy = y - ys;
+        return dx * dx + dy * dy <= r2;
+    }
+};
+
+__global__ void __launch_bounds__(kFitThreads)
+k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys, double zs,
+           double radius, double threshold, float* __restrict__ u_init, float* __restrict__ misfit,
+           uint32_t* __restrict__ flag)
+{
+    __shared__ double sh[4 * 45];
+    const int b = blockIdx.x;
+    GridFit gf;
+    gf.q = field + (int64_t)b * gh * gw * 2;
+    gf.gh = gh;
+    gf.gw = gw;
+    gf.xs = xs;
+    gf.ys = ys;
+    gf.zs = zs;
+    gf.iz = 1.0 / zs;
+    gf.r2 = radius * radius;
+    const int ng = gh * gw;
+
+    // direct linear start
+    double m[46];
+    for (int k = 0; k < 46; k++) m[k] = 0.0;
+    for (int g = threadIdx.x; g < ng; g += kFitThreads) {
+        double x, y;
+        if (!gf.point(g, x, y)) continue;
+        const double ax = x - xs, ay = y - ys;
+        const double rx = ax * gf.iz, ry = ay * gf.iz;
+        const double px = (ax + (double)gf.q[2 * g]) * gf.iz, py = (ay + (double)gf.q[2 * g + 1]) * gf.iz;
+        const double ra[9] = {rx, ry, 1.0, 0.0, 0.0, 0.0, -px * rx, -px * ry, -px};
+        const double rb[9] = {0.0, 0.0, 0.0, rx, ry, 1.0, -py * rx, -py * ry, -py};
+        int k = 0;
+        for (int a = 0; a < 9; a++)
+            for (int c = a; c < 9; c++) m[k++] += ra[a] * ra[c] + rb[a] * rb[c];
+        m[45] += 1.0;
+    }
+    {
+        double part[45];
+        for (int k = 0; k < 45; k++) part[k] = m[k];
+        fit_block_sum<45>(part, sh);
+        for (int k = 0; k < 45; k++) m[k] = part[k];
+        double cnt[1] = {m[45]};
+        fit_block_sum<1>(cnt, sh);
+        m[45] = cnt[0];
+    }
+    const double npts = m[45];
+    double M[9][9];
+    {
+        int k = 0;
+        for (int a = 0; a < 9; a++)
+            for (int c = a; c < 9; c++) {
+                M[a][c] = m[k];
+                M[c][a] = m[k];
+                k++;
+            }
+    }
+    double ev[9], V[9][9];
+    jacobi_eigen<9>(M, ev, V);
+    int kmin = 0;
+    for (int i = 1; i < 9; i++)
+        if (ev[i] < ev[kmin]) kmin = i;
+    double f[9];
+    for (int i = 0; i < 9; i++) f[i] = V[i][kmin];
+    if (f[8] == 0.0) f[8] = 1.0;
+    const double s8 = f[8];
+    for (int i = 0; i < 9; i++) f[i] /= s8;
+    f[8] = 1.0;
+
+    // Gauss-Newton on the 8 free entries
+    for (int it = 0; it < 100; it++) {
+        double t[44];
+        for (int k = 0; k < 44; k++) t[k] = 0.0;
+        for (int g = threadIdx.x; g < ng; g += kFitThreads) {
+            double x, y;
+            if (!gf.point(g, x, y)) continue;
+            const double ax = x - xs, ay = y - ys;
+            const double r0 = ax * gf.iz, r1 = ay * gf.iz;
+            const double pxi = (ax + (double)gf.q[2 * g]) * gf.iz, pyi = (ay + (double)gf.q[2 * g + 1]) * gf.iz;
+            const double n1 = f[0] * r0 + f[1] * r1 + f[2];
+            const double n2 = f[3] * r0 + f[4] * r1 + f[5];
+            const double d = f[6] * r0 + f[7] * r1 + f[8];
+            const double id = 1.0 / d;
+            const double u = n1 * id, v = n2 * id;
+            const double ex = u - pxi, ey = v - pyi;
+            const double ju[8] = {r0 * id, r1 * id, id, 0.0, 0.0, 0.0, -u * r0 * id, -u * r1 * id};
+            const double jv[8] = {0.0, 0.0, 0.0, r0 * id, r1 * id, id, -v * r0 * id, -v * r1 * id};
+            int k = 0;
+            for (int a = 0; a < 8; a++)
+                for (int c = a; c < 8; c++) t[k++] += ju[a] * ju[c] + jv[a] * jv[c];
+            for (int a = 0; a < 8; a++) t[36 + a] += ju[a] * ex + jv[a] * ey;
+        }
+        fit_block_sum<44>(t, sh);
+        double JtJ[8][8], rhs[8], dlt[8];
+        int k = 0;
+        for (int a = 0; a < 8; a++)
+            for (int c = a; c < 8; c++) {
+                JtJ[a][c] = t[k];
+                JtJ[c][a] = t[k];
+                k++;
+            }
+        for (int a = 0; a < 8; a++) rhs[a] = -t[36 + a];
+        if (!cholesky_solve8(JtJ, rhs, dlt)) break;
+        double nrm = 0.0;
+        for (int a = 0; a < 8; a++) {
+            f[a] += dlt[a];
+            nrm += dlt[a] * dlt[a];
+        }
+        if (!isfinite(nrm) || sqrt(nrm) < 1e-14) break;
+    }
+    const double dt = det3(f);
+    if (dt > 0.0) {
+        const double s = cbrt(dt);
+        for (int i = 0; i < 9; i++) f[i] /= s;
+    }
+
+    // RMS endpoint misfit of the fitted model, full-resolution px
+    double ss[1] = {0.0};
+    for (int g = threadIdx.x; g < ng; g += kFitThreads) {
+        double x, y;
+        if (!gf.point(g, x, y)) continue;
+        const double rx = x - xs, ry = y - ys;
+        const double v0 = f[0] * rx + f[1] * ry + f[2] * zs;
+        const double v1 = f[3] * rx + f[4] * ry + f[5] * zs;
+        const double v2 = f[6] * rx + f[7] * ry + f[8] * zs;
+        const double px = xs + zs * v0 / v2, py = ys + zs * v1 / v2;
+        const double dx = px - x - (double)gf.q[2 * g], dy = py - y - (double)gf.q[2 * g + 1];
+        ss[0] += dx * dx + dy * dy;
+    }
+    fit_block_sum<1>(ss, sh);
+    const double rms = sqrt(ss[0] / npts);
+    const bool use = rms <= threshold;
+    if (threadIdx.x == 0) {
+        misfit[b] = (float)rms;
+        flag[b] = use ? (uint32_t)EBSD_WARM_USED : (uint32_t)EBSD_WARM_FALLBACK;
+    }
+    float* u = u_init + (int64_t)b * 2 * ng;
+    for (int g = threadIdx.x; g < ng; g += kFitThreads) {
+        u[g] = use ? gf.q[2 * g] : 0.0f;
+        u[ng + g] = use ? gf.q[2 * g + 1] : 0.0f;
+    }
 }
 
 }  // namespace
@@ -383,6 +579,13 @@ hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, hipStream_t 
 hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scatter, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_warm(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
+{
+    const int64_t n = (int64_t)(hb.H >> 2) * (hb.W >> 2) * 2;
+    hipLaunchKernelGGL(k_scatter_warm, dim3((unsigned)((n + 255) / 256), hb.nb), dim3(256), 0, s, d_bk);
     return hipGetLastError();
 }
 
@@ -411,6 +614,16 @@ hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx
 {
     hipLaunchKernelGGL(k_stage_solve, dim3((n + 63) / 64), dim3(64), 0, s, q, n, n_roi, cx, cy, xs,
                        ys, zs, F, R, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_fit(const float* field, int n, int H, int W, double xs, double ys, double zs,
+                           double radius, double threshold, float* u_init, float* misfit,
+                           uint32_t* flag, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_warm_fit, dim3(n), dim3(kFitThreads), 0, s, field, H / 4, W / 4, xs, ys, zs,
+                       radius, threshold, u_init, misfit, flag);
     return hipGetLastError();
 }
 

@@ -23,8 +23,10 @@ LIB_PATH = os.path.join(_HERE, "lib", "libebsd.so")
 
 EBSD_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "EROI", -4: "ENOMEM", -5: "EDEVICE", -6: "ENOTSUP",
-          -8: "EVERSION"}
+          -7: "ENOMODEL", -8: "EVERSION", -9: "EIO"}
 CONVERGED, HIT_CAP, SOLVE_ILLCOND, NONFINITE_INPUT, DEGENERATE_INPUT = 1, 2, 16, 32, 64
+WARM_USED, WARM_FALLBACK = 4, 8
+CNN_PARAMS = 1762306
 MAX_LEVELS = 8
 
 
@@ -49,6 +51,8 @@ class CParams(C.Structure):
         ("roi_radius_frac", C.c_double),
         ("window", C.c_int32),
         ("second_pass", C.c_int32),
+        ("warm_start", C.c_int32),
+        ("fallback_residual_px", C.c_float),
     ]
 
 
@@ -71,6 +75,8 @@ class COutputs(C.Structure):
         ("peak_height", C.c_void_p),
         ("iters", C.c_void_p),
         ("status", C.c_void_p),
+        ("warm_field", C.c_void_p),
+        ("warm_misfit", C.c_void_p),
     ]
 
 
@@ -81,7 +87,12 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_register_batch_init", "ebsd_second_pass_batch", "ebsd_stage_normalize",
             "ebsd_stage_restrict", "ebsd_stage_demons_iter", "ebsd_stage_prolong",
             "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_set_timing", "ebsd_get_timing",
-            "ebsd_autotune", "ebsd_get_strip_height", "ebsd_set_strip_height", "ebsd_set_graphs"]
+            "ebsd_autotune", "ebsd_get_strip_height", "ebsd_set_strip_height", "ebsd_set_graphs",
+            "ebsd_cnn_num_params", "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_set_params",
+            "ebsd_cnn_get_params", "ebsd_cnn_get_grads", "ebsd_cnn_load", "ebsd_cnn_save",
+            "ebsd_cnn_forward", "ebsd_cnn_train_step", "ebsd_cnn_reset_optimizer",
+            "ebsd_load_model", "ebsd_set_model", "ebsd_stage_conv3x3", "ebsd_stage_conv3x3_dgrad",
+            "ebsd_stage_conv3x3_wgrad"]
 
 
 def lib():
@@ -117,8 +128,25 @@ def lib():
         L.ebsd_stage_xcf.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
         L.ebsd_stage_solve.argtypes = [vp, i32, i32, vp, vp, C.c_double, C.c_double, C.c_double,
                                        vp, vp, vp, vp]
+        L.ebsd_cnn_num_params.restype = i64
+        L.ebsd_cnn_create.argtypes = [C.c_int, i32, C.POINTER(vp)]
+        L.ebsd_cnn_destroy.argtypes = [vp]
+        L.ebsd_cnn_set_params.argtypes = [vp, vp, i64]
+        L.ebsd_cnn_get_params.argtypes = [vp, vp, i64]
+        L.ebsd_cnn_get_grads.argtypes = [vp, vp, i64]
+        L.ebsd_cnn_load.argtypes = [vp, C.c_char_p]
+        L.ebsd_cnn_save.argtypes = [vp, C.c_char_p]
+        L.ebsd_cnn_forward.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp]
+        L.ebsd_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, C.c_float, i32,
+                                          C.POINTER(C.c_float), vp]
+        L.ebsd_cnn_reset_optimizer.argtypes = [vp]
+        L.ebsd_load_model.argtypes = [vp, C.c_char_p]
+        L.ebsd_set_model.argtypes = [vp, vp]
+        L.ebsd_stage_conv3x3.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, i32, vp, vp]
+        L.ebsd_stage_conv3x3_dgrad.argtypes = [vp, i32, i32, i32, i32, vp, i32, vp, vp]
+        L.ebsd_stage_conv3x3_wgrad.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
         for name in EXPORTED:
-            if name != "ebsd_strerror" and name != "ebsd_version":
+            if name not in ("ebsd_strerror", "ebsd_version", "ebsd_cnn_num_params"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -157,6 +185,8 @@ class Params:
     roi_radius_frac: float = 0.3
     window: int = 1
     second_pass: int = 1
+    warm_start: int = 0
+    fallback_residual_px: float = 0.5
 
     def to_c(self):
         p = CParams()
@@ -174,6 +204,8 @@ class Params:
         p.roi_radius_frac = self.roi_radius_frac
         p.window = self.window
         p.second_pass = self.second_pass
+        p.warm_start = self.warm_start
+        p.fallback_residual_px = self.fallback_residual_px
         return p
 
 
@@ -249,6 +281,10 @@ class Registrar:
             "iters": torch.empty(n, self.params.levels, dtype=torch.int32, device=dev),
             "status": torch.empty(n, dtype=torch.int32, device=dev),
         }
+        if self.params.warm_start and shapes:
+            h, w = shapes[0]
+            out["warm_field"] = torch.empty(n, h // 4, w // 4, 2, **f32)
+            out["warm_misfit"] = torch.empty(n, **f32)
         offs = None
         if want_field:
             sizes = [2 * h * w for h, w in shapes]
@@ -263,8 +299,9 @@ class Registrar:
         co.field = out["_field_flat"].data_ptr() if want_field else None
         co.field_offset = offs.ctypes.data if want_field else None
         for k in ("F", "R", "rotvec", "R_finite", "F_first", "q1", "q2", "peak_height", "iters",
-                  "status"):
-            setattr(co, k, out[k].data_ptr())
+                  "status", "warm_field", "warm_misfit"):
+            if k in out:
+                setattr(co, k, out[k].data_ptr())
         return out, co
 
     @staticmethod
@@ -301,6 +338,14 @@ class Registrar:
         _check(rc, "ebsd_register_batch")
         out["_keep"] = (keep, co, arr, u_init)
         return self._unflatten_field(out, shapes)
+
+    def load_model(self, path):
+        """Network parameters for the warm start, from a parameter file."""
+        _check(lib().ebsd_load_model(self._h, os.fsencode(path)), "ebsd_load_model")
+
+    def set_model(self, net: "Cnn"):
+        """Network parameters for the warm start, copied from a Cnn object."""
+        _check(lib().ebsd_set_model(self._h, net._h), "ebsd_set_model")
 
     def autotune(self, refs, tests, ref_ids=None):
         """Time the demons strip heights on this batch and keep the fastest per
@@ -344,6 +389,76 @@ class Registrar:
         for k in ("F_first", "q1", "iters"):
             out.pop(k)
         return out
+
+
+class Cnn:
+    """The warm-start network (ebsd_cnn_* entry points) on one device."""
+
+    def __init__(self, device: int = 0, max_batch: int = 64):
+        self.device = device
+        self.max_batch = max_batch
+        h = C.c_void_p()
+        _check(lib().ebsd_cnn_create(device, max_batch, C.byref(h)), "ebsd_cnn_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebsd_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, vec):
+        """Flat float32 parameter vector (host numpy array)."""
+        import numpy as np
+        v = np.ascontiguousarray(vec, np.float32)
+        _check(lib().ebsd_cnn_set_params(self._h, v.ctypes.data, v.size), "ebsd_cnn_set_params")
+
+    def get_params(self):
+        import numpy as np
+        v = np.empty(CNN_PARAMS, np.float32)
+        _check(lib().ebsd_cnn_get_params(self._h, v.ctypes.data, v.size), "ebsd_cnn_get_params")
+        return v
+
+    def get_grads(self):
+        import numpy as np
+        v = np.empty(CNN_PARAMS, np.float32)
+        _check(lib().ebsd_cnn_get_grads(self._h, v.ctypes.data, v.size), "ebsd_cnn_get_grads")
+        return v
+
+    def load(self, path):
+        _check(lib().ebsd_cnn_load(self._h, os.fsencode(path)), "ebsd_cnn_load")
+
+    def save(self, path):
+        _check(lib().ebsd_cnn_save(self._h, os.fsencode(path)), "ebsd_cnn_save")
+
+    def forward(self, refs, tests, out=None):
+        """refs, tests: [n, 256, 256] float32 device (raw patterns).  Returns
+        [n, 64, 64, 2] (x, y) full-res px."""
+        refs, tests = _dev_f32(refs), _dev_f32(tests)
+        n, H, W = tests.shape
+        if out is None:
+            out = torch.empty(n, H // 4, W // 4, 2, dtype=torch.float32, device=tests.device)
+        _check(lib().ebsd_cnn_forward(self._h, _ptr(refs), _ptr(tests), n, H, W, _ptr(out), _stream()),
+               "ebsd_cnn_forward")
+        return out
+
+    def train_step(self, refs, tests, labels, lr=1e-3, update=True):
+        """One step (forward, loss, backward, Adam if update); returns the loss."""
+        refs, tests, labels = _dev_f32(refs), _dev_f32(tests), _dev_f32(labels)
+        n, H, W = tests.shape
+        loss = C.c_float()
+        _check(lib().ebsd_cnn_train_step(self._h, _ptr(refs), _ptr(tests), _ptr(labels), n, H, W,
+                                         float(lr), int(bool(update)), C.byref(loss), _stream()),
+               "ebsd_cnn_train_step")
+        return float(loss.value)
+
+    def reset_optimizer(self):
+        _check(lib().ebsd_cnn_reset_optimizer(self._h), "ebsd_cnn_reset_optimizer")
 
 
 # -- single-stage entry points -------------------------------------------------------
@@ -414,3 +529,50 @@ def stage_solve(q, cx, cy, pcs):
                                   float(pcs[2]), _ptr(F), _ptr(R), _ptr(st), _stream()),
            "ebsd_stage_solve")
     return F, R, st
+
+
+def _dev_bf16(x):
+    if not (x.is_cuda and x.dtype == torch.bfloat16 and x.is_contiguous()):
+        raise ValueError("expected a contiguous bfloat16 device tensor")
+    return x
+
+
+def stage_conv3x3(x, w, bias=None, relu_bf16=True):
+    """3x3 convolution kernel alone.  x [n, H, W, Cin] bfloat16, w [3, 3, Cin,
+    Cout] float32, bias [Cout] float32.  relu_bf16: bfloat16 max(conv + bias,
+    0); otherwise the float32 convolution."""
+    x = _dev_bf16(x)
+    w = _dev_f32(w)
+    n, H, W, Cin = x.shape
+    Cout = w.shape[3]
+    if relu_bf16:
+        bias = _dev_f32(bias)
+        out = torch.empty(n, H, W, Cout, dtype=torch.bfloat16, device=x.device)
+    else:
+        out = torch.empty(n, H, W, Cout, dtype=torch.float32, device=x.device)
+    _check(lib().ebsd_stage_conv3x3(_ptr(x), n, H, W, Cin, _ptr(w), _ptr(bias), Cout, 0 if relu_bf16 else 1,
+                                    _ptr(out), _stream()), "ebsd_stage_conv3x3")
+    return out
+
+
+def stage_conv3x3_dgrad(dz, w):
+    """Input gradient kernel alone: dz [n, H, W, Cout] bfloat16, w [3, 3, Cin, Cout] float32."""
+    dz = _dev_bf16(dz)
+    w = _dev_f32(w)
+    n, H, W, Cout = dz.shape
+    Cin = w.shape[2]
+    dx = torch.empty(n, H, W, Cin, dtype=torch.float32, device=dz.device)
+    _check(lib().ebsd_stage_conv3x3_dgrad(_ptr(dz), n, H, W, Cout, _ptr(w), Cin, _ptr(dx), _stream()),
+           "ebsd_stage_conv3x3_dgrad")
+    return dx
+
+
+def stage_conv3x3_wgrad(x, dz):
+    """Weight gradient kernel alone: x [n, H, W, Cin], dz [n, H, W, Cout] bfloat16 -> [3, 3, Cin, Cout]."""
+    x, dz = _dev_bf16(x), _dev_bf16(dz)
+    n, H, W, Cin = x.shape
+    Cout = dz.shape[3]
+    dw = torch.empty(3, 3, Cin, Cout, dtype=torch.float32, device=x.device)
+    _check(lib().ebsd_stage_conv3x3_wgrad(_ptr(x), _ptr(dz), n, H, W, Cin, Cout, _ptr(dw), _stream()),
+           "ebsd_stage_conv3x3_wgrad")
+    return dw

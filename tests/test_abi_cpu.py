@@ -38,14 +38,15 @@ def test_every_declared_symbol_is_exported(E):
 
 def test_version_defaults_strerror(E):
     L = E.lib()
-    assert L.ebsd_version() == 1
+    assert L.ebsd_version() == 2
     p = E.CParams()
     assert L.ebsd_params_default(C.byref(p)) == 0
     assert p.struct_size == C.sizeof(E.CParams)
     assert p.levels == 3 and list(p.max_iters)[:3] == [150, 150, 150]
     assert abs(p.sigma_px - 1.0) < 1e-7 and p.n_roi == 20 and p.roi_size == 64
     assert p.window == 1 and p.second_pass == 1
-    for code in (0, -1, -2, -3, -4, -5, -6, -8, -99):
+    assert p.warm_start == 0 and abs(p.fallback_residual_px - 0.5) < 1e-7
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -99):
         assert len(L.ebsd_strerror(code)) > 0
 
 
@@ -57,7 +58,8 @@ def test_create_validates_before_touching_the_device(E):
     assert L.ebsd_create(C.byref(p), 0, C.byref(h)) == -8
     for field, val, code in [("sigma_px", -1.0, -1), ("sigma_px", 2.0, -1), ("levels", 0, -1),
                              ("levels", 9, -1), ("n_roi", 3, -1), ("roi_size", 48, -3),
-                             ("window", 2, -1), ("pc_z", 0.0, -1), ("tol_px", float("nan"), -1)]:
+                             ("window", 2, -1), ("pc_z", 0.0, -1), ("tol_px", float("nan"), -1),
+                             ("warm_start", 2, -1), ("fallback_residual_px", -1.0, -1)]:
         p = E.Params().to_c()
         setattr(p, field, val)
         assert L.ebsd_create(C.byref(p), 0, C.byref(h)) == code, field
@@ -97,3 +99,23 @@ def test_null_arguments_rejected(E):
     assert L.ebsd_stage_xcf(None, None, 0, 48, 1, None, None, None) == -3
     assert L.ebsd_stage_restrict(None, 0, 5, 8, None, None) == -2
     assert L.ebsd_destroy(None) == 0
+
+
+def test_network_entry_points_validate_without_a_gpu(E):
+    import torch
+    from oracle import cnn
+    L = E.lib()
+    assert L.ebsd_cnn_num_params() == E.CNN_PARAMS == cnn.flatten(cnn.init_params(0)).size
+    h = C.c_void_p()
+    assert L.ebsd_cnn_create(0, 0, C.byref(h)) == -1
+    assert L.ebsd_cnn_create(0, 5000, C.byref(h)) == -1
+    assert L.ebsd_cnn_create(0, 4, None) == -1
+    if not torch.cuda.is_available():
+        assert L.ebsd_cnn_create(0, 4, C.byref(h)) == -5
+    assert L.ebsd_cnn_destroy(None) == 0
+    assert L.ebsd_cnn_set_params(None, None, E.CNN_PARAMS) == -1
+    assert L.ebsd_cnn_forward(None, None, None, 1, 256, 256, None, None) == -1
+    assert L.ebsd_cnn_train_step(None, None, None, None, 1, 256, 256, 1e-3, 1, None, None) == -1
+    assert L.ebsd_cnn_load(None, b"x") == -1
+    assert L.ebsd_load_model(None, b"x") == -1
+    assert L.ebsd_set_model(None, None) == -1

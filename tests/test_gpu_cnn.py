@@ -1,0 +1,297 @@
+"""Warm-start network on the GPU (bf16 matrix-core kernels, through the C ABI)
+against the FP64 oracle with bf16 rounding emulated at the same points
+(oracle/cnn.py), and the warm start inside the registration.  Needs an MI355X.
+
+Kernel bars (teacher forced: each kernel gets exactly representable bf16
+operands): fp32 results within 1e-5 of the sum of absolute products (fp32
+accumulation of exact bf16 products); bf16 results equal except for at most
+1 in 1000 elements one bf16 unit apart (values within fp32 rounding of a
+bf16 rounding boundary).
+
+Whole-network bars: output relative L2 error <= 5e-3 and max error <= 1.5e-2
+of the output range; gradients per parameter tensor cosine >= 0.9999 and
+relative L2 error <= 2e-2; the loss to 1e-3; the Adam step equal to the
+oracle's update from the same gradients to fp32 rounding.  These bars are
+twice the floor that fp32 accumulation itself sets: rounding every stored
+activation to bf16 turns accumulation-order differences into one-unit flips
+that multiply with depth (19% of the decoder's activations differ by one
+unit), and a copy of the oracle that only accumulates in fp32 in another
+order differs from the FP64 oracle by 2.8e-3 (output, relative L2), 6e-3
+(output max/range) and up to 9.5e-3 relative L2 with cosine >= 0.99995
+(gradients) on these inputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1907_05993_amd import ebsd
+    ebsd.lib()
+    return ebsd
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def pairs(n, H, W, seed=0):
+    """Synthetic pattern pairs of H x W (misorientation up to 10 degrees)."""
+    from paper_1907_05993_amd import synth as S
+    specs = [S.make_spec(40 + seed, i, H, W, mis_deg=(0.0, 10.0), strain=2e-3) for i in range(n)]
+    refs, tests = S.render_batch(specs)
+    return refs, tests, specs
+
+
+def bf16_tensor(a):
+    """float64 array -> (bfloat16 device tensor, the same values as float64)."""
+    t = torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(torch.bfloat16)
+    return t.cuda(), t.to(torch.float64).numpy()
+
+
+CONV_CASES = [(1, 8, 64, 8, 32), (3, 8, 32, 32, 64), (2, 32, 64, 16, 32), (1, 64, 32, 8, 64),
+              (2, 384, 128, 16, 32), (1, 256, 256, 8, 32), (1, 128, 384, 8, 32)]
+
+
+@pytest.mark.parametrize("n,cin,cout,H,W", CONV_CASES)
+def test_conv_kernels_teacher_forced(E, n, cin, cout, H, W):
+    """Forward (both epilogues), input-gradient and weight-gradient kernels on
+    exact bf16 operands against the FP64 definitions."""
+    print(f"case: conv kernels n={n} cin={cin} cout={cout} {H}x{W}", flush=True)
+    rng = np.random.default_rng(cin * 1000 + cout + H)
+    xg, x = bf16_tensor(np.maximum(rng.normal(0.2, 1.0, size=(n, H, W, cin)), 0.0))
+    w = rng.normal(0.0, np.sqrt(2.0 / (9 * cin)), size=(3, 3, cin, cout)).astype(np.float32)
+    wb = cnn.bf16(w)
+    b = rng.normal(0.0, 0.1, size=cout).astype(np.float32)
+    # fp32 epilogue
+    g = E.stage_conv3x3(xg, cuda(w), relu_bf16=False).cpu().numpy().astype(np.float64)
+    o = cnn.conv3x3(x, wb)
+    scale = cnn.conv3x3(np.abs(x), np.abs(wb))
+    assert np.all(np.abs(g - o) <= 1e-5 * scale + 1e-30)
+    # bias + ReLU + bf16 epilogue
+    gb = E.stage_conv3x3(xg, cuda(w), cuda(b), relu_bf16=True).to(torch.float64).cpu().numpy()
+    ob = cnn.bf16(np.maximum(o + b, 0.0))
+    diff = gb != ob
+    print("bf16 epilogue: %d of %d elements differ" % (diff.sum(), diff.size))
+    assert diff.mean() <= 1e-3
+    # one bf16 unit, or a ReLU decision on a value within accumulation error of zero
+    tol = np.maximum(1.01 * 2.0 ** -7 * np.maximum(np.abs(gb), np.abs(ob)), 1e-5 * (scale + np.abs(b)))
+    assert np.all(np.abs(gb - ob)[diff] <= tol[diff])
+    # input gradient (the network never needs it for its 8-channel padded input)
+    dzg, dz = bf16_tensor(rng.normal(0.0, 1.0, size=(n, H, W, cout)))
+    if cin % 32 == 0:
+        gd = E.stage_conv3x3_dgrad(dzg, cuda(w)).cpu().numpy().astype(np.float64)
+        od = cnn.conv3x3_dgrad(dz, wb)
+        sd = cnn.conv3x3_dgrad(np.abs(dz), np.abs(wb))
+        assert np.all(np.abs(gd - od) <= 1e-5 * sd + 1e-30)
+    else:
+        with pytest.raises(E.EbsdError) as ei:
+            E.stage_conv3x3_dgrad(dzg, cuda(w))
+        assert ei.value.code == -2
+    # weight gradient
+    if H % 4 == 0:
+        gw = E.stage_conv3x3_wgrad(xg, dzg).cpu().numpy().astype(np.float64)
+        ow = cnn.conv3x3_wgrad(x, dz)
+        sw = cnn.conv3x3_wgrad(np.abs(x), np.abs(dz))
+        assert np.all(np.abs(gw - ow) <= 1e-5 * sw + 1e-30)
+
+
+def random_params(seed):
+    p = cnn.init_params(seed)
+    rng = np.random.default_rng(seed + 1000)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = rng.normal(0.0, 0.05, size=p[k].shape)
+    return p
+
+
+def oracle_input(orc, refs, tests):
+    xs = []
+    for r, t in zip(refs, tests):
+        rn, _ = orc.normalize(r)
+        tn, _ = orc.normalize(t)
+        xs.append(np.stack([rn, tn], axis=-1))
+    return np.stack(xs)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("n,H,W", [(3, 64, 256), (1, 256, 256)])
+def test_forward_matches_oracle(E, orc, n, H, W):
+    print(f"case: forward n={n} {H}x{W}", flush=True)
+    p = random_params(1)
+    net = E.Cnn(max_batch=4)
+    net.set_params(cnn.flatten(p))
+    refs, tests, _ = pairs(n, H, W)
+    g = net.forward(cuda(refs), cuda(tests)).cpu().numpy()
+    o, _ = cnn.Net(p, emulate=True).forward(oracle_input(orc, refs, tests))
+    r = rel_l2(g, o)
+    mx = np.abs(g - o).max() / np.abs(o).max()
+    print("output rel L2 %.2e, max/range %.2e, |out| max %.3f" % (r, mx, np.abs(o).max()))
+    assert g.shape == (n, H // 4, W // 4, 2)
+    assert r <= 5e-3 and mx <= 1.5e-2
+
+
+def test_gradients_loss_and_adam_match_oracle(E, orc):
+    print("case: train step n=2 64x256", flush=True)
+    n, H, W = 2, 64, 256
+    p = random_params(2)
+    refs, tests, specs = pairs(n, H, W, seed=1)
+    rng = np.random.default_rng(3)
+    label = rng.normal(0.0, 2.0, size=(n, H // 4, W // 4, 2))
+    net = E.Cnn(max_batch=2)
+    net.set_params(cnn.flatten(p))
+    loss_g = net.train_step(cuda(refs), cuda(tests), cuda(label), lr=1e-3, update=False)
+    gg = cnn.unflatten(net.get_grads().astype(np.float64))
+    on = cnn.Net(p, emulate=True)
+    loss_o, _, go = on.loss_and_grads(oracle_input(orc, refs, tests), label)
+    print("loss gpu %.6f oracle %.6f" % (loss_g, loss_o))
+    assert abs(loss_g - loss_o) <= 1e-3 * loss_o
+    worst_cos, worst_rel = 1.0, 0.0
+    for k in cnn.flat_names():
+        a, b = gg[k].ravel(), go[k].ravel()
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        rl = rel_l2(a, b)
+        worst_cos, worst_rel = min(worst_cos, cos), max(worst_rel, rl)
+        assert cos >= 0.9999 and rl <= 2e-2, (k, cos, rl)
+    print("gradients: worst cosine %.6f, worst rel L2 %.2e" % (worst_cos, worst_rel))
+    # Adam: the GPU's updated parameters against the oracle's update from the GPU's gradients
+    p0 = cnn.flatten(p).astype(np.float32).astype(np.float64)
+    net.train_step(cuda(refs), cuda(tests), cuda(label), lr=1e-3, update=True)
+    g32 = net.get_grads().astype(np.float64)
+    p1 = net.get_params().astype(np.float64)
+    pe, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    cnn.adam_update(pe, g32, m, v, 1, lr=1e-3)
+    d = np.abs(p1 - pe)
+    print("adam max |dp| %.2e" % d.max())
+    assert d.max() <= 2e-6 * max(1.0, np.abs(pe).max())
+
+
+def test_deterministic_and_save_load(E, tmp_path):
+    print("case: determinism / save-load", flush=True)
+    p = random_params(4)
+    refs, tests, _ = pairs(2, 64, 256, seed=2)
+    label = np.random.default_rng(5).normal(size=(2, 16, 64, 2))
+    a = E.Cnn(max_batch=2)
+    a.set_params(cnn.flatten(p))
+    o1 = a.forward(cuda(refs), cuda(tests)).cpu().numpy()
+    o2 = a.forward(cuda(refs), cuda(tests)).cpu().numpy()
+    assert np.array_equal(o1, o2)
+    l1 = a.train_step(cuda(refs), cuda(tests), cuda(label), update=False)
+    g1 = a.get_grads()
+    l2 = a.train_step(cuda(refs), cuda(tests), cuda(label), update=False)
+    assert l1 == l2 and np.array_equal(g1, a.get_grads())
+    path = str(tmp_path / "net.bin")
+    a.save(path)
+    b = E.Cnn(max_batch=2)
+    b.load(path)
+    assert np.array_equal(a.get_params(), b.get_params())
+    assert np.array_equal(b.forward(cuda(refs), cuda(tests)).cpu().numpy(), o1)
+    raw = np.fromfile(path, dtype=np.uint8)
+    assert bytes(raw[:8]) == b"EBSDCNN1" and raw.size == 16 + 4 * E.CNN_PARAMS
+
+
+def test_network_argument_errors(E, tmp_path):
+    net = E.Cnn(max_batch=2)
+    x = torch.zeros(2, 256, 256, device="cuda")
+    with pytest.raises(E.EbsdError) as ei:
+        net.forward(x, x)
+    assert ei.value.code == -7  # no parameters yet
+    net.set_params(np.zeros(E.CNN_PARAMS, np.float32))
+    with pytest.raises(E.EbsdError) as ei:
+        net.forward(torch.zeros(2, 100, 256, device="cuda"), torch.zeros(2, 100, 256, device="cuda"))
+    assert ei.value.code == -2
+    with pytest.raises(E.EbsdError) as ei:
+        net.forward(torch.zeros(3, 256, 256, device="cuda"), torch.zeros(3, 256, 256, device="cuda"))
+    assert ei.value.code == -1
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTANET!" + b"\0" * 64)
+    with pytest.raises(E.EbsdError) as ei:
+        net.load(str(bad))
+    assert ei.value.code == -9
+    out = net.forward(x, x)  # all-zero parameters: zero field
+    assert not out.any()
+
+
+def warm_params(E, **kw):
+    return E.Params(levels=3, iters=(15, 15, 15), sigma_px=1.0, roi_size=64, n_roi=20, **kw)
+
+
+def test_warm_start_fallback_equals_plain(E, orc):
+    """Threshold 0: every pair falls back to the zero start, so the results
+    equal the plain registration's bit for bit, with the fallback bit set."""
+    print("case: warm fallback", flush=True)
+    refs, tests, _ = pairs(2, 256, 256, seed=3)
+    net = E.Cnn(max_batch=2)
+    net.set_params(cnn.flatten(random_params(6)))
+    plain = E.Registrar(warm_params(E)).register(cuda(refs), cuda(tests))
+    reg = E.Registrar(warm_params(E, warm_start=1, fallback_residual_px=0.0))
+    reg.set_model(net)
+    warm = reg.register(cuda(refs), cuda(tests))
+    torch.cuda.synchronize()
+    st = warm["status"].cpu().numpy()
+    assert np.all(st & E.WARM_FALLBACK) and not np.any(st & E.WARM_USED)
+    assert np.array_equal(st & ~E.WARM_FALLBACK, plain["status"].cpu().numpy())
+    for k in ("field", "F", "q1", "q2", "iters"):
+        assert torch.equal(warm[k], plain[k]), k
+    assert (warm["warm_misfit"] > 0).all()
+
+
+def test_warm_start_used_matches_oracle(E, orc):
+    """Threshold 1e9: the network field starts demons.  The fit's misfit
+    matches the oracle's fit of the same field, and the registration matches
+    the oracle started from that field."""
+    print("case: warm used", flush=True)
+    refs, tests, _ = pairs(2, 256, 256, seed=4)
+    net = E.Cnn(max_batch=2)
+    net.set_params(cnn.flatten(random_params(7)))
+    reg = E.Registrar(warm_params(E, warm_start=1, fallback_residual_px=1e9))
+    reg.set_model(net)
+    g = reg.register(cuda(refs), cuda(tests))
+    torch.cuda.synchronize()
+    st = g["status"].cpu().numpy()
+    assert np.all(st & E.WARM_USED)
+    wf = g["warm_field"].cpu().numpy().astype(np.float64)
+    # the network output inside the registration equals the standalone forward
+    assert np.array_equal(g["warm_field"].cpu().numpy(), net.forward(cuda(refs), cuda(tests)).cpu().numpy())
+    H = W = 256
+    pcs = (0.5 * W - 0.5, 0.5 * H - 0.5, 0.7 * W)
+    for i in range(2):
+        use, rms, _ = cnn.warm_fallback(wf[i], H, W, pcs)
+        gm = float(g["warm_misfit"][i])
+        print("misfit gpu %.6f oracle %.6f" % (gm, rms))
+        assert abs(gm - rms) <= 1e-6 * max(rms, 1e-3)
+    # registration from the same initial field (oracle takes coarsest-level px)
+    u0 = np.moveaxis(wf, -1, 1) / 4.0
+    op = orc.make_params(levels=3, iters=15, sigma=1.0, roi_size=64, n_roi=20)
+    o = orc.register_batch(refs, tests, op, u_init=u0)
+    gf = g["field"].cpu().numpy()
+    for i in range(2):
+        rms = float(np.sqrt(((gf[i] - o["field"][i]) ** 2).mean()))
+        print("field rms vs oracle %.2e" % rms)
+        assert rms <= 1e-3
+    rf = g["R_finite"].cpu().numpy()
+    o2 = orc.register_batch(refs, tests, op, rfin=rf, want_field=False)
+    assert np.abs(g["F"].cpu().numpy() - o2["F"]).max() <= 1e-6
+
+
+def test_warm_start_needs_a_model_and_256px(E):
+    reg = E.Registrar(warm_params(E, warm_start=1))
+    x = torch.zeros(1, 256, 256, device="cuda")
+    with pytest.raises(E.EbsdError) as ei:
+        reg.register(x, x)
+    assert ei.value.code == -7
+    net = E.Cnn(max_batch=1)
+    net.set_params(np.zeros(E.CNN_PARAMS, np.float32))
+    reg.set_model(net)
+    y = torch.zeros(1, 512, 512, device="cuda")
+    with pytest.raises(E.EbsdError) as ei:
+        reg.register(y, y)
+    assert ei.value.code == -2
