@@ -342,6 +342,39 @@ int ebsd_stage_solve(const float* q, int32_t n, int32_t n_roi, const double* cx,
                      double xs, double ys, double zs, double* F, double* R, uint32_t* status,
                      void* stream);
 
+/* ---- synthetic pattern pairs ---------------------------------------------------
+ *
+ * Training and benchmark inputs with ground truth.  A pattern is the gnomonic
+ * view (pattern centre and Z* as above) of the 25 FCC plane normals of
+ * {111}, {200}, {220}, {311}: a band profile (1 + cos(pi phi / theta_B)) / 2
+ * for |phi| <= theta_B, theta_B = asin((lambda / 2a) |hkl|), lambda / a =
+ * 0.02438, plus the background 1 + 0.2 (gx (x/(W-1) - 1/2) + gy (y/(H-1) -
+ * 1/2)); I = background + 0.5 sum(profiles).  The test pattern is rendered
+ * by pull-back through F^-1, so its exact shift field is q(x) = pi(F r(x)) - x
+ * (the projective model of Eq. (2)).  Each pattern is scaled to a mean of
+ * `counts` and, if noise != 0, replaced by Poisson draws: the uniforms of
+ * pixel p of stream s (0 reference, 1 test) come from Philox4x32-10 with
+ * counter (p, attempt, s, 0) and key (key[0], key[1]); the sampler is PTRS
+ * (transformed rejection with squeeze) for means >= 10, inversion below.
+ * Rendering is FP64, outputs fp32. */
+typedef struct ebsd_gen_spec {
+    double G[9];      /* crystal -> detector orientation of the reference, row-major */
+    double F[9];      /* applied deformation gradient (detector frame), row-major */
+    double gx, gy;    /* background gradient coefficients */
+    double counts;    /* mean count of each pattern (<= 0: unscaled) */
+    uint32_t key[2];  /* noise key */
+    int32_t noise;    /* 1 = Poisson noise */
+    int32_t bands;    /* 1 = the FCC bands, 0 = background only */
+} ebsd_gen_spec;
+
+/* n pairs of H x W: ref, test device [n][H][W] fp32; label (device, may be
+ * NULL; needs H % 4 == 0 and W % 4 == 0) [n][H/4][W/4][2] fp32, the shift
+ * field (x, y) at the coarse grid points 4 i + 1.5 (full-res px).  specs is
+ * a HOST array.  EBSD_EINVAL for a singular F or non-finite values.
+ * Allocates temporaries and synchronises `stream`. */
+int ebsd_gen_pairs(const ebsd_gen_spec* specs, int32_t n, int32_t H, int32_t W, double pc_x, double pc_y,
+                   double pc_z, float* ref, float* test, float* label, void* stream);
+
 /* ---- single-kernel entry points of the warm-start network -------------------
  * bf16 tensors are uint16_t bit patterns (the upper half of an IEEE float),
  * NHWC.  Weights are fp32 [3][3][Cin][Cout] (rounded to bf16 here).  Shapes:

@@ -56,6 +56,11 @@ class CParams(C.Structure):
     ]
 
 
+class CGenSpec(C.Structure):
+    _fields_ = [("G", C.c_double * 9), ("F", C.c_double * 9), ("gx", C.c_double), ("gy", C.c_double),
+                ("counts", C.c_double), ("key", C.c_uint32 * 2), ("noise", C.c_int32), ("bands", C.c_int32)]
+
+
 class CPair(C.Structure):
     _fields_ = [("ref", C.c_void_p), ("test", C.c_void_p), ("H", C.c_int32), ("W", C.c_int32),
                 ("ref_id", C.c_int32)]
@@ -92,7 +97,7 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_cnn_get_params", "ebsd_cnn_get_grads", "ebsd_cnn_load", "ebsd_cnn_save",
             "ebsd_cnn_forward", "ebsd_cnn_train_step", "ebsd_cnn_reset_optimizer",
             "ebsd_load_model", "ebsd_set_model", "ebsd_stage_conv3x3", "ebsd_stage_conv3x3_dgrad",
-            "ebsd_stage_conv3x3_wgrad"]
+            "ebsd_stage_conv3x3_wgrad", "ebsd_gen_pairs"]
 
 
 def lib():
@@ -142,6 +147,8 @@ def lib():
         L.ebsd_cnn_reset_optimizer.argtypes = [vp]
         L.ebsd_load_model.argtypes = [vp, C.c_char_p]
         L.ebsd_set_model.argtypes = [vp, vp]
+        L.ebsd_gen_pairs.argtypes = [C.POINTER(CGenSpec), i32, i32, i32, C.c_double, C.c_double, C.c_double,
+                                     vp, vp, vp, vp]
         L.ebsd_stage_conv3x3.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, i32, vp, vp]
         L.ebsd_stage_conv3x3_dgrad.argtypes = [vp, i32, i32, i32, i32, vp, i32, vp, vp]
         L.ebsd_stage_conv3x3_wgrad.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
@@ -576,3 +583,36 @@ def stage_conv3x3_wgrad(x, dz):
     _check(lib().ebsd_stage_conv3x3_wgrad(_ptr(x), _ptr(dz), n, H, W, Cin, Cout, _ptr(dw), _stream()),
            "ebsd_stage_conv3x3_wgrad")
     return dw
+
+
+def gen_pairs(specs, labels=True, device=0):
+    """Render pattern pairs on the GPU from synth.PairSpec descriptions (same
+    size, pattern centre and band set "basic" for all).  The noise key of a
+    spec is its (config_id, pair_index) seeds.  Returns (ref, test, label)
+    device tensors [n, H, W], [n, H, W], [n, H/4, W/4, 2] (label None if not
+    wanted)."""
+    n = len(specs)
+    if n == 0:
+        raise ValueError("no specs")
+    H, W, pc = specs[0].H, specs[0].W, tuple(specs[0].pc)
+    arr = (CGenSpec * n)()
+    for i, s in enumerate(specs):
+        if (s.H, s.W, tuple(s.pc)) != (H, W, pc) or s.bands != "basic":
+            raise ValueError("all specs need the same size, pattern centre and the basic band set")
+        G = [float(v) for v in list(s.G.ravel())]
+        F = [float(v) for v in list(s.F.ravel())]
+        for j in range(9):
+            arr[i].G[j] = G[j]
+            arr[i].F[j] = F[j]
+        arr[i].gx, arr[i].gy = float(s.gxy[0]), float(s.gxy[1])
+        arr[i].counts = float(s.counts)
+        arr[i].key[0], arr[i].key[1] = int(s.seeds[0]) & 0xFFFFFFFF, int(s.seeds[1]) & 0xFFFFFFFF
+        arr[i].noise = int(bool(s.noise))
+        arr[i].bands = 1
+    dev = torch.device("cuda", device)
+    ref = torch.empty(n, H, W, dtype=torch.float32, device=dev)
+    test = torch.empty(n, H, W, dtype=torch.float32, device=dev)
+    label = torch.empty(n, H // 4, W // 4, 2, dtype=torch.float32, device=dev) if labels else None
+    _check(lib().ebsd_gen_pairs(arr, n, H, W, pc[0], pc[1], pc[2], _ptr(ref), _ptr(test), _ptr(label),
+                                _stream()), "ebsd_gen_pairs")
+    return ref, test, label
