@@ -1,14 +1,20 @@
-"""Benchmark: batched demons + second-pass XCF registration on one MI355X.
+"""Benchmark: batched demons + second-pass XCF registration on one MI355X,
+warm-started by the network versus plain.
 
 Workload (default): 1024 synthetic Kikuchi pattern pairs of 256 x 256 px, FCC
 bands, pattern centre (0.5, 0.5, 0.7), Poisson noise at 1e4 counts, each test
 pattern misoriented by exactly 10 degrees about a random axis plus a random
-symmetric strain of +-2e-3; 3 pyramid levels, Gaussian field smoothing
-sigma = 1 px, per-pair stop at an RMS update of 1e-4 px with a cap of 150
-iterations per level, 20 ROIs of 64 x 64 for the second pass.
+symmetric strain of +-2e-3 (rendered on the GPU by the library's generator);
+3 pyramid levels, Gaussian field smoothing sigma = 1 px, per-pair stop at an
+RMS update of 1e-4 px with a cap of 150 iterations per level, 20 ROIs of
+64 x 64 for the second pass.
 
-One step = the whole path (normalise, pyramids, demons, shifts, Eq. 3 solve,
-remap, ROI XCF, composition) over the batch, inputs already in HBM.
+One step = the whole path over the batch, inputs already in HBM: for the
+warm start the network's forward pass, the Eq. (2) fit that decides between
+its field and zero, then normalise, pyramids, demons, shifts, Eq. (3) solve,
+remap, ROI XCF and composition.  `value` is the warm-started throughput; the
+plain path is timed the same way and reported beside it, with the rotation
+error of both against the generator's ground truth.
 Prints one JSON line.
 """
 import argparse
@@ -24,11 +30,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pattern pairs/sec (demons+XCF, 256² px, 10°) warm-start vs plain; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 BYTES_PER_PX_ITER = 24  # read field 8 + ref 4 + test 4 (gather), write field 8
+CNN_FLOP_PER_PAIR = 11.55e9  # network forward pass, 256 x 256 input
+WEIGHTS = os.path.join(ROOT, "paper_1907_05993_amd", "weights", "warm_cnn_256.bin")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def rotation_of(F):
+    U, _, Vt = np.linalg.svd(F)
+    return U @ Vt
+
+
+def rotvec_of(R):
+    """Rotation vector (axis times angle) of a rotation matrix."""
+    w = 0.5 * np.array([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+    s = np.linalg.norm(w)
+    th = np.arctan2(s, 0.5 * (np.trace(R) - 1.0))
+    return w * (th / s) if s > 0 else np.zeros(3)
 
 
 def main():
@@ -40,7 +62,10 @@ def main():
     ap.add_argument("--pairs", type=int, default=None, help="override the batch size")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--cap", type=int, default=150)
-    ap.add_argument("--cpu-sample", type=int, default=32, help="pairs timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--short-cap", type=int, default=10,
+                    help="also time the warm start with this iteration cap per level (0 = skip)")
+    ap.add_argument("--fallback", type=float, default=0.5, help="fallback misfit threshold, coarse-grid px")
+    ap.add_argument("--cpu-sample", type=int, default=512, help="pairs timed on the CPU oracle (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "demons_traffic.json"))
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
     ap.add_argument("--copy-probe", action="store_true",
@@ -62,58 +87,80 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: pairs are independent, so more GPUs would each run "
-              "their own share (see the sharding notes); run with --gpus 1.", file=sys.stderr)
+              "their own share of the batch; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    import torch
+    from paper_1907_05993_amd import ebsd
     from paper_1907_05993_amd import synth as S
+
     w = S.WORKLOADS[args.workload]
     n = args.pairs or w["n"]
     H, W = w["H"], w["W"]
     t0 = time.time()
     specs = S.workload_specs(args.workload, n=n)
-    refs, tests = S.render_batch(specs)
-    log(f"[bench] generated {n} pairs of {H}x{W} in {time.time() - t0:.1f} s")
+    d_refs, d_tests, _ = ebsd.gen_pairs(specs, labels=False)
+    torch.cuda.synchronize()
+    rv_true = np.array([rotvec_of(rotation_of(s.F)) for s in specs])
+    log(f"[bench] generated {n} pairs of {H}x{W} on the GPU in {time.time() - t0:.1f} s")
 
-    import torch
-    from paper_1907_05993_amd import ebsd
+    def make(warm, cap):
+        p = ebsd.Params(levels=3, iters=(cap,) * 3, sigma_px=1.0, tol_px=args.tol, roi_size=w["roi"], n_roi=20,
+                        warm_start=2 if warm else 0, fallback_residual_px=args.fallback)
+        reg = ebsd.Registrar(p, device=0)
+        if warm:
+            reg.load_model(WEIGHTS)
+        reg.set_graphs(not args.no_graphs)
+        return reg
 
-    dev = torch.device("cuda:0")
-    d_refs = torch.from_numpy(refs).to(dev)
-    d_tests = torch.from_numpy(tests).to(dev)
-    params = ebsd.Params(levels=3, iters=(args.cap,) * 3, sigma_px=1.0, tol_px=args.tol,
-                         roi_size=w["roi"], n_roi=20)
-    reg = ebsd.Registrar(params, device=0)
-    reg.set_graphs(not args.no_graphs)
-    tuned = reg.autotune(d_refs, d_tests)  # strip heights per level, outside the timed region
-    log(f"[bench] autotuned strip heights: {tuned}")
-    reg.set_timing(True)
-
-    for i in range(args.warmup):
-        out = reg.register(d_refs, d_tests, want_field=False)
+    def timed(reg, label):
+        tuned = reg.autotune(d_refs, d_tests)  # strip heights per level, outside the timed region
+        reg.set_timing(True)
+        for i in range(args.warmup):
+            reg.register(d_refs, d_tests, want_field=False)
+            torch.cuda.synchronize()
         torch.cuda.synchronize()
-        log(f"[bench] warmup step {i} done")
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        out = reg.register(d_refs, d_tests, want_field=False)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    log(f"[bench] {args.steps} timed steps in {elapsed:.3f} s")
+        ts = time.perf_counter()
+        for i in range(args.steps):
+            out = reg.register(d_refs, d_tests, want_field=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        level_ms, total_ms = reg.timing()
+        iters = out["iters"].cpu().numpy().astype(np.int64)
+        st = out["status"].cpu().numpy().astype(np.int64)
+        err = np.linalg.norm(out["rotvec"].cpu().numpy() - rv_true, axis=1)
+        log(f"[bench] {label}: {args.steps} steps in {el:.3f} s, median rotation error {np.median(err):.2e} rad")
+        return dict(elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
+                    tuned=tuned)
 
-    level_ms, total_ms = reg.timing()  # last step, HIP events on the stream
-    iters = out["iters"].cpu().numpy().astype(np.int64)  # [n, levels]
-    status = out["status"].cpu().numpy()
+    warm = timed(make(True, args.cap), "warm start")
+    plain = timed(make(False, args.cap), "plain")
+    short = timed(make(True, args.short_cap), f"warm start, cap {args.short_cap}") if args.short_cap > 0 else None
+
+    # network forward alone on the same batch (chunks of 256), HIP events on torch's stream
+    net = ebsd.Cnn(device=0, max_batch=256)
+    net.load(WEIGHTS)
+    for c0 in range(0, n, 256):
+        net.forward(d_refs[c0:c0 + 256], d_tests[c0:c0 + 256])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for c0 in range(0, n, 256):
+        net.forward(d_refs[c0:c0 + 256], d_tests[c0:c0 + 256])
+    e1.record()
+    torch.cuda.synchronize()
+    cnn_ms = e0.elapsed_time(e1)
+
+    # roofline of the dominant kernel: the finest level's demons launches (warm run)
     px = np.array([(H >> l) * (W >> l) for l in range(3)], np.int64)
-    px_iters = (iters * px[None, :]).sum(axis=0)  # per level, active pairs only
+    px_iters = (warm["iters"] * px[None, :]).sum(axis=0)
+    level_ms = warm["level_ms"]
     demons_bytes = float(BYTES_PER_PX_ITER * px_iters.sum())
     demons_ms = float(level_ms.sum())
-    level_gbs = [float(BYTES_PER_PX_ITER * px_iters[l] / (level_ms[l] * 1e-3) / 1e9) for l in range(3)]
-    # dominant launch: the finest level's demons kernel
-    launches0 = int(iters[:, 0].max())
+    launches0 = int(warm["iters"][:, 0].max())
     alg_per_launch0 = BYTES_PER_PX_ITER * px_iters[0] / max(launches0, 1)
     launch0_ms = float(level_ms[0]) / max(launches0, 1)
     achieved = alg_per_launch0 / (launch0_ms * 1e-3) / 1e9
-    rows0 = tuned.get((H, W), 0)
+    rows0 = warm["tuned"].get((H, W), 0)
 
     traffic = None
     if os.path.exists(args.traffic_json):
@@ -126,8 +173,18 @@ def main():
         except Exception:
             traffic = None
 
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = n * args.steps / elapsed
+    def summary(r):
+        return {"pairs_per_s": round(n * args.steps / r["elapsed"], 1),
+                "ms_per_step": round(r["elapsed"] * 1e3 / args.steps, 3),
+                "rotation_error_rad": {"median": float(np.median(r["err"])),
+                                       "p95": float(np.percentile(r["err"], 95))},
+                "mean_iters_per_level": [round(float(x), 2) for x in r["iters"].mean(axis=0)],
+                "converged": int(((r["status"] & 1) != 0).sum()),
+                "warm_used": int(((r["status"] & 4) != 0).sum()),
+                "warm_fallback": int(((r["status"] & 8) != 0).sum())}
+
+    ms_per_step = warm["elapsed"] * 1e3 / args.steps
+    value = n * args.steps / warm["elapsed"]
     rec = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -140,16 +197,16 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "fp32",
-        "data": "synthetic",
+        "data": "synthetic (GPU generator, seeded)",
         "config": {
             "workload": args.workload,
             "pairs": n, "H": H, "W": W,
             "misorientation_deg": w.get("exact_angle", w.get("mis_deg")),
             "strain": w["strain"], "counts": 1e4,
             "levels": 3, "iters_cap": args.cap, "tol_px": args.tol, "sigma_px": 1.0,
-            "n_roi": 20, "roi": w["roi"], "mode": "plain",
-            "strip_rows": {f"{k[0]}x{k[1]}": v for k, v in tuned.items()},
-            "parallelism": "single GPU, batch of independent pairs",
+            "n_roi": 20, "roi": w["roi"], "mode": "warm start (network field fitted to Eq. 2), bf16 network",
+            "fallback_residual_coarse_px": args.fallback,
+            "strip_rows": {f"{k[0]}x{k[1]}": v for k, v in warm["tuned"].items()},
             "launch": "direct" if args.no_graphs else "hipGraph replay",
         },
         "roofline": {
@@ -164,32 +221,42 @@ def main():
             "algorithmic_bytes_per_launch": alg_per_launch0,
             "avg_launch_ms": round(launch0_ms, 4),
             "all_levels_GBs": round(demons_bytes / (demons_ms * 1e-3) / 1e9, 1),
-            "algorithmic_bytes_per_step": demons_bytes,
             "demons_ms_per_step": round(demons_ms, 3),
             "level_ms": [round(float(x), 3) for x in level_ms],
-            "level_GBs": [round(x, 1) for x in level_gbs],
-            "mean_iters_per_level": [round(float(x), 2) for x in iters.mean(axis=0)],
-            "step_ms_events": round(total_ms, 3),
+            "step_ms_events": round(warm["total_ms"], 3),
         },
-        "status_counts": {"converged": int(((status & 1) != 0).sum()),
-                          "hit_cap": int(((status & 2) != 0).sum())},
+        "roofline_network": {
+            "bound": "mfma",
+            "kernel": "network forward (k_conv3x3 bf16 MFMA implicit GEMMs + pooling/upsampling/head)",
+            "achieved": round(CNN_FLOP_PER_PAIR * n / (cnn_ms * 1e-3) / 1e12, 1),
+            "peak": BF16_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(CNN_FLOP_PER_PAIR * n / (cnn_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
+            "traffic": None,
+            "forward_ms_per_step": round(cnn_ms, 3),
+        },
+        "warm": summary(warm),
+        "plain": summary(plain),
     }
+    if short is not None:
+        rec["warm_short_cap"] = dict(summary(short), cap=args.short_cap)
 
     if args.cpu_sample > 0:
         import oracle
         m = min(args.cpu_sample, n)
-        op = oracle.make_params(levels=3, iters=args.cap, sigma=1.0, tol=args.tol, roi_size=w["roi"],
-                                n_roi=20)
+        refs = d_refs[:m].cpu().numpy()
+        tests = d_tests[:m].cpu().numpy()
+        op = oracle.make_params(levels=3, iters=args.cap, sigma=1.0, tol=args.tol, roi_size=w["roi"], n_roi=20)
         tc = time.perf_counter()
-        o = oracle.register_batch(refs[:m], tests[:m], op, want_field=False)
+        o = oracle.register_batch(refs, tests, op, want_field=False)
         dt = time.perf_counter() - tc
         rec["cpu_baseline"] = {
             "value": round(m / dt, 3),
             "unit": "pairs/s",
             "cores": int(o["threads"]),
             "kind": "oracle",
-            "sample": f"first {m} pairs of the same workload, FP64 C oracle, OpenMP one pair per "
-                      f"thread ({dt:.1f} s wall)",
+            "sample": f"first {m} pairs of the same workload, plain path (the oracle has no network), "
+                      f"FP64 C oracle, OpenMP one pair per thread ({dt:.1f} s wall)",
         }
         log(f"[bench] cpu oracle: {m} pairs in {dt:.1f} s on {o['threads']} threads")
     print(json.dumps(rec), flush=True)

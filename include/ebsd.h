@@ -87,8 +87,10 @@ typedef struct ebsd_params {
     double roi_radius_frac;               /* ring radius / W */
     int32_t window;                       /* 1 = Hann window on each ROI (section 2), 0 = none */
     int32_t second_pass;                  /* 1 = remap + XCF second pass (Eq. (12)); 0 = demons only */
-    int32_t warm_start;                   /* 1 = start demons from the network's field (256 x 256, 3 levels) */
-    float fallback_residual_px;           /* warm start: largest RMS misfit of the Eq. (2) fit, full-res px */
+    int32_t warm_start;                   /* 256 x 256, 3 levels: 1 = start demons from the network's field,
+                                             2 = from the Eq. (2) field fitted to it; 0 = from zero */
+    float fallback_residual_px;           /* warm start: largest RMS misfit of the Eq. (2) fit, in px of the
+                                             coarsest level (the grid the field initialises) */
 } ebsd_params;
 
 /* One scan point.  ref/test: device pointers to H x W fp32 patterns.  Pairs
@@ -245,9 +247,11 @@ int ebsd_get_timing(ebsd_handle* h, double* level_ms, double* total_ms);
  * Fallback rule (warm start inside ebsd_register_batch): the Eq. (2) model is
  * fitted (Eq. (3): direct linear start, Gauss-Newton, det F = 1) to the
  * predicted field at the grid points within roi_radius_frac * W of the
- * pattern centre; if the RMS endpoint misfit exceeds fallback_residual_px the
- * pair starts from zero (EBSD_WARM_FALLBACK), otherwise from the predicted
- * field (EBSD_WARM_USED).
+ * pattern centre; if the RMS endpoint misfit, expressed in px of the coarse
+ * grid (full-resolution misfit / 4), exceeds fallback_residual_px the pair
+ * starts from zero (EBSD_WARM_FALLBACK), otherwise (EBSD_WARM_USED) from
+ * the predicted field (warm_start = 1) or from the field of the fitted model
+ * (warm_start = 2: the network's estimate projected onto Eq. (2)).
  */
 #define EBSD_CNN_PARAMS 1762306
 

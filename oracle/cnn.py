@@ -259,14 +259,17 @@ def grid_points(H, W):
     return 4.0 * xs + 1.5, 4.0 * ys + 1.5
 
 
-def warm_fallback(field, H, W, pcs, radius_frac=0.3, threshold=0.5):
+def warm_fallback(field, H, W, pcs, radius_frac=0.3, threshold=0.5, levels=3):
     """Fit the Eq. (2) model to a predicted coarse field and decide its use.
 
     field: [H/4, W/4, 2] (x, y) shifts in full-resolution px at the grid points.
     The fit uses the grid points within radius_frac * W of the pattern centre
-    and the Eq. (3) solver (DLT start, Gauss-Newton, det F = 1).  Returns
-    (use, rms_misfit_px, F): the field is used when the RMS distance between
-    the fitted model's shifts and the predicted shifts is at most threshold.
+    and the Eq. (3) solver (DLT start, Gauss-Newton, det F = 1).  The RMS
+    distance between the fitted model's shifts and the predicted shifts is
+    the misfit (full-resolution px); the field is used when the misfit,
+    expressed in px of the coarsest pyramid level (the grid the field
+    initialises, 2^(levels-1) full-resolution px), is at most threshold.
+    Returns (use, rms_misfit_px, F).
     """
     import oracle
     xs, ys = grid_points(H, W)
@@ -280,4 +283,4 @@ def warm_fallback(field, H, W, pcs, radius_frac=0.3, threshold=0.5):
     py = pcs[1] + pcs[2] * v[1] / v[2]
     d2 = (px - cx - q[:, 0]) ** 2 + (py - cy - q[:, 1]) ** 2
     rms = float(np.sqrt(d2.mean()))
-    return rms <= threshold, rms, F
+    return rms / 2 ** (levels - 1) <= threshold, rms, F

@@ -60,6 +60,8 @@ struct ebsd_cnn {
     bf16_t* dz = nullptr;
     float* part = nullptr;   // weight-gradient partial sums
     float* bpart = nullptr;  // bias / head / loss partial sums
+    float* part2 = nullptr;  // chunk sums of the column reductions
+    int64_t part2_floats = 0;
     float* dloss = nullptr;
     std::vector<void*> allocs;
 };
@@ -153,14 +155,15 @@ bool alloc_backward(ebsd_cnn* c)
     if (c->have_bwd) return true;
     const int64_t n = c->max_batch;
     const int64_t g = n * px(256) * 32;  // largest gradient tensor
-    const int64_t bp = (int64_t)mask_blocks(n * px(256)) * 32;
+    const int64_t bp = (int64_t)mask_blocks(n * px(256), 32) * 32;
+    c->part2_floats = 1600000 + 128 * n;
     bool ok = dalloc(c, &c->grads, kNumParams) && dalloc(c, &c->adam_m, kNumParams) &&
               dalloc(c, &c->adam_v, kNumParams) && dalloc(c, &c->gA, g) && dalloc(c, &c->gB, g) &&
               dalloc(c, &c->gC, n * px(64) * 128) && dalloc(c, &c->dz, g) &&
               dalloc(c, &c->part, wgrad_part_floats(c->max_batch)) &&
               dalloc(c, &c->bpart, bp > (int64_t)head_blocks(n * px(64)) * 258 ? bp
                                                                                : (int64_t)head_blocks(n * px(64)) * 258) &&
-              dalloc(c, &c->dloss, 1);
+              dalloc(c, &c->dloss, 1) && dalloc(c, &c->part2, c->part2_floats);
     if (ok) ok = hipMemset(c->grads, 0, kNumParams * sizeof(float)) == hipSuccess &&
                  hipMemset(c->adam_m, 0, kNumParams * sizeof(float)) == hipSuccess &&
                  hipMemset(c->adam_v, 0, kNumParams * sizeof(float)) == hipSuccess;
@@ -240,7 +243,7 @@ hipError_t layer_back(ebsd_cnn* c, int l, int n, int H0, int W0, const float* g,
     const int H = H0 >> d.lvl, W = W0 >> d.lvl;
     const int64_t P = (int64_t)n * H * W;
     hipError_t e = launch_mask_round(g, act, P, d.cout, act_cs, act_co, c->dz, c->bpart, s);
-    CK(launch_colsum(c->bpart, mask_blocks(P), d.cout, c->grads + c->off_b[l], s));
+    CK(launch_colsum(c->bpart, mask_blocks(P, d.cout), d.cout, c->grads + c->off_b[l], c->part2, c->part2_floats, s));
     WgradArgs w;
     w.x = x;
     w.dz = c->dz;
@@ -253,7 +256,8 @@ hipError_t layer_back(ebsd_cnn* c, int l, int n, int H0, int W0, const float* g,
     w.cin_keep = d.cin;
     w.splits = wgrad_splits(n, H, W, d.cinp, d.cout, &w.tiles_per_split);
     CK(launch_wgrad3x3(w, s));
-    CK(launch_colsum(c->part, w.splits, 9LL * d.cin * d.cout, c->grads + c->off_w[l], s));
+    CK(launch_colsum(c->part, w.splits, 9LL * d.cin * d.cout, c->grads + c->off_w[l], c->part2, c->part2_floats,
+                     s));
     if (gin) {
         ConvArgs a;
         a.x = c->dz;
@@ -281,7 +285,7 @@ hipError_t backward(ebsd_cnn* c, int n, int H, int W, const float* gout, hipStre
     const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
     const int64_t P2 = (int64_t)n * H2 * W2;
     hipError_t e = launch_head_back(c->a6, gout, P2, kHeadC, c->params + c->off_hw, c->gA, c->bpart, s);
-    CK(launch_colsum(c->bpart, head_blocks(P2), 2 * kHeadC + 2, c->grads + c->off_hw, s));
+    CK(launch_colsum(c->bpart, head_blocks(P2), 2 * kHeadC + 2, c->grads + c->off_hw, c->part2, c->part2_floats, s));
     CK(layer_back(c, 9, n, H, W, c->gA, c->a6, 128, 0, c->a5, c->gB, s));         // d2 -> g(a5)
     CK(layer_back(c, 8, n, H, W, c->gB, c->a5, 128, 0, c->cat, c->gA, s));        // d1 -> g(cat)
     CK(launch_upsample_back(c->gA, n, H3, W3, 256, kCatC, c->gB, s));             // g(e4)
@@ -491,7 +495,8 @@ int ebsd_cnn_train_step(ebsd_cnn* c, const float* ref, const float* test, const 
     if (forward(c, n, H, W, c->out, s) != hipSuccess) return EBSD_EDEVICE;
     // the loss gradient replaces the output in place
     if (launch_loss(c->out, label, P64, c->out, c->bpart, s) != hipSuccess) return EBSD_EDEVICE;
-    if (launch_colsum(c->bpart, loss_blocks(P64), 1, c->dloss, s) != hipSuccess) return EBSD_EDEVICE;
+    if (launch_colsum(c->bpart, loss_blocks(P64), 1, c->dloss, c->part2, c->part2_floats, s) != hipSuccess)
+        return EBSD_EDEVICE;
     // read the loss before the backward pass reuses bpart
     float lsum = 0.0f;
     if (hipMemcpyAsync(&lsum, c->dloss, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -623,11 +628,15 @@ int ebsd_stage_conv3x3_wgrad(const uint16_t* x, const uint16_t* dz, int32_t n, i
     a.Cout = Cout;
     a.cin_keep = Cin;
     a.splits = wgrad_splits(n, H, W, Cin, Cout, &a.tiles_per_split);
-    TempBuf part;
-    if (hipMalloc(&part.p, sizeof(float) * (size_t)a.splits * 9 * Cin * Cout) != hipSuccess) return EBSD_ENOMEM;
+    TempBuf part, tmp;
+    const int64_t tmp_floats = (int64_t)((a.splits + 511) / 512) * 9 * Cin * Cout;
+    if (hipMalloc(&part.p, sizeof(float) * (size_t)a.splits * 9 * Cin * Cout) != hipSuccess ||
+        hipMalloc(&tmp.p, sizeof(float) * (size_t)tmp_floats) != hipSuccess)
+        return EBSD_ENOMEM;
     a.part = static_cast<float*>(part.p);
     if (launch_wgrad3x3(a, s) != hipSuccess) return EBSD_EDEVICE;
-    if (launch_colsum(a.part, a.splits, 9LL * Cin * Cout, dw, s) != hipSuccess) return EBSD_EDEVICE;
+    if (launch_colsum(a.part, a.splits, 9LL * Cin * Cout, dw, static_cast<float*>(tmp.p), tmp_floats, s) != hipSuccess)
+        return EBSD_EDEVICE;
     return hipStreamSynchronize(s) == hipSuccess ? EBSD_OK : EBSD_EDEVICE;
 }
 

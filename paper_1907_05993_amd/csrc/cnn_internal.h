@@ -42,8 +42,12 @@ struct WgradArgs {
 int wgrad_splits(int n, int H, int W, int Cin, int Cout, int* tiles_per_split);
 hipError_t launch_wgrad3x3(const WgradArgs& a, hipStream_t s);
 
-// out[c] = sum_{b < nb} part[b * ncols + c], summed in increasing b.
-hipError_t launch_colsum(const float* part, int64_t nb, int64_t ncols, float* out, hipStream_t s);
+// out[c] = sum_{b < nb} part[b * ncols + c] in a fixed order: rows are
+// summed in chunks of 512 (partial sums in tmp, ceil(nb / 512) * ncols
+// floats) and the chunk sums in increasing chunk order; tmp is not used
+// when nb <= 512.
+hipError_t launch_colsum(const float* part, int64_t nb, int64_t ncols, float* out, float* tmp, int64_t tmp_floats,
+                         hipStream_t s);
 
 // Packed network input: x[i][y][x][0..7] = bf16(ref_i, test_i, 0, ..., 0) from
 // normalised fp32 images ref = ref_base + slot(i) * ref_stride, test likewise.
@@ -64,8 +68,9 @@ hipError_t launch_upsample_into(const bf16_t* in, int n, int h, int w, int C, bf
 // Gradient of the upsampling: g[n][h][w][c] = sum of the 4 copies in gout[n][2h][2w][cs] channel c.
 hipError_t launch_upsample_back(const float* gout, int n, int h, int w, int C, int cs, float* g,
                                 hipStream_t s);
-// dz = g * (act > 0) rounded to bf16; per-block partial bias sums of the fp32 dz.
-int mask_blocks(int64_t P);
+// dz = g * (act > 0) rounded to bf16; per-block partial bias sums of the fp32
+// dz (mask_blocks(P, C) rows of C).  C in {32, 64, 128, 256}.
+int mask_blocks(int64_t P, int C);
 hipError_t launch_mask_round(const float* g, const bf16_t* act, int64_t P, int C, int act_cs,
                              int act_co, bf16_t* dz, float* bias_part, hipStream_t s);
 // 1x1 head: out[p][o] = sum_c act[p][c] * hw[c][o] + hb[o], o < 2, fp32.
@@ -90,10 +95,12 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        float b2, float eps, float bc1, float bc2, hipStream_t s);
 // Warm-start fallback: fit the Eq. (2) model to each predicted field at the
 // coarse grid points within `radius` px of the pattern centre (FP64 Eq. (3)
-// solve), then u_init = use ? field : 0 in [n][2][H/4][W/4] (full-res px),
-// misfit[i] = RMS endpoint misfit (full-res px), flag[i] = use ? 4 : 8.
+// solve); use = misfit / 4 <= threshold (coarse-grid px); u_init [n][2][H/4][W/4] (full-res px) =
+// 0 if not use, else the predicted field (model_field = 0) or the fitted
+// model's field (model_field = 1); misfit[i] = RMS endpoint misfit (full-res
+// px), flag[i] = use ? 4 : 8.
 hipError_t launch_warm_fit(const float* field, int n, int H, int W, double xs, double ys, double zs,
-                           double radius, double threshold, float* u_init, float* misfit,
+                           double radius, double threshold, int model_field, float* u_init, float* misfit,
                            uint32_t* flag, hipStream_t s);
 
 // Network runner (cnn.hip), for the registration's warm start.

@@ -126,7 +126,7 @@ int check_params(const ebsd_params* p)
     if (!(p->roi_radius_frac >= 0.0) || !std::isfinite(p->roi_radius_frac)) return EBSD_EINVAL;
     if (p->window != 0 && p->window != 1) return EBSD_EINVAL;
     if (p->second_pass != 0 && p->second_pass != 1) return EBSD_EINVAL;
-    if (p->warm_start != 0 && p->warm_start != 1) return EBSD_EINVAL;
+    if (p->warm_start < 0 || p->warm_start > 2) return EBSD_EINVAL;
     if (!(p->fallback_residual_px >= 0.0f) || !std::isfinite(p->fallback_residual_px)) return EBSD_EINVAL;
     return EBSD_OK;
 }
@@ -559,7 +559,8 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
             if (ec) return ec;
         }
         EBSD_TRY(launch_warm_fit(wf, nb, H, W, b.xs, b.ys, b.zs, p.roi_radius_frac * W,
-                                 (double)p.fallback_residual_px, reinterpret_cast<float*>(base + o_uinit),
+                                 (double)p.fallback_residual_px, p.warm_start == 2 ? 1 : 0,
+                                 reinterpret_cast<float*>(base + o_uinit),
                                  reinterpret_cast<float*>(base + o_wmis), reinterpret_cast<uint32_t*>(base + o_wflag),
                                  s));
     }

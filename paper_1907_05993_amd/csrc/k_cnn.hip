@@ -229,13 +229,26 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad3x3(WgradArgs a)
 
 // ---- element-wise passes ---------------------------------------------------------
 
-__global__ void k_colsum(const float* __restrict__ part, int64_t nb, int64_t ncols, float* __restrict__ out)
+// Block: 32 columns x 8 row lanes over rows [blockIdx.y * chunk, + chunk);
+// lane r sums rows r, r + 8, ... of the chunk; the 8 lane sums are then added
+// in increasing r.  out has one row per chunk.
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ part, int64_t nb, int64_t ncols,
+                                                int64_t chunk, float* __restrict__ out)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncols) return;
+    __shared__ float sh[8][32];
+    const int cl = threadIdx.x & 31, r = threadIdx.x >> 5;
+    const int64_t c = (int64_t)blockIdx.x * 32 + cl;
+    const int64_t b0 = (int64_t)blockIdx.y * chunk, b1 = min(nb, b0 + chunk);
     float s = 0.0f;
-    for (int64_t b = 0; b < nb; b++) s += part[b * ncols + c];
-    out[c] = s;
+    if (c < ncols)
+        for (int64_t b = b0 + r; b < b1; b += 8) s += part[b * ncols + c];
+    sh[r][cl] = s;
+    __syncthreads();
+    if (r == 0 && c < ncols) {
+        float t = sh[0][cl];
+        for (int k = 1; k < 8; k++) t += sh[k][cl];
+        out[(int64_t)blockIdx.y * ncols + c] = t;
+    }
 }
 
 __global__ void k_pack_input(const float* __restrict__ rb, int64_t rs, const int32_t* __restrict__ slot,
@@ -358,56 +371,70 @@ __global__ void k_upsample_back(const float* __restrict__ gout, int n, int h, in
     g[i] = ((gout[o] + gout[o + cs]) + gout[o + (int64_t)W2 * cs]) + gout[o + (int64_t)W2 * cs + cs];
 }
 
-constexpr int kMaskPB = 256;  // pixels per mask block
-
-// Block b covers pixels [b kMaskPB, (b+1) kMaskPB).  Thread (sub, c): channel
-// c, pixels p0 + sub, p0 + sub + nsub, ...; the nsub partial bias sums are
-// combined in increasing sub.
+// One thread per (pixel, 8-channel group): 16-byte loads of the activation,
+// 32-byte loads of the gradient, a 16-byte store of dz.  A block covers
+// 2048 / C pixels; its partial bias sums add the block's pixels in order.
+// C must be 32, 64, 128 or 256.
 __global__ void __launch_bounds__(256) k_mask_round(const float* __restrict__ g, const bf16_t* __restrict__ act,
                                                     int64_t P, int C, int act_cs, int act_co,
                                                     bf16_t* __restrict__ dz, float* __restrict__ part)
 {
-    __shared__ float sh[256];
+    __shared__ float sh[256][9];
     const int tid = threadIdx.x;
-    const int nsub = C >= 256 ? 1 : 256 / C;
-    const int64_t p0 = (int64_t)blockIdx.x * kMaskPB;
-    const int64_t p1 = min(P, p0 + kMaskPB);
-    for (int cbase = 0; cbase < C; cbase += 256 / nsub) {
-        const int sub = tid / (256 / nsub), cl = tid % (256 / nsub);
-        const int c = cbase + cl;
-        float s = 0.0f;
-        if (c < C) {
-            for (int64_t p = p0 + sub; p < p1; p += nsub) {
-                const float a = bf2f(act[p * act_cs + act_co + c]);
-                const float v = a > 0.0f ? g[p * C + c] : 0.0f;
-                dz[p * C + c] = f2bf(v);
-                s += v;
-            }
+    const int cg = C >> 3, ppb = 256 / cg;
+    const int64_t p = (int64_t)blockIdx.x * ppb + tid / cg;
+    const int q = tid % cg;
+    float v[8];
+    for (int j = 0; j < 8; j++) v[j] = 0.0f;
+    if (p < P) {
+        const u16x8 a = *reinterpret_cast<const u16x8*>(act + p * act_cs + act_co + 8 * q);
+        const float4 g0 = *reinterpret_cast<const float4*>(g + p * C + 8 * q);
+        const float4 g1 = *reinterpret_cast<const float4*>(g + p * C + 8 * q + 4);
+        const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+        u16x8 o;
+        for (int j = 0; j < 8; j++) {
+            v[j] = bf2f(a[j]) > 0.0f ? gv[j] : 0.0f;
+            o[j] = f2bf(v[j]);
         }
-        sh[tid] = s;
-        __syncthreads();
-        if (sub == 0 && c < C) {
-            float t = sh[cl];
-            for (int k = 1; k < nsub; k++) t += sh[k * (256 / nsub) + cl];
-            part[(int64_t)blockIdx.x * C + c] = t;
-        }
-        __syncthreads();
+        *reinterpret_cast<u16x8*>(dz + p * C + 8 * q) = o;
+    }
+    for (int j = 0; j < 8; j++) sh[tid][j] = v[j];
+    __syncthreads();
+    if (tid < C) {
+        const int qq = tid >> 3, j = tid & 7;
+        float t = 0.0f;
+        for (int k = 0; k < ppb; k++) t += sh[k * cg + qq][j];
+        part[(int64_t)blockIdx.x * C + tid] = t;
     }
 }
 
-__global__ void k_head_fwd(const bf16_t* __restrict__ act, int64_t P, int C, const float* __restrict__ hw,
-                           const float* __restrict__ hb, float* __restrict__ out)
+// 16 threads per pixel, each 8 channels (one 16-byte load); the 16 partial
+// dot products are combined by a fixed xor tree.  C must be 128.
+__global__ void __launch_bounds__(256) k_head_fwd(const bf16_t* __restrict__ act, int64_t P, int C,
+                                                  const float* __restrict__ hw, const float* __restrict__ hb,
+                                                  float* __restrict__ out)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = t >> 4;
+    const int g = (int)(t & 15);
     float s0 = 0.0f, s1 = 0.0f;
-    for (int c = 0; c < C; c++) {
-        const float a = bf2f(act[p * C + c]);
-        s0 += a * hw[2 * c];
-        s1 += a * hw[2 * c + 1];
+    if (p < P) {
+        const u16x8 v = *reinterpret_cast<const u16x8*>(act + p * C + 8 * g);
+        for (int j = 0; j < 8; j++) {
+            const float a = bf2f(v[j]);
+            const int c = 8 * g + j;
+            s0 += a * hw[2 * c];
+            s1 += a * hw[2 * c + 1];
+        }
     }
-    out[2 * p] = s0 + hb[0];
-    out[2 * p + 1] = s1 + hb[1];
+    for (int o = 1; o < 16; o <<= 1) {
+        s0 += __shfl_xor(s0, o, 16);
+        s1 += __shfl_xor(s1, o, 16);
+    }
+    if (p < P && g == 0) {
+        out[2 * p] = s0 + hb[0];
+        out[2 * p + 1] = s1 + hb[1];
+    }
 }
 
 constexpr int kLossPB = 256;
@@ -502,6 +529,8 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+constexpr int64_t kColsumChunk = 512;
+
 }  // namespace
 
 bool conv3x3_supported(int H, int W, int Cin, int Cout)
@@ -551,9 +580,18 @@ hipError_t launch_wgrad3x3(const WgradArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float* part, int64_t nb, int64_t ncols, float* out, hipStream_t s)
+hipError_t launch_colsum(const float* part, int64_t nb, int64_t ncols, float* out, float* tmp, int64_t tmp_floats,
+                         hipStream_t s)
 {
-    hipLaunchKernelGGL(k_colsum, dim3(blocks_for(ncols, 256)), dim3(256), 0, s, part, nb, ncols, out);
+    if (nb > kColsumChunk) {
+        const int64_t nch = (nb + kColsumChunk - 1) / kColsumChunk;
+        if (!tmp || nch * ncols > tmp_floats || nch > 65535) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_colsum, dim3(blocks_for(ncols, 32), (unsigned)nch), dim3(256), 0, s, part, nb, ncols,
+                           (int64_t)kColsumChunk, tmp);
+        part = tmp;
+        nb = nch;
+    }
+    hipLaunchKernelGGL(k_colsum, dim3(blocks_for(ncols, 32), 1), dim3(256), 0, s, part, nb, ncols, nb, out);
     return hipGetLastError();
 }
 
@@ -601,12 +639,13 @@ hipError_t launch_upsample_back(const float* gout, int n, int h, int w, int C, i
     return hipGetLastError();
 }
 
-int mask_blocks(int64_t P) { return (int)((P + kMaskPB - 1) / kMaskPB); }
+int mask_blocks(int64_t P, int C) { return (int)((P * C / 8 + 255) / 256); }
 
 hipError_t launch_mask_round(const float* g, const bf16_t* act, int64_t P, int C, int act_cs,
                              int act_co, bf16_t* dz, float* bias_part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mask_round, dim3(mask_blocks(P)), dim3(256), 0, s, g, act, P, C, act_cs, act_co, dz,
+    if (C != 32 && C != 64 && C != 128 && C != 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mask_round, dim3(mask_blocks(P, C)), dim3(256), 0, s, g, act, P, C, act_cs, act_co, dz,
                        bias_part);
     return hipGetLastError();
 }
@@ -614,7 +653,8 @@ hipError_t launch_mask_round(const float* g, const bf16_t* act, int64_t P, int C
 hipError_t launch_head_fwd(const bf16_t* act, int64_t P, int C, const float* hw, const float* hb,
                            float* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_head_fwd, dim3(blocks_for(P, 256)), dim3(256), 0, s, act, P, C, hw, hb, out);
+    if (C != 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_head_fwd, dim3(blocks_for(16 * P, 256)), dim3(256), 0, s, act, P, C, hw, hb, out);
     return hipGetLastError();
 }
 

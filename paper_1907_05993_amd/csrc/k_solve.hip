@@ -430,8 +430,8 @@ struct GridFit {
 
 __global__ void __launch_bounds__(kFitThreads)
 k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys, double zs,
-           double radius, double threshold, float* __restrict__ u_init, float* __restrict__ misfit,
-           uint32_t* __restrict__ flag)
+           double radius, double threshold, int model_field, float* __restrict__ u_init,
+           float* __restrict__ misfit, uint32_t* __restrict__ flag)
 {
     __shared__ double sh[4 * 45];
     const int b = blockIdx.x;
@@ -556,15 +556,30 @@ k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys
     }
     fit_block_sum<1>(ss, sh);
     const double rms = sqrt(ss[0] / npts);
-    const bool use = rms <= threshold;
+    // the decision is taken in px of the coarse grid the field initialises
+    const bool use = rms * 0.25 <= threshold;
     if (threadIdx.x == 0) {
         misfit[b] = (float)rms;
         flag[b] = use ? (uint32_t)EBSD_WARM_USED : (uint32_t)EBSD_WARM_FALLBACK;
     }
     float* u = u_init + (int64_t)b * 2 * ng;
     for (int g = threadIdx.x; g < ng; g += kFitThreads) {
-        u[g] = use ? gf.q[2 * g] : 0.0f;
-        u[ng + g] = use ? gf.q[2 * g + 1] : 0.0f;
+        float ux = 0.0f, uy = 0.0f;
+        if (use && model_field) {
+            // the fitted model's shift at every grid point (Eq. (2))
+            const double x = 4.0 * (double)(g % gw) + 1.5, y = 4.0 * (double)(g / gw) + 1.5;
+            const double rx = x - xs, ry = y - ys;
+            const double v0 = f[0] * rx + f[1] * ry + f[2] * zs;
+            const double v1 = f[3] * rx + f[4] * ry + f[5] * zs;
+            const double v2 = f[6] * rx + f[7] * ry + f[8] * zs;
+            ux = (float)(xs + zs * v0 / v2 - x);
+            uy = (float)(ys + zs * v1 / v2 - y);
+        } else if (use) {
+            ux = gf.q[2 * g];
+            uy = gf.q[2 * g + 1];
+        }
+        u[g] = ux;
+        u[ng + g] = uy;
     }
 }
 
@@ -618,12 +633,12 @@ hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx
 }
 
 hipError_t launch_warm_fit(const float* field, int n, int H, int W, double xs, double ys, double zs,
-                           double radius, double threshold, float* u_init, float* misfit,
+                           double radius, double threshold, int model_field, float* u_init, float* misfit,
                            uint32_t* flag, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_warm_fit, dim3(n), dim3(kFitThreads), 0, s, field, H / 4, W / 4, xs, ys, zs,
-                       radius, threshold, u_init, misfit, flag);
+                       radius, threshold, model_field, u_init, misfit, flag);
     return hipGetLastError();
 }
 

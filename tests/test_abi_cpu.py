@@ -59,7 +59,7 @@ def test_create_validates_before_touching_the_device(E):
     for field, val, code in [("sigma_px", -1.0, -1), ("sigma_px", 2.0, -1), ("levels", 0, -1),
                              ("levels", 9, -1), ("n_roi", 3, -1), ("roi_size", 48, -3),
                              ("window", 2, -1), ("pc_z", 0.0, -1), ("tol_px", float("nan"), -1),
-                             ("warm_start", 2, -1), ("fallback_residual_px", -1.0, -1)]:
+                             ("warm_start", 3, -1), ("fallback_residual_px", -1.0, -1)]:
         p = E.Params().to_c()
         setattr(p, field, val)
         assert L.ebsd_create(C.byref(p), 0, C.byref(h)) == code, field
