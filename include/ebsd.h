@@ -209,6 +209,21 @@ int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w
 /* Force the strip height (16, 32, 64 or 128) for a level size. */
 int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t rows);
 
+/* Two demons iterations per launch (temporal blocking): the row-marching
+ * kernel can run iteration k + 1 on the rows of iteration k while they are
+ * still on chip, reading the field once and writing it once per two
+ * iterations.  The second iteration of a launch runs before the stop
+ * decision on the first is known; the next launch takes the decisions in
+ * iteration order and recomputes the field of a pair that should have
+ * stopped in between, so iteration counts, status and fields are identical to
+ * one iteration per launch.  ebsd_autotune times strip heights 32, 64, 128 of
+ * this kernel against the single-iteration kernel and keeps it for a level
+ * size where it is faster.  ebsd_get_fused_height returns the strip height
+ * used for a level size (0 = one iteration per launch); ebsd_set_fused_height
+ * forces it (0, 32, 64 or 128; levels up to 256 px wide). */
+int ebsd_get_fused_height(const ebsd_handle* h, int32_t level_h, int32_t level_w);
+int ebsd_set_fused_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t rows);
+
 /* Timing of the demons iterations, for measurement tools.  enable != 0 makes
  * later calls record HIP events on their stream around each pyramid level's
  * demons launches and around the whole call (of its last size bucket). */

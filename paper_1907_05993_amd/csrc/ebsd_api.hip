@@ -45,6 +45,9 @@ struct ebsd_handle {
     // strip height of the row-marching demons kernel per level size (h, w),
     // from ebsd_autotune or the tuning cache file; default kDefaultStripTY
     std::map<std::pair<int, int>, int> strip_ty;
+    // strip height of the two-iterations-per-launch kernel per level size; a
+    // level size absent here (or 0) runs one iteration per launch
+    std::map<std::pair<int, int>, int> fused_ty;
     std::string tune_cache;  // EBSD_TUNE_CACHE at create time (may be empty)
     // captured launch sequences per bucket configuration (replayed with
     // hipGraphLaunch); the capture itself runs on a private stream
@@ -63,15 +66,32 @@ int strip_ty_for(const ebsd_handle* h, int lh, int lw)
     return it == h->strip_ty.end() ? kDefaultStripTY : it->second;
 }
 
+int fused_ty_for(const ebsd_handle* h, int lh, int lw)
+{
+    if (!rows_cpl(lw)) return 0;
+    auto it = h->fused_ty.find(std::make_pair(lh, lw));
+    return it == h->fused_ty.end() ? 0 : it->second;
+}
+
 // Tuning cache: one line "gfx950 <level h> <level w> <strip height>" per entry.
+// Tuning cache: one line "gfx950 <level h> <level w> <strip height> <fused strip height>"
+// per level size (fused strip height 0: one iteration per launch).
 void load_tune_cache(ebsd_handle* h)
 {
     if (h->tune_cache.empty()) return;
     std::ifstream f(h->tune_cache);
-    std::string arch;
-    int lh, lw, ty;
-    while (f >> arch >> lh >> lw >> ty)
-        if (arch == "gfx950" && rows_ty_supported(ty)) h->strip_ty[std::make_pair(lh, lw)] = ty;
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string arch;
+        int lh = 0, lw = 0, ty = 0, fty = 0;
+        if (!(is >> arch >> lh >> lw >> ty) || arch != "gfx950") continue;
+        if (!(is >> fty)) fty = 0;
+        const auto key = std::make_pair(lh, lw);
+        if (rows_ty_supported(ty)) h->strip_ty[key] = ty;
+        if (rows2_ty_supported(fty)) h->fused_ty[key] = fty;
+        else h->fused_ty.erase(key);
+    }
 }
 
 void save_tune_cache(const ebsd_handle* h)
@@ -79,7 +99,8 @@ void save_tune_cache(const ebsd_handle* h)
     if (h->tune_cache.empty()) return;
     std::ofstream f(h->tune_cache, std::ios::trunc);
     for (auto& kv : h->strip_ty)
-        f << "gfx950 " << kv.first.first << " " << kv.first.second << " " << kv.second << "\n";
+        f << "gfx950 " << kv.first.first << " " << kv.first.second << " " << kv.second << " "
+          << fused_ty_for(h, kv.first.first, kv.first.second) << "\n";
 }
 
 struct DeviceGuard {
@@ -361,7 +382,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const size_t o_f0 = w.take(field_bytes);
     const size_t o_f1 = w.take(field_bytes);
     const size_t o_state = w.take(sizeof(PairState) * nb);
-    const size_t o_partial = w.take(sizeof(float) * 2 * (size_t)nb * max_tiles);
+    const size_t o_partial = w.take(sizeof(float) * 4 * (size_t)nb * max_tiles);
     const size_t o_iters = w.take(sizeof(int32_t) * (size_t)nb * L);
     const size_t o_q1 = w.take(sizeof(float) * 2 * (size_t)nb * nr);
     const size_t o_q2 = w.take(sizeof(float) * 2 * (size_t)nb * nr);
@@ -500,6 +521,24 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
                 }
             }
             h->strip_ty[std::make_pair(lh, lw)] = best_ty;
+            // two iterations per launch: 3 launches (6 iterations) against the best 6 single launches
+            int best_fty = 0;
+            for (int fty : {32, 64, 128}) {
+                EBSD_TRY(launch_demons_iter2(d_bk, b, l, 0, h->taps, h->radius, 0.0f, 1 << 20, fty, s));
+                EBSD_TRY(hipEventRecord(e0, s));
+                for (int L2 = 1; L2 <= 3; L2++)
+                    EBSD_TRY(launch_demons_iter2(d_bk, b, l, L2, h->taps, h->radius, 0.0f, 1 << 20, fty, s));
+                EBSD_TRY(hipEventRecord(e1, s));
+                EBSD_TRY(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                EBSD_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    best_fty = fty;
+                }
+            }
+            if (best_fty) h->fused_ty[std::make_pair(lh, lw)] = best_fty;
+            else h->fused_ty.erase(std::make_pair(lh, lw));
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -509,16 +548,25 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     // static sequence for a given configuration: captured once into a graph
     // and replayed; the few other launches and the timing events stay on the
     // stream.
-    auto level_iters = [&](int l, int ty, hipStream_t st) -> int {
-        for (int it = 0; it < p.max_iters[l]; it++)
+    // fty > 0: two iterations per launch (ceil(cap / 2) launches, plus the
+    // decision-only launch that follows an even cap when a tolerance is set)
+    auto level_iters = [&](int l, int ty, int fty, hipStream_t st) -> int {
+        const int cap = p.max_iters[l];
+        if (fty) {
+            const int nl = (cap + 1) / 2 + ((p.tol_px > 0.0f && cap > 0 && cap % 2 == 0) ? 1 : 0);
+            for (int L2 = 0; L2 < nl; L2++)
+                EBSD_TRY(launch_demons_iter2(d_bk, b, l, L2, h->taps, h->radius, p.tol_px, cap, fty, st));
+            return EBSD_OK;
+        }
+        for (int it = 0; it < cap; it++)
             EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, p.tol_px, ty, st));
         return EBSD_OK;
     };
-    auto run_level = [&](int l, int ty) -> int {
+    auto run_level = [&](int l, int ty, int fty) -> int {
         if (h->graphs && p.max_iters[l] > 0) {
             std::ostringstream key;
             key << H << ' ' << W << ' ' << nb << ' ' << nref << ' ' << l << ' ' << p.max_iters[l]
-                << ' ' << p.tol_px << ' ' << h->radius << ' ' << ty << ' ' << (void*)base;
+                << ' ' << p.tol_px << ' ' << h->radius << ' ' << ty << ' ' << fty << ' ' << (void*)base;
             auto it = h->graph_cache.find(key.str());
             hipGraphExec_t exec = nullptr;
             if (it != h->graph_cache.end()) {
@@ -530,7 +578,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
                 hipGraph_t graph = nullptr;
                 if (h->cap_stream &&
                     hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
-                    const int e = level_iters(l, ty, h->cap_stream);
+                    const int e = level_iters(l, ty, fty, h->cap_stream);
                     const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
                     if (e == EBSD_OK && ec == hipSuccess && graph &&
                         hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
@@ -545,7 +593,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
                 return EBSD_OK;
             }
         }
-        return level_iters(l, ty, s);
+        return level_iters(l, ty, fty, s);
     };
     if (warm) {
         // network field at the coarse grid, chunk by chunk, then the Eq. (2)
@@ -568,11 +616,12 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         EBSD_TRY(launch_demons_init(d_bk, b, s));
         for (int l = L - 1; l >= 0; l--) {
             const int ty = strip_ty_for(h, H >> l, W >> l);
+            const int fty = fused_ty_for(h, H >> l, W >> l);
             if (tm) EBSD_TRY(hipEventRecord(h->ev[2 + 2 * l], s));
-            const int e = run_level(l, ty);
+            const int e = run_level(l, ty, fty);
             if (e) return e;
             if (tm) EBSD_TRY(hipEventRecord(h->ev[3 + 2 * l], s));
-            EBSD_TRY(launch_level_end(d_bk, b, l, p.max_iters[l], p.tol_px, ty, s));
+            EBSD_TRY(launch_level_end(d_bk, b, l, p.max_iters[l], p.tol_px, fty ? fty : ty, fty != 0, s));
             if (l > 0) EBSD_TRY(launch_prolong_level(d_bk, b, l, s));
         }
         EBSD_TRY(launch_sample_q1(d_bk, b, s));
@@ -754,6 +803,22 @@ int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int3
 {
     if (!h || level_h <= 0 || level_w <= 0 || !rows_ty_supported(ty)) return EBSD_EINVAL;
     h->strip_ty[std::make_pair((int)level_h, (int)level_w)] = ty;
+    return EBSD_OK;
+}
+
+int ebsd_get_fused_height(const ebsd_handle* h, int32_t level_h, int32_t level_w)
+{
+    if (!h || level_h <= 0 || level_w <= 0) return EBSD_EINVAL;
+    return fused_ty_for(h, level_h, level_w);
+}
+
+int ebsd_set_fused_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t rows)
+{
+    if (!h || level_h <= 0 || level_w <= 0) return EBSD_EINVAL;
+    if (rows != 0 && (!rows2_ty_supported(rows) || !rows_cpl(level_w))) return EBSD_EINVAL;
+    const auto key = std::make_pair((int)level_h, (int)level_w);
+    if (rows) h->fused_ty[key] = rows;
+    else h->fused_ty.erase(key);
     return EBSD_OK;
 }
 

@@ -111,9 +111,13 @@ hipError_t launch_demons_init(const Bucket* d_bk, const Bucket& hb, hipStream_t 
 // strip height of the row-marching kernel.
 hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, int k,
                               const float* taps, int radius, float tol, int ty, hipStream_t s);
+// Launch L of level l run two iterations at a time (strip height ty of the
+// fused row-marching kernel; cap = the level's iteration cap).
+hipError_t launch_demons_iter2(const Bucket* d_bk, const Bucket& hb, int level, int L, const float* taps,
+                               int radius, float tol, int cap, int ty, hipStream_t s);
 // Close level l: iteration counts, convergence of the last iteration, final buffer.
 hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int cap, float tol,
-                            int ty, hipStream_t s);
+                            int ty, bool fused, hipStream_t s);
 // Prolong the field of every pair from level l to level l-1 and re-arm the pairs.
 hipError_t launch_prolong_level(const Bucket* d_bk, const Bucket& hb, int level, hipStream_t s);
 // Sample the finest field at the ROI centres -> q1.
@@ -161,6 +165,12 @@ inline int demons_tiles(int h, int w)
 // (false if not applicable).
 int rows_cpl(int w);
 bool rows_ty_supported(int ty);
+// Two iterations per launch (temporal blocking) at strip heights 32, 64, 128:
+// launch L of a level runs iterations 2L and 2L + 1 (see k_demons_rows2);
+// ceil(cap / 2) launches, plus one more when tol > 0 and cap is even.
+bool rows2_ty_supported(int ty);
+bool launch_demons_rows2(const Bucket* d_bk, const Bucket& hb, int level, int L, const Taps& tp, int radius,
+                         float tol, int cap, int ty, hipStream_t s);
 int rows_units(int h, int ty);
 bool launch_demons_rows(const Bucket* d_bk, const Bucket& hb, int level, int k, const Taps& tp,
                         int radius, float tol, int ty, hipStream_t s);

@@ -178,7 +178,9 @@ __global__ void __launch_bounds__(NT)
 
 // End of level l, one thread per pair: iteration count, convergence on the
 // last iteration (the in-loop check sees iteration k - 1 only), final buffer.
-__global__ void k_level_end(const Bucket* __restrict__ bk, int level, int cap, float tol, int ntiles)
+// fused != 0: the level ran two iterations per launch (partial slot i & 3,
+// final field after n iterations in buffer (base + ceil(n / 2)) & 1).
+__global__ void k_level_end(const Bucket* __restrict__ bk, int level, int cap, float tol, int ntiles, int fused)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= bk->nb) return;
@@ -186,7 +188,8 @@ __global__ void k_level_end(const Bucket* __restrict__ bk, int level, int cap, f
     int n = st.stop >= 0 ? st.stop : cap;
     if (st.stop < 0 && tol > 0.0f && cap > 0) {
         const int64_t npart = (int64_t)bk->nb * bk->max_tiles;
-        const float* last = bk->partial + ((cap - 1) & 1) * npart + (int64_t)b * bk->max_tiles;
+        const int slot = fused ? ((cap - 1) & 3) : ((cap - 1) & 1);
+        const float* last = bk->partial + slot * npart + (int64_t)b * bk->max_tiles;
         // same fixed order as pair_sum: 64 strided lanes, then the xor tree
         double lane[64];
         for (int l = 0; l < 64; l++) {
@@ -205,7 +208,7 @@ __global__ void k_level_end(const Bucket* __restrict__ bk, int level, int cap, f
         if (delta < (double)tol) st.convmask |= 1u << level;
     }
     bk->iters[(int64_t)b * bk->L + level] = n;
-    st.cur = (st.base + n) & 1;
+    st.cur = fused ? (st.base + (n + 1) / 2) & 1 : (st.base + n) & 1;
     st.stop = -1;
     bk->state[b] = st;
 }
@@ -253,6 +256,14 @@ void launch_iter_rad(const Bucket* d_bk, const Bucket& hb, int level, int k, con
 
 }  // namespace
 
+hipError_t launch_demons_iter2(const Bucket* d_bk, const Bucket& hb, int level, int L, const float* taps,
+                               int radius, float tol, int cap, int ty, hipStream_t s)
+{
+    const Taps tp = make_taps(taps, radius);
+    if (!launch_demons_rows2(d_bk, hb, level, L, tp, radius, tol, cap, ty, s)) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, int k,
                               const float* taps, int radius, float tol, int ty, hipStream_t s)
 {
@@ -270,11 +281,11 @@ hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, i
 }
 
 hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int cap, float tol,
-                            int ty, hipStream_t s)
+                            int ty, bool fused, hipStream_t s)
 {
     const int ntiles = demons_units(hb.H >> level, hb.W >> level, ty);
     hipLaunchKernelGGL(k_level_end, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, level, cap, tol,
-                       ntiles);
+                       ntiles, fused ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -97,7 +97,7 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_cnn_get_params", "ebsd_cnn_get_grads", "ebsd_cnn_load", "ebsd_cnn_save",
             "ebsd_cnn_forward", "ebsd_cnn_train_step", "ebsd_cnn_reset_optimizer",
             "ebsd_load_model", "ebsd_set_model", "ebsd_stage_conv3x3", "ebsd_stage_conv3x3_dgrad",
-            "ebsd_stage_conv3x3_wgrad", "ebsd_gen_pairs"]
+            "ebsd_stage_conv3x3_wgrad", "ebsd_gen_pairs", "ebsd_get_fused_height", "ebsd_set_fused_height"]
 
 
 def lib():
@@ -124,6 +124,8 @@ def lib():
         L.ebsd_set_graphs.argtypes = [vp, C.c_int]
         L.ebsd_get_strip_height.argtypes = [vp, i32, i32]
         L.ebsd_set_strip_height.argtypes = [vp, i32, i32, i32]
+        L.ebsd_get_fused_height.argtypes = [vp, i32, i32]
+        L.ebsd_set_fused_height.argtypes = [vp, i32, i32, i32]
         L.ebsd_set_timing.argtypes = [vp, C.c_int]
         L.ebsd_get_timing.argtypes = [vp, vp, vp]
         L.ebsd_stage_normalize.argtypes = [vp, i32, i64, vp, vp, vp]
@@ -372,6 +374,15 @@ class Registrar:
 
     def set_strip_height(self, level_h, level_w, rows):
         _check(lib().ebsd_set_strip_height(self._h, level_h, level_w, rows), "ebsd_set_strip_height")
+
+    def set_fused_height(self, level_h, level_w, rows):
+        """Two iterations per launch at this strip height (0 = one per launch)."""
+        _check(lib().ebsd_set_fused_height(self._h, level_h, level_w, rows), "ebsd_set_fused_height")
+
+    def fused_heights(self, H, W):
+        """{(h, w): fused strip height or 0} for the levels of an H x W pattern."""
+        return {(H >> l, W >> l): lib().ebsd_get_fused_height(self._h, H >> l, W >> l)
+                for l in range(self.params.levels)}
 
     def set_timing(self, on=True):
         _check(lib().ebsd_set_timing(self._h, int(bool(on))), "ebsd_set_timing")
