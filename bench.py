@@ -157,13 +157,13 @@ def main():
     level_ms = warm["level_ms"]
     demons_bytes = float(BYTES_PER_PX_ITER * px_iters.sum())
     demons_ms = float(level_ms.sum())
+    rows0 = warm["tuned"].get((H, W), 0)
+    frows0 = warm["fused"].get((H, W), 0)
     iters0 = int(warm["iters"][:, 0].max())
     launches0 = (iters0 + 1) // 2 if frows0 else iters0
     alg_per_launch0 = BYTES_PER_PX_ITER * px_iters[0] / max(launches0, 1)
     launch0_ms = float(level_ms[0]) / max(launches0, 1)
     achieved = alg_per_launch0 / (launch0_ms * 1e-3) / 1e9
-    rows0 = warm["tuned"].get((H, W), 0)
-    frows0 = warm["fused"].get((H, W), 0)
 
     traffic = None
     if os.path.exists(args.traffic_json):
