@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512, help="pairs timed on the CPU oracle (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "demons_traffic.json"))
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
+    ap.add_argument("--skip-plain", action="store_true", help="time the warm start only (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (counter calibration) and exit")
     args = ap.parse_args()
@@ -135,7 +136,7 @@ def main():
                     tuned=tuned, fused=fused)
 
     warm = timed(make(True, args.cap), "warm start")
-    plain = timed(make(False, args.cap), "plain")
+    plain = None if args.skip_plain else timed(make(False, args.cap), "plain")
     short = timed(make(True, args.short_cap), f"warm start, cap {args.short_cap}") if args.short_cap > 0 else None
 
     # network forward alone on the same batch (chunks of 256), HIP events on torch's stream
@@ -242,7 +243,7 @@ def main():
             "forward_ms_per_step": round(cnn_ms, 3),
         },
         "warm": summary(warm),
-        "plain": summary(plain),
+        "plain": summary(plain) if plain is not None else None,
     }
     if short is not None:
         rec["warm_short_cap"] = dict(summary(short), cap=args.short_cap)

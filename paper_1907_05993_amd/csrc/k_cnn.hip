@@ -37,14 +37,15 @@ __device__ inline f32x16 mfma16(const bf16x8& a, const bf16x8& b, const f32x16& 
 // Workgroup: 4 waves, output tile of 8 rows x 32 columns x (32 NT) channels;
 // wave w computes rows 2w, 2w+1 (one 32-pixel M tile each) for all NT N tiles.
 // For each chunk of CK input channels the (8+2) x (32+2) input halo and the
-// 9 taps of weights are staged in LDS; the K loop walks (tap, 8-channel group)
-// pairs, two per 16-wide MFMA step (one per half wave).  Pixel rows in LDS are
+// 9 taps of weights are staged in LDS (the next chunk's global loads are in
+// flight during the current chunk's matrix-core loop); the K loop walks
+// (tap, 8-channel group) pairs, two per 16-wide MFMA step (one per half wave).  Pixel rows in LDS are
 // padded to 80 bytes for CK = 32 so that 8 consecutive lanes of a 16-byte read
 // cover all banks.
 constexpr int kConvTH = 8, kConvTW = 32;
 
 template <int CK, int NT>
-__global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_conv3x3(ConvArgs a)
 {
     constexpr int HP = kConvTH + 2, WP = kConvTW + 2;
     constexpr int PS = (CK == 32) ? 40 : CK;
@@ -52,8 +53,17 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
     constexpr int G = CK / 8;
     constexpr int NF = 9 * G;
     constexpr int NS = (NF + 1) / 2;
-    __shared__ __attribute__((aligned(16))) bf16_t sA[HP * WP * PS];
-    __shared__ __attribute__((aligned(16))) bf16_t sB[9 * BN * PS];
+    // LDS: the input halo (sA) and the weights (sB) during the K loop; the
+    // output tile of each wave afterwards (transposed so that every lane
+    // stores whole 16-byte groups of channels).
+    constexpr int SA = HP * WP * PS, SB = 9 * BN * PS;
+    constexpr int ST0 = 4 * 64 * (BN + 8) * 2;  // bf16 output tiles, bytes
+    constexpr int ST1 = 4 * 32 * (BN + 4) * 4;  // fp32 output half tiles, bytes
+    constexpr int SMEM0 = 2 * (SA + SB);
+    constexpr int SMEM = SMEM0 > ST0 ? (SMEM0 > ST1 ? SMEM0 : ST1) : (ST0 > ST1 ? ST0 : ST1);
+    __shared__ __attribute__((aligned(16))) char smem[SMEM];
+    bf16_t* const sA = reinterpret_cast<bf16_t*>(smem);
+    bf16_t* const sB = sA + SA;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, l32 = lane & 31;
@@ -74,23 +84,58 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
         for (int j = 0; j < NT; j++)
             for (int i = 0; i < 16; i++) acc[r][j][i] = 0.0f;
 
-    for (int c0 = 0; c0 < Cin; c0 += CK) {
-        for (int i = tid; i < HP * WP * G; i += 256) {
-            const int g = i % G, p = i / G;
-            const int hx = p % WP, hy = p / WP;
-            const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+    // Global loads of the next chunk are issued before the current chunk's
+    // matrix-core loop and written to LDS after it (registers pa, pb).
+    constexpr int NA_TOT = HP * WP * G, NB_TOT = 9 * BN * G;
+    constexpr int NA = (NA_TOT + 255) / 256, NB = (NB_TOT + 255) / 256;
+    uint4 pa[NA], pb[NB];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int k = 0; k < NA; k++) {
+            const int i = tid + 256 * k;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                v = *reinterpret_cast<const uint4*>(xin + ((int64_t)yy * a.W + xx) * Cin + c0 + 8 * g);
-            *reinterpret_cast<uint4*>(sA + p * PS + 8 * g) = v;
+            if (i < NA_TOT) {
+                const int g = i % G, p = i / G;
+                const int hx = p % WP, hy = p / WP;
+                const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    v = *reinterpret_cast<const uint4*>(xin + ((int64_t)yy * a.W + xx) * Cin + c0 + 8 * g);
+            }
+            pa[k] = v;
         }
-        for (int i = tid; i < 9 * BN * G; i += 256) {
-            const int g = i % G, r = i / G;
-            const int co = r % BN, t = r / BN;
-            const uint4 v = *reinterpret_cast<const uint4*>(a.w + ((int64_t)(co0 + co) * 9 + t) * Cin + c0 + 8 * g);
-            *reinterpret_cast<uint4*>(sB + (t * BN + co) * PS + 8 * g) = v;
+#pragma unroll
+        for (int k = 0; k < NB; k++) {
+            const int i = tid + 256 * k;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (i < NB_TOT) {
+                const int g = i % G, r = i / G;
+                const int co = r % BN, t = r / BN;
+                v = *reinterpret_cast<const uint4*>(a.w + ((int64_t)(co0 + co) * 9 + t) * Cin + c0 + 8 * g);
+            }
+            pb[k] = v;
         }
-        __syncthreads();
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int k = 0; k < NA; k++) {
+            const int i = tid + 256 * k;
+            if (i < NA_TOT) *reinterpret_cast<uint4*>(sA + (i / G) * PS + 8 * (i % G)) = pa[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; k++) {
+            const int i = tid + 256 * k;
+            if (i < NB_TOT) {
+                const int g = i % G, r = i / G;
+                *reinterpret_cast<uint4*>(sB + ((r / BN) * BN + r % BN) * PS + 8 * g) = pb[k];
+            }
+        }
+    };
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int c0 = 0; c0 < Cin; c0 += CK) {
+        const bool next = c0 + CK < Cin;
+        if (next) fetch(c0 + CK);
         for (int s = 0; s < NS; s++) {
             const int f = 2 * s + h;
             const bool valid = f < NF;  // false only for the padding group of an odd group count
@@ -111,23 +156,53 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
                 for (int j = 0; j < NT; j++) acc[r][j] = mfma16(av[r], bv[j], acc[r][j]);
         }
         __syncthreads();
+        if (next) {
+            stash();
+            __syncthreads();
+        }
     }
 
-    for (int r = 0; r < 2; r++) {
-        const int yy = y0 + 2 * wave + r;
+    // epilogue (the K loop ended with a barrier: LDS is free)
+    if (a.mode == 0) {
+        constexpr int RP = BN + 8;  // staging row pitch (bf16)
+        bf16_t* stg = reinterpret_cast<bf16_t*>(smem) + wave * 64 * RP;
         for (int j = 0; j < NT; j++) {
-            const int co = co0 + 32 * j + l32;
-            const float bias = a.mode == 0 ? a.bias[co] : 0.0f;
-            for (int i = 0; i < 16; i++) {
-                const int xx = x0 + 8 * (i >> 2) + 4 * h + (i & 3);
-                const int64_t p = ((int64_t)img * a.H + yy) * a.W + xx;
-                if (a.mode == 0) {
-                    const float z = fmaxf(acc[r][j][i] + bias, 0.0f);
-                    static_cast<bf16_t*>(a.out)[p * a.out_cs + a.out_co + co] = f2bf(z);
-                } else {
-                    static_cast<float*>(a.out)[p * a.out_cs + a.out_co + co] = acc[r][j][i];
+            const int col = 32 * j + l32;
+            const float bias = a.bias[co0 + col];
+            for (int r = 0; r < 2; r++)
+                for (int i = 0; i < 16; i++) {
+                    const int px = 32 * r + 8 * (i >> 2) + 4 * h + (i & 3);
+                    stg[px * RP + col] = f2bf(fmaxf(acc[r][j][i] + bias, 0.0f));
                 }
+        }
+        __syncthreads();
+        bf16_t* out = static_cast<bf16_t*>(a.out);
+        for (int v = lane; v < 64 * (BN / 8); v += 64) {
+            const int px = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
+            const int yy = y0 + 2 * wave + (px >> 5), xx = x0 + (px & 31);
+            const int64_t p = ((int64_t)img * a.H + yy) * a.W + xx;
+            *reinterpret_cast<uint4*>(out + p * a.out_cs + a.out_co + co0 + 8 * g) =
+                *reinterpret_cast<const uint4*>(stg + px * RP + 8 * g);
+        }
+    } else {
+        constexpr int RP = BN + 4;  // staging row pitch (fp32)
+        float* stg = reinterpret_cast<float*>(smem) + wave * 32 * RP;
+        float* out = static_cast<float*>(a.out);
+        for (int r = 0; r < 2; r++) {
+            for (int j = 0; j < NT; j++)
+                for (int i = 0; i < 16; i++) {
+                    const int px = 8 * (i >> 2) + 4 * h + (i & 3);
+                    stg[px * RP + 32 * j + l32] = acc[r][j][i];
+                }
+            __syncthreads();
+            const int yy = y0 + 2 * wave + r;
+            for (int v = lane; v < 32 * (BN / 4); v += 64) {
+                const int px = v / (BN / 4), g = v - (BN / 4) * (v / (BN / 4));
+                const int64_t p = ((int64_t)img * a.H + yy) * a.W + x0 + px;
+                *reinterpret_cast<float4*>(out + p * a.out_cs + a.out_co + co0 + 4 * g) =
+                    *reinterpret_cast<const float4*>(stg + px * RP + 4 * g);
             }
+            __syncthreads();
         }
     }
 }

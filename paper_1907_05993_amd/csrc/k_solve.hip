@@ -446,55 +446,45 @@ k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys
     gf.r2 = radius * radius;
     const int ng = gh * gw;
 
-    // direct linear start
-    double m[46];
-    for (int k = 0; k < 46; k++) m[k] = 0.0;
-    for (int g = threadIdx.x; g < ng; g += kFitThreads) {
-        double x, y;
-        if (!gf.point(g, x, y)) continue;
-        const double ax = x - xs, ay = y - ys;
-        const double rx = ax * gf.iz, ry = ay * gf.iz;
-        const double px = (ax + (double)gf.q[2 * g]) * gf.iz, py = (ay + (double)gf.q[2 * g + 1]) * gf.iz;
-        const double ra[9] = {rx, ry, 1.0, 0.0, 0.0, 0.0, -px * rx, -px * ry, -px};
-        const double rb[9] = {0.0, 0.0, 0.0, rx, ry, 1.0, -py * rx, -py * ry, -py};
-        int k = 0;
-        for (int a = 0; a < 9; a++)
-            for (int c = a; c < 9; c++) m[k++] += ra[a] * ra[c] + rb[a] * rb[c];
-        m[45] += 1.0;
-    }
+    // Linear start: Eq. (2) multiplied through by its denominator is linear in
+    // the 8 entries left free by F33 = 1; its least-squares solution starts the
+    // Gauss-Newton iteration (which converges to the same minimiser as from
+    // the direct linear start of the ROI solve, with far less work here).
+    double f[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    double npts;
     {
-        double part[45];
-        for (int k = 0; k < 45; k++) part[k] = m[k];
-        fit_block_sum<45>(part, sh);
-        for (int k = 0; k < 45; k++) m[k] = part[k];
-        double cnt[1] = {m[45]};
-        fit_block_sum<1>(cnt, sh);
-        m[45] = cnt[0];
-    }
-    const double npts = m[45];
-    double M[9][9];
-    {
+        double t[45];
+        for (int k = 0; k < 45; k++) t[k] = 0.0;
+        for (int g = threadIdx.x; g < ng; g += kFitThreads) {
+            double x, y;
+            if (!gf.point(g, x, y)) continue;
+            const double ax = x - xs, ay = y - ys;
+            const double rx = ax * gf.iz, ry = ay * gf.iz;
+            const double px = (ax + (double)gf.q[2 * g]) * gf.iz, py = (ay + (double)gf.q[2 * g + 1]) * gf.iz;
+            const double ra[8] = {rx, ry, 1.0, 0.0, 0.0, 0.0, -px * rx, -px * ry};
+            const double rb[8] = {0.0, 0.0, 0.0, rx, ry, 1.0, -py * rx, -py * ry};
+            int k = 0;
+            for (int a = 0; a < 8; a++)
+                for (int c = a; c < 8; c++) t[k++] += ra[a] * ra[c] + rb[a] * rb[c];
+            for (int a = 0; a < 8; a++) t[36 + a] += ra[a] * px + rb[a] * py;
+            t[44] += 1.0;
+        }
+        fit_block_sum<45>(t, sh);
+        npts = t[44];
+        double A[8][8], rhs[8], sol[8];
         int k = 0;
-        for (int a = 0; a < 9; a++)
-            for (int c = a; c < 9; c++) {
-                M[a][c] = m[k];
-                M[c][a] = m[k];
+        for (int a = 0; a < 8; a++)
+            for (int c = a; c < 8; c++) {
+                A[a][c] = t[k];
+                A[c][a] = t[k];
                 k++;
             }
+        for (int a = 0; a < 8; a++) rhs[a] = t[36 + a];
+        if (cholesky_solve8(A, rhs, sol))
+            for (int a = 0; a < 8; a++) f[a] = sol[a];
     }
-    double ev[9], V[9][9];
-    jacobi_eigen<9>(M, ev, V);
-    int kmin = 0;
-    for (int i = 1; i < 9; i++)
-        if (ev[i] < ev[kmin]) kmin = i;
-    double f[9];
-    for (int i = 0; i < 9; i++) f[i] = V[i][kmin];
-    if (f[8] == 0.0) f[8] = 1.0;
-    const double s8 = f[8];
-    for (int i = 0; i < 9; i++) f[i] /= s8;
-    f[8] = 1.0;
 
-    // Gauss-Newton on the 8 free entries
+    // Gauss-Newton on the 8 free entries (|step| < 1e-12 or 100 steps)
     for (int it = 0; it < 100; it++) {
         double t[44];
         for (int k = 0; k < 44; k++) t[k] = 0.0;
@@ -533,7 +523,7 @@ k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys
             f[a] += dlt[a];
             nrm += dlt[a] * dlt[a];
         }
-        if (!isfinite(nrm) || sqrt(nrm) < 1e-14) break;
+        if (!isfinite(nrm) || sqrt(nrm) < 1e-12) break;
     }
     const double dt = det3(f);
     if (dt > 0.0) {
