@@ -265,6 +265,66 @@ def render_batch(specs, workers=None):
     return refs, tests
 
 
+# -- scan maps --------------------------------------------------------------------
+
+def scan_map(config_id=3, size=64, grains=12, max_deg=10.0):
+    """Seeded Voronoi scan map for the scan workload.
+
+    Grain seeds are uniform in [0, size)^2; a scan point belongs to the nearest
+    seed (ties to the lower index).  Each grain has a uniform SO(3) orientation,
+    a background gradient, and a linear intragranular rotation field
+    w(p) = K_g (p - seed_g) (rotation vector, rad) with K_g Gaussian 3 x 2,
+    scaled so that the largest |w| over the grain's points is theta_g, uniform
+    in (0, max_deg] degrees."""
+    rng = np.random.default_rng(np.random.SeedSequence([config_id, 0, 100]))
+    seeds = rng.uniform(0.0, size, size=(grains, 2))
+    ys, xs = np.mgrid[0:size, 0:size]
+    pts = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.float64)
+    gid = np.argmin(((pts[:, None, :] - seeds[None]) ** 2).sum(-1), axis=1)
+    G, K, theta, gxy = [], [], [], []
+    for g in range(grains):
+        rg = np.random.default_rng(np.random.SeedSequence([config_id, g, 101]))
+        G.append(random_rotation(rg))
+        k = rg.normal(size=(3, 2))
+        th = math.radians(rg.uniform(0.0, max_deg)) or math.radians(max_deg)
+        d = pts[gid == g] - seeds[g]
+        mx = np.linalg.norm(d @ k.T, axis=1).max() if d.size else 1.0
+        K.append(k * (th / mx) if mx > 0 else k)
+        theta.append(th)
+        gxy.append(tuple(rg.uniform(-1.0, 1.0, size=2)))
+    return dict(size=size, seeds=seeds, gid=gid.reshape(size, size), G=G, K=K, theta=theta, gxy=gxy)
+
+
+def scan_specs(H, W, indices, config_id=3, counts=1e4, noise=True, smap=None):
+    """PairSpecs of scan points (index = y * size + x) and the reference spec of
+    each grain they use.  Returns (tests, refs, ref_ids): the test of point p
+    is the grain's orientation under F = R(w(p)); refs[g] renders the grain's
+    reference pattern (noise seeded per grain, so every point of a grain shares
+    one reference); ref_ids[i] is the grain of point i."""
+    m = smap or scan_map(config_id)
+    size = m["size"]
+    tests, ref_ids = [], []
+    for idx in indices:
+        x, y = idx % size, idx // size
+        g = int(m["gid"][y, x])
+        w = m["K"][g] @ (np.array([x, y], np.float64) - m["seeds"][g])
+        ang = float(np.linalg.norm(w))
+        F = axis_angle_matrix(w / ang, ang) if ang > 0 else np.eye(3)
+        tests.append(PairSpec(H=H, W=W, G=m["G"][g], F=F, gxy=m["gxy"][g], counts=counts, noise=noise,
+                              seeds=(config_id, int(idx)), extra={"grain": g, "rotvec": w}))
+        ref_ids.append(g)
+    refs = {g: PairSpec(H=H, W=W, G=m["G"][g], F=np.eye(3), gxy=m["gxy"][g], counts=counts, noise=noise,
+                        seeds=(config_id, 1000000 + g)) for g in sorted(set(ref_ids))}
+    return tests, refs, ref_ids
+
+
+def render_scan(tests, refs, ref_ids):
+    """(ref patterns per grain {g: [H, W]}, test patterns [n, H, W]) for scan_specs output."""
+    ref_img = {g: render_pair(s)[0] for g, s in refs.items()}
+    _, test_img = render_batch(tests)
+    return ref_img, test_img
+
+
 # -- workloads ------------------------------------------------------------------
 
 WORKLOADS = {
@@ -277,6 +337,10 @@ WORKLOADS = {
     # the headline: 1024 pairs at 256^2, misorientation exactly 10 deg
     "batch_256_10deg": dict(config_id=6, n=1024, H=256, W=256, exact_angle=10.0, strain=2e-3,
                             iters=150, roi=64),
+    # scan map: 64 x 64 points at 400^2, 12 Voronoi grains with one reference each,
+    # intragranular rotation up to 10 deg, per-pair stop at 1e-4 px, ROIs of 128^2
+    # (patterns from scan_specs / render_scan)
+    "scan_400": dict(config_id=3, n=4096, H=400, W=400, strain=0.0, iters=150, roi=128, tol=1e-4),
 }
 
 
