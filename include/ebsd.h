@@ -87,8 +87,8 @@ typedef struct ebsd_params {
     double roi_radius_frac;               /* ring radius / W */
     int32_t window;                       /* 1 = Hann window on each ROI (section 2), 0 = none */
     int32_t second_pass;                  /* 1 = remap + XCF second pass (Eq. (12)); 0 = demons only */
-    int32_t warm_start;                   /* 256 x 256, 3 levels: 1 = start demons from the network's field,
-                                             2 = from the Eq. (2) field fitted to it; 0 = from zero */
+    int32_t warm_start;                   /* square 128, 256 or 512 px, 3 levels: 1 = start demons from the
+                                             network's field, 2 = from the Eq. (2) field fitted to it; 0 = zero */
     float fallback_residual_px;           /* warm start: largest RMS misfit of the Eq. (2) fit, in px of the
                                              coarsest level (the grid the field initialises) */
 } ebsd_params;
@@ -117,8 +117,8 @@ typedef struct ebsd_outputs {
     float* peak_height;         /* [n][n_roi] normalised XCF peak height */
     int32_t* iters;             /* [n][levels] demons iterations run per level */
     uint32_t* status;           /* [n] status bits */
-    float* warm_field;          /* [n][H/4][W/4][2] network field at the coarse grid, full-res px (warm start) */
-    float* warm_misfit;         /* [n] RMS misfit of the Eq. (2) fit to warm_field, full-res px (warm start) */
+    float* warm_field;          /* [n][64][64][2] network output (warm start), px of the 256 x 256 image it saw */
+    float* warm_misfit;         /* [n] RMS misfit of the Eq. (2) fit to warm_field, in the same px */
 } ebsd_outputs;
 
 /* Library ABI version (EBSD_ABI_VERSION). */
@@ -258,6 +258,12 @@ int ebsd_get_timing(ebsd_handle* h, double* level_ms, double* total_ms);
  * weights [3][3][cin][cout] then its bias [cout]; then the head weights
  * [128][2] and bias [2].  Files written by ebsd_cnn_save hold the 8 bytes
  * "EBSDCNN1", an int64 count and the vector (little-endian).
+ *
+ * Patterns of 512 x 512 reach the network as their pyramid level 1, patterns
+ * of 128 x 128 as their level 0 upsampled x2 (bilinear); the fit below works
+ * in the 256 x 256 frame (Eq. (2) is unchanged by a common scaling of the
+ * detector coordinates), and the starting field is evaluated on, or resampled
+ * to, the pattern's own coarse grid.
  *
  * Fallback rule (warm start inside ebsd_register_batch): the Eq. (2) model is
  * fitted (Eq. (3): direct linear start, Gauss-Newton, det F = 1) to the

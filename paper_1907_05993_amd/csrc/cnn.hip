@@ -333,13 +333,15 @@ bool cnn_ready(const ebsd_cnn* c) { return c && c->have_params; }
 // Pack n <= max_batch normalised pairs (see launch_pack_input) and run the
 // forward pass into out [n][64][64][2].
 int cnn_forward_from(ebsd_cnn* c, const float* ref_base, int64_t ref_stride, const int32_t* ref_slot,
-                     const float* test_base, int64_t test_stride, int n, float* out, hipStream_t s)
+                     const float* test_base, int64_t test_stride, int n, int up2, float* out, hipStream_t s)
 {
     DevGuard g(c->device);
     if (!g.ok) return EBSD_EDEVICE;
-    if (launch_pack_input(ref_base, ref_stride, ref_slot, test_base, test_stride, n, kRes, kRes, c->x0, s) !=
-        hipSuccess)
-        return EBSD_EDEVICE;
+    const hipError_t e = up2 ? launch_pack_input_up2(ref_base, ref_stride, ref_slot, test_base, test_stride, n,
+                                                     kRes / 2, kRes / 2, c->x0, s)
+                             : launch_pack_input(ref_base, ref_stride, ref_slot, test_base, test_stride, n, kRes,
+                                                 kRes, c->x0, s);
+    if (e != hipSuccess) return EBSD_EDEVICE;
     return forward(c, n, kRes, kRes, out, s) == hipSuccess ? EBSD_OK : EBSD_EDEVICE;
 }
 

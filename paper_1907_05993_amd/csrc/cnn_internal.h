@@ -54,6 +54,11 @@ hipError_t launch_colsum(const float* part, int64_t nb, int64_t ncols, float* ou
 hipError_t launch_pack_input(const float* ref_base, int64_t ref_stride, const int32_t* ref_slot,
                              const float* test_base, int64_t test_stride, int n, int H, int W,
                              bf16_t* x, hipStream_t s);
+// Same from h x w images upsampled x2 to 2h x 2w (bilinear, clamped, source
+// coordinate (i - 0.5) / 2).
+hipError_t launch_pack_input_up2(const float* ref_base, int64_t ref_stride, const int32_t* ref_slot,
+                                 const float* test_base, int64_t test_stride, int n, int h, int w,
+                                 bf16_t* x, hipStream_t s);
 // 2x2 max pooling of bf16 [n][H][W][cs] (channels [co, co + C)) -> [n][H/2][W/2][C].
 hipError_t launch_maxpool(const bf16_t* in, int n, int H, int W, int C, int cs, int co, bf16_t* out,
                           hipStream_t s);
@@ -93,22 +98,27 @@ hipError_t launch_pack_weights(const float* w, int cin, int cin_pad, int cout, b
 // Adam (fp32): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr mhat / (sqrt(vhat) + eps).
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, float bc1, float bc2, hipStream_t s);
-// Warm-start fallback: fit the Eq. (2) model to each predicted field at the
-// coarse grid points within `radius` px of the pattern centre (FP64 Eq. (3)
-// solve); use = misfit / 4 <= threshold (coarse-grid px); u_init [n][2][H/4][W/4] (full-res px) =
-// 0 if not use, else the predicted field (model_field = 0) or the fitted
-// model's field (model_field = 1); misfit[i] = RMS endpoint misfit (full-res
-// px), flag[i] = use ? 4 : 8.
-hipError_t launch_warm_fit(const float* field, int n, int H, int W, double xs, double ys, double zs,
-                           double radius, double threshold, int model_field, float* u_init, float* misfit,
-                           uint32_t* flag, hipStream_t s);
+// Warm-start fallback: fit the Eq. (2) model to each predicted field (net_res
+// / 4 square grid, px of the net_res x net_res image; geometry xs, ys, zs) at
+// the grid points within `radius` px of the pattern centre (FP64 Eq. (3)
+// solve); use = misfit / 4 <= threshold (px of that grid).  u_init
+// [n][2][N/4][N/4] (px of the N x N pattern, geometry xsN, ysN, zsN) = 0 if
+// not use, else the fitted model's field (model_field = 1) or the predicted
+// field resampled to the N / 4 grid (N = net_res: copy; 2 net_res:
+// prolongation; net_res / 2: restriction); misfit[i] = RMS endpoint misfit
+// (px of the network's image), flag[i] = use ? 4 : 8.
+hipError_t launch_warm_fit(const float* field, int n, int net_res, double xs, double ys, double zs, double radius,
+                           double threshold, int model_field, int N, double xsN, double ysN, double zsN,
+                           float* u_init, float* misfit, uint32_t* flag, hipStream_t s);
 
 // Network runner (cnn.hip), for the registration's warm start.
 int cnn_max_batch(const ebsd_cnn* c);
 bool cnn_ready(const ebsd_cnn* c);
 // Pack n <= max_batch normalised pairs and run the forward pass into out
-// [n][64][64][2] (x, y) full-res px, on stream s.
+// [n][64][64][2] (x, y) px of the 256 x 256 input, on stream s.  up2 != 0:
+// the images are 128 x 128 and are upsampled x2 (bilinear, pixel centres at
+// (i - 0.5) / 2) on the way in.
 int cnn_forward_from(ebsd_cnn* c, const float* ref_base, int64_t ref_stride, const int32_t* ref_slot,
-                     const float* test_base, int64_t test_stride, int n, float* out, hipStream_t s);
+                     const float* test_base, int64_t test_stride, int n, int up2, float* out, hipStream_t s);
 
 }  // namespace ebsd

@@ -394,8 +394,9 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const size_t o_rv = w.take(sizeof(double) * 3 * nb);
     const size_t o_st = w.take(sizeof(uint32_t) * nb);
     const bool warm = mode == Mode::Full && !tune_only && !u_init && p.warm_start;
-    const int64_t gcell = (int64_t)(H >> 2) * (W >> 2);
-    const size_t o_wfield = w.take(warm ? sizeof(float) * 2 * (size_t)nb * gcell : 0);
+    const int64_t gcell = (int64_t)(H >> 2) * (W >> 2);  // coarse grid of the pattern
+    const int64_t ncell = (int64_t)(kWarmRes / 4) * (kWarmRes / 4);  // the network's output grid
+    const size_t o_wfield = w.take(warm ? sizeof(float) * 2 * (size_t)nb * ncell : 0);
     const size_t o_uinit = w.take(warm ? sizeof(float) * 2 * (size_t)nb * gcell : 0);
     const size_t o_wmis = w.take(warm ? sizeof(float) * (size_t)nb : 0);
     const size_t o_wflag = w.take(warm ? sizeof(uint32_t) * (size_t)nb : 0);
@@ -598,16 +599,22 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     if (warm) {
         // network field at the coarse grid, chunk by chunk, then the Eq. (2)
         // fit that decides between it and zero
+        // The network sees 256 x 256 images: level 0 of a 256 px pattern, level
+        // 1 of a 512 px pattern, level 0 of a 128 px pattern upsampled x2.
         float* wf = reinterpret_cast<float*>(base + o_wfield);
+        const int in_lvl = H == 2 * kWarmRes ? 1 : 0;
+        const int up2 = H * 2 == kWarmRes ? 1 : 0;
         const int cm = cnn_max_batch(h->cnn);
         for (int c0 = 0; c0 < nb; c0 += cm) {
             const int cnt = std::min(cm, nb - c0);
-            const int ec = cnn_forward_from(h->cnn, b.ref_pyr, pe, b.ref_slot + c0, b.test_pyr + (int64_t)c0 * pe, pe,
-                                            cnt, wf + (int64_t)c0 * 2 * gcell, s);
+            const int ec = cnn_forward_from(h->cnn, b.ref_pyr + b.lvl_off[in_lvl], pe, b.ref_slot + c0,
+                                            b.test_pyr + (int64_t)c0 * pe + b.lvl_off[in_lvl], pe, cnt, up2,
+                                            wf + (int64_t)c0 * 2 * ncell, s);
             if (ec) return ec;
         }
-        EBSD_TRY(launch_warm_fit(wf, nb, H, W, b.xs, b.ys, b.zs, p.roi_radius_frac * W,
-                                 (double)p.fallback_residual_px, p.warm_start == 2 ? 1 : 0,
+        const double xn = p.pc_x * kWarmRes - 0.5, yn = p.pc_y * kWarmRes - 0.5, zn = p.pc_z * kWarmRes;
+        EBSD_TRY(launch_warm_fit(wf, nb, kWarmRes, xn, yn, zn, p.roi_radius_frac * kWarmRes,
+                                 (double)p.fallback_residual_px, p.warm_start == 2 ? 1 : 0, H, b.xs, b.ys, b.zs,
                                  reinterpret_cast<float*>(base + o_uinit),
                                  reinterpret_cast<float*>(base + o_wmis), reinterpret_cast<uint32_t*>(base + o_wflag),
                                  s));
@@ -667,7 +674,8 @@ int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u
         if (!cnn_ready(h->cnn)) return EBSD_ENOMODEL;
         if (h->p.levels != kWarmLevels) return EBSD_ESHAPE;
         for (auto& hb : buckets)
-            if (hb.H != kWarmRes || hb.W != kWarmRes) return EBSD_ESHAPE;
+            if (hb.H != hb.W || (hb.H != kWarmRes && hb.H != kWarmRes / 2 && hb.H != 2 * kWarmRes))
+                return EBSD_ESHAPE;
     }
     DeviceGuard g(h->device);
     if (!g.ok) return EBSD_EDEVICE;

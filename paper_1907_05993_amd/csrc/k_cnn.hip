@@ -343,6 +343,38 @@ __global__ void k_pack_input(const float* __restrict__ rb, int64_t rs, const int
     *reinterpret_cast<uint4*>(x + 8 * i) = v;
 }
 
+__device__ inline float up2_sample(const float* __restrict__ img, int h, int w, int X, int Y)
+{
+    const float cx = fminf(fmaxf(0.5f * ((float)X - 0.5f), 0.0f), (float)(w - 1));
+    const float cy = fminf(fmaxf(0.5f * ((float)Y - 0.5f), 0.0f), (float)(h - 1));
+    const int x0 = (int)floorf(cx), y0 = (int)floorf(cy);
+    const int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
+    const float fx = cx - (float)x0, fy = cy - (float)y0;
+    const float a0 = img[y0 * w + x0], a1 = img[y0 * w + x1], b0 = img[y1 * w + x0], b1 = img[y1 * w + x1];
+    const float top = a0 + fx * (a1 - a0), bot = b0 + fx * (b1 - b0);
+    return top + fy * (bot - top);
+}
+
+__global__ void k_pack_input_up2(const float* __restrict__ rb, int64_t rs, const int32_t* __restrict__ slot,
+                                 const float* __restrict__ tb, int64_t ts, int n, int h, int w,
+                                 bf16_t* __restrict__ x)
+{
+    const int W2 = 2 * w, H2 = 2 * h;
+    const int64_t hw2 = (int64_t)H2 * W2;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * hw2) return;
+    const int64_t pair = i / hw2, p = i - pair * hw2;
+    const int X = (int)(p % W2), Y = (int)(p / W2);
+    const int64_t rsl = slot ? slot[pair] : pair;
+    const float r = up2_sample(rb + rsl * rs, h, w, X, Y), t = up2_sample(tb + pair * ts, h, w, X, Y);
+    uint4 v;
+    v.x = (uint32_t)f2bf(r) | ((uint32_t)f2bf(t) << 16);
+    v.y = 0u;
+    v.z = 0u;
+    v.w = 0u;
+    *reinterpret_cast<uint4*>(x + 8 * i) = v;
+}
+
 // One thread per (pooled pixel, 8-channel group).
 __global__ void k_maxpool(const bf16_t* __restrict__ in, int n, int H, int W, int C, int cs, int co,
                           bf16_t* __restrict__ out)
@@ -677,6 +709,16 @@ hipError_t launch_pack_input(const float* ref_base, int64_t ref_stride, const in
     const int64_t hw = (int64_t)H * W;
     hipLaunchKernelGGL(k_pack_input, dim3(blocks_for((int64_t)n * hw, 256)), dim3(256), 0, s, ref_base,
                        ref_stride, ref_slot, test_base, test_stride, n, hw, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_input_up2(const float* ref_base, int64_t ref_stride, const int32_t* ref_slot,
+                                 const float* test_base, int64_t test_stride, int n, int h, int w,
+                                 bf16_t* x, hipStream_t s)
+{
+    const int64_t hw2 = (int64_t)4 * h * w;
+    hipLaunchKernelGGL(k_pack_input_up2, dim3(blocks_for((int64_t)n * hw2, 256)), dim3(256), 0, s, ref_base,
+                       ref_stride, ref_slot, test_base, test_stride, n, h, w, x);
     return hipGetLastError();
 }
 

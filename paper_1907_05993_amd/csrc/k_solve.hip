@@ -379,7 +379,7 @@ __global__ void k_scatter(const Bucket* __restrict__ bk)
 __global__ void k_scatter_warm(const Bucket* __restrict__ bk)
 {
     const int b = blockIdx.y;
-    const int64_t n = (int64_t)(bk->H >> 2) * (bk->W >> 2) * 2;
+    const int64_t n = 64 * 64 * 2;  // the network's output grid
     const int64_t g = bk->pair_index[b];
     float* dst = bk->out.warm_field + g * n;
     const float* src = bk->warm_field + (int64_t)b * n;
@@ -430,8 +430,8 @@ struct GridFit {
 
 __global__ void __launch_bounds__(kFitThreads)
 k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys, double zs,
-           double radius, double threshold, int model_field, float* __restrict__ u_init,
-           float* __restrict__ misfit, uint32_t* __restrict__ flag)
+           double radius, double threshold, int model_field, int go, double xsN, double ysN, double zsN,
+           float* __restrict__ u_init, float* __restrict__ misfit, uint32_t* __restrict__ flag)
 {
     __shared__ double sh[4 * 45];
     const int b = blockIdx.x;
@@ -552,24 +552,61 @@ k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys
         misfit[b] = (float)rms;
         flag[b] = use ? (uint32_t)EBSD_WARM_USED : (uint32_t)EBSD_WARM_FALLBACK;
     }
-    float* u = u_init + (int64_t)b * 2 * ng;
-    for (int g = threadIdx.x; g < ng; g += kFitThreads) {
+    // initial field on the coarse grid of the registered pattern (go x go
+    // points at 4 i + 1.5 of its own px): the fitted model evaluated there
+    // (the projective map is unchanged by a common scaling of the detector
+    // coordinates), or the network field resampled from its 64 x 64 grid
+    // (same grid: copy; go = 2 gw: prolongation, x 2 in px; go = gw / 2:
+    // [1,3,3,1]/8 restriction, x 1/2 in px)
+    const int no = go * go;
+    float* u = u_init + (int64_t)b * 2 * no;
+    for (int g = threadIdx.x; g < no; g += kFitThreads) {
         float ux = 0.0f, uy = 0.0f;
+        const int gxo = g % go, gyo = g / go;
         if (use && model_field) {
-            // the fitted model's shift at every grid point (Eq. (2))
-            const double x = 4.0 * (double)(g % gw) + 1.5, y = 4.0 * (double)(g / gw) + 1.5;
-            const double rx = x - xs, ry = y - ys;
-            const double v0 = f[0] * rx + f[1] * ry + f[2] * zs;
-            const double v1 = f[3] * rx + f[4] * ry + f[5] * zs;
-            const double v2 = f[6] * rx + f[7] * ry + f[8] * zs;
-            ux = (float)(xs + zs * v0 / v2 - x);
-            uy = (float)(ys + zs * v1 / v2 - y);
-        } else if (use) {
+            const double x = 4.0 * (double)gxo + 1.5, y = 4.0 * (double)gyo + 1.5;
+            const double rx = x - xsN, ry = y - ysN;
+            const double v0 = f[0] * rx + f[1] * ry + f[2] * zsN;
+            const double v1 = f[3] * rx + f[4] * ry + f[5] * zsN;
+            const double v2 = f[6] * rx + f[7] * ry + f[8] * zsN;
+            ux = (float)(xsN + zsN * v0 / v2 - x);
+            uy = (float)(ysN + zsN * v1 / v2 - y);
+        } else if (use && go == gw) {
             ux = gf.q[2 * g];
             uy = gf.q[2 * g + 1];
+        } else if (use && go == 2 * gw) {
+            const float cx = fminf(fmaxf(0.5f * ((float)gxo - 0.5f), 0.0f), (float)(gw - 1));
+            const float cy = fminf(fmaxf(0.5f * ((float)gyo - 0.5f), 0.0f), (float)(gh - 1));
+            const int x0 = (int)floorf(cx), y0 = (int)floorf(cy);
+            const int x1 = min(x0 + 1, gw - 1), y1 = min(y0 + 1, gh - 1);
+            const float fx = cx - (float)x0, fy = cy - (float)y0;
+            for (int c = 0; c < 2; c++) {
+                const float a0 = gf.q[2 * (y0 * gw + x0) + c], a1 = gf.q[2 * (y0 * gw + x1) + c];
+                const float b0 = gf.q[2 * (y1 * gw + x0) + c], b1 = gf.q[2 * (y1 * gw + x1) + c];
+                const float top = a0 + fx * (a1 - a0), bot = b0 + fx * (b1 - b0);
+                const float v = 2.0f * (top + fy * (bot - top));
+                if (c == 0) ux = v;
+                else uy = v;
+            }
+        } else if (use && 2 * go == gw) {
+            const float wt[4] = {0.125f, 0.375f, 0.375f, 0.125f};
+            for (int c = 0; c < 2; c++) {
+                float v = 0.0f;
+                for (int j = 0; j < 4; j++) {
+                    const int yy = min(max(2 * gyo - 1 + j, 0), gh - 1);
+                    float rowv = 0.0f;
+                    for (int i = 0; i < 4; i++) {
+                        const int xx = min(max(2 * gxo - 1 + i, 0), gw - 1);
+                        rowv += wt[i] * gf.q[2 * (yy * gw + xx) + c];
+                    }
+                    v += wt[j] * rowv;
+                }
+                if (c == 0) ux = 0.5f * v;
+                else uy = 0.5f * v;
+            }
         }
         u[g] = ux;
-        u[ng + g] = uy;
+        u[no + g] = uy;
     }
 }
 
@@ -589,7 +626,7 @@ hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 
 hipError_t launch_scatter_warm(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
-    const int64_t n = (int64_t)(hb.H >> 2) * (hb.W >> 2) * 2;
+    const int64_t n = 64 * 64 * 2;
     hipLaunchKernelGGL(k_scatter_warm, dim3((unsigned)((n + 255) / 256), hb.nb), dim3(256), 0, s, d_bk);
     return hipGetLastError();
 }
@@ -622,13 +659,15 @@ hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx
     return hipGetLastError();
 }
 
-hipError_t launch_warm_fit(const float* field, int n, int H, int W, double xs, double ys, double zs,
-                           double radius, double threshold, int model_field, float* u_init, float* misfit,
-                           uint32_t* flag, hipStream_t s)
+hipError_t launch_warm_fit(const float* field, int n, int net_res, double xs, double ys, double zs, double radius,
+                           double threshold, int model_field, int N, double xsN, double ysN, double zsN,
+                           float* u_init, float* misfit, uint32_t* flag, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_warm_fit, dim3(n), dim3(kFitThreads), 0, s, field, H / 4, W / 4, xs, ys, zs,
-                       radius, threshold, model_field, u_init, misfit, flag);
+    const int g = net_res / 4, go = N / 4;
+    if (!(go == g || go == 2 * g || 2 * go == g)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_warm_fit, dim3(n), dim3(kFitThreads), 0, s, field, g, g, xs, ys, zs, radius, threshold,
+                       model_field, go, xsN, ysN, zsN, u_init, misfit, flag);
     return hipGetLastError();
 }
 

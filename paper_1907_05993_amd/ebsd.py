@@ -291,8 +291,7 @@ class Registrar:
             "status": torch.empty(n, dtype=torch.int32, device=dev),
         }
         if self.params.warm_start and shapes:
-            h, w = shapes[0]
-            out["warm_field"] = torch.empty(n, h // 4, w // 4, 2, **f32)
+            out["warm_field"] = torch.empty(n, 64, 64, 2, **f32)
             out["warm_misfit"] = torch.empty(n, **f32)
         offs = None
         if want_field:

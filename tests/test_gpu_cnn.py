@@ -338,7 +338,7 @@ def test_trained_network_gain(E):
     assert np.median(e_short) * 5 <= np.median(e_plain)
 
 
-def test_warm_start_needs_a_model_and_256px(E):
+def test_warm_start_needs_a_model_and_a_supported_size(E):
     reg = E.Registrar(warm_params(E, warm_start=1))
     x = torch.zeros(1, 256, 256, device="cuda")
     with pytest.raises(E.EbsdError) as ei:
@@ -347,7 +347,56 @@ def test_warm_start_needs_a_model_and_256px(E):
     net = E.Cnn(max_batch=1)
     net.set_params(np.zeros(E.CNN_PARAMS, np.float32))
     reg.set_model(net)
-    y = torch.zeros(1, 512, 512, device="cuda")
+    y = torch.zeros(1, 384, 384, device="cuda")  # warm start takes 128, 256 or 512 px
     with pytest.raises(E.EbsdError) as ei:
         reg.register(y, y)
     assert ei.value.code == -2
+
+
+@pytest.mark.parametrize("N,mode", [(512, 1), (512, 2), (128, 1), (128, 2)])
+def test_warm_start_resampled_sizes_match_oracle(E, orc, N, mode):
+    """Patterns of 128 and 512 px: the network sees them resampled to 256 px
+    (level 0 upsampled x2, or level 1); the fit works in the 256 px frame and
+    the starting field is the fitted model on the pattern's own coarse grid
+    (mode 2) or the network field resampled to it (mode 1: prolongation x2
+    for 512, [1,3,3,1]/8 restriction x 1/2 for 128).  The oracle rebuilds the
+    starting field from the GPU's network output and registers from it."""
+    print(f"case: warm resampled N={N} mode={mode}", flush=True)
+    roi = 128 if N == 512 else 32
+    refs, tests, _ = pairs(2, N, N, seed=9)
+    net = E.Cnn(max_batch=2)
+    net.set_params(cnn.flatten(random_params(8)))
+    p = E.Params(levels=3, iters=(15, 15, 15), sigma_px=1.0, roi_size=roi, n_roi=20, warm_start=mode,
+                 fallback_residual_px=1e9)
+    reg = E.Registrar(p)
+    reg.set_model(net)
+    g = reg.register(cuda(refs), cuda(tests))
+    torch.cuda.synchronize()
+    assert np.all(g["status"].cpu().numpy() & E.WARM_USED)
+    wf = g["warm_field"].cpu().numpy().astype(np.float64)
+    pc256 = (0.5 * 256 - 0.5, 0.5 * 256 - 0.5, 0.7 * 256)
+    pcN = (0.5 * N - 0.5, 0.5 * N - 0.5, 0.7 * N)
+    gx, gy = cnn.grid_points(N, N)
+    u0 = np.empty((2, 2, N // 4, N // 4))
+    for i in range(2):
+        use, rms, Ff = cnn.warm_fallback(wf[i], 256, 256, pc256)
+        assert abs(float(g["warm_misfit"][i]) - rms) <= 1e-6 * max(rms, 1e-3)
+        if mode == 2:
+            r = np.stack([gx - pcN[0], gy - pcN[1], np.full_like(gx, pcN[2])])
+            v = np.einsum("ij,jhw->ihw", Ff, r)
+            u0[i, 0] = pcN[0] + pcN[2] * v[0] / v[2] - gx
+            u0[i, 1] = pcN[1] + pcN[2] * v[1] / v[2] - gy
+        elif N == 512:
+            u0[i] = orc.prolong(np.moveaxis(wf[i], -1, 0))
+        else:
+            f2 = np.moveaxis(wf[i], -1, 0)
+            u0[i] = 0.5 * np.stack([orc.restrict(f2[0]), orc.restrict(f2[1])])
+    op = orc.make_params(levels=3, iters=15, sigma=1.0, roi_size=roi, n_roi=20)
+    o = orc.register_batch(refs, tests, op, u_init=u0 / 4.0)
+    gf = g["field"].cpu().numpy()
+    for i in range(2):
+        rms = float(np.sqrt(((gf[i] - o["field"][i]) ** 2).mean()))
+        print("field rms vs oracle %.2e" % rms)
+        assert rms <= 1e-3
+    o2 = orc.register_batch(refs, tests, op, rfin=g["R_finite"].cpu().numpy(), want_field=False)
+    assert np.abs(g["F"].cpu().numpy() - o2["F"]).max() <= 1e-6
