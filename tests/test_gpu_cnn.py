@@ -400,3 +400,44 @@ def test_warm_start_resampled_sizes_match_oracle(E, orc, N, mode):
         assert rms <= 1e-3
     o2 = orc.register_batch(refs, tests, op, rfin=g["R_finite"].cpu().numpy(), want_field=False)
     assert np.abs(g["F"].cpu().numpy() - o2["F"]).max() <= 1e-6
+
+
+def test_mixed_size_stream_with_warm_start(E, orc):
+    """Uneven sizes in one call (128, 256, 512 px; the trained network, fitted
+    field, fallback at 0.5): each pair's result equals its own single-size
+    call bit for bit, and the second pass matches the oracle's from the same
+    R_finite."""
+    import os
+    from paper_1907_05993_amd import synth as S
+    print("case: mixed-size warm stream", flush=True)
+    weights = os.path.join(os.path.dirname(E.__file__), "weights", "warm_cnn_256.bin")
+    sizes = [128, 256, 512, 256, 128, 512]
+    specs = [S.make_spec(60, i, N, N, mis_deg=(0.0, 12.0), strain=2e-3) for i, N in enumerate(sizes)]
+    pats = [S.render_pair(s) for s in specs]
+    refs = [cuda(r) for r, _ in pats]
+    tests = [cuda(t) for _, t in pats]
+
+    def registrar(roi):
+        p = E.Params(levels=3, iters=(150,) * 3, sigma_px=1.0, tol_px=1e-4, roi_size=roi, n_roi=20, warm_start=2)
+        reg = E.Registrar(p)
+        reg.load_model(weights)
+        return reg
+
+    # one ROI size for all sizes of the stream: 32 px fits every size's ring
+    mixed = registrar(32).register(refs, tests)
+    torch.cuda.synchronize()
+    for N in (128, 256, 512):
+        idx = [i for i, n in enumerate(sizes) if n == N]
+        single = registrar(32).register([refs[i] for i in idx], [tests[i] for i in idx])
+        torch.cuda.synchronize()
+        for j, i in enumerate(idx):
+            assert torch.equal(mixed["field"][i], single["field"][j])
+            for k in ("F", "iters", "status", "warm_misfit"):
+                assert torch.equal(mixed[k][i], single[k][j]), (k, N)
+        op = orc.make_params(levels=3, iters=150, sigma=1.0, tol=1e-4, roi_size=32, n_roi=20)
+        r = np.stack([pats[i][0] for i in idx])
+        t = np.stack([pats[i][1] for i in idx])
+        o2 = orc.register_batch(r, t, op, rfin=mixed["R_finite"][idx].cpu().numpy(), want_field=False)
+        dF = np.abs(mixed["F"][idx].cpu().numpy() - o2["F"]).max()
+        print("N=%d: max |dF| from a common R_finite %.2e, status %s" % (N, dF, mixed["status"][idx].tolist()))
+        assert dF <= 1e-6
