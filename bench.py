@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "demons_traffic.json"))
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
     ap.add_argument("--skip-plain", action="store_true", help="time the warm start only (profiling runs)")
+    ap.add_argument("--latency-reps", type=int, default=20,
+                    help="also time the single-pair configuration (128^2, 3 x 100) this many times (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (counter calibration) and exit")
     args = ap.parse_args()
@@ -247,6 +249,27 @@ def main():
     }
     if short is not None:
         rec["warm_short_cap"] = dict(summary(short), cap=args.short_cap)
+
+    if args.latency_reps > 0:
+        # single pair, 128 x 128, 2 degrees, 3 levels x 100 iterations, 20 ROIs of 32: latency per call
+        sp = S.workload_specs("single_128", n=1)
+        r1, t1, _ = ebsd.gen_pairs(sp, labels=False)
+        p1 = ebsd.Params(levels=3, iters=(100, 100, 100), sigma_px=1.0, tol_px=0.0, roi_size=32, n_roi=20)
+        reg1 = ebsd.Registrar(p1, device=0)
+        reg1.set_graphs(not args.no_graphs)
+        for _ in range(3):
+            reg1.register(r1, t1, want_field=False)
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(args.latency_reps):
+            ts = time.perf_counter()
+            reg1.register(r1, t1, want_field=False)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - ts) * 1e6)
+        rec["single_pair_latency_us"] = {"median": round(float(np.median(lat)), 1), "min": round(float(min(lat)), 1),
+                                         "config": "1 pair 128x128, 2 deg, 3 levels x 100 iterations, 20 ROIs of 32, "
+                                                   "host call to completion"}
+        log(f"[bench] single pair latency: median {np.median(lat):.0f} us")
 
     if args.cpu_sample > 0:
         import oracle
