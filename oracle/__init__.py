@@ -40,6 +40,8 @@ class Params(C.Structure):
         ("roi_radius_frac", C.c_double),
         ("window", C.c_int32),
         ("second_pass", C.c_int32),
+        ("remap_interp", C.c_int32),
+        ("xcf_passes", C.c_int32),
     ]
 
 
@@ -60,7 +62,8 @@ class _Outputs(C.Structure):
 
 
 def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_roi=20,
-                roi_size=32, roi_radius_frac=0.3, window=1, second_pass=1):
+                roi_size=32, roi_radius_frac=0.3, window=1, second_pass=1, remap_interp=3,
+                xcf_passes=1):
     p = Params()
     p.levels = levels
     its = [iters] * MAX_LEVELS if np.isscalar(iters) else list(iters) + [0] * (MAX_LEVELS - len(iters))
@@ -74,6 +77,8 @@ def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_r
     p.roi_radius_frac = roi_radius_frac
     p.window = window
     p.second_pass = second_pass
+    p.remap_interp = remap_interp
+    p.xcf_passes = xcf_passes
     return p
 
 
@@ -110,7 +115,11 @@ def lib():
         L.orc_solve_F.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d]
         L.orc_polar.argtypes = [d, d]
         L.orc_rotvec.argtypes = [d, d]
-        L.orc_remap.argtypes = [d, C.c_int, C.c_int, d, C.c_double, C.c_double, C.c_double, d]
+        L.orc_remap.argtypes = [d, C.c_int, C.c_int, d, C.c_double, C.c_double, C.c_double, C.c_int, d]
+        L.orc_bspline_coeffs.argtypes = [d, C.c_int, C.c_int, d]
+        L.orc_bspline_at.restype = C.c_double
+        L.orc_bspline_at.argtypes = [d, C.c_int, C.c_int, C.c_double, C.c_double]
+        L.orc_bspline_points.argtypes = [d, C.c_int, C.c_int, d, d, C.c_int64, d]
         L.orc_fft1.argtypes = [d, d, C.c_int, C.c_int]
         L.orc_fft2.argtypes = [d, d, C.c_int, C.c_int]
         L.orc_xcf.argtypes = [d, d, C.c_int, C.c_int, d, d, d]
@@ -282,13 +291,35 @@ def det_normalize(F):
     return F.reshape(3, 3)
 
 
-def remap(ref, Rfin, pcs):
-    """Reference remapped by R_finite: Rm(x') = ref(pi(R^T r(x')))."""
+def remap(ref, Rfin, pcs, interp=3):
+    """Reference remapped by R_finite: Rm(x') = ref(pi(R^T r(x'))) (section 2,
+    before Eq. (12)); interp 3 = cubic B-spline, 1 = bilinear."""
     a = _f64(ref)
     H, W = a.shape
     Rf = _f64(Rfin).reshape(9)
     out = np.empty_like(a)
-    lib().orc_remap(_d(a), H, W, _d(Rf), float(pcs[0]), float(pcs[1]), float(pcs[2]), _d(out))
+    lib().orc_remap(_d(a), H, W, _d(Rf), float(pcs[0]), float(pcs[1]), float(pcs[2]), int(interp),
+                    _d(out))
+    return out
+
+
+def bspline_coeffs(img):
+    """Cubic B-spline coefficients of img under whole-sample mirroring."""
+    a = _f64(img)
+    H, W = a.shape
+    out = np.empty_like(a)
+    lib().orc_bspline_coeffs(_d(a), H, W, _d(out))
+    return out
+
+
+def bspline_points(coef, xs, ys):
+    """Cubic B-spline interpolant with coefficients coef at (xs, ys), clamped."""
+    c = _f64(coef)
+    H, W = c.shape
+    xs = _f64(xs).ravel()
+    ys = _f64(ys).ravel()
+    out = np.empty(xs.size)
+    lib().orc_bspline_points(_d(c), H, W, _d(xs), _d(ys), xs.size, _d(out))
     return out
 
 

@@ -18,10 +18,13 @@
  *   shifts           field sampled at the ROI centres (section 2)
  *   F solve          Eq. (2)/(3) projective model, DLT + Gauss-Newton
  *   polar            Eq. (4)/(5): F = P D Q^T, R = P Q^T
- *   remap            reference remapped by R_finite (section 2, before Eq. 12)
+ *   remap            reference remapped by R_finite (section 2, before Eq. 12),
+ *                    cubic B-spline interpolation (the paper's cubic scheme)
+ *                    or bilinear
  *   XCF              zero mean, Hann window, FFT, F_test . conj(F_ref), IFFT,
  *                    interpolated peak (section 2)
- *   compose          Eq. (12): F = F_inf R_finite
+ *   compose          Eq. (12): F = F_inf R_finite; optional further passes
+ *                    remap by the rotation of the previous pass's F
  *   rotation vector  axis-angle of R (the passage after Eq. 5, Eq. 6)
  *
  * Readings where the paper is silent or ambiguous (sign of the force, which
@@ -63,6 +66,8 @@ typedef struct {
     double roi_radius_frac;            /* ring radius / W */
     int32_t window;                    /* 1 = Hann window, 0 = none */
     int32_t second_pass;               /* 1 = remap + XCF second pass */
+    int32_t remap_interp;              /* 3 = cubic B-spline, 1 = bilinear */
+    int32_t xcf_passes;                /* remap + XCF passes (>= 1) */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -691,13 +696,109 @@ void orc_rotvec(const double* R, double* rv)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Remap of the reference by R_finite (section 2, before Eq. (12)):
- * Rm(x') = R0( pi( R_finite^T r(x') ) ), r(x') = (x'-x*, y'-y*, Z*),
- * pi(v) = (x* + Z* v_x/v_z, y* + Z* v_y/v_z); bilinear with clamping (the
- * paper remaps with cubic interpolation; bilinear is this build's reading). */
-void orc_remap(const double* ref, int H, int W, const double* Rf, double xs, double ys,
-               double zs, double* out)
+/* Cubic B-spline interpolation (the paper remaps with a cubic scheme; the
+ * reading here is the interpolating cubic B-spline).  The image s is
+ * extended by whole-sample mirroring (s[-k] = s[k], s[N-1+k] = s[N-1-k]);
+ * the coefficients c solve sum_k c[k] beta3(x - k) = s[x] at every integer x,
+ * separably along rows then columns.  Along one line that is the inverse of
+ * the filter (1, 4, 1)/6, factored into a causal and an anti-causal
+ * first-order recursion with pole z = sqrt(3) - 2 (Unser, Aldroubi & Eden,
+ * IEEE Trans. Signal Process. 41 (1993) 821-833):
+ *   c+[0] = sum_{k=0}^{2N-3} z^k s~[k] / (1 - z^(2N-2))   (s~ = the mirror
+ *           extension, period 2N-2: the exact start for that extension)
+ *   c+[k] = s[k] + z c+[k-1]
+ *   c-[N-1] = z / (z^2 - 1) (c+[N-1] + z c+[N-2])
+ *   c-[k] = z (c-[k+1] - c+[k])
+ *   c[k] = 6 c-[k].
+ * N == 1 gives c = s.                                                       */
+static void bspline_line(double* v, int N, size_t stride)
 {
+    if (N < 2) return;
+    const double z = sqrt(3.0) - 2.0;
+    const int P = 2 * N - 2;
+    double zk = 1.0, acc = 0.0;
+    for (int k = 0; k < P; k++) {
+        int m = k < N ? k : P - k;
+        acc += zk * v[(size_t)m * stride];
+        zk *= z;
+    }
+    double* cp = (double*)malloc(sizeof(double) * N);
+    cp[0] = acc / (1.0 - zk);
+    for (int k = 1; k < N; k++) cp[k] = v[(size_t)k * stride] + z * cp[k - 1];
+    double cm = z / (z * z - 1.0) * (cp[N - 1] + z * cp[N - 2]);
+    v[(size_t)(N - 1) * stride] = 6.0 * cm;
+    for (int k = N - 2; k >= 0; k--) {
+        cm = z * (cm - cp[k]);
+        v[(size_t)k * stride] = 6.0 * cm;
+    }
+    free(cp);
+}
+
+void orc_bspline_coeffs(const double* img, int H, int W, double* c)
+{
+    memcpy(c, img, sizeof(double) * (size_t)H * W);
+    for (int y = 0; y < H; y++) bspline_line(c + (size_t)y * W, W, 1);
+    for (int x = 0; x < W; x++) bspline_line(c + x, H, (size_t)W);
+}
+
+/* Whole-sample mirror of index i into [0, N-1]. */
+static int mirror_index(int i, int N)
+{
+    if (N == 1) return 0;
+    const int P = 2 * N - 2;
+    int m = i % P;
+    if (m < 0) m += P;
+    return m < N ? m : P - m;
+}
+
+/* Cubic B-spline  beta3(t) = (4 - 6t^2 + 3|t|^3)/6 for |t| <= 1,
+ * (2 - |t|)^3/6 for 1 < |t| < 2, else 0. */
+static double beta3(double t)
+{
+    t = fabs(t);
+    if (t < 1.0) return (4.0 - 6.0 * t * t + 3.0 * t * t * t) / 6.0;
+    if (t < 2.0) return (2.0 - t) * (2.0 - t) * (2.0 - t) / 6.0;
+    return 0.0;
+}
+
+/* Interpolant sum_{j,k} c[j][k] beta3(y - j) beta3(x - k) at (x, y), with
+ * the coordinates clamped to [0, W-1] x [0, H-1] as for the bilinear
+ * sample, coefficients indexed through the mirror extension. */
+double orc_bspline_at(const double* c, int H, int W, double x, double y)
+{
+    double xc = clampd(x, 0.0, (double)(W - 1));
+    double yc = clampd(y, 0.0, (double)(H - 1));
+    int ix = (int)floor(xc), iy = (int)floor(yc);
+    double acc = 0.0;
+    for (int j = iy - 1; j <= iy + 2; j++) {
+        double wy = beta3(yc - (double)j);
+        const double* row = c + (size_t)mirror_index(j, H) * W;
+        for (int k = ix - 1; k <= ix + 2; k++)
+            acc += wy * beta3(xc - (double)k) * row[mirror_index(k, W)];
+    }
+    return acc;
+}
+
+void orc_bspline_points(const double* c, int H, int W, const double* xs, const double* ys,
+                        int64_t n, double* out)
+{
+    for (int64_t i = 0; i < n; i++) out[i] = orc_bspline_at(c, H, W, xs[i], ys[i]);
+}
+
+/* Remap of the reference by R_finite (section 2, before Eq. (12)), R
+ * row-major:
+ *   Rm(x') = ref(pi(R^T r(x'))),  r(x) = (x - x*, y - y*, Z*),
+ *   pi(v) = (x* + Z* v_x/v_z, y* + Z* v_y/v_z);
+ * interp 3: cubic B-spline interpolation (above), interp 1: bilinear; both
+ * clamp the sample position to the pattern. */
+void orc_remap(const double* ref, int H, int W, const double* Rf, double xs, double ys,
+               double zs, int interp, double* out)
+{
+    double* c = NULL;
+    if (interp == 3) {
+        c = (double*)malloc(sizeof(double) * (size_t)H * W);
+        orc_bspline_coeffs(ref, H, W, c);
+    }
     for (int y = 0; y < H; y++)
         for (int x = 0; x < W; x++) {
             double r0 = x - xs, r1 = y - ys, r2 = zs;
@@ -705,8 +806,9 @@ void orc_remap(const double* ref, int H, int W, const double* Rf, double xs, dou
             double v1 = Rf[1] * r0 + Rf[4] * r1 + Rf[7] * r2;
             double v2 = Rf[2] * r0 + Rf[5] * r1 + Rf[8] * r2;
             double sx = xs + zs * v0 / v2, sy = ys + zs * v1 / v2;
-            out[(size_t)y * W + x] = orc_bilinear(ref, H, W, sx, sy);
+            out[(size_t)y * W + x] = c ? orc_bspline_at(c, H, W, sx, sy) : orc_bilinear(ref, H, W, sx, sy);
         }
+    free(c);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -864,6 +966,9 @@ void orc_xcf(const double* A, const double* B, int N, int window, double* C, dou
  *   R_finite = polar(F1) (Eq. 4-5) -> remap the reference by R_finite ->
  *   XCF per ROI -> q2 -> F_inf (Eq. 3) -> F = F_inf R_finite (Eq. 12),
  *   det F = 1 -> R = polar(F) -> rotation vector.
+ * With xcf_passes = P > 1 the remap + XCF + compose step runs P times, pass
+ * k remapping by polar(F) of pass k-1 in place of R_finite; q2 and ph are
+ * the last pass's.
  * rfin_in (optional) replaces the first pass's R_finite: it lets the second
  * pass be checked in isolation against another implementation's R_finite.
  * Any output pointer may be NULL.                                         */
@@ -919,22 +1024,30 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
     orc_polar(F1, Rfin);
     if (rfin_in) memcpy(Rfin, rfin_in, sizeof Rfin);
     if (p->second_pass) {
+        /* pass 1 remaps by R_finite; each further pass remaps by the rotation
+         * of the F the previous pass found and composes with it. */
+        int passes = p->xcf_passes > 1 ? p->xcf_passes : 1;
+        double Rcur[9];
+        memcpy(Rcur, Rfin, sizeof Rcur);
         double* Rm = (double*)malloc(sizeof(double) * HW);
-        orc_remap(Rn, H, W, Rfin, xs, ys, zs, Rm);
         double* a = (double*)malloc(sizeof(double) * N * N);
         double* b = (double*)malloc(sizeof(double) * N * N);
-        for (int j = 0; j < nr; j++) {
-            for (int y = 0; y < N; y++)
-                for (int x = 0; x < N; x++) {
-                    a[y * N + x] = Rm[(size_t)(y0[j] + y) * W + x0[j] + x];
-                    b[y * N + x] = Tn[(size_t)(y0[j] + y) * W + x0[j] + x];
-                }
-            orc_xcf(a, b, N, p->window, NULL, q2 + 2 * j, ph + j);
+        for (int pass = 0; pass < passes; pass++) {
+            orc_remap(Rn, H, W, Rcur, xs, ys, zs, p->remap_interp, Rm);
+            for (int j = 0; j < nr; j++) {
+                for (int y = 0; y < N; y++)
+                    for (int x = 0; x < N; x++) {
+                        a[y * N + x] = Rm[(size_t)(y0[j] + y) * W + x0[j] + x];
+                        b[y * N + x] = Tn[(size_t)(y0[j] + y) * W + x0[j] + x];
+                    }
+                orc_xcf(a, b, N, p->window, NULL, q2 + 2 * j, ph + j);
+            }
+            double Finf[9];
+            st |= orc_solve_F(q2, cx, cy, nr, xs, ys, zs, Finf);
+            matmul3(Finf, Rcur, F);
+            if (det3(F) > 0.0) orc_det_normalize(F);
+            orc_polar(F, Rcur);
         }
-        double Finf[9];
-        st |= orc_solve_F(q2, cx, cy, nr, xs, ys, zs, Finf);
-        matmul3(Finf, Rfin, F);
-        if (det3(F) > 0.0) orc_det_normalize(F);
         free(Rm);
         free(a);
         free(b);
