@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define EBSD_ABI_VERSION 2
+#define EBSD_ABI_VERSION 3
 #define EBSD_MAX_LEVELS 8
 
 /* return codes */
@@ -91,6 +91,10 @@ typedef struct ebsd_params {
                                              network's field, 2 = from the Eq. (2) field fitted to it; 0 = zero */
     float fallback_residual_px;           /* warm start: largest RMS misfit of the Eq. (2) fit, in px of the
                                              coarsest level (the grid the field initialises) */
+    int32_t remap_interp;                 /* remap before the XCF (section 2, before Eq. (12)): 3 = cubic
+                                             B-spline interpolation (the paper's cubic scheme), 1 = bilinear */
+    int32_t xcf_passes;                   /* remap + XCF + Eq. (12) passes, 1..16: pass 1 remaps by R_finite
+                                             (the paper's method), pass k > 1 by the rotation of pass k-1's F */
 } ebsd_params;
 
 /* One scan point.  ref/test: device pointers to H x W fp32 patterns.  Pairs
@@ -126,8 +130,8 @@ int ebsd_version(void);
 
 /* Fill *p with the defaults: 3 levels x 150 iterations, sigma 1 px, tol 0,
  * pattern centre (0.5, 0.5, 0.7), 20 ROIs of 64 px on a ring of 0.3 W, Hann
- * window, second pass on, warm start off (fallback misfit 0.5 px).  Returns
- * EBSD_OK or EBSD_EINVAL (p == NULL). */
+ * window, second pass on (cubic B-spline remap, one pass), warm start off
+ * (fallback misfit 0.5 px).  Returns EBSD_OK or EBSD_EINVAL (p == NULL). */
 int ebsd_params_default(ebsd_params* p);
 
 /* Human-readable text of a return code (static storage). */
@@ -358,6 +362,17 @@ int ebsd_stage_prolong(const float* u, int32_t n, int32_t h, int32_t w, float* o
  * shift of B relative to A; ph: [n] normalised peak height (may be NULL). */
 int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t window, float* q,
                    float* ph, void* stream);
+
+/* Remap of n images (section 2, before Eq. (12)): out(x') = img(pi(R^T
+ * r(x'))) with r(x) = (x - xs, y - ys, zs), pi(v) = (xs + zs v_x / v_z,
+ * ys + zs v_y / v_z), the sample position clamped to the image.  img, out:
+ * [n][H][W] fp32 (device); R: [n][9] fp64 row-major (device); pattern centre
+ * (xs, ys) and detector distance zs in px.  interp 3: cubic B-spline
+ * interpolation (whole-sample mirror extension); coef (device, [n][H][W]
+ * fp32, required) receives the B-spline coefficients of each image.  interp
+ * 1: bilinear; coef is not used (may be NULL).  H, W >= 3, n <= 65535. */
+int ebsd_stage_remap(const float* img, int32_t n, int32_t H, int32_t W, const double* R, double xs,
+                     double ys, double zs, int32_t interp, float* coef, float* out, void* stream);
 
 /* Eq. (3) solve for n shift sets: q [n][n_roi][2] fp32 at ROI centres
  * cx, cy (device, [n_roi] fp64), pattern centre (xs, ys, zs) in px.

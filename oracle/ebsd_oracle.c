@@ -882,7 +882,7 @@ void orc_fft2(double* re, double* im, int N, int inverse)
  *   peak at +s;
  *   integer peak = argmax C, ties to the lowest row-major index; index
  *   k >= N/2 means k - N;
- *   sub-pixel ("interpolating the XCF peak"): the 2-D quadratic through the
+ *   sub-pixel (the paper interpolates the peak): the 2-D quadratic through the
  *   3 x 3 circular neighbourhood of the integer peak, with central
  *   differences g = (dC/dx, dC/dy) and Hessian Hs = [[Cxx, Cxy], [Cxy, Cyy]];
  *   d = -Hs^-1 g when Hs is negative definite (Cxx < 0, det > 0), each

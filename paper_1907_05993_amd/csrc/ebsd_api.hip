@@ -149,6 +149,8 @@ int check_params(const ebsd_params* p)
     if (p->second_pass != 0 && p->second_pass != 1) return EBSD_EINVAL;
     if (p->warm_start < 0 || p->warm_start > 2) return EBSD_EINVAL;
     if (!(p->fallback_residual_px >= 0.0f) || !std::isfinite(p->fallback_residual_px)) return EBSD_EINVAL;
+    if (p->remap_interp != 1 && p->remap_interp != 3) return EBSD_EINVAL;
+    if (p->xcf_passes < 1 || p->xcf_passes > 16) return EBSD_EINVAL;
     return EBSD_OK;
 }
 
@@ -393,6 +395,9 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const size_t o_R = w.take(sizeof(double) * 9 * nb);
     const size_t o_rv = w.take(sizeof(double) * 3 * nb);
     const size_t o_st = w.take(sizeof(uint32_t) * nb);
+    const bool xcf = mode == Mode::SecondPassOnly || p.second_pass;
+    const bool cubic = xcf && p.remap_interp == 3 && !tune_only;
+    const size_t o_coef = w.take(cubic ? sizeof(float) * (size_t)nref * H * W : 0);
     const bool warm = mode == Mode::Full && !tune_only && !u_init && p.warm_start;
     const int64_t gcell = (int64_t)(H >> 2) * (W >> 2);  // coarse grid of the pattern
     const int64_t ncell = (int64_t)(kWarmRes / 4) * (kWarmRes / 4);  // the network's output grid
@@ -428,6 +433,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.R = reinterpret_cast<double*>(base + o_R);
     b.rotvec = reinterpret_cast<double*>(base + o_rv);
     b.status = reinterpret_cast<uint32_t*>(base + o_st);
+    b.ref_coef = cubic ? reinterpret_cast<float*>(base + o_coef) : nullptr;
 
     bool want_field = mode == Mode::Full && out->field;
     b.out.F = out->F;
@@ -634,13 +640,19 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         EBSD_TRY(launch_sample_q1(d_bk, b, s));
         if (want_field) EBSD_TRY(launch_copy_field(d_bk, b, s));
         EBSD_TRY(launch_solve_first(d_bk, b, p.tol_px, s));
-        if (p.second_pass) EBSD_TRY(launch_xcf_pairs(d_bk, b, p.window, s));
-        EBSD_TRY(launch_solve_second(d_bk, b, p.second_pass, s));
     } else {
         EBSD_TRY(launch_gather_rfin(d_bk, b, s));
         EBSD_TRY(launch_status_inputs(d_bk, b, s));
-        EBSD_TRY(launch_xcf_pairs(d_bk, b, p.window, s));
-        EBSD_TRY(launch_solve_second(d_bk, b, 1, s));
+    }
+    if (xcf) {
+        // remap + XCF + Eq. (12); pass k > 0 remaps by the rotation of pass k-1
+        if (cubic) EBSD_TRY(launch_bspline_coef(d_bk, b, s));
+        for (int pass = 0; pass < p.xcf_passes; pass++) {
+            EBSD_TRY(launch_xcf_pairs(d_bk, b, p.window, p.remap_interp, pass, s));
+            EBSD_TRY(launch_solve_second(d_bk, b, 1, pass, s));
+        }
+    } else {
+        EBSD_TRY(launch_solve_second(d_bk, b, 0, 0, s));
     }
     EBSD_TRY(launch_scatter(d_bk, b, s));
     if (warm && out->warm_field) EBSD_TRY(launch_scatter_warm(d_bk, b, s));
@@ -712,16 +724,18 @@ int ebsd_params_default(ebsd_params* p)
     for (int l = 0; l < EBSD_MAX_LEVELS; l++) p->max_iters[l] = 150;
     p->sigma_px = 1.0f;
     p->tol_px = 0.0f;
-    p->pc_x = 0.5f;
-    p->pc_y = 0.5f;
-    p->pc_z = 0.7f;
+    p->pc_x = 0.5;
+    p->pc_y = 0.5;
+    p->pc_z = 0.7;
     p->n_roi = 20;
     p->roi_size = 64;
-    p->roi_radius_frac = 0.3f;
+    p->roi_radius_frac = 0.3;
     p->window = 1;
     p->second_pass = 1;
     p->warm_start = 0;
     p->fallback_residual_px = 0.5f;
+    p->remap_interp = 3;
+    p->xcf_passes = 1;
     return EBSD_OK;
 }
 
@@ -996,6 +1010,18 @@ int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t
     if (window != 0 && window != 1) return EBSD_EINVAL;
     if (n == 0) return EBSD_OK;
     return map_err(launch_stage_xcf(A, B, n, N, window, q, ph, (hipStream_t)stream));
+}
+
+int ebsd_stage_remap(const float* img, int32_t n, int32_t H, int32_t W, const double* R, double xs,
+                     double ys, double zs, int32_t interp, float* coef, float* out, void* stream)
+{
+    if (n < 0 || (n > 0 && (!img || !R || !out))) return EBSD_EINVAL;
+    if (interp != 1 && interp != 3) return EBSD_EINVAL;
+    if (interp == 3 && n > 0 && !coef) return EBSD_EINVAL;
+    if (!std::isfinite(xs) || !std::isfinite(ys) || !(zs > 0.0) || !std::isfinite(zs)) return EBSD_EINVAL;
+    if (H < 3 || W < 3 || n > 65535) return EBSD_ESHAPE;
+    if (n == 0) return EBSD_OK;
+    return map_err(launch_stage_remap(img, n, H, W, R, xs, ys, zs, interp, coef, out, (hipStream_t)stream));
 }
 
 int ebsd_stage_solve(const float* q, int32_t n, int32_t n_roi, const double* cx, const double* cy,

@@ -85,6 +85,7 @@ struct Bucket {
     double* R;                  // [nb][9]
     double* rotvec;             // [nb][3]
     uint32_t* status;           // [nb]
+    float* ref_coef;            // [nref][H][W] cubic B-spline coefficients of level 0 (NULL: bilinear remap)
     // per-call caller pointers (so that a bucket's launch sequence is static
     // and can be replayed from a captured graph)
     OutPtrs out;                // results, scattered by pair_index
@@ -129,15 +130,21 @@ hipError_t launch_copy_field(const Bucket* d_bk, const Bucket& hb, hipStream_t s
 hipError_t launch_solve_first(const Bucket* d_bk, const Bucket& hb, float tol, hipStream_t s);
 // Status from the input flags only (second-pass-only entry).
 hipError_t launch_status_inputs(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
-// Remap + ROI XCF for every (pair, ROI) -> q2, ph.
-hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, hipStream_t s);
+// Cubic B-spline coefficients of level 0 of every reference -> bk->ref_coef.
+hipError_t launch_bspline_coef(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
+// Remap + ROI XCF for every (pair, ROI) -> q2, ph.  interp 3: cubic B-spline
+// from bk->ref_coef, 1: bilinear; pass 0 remaps by Rfin, pass k > 0 by R.
+hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, int interp, int pass,
+                            hipStream_t s);
 // Rfin[b] = bk->rfin_in[pair_index[b]] (second-pass-only entry).
 hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Copy the warm-start field and misfit of every pair to the caller's outputs.
 hipError_t launch_scatter_warm(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
-// Second-pass solve: F_inf from q2, F = F_inf Rfin, det 1, R, rotvec.
-hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass,
+// Second-pass solve: F_inf from q2, F = F_inf M, det 1, R = polar(F), rotvec,
+// with M = Rfin for pass 0 and M = R (the previous pass's) after.
+// second_pass == 0: F = F1.
+hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass, int pass,
                                hipStream_t s);
 
 // ---- stage launchers -----------------------------------------------------------
@@ -150,6 +157,8 @@ hipError_t launch_stage_demons_iter(const float* R, const float* T, int n, int H
 hipError_t launch_stage_prolong(const float* u, int n, int h, int w, float* out, hipStream_t s);
 hipError_t launch_stage_xcf(const float* A, const float* B, int n, int N, int window, float* q,
                             float* ph, hipStream_t s);
+hipError_t launch_stage_remap(const float* ref, int n, int H, int W, const double* R, double xs, double ys,
+                              double zs, int interp, float* coef, float* out, hipStream_t s);
 hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx,
                               const double* cy, double xs, double ys, double zs, double* F,
                               double* R, uint32_t* status, hipStream_t s);

@@ -288,11 +288,15 @@ __global__ void k_status_inputs(const Bucket* __restrict__ bk)
     bk->status[b] = bk->test_stat[b].flags | bk->ref_stat[bk->ref_slot[b]].flags;
 }
 
-__global__ void k_solve_second(const Bucket* __restrict__ bk, int second_pass)
+// pass 0 composes with R_finite (Eq. (12)); pass k > 0 with the rotation
+// the previous pass left in R (read before R is overwritten).
+__global__ void k_solve_second(const Bucket* __restrict__ bk, int second_pass, int pass)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= bk->nb) return;
-    const double* Rf = bk->Rfin + 9 * (int64_t)b;
+    double Rf[9];
+    const double* Rsrc = (pass == 0 ? bk->Rfin : bk->R) + 9 * (int64_t)b;
+    for (int i = 0; i < 9; i++) Rf[i] = Rsrc[i];
     double* F = bk->F + 9 * (int64_t)b;
     uint32_t st = bk->status[b];
     if (second_pass) {
@@ -643,10 +647,10 @@ hipError_t launch_status_inputs(const Bucket* d_bk, const Bucket& hb, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass,
+hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass, int pass,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_solve_second, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, second_pass);
+    hipLaunchKernelGGL(k_solve_second, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, second_pass, pass);
     return hipGetLastError();
 }
 

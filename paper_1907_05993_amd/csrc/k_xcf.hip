@@ -5,7 +5,9 @@
 //
 // One 256-thread workgroup per (pair, ROI), N in {32, 64, 128}:
 //   gather   reference ROI remapped on the fly, Rm(x') = R0(pi(R_finite^T r(x'))),
-//            and test ROI, packed as z = a + i b (one complex FFT serves both);
+//            interpolated by the cubic B-spline (the paper's cubic scheme,
+//            coefficients from k_bspline_coef) or bilinearly, and test ROI,
+//            packed as z = a + i b (one complex FFT serves both);
 //   window   per-ROI mean removed, symmetric Hann window h (x) h;
 //   FFT      2-D radix-2 in LDS: decimation-in-frequency forward (natural in,
 //            bit-reversed out), so no explicit permutation is needed;
@@ -64,6 +66,143 @@ __device__ inline float bilinear_d(const float* __restrict__ img, int h, int w, 
     float top = (1.0f - fx) * r0[x0] + fx * r0[x1];
     float bot = (1.0f - fx) * r1[x0] + fx * r1[x1];
     return (1.0f - fy) * top + fy * bot;
+}
+
+// Whole-sample mirror of an index at most n - 1 outside [0, n - 1] (n >= 2).
+__device__ inline int mirror1(int i, int n)
+{
+    i = i < 0 ? -i : i;
+    return i > n - 1 ? 2 * n - 2 - i : i;
+}
+
+// Cubic B-spline interpolant with coefficients c (h x w, whole-sample mirror
+// extension) at double-precision coordinates clamped to the image: weights
+// beta3(t + 1), beta3(t), beta3(t - 1), beta3(t - 2) on the four nodes
+// floor(x) - 1 .. floor(x) + 2 per axis.  Needs w, h >= 3.
+__device__ inline float bspline_d(const float* __restrict__ c, int h, int w, double x, double y)
+{
+    const double xc = fmin(fmax(x, 0.0), (double)(w - 1));
+    const double yc = fmin(fmax(y, 0.0), (double)(h - 1));
+    const int ix = clampi((int)floor(xc), 0, w - 1), iy = clampi((int)floor(yc), 0, h - 1);
+    const float tx = (float)(xc - (double)ix), ty = (float)(yc - (double)iy);
+    float wx[4], wy[4];
+    {
+        const float t = tx, t2 = t * t, t3 = t2 * t, u = 1.0f - t;
+        wx[0] = u * u * u * (1.0f / 6.0f);
+        wx[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
+        wx[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
+        wx[3] = t3 * (1.0f / 6.0f);
+    }
+    {
+        const float t = ty, t2 = t * t, t3 = t2 * t, u = 1.0f - t;
+        wy[0] = u * u * u * (1.0f / 6.0f);
+        wy[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
+        wy[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
+        wy[3] = t3 * (1.0f / 6.0f);
+    }
+    int cx[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) cx[k] = mirror1(ix - 1 + k, w);
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const float* row = c + (int64_t)mirror1(iy - 1 + j, h) * w;
+        float r = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; k++) r += wx[k] * row[cx[k]];
+        acc += wy[j] * r;
+    }
+    return acc;
+}
+
+// Cubic B-spline coefficients of level 0 of every reference (whole-sample
+// mirror extension).  Along one line the coefficients are the samples
+// filtered by the inverse of (1, 4, 1)/6, whose impulse response is
+// sqrt(3) z^|k| with z = sqrt(3) - 2; it is applied here as a 31-tap FIR
+// (|k| <= 15; the dropped tail is below 3.4e-9 of the largest sample), rows
+// then columns, on 64 x 64 output tiles with a 15 px mirrored halo in LDS.
+// grid: (tiles of the image, images); image i is src + i * src_stride (H x W
+// floats, row-major) -> dst + i * H * W; 256 threads.
+constexpr int kCoefT = 64, kCoefK = 15, kCoefS = kCoefT + 2 * kCoefK;
+
+__device__ inline int mirror_any(int i, int n)
+{
+    if (n == 1) return 0;
+    const int P = 2 * n - 2;
+    int m = i % P;
+    m = m < 0 ? m + P : m;
+    return m < n ? m : P - m;
+}
+
+__global__ void __launch_bounds__(256)
+    k_bspline_coef(const float* __restrict__ src_all, int64_t src_stride, float* __restrict__ dst_all, int H,
+                   int W)
+{
+    __shared__ float sIn[kCoefS][kCoefS + 1];
+    __shared__ float sRow[kCoefS][kCoefT + 1];
+    __shared__ float sH[kCoefK + 1];
+    const int tiles_x = (W + kCoefT - 1) / kCoefT;
+    const int tx0 = (blockIdx.x % tiles_x) * kCoefT, ty0 = (blockIdx.x / tiles_x) * kCoefT;
+    const float* src = src_all + (int64_t)blockIdx.y * src_stride;
+    float* dst = dst_all + (int64_t)blockIdx.y * H * W;
+    const int tid = threadIdx.x;
+    if (tid <= kCoefK) {
+        const double z = sqrt(3.0) - 2.0;
+        double v = sqrt(3.0);
+        for (int j = 0; j < tid; j++) v *= z;
+        sH[tid] = (float)v;
+    }
+    for (int i = tid; i < kCoefS * kCoefS; i += 256) {
+        const int y = i / kCoefS, x = i - y * kCoefS;
+        const int gy = mirror_any(ty0 - kCoefK + y, H), gx = mirror_any(tx0 - kCoefK + x, W);
+        sIn[y][x] = src[(int64_t)gy * W + gx];
+    }
+    __syncthreads();
+    for (int i = tid; i < kCoefS * kCoefT; i += 256) {
+        const int y = i / kCoefT, x = i - y * kCoefT;
+        float acc = sH[0] * sIn[y][x + kCoefK];
+#pragma unroll
+        for (int k = 1; k <= kCoefK; k++) acc += sH[k] * (sIn[y][x + kCoefK - k] + sIn[y][x + kCoefK + k]);
+        sRow[y][x] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < kCoefT * kCoefT; i += 256) {
+        const int y = i / kCoefT, x = i - y * kCoefT;
+        if (ty0 + y >= H || tx0 + x >= W) continue;
+        float acc = sH[0] * sRow[y + kCoefK][x];
+#pragma unroll
+        for (int k = 1; k <= kCoefK; k++) acc += sH[k] * (sRow[y + kCoefK - k][x] + sRow[y + kCoefK + k][x]);
+        dst[(int64_t)(ty0 + y) * W + tx0 + x] = acc;
+    }
+}
+
+hipError_t launch_coef_images(const float* src, int64_t src_stride, int n, int H, int W, float* dst,
+                              hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int tiles = ((W + kCoefT - 1) / kCoefT) * ((H + kCoefT - 1) / kCoefT);
+    hipLaunchKernelGGL(k_bspline_coef, dim3(tiles, n), dim3(256), 0, s, src, src_stride, dst, H, W);
+    return hipGetLastError();
+}
+
+// Whole-image remap Rm(x') = I(pi(R^T r(x'))) of n images (stage entry):
+// INTERP 3 samples the cubic B-spline with coefficients `img`, 1 samples
+// `img` bilinearly.  grid (ceil(W / 64), H, n), 64 threads per row segment.
+template <int INTERP>
+__global__ void __launch_bounds__(64)
+    k_remap_stage(const float* __restrict__ img_all, int n, int H, int W, const double* __restrict__ Rall,
+                  double xs, double ys, double zs, float* __restrict__ out)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y, i = blockIdx.z;
+    if (x >= W || i >= n) return;
+    const double* Rf = Rall + 9 * (int64_t)i;
+    const float* img = img_all + (int64_t)i * H * W;
+    const double p0 = (double)x - xs, p1 = (double)y - ys, p2 = zs;
+    const double v0 = Rf[0] * p0 + Rf[3] * p1 + Rf[6] * p2;
+    const double v1 = Rf[1] * p0 + Rf[4] * p1 + Rf[7] * p2;
+    const double v2 = Rf[2] * p0 + Rf[5] * p1 + Rf[8] * p2;
+    const double sx = xs + zs * v0 / v2, sy = ys + zs * v1 / v2;
+    out[((int64_t)i * H + y) * W + x] = INTERP == 3 ? bspline_d(img, H, W, sx, sy) : bilinear_d(img, H, W, sx, sy);
 }
 
 template <int N>
@@ -298,8 +437,8 @@ __device__ void xcf_core(XcfShared<N>& S, Loader load, int window, float* q, flo
     }
 }
 
-template <int N>
-__global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk, int window)
+template <int N, int INTERP>
+__global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk, int window, int pass)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     XcfShared<N>& S = *reinterpret_cast<XcfShared<N>*>(smem);
@@ -309,7 +448,9 @@ __global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk,
     const float* Rn = bk->ref_pyr + (int64_t)bk->ref_slot[b] * bk->pyr_elems;
     const float* Tn = bk->test_pyr + (int64_t)b * bk->pyr_elems;
     const int x0 = bk->roi_xy[2 * j], y0 = bk->roi_xy[2 * j + 1];
-    const double* Rf = bk->Rfin + 9 * (int64_t)b;
+    // pass 0 remaps by R_finite, later passes by the previous pass's rotation
+    const double* Rf = (pass == 0 ? bk->Rfin : bk->R) + 9 * (int64_t)b;
+    const float* Cf = INTERP == 3 ? bk->ref_coef + (int64_t)bk->ref_slot[b] * H * W : nullptr;
     const double r00 = Rf[0], r01 = Rf[1], r02 = Rf[2], r10 = Rf[3], r11 = Rf[4], r12 = Rf[5],
                  r20 = Rf[6], r21 = Rf[7], r22 = Rf[8];
     const double xs = bk->xs, ys = bk->ys, zs = bk->zs;
@@ -321,7 +462,7 @@ __global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk,
         const double v1 = r01 * p0 + r11 * p1 + r21 * p2;
         const double v2 = r02 * p0 + r12 * p1 + r22 * p2;
         const double sx = xs + zs * v0 / v2, sy = ys + zs * v1 / v2;
-        const float a = bilinear_d(Rn, H, W, sx, sy);
+        const float a = INTERP == 3 ? bspline_d(Cf, H, W, sx, sy) : bilinear_d(Rn, H, W, sx, sy);
         const float t = Tn[(int64_t)Y * W + X];
         return make_float2(a, t);
     };
@@ -343,19 +484,31 @@ __global__ void __launch_bounds__(NT)
     xcf_core<N>(S, load, window, q + 2 * r, ph ? ph + r : nullptr);
 }
 
-template <int N>
-hipError_t launch_pairs_n(const Bucket* d_bk, int blocks, int window, hipStream_t s)
+template <int N, int INTERP>
+hipError_t launch_pairs_n(const Bucket* d_bk, int blocks, int window, int pass, hipStream_t s)
 {
     const size_t sm = sizeof(XcfShared<N>);
     static bool attr_set = false;  // a host attribute, set once (not a stream operation)
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_xcf_pairs<N>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_xcf_pairs<N, INTERP>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_xcf_pairs<N>, dim3(blocks), dim3(NT), sm, s, d_bk, window);
+    hipLaunchKernelGGL((k_xcf_pairs<N, INTERP>), dim3(blocks), dim3(NT), sm, s, d_bk, window, pass);
     return hipGetLastError();
+}
+
+template <int INTERP>
+hipError_t launch_pairs_i(const Bucket* d_bk, const Bucket& hb, int window, int pass, hipStream_t s)
+{
+    const int blocks = hb.nb * hb.n_roi;
+    switch (hb.roi_N) {
+    case 32: return launch_pairs_n<32, INTERP>(d_bk, blocks, window, pass, s);
+    case 64: return launch_pairs_n<64, INTERP>(d_bk, blocks, window, pass, s);
+    case 128: return launch_pairs_n<128, INTERP>(d_bk, blocks, window, pass, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int N>
@@ -372,15 +525,37 @@ hipError_t launch_stage_n(const float* A, const float* B, int n, int window, flo
 
 }  // namespace
 
-hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, hipStream_t s)
+hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, int interp, int pass,
+                            hipStream_t s)
 {
-    const int blocks = hb.nb * hb.n_roi;
-    switch (hb.roi_N) {
-    case 32: return launch_pairs_n<32>(d_bk, blocks, window, s);
-    case 64: return launch_pairs_n<64>(d_bk, blocks, window, s);
-    case 128: return launch_pairs_n<128>(d_bk, blocks, window, s);
-    default: return hipErrorInvalidValue;
+    if (interp == 3) {
+        if (!hb.ref_coef || hb.H < 3 || hb.W < 3) return hipErrorInvalidValue;
+        return launch_pairs_i<3>(d_bk, hb, window, pass, s);
     }
+    return launch_pairs_i<1>(d_bk, hb, window, pass, s);
+}
+
+hipError_t launch_bspline_coef(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
+{
+    (void)d_bk;
+    if (!hb.ref_coef || hb.nref == 0) return hipSuccess;
+    // level 0 of each (normalised) reference pyramid
+    return launch_coef_images(hb.ref_pyr, hb.pyr_elems, hb.nref, hb.H, hb.W, hb.ref_coef, s);
+}
+
+hipError_t launch_stage_remap(const float* ref, int n, int H, int W, const double* R, double xs, double ys,
+                              double zs, int interp, float* coef, float* out, hipStream_t s)
+{
+    if (interp == 3) {
+        hipError_t e = launch_coef_images(ref, (int64_t)H * W, n, H, W, coef, s);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((W + 63) / 64, H, n);
+    if (interp == 3)
+        hipLaunchKernelGGL((k_remap_stage<3>), grid, dim3(64), 0, s, coef, n, H, W, R, xs, ys, zs, out);
+    else
+        hipLaunchKernelGGL((k_remap_stage<1>), grid, dim3(64), 0, s, ref, n, H, W, R, xs, ys, zs, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_stage_xcf(const float* A, const float* B, int n, int N, int window, float* q,

@@ -53,6 +53,8 @@ class CParams(C.Structure):
         ("second_pass", C.c_int32),
         ("warm_start", C.c_int32),
         ("fallback_residual_px", C.c_float),
+        ("remap_interp", C.c_int32),
+        ("xcf_passes", C.c_int32),
     ]
 
 
@@ -91,7 +93,7 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_get_params", "ebsd_roi_layout", "ebsd_register_batch",
             "ebsd_register_batch_init", "ebsd_second_pass_batch", "ebsd_stage_normalize",
             "ebsd_stage_restrict", "ebsd_stage_demons_iter", "ebsd_stage_prolong",
-            "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_set_timing", "ebsd_get_timing",
+            "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_stage_remap", "ebsd_set_timing", "ebsd_get_timing",
             "ebsd_autotune", "ebsd_get_strip_height", "ebsd_set_strip_height", "ebsd_set_graphs",
             "ebsd_cnn_num_params", "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_set_params",
             "ebsd_cnn_get_params", "ebsd_cnn_get_grads", "ebsd_cnn_load", "ebsd_cnn_save",
@@ -135,6 +137,8 @@ def lib():
         L.ebsd_stage_xcf.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp]
         L.ebsd_stage_solve.argtypes = [vp, i32, i32, vp, vp, C.c_double, C.c_double, C.c_double,
                                        vp, vp, vp, vp]
+        L.ebsd_stage_remap.argtypes = [vp, i32, i32, i32, vp, C.c_double, C.c_double, C.c_double, i32,
+                                       vp, vp, vp]
         L.ebsd_cnn_num_params.restype = i64
         L.ebsd_cnn_create.argtypes = [C.c_int, i32, C.POINTER(vp)]
         L.ebsd_cnn_destroy.argtypes = [vp]
@@ -196,6 +200,8 @@ class Params:
     second_pass: int = 1
     warm_start: int = 0
     fallback_residual_px: float = 0.5
+    remap_interp: int = 3
+    xcf_passes: int = 1
 
     def to_c(self):
         p = CParams()
@@ -215,6 +221,8 @@ class Params:
         p.second_pass = self.second_pass
         p.warm_start = self.warm_start
         p.fallback_residual_px = self.fallback_residual_px
+        p.remap_interp = self.remap_interp
+        p.xcf_passes = self.xcf_passes
         return p
 
 
@@ -531,6 +539,20 @@ def stage_xcf(A, B, window=1):
     _check(lib().ebsd_stage_xcf(_ptr(A), _ptr(B), n, N, window, _ptr(q), _ptr(ph), _stream()),
            "ebsd_stage_xcf")
     return q, ph
+
+
+def stage_remap(img, R, pcs, interp=3):
+    """Remap of n images [n, H, W] by rotations R [n, 3, 3]: returns (out,
+    coef); coef holds the cubic B-spline coefficients (None for bilinear)."""
+    img = _dev_f32(img)
+    n, H, W = img.shape
+    R = torch.as_tensor(R, dtype=torch.float64).to(img.device).reshape(n, 9).contiguous()
+    out = torch.empty_like(img)
+    coef = torch.empty_like(img) if interp == 3 else None
+    _check(lib().ebsd_stage_remap(_ptr(img), n, H, W, _ptr(R), float(pcs[0]), float(pcs[1]), float(pcs[2]),
+                                  interp, _ptr(coef) if coef is not None else None, _ptr(out), _stream()),
+           "ebsd_stage_remap")
+    return out, coef
 
 
 def stage_solve(q, cx, cy, pcs):

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(E):
 
 def test_version_defaults_strerror(E):
     L = E.lib()
-    assert L.ebsd_version() == 2
+    assert L.ebsd_version() == 3
     p = E.CParams()
     assert L.ebsd_params_default(C.byref(p)) == 0
     assert p.struct_size == C.sizeof(E.CParams)
@@ -46,6 +46,12 @@ def test_version_defaults_strerror(E):
     assert abs(p.sigma_px - 1.0) < 1e-7 and p.n_roi == 20 and p.roi_size == 64
     assert p.window == 1 and p.second_pass == 1
     assert p.warm_start == 0 and abs(p.fallback_residual_px - 0.5) < 1e-7
+    assert p.remap_interp == 3 and p.xcf_passes == 1
+    # the defaults are exactly the Python mirror's (pattern centre and ring radius as doubles)
+    q = E.Params().to_c()
+    for f, _ in E.CParams._fields_:
+        a, b = getattr(p, f), getattr(q, f)
+        assert (list(a)[:3] == list(b)[:3]) if f == "max_iters" else a == b, f
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -99):
         assert len(L.ebsd_strerror(code)) > 0
 
@@ -59,7 +65,9 @@ def test_create_validates_before_touching_the_device(E):
     for field, val, code in [("sigma_px", -1.0, -1), ("sigma_px", 2.0, -1), ("levels", 0, -1),
                              ("levels", 9, -1), ("n_roi", 3, -1), ("roi_size", 48, -3),
                              ("window", 2, -1), ("pc_z", 0.0, -1), ("tol_px", float("nan"), -1),
-                             ("warm_start", 3, -1), ("fallback_residual_px", -1.0, -1)]:
+                             ("warm_start", 3, -1), ("fallback_residual_px", -1.0, -1),
+                             ("remap_interp", 2, -1), ("remap_interp", 0, -1), ("xcf_passes", 0, -1),
+                             ("xcf_passes", 17, -1)]:
         p = E.Params().to_c()
         setattr(p, field, val)
         assert L.ebsd_create(C.byref(p), 0, C.byref(h)) == code, field
@@ -98,6 +106,13 @@ def test_null_arguments_rejected(E):
     assert L.ebsd_stage_xcf(None, None, 1, 64, 1, None, None, None) == -1
     assert L.ebsd_stage_xcf(None, None, 0, 48, 1, None, None, None) == -3
     assert L.ebsd_stage_restrict(None, 0, 5, 8, None, None) == -2
+    fake = C.c_void_p(16)  # never dereferenced: validation fails first
+    assert L.ebsd_stage_remap(None, 1, 64, 64, None, 31.5, 31.5, 44.8, 3, None, None, None) == -1
+    assert L.ebsd_stage_remap(fake, 1, 64, 64, fake, 31.5, 31.5, 44.8, 3, None, fake, None) == -1  # no coef
+    assert L.ebsd_stage_remap(fake, 1, 64, 64, fake, 31.5, 31.5, 44.8, 2, fake, fake, None) == -1
+    assert L.ebsd_stage_remap(fake, 1, 64, 64, fake, 31.5, 31.5, 0.0, 1, None, fake, None) == -1
+    assert L.ebsd_stage_remap(fake, 1, 2, 64, fake, 31.5, 31.5, 44.8, 1, None, fake, None) == -2
+    assert L.ebsd_stage_remap(None, 0, 64, 64, None, 31.5, 31.5, 44.8, 3, None, None, None) == 0
     assert L.ebsd_destroy(None) == 0
 
 
