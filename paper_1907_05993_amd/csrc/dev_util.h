@@ -66,6 +66,17 @@ __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
 }
 
+// The same with a uniform byte offset `soff` (a scalar register, no vector
+// add).  Callers keep voff + soff inside the buffer.
+__device__ inline float bload_s(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ inline void bstore_s(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+
 // Bilinear sample through a buffer descriptor (image of h x w floats).
 // xc, yc are clamped to the image by fminf/fmaxf (NaN -> the bound), so the
 // floors need no further clamping.
@@ -109,6 +120,48 @@ __device__ inline Bilin bilinear_issue(__amdgpu_buffer_rsrc_t img, int h, int w,
     b.v11 = bload(img, o + dy + dx);
     return b;
 }
+// Per-level constants of the bilinear gather below.
+struct BilGeom {
+    float wm1, hm1;   // last column / row
+    float wm2, hm2;   // largest left / top corner: max(w - 2, 0), max(h - 2, 0)
+    float wf;         // row length
+    unsigned dx, dy;  // byte steps to the right / lower neighbours (0 for a 1-px dimension)
+};
+__device__ inline BilGeom bil_geom(int h, int w)
+{
+    BilGeom g;
+    g.wm1 = (float)(w - 1);
+    g.hm1 = (float)(h - 1);
+    g.wm2 = (float)max(w - 2, 0);
+    g.hm2 = (float)max(h - 2, 0);
+    g.wf = (float)w;
+    g.dx = w > 1 ? 4u : 0u;
+    g.dy = h > 1 ? 4u * (unsigned)w : 0u;
+    return g;
+}
+// Gather half of a bilinear sample whose 2 x 2 cell always lies inside the
+// image: the position is clamped to [0, w-1] x [0, h-1], the cell's corner to
+// [0, w-2] x [0, h-2], so a sample on the last column or row takes weight 1
+// on the far corner instead of weight 0 on a neighbour outside; blended with
+// lerp_ends (exact at both weights 0 and 1), it returns that pixel exactly.
+// One vector offset, the neighbours through the uniform byte steps
+// (y0 w + x0 < 2^24 is exact in the fma).
+__device__ inline Bilin bilinear_issue_g(__amdgpu_buffer_rsrc_t img, const BilGeom& g, float x, float y)
+{
+    Bilin b;
+    const float xc = fminf(fmaxf(x, 0.0f), g.wm1);
+    const float yc = fminf(fmaxf(y, 0.0f), g.hm1);
+    const float xf = fminf(floorf(xc), g.wm2), yf = fminf(floorf(yc), g.hm2);
+    b.fx = xc - xf;
+    b.fy = yc - yf;
+    const unsigned o = 4u * (unsigned)fmaf(yf, g.wf, xf);
+    b.v00 = bload_s(img, o, 0u);
+    b.v01 = bload_s(img, o, g.dx);
+    b.v10 = bload_s(img, o, g.dy);
+    b.v11 = bload_s(img, o, g.dx + g.dy);
+    return b;
+}
+
 // Lerps as a + f (b - a) with one rounding for the product-sum (fmaf): exact
 // for f = 0, and the same instruction sequence in every kernel variant (the
 // library is built without automatic contraction).
@@ -116,6 +169,14 @@ __device__ inline float lerpf(float a, float b, float f) { return fmaf(f, b - a,
 __device__ inline float bilinear_blend(const Bilin& b)
 {
     return lerpf(lerpf(b.v00, b.v01, b.fx), lerpf(b.v10, b.v11, b.fx), b.fy);
+}
+// Lerp as (a - f a) + f b with two fmas: returns a exactly for f = 0 and b
+// exactly for f = 1.
+__device__ inline float lerp_ends(float a, float b, float f) { return fmaf(f, b, fmaf(-f, a, a)); }
+// Blend of a bilinear_issue_g gather.
+__device__ inline float bilinear_blend_g(const Bilin& b)
+{
+    return lerp_ends(lerp_ends(b.v00, b.v01, b.fx), lerp_ends(b.v10, b.v11, b.fx), b.fy);
 }
 
 // Bilinear sample (lerp form, see lerpf) through a plain pointer.

@@ -6,7 +6,10 @@
 //   R = F (F^T F)^(-1/2), composition F = F_inf R_finite (Eq. (12)) and the
 //   rotation vector theta m (axis-angle after Eq. (5)) with theta from atan2 so
 //   small angles keep their digits.
-// One thread per pair: this is a few microseconds of FP64 work per batch.
+// One thread per pair.  The dense algebra with data-dependent indices (the
+// Jacobi eigen-solvers of the 9 x 9 and 8 x 8 systems) works on matrices in
+// LDS, one column of words per thread, so that no array goes to scratch
+// memory; the small fixed-index algebra stays in registers.
 #include "ebsd_internal.h"
 #include "cnn_internal.h"
 
@@ -17,20 +20,27 @@ namespace ebsd {
 namespace {
 
 // Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (destroyed);
-// columns of V are the eigenvectors.
+// columns of V are the eigenvectors.  Small n: every loop is unrolled so the
+// matrices stay in registers.
 template <int n>
 __device__ void jacobi_eigen(double (&A)[n][n], double (&ev)[n], double (&V)[n][n])
 {
+#pragma unroll
     for (int i = 0; i < n; i++)
+#pragma unroll
         for (int j = 0; j < n; j++) V[i][j] = i == j ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 60; sweep++) {
         double off = 0.0, diag = 0.0;
+#pragma unroll
         for (int i = 0; i < n; i++) {
             diag += A[i][i] * A[i][i];
+#pragma unroll
             for (int j = i + 1; j < n; j++) off += 2.0 * A[i][j] * A[i][j];
         }
         if (off == 0.0 || off <= 1e-30 * (off + diag)) break;
+#pragma unroll
         for (int p = 0; p < n - 1; p++)
+#pragma unroll
             for (int q = p + 1; q < n; q++) {
                 const double apq = A[p][q];
                 if (apq == 0.0) continue;
@@ -55,6 +65,61 @@ __device__ void jacobi_eigen(double (&A)[n][n], double (&ev)[n], double (&V)[n][
             }
     }
     for (int i = 0; i < n; i++) ev[i] = A[i][i];
+}
+
+// Threads per block of the kernels that run solve_F, and the LDS words each
+// thread needs for a 9 x 9 matrix and its eigenvectors.
+constexpr int kSolveThreads = 32;
+constexpr int kSolvePool = 2 * 81;
+
+// n x n matrix of one thread in LDS: element (i, j) at p[(i n + j) kSolveThreads],
+// p = block pool + thread index (the lanes of a wavefront read consecutive words).
+template <int n>
+struct LMat {
+    double* p;
+    __device__ double& operator()(int i, int j) const { return p[(i * n + j) * kSolveThreads]; }
+};
+
+// The same cyclic Jacobi iteration (same operation order, hence the same
+// results) on LDS matrices.
+template <int n>
+__device__ void jacobi_eigen_l(LMat<n> A, double (&ev)[n], LMat<n> V)
+{
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) V(i, j) = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; sweep++) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; i++) {
+            diag += A(i, i) * A(i, i);
+            for (int j = i + 1; j < n; j++) off += 2.0 * A(i, j) * A(i, j);
+        }
+        if (off == 0.0 || off <= 1e-30 * (off + diag)) break;
+        for (int p = 0; p < n - 1; p++)
+            for (int q = p + 1; q < n; q++) {
+                const double apq = A(p, q);
+                if (apq == 0.0) continue;
+                const double tau = (A(q, q) - A(p, p)) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = rsqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < n; k++) {
+                    const double akp = A(k, p), akq = A(k, q);
+                    A(k, p) = c * akp - s * akq;
+                    A(k, q) = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; k++) {
+                    const double apk = A(p, k), aqk = A(q, k);
+                    A(p, k) = c * apk - s * aqk;
+                    A(q, k) = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; k++) {
+                    const double vkp = V(k, p), vkq = V(k, q);
+                    V(k, p) = c * vkp - s * vkq;
+                    V(k, q) = s * vkp + c * vkq;
+                }
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < n; i++) ev[i] = A(i, i);
 }
 
 __device__ inline double det3(const double* F)
@@ -85,8 +150,10 @@ struct RoiSet {
 __device__ void gn_terms(const double* f, const RoiSet& rs, double (&JtJ)[8][8], double (&Jte)[8])
 {
     const int n = rs.n;
+#pragma unroll
     for (int a = 0; a < 8; a++) {
         Jte[a] = 0.0;
+#pragma unroll
         for (int b = 0; b < 8; b++) JtJ[a][b] = 0.0;
     }
     for (int i = 0; i < n; i++) {
@@ -101,12 +168,16 @@ __device__ void gn_terms(const double* f, const RoiSet& rs, double (&JtJ)[8][8],
         // d(u)/d theta and d(v)/d theta, theta = (F11..F23, F31, F32)
         double ju[8] = {r0 * id, r1 * id, id, 0.0, 0.0, 0.0, -u * r0 * id, -u * r1 * id};
         double jv[8] = {0.0, 0.0, 0.0, r0 * id, r1 * id, id, -v * r0 * id, -v * r1 * id};
+#pragma unroll
         for (int a = 0; a < 8; a++) {
             Jte[a] += ju[a] * ex + jv[a] * ey;
+#pragma unroll
             for (int b = a; b < 8; b++) JtJ[a][b] += ju[a] * ju[b] + jv[a] * jv[b];
         }
     }
+#pragma unroll
     for (int a = 0; a < 8; a++)
+#pragma unroll
         for (int b = 0; b < a; b++) JtJ[a][b] = JtJ[b][a];
 }
 
@@ -114,9 +185,12 @@ __device__ void gn_terms(const double* f, const RoiSet& rs, double (&JtJ)[8][8],
 __device__ bool cholesky_solve8(double (&M)[8][8], const double (&rhs)[8], double (&x)[8])
 {
     double Lm[8][8];
+#pragma unroll
     for (int i = 0; i < 8; i++)
+#pragma unroll
         for (int j = 0; j <= i; j++) {
             double s = M[i][j];
+#pragma unroll
             for (int k = 0; k < j; k++) s -= Lm[i][k] * Lm[j][k];
             if (i == j) {
                 if (!(s > 0.0)) return false;
@@ -126,13 +200,17 @@ __device__ bool cholesky_solve8(double (&M)[8][8], const double (&rhs)[8], doubl
             }
         }
     double y[8];
+#pragma unroll
     for (int i = 0; i < 8; i++) {
         double s = rhs[i];
+#pragma unroll
         for (int k = 0; k < i; k++) s -= Lm[i][k] * y[k];
         y[i] = s / Lm[i][i];
     }
+#pragma unroll
     for (int i = 7; i >= 0; i--) {
         double s = y[i];
+#pragma unroll
         for (int k = i + 1; k < 8; k++) s -= Lm[k][i] * x[k];
         x[i] = s / Lm[i][i];
     }
@@ -140,31 +218,41 @@ __device__ bool cholesky_solve8(double (&M)[8][8], const double (&rhs)[8], doubl
 }
 
 // Eq. (3) for one shift set.  Writes det-1 F (row-major), returns status bits.
-__device__ uint32_t solve_F(const RoiSet& rs, double* F)
+// pool: this thread's kSolvePool LDS words (stride kSolveThreads).
+__device__ uint32_t solve_F(const RoiSet& rs, double* F, double* pool)
 {
     const int n = rs.n;
     uint32_t st = 0;
     // direct linear start: null vector of the stacked constraints
-    double M[9][9];
+    double Mu[9][9];
+#pragma unroll
     for (int a = 0; a < 9; a++)
-        for (int b = 0; b < 9; b++) M[a][b] = 0.0;
+#pragma unroll
+        for (int b = 0; b < 9; b++) Mu[a][b] = 0.0;
     for (int i = 0; i < n; i++) {
         double rx, ry, px, py;
         rs.get(i, rx, ry, px, py);
         const double ra[9] = {rx, ry, 1.0, 0.0, 0.0, 0.0, -px * rx, -px * ry, -px};
         const double rb[9] = {0.0, 0.0, 0.0, rx, ry, 1.0, -py * rx, -py * ry, -py};
+#pragma unroll
         for (int a = 0; a < 9; a++)
-            for (int b = a; b < 9; b++) M[a][b] += ra[a] * ra[b] + rb[a] * rb[b];
+#pragma unroll
+            for (int b = a; b < 9; b++) Mu[a][b] += ra[a] * ra[b] + rb[a] * rb[b];
     }
+    const LMat<9> M{pool}, V{pool + 81 * kSolveThreads};
+#pragma unroll
     for (int a = 0; a < 9; a++)
-        for (int b = 0; b < a; b++) M[a][b] = M[b][a];
-    double ev[9], V[9][9];
-    jacobi_eigen<9>(M, ev, V);
+#pragma unroll
+        for (int b = 0; b < 9; b++) M(a, b) = b >= a ? Mu[a][b] : Mu[b][a];
+    double ev[9];
+    jacobi_eigen_l<9>(M, ev, V);
     int k = 0;
+#pragma unroll
     for (int i = 1; i < 9; i++)
         if (ev[i] < ev[k]) k = i;
     double f[9];
-    for (int i = 0; i < 9; i++) f[i] = V[i][k];
+#pragma unroll
+    for (int i = 0; i < 9; i++) f[i] = V(i, k);
     if (f[8] == 0.0) {
         st |= EBSD_SOLVE_ILLCOND;
         f[8] = 1.0;
@@ -194,8 +282,15 @@ __device__ uint32_t solve_F(const RoiSet& rs, double* F)
         if (sqrt(nrm) < 1e-14) break;
     }
     gn_terms(f, rs, JtJ, Jte);
-    double e8[8], V8[8][8];
-    jacobi_eigen<8>(JtJ, e8, V8);
+    double e8[8];
+    {
+        const LMat<8> A8{pool}, V8{pool + 64 * kSolveThreads};
+#pragma unroll
+        for (int a = 0; a < 8; a++)
+#pragma unroll
+            for (int b = 0; b < 8; b++) A8(a, b) = JtJ[a][b];
+        jacobi_eigen_l<8>(A8, e8, V8);
+    }
     double lo = e8[0], hi = e8[0];
     for (int a = 1; a < 8; a++) {
         lo = fmin(lo, e8[a]);
@@ -263,8 +358,9 @@ __device__ RoiSet bucket_rois(const Bucket* bk, const float* q)
     return rs;
 }
 
-__global__ void k_solve_first(const Bucket* __restrict__ bk, float tol)
+__global__ void __launch_bounds__(kSolveThreads) k_solve_first(const Bucket* __restrict__ bk, float tol)
 {
+    __shared__ double pool[kSolvePool * kSolveThreads];
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= bk->nb) return;
     uint32_t st = bk->test_stat[b].flags | bk->ref_stat[bk->ref_slot[b]].flags;
@@ -275,7 +371,7 @@ __global__ void k_solve_first(const Bucket* __restrict__ bk, float tol)
         else st |= EBSD_HIT_CAP;
     }
     double* F1 = bk->F1 + 9 * (int64_t)b;
-    st |= solve_F(bucket_rois(bk, bk->q1 + 2 * (int64_t)b * bk->n_roi), F1);
+    st |= solve_F(bucket_rois(bk, bk->q1 + 2 * (int64_t)b * bk->n_roi), F1, pool + threadIdx.x);
     polar_rot(F1, bk->Rfin + 9 * (int64_t)b);
     bk->status[b] = st;
 }
@@ -290,8 +386,10 @@ __global__ void k_status_inputs(const Bucket* __restrict__ bk)
 
 // pass 0 composes with R_finite (Eq. (12)); pass k > 0 with the rotation
 // the previous pass left in R (read before R is overwritten).
-__global__ void k_solve_second(const Bucket* __restrict__ bk, int second_pass, int pass)
+__global__ void __launch_bounds__(kSolveThreads)
+    k_solve_second(const Bucket* __restrict__ bk, int second_pass, int pass)
 {
+    __shared__ double pool[kSolvePool * kSolveThreads];
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= bk->nb) return;
     double Rf[9];
@@ -301,7 +399,7 @@ __global__ void k_solve_second(const Bucket* __restrict__ bk, int second_pass, i
     uint32_t st = bk->status[b];
     if (second_pass) {
         double Fi[9];
-        st |= solve_F(bucket_rois(bk, bk->q2 + 2 * (int64_t)b * bk->n_roi), Fi);
+        st |= solve_F(bucket_rois(bk, bk->q2 + 2 * (int64_t)b * bk->n_roi), Fi, pool + threadIdx.x);
         double Ft[9];
         for (int i = 0; i < 3; i++)
             for (int j = 0; j < 3; j++)
@@ -322,11 +420,12 @@ __global__ void k_solve_second(const Bucket* __restrict__ bk, int second_pass, i
     bk->status[b] = st;
 }
 
-__global__ void k_stage_solve(const float* __restrict__ q, int n, int n_roi,
+__global__ void __launch_bounds__(kSolveThreads) k_stage_solve(const float* __restrict__ q, int n, int n_roi,
                               const double* __restrict__ cx, const double* __restrict__ cy,
                               double xs, double ys, double zs, double* __restrict__ F,
                               double* __restrict__ R, uint32_t* __restrict__ status)
 {
+    __shared__ double pool[kSolvePool * kSolveThreads];
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
     RoiSet rs;
@@ -338,7 +437,7 @@ __global__ void k_stage_solve(const float* __restrict__ q, int n, int n_roi,
     rs.xs = xs;
     rs.ys = ys;
     rs.iz = 1.0 / zs;
-    uint32_t st = solve_F(rs, F + 9 * (int64_t)b);
+    uint32_t st = solve_F(rs, F + 9 * (int64_t)b, pool + threadIdx.x);
     if (R) polar_rot(F + 9 * (int64_t)b, R + 9 * (int64_t)b);
     if (status) status[b] = st;
 }
@@ -637,7 +736,8 @@ hipError_t launch_scatter_warm(const Bucket* d_bk, const Bucket& hb, hipStream_t
 
 hipError_t launch_solve_first(const Bucket* d_bk, const Bucket& hb, float tol, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_solve_first, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, tol);
+    hipLaunchKernelGGL(k_solve_first, dim3((hb.nb + kSolveThreads - 1) / kSolveThreads), dim3(kSolveThreads), 0, s,
+                       d_bk, tol);
     return hipGetLastError();
 }
 
@@ -650,7 +750,8 @@ hipError_t launch_status_inputs(const Bucket* d_bk, const Bucket& hb, hipStream_
 hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass, int pass,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_solve_second, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, second_pass, pass);
+    hipLaunchKernelGGL(k_solve_second, dim3((hb.nb + kSolveThreads - 1) / kSolveThreads), dim3(kSolveThreads), 0,
+                       s, d_bk, second_pass, pass);
     return hipGetLastError();
 }
 
@@ -658,7 +759,8 @@ hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx
                               double xs, double ys, double zs, double* F, double* R,
                               uint32_t* status, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stage_solve, dim3((n + 63) / 64), dim3(64), 0, s, q, n, n_roi, cx, cy, xs,
+    hipLaunchKernelGGL(k_stage_solve, dim3((n + kSolveThreads - 1) / kSolveThreads), dim3(kSolveThreads), 0, s, q,
+                       n, n_roi, cx, cy, xs,
                        ys, zs, F, R, status);
     return hipGetLastError();
 }
