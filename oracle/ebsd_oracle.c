@@ -24,7 +24,7 @@
  *   XCF              zero mean, Hann window, FFT, F_test . conj(F_ref), IFFT,
  *                    interpolated peak (section 2)
  *   compose          Eq. (12): F = F_inf R_finite; optional further passes
- *                    remap by the rotation of the previous pass's F
+ *                    remap by the previous pass's F and compose with it
  *   rotation vector  axis-angle of R (the passage after Eq. 5, Eq. 6)
  *
  * Readings where the paper is silent or ambiguous (sign of the force, which
@@ -493,6 +493,23 @@ static double det3(const double* F)
            F[2] * (F[3] * F[7] - F[4] * F[6]);
 }
 
+/* (A^-1)^T = cofactor matrix / det A (row-major); A must be invertible. */
+static void inv3_transposed(const double* A, double* out)
+{
+    double c[9];
+    c[0] = A[4] * A[8] - A[5] * A[7];
+    c[1] = A[5] * A[6] - A[3] * A[8];
+    c[2] = A[3] * A[7] - A[4] * A[6];
+    c[3] = A[2] * A[7] - A[1] * A[8];
+    c[4] = A[0] * A[8] - A[2] * A[6];
+    c[5] = A[1] * A[6] - A[0] * A[7];
+    c[6] = A[1] * A[5] - A[2] * A[4];
+    c[7] = A[2] * A[3] - A[0] * A[5];
+    c[8] = A[0] * A[4] - A[1] * A[3];
+    double det = A[0] * c[0] + A[1] * c[1] + A[2] * c[2];
+    for (int i = 0; i < 9; i++) out[i] = c[i] / det;
+}
+
 static void matmul3(const double* A, const double* B, double* C)
 {
     double t[9];
@@ -790,7 +807,8 @@ void orc_bspline_points(const double* c, int H, int W, const double* xs, const d
  *   Rm(x') = ref(pi(R^T r(x'))),  r(x) = (x - x*, y - y*, Z*),
  *   pi(v) = (x* + Z* v_x/v_z, y* + Z* v_y/v_z);
  * interp 3: cubic B-spline interpolation (above), interp 1: bilinear; both
- * clamp the sample position to the pattern. */
+ * clamp the sample position to the pattern.  With R = (F^-1)^T for a
+ * deformation gradient F the same map remaps by F (pi is scale-invariant). */
 void orc_remap(const double* ref, int H, int W, const double* Rf, double xs, double ys,
                double zs, int interp, double* out)
 {
@@ -967,8 +985,8 @@ void orc_xcf(const double* A, const double* B, int N, int window, double* C, dou
  *   XCF per ROI -> q2 -> F_inf (Eq. 3) -> F = F_inf R_finite (Eq. 12),
  *   det F = 1 -> R = polar(F) -> rotation vector.
  * With xcf_passes = P > 1 the remap + XCF + compose step runs P times, pass
- * k remapping by polar(F) of pass k-1 in place of R_finite; q2 and ph are
- * the last pass's.
+ * k remapping by the whole F of pass k-1 in place of R_finite and composing
+ * F_inf with that F; q2 and ph are the last pass's.
  * rfin_in (optional) replaces the first pass's R_finite: it lets the second
  * pass be checked in isolation against another implementation's R_finite.
  * Any output pointer may be NULL.                                         */
@@ -1024,11 +1042,14 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
     orc_polar(F1, Rfin);
     if (rfin_in) memcpy(Rfin, rfin_in, sizeof Rfin);
     if (p->second_pass) {
-        /* pass 1 remaps by R_finite; each further pass remaps by the rotation
-         * of the F the previous pass found and composes with it. */
+        /* pass 1 remaps by R_finite and composes with it (Eq. 12); each
+         * further pass remaps by the whole F of the previous pass, the source
+         * direction of x' being F^-1 r(x') (orc_remap with (F^-1)^T), and
+         * composes with that F. */
         int passes = p->xcf_passes > 1 ? p->xcf_passes : 1;
-        double Rcur[9];
+        double Rcur[9], Fprev[9];
         memcpy(Rcur, Rfin, sizeof Rcur);
+        memcpy(Fprev, Rfin, sizeof Fprev);
         double* Rm = (double*)malloc(sizeof(double) * HW);
         double* a = (double*)malloc(sizeof(double) * N * N);
         double* b = (double*)malloc(sizeof(double) * N * N);
@@ -1044,9 +1065,10 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
             }
             double Finf[9];
             st |= orc_solve_F(q2, cx, cy, nr, xs, ys, zs, Finf);
-            matmul3(Finf, Rcur, F);
+            matmul3(Finf, Fprev, F);
             if (det3(F) > 0.0) orc_det_normalize(F);
-            orc_polar(F, Rcur);
+            memcpy(Fprev, F, sizeof Fprev);
+            inv3_transposed(F, Rcur);
         }
         free(Rm);
         free(a);

@@ -467,23 +467,44 @@ def test_pipeline_identical_pair(orc):
     np.testing.assert_allclose(out["ph"][0], 1.0, atol=1e-12)
 
 
-@pytest.mark.parametrize("angle,seed", [(1e-4, 0), (1e-3, 1), (1e-3, 2), (math.radians(2.0), 3)])
-def test_pipeline_recovers_known_small_rotation(orc, angle, seed):
-    """Noise-free 256 px pair (rich band set, random crystal orientation)
-    whose test pattern is the reference seen through a known rotation about
-    a random axis: demons + 8 remap/XCF passes with the cubic remap recover
-    the rotation vector to better than 1e-5 rad."""
+KNOWN_ROTATION_CASES = [("axis", 1e-4, 0), ("axis", 1e-3, 1), ("axis", 1e-3, 2), ("axis", math.radians(2.0), 3),
+                        ("z", 1e-3, 4), ("z", math.radians(2.0), 5), ("affine", math.radians(2.0), 6),
+                        ("affine", 1e-3, 7)]
+
+
+def known_rotation_pair(kind, angle, seed):
+    """Noise-free 256 px pair (rich band set, flat background, random crystal
+    orientation) whose test pattern is the reference seen through F: a
+    rotation about a random axis or about z, or that rotation times a
+    symmetric strain with components in +-1e-3 ("affine")."""
     from paper_1907_05993_amd import synth as S
     r = np.random.default_rng(100 + seed)
     G = S.random_rotation(r)
-    F = S.axis_angle_matrix(S.random_axis(r), angle)
+    if kind == "z":
+        F = Rotation.from_rotvec([0.0, 0.0, angle]).as_matrix()
+    else:
+        F = S.axis_angle_matrix(S.random_axis(r), angle)
+    if kind == "affine":
+        F = (np.eye(3) + S.strain_matrix(r, 1e-3)) @ F
     spec = S.PairSpec(H=256, W=256, G=G, F=F, gxy=(0.0, 0.0), noise=False, bands="rich")
     ref, test = S.render_pair(spec)
-    truth = Rotation.from_matrix(F).as_rotvec()
+    return ref, test, F
+
+
+@pytest.mark.parametrize("kind,angle,seed", KNOWN_ROTATION_CASES)
+def test_pipeline_recovers_known_small_rotation(orc, kind, angle, seed):
+    """Demons + 8 remap/XCF passes (cubic remap) recover the rotation of F to
+    better than 1e-5 rad; for the affine cases the isochoric F as well."""
+    ref, test, F = known_rotation_pair(kind, angle, seed)
+    Rt = scipy.linalg.polar(F)[0]
+    truth = Rotation.from_matrix(Rt).as_rotvec()
     p = orc.make_params(levels=3, iters=50, sigma=1.0, roi_size=64, n_roi=20, xcf_passes=8)
     out = orc.register_batch(ref, test, p, want_field=False)
     err = np.linalg.norm(out["rotvec"][0] - truth)
+    dF = np.abs(out["F"][0] - F / np.cbrt(np.linalg.det(F))).max()
+    print(f"{kind} {angle:.1e}: rotation error {err:.2e} rad, max |dF| {dF:.2e}")
     assert err < 1e-5, err
+    assert dF < 2e-5, dF
     # a single pass leaves more (the sub-pixel fit under-reads the residual)
     one = orc.register_batch(ref, test, orc.make_params(levels=3, iters=50, sigma=1.0, roi_size=64,
                                                         n_roi=20), want_field=False)
