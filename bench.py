@@ -257,6 +257,7 @@ def main():
         p1 = ebsd.Params(levels=3, iters=(100, 100, 100), sigma_px=1.0, tol_px=0.0, roi_size=32, n_roi=20)
         reg1 = ebsd.Registrar(p1, device=0)
         reg1.set_graphs(not args.no_graphs)
+        reg1.autotune(r1, t1)  # strip heights for this one-pair batch
         for _ in range(3):
             reg1.register(r1, t1, want_field=False)
         torch.cuda.synchronize()

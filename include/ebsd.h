@@ -94,7 +94,8 @@ typedef struct ebsd_params {
     int32_t remap_interp;                 /* remap before the XCF (section 2, before Eq. (12)): 3 = cubic
                                              B-spline interpolation (the paper's cubic scheme), 1 = bilinear */
     int32_t xcf_passes;                   /* remap + XCF + Eq. (12) passes, 1..16: pass 1 remaps by R_finite
-                                             (the paper's method), pass k > 1 by the rotation of pass k-1's F */
+                                             and composes with it (the paper's method), pass k > 1 remaps by
+                                             pass k-1's F and composes with that F */
 } ebsd_params;
 
 /* One scan point.  ref/test: device pointers to H x W fp32 patterns.  Pairs
@@ -207,7 +208,9 @@ int ebsd_autotune(ebsd_handle* h, const ebsd_pair* pairs, int32_t n, void* strea
 int ebsd_set_graphs(ebsd_handle* h, int enable);
 
 /* Strip height used for a pyramid level of level_h x level_w px (0 if that
- * level uses the 2-D tile kernel, i.e. wider than 256 px). */
+ * level uses the 2-D tile kernel, i.e. wider than 256 px): the tuned or
+ * forced value, else 64.  Untuned levels of a batch with fewer than 512
+ * strips of 64 rows use 32 or 16 rows (more workgroups for small batches). */
 int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w);
 
 /* Force the strip height (16, 32, 64 or 128) for a level size. */

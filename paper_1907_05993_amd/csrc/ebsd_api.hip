@@ -60,10 +60,18 @@ struct ebsd_handle {
 
 namespace {
 
-int strip_ty_for(const ebsd_handle* h, int lh, int lw)
+// Strip height of the row-marching kernel for a level: the tuned or forced
+// value, else kDefaultStripTY when the batch has enough strips to fill the
+// device (>= 2 per compute unit), else the tallest of 32, 16 rows that does,
+// or 16 (a small batch is latency-bound: shorter strips, more workgroups).
+int strip_ty_for(const ebsd_handle* h, int lh, int lw, int nb = 1 << 20)
 {
     auto it = h->strip_ty.find(std::make_pair(lh, lw));
-    return it == h->strip_ty.end() ? kDefaultStripTY : it->second;
+    if (it != h->strip_ty.end()) return it->second;
+    constexpr int kFill = 512;
+    for (int ty = kDefaultStripTY; ty > kMinStripTY; ty /= 2)
+        if ((int64_t)nb * ((lh + ty - 1) / ty) >= kFill) return ty;
+    return kMinStripTY;
 }
 
 int fused_ty_for(const ebsd_handle* h, int lh, int lw)
@@ -628,7 +636,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     if (mode == Mode::Full) {
         EBSD_TRY(launch_demons_init(d_bk, b, s));
         for (int l = L - 1; l >= 0; l--) {
-            const int ty = strip_ty_for(h, H >> l, W >> l);
+            const int ty = strip_ty_for(h, H >> l, W >> l, nb);
             const int fty = fused_ty_for(h, H >> l, W >> l);
             if (tm) EBSD_TRY(hipEventRecord(h->ev[2 + 2 * l], s));
             const int e = run_level(l, ty, fty);

@@ -133,7 +133,7 @@ hipError_t launch_status_inputs(const Bucket* d_bk, const Bucket& hb, hipStream_
 // Cubic B-spline coefficients of level 0 of every reference -> bk->ref_coef.
 hipError_t launch_bspline_coef(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Remap + ROI XCF for every (pair, ROI) -> q2, ph.  interp 3: cubic B-spline
-// from bk->ref_coef, 1: bilinear; pass 0 remaps by Rfin, pass k > 0 by R.
+// from bk->ref_coef, 1: bilinear; pass 0 remaps by Rfin, pass k > 0 by F.
 hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, int interp, int pass,
                             hipStream_t s);
 // Rfin[b] = bk->rfin_in[pair_index[b]] (second-pass-only entry).
@@ -142,7 +142,7 @@ hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Copy the warm-start field and misfit of every pair to the caller's outputs.
 hipError_t launch_scatter_warm(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Second-pass solve: F_inf from q2, F = F_inf M, det 1, R = polar(F), rotvec,
-// with M = Rfin for pass 0 and M = R (the previous pass's) after.
+// with M = Rfin for pass 0 and M = F (the previous pass's) after.
 // second_pass == 0: F = F1.
 hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass, int pass,
                                hipStream_t s);

@@ -384,8 +384,8 @@ __global__ void k_status_inputs(const Bucket* __restrict__ bk)
     bk->status[b] = bk->test_stat[b].flags | bk->ref_stat[bk->ref_slot[b]].flags;
 }
 
-// pass 0 composes with R_finite (Eq. (12)); pass k > 0 with the rotation
-// the previous pass left in R (read before R is overwritten).
+// pass 0 composes with R_finite (Eq. (12)); pass k > 0 with the F the
+// previous pass left in F (read before F is overwritten).
 __global__ void __launch_bounds__(kSolveThreads)
     k_solve_second(const Bucket* __restrict__ bk, int second_pass, int pass)
 {
@@ -393,7 +393,7 @@ __global__ void __launch_bounds__(kSolveThreads)
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= bk->nb) return;
     double Rf[9];
-    const double* Rsrc = (pass == 0 ? bk->Rfin : bk->R) + 9 * (int64_t)b;
+    const double* Rsrc = (pass == 0 ? bk->Rfin : bk->F) + 9 * (int64_t)b;
     for (int i = 0; i < 9; i++) Rf[i] = Rsrc[i];
     double* F = bk->F + 9 * (int64_t)b;
     uint32_t st = bk->status[b];

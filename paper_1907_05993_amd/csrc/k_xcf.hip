@@ -448,11 +448,30 @@ __global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk,
     const float* Rn = bk->ref_pyr + (int64_t)bk->ref_slot[b] * bk->pyr_elems;
     const float* Tn = bk->test_pyr + (int64_t)b * bk->pyr_elems;
     const int x0 = bk->roi_xy[2 * j], y0 = bk->roi_xy[2 * j + 1];
-    // pass 0 remaps by R_finite, later passes by the previous pass's rotation
-    const double* Rf = (pass == 0 ? bk->Rfin : bk->R) + 9 * (int64_t)b;
+    // pass 0 remaps by R_finite: source direction R^T r; a later pass by the
+    // previous pass's F: source direction F^-1 r, i.e. the same map with
+    // (F^-1)^T = cofactor(F) / det F in place of R
     const float* Cf = INTERP == 3 ? bk->ref_coef + (int64_t)bk->ref_slot[b] * H * W : nullptr;
-    const double r00 = Rf[0], r01 = Rf[1], r02 = Rf[2], r10 = Rf[3], r11 = Rf[4], r12 = Rf[5],
-                 r20 = Rf[6], r21 = Rf[7], r22 = Rf[8];
+    double m[9];
+    if (pass == 0) {
+        const double* Rf = bk->Rfin + 9 * (int64_t)b;
+        for (int i = 0; i < 9; i++) m[i] = Rf[i];
+    } else {
+        const double* A = bk->F + 9 * (int64_t)b;
+        m[0] = A[4] * A[8] - A[5] * A[7];
+        m[1] = A[5] * A[6] - A[3] * A[8];
+        m[2] = A[3] * A[7] - A[4] * A[6];
+        m[3] = A[2] * A[7] - A[1] * A[8];
+        m[4] = A[0] * A[8] - A[2] * A[6];
+        m[5] = A[1] * A[6] - A[0] * A[7];
+        m[6] = A[1] * A[5] - A[2] * A[4];
+        m[7] = A[2] * A[3] - A[0] * A[5];
+        m[8] = A[0] * A[4] - A[1] * A[3];
+        const double det = A[0] * m[0] + A[1] * m[1] + A[2] * m[2];
+        for (int i = 0; i < 9; i++) m[i] /= det;
+    }
+    const double r00 = m[0], r01 = m[1], r02 = m[2], r10 = m[3], r11 = m[4], r12 = m[5],
+                 r20 = m[6], r21 = m[7], r22 = m[8];
     const double xs = bk->xs, ys = bk->ys, zs = bk->zs;
     auto load = [&](int x, int y) -> float2 {
         const int X = x0 + x, Y = y0 + y;
