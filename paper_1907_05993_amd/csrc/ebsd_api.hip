@@ -406,6 +406,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const bool xcf = mode == Mode::SecondPassOnly || p.second_pass;
     const bool cubic = xcf && p.remap_interp == 3 && !tune_only;
     const size_t o_coef = w.take(cubic ? sizeof(float) * (size_t)nref * H * W : 0);
+    const size_t o_coef_tmp = w.take(cubic ? sizeof(float) * (size_t)nref * H * W : 0);
     const bool warm = mode == Mode::Full && !tune_only && !u_init && p.warm_start;
     const int64_t gcell = (int64_t)(H >> 2) * (W >> 2);  // coarse grid of the pattern
     const int64_t ncell = (int64_t)(kWarmRes / 4) * (kWarmRes / 4);  // the network's output grid
@@ -442,6 +443,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.rotvec = reinterpret_cast<double*>(base + o_rv);
     b.status = reinterpret_cast<uint32_t*>(base + o_st);
     b.ref_coef = cubic ? reinterpret_cast<float*>(base + o_coef) : nullptr;
+    b.coef_tmp = cubic ? reinterpret_cast<float*>(base + o_coef_tmp) : nullptr;
 
     bool want_field = mode == Mode::Full && out->field;
     b.out.F = out->F;

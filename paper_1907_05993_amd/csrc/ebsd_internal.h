@@ -86,6 +86,7 @@ struct Bucket {
     double* rotvec;             // [nb][3]
     uint32_t* status;           // [nb]
     float* ref_coef;            // [nref][H][W] cubic B-spline coefficients of level 0 (NULL: bilinear remap)
+    float* coef_tmp;            // [nref][H][W] row pass of the coefficients
     // per-call caller pointers (so that a bucket's launch sequence is static
     // and can be replayed from a captured graph)
     OutPtrs out;                // results, scattered by pair_index

@@ -6,7 +6,7 @@
 // One 256-thread workgroup per (pair, ROI), N in {32, 64, 128}:
 //   gather   reference ROI remapped on the fly, Rm(x') = R0(pi(R_finite^T r(x'))),
 //            interpolated by the cubic B-spline (the paper's cubic scheme,
-//            coefficients from k_bspline_coef) or bilinearly, and test ROI,
+//            coefficients from k_bspline_rows / k_bspline_cols) or bilinearly, and test ROI,
 //            packed as z = a + i b (one complex FFT serves both);
 //   window   per-ROI mean removed, symmetric Hann window h (x) h;
 //   FFT      2-D radix-2 in LDS: decimation-in-frequency forward (natural in,
@@ -19,6 +19,8 @@
 //            peak height C0 / sqrt(sum (a)^2 sum (b)^2).
 // The N x N complex tile (padded rows) is LDS resident: 132 KiB at N = 128.
 // Twiddles and the window are evaluated per block in FP64 and rounded.
+#include <algorithm>
+
 #include "ebsd_internal.h"
 
 namespace ebsd {
@@ -115,16 +117,20 @@ __device__ inline float bspline_d(const float* __restrict__ c, int h, int w, dou
     return acc;
 }
 
-// Cubic B-spline coefficients of level 0 of every reference (whole-sample
-// mirror extension).  Along one line the coefficients are the samples
-// filtered by the inverse of (1, 4, 1)/6, whose impulse response is
-// sqrt(3) z^|k| with z = sqrt(3) - 2; it is applied here as a 31-tap FIR
-// (|k| <= 15; the dropped tail is below 3.4e-9 of the largest sample), rows
-// then columns, on 64 x 64 output tiles with a 15 px mirrored halo in LDS.
-// grid: (tiles of the image, images); image i is src + i * src_stride (H x W
-// floats, row-major) -> dst + i * H * W; 256 threads.
-constexpr int kCoefT = 64, kCoefK = 15, kCoefS = kCoefT + 2 * kCoefK;
+// Cubic B-spline coefficients of images (whole-sample mirror extension).
+// Along one line the coefficients are the samples filtered by the inverse of
+// (1, 4, 1)/6: a causal recursion c+[k] = s[k] + z c+[k-1] followed by an
+// anti-causal one c-[k] = z (c-[k+1] - c+[k]), c = 6 c-, pole z = sqrt(3) - 2.
+// Each thread produces 32 consecutive outputs of one line: it starts the
+// causal recursion 16 samples before its block and the anti-causal one 16
+// after it, both from zero, on the mirror-extended line; the starting values
+// it drops weigh |z|^16 < 7.1e-10 (times at most 1.4 max|s|), so the result
+// equals the exact filtering of the mirror extension to FP32 rounding.  Rows
+// first (image -> tmp), then columns (tmp -> dst); consecutive lanes take
+// consecutive rows (row pass) or columns (column pass).
+constexpr int kCoefB = 32, kCoefWarm = 16;
 
+// Whole-sample mirror of any index into [0, n - 1].
 __device__ inline int mirror_any(int i, int n)
 {
     if (n == 1) return 0;
@@ -134,54 +140,104 @@ __device__ inline int mirror_any(int i, int n)
     return m < n ? m : P - m;
 }
 
-__global__ void __launch_bounds__(256)
-    k_bspline_coef(const float* __restrict__ src_all, int64_t src_stride, float* __restrict__ dst_all, int H,
-                   int W)
+// One line of n samples at stride `st` (elements) from `in` into `out`,
+// outputs a .. a + kCoefB - 1 (those inside the line).
+__device__ inline void bspline_line_block(const float* __restrict__ in, float* __restrict__ out, int n, int64_t st,
+                                          int a)
 {
-    __shared__ float sIn[kCoefS][kCoefS + 1];
-    __shared__ float sRow[kCoefS][kCoefT + 1];
-    __shared__ float sH[kCoefK + 1];
-    const int tiles_x = (W + kCoefT - 1) / kCoefT;
-    const int tx0 = (blockIdx.x % tiles_x) * kCoefT, ty0 = (blockIdx.x / tiles_x) * kCoefT;
-    const float* src = src_all + (int64_t)blockIdx.y * src_stride;
-    float* dst = dst_all + (int64_t)blockIdx.y * H * W;
-    const int tid = threadIdx.x;
-    if (tid <= kCoefK) {
-        const double z = sqrt(3.0) - 2.0;
-        double v = sqrt(3.0);
-        for (int j = 0; j < tid; j++) v *= z;
-        sH[tid] = (float)v;
-    }
-    for (int i = tid; i < kCoefS * kCoefS; i += 256) {
-        const int y = i / kCoefS, x = i - y * kCoefS;
-        const int gy = mirror_any(ty0 - kCoefK + y, H), gx = mirror_any(tx0 - kCoefK + x, W);
-        sIn[y][x] = src[(int64_t)gy * W + gx];
-    }
-    __syncthreads();
-    for (int i = tid; i < kCoefS * kCoefT; i += 256) {
-        const int y = i / kCoefT, x = i - y * kCoefT;
-        float acc = sH[0] * sIn[y][x + kCoefK];
+    const float z = -0.267949192431122706f;  // sqrt(3) - 2
+    float cp = 0.0f, buf[kCoefB + kCoefWarm];
+    if (n > kCoefWarm + kCoefB) {
+        // one reflection covers indices a - 16 .. a + 47 (a <= n - 1)
 #pragma unroll
-        for (int k = 1; k <= kCoefK; k++) acc += sH[k] * (sIn[y][x + kCoefK - k] + sIn[y][x + kCoefK + k]);
-        sRow[y][x] = acc;
-    }
-    __syncthreads();
-    for (int i = tid; i < kCoefT * kCoefT; i += 256) {
-        const int y = i / kCoefT, x = i - y * kCoefT;
-        if (ty0 + y >= H || tx0 + x >= W) continue;
-        float acc = sH[0] * sRow[y + kCoefK][x];
+        for (int j = 0; j < kCoefB + 3 * kCoefWarm; j++) {
+            int k = a - kCoefWarm + j;
+            k = k < 0 ? -k : (k > n - 1 ? 2 * n - 2 - k : k);
+            cp = in[(int64_t)k * st] + z * cp;
+            if (j >= kCoefWarm) buf[j - kCoefWarm] = cp;
+        }
+    } else {
 #pragma unroll
-        for (int k = 1; k <= kCoefK; k++) acc += sH[k] * (sRow[y + kCoefK - k][x] + sRow[y + kCoefK + k][x]);
-        dst[(int64_t)(ty0 + y) * W + tx0 + x] = acc;
+        for (int j = 0; j < kCoefB + 3 * kCoefWarm; j++) {
+            cp = in[(int64_t)mirror_any(a - kCoefWarm + j, n) * st] + z * cp;
+            if (j >= kCoefWarm) buf[j - kCoefWarm] = cp;
+        }
+    }
+    float cm = 0.0f;
+#pragma unroll
+    for (int j = kCoefB + kCoefWarm - 1; j >= 0; j--) {
+        cm = z * (cm - buf[j]);
+        if (j < kCoefB && a + j < n) out[(int64_t)(a + j) * st] = 6.0f * cm;
     }
 }
 
-hipError_t launch_coef_images(const float* src, int64_t src_stride, int n, int H, int W, float* dst,
+// Row pass: a workgroup stages nr rows of one image in LDS with coalesced
+// loads (row pitch W + 1 words: the lanes of a wavefront, which walk
+// different rows, hit different banks), runs the recursions of every
+// (row, 32-column block) from LDS into a second LDS copy, and stores it
+// coalesced.  grid (ceil(H / nr), images); dynamic LDS 2 nr (W + 1) words.
+constexpr int kCoefRows = 32;
+constexpr int kCoefLdsWords = 40960;  // 160 KiB
+
+__global__ void __launch_bounds__(256)
+    k_bspline_rows(const float* __restrict__ src_all, int64_t src_stride, float* __restrict__ tmp_all, int H, int W,
+                   int nr)
+{
+    extern __shared__ float lds[];
+    const int P = W + 1;
+    float* sin = lds;
+    float* sout = lds + nr * P;
+    const int y0 = blockIdx.x * nr, img = blockIdx.y;
+    const int rows = min(nr, H - y0);
+    const float* src = src_all + img * src_stride + (int64_t)y0 * W;
+    float* dst = tmp_all + ((int64_t)img * H + y0) * W;
+    for (int r = 0; r < rows; r++)
+        for (int x = threadIdx.x; x < W; x += blockDim.x) sin[r * P + x] = src[(int64_t)r * W + x];
+    __syncthreads();
+    const int nblk = (W + kCoefB - 1) / kCoefB;
+    for (int t = threadIdx.x; t < rows * nblk; t += blockDim.x) {
+        const int r = t % rows, blk = t / rows;
+        bspline_line_block(sin + r * P, sout + r * P, W, 1, blk * kCoefB);
+    }
+    __syncthreads();
+    for (int r = 0; r < rows; r++)
+        for (int x = threadIdx.x; x < W; x += blockDim.x) dst[(int64_t)r * W + x] = sout[r * P + x];
+}
+
+// thread = (image, row block, column), columns fastest
+__global__ void __launch_bounds__(256)
+    k_bspline_cols(const float* __restrict__ tmp_all, float* __restrict__ dst_all, int nimg, int H, int W)
+{
+    const int nblk = (H + kCoefB - 1) / kCoefB;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nimg * nblk * W) return;
+    const int x = (int)(t % W);
+    const int64_t r = t / W;
+    const int blk = (int)(r % nblk), img = (int)(r / nblk);
+    const int64_t o = (int64_t)img * H * W + x;
+    bspline_line_block(tmp_all + o, dst_all + o, H, W, blk * kCoefB);
+}
+
+// Coefficients of n images (image i at src + i src_stride, H x W) into dst
+// [n][H][W]; tmp [n][H][W] holds the row pass.
+hipError_t launch_coef_images(const float* src, int64_t src_stride, int n, int H, int W, float* dst, float* tmp,
                               hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const int tiles = ((W + kCoefT - 1) / kCoefT) * ((H + kCoefT - 1) / kCoefT);
-    hipLaunchKernelGGL(k_bspline_coef, dim3(tiles, n), dim3(256), 0, s, src, src_stride, dst, H, W);
+    const int64_t tc = (int64_t)n * W * ((H + kCoefB - 1) / kCoefB);
+    const int nr = std::max(1, std::min(kCoefRows, kCoefLdsWords / (2 * (W + 1))));
+    if (2 * nr * (W + 1) > kCoefLdsWords) return hipErrorInvalidValue;  // rows longer than 20479 samples
+    const size_t lds = sizeof(float) * 2 * nr * (size_t)(W + 1);
+    static bool attr_set = false;  // a host attribute, set once (not a stream operation)
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_bspline_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(sizeof(float) * kCoefLdsWords));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_bspline_rows, dim3((unsigned)((H + nr - 1) / nr), (unsigned)n), dim3(256), lds, s, src,
+                       src_stride, tmp, H, W, nr);
+    hipLaunchKernelGGL(k_bspline_cols, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, s, tmp, dst, n, H, W);
     return hipGetLastError();
 }
 
@@ -557,16 +613,17 @@ hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, in
 hipError_t launch_bspline_coef(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
     (void)d_bk;
-    if (!hb.ref_coef || hb.nref == 0) return hipSuccess;
+    if (!hb.ref_coef || !hb.coef_tmp || hb.nref == 0) return hipSuccess;
     // level 0 of each (normalised) reference pyramid
-    return launch_coef_images(hb.ref_pyr, hb.pyr_elems, hb.nref, hb.H, hb.W, hb.ref_coef, s);
+    return launch_coef_images(hb.ref_pyr, hb.pyr_elems, hb.nref, hb.H, hb.W, hb.ref_coef, hb.coef_tmp, s);
 }
 
 hipError_t launch_stage_remap(const float* ref, int n, int H, int W, const double* R, double xs, double ys,
                               double zs, int interp, float* coef, float* out, hipStream_t s)
 {
     if (interp == 3) {
-        hipError_t e = launch_coef_images(ref, (int64_t)H * W, n, H, W, coef, s);
+        // the output buffer holds the row pass until the remap overwrites it
+        hipError_t e = launch_coef_images(ref, (int64_t)H * W, n, H, W, coef, out, s);
         if (e != hipSuccess) return e;
     }
     const dim3 grid((W + 63) / 64, H, n);

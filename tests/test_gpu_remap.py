@@ -3,13 +3,17 @@ repeated remap/XCF passes, on the GPU through the C ABI, against the FP64
 oracle.  Needs an MI355X; run with -m gpu.
 
 Bars:
-  * B-spline coefficients and remapped images: the GPU filters with a 31-tap
-    FIR in FP32 (rows, then columns), the oracle runs the exact recursion in
-    FP64.  Each output is a sum of 31 products whose absolute weights add up
-    to 3.0, over inputs bounded by 3.0 max|img| after the row pass, so the
-    rounding is below 2 x 31 x 2^-24 x 3.0 x 3.0 max|img| = 3.3e-5 max|img|;
-    the FIR's dropped tail adds 3.4e-9 max|img|.  Bar: 4e-5 max|img|.
-    Bilinear samples: 4 products, bar 1e-5 max|img|;
+  * B-spline coefficients and remapped images: the GPU runs the two
+    first-order recursions in FP32 on 32-sample blocks started from zero 16
+    samples outside the block (rows, then columns), the oracle runs them in
+    FP64 with the exact start.  Each recursion step rounds once and damps
+    earlier errors by |z| = 0.268, so a recursion adds at most
+    2^-24 x max|input| / (1 - |z|); the row pass sees inputs up to max|img|,
+    its output is bounded by 3 max|img| (the gain of the inverse filter), so
+    the four recursions stay below 4 x 6 x 3 x 2^-24 / 0.73 max|img| =
+    5.9e-6 max|img|, and the 16-sample starts add 2 x 6 x 1.4 x 7.1e-10
+    max|img|.  Bar: 4e-5 max|img| (the 16 products of a cubic sample
+    included).  Bilinear samples: 4 products, bar 1e-5 max|img|;
   * deformation gradient after P passes from the same R_finite: |dF| <= 1e-6
     (the single-pass bar: each pass starts from the previous pass's F, which
     agrees to ~1e-7 between the two sides);
