@@ -85,12 +85,16 @@ struct LMat {
 template <int n>
 __device__ void jacobi_eigen_l(LMat<n> A, double (&ev)[n], LMat<n> V)
 {
+#pragma unroll
     for (int i = 0; i < n; i++)
+#pragma unroll
         for (int j = 0; j < n; j++) V(i, j) = i == j ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 60; sweep++) {
         double off = 0.0, diag = 0.0;
+#pragma unroll
         for (int i = 0; i < n; i++) {
             diag += A(i, i) * A(i, i);
+#pragma unroll
             for (int j = i + 1; j < n; j++) off += 2.0 * A(i, j) * A(i, j);
         }
         if (off == 0.0 || off <= 1e-30 * (off + diag)) break;
@@ -101,20 +105,39 @@ __device__ void jacobi_eigen_l(LMat<n> A, double (&ev)[n], LMat<n> V)
                 const double tau = (A(q, q) - A(p, p)) / (2.0 * apq);
                 const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                 const double c = rsqrt(1.0 + t * t), s = t * c;
+                // each update reads its two lines whole before writing them
+                // (the element updates of a line are independent), so the
+                // LDS reads of a line are in flight together
+                double lp[n], lq[n];
+#pragma unroll
                 for (int k = 0; k < n; k++) {
-                    const double akp = A(k, p), akq = A(k, q);
-                    A(k, p) = c * akp - s * akq;
-                    A(k, q) = s * akp + c * akq;
+                    lp[k] = A(k, p);
+                    lq[k] = A(k, q);
                 }
+#pragma unroll
                 for (int k = 0; k < n; k++) {
-                    const double apk = A(p, k), aqk = A(q, k);
-                    A(p, k) = c * apk - s * aqk;
-                    A(q, k) = s * apk + c * aqk;
+                    A(k, p) = c * lp[k] - s * lq[k];
+                    A(k, q) = s * lp[k] + c * lq[k];
                 }
+#pragma unroll
                 for (int k = 0; k < n; k++) {
-                    const double vkp = V(k, p), vkq = V(k, q);
-                    V(k, p) = c * vkp - s * vkq;
-                    V(k, q) = s * vkp + c * vkq;
+                    lp[k] = A(p, k);
+                    lq[k] = A(q, k);
+                }
+#pragma unroll
+                for (int k = 0; k < n; k++) {
+                    A(p, k) = c * lp[k] - s * lq[k];
+                    A(q, k) = s * lp[k] + c * lq[k];
+                }
+#pragma unroll
+                for (int k = 0; k < n; k++) {
+                    lp[k] = V(k, p);
+                    lq[k] = V(k, q);
+                }
+#pragma unroll
+                for (int k = 0; k < n; k++) {
+                    V(k, p) = c * lp[k] - s * lq[k];
+                    V(k, q) = s * lp[k] + c * lq[k];
                 }
             }
     }
