@@ -170,7 +170,7 @@ inline int demons_tiles(int h, int w)
     return ((w + kDemonsTX - 1) / kDemonsTX) * ((h + kDemonsTY - 1) / kDemonsTY);
 }
 
-// Row-marching kernel (levels up to 256 px wide): wavefronts per row (0 = not
+// Row-marching kernel (levels up to 512 px wide): wavefronts per row (0 = not
 // applicable), supported strip heights, number of strips, and its launchers
 // (false if not applicable).
 int rows_cpl(int w);

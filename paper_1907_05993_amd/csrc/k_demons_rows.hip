@@ -1,8 +1,8 @@
 // Row-marching demons iteration for gfx950 (multi-resolution demons of
-// arXiv:1907.05993 section 1, Eq. (1) force), used for levels up to 256 px wide.
+// arXiv:1907.05993 section 1, Eq. (1) force), used for levels up to 512 px wide.
 //
-// One workgroup of 64 NW threads (NW = 4 wavefronts for 256 px, 2 for 128 px,
-// 1 for 64 px) owns a strip of TY output rows of one pair; thread t owns column
+// One workgroup of 64 NW threads (NW = 8 wavefronts for 512 px, 4 for 256 px,
+// 2 for 128 px, 1 for 64 px) owns a strip of TY output rows of one pair; thread t owns column
 // t, so a workgroup spans a whole row and every memory instruction is
 // contiguous across the lanes.
 // Marching down the strip, for each row y = y0 - r .. y0 + TY - 1 + r:
@@ -816,6 +816,7 @@ int rows_cpl(int w)
     if (w <= 64) return 1;
     if (w <= 128) return 2;
     if (w <= 256) return 4;
+    if (w <= 512) return 8;
     return 0;
 }
 
@@ -831,6 +832,7 @@ bool launch_demons_rows2(const Bucket* d_bk, const Bucket& hb, int level, int L,
     case 1: return dispatch_rad2<1>(d_bk, hb.nb, h, level, L, tp, radius, tol, cap, ty, s);
     case 2: return dispatch_rad2<2>(d_bk, hb.nb, h, level, L, tp, radius, tol, cap, ty, s);
     case 4: return dispatch_rad2<4>(d_bk, hb.nb, h, level, L, tp, radius, tol, cap, ty, s);
+    case 8: return dispatch_rad2<8>(d_bk, hb.nb, h, level, L, tp, radius, tol, cap, ty, s);
     default: return false;
     }
 }
@@ -845,6 +847,7 @@ bool launch_demons_rows(const Bucket* d_bk, const Bucket& hb, int level, int k, 
     case 1: return dispatch_rad<1>(d_bk, hb.nb, h, level, k, tp, radius, tol, ty, s);
     case 2: return dispatch_rad<2>(d_bk, hb.nb, h, level, k, tp, radius, tol, ty, s);
     case 4: return dispatch_rad<4>(d_bk, hb.nb, h, level, k, tp, radius, tol, ty, s);
+    case 8: return dispatch_rad<8>(d_bk, hb.nb, h, level, k, tp, radius, tol, ty, s);
     default: return false;
     }
 }
@@ -856,6 +859,7 @@ bool launch_demons_rows_stage(const float* R, const float* T, int n, int h, int 
     case 1: return dispatch_rad_stage<1>(R, T, n, h, w, u, tp, radius, un, rms, s);
     case 2: return dispatch_rad_stage<2>(R, T, n, h, w, u, tp, radius, un, rms, s);
     case 4: return dispatch_rad_stage<4>(R, T, n, h, w, u, tp, radius, un, rms, s);
+    case 8: return dispatch_rad_stage<8>(R, T, n, h, w, u, tp, radius, un, rms, s);
     default: return false;
     }
 }
