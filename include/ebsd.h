@@ -227,7 +227,7 @@ int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int3
  * this kernel against the single-iteration kernel and keeps it for a level
  * size where it is faster.  ebsd_get_fused_height returns the strip height
  * used for a level size (0 = one iteration per launch); ebsd_set_fused_height
- * forces it (0, 32, 64 or 128; levels up to 512 px wide). */
+ * forces it (0, 16, 32, 64 or 128; levels up to 512 px wide). */
 int ebsd_get_fused_height(const ebsd_handle* h, int32_t level_h, int32_t level_w);
 int ebsd_set_fused_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t rows);
 

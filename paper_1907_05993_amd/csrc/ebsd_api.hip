@@ -540,7 +540,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
             h->strip_ty[std::make_pair(lh, lw)] = best_ty;
             // two iterations per launch: 3 launches (6 iterations) against the best 6 single launches
             int best_fty = 0;
-            for (int fty : {32, 64, 128}) {
+            for (int fty : {16, 32, 64, 128}) {
                 EBSD_TRY(launch_demons_iter2(d_bk, b, l, 0, h->taps, h->radius, 0.0f, 1 << 20, fty, s));
                 EBSD_TRY(hipEventRecord(e0, s));
                 for (int L2 = 1; L2 <= 3; L2++)

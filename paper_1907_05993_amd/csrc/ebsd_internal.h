@@ -175,7 +175,7 @@ inline int demons_tiles(int h, int w)
 // (false if not applicable).
 int rows_cpl(int w);
 bool rows_ty_supported(int ty);
-// Two iterations per launch (temporal blocking) at strip heights 32, 64, 128:
+// Two iterations per launch (temporal blocking) at strip heights 16, 32, 64, 128:
 // launch L of a level runs iterations 2L and 2L + 1 (see k_demons_rows2);
 // ceil(cap / 2) launches, plus one more when tol > 0 and cap is even.
 bool rows2_ty_supported(int ty);

@@ -764,6 +764,7 @@ bool dispatch_ty2(const Bucket* d_bk, int nb, int h, int level, int L, const Tap
                   hipStream_t s)
 {
     switch (ty) {
+    case 16: launch_rows2<CPL, RAD, 16>(d_bk, nb, h, level, L, tp, tol, cap, s); return true;
     case 32: launch_rows2<CPL, RAD, 32>(d_bk, nb, h, level, L, tp, tol, cap, s); return true;
     case 64: launch_rows2<CPL, RAD, 64>(d_bk, nb, h, level, L, tp, tol, cap, s); return true;
     case 128: launch_rows2<CPL, RAD, 128>(d_bk, nb, h, level, L, tp, tol, cap, s); return true;
@@ -822,7 +823,7 @@ int rows_cpl(int w)
 
 bool rows_ty_supported(int ty) { return ty == 16 || ty == 32 || ty == 64 || ty == 128; }
 
-bool rows2_ty_supported(int ty) { return ty == 32 || ty == 64 || ty == 128; }
+bool rows2_ty_supported(int ty) { return ty == 16 || ty == 32 || ty == 64 || ty == 128; }
 
 bool launch_demons_rows2(const Bucket* d_bk, const Bucket& hb, int level, int L, const Taps& tp, int radius,
                          float tol, int cap, int ty, hipStream_t s)

@@ -47,7 +47,7 @@ def test_fused_equals_single(E, name, H, iters, tol):
     n = 4 if H == 256 else 1
     refs, tests = gen(name, n)
     a = run(E, refs, tests, H, H, iters, tol, 0)
-    for rows in (32, 64):
+    for rows in (16, 32, 64):
         b = run(E, refs, tests, H, H, iters, tol, rows)
         print("iters per level (single):", a["iters"].tolist(), "status", a["status"].tolist())
         for k in ("field", "iters", "status", "F", "q1", "q2", "R_finite"):
@@ -55,6 +55,22 @@ def test_fused_equals_single(E, name, H, iters, tol):
     # also without graph replay
     c = run(E, refs, tests, H, H, iters, tol, 64, graphs=False)
     assert np.array_equal(a["field"], c["field"]) and np.array_equal(a["iters"], c["iters"])
+
+
+@pytest.mark.parametrize("N", [400, 512])
+def test_fused_equals_single_wide(E, N):
+    """Levels up to 512 px wide (eight wavefronts per row): two iterations
+    per launch equal one per launch bit for bit, fixed count and tolerance."""
+    from paper_1907_05993_amd import synth as S
+    print(f"case: fused vs single {N} px", flush=True)
+    specs = [S.make_spec(70, i, N, N, mis_deg=(0.0, 6.0)) for i in range(2)]
+    refs, tests = S.render_batch(specs)
+    for iters, tol in ((9, 0.0), (60, 0.1)):
+        a = run(E, refs, tests, N, N, iters, tol, 0)
+        for rows in (16, 64):
+            b = run(E, refs, tests, N, N, iters, tol, rows)
+            for k in ("field", "iters", "status", "F", "q1", "q2", "R_finite"):
+                assert np.array_equal(a[k], b[k]), (k, rows, iters)
 
 
 def test_fused_stops_on_odd_and_even_iterations(E):
