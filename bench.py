@@ -298,8 +298,12 @@ def kernel_sha():
     while it matches (counters must come from the kernel being timed)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_demons.hip", "k_demons_rows.hip", "dev_util.h"):
-        h.update(open(os.path.join(ROOT, "paper_1907_05993_amd", "csrc", f), "rb").read())
+    import glob
+    csrc = os.path.join(ROOT, "paper_1907_05993_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "k_demons*.hip"))) + [os.path.join(csrc, "demons_rows_impl.h"),
+                                                                         os.path.join(csrc, "dev_util.h")]
+    for f in files:
+        h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 
