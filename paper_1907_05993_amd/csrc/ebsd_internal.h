@@ -69,7 +69,8 @@ struct Bucket {
     PatStat* ref_stat;          // [nref]
     float* field[2];            // [nb][2][H][W] each (level l uses the leading 2 h w)
     PairState* state;           // [nb]
-    float* partial;             // [2][nb][max tiles] per-tile sums of squared updates (by iteration parity)
+    float* partial;             // [4][nb][max tiles] per-tile sums of squared updates (slot k & 1 for one
+                                // iteration per launch, k & 3 for two)
     int32_t max_tiles;          // tiles of the finest level
     int32_t* iters;             // [nb][L]
     int32_t n_roi, roi_N;
