@@ -42,6 +42,7 @@ class Params(C.Structure):
         ("second_pass", C.c_int32),
         ("remap_interp", C.c_int32),
         ("xcf_passes", C.c_int32),
+        ("first_pass", C.c_int32),
     ]
 
 
@@ -58,12 +59,14 @@ class _Outputs(C.Structure):
         ("rotvec", C.c_void_p),
         ("iters", C.c_void_p),
         ("status", C.c_void_p),
+        ("mae1", C.c_void_p),
+        ("mae", C.c_void_p),
     ]
 
 
 def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_roi=20,
                 roi_size=32, roi_radius_frac=0.3, window=1, second_pass=1, remap_interp=3,
-                xcf_passes=1):
+                xcf_passes=1, first_pass=0):
     p = Params()
     p.levels = levels
     its = [iters] * MAX_LEVELS if np.isscalar(iters) else list(iters) + [0] * (MAX_LEVELS - len(iters))
@@ -79,6 +82,7 @@ def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_r
     p.second_pass = second_pass
     p.remap_interp = remap_interp
     p.xcf_passes = xcf_passes
+    p.first_pass = first_pass
     return p
 
 
@@ -113,6 +117,8 @@ def lib():
         L.orc_det_normalize.argtypes = [d]
         L.orc_solve_F.restype = C.c_uint32
         L.orc_solve_F.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d]
+        L.orc_mae.restype = C.c_double
+        L.orc_mae.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d]
         L.orc_polar.argtypes = [d, d]
         L.orc_rotvec.argtypes = [d, d]
         L.orc_remap.argtypes = [d, C.c_int, C.c_int, d, C.c_double, C.c_double, C.c_double, C.c_int, d]
@@ -270,6 +276,18 @@ def solve_F(q, cx, cy, pcs):
     return F.reshape(3, 3), int(st)
 
 
+def mae(q, F, cx, cy, pcs):
+    """Mean angular error (rad) of the Eq. (3) fit F to the shifts q at the ROI
+    centres (cx, cy): the mean over ROIs of the angle between F r_i and
+    r_i + q_i (the reading of the figure section 3 compares methods by)."""
+    q = _f64(q).reshape(-1, 2)
+    cx = _f64(cx)
+    cy = _f64(cy)
+    F = _f64(F).reshape(9)
+    return float(lib().orc_mae(_d(q), _d(cx), _d(cy), len(cx), float(pcs[0]), float(pcs[1]),
+                               float(pcs[2]), _d(F)))
+
+
 def polar(F):
     """Rotation factor of F via SVD, Eq. (4)-(5)."""
     F = _f64(F).reshape(9)
@@ -356,6 +374,9 @@ def pc_pixels(H, W, params):
     return (params.pc_x * W - 0.5, params.pc_y * H - 0.5, params.pc_z * W)
 
 
+_OUT_KEYS = ("field", "q1", "F1", "Rfin", "q2", "ph", "F", "R", "rotvec", "iters", "status", "mae1", "mae")
+
+
 def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None):
     """Whole pipeline for a batch of pairs (OpenMP over pairs).
 
@@ -383,11 +404,12 @@ def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None)
         "rotvec": np.empty((n, 3)),
         "iters": np.empty((n, params.levels), np.int32),
         "status": np.empty(n, np.uint32),
+        "mae1": np.empty(n),
+        "mae": np.empty(n),
     }
     o = _Outputs()
-    for k in ("field", "q1", "F1", "Rfin", "q2", "ph", "F", "R", "rotvec", "iters", "status"):
-        key = "ph" if k == "ph" else k
-        setattr(o, k, out[key].ctypes.data if out[key] is not None else None)
+    for k in _OUT_KEYS:
+        setattr(o, k, out[k].ctypes.data if out[k] is not None else None)
     rf = None
     if rfin is not None:
         rf = _f64(rfin).reshape(n, 9)
@@ -399,7 +421,7 @@ def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None)
         used = 1
         for i in range(n):
             oi = _Outputs()
-            for k in ("field", "q1", "F1", "Rfin", "q2", "ph", "F", "R", "rotvec", "iters", "status"):
+            for k in _OUT_KEYS:
                 a = out[k]
                 setattr(oi, k, a[i:i + 1].ctypes.data if a is not None else None)
             r_i = np.ascontiguousarray(refs[i])

@@ -68,6 +68,9 @@ typedef struct {
     int32_t second_pass;               /* 1 = remap + XCF second pass */
     int32_t remap_interp;              /* 3 = cubic B-spline, 1 = bilinear */
     int32_t xcf_passes;                /* remap + XCF passes (>= 1) */
+    int32_t first_pass;                /* 0 = demons (the paper's method), 1 = ROI
+                                          cross-correlation of the unremapped
+                                          patterns (the conventional first pass) */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -979,6 +982,29 @@ void orc_xcf(const double* A, const double* B, int N, int window, double* C, dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* Mean angular error of an Eq. (3) fit, the quality figure section 3
+ * compares the four methods by (its formula is not given; this is the
+ * reading used here): for ROI i the angle between the direction the fitted
+ * model assigns to the ROI centre, F r_i, and the measured one,
+ * (r_i + q_i) on the screen plane z = Z*, as atan2(|a x b|, a . b); the
+ * mean over the n ROIs, in rad.                                           */
+double orc_mae(const double* q, const double* cx, const double* cy, int n, double xs, double ys,
+               double zs, const double* F)
+{
+    double sum = 0.0;
+    for (int i = 0; i < n; i++) {
+        double r[3] = {cx[i] - xs, cy[i] - ys, zs};
+        double a[3], b[3] = {r[0] + q[2 * i], r[1] + q[2 * i + 1], zs};
+        for (int k = 0; k < 3; k++) a[k] = F[3 * k] * r[0] + F[3 * k + 1] * r[1] + F[3 * k + 2] * r[2];
+        double c0 = a[1] * b[2] - a[2] * b[1];
+        double c1 = a[2] * b[0] - a[0] * b[2];
+        double c2 = a[0] * b[1] - a[1] * b[0];
+        sum += atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+    }
+    return n > 0 ? sum / n : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole pipeline for one pair.
  *   demons (first pass) -> q1 at the ROI centres -> F1 (Eq. 3) ->
  *   R_finite = polar(F1) (Eq. 4-5) -> remap the reference by R_finite ->
@@ -989,6 +1015,14 @@ void orc_xcf(const double* A, const double* B, int N, int window, double* C, dou
  * F_inf with that F; q2 and ph are the last pass's.
  * rfin_in (optional) replaces the first pass's R_finite: it lets the second
  * pass be checked in isolation against another implementation's R_finite.
+ * first_pass = 1 replaces demons by the conventional first pass (section 1;
+ * method (c) of the comparison in section 3, method (a) without the second
+ * pass): q1 is the ROI cross-correlation of the normalised, unremapped
+ * patterns (same XCF as the second pass), the field is zero and no
+ * iterations run; ph then holds that XCF's peak heights unless a second
+ * pass overwrites them.  mae1 / mae: mean angular error (orc_mae) of the
+ * first fit (F1 to q1) and of the last fit (F_inf to the last q2; F1 to q1
+ * without a second pass).
  * Any output pointer may be NULL.                                         */
 typedef struct {
     double* field;   /* [2][H][W] full-res px */
@@ -1002,6 +1036,8 @@ typedef struct {
     double* rotvec;  /* [3] */
     int32_t* iters;  /* [levels] */
     uint32_t* status;
+    double* mae1;    /* [1] */
+    double* mae;     /* [1] */
 } orc_outputs;
 
 static void store(double* dst, const double* src, size_t n)
@@ -1028,17 +1064,33 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
     uint32_t st = 0;
     st |= orc_normalize(ref, (int64_t)HW, Rn);
     st |= orc_normalize(test, (int64_t)HW, Tn);
-    st |= orc_demons(Rn, Tn, H, W, p, u_init, field, its);
     orc_roi_layout(H, W, p, cx, cy, x0, y0);
-    double* ux = field;
-    double* uy = field + HW;
-    for (int j = 0; j < nr; j++) {
-        q1[2 * j] = orc_bilinear(ux, H, W, cx[j], cy[j]);
-        q1[2 * j + 1] = orc_bilinear(uy, H, W, cx[j], cy[j]);
+    double* a = (double*)malloc(sizeof(double) * N * N);
+    double* b = (double*)malloc(sizeof(double) * N * N);
+    if (p->first_pass == 1) {
+        /* conventional first pass: XCF of each ROI of the unremapped patterns */
+        memset(field, 0, sizeof(double) * 2 * HW);
+        for (int j = 0; j < nr; j++) {
+            for (int y = 0; y < N; y++)
+                for (int x = 0; x < N; x++) {
+                    a[y * N + x] = Rn[(size_t)(y0[j] + y) * W + x0[j] + x];
+                    b[y * N + x] = Tn[(size_t)(y0[j] + y) * W + x0[j] + x];
+                }
+            orc_xcf(a, b, N, p->window, NULL, q1 + 2 * j, ph + j);
+        }
+    } else {
+        st |= orc_demons(Rn, Tn, H, W, p, u_init, field, its);
+        double* ux = field;
+        double* uy = field + HW;
+        for (int j = 0; j < nr; j++) {
+            q1[2 * j] = orc_bilinear(ux, H, W, cx[j], cy[j]);
+            q1[2 * j + 1] = orc_bilinear(uy, H, W, cx[j], cy[j]);
+        }
     }
     double xs = p->pc_x * W - 0.5, ys = p->pc_y * H - 0.5, zs = p->pc_z * W;
     double F1[9], Rfin[9], F[9], R[9], rv[3];
     st |= orc_solve_F(q1, cx, cy, nr, xs, ys, zs, F1);
+    double mae1 = orc_mae(q1, cx, cy, nr, xs, ys, zs, F1), mae = mae1;
     orc_polar(F1, Rfin);
     if (rfin_in) memcpy(Rfin, rfin_in, sizeof Rfin);
     if (p->second_pass) {
@@ -1051,8 +1103,6 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
         memcpy(Rcur, Rfin, sizeof Rcur);
         memcpy(Fprev, Rfin, sizeof Fprev);
         double* Rm = (double*)malloc(sizeof(double) * HW);
-        double* a = (double*)malloc(sizeof(double) * N * N);
-        double* b = (double*)malloc(sizeof(double) * N * N);
         for (int pass = 0; pass < passes; pass++) {
             orc_remap(Rn, H, W, Rcur, xs, ys, zs, p->remap_interp, Rm);
             for (int j = 0; j < nr; j++) {
@@ -1065,17 +1115,18 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
             }
             double Finf[9];
             st |= orc_solve_F(q2, cx, cy, nr, xs, ys, zs, Finf);
+            mae = orc_mae(q2, cx, cy, nr, xs, ys, zs, Finf);
             matmul3(Finf, Fprev, F);
             if (det3(F) > 0.0) orc_det_normalize(F);
             memcpy(Fprev, F, sizeof Fprev);
             inv3_transposed(F, Rcur);
         }
         free(Rm);
-        free(a);
-        free(b);
     } else {
         memcpy(F, F1, sizeof F);
     }
+    free(a);
+    free(b);
     orc_polar(F, R);
     orc_rotvec(R, rv);
     store(o->field, field, 2 * HW);
@@ -1089,6 +1140,8 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
     store(o->rotvec, rv, 3);
     if (o->iters) memcpy(o->iters, its, sizeof(int32_t) * p->levels);
     if (o->status) *o->status = st;
+    store(o->mae1, &mae1, 1);
+    store(o->mae, &mae, 1);
     free(Rn);
     free(Tn);
     free(field);
@@ -1132,6 +1185,8 @@ int orc_register_batch(const float* refs, const float* tests, int n, int H, int 
             oi.rotvec = o->rotvec ? o->rotvec + (size_t)i * 3 : NULL;
             oi.iters = o->iters ? o->iters + (size_t)i * p->levels : NULL;
             oi.status = o->status ? o->status + i : NULL;
+            oi.mae1 = o->mae1 ? o->mae1 + i : NULL;
+            oi.mae = o->mae ? o->mae + i : NULL;
             orc_register_pair(refs + (size_t)i * HW, tests + (size_t)i * HW, H, W, p, NULL,
                               rfin_in ? rfin_in + (size_t)i * 9 : NULL, &oi);
         }

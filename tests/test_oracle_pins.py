@@ -326,6 +326,44 @@ def test_solve_F_in_plane_rotation_about_pc(orc):
     np.testing.assert_allclose(F, Rotation.from_rotvec([0, 0, th]).as_matrix(), atol=1e-13)
 
 
+# -- mean angular error of a fit (the figure section 3 compares the methods by) -----------------
+
+def test_mae_zero_for_exact_shifts_and_scale_invariant(orc):
+    cx, cy, pcs = _layout()
+    Ftrue = (np.eye(3) + np.array([[1e-3, -5e-4, 2e-4], [-5e-4, -2e-3, 7e-4], [2e-4, 7e-4, 1e-3]])) \
+        @ Rotation.from_rotvec([0.05, -0.08, 0.03]).as_matrix()
+    q = _project(Ftrue, cx, cy, *pcs)
+    assert orc.mae(q, Ftrue, cx, cy, pcs) < 1e-14
+    assert orc.mae(q, 3.7 * Ftrue, cx, cy, pcs) < 1e-14  # directions only: F and sF predict the same
+
+
+def test_mae_single_shift_at_pattern_centre(orc):
+    # F = I and only the pattern-centre ROI (r = (0, 0, Z*)) moved by s along x:
+    # one angle atan(s / Z*), the other ROIs none
+    cx, cy, pcs = _layout()
+    assert cx[0] == pcs[0] and cy[0] == pcs[1]
+    q = np.zeros((20, 2))
+    q[0, 0] = 2.5
+    np.testing.assert_allclose(orc.mae(q, np.eye(3), cx, cy, pcs), math.atan(2.5 / pcs[2]) / 20, rtol=1e-13)
+
+
+def test_mae_equals_mean_aligning_rotation_angle(orc):
+    # the angle between F r_i and r_i + q_i is the angle of the smallest rotation
+    # taking one direction onto the other (scipy's align_vectors)
+    cx, cy, pcs = _layout()
+    xs, ys, zs = pcs
+    F = Rotation.from_rotvec([0.01, -0.02, 0.015]).as_matrix() @ (np.eye(3) + 1e-3 * np.diag([1, -2, 1]))
+    q = rng(31).normal(scale=2.0, size=(20, 2))
+    angs = []
+    for i in range(20):
+        r = np.array([cx[i] - xs, cy[i] - ys, zs])
+        a = F @ r
+        b = np.array([r[0] + q[i, 0], r[1] + q[i, 1], zs])
+        rot, _ = Rotation.align_vectors([b / np.linalg.norm(b)], [a / np.linalg.norm(a)])
+        angs.append(rot.magnitude())
+    np.testing.assert_allclose(orc.mae(q, F, cx, cy, pcs), np.mean(angs), rtol=1e-9)
+
+
 def test_polar_matches_scipy(orc):
     F = np.eye(3) + rng(31).normal(scale=0.05, size=(3, 3))
     R = orc.polar(F)
@@ -465,6 +503,43 @@ def test_pipeline_identical_pair(orc):
     np.testing.assert_allclose(out["F"][0], np.eye(3), atol=1e-13)
     assert np.all(out["rotvec"][0] == 0) or np.abs(out["rotvec"][0]).max() < 1e-13
     np.testing.assert_allclose(out["ph"][0], 1.0, atol=1e-12)
+
+
+def _tiled_pair(N, tiles, shift, seed):
+    """A pattern of period N in both axes (a smoothed random N x N block,
+    tiled) and the same pattern shifted by shift = (sx, sy) whole pixels."""
+    block = ndi.gaussian_filter(rng(seed).normal(size=(N, N)), 1.5, mode="wrap")
+    ref = np.tile(block, (tiles, tiles)).astype(np.float32)
+    test = np.roll(ref, (shift[1], shift[0]), axis=(0, 1))
+    return ref, test
+
+
+@pytest.mark.parametrize("shift", [(3, -2), (-5, 0), (0, 7)])
+def test_xcf_first_pass_integer_pattern_shift_exact(orc, shift):
+    """Conventional first pass (ROI XCF of the unremapped patterns) on a
+    pattern of period N = ROI size shifted by whole pixels: every ROI of the
+    test is a circular shift of the reference ROI, so without a window the
+    correlation is the autocorrelation moved to s (symmetric peak, no
+    sub-pixel offset, peak height 1), q1 = s exactly, and Eq. (3) gives
+    F = I + (sx/Z*) e1 (x) e3 + (sy/Z*) e2 (x) e3.  No demons iterations run."""
+    ref, test = _tiled_pair(32, 4, shift, seed=40 + shift[0])
+    p = orc.make_params(levels=3, iters=10, roi_size=32, window=0, second_pass=0, first_pass=1)
+    out = orc.register_batch(ref, test, p)
+    np.testing.assert_allclose(out["q1"][0], np.tile(shift, (20, 1)), atol=1e-9)
+    np.testing.assert_allclose(out["ph"][0], 1.0, atol=1e-12)
+    zs = p.pc_z * 128
+    Fe = np.eye(3)
+    Fe[0, 2] = shift[0] / zs
+    Fe[1, 2] = shift[1] / zs
+    np.testing.assert_allclose(out["F1"][0], Fe, atol=1e-11)
+    np.testing.assert_allclose(out["F"][0], out["F1"][0], atol=0)
+    assert out["mae1"][0] < 1e-11 and out["mae"][0] == out["mae1"][0]
+    assert not out["field"].any() and not out["iters"].any() and out["status"][0] == 0
+    # with the second pass the first pass is unchanged
+    p2 = orc.make_params(levels=3, iters=10, roi_size=32, window=0, second_pass=1, first_pass=1)
+    out2 = orc.register_batch(ref, test, p2)
+    np.testing.assert_array_equal(out2["q1"], out["q1"])
+    np.testing.assert_array_equal(out2["F1"], out["F1"])
 
 
 KNOWN_ROTATION_CASES = [("axis", 1e-4, 0), ("axis", 1e-3, 1), ("axis", 1e-3, 2), ("axis", math.radians(2.0), 3),
