@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "demons_traffic.json"))
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
     ap.add_argument("--skip-plain", action="store_true", help="time the warm start only (profiling runs)")
+    ap.add_argument("--skip-comparison", action="store_true",
+                    help="skip the conventional-first-pass comparison (section 3's four methods)")
     ap.add_argument("--latency-reps", type=int, default=20,
                     help="also time the single-pair configuration (128^2, 3 x 100) this many times (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -107,17 +109,19 @@ def main():
     rv_true = np.array([rotvec_of(rotation_of(s.F)) for s in specs])
     log(f"[bench] generated {n} pairs of {H}x{W} on the GPU in {time.time() - t0:.1f} s")
 
-    def make(warm, cap):
+    def make(warm, cap, first_pass=0, second_pass=1):
         p = ebsd.Params(levels=3, iters=(cap,) * 3, sigma_px=1.0, tol_px=args.tol, roi_size=w["roi"], n_roi=20,
-                        warm_start=2 if warm else 0, fallback_residual_px=args.fallback)
+                        warm_start=2 if warm else 0, fallback_residual_px=args.fallback,
+                        first_pass=first_pass, second_pass=second_pass)
         reg = ebsd.Registrar(p, device=0)
         if warm:
             reg.load_model(WEIGHTS)
         reg.set_graphs(not args.no_graphs)
         return reg
 
-    def timed(reg, label):
-        tuned = reg.autotune(d_refs, d_tests)  # strip heights per level, outside the timed region
+    def timed(reg, label, tune=True):
+        # strip heights per level, outside the timed region
+        tuned = reg.autotune(d_refs, d_tests) if tune else {}
         fused = reg.fused_heights(H, W)
         reg.set_timing(True)
         for i in range(args.warmup):
@@ -133,13 +137,21 @@ def main():
         iters = out["iters"].cpu().numpy().astype(np.int64)
         st = out["status"].cpu().numpy().astype(np.int64)
         err = np.linalg.norm(out["rotvec"].cpu().numpy() - rv_true, axis=1)
+        rf = out["R_finite"].cpu().numpy()
+        err_first = np.linalg.norm(np.stack([rotvec_of(r) for r in rf]) - rv_true, axis=1)
         log(f"[bench] {label}: {args.steps} steps in {el:.3f} s, median rotation error {np.median(err):.2e} rad")
         return dict(elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
-                    tuned=tuned, fused=fused)
+                    tuned=tuned, fused=fused, err_first=err_first, mae_first=out["mae_first"].cpu().numpy(),
+                    mae=out["mae"].cpu().numpy(), ph=out["peak_height"].cpu().numpy().mean(axis=1))
 
     warm = timed(make(True, args.cap), "warm start")
     plain = None if args.skip_plain else timed(make(False, args.cap), "plain")
     short = timed(make(True, args.short_cap), f"warm start, cap {args.short_cap}") if args.short_cap > 0 else None
+    # the conventional first pass (ROI cross-correlation of the unremapped patterns), with and
+    # without the remap + second pass: methods (c) and (a) of section 3's comparison
+    xcf_c = None if args.skip_comparison else timed(make(False, args.cap, first_pass=1), "XCF first pass", tune=False)
+    xcf_a = None if args.skip_comparison else timed(make(False, args.cap, first_pass=1, second_pass=0),
+                                                   "XCF only", tune=False)
 
     # network forward alone on the same batch (chunks of 256), HIP events on torch's stream
     net = ebsd.Cnn(device=0, max_batch=256)
@@ -249,6 +261,26 @@ def main():
     }
     if short is not None:
         rec["warm_short_cap"] = dict(summary(short), cap=args.short_cap)
+    if xcf_c is not None:
+        def method(r, first, ph=True):
+            e = r["err_first"] if first else r["err"]
+            m = r["mae_first"] if first else r["mae"]
+            d = {"rotation_error_rad": {"median": float(np.median(e)), "p95": float(np.percentile(e, 95))},
+                 "mean_angular_error_rad": {"median": float(np.median(m)), "p95": float(np.percentile(m, 95))}}
+            if ph:
+                d["peak_height_mean"] = float(np.mean(r["ph"]))
+            return d
+        rec["comparison"] = {
+            "note": "section 3's four methods on this batch; (b) and (d) from the warm-start run (its first "
+                    "fit and its result), (a) and (c) from the conventional XCF first pass",
+            "a_xcf": dict(method(xcf_a, False), pairs_per_s=round(n * args.steps / xcf_a["elapsed"], 1)),
+            "b_demons": method(warm, True, ph=False),
+            "c_xcf_remap_xcf": dict(method(xcf_c, False), pairs_per_s=round(n * args.steps / xcf_c["elapsed"], 1)),
+            "d_demons_remap_xcf": method(warm, False),
+        }
+        if plain is not None:
+            rec["comparison"]["b_demons_plain"] = method(plain, True, ph=False)
+            rec["comparison"]["d_demons_plain_remap_xcf"] = method(plain, False)
 
     if args.latency_reps > 0:
         # single pair, 128 x 128, 2 degrees, 3 levels x 100 iterations, 20 ROIs of 32: latency per call

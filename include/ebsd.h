@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define EBSD_ABI_VERSION 3
+#define EBSD_ABI_VERSION 4
 #define EBSD_MAX_LEVELS 8
 
 /* return codes */
@@ -96,6 +96,11 @@ typedef struct ebsd_params {
     int32_t xcf_passes;                   /* remap + XCF + Eq. (12) passes, 1..16: pass 1 remaps by R_finite
                                              and composes with it (the paper's method), pass k > 1 remaps by
                                              pass k-1's F and composes with that F */
+    int32_t first_pass;                   /* 0 = demons (the paper's method); 1 = the conventional first
+                                             pass it is compared with (sections 1 and 3): q1 is the ROI
+                                             cross-correlation of the unremapped patterns, no demons run,
+                                             the field output is not written and iters are 0; needs
+                                             warm_start = 0 */
 } ebsd_params;
 
 /* One scan point.  ref/test: device pointers to H x W fp32 patterns.  Pairs
@@ -124,6 +129,11 @@ typedef struct ebsd_outputs {
     uint32_t* status;           /* [n] status bits */
     float* warm_field;          /* [n][64][64][2] network output (warm start), px of the 256 x 256 image it saw */
     float* warm_misfit;         /* [n] RMS misfit of the Eq. (2) fit to warm_field, in the same px */
+    double* mae_first;          /* [n] mean angular error of the first fit (F_first to q1), rad */
+    double* mae;                /* [n] mean angular error of the last fit (F_inf to the last pass's q2;
+                                   F_first to q1 without a second pass), rad.  Mean angular error:
+                                   the mean over the ROIs of the angle between F r_i and r_i + q_i
+                                   (the quality figure section 3 compares the methods by) */
 } ebsd_outputs;
 
 /* Library ABI version (EBSD_ABI_VERSION). */
@@ -131,8 +141,9 @@ int ebsd_version(void);
 
 /* Fill *p with the defaults: 3 levels x 150 iterations, sigma 1 px, tol 0,
  * pattern centre (0.5, 0.5, 0.7), 20 ROIs of 64 px on a ring of 0.3 W, Hann
- * window, second pass on (cubic B-spline remap, one pass), warm start off
- * (fallback misfit 0.5 px).  Returns EBSD_OK or EBSD_EINVAL (p == NULL). */
+ * window, second pass on (cubic B-spline remap, one pass), demons first
+ * pass, warm start off (fallback misfit 0.5 px).  Returns EBSD_OK or
+ * EBSD_EINVAL (p == NULL). */
 int ebsd_params_default(ebsd_params* p);
 
 /* Human-readable text of a return code (static storage). */
@@ -237,8 +248,9 @@ int ebsd_set_fused_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int3
 int ebsd_set_timing(ebsd_handle* h, int enable);
 
 /* Waits for the last timed call to complete and reports level_ms[l] (host,
- * [levels]): the time of level l's demons launches, and *total_ms: the whole
- * call.  EBSD_EINVAL if no timed call has been made. */
+ * [levels]): the time of level l's demons launches (left unwritten with the
+ * XCF first pass, which runs none), and *total_ms: the whole call.
+ * EBSD_EINVAL if no timed call has been made. */
 int ebsd_get_timing(ebsd_handle* h, double* level_ms, double* total_ms);
 
 /* ---- warm-start network ------------------------------------------------------

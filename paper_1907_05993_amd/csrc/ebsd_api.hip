@@ -159,6 +159,8 @@ int check_params(const ebsd_params* p)
     if (!(p->fallback_residual_px >= 0.0f) || !std::isfinite(p->fallback_residual_px)) return EBSD_EINVAL;
     if (p->remap_interp != 1 && p->remap_interp != 3) return EBSD_EINVAL;
     if (p->xcf_passes < 1 || p->xcf_passes > 16) return EBSD_EINVAL;
+    if (p->first_pass != 0 && p->first_pass != 1) return EBSD_EINVAL;
+    if (p->first_pass == 1 && p->warm_start != 0) return EBSD_EINVAL;
     return EBSD_OK;
 }
 
@@ -403,6 +405,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const size_t o_R = w.take(sizeof(double) * 9 * nb);
     const size_t o_rv = w.take(sizeof(double) * 3 * nb);
     const size_t o_st = w.take(sizeof(uint32_t) * nb);
+    const size_t o_mae = w.take(sizeof(double) * 2 * nb);
     const bool xcf = mode == Mode::SecondPassOnly || p.second_pass;
     const bool cubic = xcf && p.remap_interp == 3 && !tune_only;
     const size_t o_coef = w.take(cubic ? sizeof(float) * (size_t)nref * H * W : 0);
@@ -442,10 +445,13 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.R = reinterpret_cast<double*>(base + o_R);
     b.rotvec = reinterpret_cast<double*>(base + o_rv);
     b.status = reinterpret_cast<uint32_t*>(base + o_st);
+    b.mae1 = reinterpret_cast<double*>(base + o_mae);
+    b.mae = b.mae1 + nb;
     b.ref_coef = cubic ? reinterpret_cast<float*>(base + o_coef) : nullptr;
     b.coef_tmp = cubic ? reinterpret_cast<float*>(base + o_coef_tmp) : nullptr;
 
-    bool want_field = mode == Mode::Full && out->field;
+    const bool xcf_first = mode == Mode::Full && p.first_pass == 1;
+    bool want_field = mode == Mode::Full && out->field && !xcf_first;
     b.out.F = out->F;
     b.out.R = out->R;
     b.out.rotvec = out->rotvec;
@@ -456,6 +462,8 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.out.ph = out->peak_height;
     b.out.iters = mode == Mode::Full ? out->iters : nullptr;
     b.out.status = out->status;
+    b.out.mae1 = mode == Mode::Full ? out->mae_first : nullptr;
+    b.out.mae = out->mae;
     b.u_init = warm ? reinterpret_cast<const float*>(base + o_uinit) : u_init;
     if (warm) {
         b.warm_field = reinterpret_cast<const float*>(base + o_wfield);
@@ -635,7 +643,12 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
                                  reinterpret_cast<float*>(base + o_wmis), reinterpret_cast<uint32_t*>(base + o_wflag),
                                  s));
     }
-    if (mode == Mode::Full) {
+    if (xcf_first) {
+        // the conventional first pass: ROI XCF of the unremapped patterns
+        EBSD_TRY(launch_zero_iters(d_bk, b, s));
+        EBSD_TRY(launch_xcf_first(d_bk, b, p.window, s));
+        EBSD_TRY(launch_solve_first(d_bk, b, 0.0f, s));
+    } else if (mode == Mode::Full) {
         EBSD_TRY(launch_demons_init(d_bk, b, s));
         for (int l = L - 1; l >= 0; l--) {
             const int ty = strip_ty_for(h, H >> l, W >> l, nb);
@@ -669,7 +682,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     if (tm) {
         EBSD_TRY(hipEventRecord(h->ev[1], s));
         h->timed_call = true;
-        h->timed_levels = L;
+        h->timed_levels = xcf_first ? 0 : L;  // no demons levels with the XCF first pass
     }
 #undef EBSD_TRY
     return EBSD_OK;
@@ -692,6 +705,7 @@ int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u
     if (mode == Mode::SecondPassOnly && !rfin_in) return EBSD_EINVAL;
     std::vector<HostBucket> buckets = make_buckets(pairs, n);
     if (u_init && buckets.size() != 1) return EBSD_EINVAL;
+    if (u_init && h->p.first_pass == 1) return EBSD_EINVAL;
     if (mode == Mode::Full && !tune_only && !u_init && h->p.warm_start) {
         if (!cnn_ready(h->cnn)) return EBSD_ENOMODEL;
         if (h->p.levels != kWarmLevels) return EBSD_ESHAPE;
@@ -746,6 +760,7 @@ int ebsd_params_default(ebsd_params* p)
     p->fallback_residual_px = 0.5f;
     p->remap_interp = 3;
     p->xcf_passes = 1;
+    p->first_pass = 0;
     return EBSD_OK;
 }
 

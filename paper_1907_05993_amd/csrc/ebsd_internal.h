@@ -51,6 +51,8 @@ struct OutPtrs {
     uint32_t* status;
     float* warm_field;   // [n][h][w][2] network field (warm start)
     float* warm_misfit;  // [n]
+    double* mae1;        // [n] mean angular error of the first fit
+    double* mae;         // [n] mean angular error of the last fit
 };
 // Everything a bucket's kernels need, in device memory (one copy per bucket).
 struct Bucket {
@@ -86,6 +88,8 @@ struct Bucket {
     double* R;                  // [nb][9]
     double* rotvec;             // [nb][3]
     uint32_t* status;           // [nb]
+    double* mae1;               // [nb] mean angular error of the first fit (F1 to q1), rad
+    double* mae;                // [nb] mean angular error of the last fit, rad
     float* ref_coef;            // [nref][H][W] cubic B-spline coefficients of level 0 (NULL: bilinear remap)
     float* coef_tmp;            // [nref][H][W] row pass of the coefficients
     // per-call caller pointers (so that a bucket's launch sequence is static
@@ -127,8 +131,8 @@ hipError_t launch_prolong_level(const Bucket* d_bk, const Bucket& hb, int level,
 hipError_t launch_sample_q1(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Copy the finest field to the caller (bk->field_dst[i] = destination of pair i or NULL).
 hipError_t launch_copy_field(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
-// First-pass solve: F1 from q1 (Eq. (3)), Rfin = polar(F1); status from the
-// input flags and, when tol > 0, the per-level convergence.
+// First-pass solve: F1 from q1 (Eq. (3)), Rfin = polar(F1), mae1; status
+// from the input flags and, when tol > 0, the per-level convergence.
 hipError_t launch_solve_first(const Bucket* d_bk, const Bucket& hb, float tol, hipStream_t s);
 // Status from the input flags only (second-pass-only entry).
 hipError_t launch_status_inputs(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
@@ -138,6 +142,11 @@ hipError_t launch_bspline_coef(const Bucket* d_bk, const Bucket& hb, hipStream_t
 // from bk->ref_coef, 1: bilinear; pass 0 remaps by Rfin, pass k > 0 by F.
 hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, int interp, int pass,
                             hipStream_t s);
+// The conventional first pass: ROI XCF of the unremapped level-0 patterns ->
+// q1, ph.
+hipError_t launch_xcf_first(const Bucket* d_bk, const Bucket& hb, int window, hipStream_t s);
+// iters[b][l] = 0 for every pair and level (no demons iterations run).
+hipError_t launch_zero_iters(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Rfin[b] = bk->rfin_in[pair_index[b]] (second-pass-only entry).
 hipError_t launch_gather_rfin(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
@@ -145,7 +154,7 @@ hipError_t launch_scatter(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 hipError_t launch_scatter_warm(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Second-pass solve: F_inf from q2, F = F_inf M, det 1, R = polar(F), rotvec,
 // with M = Rfin for pass 0 and M = F (the previous pass's) after.
-// second_pass == 0: F = F1.
+// second_pass == 0: F = F1.  mae: of the F_inf fit (of F1 without a second pass).
 hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass, int pass,
                                hipStream_t s);
 

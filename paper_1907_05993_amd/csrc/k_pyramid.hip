@@ -240,6 +240,12 @@ __global__ void k_sample_q1(const Bucket* __restrict__ bk)
     bk->q1[2 * t + 1] = bilinear_clamped(f + (int64_t)H * W, H, W, cx, cy);
 }
 
+__global__ void k_zero_iters(const Bucket* __restrict__ bk)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (int64_t)bk->nb * bk->L) bk->iters[t] = 0;
+}
+
 __global__ void k_copy_field(const Bucket* __restrict__ bk)
 {
     const int b = blockIdx.y;
@@ -327,6 +333,13 @@ hipError_t launch_sample_q1(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
     int n = hb.nb * hb.n_roi;
     hipLaunchKernelGGL(k_sample_q1, dim3((n + 255) / 256), dim3(256), 0, s, d_bk);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_iters(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
+{
+    const int64_t n = (int64_t)hb.nb * hb.L;
+    hipLaunchKernelGGL(k_zero_iters, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_bk);
     return hipGetLastError();
 }
 

@@ -367,6 +367,27 @@ __device__ void rotation_vector(const double* R, double* rv)
     rv[2] = th * w2;
 }
 
+// Mean angular error of the fit F to the shifts of rs (the figure section 3
+// compares remapping methods by; its formula is not given, this reading is
+// used): the mean over the ROIs of the angle between F r_i and r_i + q_i,
+// atan2(|a x b|, a . b).  Both vectors are in units of Z*, which leaves the
+// angles unchanged.
+__device__ double mean_angular_error(const RoiSet& rs, const double* F)
+{
+    double sum = 0.0;
+    for (int i = 0; i < rs.n; i++) {
+        double r0, r1, p0, p1;
+        rs.get(i, r0, r1, p0, p1);
+        const double a0 = F[0] * r0 + F[1] * r1 + F[2];
+        const double a1 = F[3] * r0 + F[4] * r1 + F[5];
+        const double a2 = F[6] * r0 + F[7] * r1 + F[8];
+        // b = (p0, p1, 1)
+        const double c0 = a1 - a2 * p1, c1 = a2 * p0 - a0, c2 = a0 * p1 - a1 * p0;
+        sum += atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), a0 * p0 + a1 * p1 + a2);
+    }
+    return rs.n > 0 ? sum / rs.n : 0.0;
+}
+
 __device__ RoiSet bucket_rois(const Bucket* bk, const float* q)
 {
     RoiSet rs;
@@ -394,7 +415,9 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_first(const Bucket* __r
         else st |= EBSD_HIT_CAP;
     }
     double* F1 = bk->F1 + 9 * (int64_t)b;
-    st |= solve_F(bucket_rois(bk, bk->q1 + 2 * (int64_t)b * bk->n_roi), F1, pool + threadIdx.x);
+    const RoiSet rs = bucket_rois(bk, bk->q1 + 2 * (int64_t)b * bk->n_roi);
+    st |= solve_F(rs, F1, pool + threadIdx.x);
+    bk->mae1[b] = mean_angular_error(rs, F1);
     polar_rot(F1, bk->Rfin + 9 * (int64_t)b);
     bk->status[b] = st;
 }
@@ -422,7 +445,9 @@ __global__ void __launch_bounds__(kSolveThreads)
     uint32_t st = bk->status[b];
     if (second_pass) {
         double Fi[9];
-        st |= solve_F(bucket_rois(bk, bk->q2 + 2 * (int64_t)b * bk->n_roi), Fi, pool + threadIdx.x);
+        const RoiSet rs = bucket_rois(bk, bk->q2 + 2 * (int64_t)b * bk->n_roi);
+        st |= solve_F(rs, Fi, pool + threadIdx.x);
+        bk->mae[b] = mean_angular_error(rs, Fi);
         double Ft[9];
         for (int i = 0; i < 3; i++)
             for (int j = 0; j < 3; j++)
@@ -436,6 +461,7 @@ __global__ void __launch_bounds__(kSolveThreads)
     } else {
         const double* F1 = bk->F1 + 9 * (int64_t)b;
         for (int i = 0; i < 9; i++) F[i] = F1[i];
+        bk->mae[b] = bk->mae1[b];
     }
     double* R = bk->R + 9 * (int64_t)b;
     polar_rot(F, R);
@@ -499,6 +525,8 @@ __global__ void k_scatter(const Bucket* __restrict__ bk)
         for (int l = 0; l < bk->L; l++) o.iters[bk->L * g + l] = bk->iters[bk->L * (int64_t)b + l];
     if (o.status) o.status[g] = bk->status[b];
     if (o.warm_misfit && bk->warm_misfit) o.warm_misfit[g] = bk->warm_misfit[b];
+    if (o.mae1) o.mae1[g] = bk->mae1[b];
+    if (o.mae) o.mae[g] = bk->mae[b];
 }
 
 // blockIdx.y = pair; the field of one pair is h * w * 2 floats.

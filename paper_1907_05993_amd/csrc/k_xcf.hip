@@ -493,6 +493,10 @@ __device__ void xcf_core(XcfShared<N>& S, Loader load, int window, float* q, flo
     }
 }
 
+// One workgroup per (pair, ROI).  INTERP 3 / 1: the second pass, the
+// reference remapped (cubic B-spline / bilinear) -> q2; INTERP 0: the
+// conventional first pass, the unremapped reference ROI -> q1.  Both write
+// the peak height.
 template <int N, int INTERP>
 __global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk, int window, int pass)
 {
@@ -509,7 +513,9 @@ __global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk,
     // (F^-1)^T = cofactor(F) / det F in place of R
     const float* Cf = INTERP == 3 ? bk->ref_coef + (int64_t)bk->ref_slot[b] * H * W : nullptr;
     double m[9];
-    if (pass == 0) {
+    if (INTERP == 0) {
+        for (int i = 0; i < 9; i++) m[i] = 0.0;  // unused
+    } else if (pass == 0) {
         const double* Rf = bk->Rfin + 9 * (int64_t)b;
         for (int i = 0; i < 9; i++) m[i] = Rf[i];
     } else {
@@ -531,6 +537,7 @@ __global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk,
     const double xs = bk->xs, ys = bk->ys, zs = bk->zs;
     auto load = [&](int x, int y) -> float2 {
         const int X = x0 + x, Y = y0 + y;
+        if (INTERP == 0) return make_float2(Rn[(int64_t)Y * W + X], Tn[(int64_t)Y * W + X]);
         const double p0 = (double)X - xs, p1 = (double)Y - ys, p2 = zs;
         // v = R_finite^T r
         const double v0 = r00 * p0 + r10 * p1 + r20 * p2;
@@ -542,7 +549,7 @@ __global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk,
         return make_float2(a, t);
     };
     const int64_t o = (int64_t)b * bk->n_roi + j;
-    xcf_core<N>(S, load, window, bk->q2 + 2 * o, bk->ph + o);
+    xcf_core<N>(S, load, window, (INTERP == 0 ? bk->q1 : bk->q2) + 2 * o, bk->ph + o);
 }
 
 template <int N>
@@ -608,6 +615,11 @@ hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, in
         return launch_pairs_i<3>(d_bk, hb, window, pass, s);
     }
     return launch_pairs_i<1>(d_bk, hb, window, pass, s);
+}
+
+hipError_t launch_xcf_first(const Bucket* d_bk, const Bucket& hb, int window, hipStream_t s)
+{
+    return launch_pairs_i<0>(d_bk, hb, window, 0, s);
 }
 
 hipError_t launch_bspline_coef(const Bucket* d_bk, const Bucket& hb, hipStream_t s)

@@ -55,6 +55,7 @@ class CParams(C.Structure):
         ("fallback_residual_px", C.c_float),
         ("remap_interp", C.c_int32),
         ("xcf_passes", C.c_int32),
+        ("first_pass", C.c_int32),
     ]
 
 
@@ -84,6 +85,8 @@ class COutputs(C.Structure):
         ("status", C.c_void_p),
         ("warm_field", C.c_void_p),
         ("warm_misfit", C.c_void_p),
+        ("mae_first", C.c_void_p),
+        ("mae", C.c_void_p),
     ]
 
 
@@ -202,6 +205,7 @@ class Params:
     fallback_residual_px: float = 0.5
     remap_interp: int = 3
     xcf_passes: int = 1
+    first_pass: int = 0
 
     def to_c(self):
         p = CParams()
@@ -223,6 +227,7 @@ class Params:
         p.fallback_residual_px = self.fallback_residual_px
         p.remap_interp = self.remap_interp
         p.xcf_passes = self.xcf_passes
+        p.first_pass = self.first_pass
         return p
 
 
@@ -297,6 +302,8 @@ class Registrar:
             "peak_height": torch.empty(n, nr, **f32),
             "iters": torch.empty(n, self.params.levels, dtype=torch.int32, device=dev),
             "status": torch.empty(n, dtype=torch.int32, device=dev),
+            "mae_first": torch.empty(n, **f64),
+            "mae": torch.empty(n, **f64),
         }
         if self.params.warm_start and shapes:
             out["warm_field"] = torch.empty(n, 64, 64, 2, **f32)
@@ -315,7 +322,7 @@ class Registrar:
         co.field = out["_field_flat"].data_ptr() if want_field else None
         co.field_offset = offs.ctypes.data if want_field else None
         for k in ("F", "R", "rotvec", "R_finite", "F_first", "q1", "q2", "peak_height", "iters",
-                  "status", "warm_field", "warm_misfit"):
+                  "status", "warm_field", "warm_misfit", "mae_first", "mae"):
             if k in out:
                 setattr(co, k, out[k].data_ptr())
         return out, co
@@ -340,10 +347,13 @@ class Registrar:
         one reference pyramid.  u_init: optional [n, 2, h, w] coarsest-level
         initial field (full-res px).  Returns a dict of device tensors:
         field, F, R, rotvec, R_finite, F_first, q1, q2, peak_height, iters,
-        status.  Runs on torch's current stream.
+        status, mae_first, mae (mean angular errors of the first and the last
+        fit, rad).  With first_pass = 1 (the conventional XCF first pass) no
+        field is returned.  Runs on torch's current stream.
         """
         arr, n, shapes, keep = self._pairs(refs, tests, ref_ids)
         dev = keep[0].device if keep else torch.device("cuda", self.device)
+        want_field = want_field and self.params.first_pass == 0
         out, co = self._outputs(shapes, want_field, dev)
         if u_init is not None:
             if not (u_init.is_cuda and u_init.dtype == torch.float32 and u_init.is_contiguous()):
@@ -411,7 +421,7 @@ class Registrar:
         _check(lib().ebsd_second_pass_batch(self._h, arr, n, _ptr(rf), C.byref(co), _stream()),
                "ebsd_second_pass_batch")
         out["_keep"] = (keep, co, arr, rf)
-        for k in ("F_first", "q1", "iters"):
+        for k in ("F_first", "q1", "iters", "mae_first"):
             out.pop(k)
         return out
 

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(E):
 
 def test_version_defaults_strerror(E):
     L = E.lib()
-    assert L.ebsd_version() == 3
+    assert L.ebsd_version() == 4
     p = E.CParams()
     assert L.ebsd_params_default(C.byref(p)) == 0
     assert p.struct_size == C.sizeof(E.CParams)
@@ -46,7 +46,7 @@ def test_version_defaults_strerror(E):
     assert abs(p.sigma_px - 1.0) < 1e-7 and p.n_roi == 20 and p.roi_size == 64
     assert p.window == 1 and p.second_pass == 1
     assert p.warm_start == 0 and abs(p.fallback_residual_px - 0.5) < 1e-7
-    assert p.remap_interp == 3 and p.xcf_passes == 1
+    assert p.remap_interp == 3 and p.xcf_passes == 1 and p.first_pass == 0
     # the defaults are exactly the Python mirror's (pattern centre and ring radius as doubles)
     q = E.Params().to_c()
     for f, _ in E.CParams._fields_:
@@ -67,11 +67,14 @@ def test_create_validates_before_touching_the_device(E):
                              ("window", 2, -1), ("pc_z", 0.0, -1), ("tol_px", float("nan"), -1),
                              ("warm_start", 3, -1), ("fallback_residual_px", -1.0, -1),
                              ("remap_interp", 2, -1), ("remap_interp", 0, -1), ("xcf_passes", 0, -1),
-                             ("xcf_passes", 17, -1)]:
+                             ("xcf_passes", 17, -1), ("first_pass", 2, -1), ("first_pass", -1, -1)]:
         p = E.Params().to_c()
         setattr(p, field, val)
         assert L.ebsd_create(C.byref(p), 0, C.byref(h)) == code, field
     assert L.ebsd_create(C.byref(E.Params().to_c()), 0, None) == -1
+    # the conventional first pass takes no warm start
+    p = E.Params(first_pass=1, warm_start=1).to_c()
+    assert L.ebsd_create(C.byref(p), 0, C.byref(h)) == -1
 
 
 def test_create_without_gpu_reports_device_error(E):
