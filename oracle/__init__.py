@@ -117,6 +117,11 @@ def lib():
         L.orc_det_normalize.argtypes = [d]
         L.orc_solve_F.restype = C.c_uint32
         L.orc_solve_F.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d]
+        L.orc_stress.argtypes = [d, d, C.c_double, C.c_double, C.c_double, d]
+        L.orc_strain_stress.argtypes = [d, d, d, C.c_double, C.c_double, C.c_double, d, d, d]
+        L.orc_solve_F_traction_free.restype = C.c_uint32
+        L.orc_solve_F_traction_free.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d, d,
+                                                d, C.c_double, C.c_double, C.c_double, d, d, d]
         L.orc_mae.restype = C.c_double
         L.orc_mae.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d]
         L.orc_polar.argtypes = [d, d]
@@ -286,6 +291,41 @@ def mae(q, F, cx, cy, pcs):
     F = _f64(F).reshape(9)
     return float(lib().orc_mae(_d(q), _d(cx), _d(cy), len(cx), float(pcs[0]), float(pcs[1]),
                                float(pcs[2]), _d(F)))
+
+
+def stress(eps_S, g, C):
+    """Sample-frame stress of a sample-frame strain (Eq. (16), supplementary
+    Eq. (2.4)-(2.8)): g is the passive sample-to-crystal orientation, C =
+    (C11, C12, C44) the cubic stiffness of the crystal frame."""
+    e = _f64(eps_S).reshape(9)
+    out = np.empty(9)
+    lib().orc_stress(_d(e), _d(_f64(g).reshape(9)), float(C[0]), float(C[1]), float(C[2]), _d(out))
+    return out.reshape(3, 3)
+
+
+def strain_stress(F, S, g, C):
+    """(F_S, eps_S, sigma_S) of a detector-frame F (Eq. (14)-(16)); S is the
+    detector-to-sample rotation."""
+    FS, e, sg = np.empty(9), np.empty(9), np.empty(9)
+    lib().orc_strain_stress(_d(_f64(F).reshape(9)), _d(_f64(S).reshape(9)), _d(_f64(g).reshape(9)),
+                            float(C[0]), float(C[1]), float(C[2]), _d(FS), _d(e), _d(sg))
+    return FS.reshape(3, 3), e.reshape(3, 3), sg.reshape(3, 3)
+
+
+def solve_F_traction_free(q, cx, cy, pcs, S, g, C, M=None):
+    """Eq. (3) under the traction-free constraint sigma_S33 = sigma_S23 =
+    sigma_S13 = 0 of the total F = F_inf M.  Returns (F, eps_S, sigma_S,
+    status)."""
+    q = _f64(q).reshape(-1, 2)
+    cx = _f64(cx)
+    cy = _f64(cy)
+    F, e, sg = np.empty(9), np.empty(9), np.empty(9)
+    Mm = _f64(M).reshape(9) if M is not None else None
+    st = lib().orc_solve_F_traction_free(_d(q), _d(cx), _d(cy), len(cx), float(pcs[0]), float(pcs[1]),
+                                         float(pcs[2]), _d(Mm) if Mm is not None else None,
+                                         _d(_f64(S).reshape(9)), _d(_f64(g).reshape(9)), float(C[0]),
+                                         float(C[1]), float(C[2]), _d(F), _d(e), _d(sg))
+    return F.reshape(3, 3), e.reshape(3, 3), sg.reshape(3, 3), int(st)
 
 
 def polar(F):

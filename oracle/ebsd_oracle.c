@@ -652,6 +652,190 @@ uint32_t orc_solve_F(const double* q, const double* cx, const double* cy, int n,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Stress of a sample-frame strain (Eq. (16); supplementary Eq. (2.4)-(2.8)).
+ * The strain goes to the crystal frame, eps_C = g eps_S g^T (g: the passive
+ * orientation taking sample coordinates to crystal coordinates, Eq. (2.1)),
+ * Hooke's law acts there with the cubic stiffness in Voigt form (C11 on the
+ * normal strains, C12 between them, C44 on the engineering shears
+ * 2 eps_ij), and the stress comes back, sigma_S = g^T sigma_C g.           */
+void orc_stress(const double* eps_S, const double* g, double C11, double C12, double C44,
+                double* sig_S)
+{
+    double t[9], e[9], sc[9];
+    matmul3(g, eps_S, t);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) e[3 * i + j] = t[3 * i] * g[3 * j] + t[3 * i + 1] * g[3 * j + 1] +
+                                                   t[3 * i + 2] * g[3 * j + 2];
+    sc[0] = C11 * e[0] + C12 * (e[4] + e[8]);
+    sc[4] = C11 * e[4] + C12 * (e[0] + e[8]);
+    sc[8] = C11 * e[8] + C12 * (e[0] + e[4]);
+    sc[1] = sc[3] = C44 * (e[1] + e[3]);
+    sc[2] = sc[6] = C44 * (e[2] + e[6]);
+    sc[5] = sc[7] = C44 * (e[5] + e[7]);
+    /* sigma_S = g^T sc g */
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double acc = 0.0;
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++) acc += g[3 * a + i] * sc[3 * a + b] * g[3 * b + j];
+            sig_S[3 * i + j] = acc;
+        }
+}
+
+/* Strain and stress of a detector-frame deformation gradient (Eq. (14)-(16)):
+ * F_S = S F S^T with S the detector-to-sample rotation (Eq. (13)'s R_tilt
+ * is one), eps_S = (F_S F_S^T - I)/2 (the first form of Eq. (15): the
+ * rotation in F cancels), sigma_S from orc_stress.  Any output may be NULL. */
+void orc_strain_stress(const double* F, const double* S, const double* g, double C11, double C12,
+                       double C44, double* FS_out, double* eps_out, double* sig_out)
+{
+    double t[9], FS[9], eps[9], sig[9];
+    matmul3(S, F, t);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            FS[3 * i + j] = t[3 * i] * S[3 * j] + t[3 * i + 1] * S[3 * j + 1] + t[3 * i + 2] * S[3 * j + 2];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            eps[3 * i + j] = 0.5 * (FS[3 * i] * FS[3 * j] + FS[3 * i + 1] * FS[3 * j + 1] +
+                                    FS[3 * i + 2] * FS[3 * j + 2] - (i == j ? 1.0 : 0.0));
+    orc_stress(eps, g, C11, C12, C44, sig);
+    if (FS_out) memcpy(FS_out, FS, sizeof FS);
+    if (eps_out) memcpy(eps_out, eps, sizeof eps);
+    if (sig_out) memcpy(sig_out, sig, sizeof sig);
+}
+
+/* The three surface tractions of the total F = X M, sigma_S33, sigma_S23,
+ * sigma_S13, divided by C11, and (if A != NULL) their derivatives with
+ * respect to the nine entries of X (A: 3 x 9, row-major): eps_S is
+ * quadratic in X, d eps_S = (dF_S F_S^T + F_S dF_S^T)/2 with
+ * dF_S = S E_ab M S^T, and the stress is linear in the strain.            */
+static void traction_terms(const double* X, const double* M, const double* S, const double* g,
+                           double C11, double C12, double C44, double* c, double* A)
+{
+    double F[9], FS[9], sig[9];
+    matmul3(X, M, F);
+    orc_strain_stress(F, S, g, C11, C12, C44, FS, NULL, sig);
+    c[0] = sig[8] / C11;
+    c[1] = sig[5] / C11;
+    c[2] = sig[2] / C11;
+    if (!A) return;
+    double MS[9]; /* M S^T */
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) MS[3 * i + j] = M[3 * i] * S[3 * j] + M[3 * i + 1] * S[3 * j + 1] + M[3 * i + 2] * S[3 * j + 2];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            double dFS[9], de[9], ds[9];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) dFS[3 * i + j] = S[3 * i + a] * MS[3 * b + j];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 3; k++) acc += dFS[3 * i + k] * FS[3 * j + k] + FS[3 * i + k] * dFS[3 * j + k];
+                    de[3 * i + j] = 0.5 * acc;
+                }
+            orc_stress(de, g, C11, C12, C44, ds);
+            A[0 * 9 + 3 * a + b] = ds[8] / C11;
+            A[1 * 9 + 3 * a + b] = ds[5] / C11;
+            A[2 * 9 + 3 * a + b] = ds[2] / C11;
+        }
+}
+
+/* Eq. (3) under the traction-free equality constraint (section 2; Eq. (16);
+ * supplementary Part 2): minimise the Eq. (3) objective over F_inf subject
+ * to sigma_S33 = sigma_S23 = sigma_S13 = 0 (no traction on the surface,
+ * t = sigma_S z_S) for the total F = F_inf M (M: what a second-pass fit
+ * composes with, Eq. (12); NULL = identity, a first-pass fit).  The
+ * objective fixes F_inf only up to scale; the constraints fix the scale and
+ * tie two more directions.
+ *   1. F_inf up to scale: orc_solve_F.
+ *   2. Starting scale from sigma_S33 = 0 alone: with B = F_S F_S^T at unit
+ *      scale, sigma(s) = (s^2 sigma[B] - sigma[I]) / 2 (sigma[.] Hooke's law
+ *      of a strain), so s^2 = sigma[I]_33 / sigma[B]_33.
+ *   3. Lagrange-Newton steps over all nine entries (Gauss-Newton on the
+ *      objective, Newton on the constraints): [J^T J  A^T; A  0] [d; l] =
+ *      [-J^T e; -c], e the residuals in units of Z*, J their Jacobian, c the
+ *      three stresses over C11 and A their Jacobian; stop when |d| < 1e-14
+ *      or after 100 steps.
+ * F receives the total F (detector frame), eps and sig (optional) the
+ * sample-frame strain and stress (units of the stiffness constants).
+ * Returns ORC_SOLVE_ILLCOND if a step fails or the steps do not converge. */
+uint32_t orc_solve_F_traction_free(const double* q, const double* cx, const double* cy, int n,
+                                   double xs, double ys, double zs, const double* M_in,
+                                   const double* S, const double* g, double C11, double C12,
+                                   double C44, double* F, double* eps, double* sig)
+{
+    const double I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    const double* M = M_in ? M_in : I3;
+    double X[9];
+    uint32_t st = orc_solve_F(q, cx, cy, n, xs, ys, zs, X);
+    /* 2. starting scale */
+    {
+        double Ft[9], B[9], sB[9], sI[9];
+        matmul3(X, M, Ft);
+        orc_strain_stress(Ft, S, g, C11, C12, C44, NULL, B, NULL);
+        for (int i = 0; i < 9; i++) B[i] = 2.0 * B[i] + I3[i]; /* F_S F_S^T */
+        orc_stress(B, g, C11, C12, C44, sB);
+        orc_stress(I3, g, C11, C12, C44, sI);
+        double s2 = sI[8] / sB[8];
+        if (!(s2 > 0.0) || !isfinite(s2)) {
+            st |= ORC_SOLVE_ILLCOND;
+            s2 = 1.0;
+        }
+        for (int i = 0; i < 9; i++) X[i] *= sqrt(s2);
+    }
+    /* 3. Lagrange-Newton */
+    int done = 0;
+    for (int it = 0; it < 100 && !done; it++) {
+        double K[144], rhs[12], sol[12];
+        memset(K, 0, sizeof K);
+        memset(rhs, 0, sizeof rhs);
+        for (int i = 0; i < n; i++) {
+            double r[3] = {(cx[i] - xs) / zs, (cy[i] - ys) / zs, 1.0};
+            double px = (cx[i] - xs + q[2 * i]) / zs, py = (cy[i] - ys + q[2 * i + 1]) / zs;
+            double n1 = X[0] * r[0] + X[1] * r[1] + X[2] * r[2];
+            double n2 = X[3] * r[0] + X[4] * r[1] + X[5] * r[2];
+            double d = X[6] * r[0] + X[7] * r[1] + X[8] * r[2];
+            double ex = n1 / d - px, ey = n2 / d - py;
+            double jx[9] = {r[0] / d, r[1] / d, r[2] / d, 0, 0, 0,
+                            -n1 * r[0] / (d * d), -n1 * r[1] / (d * d), -n1 * r[2] / (d * d)};
+            double jy[9] = {0, 0, 0, r[0] / d, r[1] / d, r[2] / d,
+                            -n2 * r[0] / (d * d), -n2 * r[1] / (d * d), -n2 * r[2] / (d * d)};
+            for (int a = 0; a < 9; a++) {
+                rhs[a] -= jx[a] * ex + jy[a] * ey;
+                for (int b = 0; b < 9; b++) K[12 * a + b] += jx[a] * jx[b] + jy[a] * jy[b];
+            }
+        }
+        double c[3], A[27];
+        traction_terms(X, M, S, g, C11, C12, C44, c, A);
+        for (int k = 0; k < 3; k++) {
+            rhs[9 + k] = -c[k];
+            for (int a = 0; a < 9; a++) {
+                K[12 * (9 + k) + a] = A[9 * k + a];
+                K[12 * a + 9 + k] = A[9 * k + a];
+            }
+        }
+        if (orc_gauss_solve(K, rhs, 12, sol)) {
+            st |= ORC_SOLVE_ILLCOND;
+            break;
+        }
+        double nrm = 0.0;
+        for (int a = 0; a < 9; a++) {
+            X[a] += sol[a];
+            nrm += sol[a] * sol[a];
+        }
+        if (!isfinite(nrm)) {
+            st |= ORC_SOLVE_ILLCOND;
+            break;
+        }
+        if (sqrt(nrm) < 1e-14) done = 1;
+    }
+    if (!done) st |= ORC_SOLVE_ILLCOND;
+    matmul3(X, M, F);
+    orc_strain_stress(F, S, g, C11, C12, C44, NULL, eps, sig);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Polar rotation, Eq. (4)-(5): F = P D Q^T (SVD), R = P Q^T.  With the
  * eigen-decomposition F^T F = Q D^2 Q^T, P = F Q D^-1 and so
  * R = F Q D^-1 Q^T.  If det R < 0 the last column of P is negated.        */

@@ -364,6 +364,141 @@ def test_mae_equals_mean_aligning_rotation_angle(orc):
     np.testing.assert_allclose(orc.mae(q, F, cx, cy, pcs), np.mean(angs), rtol=1e-9)
 
 
+# -- traction-free constraint, strain and stress (Eq. (13)-(16), supplementary Part 2) -----------
+
+NI = (2.76e11, 1.59e11, 1.32e11)  # the paper's nickel constants C11, C12, C44, Pa
+
+
+def _cubic_tensor(C11, C12, C44):
+    Ct = np.zeros((3, 3, 3, 3))
+    for i in range(3):
+        for j in range(3):
+            if i == j:
+                Ct[i, i, i, i] = C11
+            else:
+                Ct[i, i, j, j] = C12
+                Ct[i, j, i, j] = Ct[i, j, j, i] = C44
+    return Ct
+
+
+def _stress_tensor_route(eps_S, g, C):
+    # the fourth-order stiffness rotated into the sample frame, C_S = g g g g : C
+    CS = np.einsum("pi,qj,rk,sl,pqrs->ijkl", g, g, g, g, _cubic_tensor(*C))
+    return np.einsum("ijkl,kl->ij", CS, eps_S)
+
+
+def _r_tilt(theta):
+    # Eq. (13) as printed
+    c, s = math.cos(theta), math.sin(theta)
+    return np.array([[c, s, 0.0], [-s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def _sym(a):
+    return 0.5 * (a + a.T)
+
+
+def test_stress_matches_rotated_fourth_order_tensor(orc):
+    r = rng(50)
+    for k in range(5):
+        g = Rotation.random(random_state=100 + k).as_matrix()
+        eps = _sym(r.normal(scale=1e-3, size=(3, 3)))
+        np.testing.assert_allclose(orc.stress(eps, g, NI), _stress_tensor_route(eps, g, NI), rtol=1e-12,
+                                   atol=1e-12 * NI[0] * 1e-3)
+
+
+def test_stress_isotropic_and_cubic_symmetry(orc):
+    eps = _sym(rng(51).normal(scale=1e-3, size=(3, 3)))
+    g = Rotation.random(random_state=7).as_matrix()
+    # isotropic constants: Lame's law in every orientation
+    lam, mu = 1.2e11, 0.8e11
+    iso = orc.stress(eps, g, (lam + 2 * mu, lam, mu))
+    np.testing.assert_allclose(iso, lam * np.trace(eps) * np.eye(3) + 2 * mu * eps, rtol=1e-12, atol=1e-3)
+    # a cube symmetry applied to the crystal frame leaves the stress unchanged
+    P = Rotation.from_euler("z", 90, degrees=True).as_matrix()
+    np.testing.assert_allclose(orc.stress(eps, P @ g, NI), orc.stress(eps, g, NI), rtol=1e-12, atol=1e-3)
+
+
+def _traction_free_strain(inplane, g, C):
+    """A sample-frame strain with the given in-plane parts (e11, e22, e12) and
+    e33, e23, e13 chosen so that sigma_S33 = sigma_S23 = sigma_S13 = 0."""
+    e11, e22, e12 = inplane
+    base = np.array([[e11, e12, 0.0], [e12, e22, 0.0], [0.0, 0.0, 0.0]])
+    basis = [np.diag([0.0, 0.0, 1.0]), _sym(np.outer([0, 1, 0], [0, 0, 1])) * 2,
+             _sym(np.outer([1, 0, 0], [0, 0, 1])) * 2]
+    pick = lambda sg: np.array([sg[2, 2], sg[1, 2], sg[0, 2]])
+    Amat = np.stack([pick(_stress_tensor_route(b, g, C)) for b in basis], axis=1)
+    x = np.linalg.solve(Amat, -pick(_stress_tensor_route(base, g, C)))
+    return base + sum(xi * b for xi, b in zip(x, basis))
+
+
+def _traction_free_case(seed):
+    g = Rotation.random(random_state=seed).as_matrix()
+    S = _r_tilt(math.radians(70.0))
+    eps_S = _traction_free_strain((1.2e-3, -0.7e-3, 0.5e-3), g, NI)
+    V = np.real(scipy.linalg.sqrtm(np.eye(3) + 2 * eps_S))  # F_S F_S^T = I + 2 eps_S (Eq. (15))
+    F_S = V @ Rotation.from_rotvec([0.01, -0.02, 0.03]).as_matrix()
+    F = S.T @ F_S @ S  # Eq. (14): F_S = S F S^T
+    return g, S, eps_S, F
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_traction_free_recovers_exact_F_with_scale(orc, seed):
+    """Exact shifts of a traction-free F: the constrained solve returns F itself,
+    its scale included (which Eq. (3) alone cannot fix), the strain it was built
+    from and zero surface tractions; likewise for a second-pass fit F_inf
+    composing with a finite rotation M (F = F_inf M)."""
+    cx, cy, pcs = _layout()
+    g, S, eps_S, F = _traction_free_case(seed)
+    q = _project(F, cx, cy, *pcs)
+    Fo, eo, so, st = orc.solve_F_traction_free(q, cx, cy, pcs, S, g, NI)
+    assert st == 0
+    np.testing.assert_allclose(Fo, F, atol=1e-12)
+    np.testing.assert_allclose(eo, eps_S, atol=1e-12)
+    assert np.abs(so[2, :]).max() < 1e-12 * NI[0]
+    np.testing.assert_allclose(so, _stress_tensor_route(eps_S, g, NI), atol=1e-12 * NI[0])
+    # the unconstrained det-1 solution differs from F by its scale only
+    Fd, _ = orc.solve_F(q, cx, cy, pcs)
+    np.testing.assert_allclose(Fd * np.cbrt(np.linalg.det(F)), F, atol=1e-12)
+    # second-pass form
+    M = Rotation.from_rotvec([0.05, 0.12, -0.07]).as_matrix()
+    q2 = _project(F @ M.T, cx, cy, *pcs)
+    F2, e2, _, st2 = orc.solve_F_traction_free(q2, cx, cy, pcs, S, g, NI, M=M)
+    assert st2 == 0
+    np.testing.assert_allclose(F2, F, atol=1e-12)
+    np.testing.assert_allclose(e2, eps_S, atol=1e-12)
+
+
+def test_traction_free_matches_scipy_constrained_minimiser(orc):
+    """Noisy shifts: the constrained minimiser agrees with scipy's SLSQP on the
+    same objective (Eq. (3)) and constraints (surface tractions from the
+    rotated fourth-order stiffness)."""
+    cx, cy, pcs = _layout()
+    xs, ys, zs = pcs
+    g, S, _, F = _traction_free_case(5)
+    M = Rotation.from_rotvec([0.03, -0.04, 0.02]).as_matrix()
+    q = _project(F @ M.T, cx, cy, *pcs) + rng(52).normal(scale=0.05, size=(20, 2))
+    Fo, eo, so, st = orc.solve_F_traction_free(q, cx, cy, pcs, S, g, NI, M=M)
+    assert st == 0
+
+    def obj(x):
+        return 0.5 * np.sum(((_project(x.reshape(3, 3), cx, cy, xs, ys, zs) - q) / zs) ** 2)
+
+    def cons(x):
+        FS = S @ (x.reshape(3, 3) @ M) @ S.T
+        sg = _stress_tensor_route(0.5 * (FS @ FS.T - np.eye(3)), g, NI) / NI[0]
+        return np.array([sg[2, 2], sg[1, 2], sg[0, 2]])
+
+    x0 = (F @ M.T).ravel()
+    sol = scipy.optimize.minimize(obj, x0, method="SLSQP", constraints=[{"type": "eq", "fun": cons}],
+                                  options={"ftol": 1e-20, "maxiter": 500})
+    Fs = sol.x.reshape(3, 3) @ M
+    assert np.abs(cons(sol.x)).max() < 1e-10
+    # SLSQP stops ~1e-8 short of the minimum; the oracle's point is feasible and no worse
+    np.testing.assert_allclose(Fo, Fs, atol=3e-8)
+    assert obj((Fo @ M.T).ravel()) <= obj(sol.x) * (1 + 1e-12)
+    assert np.abs(so[2, :]).max() < 1e-12 * NI[0]
+
+
 def test_polar_matches_scipy(orc):
     F = np.eye(3) + rng(31).normal(scale=0.05, size=(3, 3))
     R = orc.polar(F)
