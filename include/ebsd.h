@@ -389,6 +389,37 @@ int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t
 int ebsd_stage_remap(const float* img, int32_t n, int32_t H, int32_t W, const double* R, double xs,
                      double ys, double zs, int32_t interp, float* coef, float* out, void* stream);
 
+/* Eq. (3) under the traction-free equality constraint, with the strain and
+ * stress it implies (section 2; Eq. (13)-(16); supplementary Eq. (2.1)-(2.11)).
+ * For each of n shift sets q [n][n_roi][2] (fp32, device) at the ROI centres
+ * cx, cy ([n_roi] fp64, device), pattern centre (xs, ys) and detector
+ * distance zs in px: F_inf minimises the Eq. (3) objective subject to zero
+ * traction on the sample surface, sigma_S33 = sigma_S23 = sigma_S13 = 0, for
+ * the total F = F_inf M (detector frame), where
+ *   F_S = S F S^T                   (Eq. (14); S: detector-to-sample rotation,
+ *                                    HOST, 9 fp64 row-major, e.g. Eq. (13)'s
+ *                                    R_tilt),
+ *   eps_S = (F_S F_S^T - I) / 2     (Eq. (15), its first form: free of the
+ *                                    rotation in F),
+ *   sigma_S = g^T (C : (g eps_S g^T)) g  (Eq. (16) with the stiffness taken
+ *                                    to the sample frame, supplementary
+ *                                    Eq. (2.4)-(2.11); C cubic with C11, C12,
+ *                                    C44 in any stress unit; g [n][9] fp64,
+ *                                    device: the passive orientation taking
+ *                                    sample to crystal coordinates, Eq. (2.1)).
+ * The shifts fix F_inf up to scale; the constraint fixes the scale (and two
+ * more directions).  M [n][9] (device) is what the fit composes with:
+ * R_finite for the shifts q2 of a single second pass, NULL (identity) for a
+ * first-pass fit (q1).  Outputs (device): F [n][9] the total F, eps_S and
+ * sigma_S [n][9] (may be NULL), status [n] (may be NULL; SOLVE_ILLCOND when
+ * a step fails or the steps do not converge).  EBSD_EINVAL for NULL inputs,
+ * n_roi outside 5..256, zs <= 0, an S that is not a rotation, or a stiffness
+ * that is not positive definite (C44 > 0, C11 > C12, C11 + 2 C12 > 0). */
+int ebsd_traction_free(const float* q, int32_t n, int32_t n_roi, const double* cx, const double* cy,
+                       double xs, double ys, double zs, const double* M, const double* g, const double* S,
+                       double C11, double C12, double C44, double* F, double* eps_S, double* sigma_S,
+                       uint32_t* status, void* stream);
+
 /* Eq. (3) solve for n shift sets: q [n][n_roi][2] fp32 at ROI centres
  * cx, cy (device, [n_roi] fp64), pattern centre (xs, ys, zs) in px.
  * Writes F [n][9] (det 1) and, if R != NULL, R = polar(F) [n][9] (fp64);

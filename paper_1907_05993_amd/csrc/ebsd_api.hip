@@ -1060,4 +1060,36 @@ int ebsd_stage_solve(const float* q, int32_t n, int32_t n_roi, const double* cx,
                                       (hipStream_t)stream));
 }
 
+int ebsd_traction_free(const float* q, int32_t n, int32_t n_roi, const double* cx, const double* cy,
+                       double xs, double ys, double zs, const double* M, const double* g, const double* S,
+                       double C11, double C12, double C44, double* F, double* eps_S, double* sigma_S,
+                       uint32_t* status, void* stream)
+{
+    if (n < 0 || (n > 0 && (!q || !cx || !cy || !g || !F))) return EBSD_EINVAL;
+    if (n_roi < 5 || n_roi > 256 || !(zs > 0.0) || !std::isfinite(xs) || !std::isfinite(ys) || !std::isfinite(zs))
+        return EBSD_EINVAL;
+    if (!S) return EBSD_EINVAL;
+    // a rotation: S S^T = I, det S = +1
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            const double d = S[3 * i] * S[3 * j] + S[3 * i + 1] * S[3 * j + 1] + S[3 * i + 2] * S[3 * j + 2];
+            if (!(std::fabs(d - (i == j ? 1.0 : 0.0)) <= 1e-9)) return EBSD_EINVAL;
+        }
+    const double det = S[0] * (S[4] * S[8] - S[5] * S[7]) - S[1] * (S[3] * S[8] - S[5] * S[6]) +
+                       S[2] * (S[3] * S[7] - S[4] * S[6]);
+    if (!(det > 0.0)) return EBSD_EINVAL;
+    // a positive definite cubic stiffness
+    if (!std::isfinite(C11) || !std::isfinite(C12) || !std::isfinite(C44) || !(C44 > 0.0) || !(C11 - C12 > 0.0) ||
+        !(C11 + 2.0 * C12 > 0.0))
+        return EBSD_EINVAL;
+    if (n == 0) return EBSD_OK;
+    TractionFrame tf;
+    for (int i = 0; i < 9; i++) tf.S[i] = S[i];
+    tf.c11 = C11;
+    tf.c12 = C12;
+    tf.c44 = C44;
+    return map_err(launch_traction_free(q, n, n_roi, cx, cy, xs, ys, zs, M, g, tf, F, eps_S, sigma_S, status,
+                                        (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -173,6 +173,18 @@ hipError_t launch_stage_remap(const float* ref, int n, int H, int W, const doubl
 hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx,
                               const double* cy, double xs, double ys, double zs, double* F,
                               double* R, uint32_t* status, hipStream_t s);
+// Detector-to-sample rotation S (Eq. (13)-(14)) and the cubic stiffness of
+// the crystal frame, for the traction-free solve.
+struct TractionFrame {
+    double S[9];
+    double c11, c12, c44;
+};
+// Eq. (3) under the traction-free constraint for n shift sets; M [n][9]
+// (NULL = identity), g [n][9]; F, eps, sig [n][9] (eps, sig may be NULL).
+hipError_t launch_traction_free(const float* q, int n, int n_roi, const double* cx, const double* cy,
+                                double xs, double ys, double zs, const double* M, const double* g,
+                                const TractionFrame& tf, double* F, double* eps, double* sig,
+                                uint32_t* status, hipStream_t s);
 
 // Number of demons tiles of an h x w level (2-D tile kernel).
 inline int demons_tiles(int h, int w)

@@ -491,6 +491,216 @@ __global__ void __launch_bounds__(kSolveThreads) k_stage_solve(const float* __re
     if (status) status[b] = st;
 }
 
+// ---- traction-free constraint, strain and stress ----------------------------------
+
+// sigma_S of a sample-frame strain e: the strain in crystal coordinates
+// g e g^T (g: passive, sample -> crystal), the cubic Hooke law in Voigt form
+// (c11 normal, c12 between normals, c44 on the engineering shears), the
+// stress back in sample coordinates, g^T sigma_C g.
+__device__ void hooke_sample(const double* e, const double* g, const TractionFrame& tf, double* sig)
+{
+    double t[9], ec[9], sc[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) t[3 * i + j] = g[3 * i] * e[j] + g[3 * i + 1] * e[3 + j] + g[3 * i + 2] * e[6 + j];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) ec[3 * i + j] = t[3 * i] * g[3 * j] + t[3 * i + 1] * g[3 * j + 1] + t[3 * i + 2] * g[3 * j + 2];
+    const double tr = ec[0] + ec[4] + ec[8];
+    const double dc = tf.c11 - tf.c12;
+    sc[0] = dc * ec[0] + tf.c12 * tr;
+    sc[4] = dc * ec[4] + tf.c12 * tr;
+    sc[8] = dc * ec[8] + tf.c12 * tr;
+    sc[1] = sc[3] = tf.c44 * (ec[1] + ec[3]);
+    sc[2] = sc[6] = tf.c44 * (ec[2] + ec[6]);
+    sc[5] = sc[7] = tf.c44 * (ec[5] + ec[7]);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) t[3 * i + j] = sc[3 * i] * g[j] + sc[3 * i + 1] * g[3 + j] + sc[3 * i + 2] * g[6 + j];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) sig[3 * i + j] = g[i] * t[j] + g[3 + i] * t[3 + j] + g[6 + i] * t[6 + j];
+}
+
+// F_S = S F S^T (Eq. (14)) and B = F_S F_S^T.
+__device__ void sample_frame(const double* F, const double* S, double* FS, double* B)
+{
+    double t[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) t[3 * i + j] = S[3 * i] * F[j] + S[3 * i + 1] * F[3 + j] + S[3 * i + 2] * F[6 + j];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) FS[3 * i + j] = t[3 * i] * S[3 * j] + t[3 * i + 1] * S[3 * j + 1] + t[3 * i + 2] * S[3 * j + 2];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            B[3 * i + j] = FS[3 * i] * FS[3 * j] + FS[3 * i + 1] * FS[3 * j + 1] + FS[3 * i + 2] * FS[3 * j + 2];
+}
+
+// Eq. (3) under the traction-free constraint for one shift set (section 2,
+// Eq. (16), supplementary Part 2): minimise Eq. (3) over X = F_inf subject to
+// sigma_S33 = sigma_S23 = sigma_S13 = 0 for the total F = X M, with
+// eps_S = (F_S F_S^T - I) / 2 (Eq. (15)).  Start: the det-1 solution scaled so
+// that sigma_S33 = 0 (sigma is (s^2 sigma[B] - sigma[I]) / 2 at scale s); then
+// Lagrange-Newton steps [J^T J  A^T; A  0] [d; l] = [-J^T e; -c] over the nine
+// entries (e in units of Z*, c the three stresses over c11), the augmented
+// 12 x 13 system in this thread's LDS pool.  Writes F, eps_S, sigma_S.
+__device__ uint32_t solve_F_traction_free(const RoiSet& rs, const double* M, const double* g,
+                                          const TractionFrame& tf, double* F, double* eps, double* sig,
+                                          double* pool)
+{
+    double X[9];
+    uint32_t st = solve_F(rs, X, pool);
+    const double* S = tf.S;
+    double MSt[9];  // M S^T
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) MSt[3 * i + j] = M[3 * i] * S[3 * j] + M[3 * i + 1] * S[3 * j + 1] + M[3 * i + 2] * S[3 * j + 2];
+    const double I3[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    {
+        double Ft[9], FS[9], B[9], sB[9], sI[9];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) Ft[3 * i + j] = X[3 * i] * M[j] + X[3 * i + 1] * M[3 + j] + X[3 * i + 2] * M[6 + j];
+        sample_frame(Ft, S, FS, B);
+        hooke_sample(B, g, tf, sB);
+        hooke_sample(I3, g, tf, sI);
+        double s2 = sI[8] / sB[8];
+        if (!(s2 > 0.0) || !isfinite(s2)) {
+            st |= EBSD_SOLVE_ILLCOND;
+            s2 = 1.0;
+        }
+        const double sc = sqrt(s2);
+        for (int i = 0; i < 9; i++) X[i] *= sc;
+    }
+    const LMat<13> K{pool};
+    bool done = false;
+    for (int it = 0; it < 100 && !done; it++) {
+        for (int a = 0; a < 12; a++)
+            for (int b = 0; b < 13; b++) K(a, b) = 0.0;
+        for (int i = 0; i < rs.n; i++) {
+            double r0, r1, p0, p1;
+            rs.get(i, r0, r1, p0, p1);
+            const double n1 = X[0] * r0 + X[1] * r1 + X[2];
+            const double n2 = X[3] * r0 + X[4] * r1 + X[5];
+            const double id = 1.0 / (X[6] * r0 + X[7] * r1 + X[8]);
+            const double u = n1 * id, v = n2 * id;
+            const double ex = u - p0, ey = v - p1;
+            const double ju[9] = {r0 * id, r1 * id, id, 0.0, 0.0, 0.0, -u * r0 * id, -u * r1 * id, -u * id};
+            const double jv[9] = {0.0, 0.0, 0.0, r0 * id, r1 * id, id, -v * r0 * id, -v * r1 * id, -v * id};
+            for (int a = 0; a < 9; a++) {
+                K(a, 12) -= ju[a] * ex + jv[a] * ey;
+                for (int b = a; b < 9; b++) K(a, b) += ju[a] * ju[b] + jv[a] * jv[b];
+            }
+        }
+        for (int a = 1; a < 9; a++)
+            for (int b = 0; b < a; b++) K(a, b) = K(b, a);
+        // constraints and their derivatives
+        double Ft[9], FS[9], B[9], sg[9];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) Ft[3 * i + j] = X[3 * i] * M[j] + X[3 * i + 1] * M[3 + j] + X[3 * i + 2] * M[6 + j];
+        sample_frame(Ft, S, FS, B);
+        for (int i = 0; i < 9; i++) B[i] = 0.5 * (B[i] - I3[i]);
+        hooke_sample(B, g, tf, sg);
+        const double ic = 1.0 / tf.c11;
+        K(9, 12) = -sg[8] * ic;
+        K(10, 12) = -sg[5] * ic;
+        K(11, 12) = -sg[2] * ic;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                // dF_S for a unit change of X_ab: column a of S times row b of M S^T
+                double de[9], ds[9];
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) {
+                        const double d1 = S[3 * i + a] * (MSt[3 * b] * FS[3 * j] + MSt[3 * b + 1] * FS[3 * j + 1] + MSt[3 * b + 2] * FS[3 * j + 2]);
+                        const double d2 = S[3 * j + a] * (FS[3 * i] * MSt[3 * b] + FS[3 * i + 1] * MSt[3 * b + 1] + FS[3 * i + 2] * MSt[3 * b + 2]);
+                        de[3 * i + j] = 0.5 * (d1 + d2);
+                    }
+                hooke_sample(de, g, tf, ds);
+                const int c = 3 * a + b;
+                K(9, c) = K(c, 9) = ds[8] * ic;
+                K(10, c) = K(c, 10) = ds[5] * ic;
+                K(11, c) = K(c, 11) = ds[2] * ic;
+            }
+        // Gaussian elimination with partial pivoting on the augmented system
+        bool ok = true;
+        for (int k = 0; k < 12 && ok; k++) {
+            int piv = k;
+            for (int i = k + 1; i < 12; i++)
+                if (fabs(K(i, k)) > fabs(K(piv, k))) piv = i;
+            if (K(piv, k) == 0.0) {
+                ok = false;
+                break;
+            }
+            if (piv != k)
+                for (int j = k; j < 13; j++) {
+                    const double t = K(k, j);
+                    K(k, j) = K(piv, j);
+                    K(piv, j) = t;
+                }
+            const double ip = 1.0 / K(k, k);
+            for (int i = k + 1; i < 12; i++) {
+                const double m = K(i, k) * ip;
+                if (m != 0.0)
+                    for (int j = k; j < 13; j++) K(i, j) -= m * K(k, j);
+            }
+        }
+        if (!ok) {
+            st |= EBSD_SOLVE_ILLCOND;
+            break;
+        }
+        for (int i = 11; i >= 0; i--) {
+            double sacc = K(i, 12);
+            for (int j = i + 1; j < 12; j++) sacc -= K(i, j) * K(j, 12);
+            K(i, 12) = sacc / K(i, i);
+        }
+        double nrm = 0.0;
+        for (int a = 0; a < 9; a++) {
+            const double d = K(a, 12);
+            X[a] += d;
+            nrm += d * d;
+        }
+        if (!isfinite(nrm)) {
+            st |= EBSD_SOLVE_ILLCOND;
+            break;
+        }
+        done = sqrt(nrm) < 1e-14;
+    }
+    if (!done) st |= EBSD_SOLVE_ILLCOND;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) F[3 * i + j] = X[3 * i] * M[j] + X[3 * i + 1] * M[3 + j] + X[3 * i + 2] * M[6 + j];
+    double FS[9], B[9];
+    sample_frame(F, S, FS, B);
+    for (int i = 0; i < 9; i++) eps[i] = 0.5 * (B[i] - I3[i]);
+    hooke_sample(eps, g, tf, sig);
+    return st;
+}
+
+__global__ void __launch_bounds__(kSolveThreads)
+    k_traction_free(const float* __restrict__ q, int n, int n_roi, const double* __restrict__ cx,
+                    const double* __restrict__ cy, double xs, double ys, double zs,
+                    const double* __restrict__ Mall, const double* __restrict__ gall, TractionFrame tf,
+                    double* __restrict__ Fout, double* __restrict__ eout, double* __restrict__ sout,
+                    uint32_t* __restrict__ status)
+{
+    __shared__ double pool[kSolvePool * kSolveThreads];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    RoiSet rs;
+    rs.q = q + 2 * (int64_t)b * n_roi;
+    rs.cx = cx;
+    rs.cy = cy;
+    rs.cs = 1;
+    rs.n = n_roi;
+    rs.xs = xs;
+    rs.ys = ys;
+    rs.iz = 1.0 / zs;
+    double M[9], g[9], F[9], e[9], sg[9];
+    for (int i = 0; i < 9; i++) {
+        M[i] = Mall ? Mall[9 * (int64_t)b + i] : (i % 4 == 0 ? 1.0 : 0.0);
+        g[i] = gall[9 * (int64_t)b + i];
+    }
+    const uint32_t st = solve_F_traction_free(rs, M, g, tf, F, e, sg, pool + threadIdx.x);
+    for (int i = 0; i < 9; i++) {
+        Fout[9 * (int64_t)b + i] = F[i];
+        if (eout) eout[9 * (int64_t)b + i] = e[i];
+        if (sout) sout[9 * (int64_t)b + i] = sg[i];
+    }
+    if (status) status[b] = st;
+}
+
 __global__ void k_gather_rfin(const Bucket* __restrict__ bk)
 {
     const double* __restrict__ rin = bk->rfin_in;
@@ -813,6 +1023,16 @@ hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx
     hipLaunchKernelGGL(k_stage_solve, dim3((n + kSolveThreads - 1) / kSolveThreads), dim3(kSolveThreads), 0, s, q,
                        n, n_roi, cx, cy, xs,
                        ys, zs, F, R, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_traction_free(const float* q, int n, int n_roi, const double* cx, const double* cy,
+                                double xs, double ys, double zs, const double* M, const double* g,
+                                const TractionFrame& tf, double* F, double* eps, double* sig,
+                                uint32_t* status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_traction_free, dim3((n + kSolveThreads - 1) / kSolveThreads), dim3(kSolveThreads), 0, s,
+                       q, n, n_roi, cx, cy, xs, ys, zs, M, g, tf, F, eps, sig, status);
     return hipGetLastError();
 }
 

@@ -96,7 +96,7 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_get_params", "ebsd_roi_layout", "ebsd_register_batch",
             "ebsd_register_batch_init", "ebsd_second_pass_batch", "ebsd_stage_normalize",
             "ebsd_stage_restrict", "ebsd_stage_demons_iter", "ebsd_stage_prolong",
-            "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_stage_remap", "ebsd_set_timing", "ebsd_get_timing",
+            "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_stage_remap", "ebsd_traction_free", "ebsd_set_timing", "ebsd_get_timing",
             "ebsd_autotune", "ebsd_get_strip_height", "ebsd_set_strip_height", "ebsd_set_graphs",
             "ebsd_cnn_num_params", "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_set_params",
             "ebsd_cnn_get_params", "ebsd_cnn_get_grads", "ebsd_cnn_load", "ebsd_cnn_save",
@@ -142,6 +142,9 @@ def lib():
                                        vp, vp, vp, vp]
         L.ebsd_stage_remap.argtypes = [vp, i32, i32, i32, vp, C.c_double, C.c_double, C.c_double, i32,
                                        vp, vp, vp]
+        L.ebsd_traction_free.argtypes = [vp, i32, i32, vp, vp, C.c_double, C.c_double, C.c_double, vp, vp,
+                                         C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double, vp, vp, vp,
+                                         vp, vp]
         L.ebsd_cnn_num_params.restype = i64
         L.ebsd_cnn_create.argtypes = [C.c_int, i32, C.POINTER(vp)]
         L.ebsd_cnn_destroy.argtypes = [vp]
@@ -578,6 +581,44 @@ def stage_solve(q, cx, cy, pcs):
                                   float(pcs[2]), _ptr(F), _ptr(R), _ptr(st), _stream()),
            "ebsd_stage_solve")
     return F, R, st
+
+
+# the paper's nickel constants (C11, C12, C44), Pa
+NICKEL_STIFFNESS = (2.76e11, 1.59e11, 1.32e11)
+
+
+def r_tilt(theta):
+    """Eq. (13)'s detector-to-sample rotation for a tilt theta (rad), as printed."""
+    import math
+    c, s = math.cos(theta), math.sin(theta)
+    return ((c, s, 0.0), (-s, c, 0.0), (0.0, 0.0, 1.0))
+
+
+def traction_free(q, cx, cy, pcs, g, S, stiffness=NICKEL_STIFFNESS, M=None):
+    """Eq. (3) under the traction-free constraint with strain and stress
+    (ebsd_traction_free).  q [n, n_roi, 2] float32 device shifts; cx, cy
+    [n_roi] ROI centres; pcs = (x*, y*, Z*) px; g [n, 3, 3] passive
+    sample-to-crystal orientations; S 3 x 3 detector-to-sample rotation
+    (host); stiffness = (C11, C12, C44); M [n, 3, 3] what the fit composes with
+    (R_finite for second-pass shifts) or None.  Returns a dict of device
+    tensors F, eps_S, sigma_S [n, 3, 3] and status [n]."""
+    q = _dev_f32(q)
+    n, nr, _ = q.shape
+    dev = q.device
+    cx = torch.as_tensor(cx, dtype=torch.float64).to(dev).contiguous()
+    cy = torch.as_tensor(cy, dtype=torch.float64).to(dev).contiguous()
+    g = torch.as_tensor(g, dtype=torch.float64).to(dev).reshape(n, 3, 3).contiguous()
+    Mt = None if M is None else torch.as_tensor(M, dtype=torch.float64).to(dev).reshape(n, 3, 3).contiguous()
+    Sh = (C.c_double * 9)(*[float(v) for row in S for v in row])
+    out = {k: torch.empty(n, 3, 3, dtype=torch.float64, device=dev) for k in ("F", "eps_S", "sigma_S")}
+    out["status"] = torch.empty(n, dtype=torch.int32, device=dev)
+    _check(lib().ebsd_traction_free(_ptr(q), n, nr, _ptr(cx), _ptr(cy), float(pcs[0]), float(pcs[1]),
+                                    float(pcs[2]), _ptr(Mt) if Mt is not None else None, _ptr(g), Sh,
+                                    float(stiffness[0]), float(stiffness[1]), float(stiffness[2]),
+                                    _ptr(out["F"]), _ptr(out["eps_S"]),
+                                    _ptr(out["sigma_S"]), _ptr(out["status"]), _stream()),
+           "ebsd_traction_free")
+    return out
 
 
 def _dev_bf16(x):

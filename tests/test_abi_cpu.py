@@ -117,6 +117,20 @@ def test_null_arguments_rejected(E):
     assert L.ebsd_stage_remap(fake, 1, 2, 64, fake, 31.5, 31.5, 44.8, 1, None, fake, None) == -2
     assert L.ebsd_stage_remap(None, 0, 64, 64, None, 31.5, 31.5, 44.8, 3, None, None, None) == 0
     assert L.ebsd_destroy(None) == 0
+    # traction-free solve: validation before any launch
+    eye = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    bad = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, -1)  # a reflection
+    ni = (2.76e11, 1.59e11, 1.32e11)
+    tf = L.ebsd_traction_free
+    assert tf(None, 1, 20, fake, fake, 127.5, 127.5, 179.2, None, fake, eye, *ni, fake, None, None, None, None) == -1
+    assert tf(fake, 1, 20, fake, fake, 127.5, 127.5, 179.2, None, fake, None, *ni, fake, None, None, None, None) == -1
+    assert tf(fake, 1, 20, fake, fake, 127.5, 127.5, 179.2, None, fake, bad, *ni, fake, None, None, None, None) == -1
+    assert tf(fake, 1, 4, fake, fake, 127.5, 127.5, 179.2, None, fake, eye, *ni, fake, None, None, None, None) == -1
+    assert tf(fake, 1, 20, fake, fake, 127.5, 127.5, 0.0, None, fake, eye, *ni, fake, None, None, None, None) == -1
+    for c in [(1.0, 2.0, 1.0), (1.0, 0.5, 0.0), (1.0, -0.6, 1.0), (float("nan"), 0.5, 1.0)]:
+        assert tf(fake, 1, 20, fake, fake, 127.5, 127.5, 179.2, None, fake, eye, *c, fake, None, None, None,
+                  None) == -1
+    assert tf(None, 0, 20, None, None, 127.5, 127.5, 179.2, None, None, eye, *ni, None, None, None, None, None) == 0
 
 
 def test_network_entry_points_validate_without_a_gpu(E):
