@@ -106,7 +106,7 @@ def lib():
         L.orc_smooth.argtypes = [d, C.c_int, C.c_int, C.c_double, d]
         L.orc_demons_iter.restype = C.c_double
         L.orc_demons_iter.argtypes = [d, d, d, d, C.c_int, C.c_int, d, C.c_double, d]
-        L.orc_prolong.argtypes = [d, C.c_int, C.c_int, d]
+        L.orc_prolong.argtypes = [d, C.c_int, C.c_int, C.c_int, C.c_int, d]
         L.orc_demons.restype = C.c_uint32
         L.orc_demons.argtypes = [d, d, C.c_int, C.c_int, C.POINTER(Params), d, d,
                                  C.POINTER(C.c_int32)]
@@ -167,10 +167,11 @@ def normalize(p):
 
 
 def restrict(img):
-    """Factor-2 pyramid restriction with the [1,3,3,1]/8 filter (section 1)."""
+    """Factor-2 pyramid restriction with the [1,3,3,1]/8 filter (section 1);
+    ceil(H/2) x ceil(W/2) outputs."""
     a = _f64(img)
     H, W = a.shape
-    out = np.empty((H // 2, W // 2), np.float64)
+    out = np.empty(((H + 1) // 2, (W + 1) // 2), np.float64)
     lib().orc_restrict(_d(a), H, W, _d(out))
     return out
 
@@ -225,11 +226,13 @@ def demons_iter(R, T, u, sigma):
     return out, rms
 
 
-def prolong(u):
+def prolong(u, shape=None):
+    """Field [2, h, w] to the finer level, shape (H, W) (default (2h, 2w))."""
     u = _f64(u)
     _, h, w = u.shape
-    out = np.empty((2, 2 * h, 2 * w), np.float64)
-    lib().orc_prolong(_d(u), h, w, _d(out))
+    H, W = shape if shape is not None else (2 * h, 2 * w)
+    out = np.empty((2, H, W), np.float64)
+    lib().orc_prolong(_d(u), h, w, H, W, _d(out))
     return out
 
 

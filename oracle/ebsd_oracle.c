@@ -114,17 +114,19 @@ uint32_t orc_normalize(const float* in, int64_t n, double* out)
 /* Pyramid restriction (multi-resolution demons, section 1; the paper gives
  * neither factor nor filter).  Factor 2, separable [1,3,3,1]/8 filter with
  * clamped borders, so that coarse pixel i is centred on fine 2i + 0.5:
- *   out[i] = (in[c(2i-1)] + 3 in[2i] + 3 in[2i+1] + in[c(2i+2)]) / 8.     */
+ *   out[i] = (in[c(2i-1)] + 3 in[c(2i)] + 3 in[c(2i+1)] + in[c(2i+2)]) / 8,
+ * c clamping to [0, N-1].  N fine pixels give ceil(N/2) coarse ones (an odd
+ * N: the last coarse pixel sees the last fine pixel through the clamp).    */
 void orc_restrict(const double* in, int H, int W, double* out)
 {
-    int h = H / 2, w = W / 2;
+    int h = (H + 1) / 2, w = (W + 1) / 2;
     double* tmp = (double*)malloc(sizeof(double) * (size_t)H * (size_t)w);
     for (int y = 0; y < H; y++) {
         const double* row = in + (size_t)y * W;
         for (int i = 0; i < w; i++) {
             double a = row[clampi(2 * i - 1, 0, W - 1)];
-            double b = row[2 * i];
-            double c = row[2 * i + 1];
+            double b = row[clampi(2 * i, 0, W - 1)];
+            double c = row[clampi(2 * i + 1, 0, W - 1)];
             double d = row[clampi(2 * i + 2, 0, W - 1)];
             tmp[(size_t)y * w + i] = (a + 3.0 * b + 3.0 * c + d) / 8.0;
         }
@@ -132,8 +134,8 @@ void orc_restrict(const double* in, int H, int W, double* out)
     for (int j = 0; j < h; j++) {
         for (int x = 0; x < w; x++) {
             double a = tmp[(size_t)clampi(2 * j - 1, 0, H - 1) * w + x];
-            double b = tmp[(size_t)(2 * j) * w + x];
-            double c = tmp[(size_t)(2 * j + 1) * w + x];
+            double b = tmp[(size_t)clampi(2 * j, 0, H - 1) * w + x];
+            double c = tmp[(size_t)clampi(2 * j + 1, 0, H - 1) * w + x];
             double d = tmp[(size_t)clampi(2 * j + 2, 0, H - 1) * w + x];
             out[(size_t)j * w + x] = (a + 3.0 * b + 3.0 * c + d) / 8.0;
         }
@@ -282,12 +284,12 @@ double orc_demons_iter(const double* R, const double* T, const double* gx,
     return sqrt(ss / (double)HW);
 }
 
-/* Prolongation of the field to the next finer level: bilinear with the
- * half-pixel-centre map (fine i -> coarse (i - 0.5)/2), values doubled
- * because the field is measured in the pixels of its level.               */
-void orc_prolong(const double* u, int h, int w, double* out)
+/* Prolongation of the field to the next finer level (H x W, 2h x 2w or one
+ * less where the finer level was odd): bilinear with the half-pixel-centre
+ * map (fine i -> coarse (i - 0.5)/2), values doubled because the field is
+ * measured in the pixels of its level.                                    */
+void orc_prolong(const double* u, int h, int w, int H, int W, double* out)
 {
-    int H = 2 * h, W = 2 * w;
     size_t hw = (size_t)h * w, HW = (size_t)H * W;
     for (int c = 0; c < 2; c++)
         for (int y = 0; y < H; y++)
@@ -318,8 +320,8 @@ uint32_t orc_demons(const double* Rn, const double* Tn, int H, int W, const orc_
     Hs[0] = H;
     Ws[0] = W;
     for (int l = 1; l < L; l++) {
-        Hs[l] = Hs[l - 1] / 2;
-        Ws[l] = Ws[l - 1] / 2;
+        Hs[l] = (Hs[l - 1] + 1) / 2;
+        Ws[l] = (Ws[l - 1] + 1) / 2;
         double* r = (double*)malloc(sizeof(double) * (size_t)Hs[l] * Ws[l]);
         double* t = (double*)malloc(sizeof(double) * (size_t)Hs[l] * Ws[l]);
         orc_restrict(Rl[l - 1], Hs[l - 1], Ws[l - 1], r);
@@ -361,7 +363,7 @@ uint32_t orc_demons(const double* Rn, const double* Tn, int H, int W, const orc_
         if (!conv) all_conv = 0;
         if (!conv && p->tol > 0.0) any_cap = 1;
         if (l > 0) {
-            orc_prolong(ua, h, w, ub);
+            orc_prolong(ua, h, w, Hs[l - 1], Ws[l - 1], ub);
             double* t = ua;
             ua = ub;
             ub = t;

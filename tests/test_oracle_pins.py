@@ -44,9 +44,12 @@ def test_normalize_degenerate_and_nonfinite(orc):
 
 # -- pyramid restriction --------------------------------------------------------------------
 
-def test_restrict_matches_scipy_correlate(orc):
-    x = rng(2).normal(size=(16, 24))
+@pytest.mark.parametrize("shape", [(16, 24), (7, 9), (13, 6), (1, 5)])
+def test_restrict_matches_scipy_correlate(orc, shape):
+    # odd sizes give ceil(N/2) outputs; the last one reads the clamped border
+    x = rng(2).normal(size=shape)
     out = orc.restrict(x)
+    assert out.shape == ((shape[0] + 1) // 2, (shape[1] + 1) // 2)
     w = np.array([1.0, 3.0, 3.0, 1.0]) / 8.0
     # correlate with taps at offsets -1..+2 (origin -1 for an even kernel), clamp borders
     t = ndi.correlate1d(x, w, axis=1, mode="nearest", origin=-1)
@@ -172,6 +175,27 @@ def test_prolong_matches_torch_interpolate(orc):
     ref = 2.0 * torch.nn.functional.interpolate(torch.from_numpy(u)[None], scale_factor=2,
                                                 mode="bilinear", align_corners=False)[0].numpy()
     np.testing.assert_allclose(out, ref, atol=1e-13)
+
+
+def test_prolong_to_odd_sizes_is_the_crop(orc):
+    # a finer level one pixel short (odd) uses the same half-pixel map: the crop of the 2h x 2w result
+    u = rng(18).normal(size=(2, 7, 9))
+    full = orc.prolong(u)
+    for shape in [(13, 17), (14, 17), (13, 18)]:
+        np.testing.assert_array_equal(orc.prolong(u, shape), full[:, :shape[0], :shape[1]])
+
+
+def test_demons_odd_level_sizes(orc):
+    # 4 levels of a 50 x 38 pair (50, 25, 13, 7 by 38, 19, 10, 5): the level loop runs on odd sizes,
+    # an identical pair stays exactly at zero and a whole-pixel shift is followed in the interior
+    img = ndi.gaussian_filter(rng(19).normal(size=(50, 38)), 2.0)
+    img = (img - img.mean()) / img.std()
+    p = orc.make_params(levels=4, iters=30, sigma=1.0)
+    f, its, _ = orc.demons(img, img, p)
+    assert not f.any() and list(its) == [30] * 4
+    shifted = np.roll(img, 1, axis=1)  # T(x) = R(x - 1): u -> +1 along x
+    f, _, _ = orc.demons(img, shifted, orc.make_params(levels=4, iters=60, sigma=1.0))
+    assert abs(np.median(f[0, 10:-10, 10:-10]) - 1.0) < 0.1 and abs(np.median(f[1, 10:-10, 10:-10])) < 0.1
 
 
 # -- whole demons loop ----------------------------------------------------------------------
