@@ -54,7 +54,7 @@ extern "C" {
 enum {
     EBSD_OK = 0,
     EBSD_EINVAL = -1,   /* bad argument (NULL pointer, n < 0, bad parameter value) */
-    EBSD_ESHAPE = -2,   /* pattern size not supported (too small, not divisible by 2^(levels-1)) */
+    EBSD_ESHAPE = -2,   /* pattern size not supported (coarsest level under 4 x 4, over 16384) */
     EBSD_EROI = -3,     /* a ROI falls outside the pattern, or ROI size is not 32/64/128 */
     EBSD_ENOMEM = -4,   /* device or pinned allocation failed */
     EBSD_EDEVICE = -5,  /* a HIP runtime call failed */
@@ -77,7 +77,9 @@ enum {
 
 typedef struct ebsd_params {
     uint32_t struct_size;                 /* sizeof(ebsd_params) */
-    int32_t levels;                       /* pyramid levels, 1..8 (multi-resolution demons) */
+    int32_t levels;                       /* pyramid levels, 1..8 (multi-resolution demons); level l is the
+                                             pattern halved l times, sizes rounding up (an odd size keeps
+                                             its last pixel), and must keep 4 x 4 pixels */
     int32_t max_iters[EBSD_MAX_LEVELS];   /* demons iterations per level, [0] = finest */
     float sigma_px;                       /* Gaussian smoothing of the accumulated field, 0 <= sigma <= 1.3 */
     float tol_px;                         /* stop a level when 2^l RMS|u_new - u| < tol (full-res px); 0 = fixed count */
@@ -185,7 +187,8 @@ int ebsd_register_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
                         const ebsd_outputs* out, void* stream);
 
 /* Same as ebsd_register_batch, but demons starts on the coarsest level from
- * the caller's field u_init (device, [n][2][H/2^(L-1)][W/2^(L-1)] fp32, in
+ * the caller's field u_init (device, [n][2][h][w] fp32, h x w the coarsest
+ * level's size: H and W halved L-1 times rounding up, in
  * full-resolution px) instead of zero: the warm start.  All pairs must have
  * the same size.  u_init == NULL behaves as ebsd_register_batch. */
 int ebsd_register_batch_init(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
@@ -353,8 +356,9 @@ int ebsd_set_model(ebsd_handle* h, const ebsd_cnn* c);
 int ebsd_stage_normalize(const float* in, int32_t n, int64_t elems, float* out, uint32_t* flags,
                          void* stream);
 
-/* Factor-2 restriction of n images [n][H][W] -> [n][H/2][W/2] with the
- * separable [1,3,3,1]/8 filter, clamped borders (H, W even). */
+/* Factor-2 restriction of n images [n][H][W] -> [n][ceil(H/2)][ceil(W/2)]
+ * with the separable [1,3,3,1]/8 filter, clamped borders (H, W >= 2; an odd
+ * size's last output reads the border through the clamp). */
 int ebsd_stage_restrict(const float* in, int32_t n, int32_t H, int32_t W, float* out, void* stream);
 
 /* One demons iteration (Eq. (1) force with the reference gradient, then

@@ -607,7 +607,7 @@ __global__ void __launch_bounds__(64 * NW)
     const int strip = lb - b * nstrips;
     const PairState st = bk->state[b];
     if (st.stop >= 0) return;  // uniform
-    const int h = bk->H >> level, w = bk->W >> level;
+    const int h = bk->lh[level], w = bk->lw[level];
     const int64_t npart = (int64_t)bk->nb * bk->max_tiles;
     if (tol > 0.0f && k > 0) {
         const float* prev = bk->partial + ((k - 1) & 1) * npart + (int64_t)b * bk->max_tiles;
@@ -654,7 +654,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
     const int strip = lb - b * nstrips;
     const PairState st = bk->state[b];
     if (st.stop >= 0) return;  // uniform
-    const int h = bk->H >> level, w = bk->W >> level;
+    const int h = bk->lh[level], w = bk->lw[level];
     const int64_t npart = (int64_t)bk->nb * bk->max_tiles;
     const int64_t pofs = (int64_t)b * bk->max_tiles;
     const int k = 2 * L;

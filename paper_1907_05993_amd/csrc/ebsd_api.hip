@@ -196,10 +196,14 @@ int roi_layout(const ebsd_params& p, int H, int W, double* cx, double* cy, int32
 
 int check_shape(const ebsd_params& p, int H, int W)
 {
-    const int f = 1 << (p.levels - 1);
     if (H <= 0 || W <= 0 || H > 16384 || W > 16384) return EBSD_ESHAPE;
-    if (H % f != 0 || W % f != 0) return EBSD_ESHAPE;
-    if (H / f < 4 || W / f < 4) return EBSD_ESHAPE;
+    // the coarsest level (sizes halved, rounding up) must keep 4 x 4 pixels
+    int hc = H, wc = W;
+    for (int l = 1; l < p.levels; l++) {
+        hc = (hc + 1) / 2;
+        wc = (wc + 1) / 2;
+    }
+    if (hc < 4 || wc < 4) return EBSD_ESHAPE;
     if (H < p.roi_size || W < p.roi_size) return EBSD_EROI;
     return roi_layout(p, H, W, nullptr, nullptr, nullptr, nullptr);
 }
@@ -361,11 +365,14 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     int64_t pe = 0;
     int max_units = 1;
     for (int l = 0; l < L; l++) {
+        // level sizes halve rounding up (odd sizes keep their last pixel)
+        b.lh[l] = l == 0 ? H : (b.lh[l - 1] + 1) / 2;
+        b.lw[l] = l == 0 ? W : (b.lw[l - 1] + 1) / 2;
         b.lvl_off[l] = (int32_t)pe;
-        pe += (int64_t)(H >> l) * (W >> l);
-        max_units = std::max(max_units, demons_units(H >> l, W >> l, kMinStripTY));
+        pe += (int64_t)b.lh[l] * b.lw[l];
+        pe = (pe + 63) / 64 * 64;  // every level 256 B aligned
+        max_units = std::max(max_units, demons_units(b.lh[l], b.lw[l], kMinStripTY));
     }
-    pe = (pe + 63) / 64 * 64;  // 256 B aligned pyramids (vector loads)
     b.pyr_elems = pe;
     b.max_tiles = max_units;
     b.n_roi = nr;
@@ -526,7 +533,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         EBSD_TRY(hipEventCreate(&e0));
         EBSD_TRY(hipEventCreate(&e1));
         for (int l = L - 1; l >= 0; l--) {
-            const int lh = H >> l, lw = W >> l;
+            const int lh = b.lh[l], lw = b.lw[l];
             if (!rows_cpl(lw)) continue;
             float best = 1e30f;
             int best_ty = kDefaultStripTY;
@@ -651,8 +658,8 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     } else if (mode == Mode::Full) {
         EBSD_TRY(launch_demons_init(d_bk, b, s));
         for (int l = L - 1; l >= 0; l--) {
-            const int ty = strip_ty_for(h, H >> l, W >> l, nb);
-            const int fty = fused_ty_for(h, H >> l, W >> l);
+            const int ty = strip_ty_for(h, b.lh[l], b.lw[l], nb);
+            const int fty = fused_ty_for(h, b.lh[l], b.lw[l]);
             if (tm) EBSD_TRY(hipEventRecord(h->ev[2 + 2 * l], s));
             const int e = run_level(l, ty, fty);
             if (e) return e;
@@ -989,7 +996,7 @@ int ebsd_stage_normalize(const float* in, int32_t n, int64_t elems, float* out, 
 int ebsd_stage_restrict(const float* in, int32_t n, int32_t H, int32_t W, float* out, void* stream)
 {
     if (n < 0 || (n > 0 && (!in || !out))) return EBSD_EINVAL;
-    if (H < 2 || W < 2 || (H & 1) || (W & 1) || n > 65535) return EBSD_ESHAPE;
+    if (H < 2 || W < 2 || H > 16384 || W > 16384 || n > 65535) return EBSD_ESHAPE;
     if (n == 0) return EBSD_OK;
     return map_err(launch_stage_restrict(in, n, H, W, out, (hipStream_t)stream));
 }

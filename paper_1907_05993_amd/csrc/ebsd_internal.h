@@ -59,7 +59,9 @@ struct Bucket {
     int32_t nb;                 // pairs in the bucket
     int32_t nref;               // distinct reference patterns
     int32_t H, W, L;            // finest size and number of levels
-    int32_t lvl_off[kMaxLevels];// float offset of level l inside one pyramid
+    int32_t lvl_off[kMaxLevels];// float offset of level l inside one pyramid (multiple of 64)
+    int32_t lh[kMaxLevels];     // level sizes: lh[0] = H, lh[l] = ceil(lh[l-1] / 2)
+    int32_t lw[kMaxLevels];     // lw[0] = W, lw[l] = ceil(lw[l-1] / 2)
     int64_t pyr_elems;          // floats per pyramid (all levels)
     const float* const* test_in;// [nb] caller test patterns
     const float* const* ref_in; // [nref] caller reference patterns

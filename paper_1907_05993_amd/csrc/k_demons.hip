@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(NT)
     const int tile = lb - b * ntiles;
     const PairState st = bk->state[b];
     if (st.stop >= 0) return;  // uniform over the block
-    const int h = bk->H >> level, w = bk->W >> level;
+    const int h = bk->lh[level], w = bk->lw[level];
     const int64_t npart = (int64_t)bk->nb * bk->max_tiles;
     if (tol > 0.0f && k > 0) {
         const float* prev = bk->partial + ((k - 1) & 1) * npart + (int64_t)b * bk->max_tiles;
@@ -203,7 +203,7 @@ __global__ void k_level_end(const Bucket* __restrict__ bk, int level, int cap, f
                     lane[l] = a + c;
                     lane[l | off] = c + a;
                 }
-        const int h = bk->H >> level, w = bk->W >> level;
+        const int h = bk->lh[level], w = bk->lw[level];
         const double delta = sqrt(lane[0] / ((double)h * (double)w)) * (double)(1 << level);
         if (delta < (double)tol) st.convmask |= 1u << level;
     }
@@ -246,7 +246,7 @@ template <int RAD>
 void launch_iter_rad(const Bucket* d_bk, const Bucket& hb, int level, int k, const Taps& tp,
                      float tol, hipStream_t s)
 {
-    const int h = hb.H >> level, w = hb.W >> level;
+    const int h = hb.lh[level], w = hb.lw[level];
     const int tiles_x = (w + TX - 1) / TX;
     const int ntiles = demons_tiles(h, w);
     const int G = hb.nb * ntiles;
@@ -283,7 +283,7 @@ hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, i
 hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int cap, float tol,
                             int ty, bool fused, hipStream_t s)
 {
-    const int ntiles = demons_units(hb.H >> level, hb.W >> level, ty);
+    const int ntiles = demons_units(hb.lh[level], hb.lw[level], ty);
     hipLaunchKernelGGL(k_level_end, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, level, cap, tol,
                        ntiles, fused ? 1 : 0);
     return hipGetLastError();

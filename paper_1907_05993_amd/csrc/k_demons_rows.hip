@@ -47,7 +47,7 @@ bool rows2_ty_supported(int ty) { return ty == 16 || ty == 32 || ty == 64 || ty 
 bool launch_demons_rows2(const Bucket* d_bk, const Bucket& hb, int level, int L, const Taps& tp, int radius,
                          float tol, int cap, int ty, hipStream_t s)
 {
-    const int h = hb.H >> level, w = hb.W >> level;
+    const int h = hb.lh[level], w = hb.lw[level];
     switch (rows_cpl(w)) {
     case 1: return demons_rows2_nw1(d_bk, hb.nb, h, level, L, tp, radius, tol, cap, ty, s);
     case 2: return demons_rows2_nw2(d_bk, hb.nb, h, level, L, tp, radius, tol, cap, ty, s);
@@ -62,7 +62,7 @@ int rows_units(int h, int ty) { return (h + ty - 1) / ty; }
 bool launch_demons_rows(const Bucket* d_bk, const Bucket& hb, int level, int k, const Taps& tp,
                         int radius, float tol, int ty, hipStream_t s)
 {
-    const int h = hb.H >> level, w = hb.W >> level;
+    const int h = hb.lh[level], w = hb.lw[level];
     switch (rows_cpl(w)) {
     case 1: return demons_rows_nw1(d_bk, hb.nb, h, level, k, tp, radius, tol, ty, s);
     case 2: return demons_rows_nw2(d_bk, hb.nb, h, level, k, tp, radius, tol, ty, s);

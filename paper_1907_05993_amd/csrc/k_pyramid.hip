@@ -110,7 +110,9 @@ __global__ void k_normalize_l0(const Bucket* __restrict__ bk)
 }
 
 // Factor-2 restriction, separable [1,3,3,1]/8 with clamped borders:
-// coarse pixel i is centred on fine 2i + 0.5.  Horizontal pass first.
+// coarse pixel i is centred on fine 2i + 0.5; an odd size N gives ceil(N/2)
+// coarse pixels, the last reading the border through the clamp.  Horizontal
+// pass first.
 __device__ inline float restrict_at(const float* __restrict__ in, int H, int W, int j, int i)
 {
     float h[4];
@@ -118,8 +120,8 @@ __device__ inline float restrict_at(const float* __restrict__ in, int H, int W, 
     for (int k = 0; k < 4; k++) {
         const float* row = in + (int64_t)clampi(2 * j - 1 + k, 0, H - 1) * W;
         float a = row[clampi(2 * i - 1, 0, W - 1)];
-        float b = row[2 * i];
-        float c = row[2 * i + 1];
+        float b = row[clampi(2 * i, 0, W - 1)];
+        float c = row[clampi(2 * i + 1, 0, W - 1)];
         float d = row[clampi(2 * i + 2, 0, W - 1)];
         h[k] = (a + 3.0f * b + 3.0f * c + d) / 8.0f;
     }
@@ -131,8 +133,8 @@ __global__ void k_restrict_level(const Bucket* __restrict__ bk, int level)
     const int pat = blockIdx.y;
     float* base = pat < bk->nb ? bk->test_pyr + (int64_t)pat * bk->pyr_elems
                                : bk->ref_pyr + (int64_t)(pat - bk->nb) * bk->pyr_elems;
-    const int Hi = bk->H >> (level - 1), Wi = bk->W >> (level - 1);
-    const int h = Hi / 2, w = Wi / 2;
+    const int Hi = bk->lh[level - 1], Wi = bk->lw[level - 1];
+    const int h = bk->lh[level], w = bk->lw[level];
     const float* in = base + bk->lvl_off[level - 1];
     float* out = base + bk->lvl_off[level];
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)h * w;
@@ -146,7 +148,7 @@ __global__ void k_restrict_plain(const float* __restrict__ in, int H, int W,
                                  float* __restrict__ out)
 {
     const int pat = blockIdx.y;
-    const int h = H / 2, w = W / 2;
+    const int h = (H + 1) / 2, w = (W + 1) / 2;
     const float* src = in + (int64_t)pat * H * W;
     float* dst = out + (int64_t)pat * h * w;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)h * w;
@@ -156,11 +158,11 @@ __global__ void k_restrict_plain(const float* __restrict__ in, int H, int W,
     }
 }
 
-// Prolongation u_{l-1}(x) = 2 bilinear(u_l, (x - 0.5)/2): half-pixel centres.
-__device__ inline void prolong_one(const float* __restrict__ src, int h, int w,
+// Prolongation u_{l-1}(x) = 2 bilinear(u_l, (x - 0.5)/2): half-pixel centres;
+// the finer level is H2 x W2 (2h x 2w, or one less where it was odd).
+__device__ inline void prolong_one(const float* __restrict__ src, int h, int w, int H2, int W2,
                                    float* __restrict__ dst, int64_t t)
 {
-    const int H2 = 2 * h, W2 = 2 * w;
     const int64_t hw2 = (int64_t)H2 * W2;
     int c = (int)(t / hw2);
     int64_t r = t - (int64_t)c * hw2;
@@ -172,15 +174,16 @@ __device__ inline void prolong_one(const float* __restrict__ src, int h, int w,
 __global__ void k_prolong_level(const Bucket* __restrict__ bk, int level)
 {
     const int b = blockIdx.y;
-    const int h = bk->H >> level, w = bk->W >> level;
+    const int h = bk->lh[level], w = bk->lw[level];
+    const int H2 = bk->lh[level - 1], W2 = bk->lw[level - 1];
     const int cur = bk->state[b].cur;
     const int64_t slot = (int64_t)b * 2 * bk->H * bk->W;
     const float* src = bk->field[cur] + slot;
     float* dst = bk->field[cur ^ 1] + slot;
-    const int64_t n = (int64_t)2 * (2 * h) * (2 * w);
+    const int64_t n = (int64_t)2 * H2 * W2;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x)
-        prolong_one(src, h, w, dst, t);
+        prolong_one(src, h, w, H2, W2, dst, t);
 }
 
 __global__ void k_rearm(const Bucket* __restrict__ bk)
@@ -201,7 +204,7 @@ __global__ void k_prolong_plain(const float* __restrict__ u, int h, int w, float
     const int64_t n = (int64_t)2 * 4 * h * w;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x)
-        prolong_one(src, h, w, dst, t);
+        prolong_one(src, h, w, 2 * h, 2 * w, dst, t);
 }
 
 // Reset demons state; coarsest-level field = u_init / 2^(L-1) or zero.
@@ -210,7 +213,7 @@ __global__ void k_demons_init(const Bucket* __restrict__ bk)
     const float* __restrict__ u_init = bk->u_init;
     const int b = blockIdx.y;
     const int L = bk->L;
-    const int h = bk->H >> (L - 1), w = bk->W >> (L - 1);
+    const int h = bk->lh[L - 1], w = bk->lw[L - 1];
     const int64_t n = (int64_t)2 * h * w;
     float* dst = bk->field[0] + (int64_t)b * 2 * bk->H * bk->W;
     const float scale = 1.0f / (float)(1 << (L - 1));
@@ -308,7 +311,7 @@ hipError_t launch_pyramids(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
     int64_t n0 = (int64_t)hb.H * hb.W;
     hipLaunchKernelGGL(k_normalize_l0, dim3(grid_for(n0, 64), npat), dim3(256), 0, s, d_bk);
     for (int l = 1; l < hb.L; l++) {
-        int64_t n = (int64_t)(hb.H >> l) * (hb.W >> l);
+        int64_t n = (int64_t)hb.lh[l] * hb.lw[l];
         hipLaunchKernelGGL(k_restrict_level, dim3(grid_for(n, 64), npat), dim3(256), 0, s, d_bk, l);
     }
     return hipGetLastError();
@@ -316,14 +319,14 @@ hipError_t launch_pyramids(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 
 hipError_t launch_demons_init(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
-    int64_t n = (int64_t)2 * (hb.H >> (hb.L - 1)) * (hb.W >> (hb.L - 1));
+    int64_t n = (int64_t)2 * hb.lh[hb.L - 1] * hb.lw[hb.L - 1];
     hipLaunchKernelGGL(k_demons_init, dim3(grid_for(n, 64), hb.nb), dim3(256), 0, s, d_bk);
     return hipGetLastError();
 }
 
 hipError_t launch_prolong_level(const Bucket* d_bk, const Bucket& hb, int level, hipStream_t s)
 {
-    int64_t n = (int64_t)2 * (hb.H >> (level - 1)) * (hb.W >> (level - 1));
+    int64_t n = (int64_t)2 * hb.lh[level - 1] * hb.lw[level - 1];
     hipLaunchKernelGGL(k_prolong_level, dim3(grid_for(n, 128), hb.nb), dim3(256), 0, s, d_bk, level);
     hipLaunchKernelGGL(k_rearm, dim3((hb.nb + 255) / 256), dim3(256), 0, s, d_bk);
     return hipGetLastError();
@@ -359,7 +362,7 @@ hipError_t launch_stage_normalize(const float* in, int n, int64_t elems, float* 
 
 hipError_t launch_stage_restrict(const float* in, int n, int H, int W, float* out, hipStream_t s)
 {
-    int64_t m = (int64_t)(H / 2) * (W / 2);
+    int64_t m = (int64_t)((H + 1) / 2) * ((W + 1) / 2);
     hipLaunchKernelGGL(k_restrict_plain, dim3(grid_for(m, 64), n), dim3(256), 0, s, in, H, W, out);
     return hipGetLastError();
 }

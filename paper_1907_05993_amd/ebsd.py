@@ -234,6 +234,13 @@ class Params:
         return p
 
 
+def level_size(H, W, level):
+    """(h, w) of pyramid level `level`: H and W halved that many times, rounding up."""
+    for _ in range(level):
+        H, W = (H + 1) // 2, (W + 1) // 2
+    return H, W
+
+
 def roi_layout(params: Params, H, W):
     """ROI centres (cx, cy) and corners (x0, y0) as computed by the library."""
     import numpy as np
@@ -385,7 +392,8 @@ class Registrar:
         if shapes:
             H, W = shapes[0]
             for l in range(self.params.levels):
-                out[(H >> l, W >> l)] = lib().ebsd_get_strip_height(self._h, H >> l, W >> l)
+                h, w = level_size(H, W, l)
+                out[(h, w)] = lib().ebsd_get_strip_height(self._h, h, w)
         return out
 
     def set_graphs(self, on=True):
@@ -401,8 +409,8 @@ class Registrar:
 
     def fused_heights(self, H, W):
         """{(h, w): fused strip height or 0} for the levels of an H x W pattern."""
-        return {(H >> l, W >> l): lib().ebsd_get_fused_height(self._h, H >> l, W >> l)
-                for l in range(self.params.levels)}
+        sizes = [level_size(H, W, l) for l in range(self.params.levels)]
+        return {(h, w): lib().ebsd_get_fused_height(self._h, h, w) for h, w in sizes}
 
     def set_timing(self, on=True):
         _check(lib().ebsd_set_timing(self._h, int(bool(on))), "ebsd_set_timing")
@@ -521,7 +529,7 @@ def stage_normalize(p):
 def stage_restrict(img):
     img = _dev_f32(img)
     n, H, W = img.shape
-    out = torch.empty(n, H // 2, W // 2, dtype=torch.float32, device=img.device)
+    out = torch.empty(n, (H + 1) // 2, (W + 1) // 2, dtype=torch.float32, device=img.device)
     _check(lib().ebsd_stage_restrict(_ptr(img), n, H, W, _ptr(out), _stream()), "ebsd_stage_restrict")
     return out
 

@@ -341,6 +341,11 @@ WORKLOADS = {
     # intragranular rotation up to 10 deg, per-pair stop at 1e-4 px, ROIs of 128^2
     # (patterns from scan_specs / render_scan)
     "scan_400": dict(config_id=3, n=4096, H=400, W=400, strain=0.0, iters=150, roi=128, tol=1e-4),
+    # the paper's own pattern size and settings (section 3.1): 1244 x 1024 px (width x height),
+    # pattern centre (0.5, 0.5, 0.5), 7 levels x 25 iterations, no field smoothing; 10 deg;
+    # 100 ROIs on a ring plus one at the centre (128 px here, 256 in the paper)
+    "paper_1244": dict(config_id=7, n=256, H=1024, W=1244, exact_angle=10.0, strain=2e-3, iters=25,
+                       levels=7, sigma=0.0, roi=128, n_roi=101, pc=(0.5, 0.5, 0.5)),
 }
 
 
@@ -348,5 +353,5 @@ def workload_specs(name, n=None, start=0):
     w = WORKLOADS[name]
     n = w["n"] if n is None else n
     kw = dict(mis_deg=w.get("mis_deg", (0.0, 10.0)), strain=w["strain"],
-              exact_angle=w.get("exact_angle"))
+              exact_angle=w.get("exact_angle"), pc=w.get("pc", (0.5, 0.5, 0.7)))
     return [make_spec(w["config_id"], start + i, w["H"], w["W"], **kw) for i in range(n)]

@@ -108,7 +108,7 @@ def test_null_arguments_rejected(E):
     assert L.ebsd_register_batch(None, None, 0, None, None) == -1
     assert L.ebsd_stage_xcf(None, None, 1, 64, 1, None, None, None) == -1
     assert L.ebsd_stage_xcf(None, None, 0, 48, 1, None, None, None) == -3
-    assert L.ebsd_stage_restrict(None, 0, 5, 8, None, None) == -2
+    assert L.ebsd_stage_restrict(None, 0, 1, 8, None, None) == -2  # odd sizes are accepted, 1 row is not
     fake = C.c_void_p(16)  # never dereferenced: validation fails first
     assert L.ebsd_stage_remap(None, 1, 64, 64, None, 31.5, 31.5, 44.8, 3, None, None, None) == -1
     assert L.ebsd_stage_remap(fake, 1, 64, 64, fake, 31.5, 31.5, 44.8, 3, None, fake, None) == -1  # no coef
