@@ -61,6 +61,7 @@ class _Outputs(C.Structure):
         ("status", C.c_void_p),
         ("mae1", C.c_void_p),
         ("mae", C.c_void_p),
+        ("ssim", C.c_void_p),
     ]
 
 
@@ -122,6 +123,8 @@ def lib():
         L.orc_solve_F_traction_free.restype = C.c_uint32
         L.orc_solve_F_traction_free.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d, d,
                                                 d, C.c_double, C.c_double, C.c_double, d, d, d]
+        L.orc_ssim.restype = C.c_double
+        L.orc_ssim.argtypes = [d, d, C.c_int, C.c_int]
         L.orc_mae.restype = C.c_double
         L.orc_mae.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d]
         L.orc_polar.argtypes = [d, d]
@@ -331,6 +334,15 @@ def solve_F_traction_free(q, cx, cy, pcs, S, g, C, M=None):
     return F.reshape(3, 3), e.reshape(3, 3), sg.reshape(3, 3), int(st)
 
 
+def ssim(R, Tw):
+    """Mean structural similarity of R and Tw (11 x 11 Gaussian window of
+    sigma 1.5, L = 6 for z-scored patterns, pixels whose window fits)."""
+    a = _f64(R)
+    b = _f64(Tw)
+    H, W = a.shape
+    return float(lib().orc_ssim(_d(a), _d(b), H, W))
+
+
 def polar(F):
     """Rotation factor of F via SVD, Eq. (4)-(5)."""
     F = _f64(F).reshape(9)
@@ -417,7 +429,8 @@ def pc_pixels(H, W, params):
     return (params.pc_x * W - 0.5, params.pc_y * H - 0.5, params.pc_z * W)
 
 
-_OUT_KEYS = ("field", "q1", "F1", "Rfin", "q2", "ph", "F", "R", "rotvec", "iters", "status", "mae1", "mae")
+_OUT_KEYS = ("field", "q1", "F1", "Rfin", "q2", "ph", "F", "R", "rotvec", "iters", "status", "mae1", "mae",
+             "ssim")
 
 
 def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None):
@@ -449,6 +462,7 @@ def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None)
         "status": np.empty(n, np.uint32),
         "mae1": np.empty(n),
         "mae": np.empty(n),
+        "ssim": np.empty(n),
     }
     o = _Outputs()
     for k in _OUT_KEYS:

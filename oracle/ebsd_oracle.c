@@ -203,6 +203,46 @@ void orc_warp(const double* img, int H, int W, const double* u, double* out)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Structural similarity of the registration (the SSIM section 3 reports for
+ * demons; its window and constants are not given, the standard choices are
+ * taken): between the normalised reference R and the test warped by the
+ * final field, Tw(x) = T(x + u(x)).  For each pixel whose 11 x 11 window lies
+ * inside the pattern, with the Gaussian window w (sigma 1.5 px, radius 5,
+ * unit sum): mu_a = sum w a, var_a = sum w a^2 - mu_a^2, cov = sum w R Tw -
+ * mu_R mu_T, and
+ *   SSIM = (2 mu_R mu_T + C1)(2 cov + C2) / ((mu_R^2 + mu_T^2 + C1)(var_R + var_T + C2))
+ * with C1 = (0.01 L)^2, C2 = (0.03 L)^2 and L = 6 (the patterns are z-scored:
+ * +-3 standard deviations).  Returns the mean over those pixels.          */
+double orc_ssim(const double* R, const double* Tw, int H, int W)
+{
+    const int rad = 5;
+    double w[11], ws = 0.0;
+    for (int j = -rad; j <= rad; j++) ws += (w[j + rad] = exp(-(double)(j * j) / (2.0 * 1.5 * 1.5)));
+    for (int j = 0; j < 11; j++) w[j] /= ws;
+    const double L = 6.0, C1 = (0.01 * L) * (0.01 * L), C2 = (0.03 * L) * (0.03 * L);
+    double sum = 0.0;
+    long count = 0;
+    for (int y = rad; y < H - rad; y++)
+        for (int x = rad; x < W - rad; x++) {
+            double ma = 0, mb = 0, saa = 0, sbb = 0, sab = 0;
+            for (int j = -rad; j <= rad; j++)
+                for (int i = -rad; i <= rad; i++) {
+                    double ww = w[j + rad] * w[i + rad];
+                    double a = R[(size_t)(y + j) * W + x + i], b = Tw[(size_t)(y + j) * W + x + i];
+                    ma += ww * a;
+                    mb += ww * b;
+                    saa += ww * a * a;
+                    sbb += ww * b * b;
+                    sab += ww * a * b;
+                }
+            double va = saa - ma * ma, vb = sbb - mb * mb, cv = sab - ma * mb;
+            sum += (2.0 * ma * mb + C1) * (2.0 * cv + C2) / ((ma * ma + mb * mb + C1) * (va + vb + C2));
+            count++;
+        }
+    return count > 0 ? sum / (double)count : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Gaussian smoothing of one field channel: separable taps
  * w_j = exp(-j^2 / (2 sigma^2)), j = -r..r, r = floor(3 sigma + 0.5),
  * normalised to unit sum; the border is replicated.  sigma <= 0 copies.    */
@@ -1224,6 +1264,7 @@ typedef struct {
     uint32_t* status;
     double* mae1;    /* [1] */
     double* mae;     /* [1] */
+    double* ssim;    /* [1] orc_ssim of the final field (NaN with the XCF first pass) */
 } orc_outputs;
 
 static void store(double* dst, const double* src, size_t n)
@@ -1272,6 +1313,13 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
             q1[2 * j] = orc_bilinear(ux, H, W, cx[j], cy[j]);
             q1[2 * j + 1] = orc_bilinear(uy, H, W, cx[j], cy[j]);
         }
+    }
+    double ssim = NAN;
+    if (p->first_pass != 1 && o->ssim) {
+        double* Tw = (double*)malloc(sizeof(double) * HW);
+        orc_warp(Tn, H, W, field, Tw);
+        ssim = orc_ssim(Rn, Tw, H, W);
+        free(Tw);
     }
     double xs = p->pc_x * W - 0.5, ys = p->pc_y * H - 0.5, zs = p->pc_z * W;
     double F1[9], Rfin[9], F[9], R[9], rv[3];
@@ -1328,6 +1376,7 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
     if (o->status) *o->status = st;
     store(o->mae1, &mae1, 1);
     store(o->mae, &mae, 1);
+    store(o->ssim, &ssim, 1);
     free(Rn);
     free(Tn);
     free(field);
@@ -1373,6 +1422,7 @@ int orc_register_batch(const float* refs, const float* tests, int n, int H, int 
             oi.status = o->status ? o->status + i : NULL;
             oi.mae1 = o->mae1 ? o->mae1 + i : NULL;
             oi.mae = o->mae ? o->mae + i : NULL;
+            oi.ssim = o->ssim ? o->ssim + i : NULL;
             orc_register_pair(refs + (size_t)i * HW, tests + (size_t)i * HW, H, W, p, NULL,
                               rfin_in ? rfin_in + (size_t)i * 9 : NULL, &oi);
         }

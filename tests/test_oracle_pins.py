@@ -523,6 +523,36 @@ def test_traction_free_matches_scipy_constrained_minimiser(orc):
     assert np.abs(so[2, :]).max() < 1e-12 * NI[0]
 
 
+# -- structural similarity of the registration (section 3's SSIM) -----------------------------
+
+def _ssim_scipy(a, b, L=6.0):
+    # the same definition through scipy's Gaussian filter (sigma 1.5, radius int(3.5 * 1.5 + 0.5) = 5)
+    g = lambda x: ndi.gaussian_filter(x, 1.5, truncate=3.5, mode="nearest")
+    ma, mb = g(a), g(b)
+    va, vb, cv = g(a * a) - ma * ma, g(b * b) - mb * mb, g(a * b) - ma * mb
+    C1, C2 = (0.01 * L) ** 2, (0.03 * L) ** 2
+    m = (2 * ma * mb + C1) * (2 * cv + C2) / ((ma * ma + mb * mb + C1) * (va + vb + C2))
+    return m[5:-5, 5:-5].mean()  # pixels whose window lies inside
+
+
+def test_ssim_matches_scipy_gaussian_route(orc):
+    r = rng(60)
+    a = ndi.gaussian_filter(r.normal(size=(40, 52)), 1.0)
+    a = (a - a.mean()) / a.std()
+    b = 0.8 * a + 0.3 * r.normal(size=a.shape) + 0.1
+    np.testing.assert_allclose(orc.ssim(a, b), _ssim_scipy(a, b), rtol=1e-12)
+
+
+def test_ssim_identity_symmetry_and_noise(orc):
+    r = rng(61)
+    a = ndi.gaussian_filter(r.normal(size=(32, 32)), 1.0)
+    a = (a - a.mean()) / a.std()
+    b = a + 0.5 * r.normal(size=a.shape)
+    assert abs(orc.ssim(a, a) - 1.0) < 1e-14
+    assert abs(orc.ssim(a, b) - orc.ssim(b, a)) < 1e-14
+    assert orc.ssim(a, b) < orc.ssim(a, a + 0.1 * (b - a)) < 1.0
+
+
 def test_polar_matches_scipy(orc):
     F = np.eye(3) + rng(31).normal(scale=0.05, size=(3, 3))
     R = orc.polar(F)
@@ -662,6 +692,7 @@ def test_pipeline_identical_pair(orc):
     np.testing.assert_allclose(out["F"][0], np.eye(3), atol=1e-13)
     assert np.all(out["rotvec"][0] == 0) or np.abs(out["rotvec"][0]).max() < 1e-13
     np.testing.assert_allclose(out["ph"][0], 1.0, atol=1e-12)
+    assert abs(out["ssim"][0] - 1.0) < 1e-14
 
 
 def _tiled_pair(N, tiles, shift, seed):
