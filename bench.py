@@ -142,7 +142,11 @@ def main():
         rf = out["R_finite"].cpu().numpy()
         err_first = np.linalg.norm(np.stack([rotvec_of(r) for r in rf]) - rv_true, axis=1)
         log(f"[bench] {label}: {args.steps} steps in {el:.3f} s, median rotation error {np.median(err):.2e} rad")
-        return dict(elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
+        ssim = None
+        if reg.params.first_pass == 0 and not args.skip_comparison:
+            # one more (untimed) call for the structural similarity of the registration
+            ssim = reg.register(d_refs, d_tests, want_field=False, want_ssim=True)["ssim"].cpu().numpy()
+        return dict(ssim=ssim, elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
                     tuned=tuned, fused=fused, err_first=err_first, mae_first=out["mae_first"].cpu().numpy(),
                     mae=out["mae"].cpu().numpy(), ph=out["peak_height"].cpu().numpy().mean(axis=1))
 
@@ -271,6 +275,8 @@ def main():
                  "mean_angular_error_rad": {"median": float(np.median(m)), "p95": float(np.percentile(m, 95))}}
             if ph:
                 d["peak_height_mean"] = float(np.mean(r["ph"]))
+            if first and r.get("ssim") is not None:
+                d["ssim"] = {"median": float(np.median(r["ssim"])), "p5": float(np.percentile(r["ssim"], 5))}
             return d
         rec["comparison"] = {
             "note": "section 3's four methods on this batch; (b) and (d) from the warm-start run (its first "

@@ -136,6 +136,13 @@ typedef struct ebsd_outputs {
                                    F_first to q1 without a second pass), rad.  Mean angular error:
                                    the mean over the ROIs of the angle between F r_i and r_i + q_i
                                    (the quality figure section 3 compares the methods by) */
+    double* ssim;               /* [n] structural similarity of the registration (the SSIM section 3
+                                   reports for demons): mean over the pixels whose 11 x 11 window fits
+                                   (Gaussian, sigma 1.5 px) of SSIM(R, T(x + u(x))) between the
+                                   normalised reference and the test warped by the final field,
+                                   C1 = (0.01 L)^2, C2 = (0.03 L)^2, L = 6 (z-scored patterns); NaN with
+                                   the XCF first pass or a pattern of 10 px or less; computed only when
+                                   this pointer is set */
 } ebsd_outputs;
 
 /* Library ABI version (EBSD_ABI_VERSION). */

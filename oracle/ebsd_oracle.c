@@ -212,7 +212,8 @@ void orc_warp(const double* img, int H, int W, const double* u, double* out)
  * mu_R mu_T, and
  *   SSIM = (2 mu_R mu_T + C1)(2 cov + C2) / ((mu_R^2 + mu_T^2 + C1)(var_R + var_T + C2))
  * with C1 = (0.01 L)^2, C2 = (0.03 L)^2 and L = 6 (the patterns are z-scored:
- * +-3 standard deviations).  Returns the mean over those pixels.          */
+ * +-3 standard deviations).  Returns the mean over those pixels (NaN when
+ * the pattern is 10 px or less in either direction: no window fits).      */
 double orc_ssim(const double* R, const double* Tw, int H, int W)
 {
     const int rad = 5;
@@ -239,7 +240,7 @@ double orc_ssim(const double* R, const double* Tw, int H, int W)
             sum += (2.0 * ma * mb + C1) * (2.0 * cv + C2) / ((ma * ma + mb * mb + C1) * (va + vb + C2));
             count++;
         }
-    return count > 0 ? sum / (double)count : 0.0;
+    return count > 0 ? sum / (double)count : NAN; /* no window fits: undefined */
 }
 
 /* ------------------------------------------------------------------------ */

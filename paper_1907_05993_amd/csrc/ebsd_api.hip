@@ -413,6 +413,9 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const size_t o_rv = w.take(sizeof(double) * 3 * nb);
     const size_t o_st = w.take(sizeof(uint32_t) * nb);
     const size_t o_mae = w.take(sizeof(double) * 2 * nb);
+    const bool want_ssim = mode == Mode::Full && p.first_pass == 0 && out->ssim && !tune_only &&
+                           ssim_tiles(H, W) > 0;
+    const size_t o_ssim = w.take(want_ssim ? sizeof(double) * (size_t)nb * (1 + ssim_tiles(H, W)) : 0);
     const bool xcf = mode == Mode::SecondPassOnly || p.second_pass;
     const bool cubic = xcf && p.remap_interp == 3 && !tune_only;
     const size_t o_coef = w.take(cubic ? sizeof(float) * (size_t)nref * H * W : 0);
@@ -454,6 +457,8 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.status = reinterpret_cast<uint32_t*>(base + o_st);
     b.mae1 = reinterpret_cast<double*>(base + o_mae);
     b.mae = b.mae1 + nb;
+    b.ssim = want_ssim ? reinterpret_cast<double*>(base + o_ssim) : nullptr;
+    b.ssim_part = want_ssim ? b.ssim + nb : nullptr;
     b.ref_coef = cubic ? reinterpret_cast<float*>(base + o_coef) : nullptr;
     b.coef_tmp = cubic ? reinterpret_cast<float*>(base + o_coef_tmp) : nullptr;
 
@@ -471,6 +476,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.out.status = out->status;
     b.out.mae1 = mode == Mode::Full ? out->mae_first : nullptr;
     b.out.mae = out->mae;
+    b.out.ssim = mode == Mode::Full ? out->ssim : nullptr;
     b.u_init = warm ? reinterpret_cast<const float*>(base + o_uinit) : u_init;
     if (warm) {
         b.warm_field = reinterpret_cast<const float*>(base + o_wfield);
@@ -668,6 +674,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
             if (l > 0) EBSD_TRY(launch_prolong_level(d_bk, b, l, s));
         }
         EBSD_TRY(launch_sample_q1(d_bk, b, s));
+        if (want_ssim) EBSD_TRY(launch_ssim(d_bk, b, s));
         if (want_field) EBSD_TRY(launch_copy_field(d_bk, b, s));
         EBSD_TRY(launch_solve_first(d_bk, b, p.tol_px, s));
     } else {

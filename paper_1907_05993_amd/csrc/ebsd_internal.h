@@ -53,6 +53,7 @@ struct OutPtrs {
     float* warm_misfit;  // [n]
     double* mae1;        // [n] mean angular error of the first fit
     double* mae;         // [n] mean angular error of the last fit
+    double* ssim;        // [n] structural similarity of the registration
 };
 // Everything a bucket's kernels need, in device memory (one copy per bucket).
 struct Bucket {
@@ -92,6 +93,8 @@ struct Bucket {
     uint32_t* status;           // [nb]
     double* mae1;               // [nb] mean angular error of the first fit (F1 to q1), rad
     double* mae;                // [nb] mean angular error of the last fit, rad
+    double* ssim;               // [nb] structural similarity of the registration (NULL: not computed)
+    double* ssim_part;          // [nb][ssim tiles] per-tile sums
     float* ref_coef;            // [nref][H][W] cubic B-spline coefficients of level 0 (NULL: bilinear remap)
     float* coef_tmp;            // [nref][H][W] row pass of the coefficients
     // per-call caller pointers (so that a bucket's launch sequence is static
@@ -147,6 +150,11 @@ hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, in
 // The conventional first pass: ROI XCF of the unremapped level-0 patterns ->
 // q1, ph.
 hipError_t launch_xcf_first(const Bucket* d_bk, const Bucket& hb, int window, hipStream_t s);
+// Structural similarity of the normalised reference and the test warped by the
+// final field (11 x 11 Gaussian window, sigma 1.5; L = 6) -> bk->ssim, via
+// per-tile sums in bk->ssim_part.
+int ssim_tiles(int H, int W);
+hipError_t launch_ssim(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // iters[b][l] = 0 for every pair and level (no demons iterations run).
 hipError_t launch_zero_iters(const Bucket* d_bk, const Bucket& hb, hipStream_t s);
 // Rfin[b] = bk->rfin_in[pair_index[b]] (second-pass-only entry).

@@ -243,6 +243,98 @@ __global__ void k_sample_q1(const Bucket* __restrict__ bk)
     bk->q1[2 * t + 1] = bilinear_clamped(f + (int64_t)H * W, H, W, cx, cy);
 }
 
+// ---- structural similarity of the registration -----------------------------------
+// Tiles of 32 x 32 output pixels over the pixels whose 11 x 11 window fits
+// (x, y in [5, W - 5) x [5, H - 5)); the (32 + 10)^2 patch of the reference
+// and of the warped test, T(x + u(x)) (bilinear, clamped), sits in LDS; a
+// horizontal pass leaves the five windowed sums (a, b, a^2, b^2, ab) of 42
+// rows x 32 columns in LDS, the vertical pass forms SSIM per pixel; the tile's
+// sum (double) goes to ssim_part, and k_ssim_finish adds the tiles of a pair
+// in order.
+constexpr int kSsimT = 32, kSsimR = 5, kSsimP = kSsimT + 2 * kSsimR;
+
+__device__ inline void ssim_taps(float (&w)[2 * kSsimR + 1])
+{
+    double ws = 0.0, t[2 * kSsimR + 1];
+    for (int j = -kSsimR; j <= kSsimR; j++) ws += (t[j + kSsimR] = exp(-(double)(j * j) / (2.0 * 1.5 * 1.5)));
+    for (int j = 0; j <= 2 * kSsimR; j++) w[j] = (float)(t[j] / ws);
+}
+
+__global__ void __launch_bounds__(256) k_ssim_tiles(const Bucket* __restrict__ bk, int tiles_x)
+{
+    __shared__ float sa[kSsimP][kSsimP + 1], sb[kSsimP][kSsimP + 1];
+    __shared__ float hsum[5][kSsimP][kSsimT + 1];
+    __shared__ double red[256];
+    const int b = blockIdx.y, tile = blockIdx.x;
+    const int H = bk->H, W = bk->W;
+    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+    const int ox = kSsimR + txi * kSsimT, oy = kSsimR + tyi * kSsimT;
+    const float* __restrict__ R = bk->ref_pyr + (int64_t)bk->ref_slot[b] * bk->pyr_elems;
+    const float* __restrict__ T = bk->test_pyr + (int64_t)b * bk->pyr_elems;
+    const int64_t HW = (int64_t)H * W;
+    const float* __restrict__ u = bk->field[bk->state[b].cur] + (int64_t)b * 2 * HW;
+    float w[2 * kSsimR + 1];
+    ssim_taps(w);
+    for (int i = threadIdx.x; i < kSsimP * kSsimP; i += 256) {
+        const int py = i / kSsimP, px = i - kSsimP * (i / kSsimP);
+        // rows / columns past the pattern only feed outputs that are skipped
+        const int y = min(oy - kSsimR + py, H - 1), x = min(ox - kSsimR + px, W - 1);
+        const int64_t o = (int64_t)y * W + x;
+        sa[py][px] = R[o];
+        sb[py][px] = bilinear_clamped(T, H, W, (float)x + u[o], (float)y + u[HW + o]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSsimP * kSsimT; i += 256) {
+        const int py = i / kSsimT, c = i - kSsimT * (i / kSsimT);
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, s4 = 0.0f;
+#pragma unroll
+        for (int j = 0; j <= 2 * kSsimR; j++) {
+            const float a = sa[py][c + j], bv = sb[py][c + j], ww = w[j];
+            s0 += ww * a;
+            s1 += ww * bv;
+            s2 += ww * (a * a);
+            s3 += ww * (bv * bv);
+            s4 += ww * (a * bv);
+        }
+        hsum[0][py][c] = s0;
+        hsum[1][py][c] = s1;
+        hsum[2][py][c] = s2;
+        hsum[3][py][c] = s3;
+        hsum[4][py][c] = s4;
+    }
+    __syncthreads();
+    const float L = 6.0f, C1 = (0.01f * L) * (0.01f * L), C2 = (0.03f * L) * (0.03f * L);
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < kSsimT * kSsimT; i += 256) {
+        const int r = i / kSsimT, c = i - kSsimT * (i / kSsimT);
+        if (oy + r >= H - kSsimR || ox + c >= W - kSsimR) continue;
+        float m[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int j = 0; j <= 2 * kSsimR; j++)
+#pragma unroll
+            for (int k = 0; k < 5; k++) m[k] += w[j] * hsum[k][r + j][c];
+        const float va = m[2] - m[0] * m[0], vb = m[3] - m[1] * m[1], cv = m[4] - m[0] * m[1];
+        acc += (double)((2.0f * m[0] * m[1] + C1) * (2.0f * cv + C2) /
+                        ((m[0] * m[0] + m[1] * m[1] + C1) * (va + vb + C2)));
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bk->ssim_part[(int64_t)b * gridDim.x + tile] = red[0];
+}
+
+__global__ void k_ssim_finish(const Bucket* __restrict__ bk, int tiles)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bk->nb) return;
+    double s = 0.0;
+    for (int t = 0; t < tiles; t++) s += bk->ssim_part[(int64_t)b * tiles + t];
+    bk->ssim[b] = s / ((double)(bk->H - 2 * kSsimR) * (double)(bk->W - 2 * kSsimR));
+}
+
 __global__ void k_zero_iters(const Bucket* __restrict__ bk)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -336,6 +428,22 @@ hipError_t launch_sample_q1(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
     int n = hb.nb * hb.n_roi;
     hipLaunchKernelGGL(k_sample_q1, dim3((n + 255) / 256), dim3(256), 0, s, d_bk);
+    return hipGetLastError();
+}
+
+int ssim_tiles(int H, int W)
+{
+    if (H <= 2 * kSsimR || W <= 2 * kSsimR) return 0;
+    return ((W - 2 * kSsimR + kSsimT - 1) / kSsimT) * ((H - 2 * kSsimR + kSsimT - 1) / kSsimT);
+}
+
+hipError_t launch_ssim(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
+{
+    const int tiles = ssim_tiles(hb.H, hb.W);
+    if (!hb.ssim || !hb.ssim_part || tiles == 0 || hb.nb > 65535) return hipErrorInvalidValue;
+    const int tiles_x = (hb.W - 2 * kSsimR + kSsimT - 1) / kSsimT;
+    hipLaunchKernelGGL(k_ssim_tiles, dim3((unsigned)tiles, (unsigned)hb.nb), dim3(256), 0, s, d_bk, tiles_x);
+    hipLaunchKernelGGL(k_ssim_finish, dim3((hb.nb + 63) / 64), dim3(64), 0, s, d_bk, tiles);
     return hipGetLastError();
 }
 

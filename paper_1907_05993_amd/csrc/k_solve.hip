@@ -737,6 +737,7 @@ __global__ void k_scatter(const Bucket* __restrict__ bk)
     if (o.warm_misfit && bk->warm_misfit) o.warm_misfit[g] = bk->warm_misfit[b];
     if (o.mae1) o.mae1[g] = bk->mae1[b];
     if (o.mae) o.mae[g] = bk->mae[b];
+    if (o.ssim) o.ssim[g] = bk->ssim ? bk->ssim[b] : __builtin_nan("");
 }
 
 // blockIdx.y = pair; the field of one pair is h * w * 2 floats.

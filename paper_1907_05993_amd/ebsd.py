@@ -87,6 +87,7 @@ class COutputs(C.Structure):
         ("warm_misfit", C.c_void_p),
         ("mae_first", C.c_void_p),
         ("mae", C.c_void_p),
+        ("ssim", C.c_void_p),
     ]
 
 
@@ -296,7 +297,7 @@ class Registrar:
             keep += [r, t]
         return arr, n, [(t.shape[-2], t.shape[-1]) for t in tests], keep
 
-    def _outputs(self, shapes, want_field, dev):
+    def _outputs(self, shapes, want_field, dev, want_ssim=False):
         n = len(shapes)
         nr = self.params.n_roi
         f64 = dict(dtype=torch.float64, device=dev)
@@ -315,6 +316,8 @@ class Registrar:
             "mae_first": torch.empty(n, **f64),
             "mae": torch.empty(n, **f64),
         }
+        if want_ssim:
+            out["ssim"] = torch.empty(n, **f64)
         if self.params.warm_start and shapes:
             out["warm_field"] = torch.empty(n, 64, 64, 2, **f32)
             out["warm_misfit"] = torch.empty(n, **f32)
@@ -332,7 +335,7 @@ class Registrar:
         co.field = out["_field_flat"].data_ptr() if want_field else None
         co.field_offset = offs.ctypes.data if want_field else None
         for k in ("F", "R", "rotvec", "R_finite", "F_first", "q1", "q2", "peak_height", "iters",
-                  "status", "warm_field", "warm_misfit", "mae_first", "mae"):
+                  "status", "warm_field", "warm_misfit", "mae_first", "mae", "ssim"):
             if k in out:
                 setattr(co, k, out[k].data_ptr())
         return out, co
@@ -349,7 +352,7 @@ class Registrar:
             out["field"] = fields
         return out
 
-    def register(self, refs, tests, ref_ids=None, want_field=True, u_init=None):
+    def register(self, refs, tests, ref_ids=None, want_field=True, u_init=None, want_ssim=False):
         """Register test patterns against references (the whole path).
 
         refs, tests: float32 device tensors [n, H, W] (or lists of [H, W]
@@ -358,13 +361,15 @@ class Registrar:
         initial field (full-res px).  Returns a dict of device tensors:
         field, F, R, rotvec, R_finite, F_first, q1, q2, peak_height, iters,
         status, mae_first, mae (mean angular errors of the first and the last
-        fit, rad).  With first_pass = 1 (the conventional XCF first pass) no
-        field is returned.  Runs on torch's current stream.
+        fit, rad) and, with want_ssim, ssim (structural similarity of the
+        reference and the test warped by the final field).  With first_pass =
+        1 (the conventional XCF first pass) no field is returned.  Runs on
+        torch's current stream.
         """
         arr, n, shapes, keep = self._pairs(refs, tests, ref_ids)
         dev = keep[0].device if keep else torch.device("cuda", self.device)
         want_field = want_field and self.params.first_pass == 0
-        out, co = self._outputs(shapes, want_field, dev)
+        out, co = self._outputs(shapes, want_field, dev, want_ssim)
         if u_init is not None:
             if not (u_init.is_cuda and u_init.dtype == torch.float32 and u_init.is_contiguous()):
                 raise ValueError("u_init must be a contiguous float32 device tensor")

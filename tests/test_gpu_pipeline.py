@@ -279,9 +279,13 @@ def test_zero_pairs_and_validation(E, orc):
     reg = E.Registrar(gp)
     out = reg.register(torch.empty(0, 128, 128, device="cuda"), torch.empty(0, 128, 128, device="cuda"))
     assert out["F"].shape[0] == 0
+    # sizes that do not halve evenly are accepted (130 -> 65 -> 33); a coarsest level under 4 px is not
+    out = reg.register(cuda(np.zeros((1, 130, 128))), cuda(np.zeros((1, 130, 128))))
+    torch.cuda.synchronize()
+    assert out["F"].shape[0] == 1
     with pytest.raises(E.EbsdError) as ei:
-        reg.register(cuda(np.zeros((1, 130, 128))), cuda(np.zeros((1, 130, 128))))
-    assert ei.value.code == -2  # 130 not divisible by 4 at 3 levels
+        reg.register(cuda(np.zeros((1, 12, 128))), cuda(np.zeros((1, 12, 128))))
+    assert ei.value.code == -2  # 12 -> 6 -> 3
     with pytest.raises(E.EbsdError) as ei:
         E.Registrar(E.Params(roi_size=128)).register(cuda(np.zeros((1, 128, 128))),
                                                      cuda(np.zeros((1, 128, 128))))
