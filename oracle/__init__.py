@@ -43,6 +43,8 @@ class Params(C.Structure):
         ("remap_interp", C.c_int32),
         ("xcf_passes", C.c_int32),
         ("first_pass", C.c_int32),
+        ("bandpass_lo", C.c_double),
+        ("bandpass_hi", C.c_double),
     ]
 
 
@@ -67,7 +69,7 @@ class _Outputs(C.Structure):
 
 def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_roi=20,
                 roi_size=32, roi_radius_frac=0.3, window=1, second_pass=1, remap_interp=3,
-                xcf_passes=1, first_pass=0):
+                xcf_passes=1, first_pass=0, bandpass=(0.0, 0.0)):
     p = Params()
     p.levels = levels
     its = [iters] * MAX_LEVELS if np.isscalar(iters) else list(iters) + [0] * (MAX_LEVELS - len(iters))
@@ -84,6 +86,7 @@ def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_r
     p.remap_interp = remap_interp
     p.xcf_passes = xcf_passes
     p.first_pass = first_pass
+    p.bandpass_lo, p.bandpass_hi = bandpass
     return p
 
 
@@ -123,6 +126,7 @@ def lib():
         L.orc_solve_F_traction_free.restype = C.c_uint32
         L.orc_solve_F_traction_free.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d, d,
                                                 d, C.c_double, C.c_double, C.c_double, d, d, d]
+        L.orc_bandpass.argtypes = [f, C.c_int, C.c_int, C.c_double, C.c_double, d]
         L.orc_ssim.restype = C.c_double
         L.orc_ssim.argtypes = [d, d, C.c_int, C.c_int]
         L.orc_mae.restype = C.c_double
@@ -332,6 +336,16 @@ def solve_F_traction_free(q, cx, cy, pcs, S, g, C, M=None):
                                          _d(_f64(S).reshape(9)), _d(_f64(g).reshape(9)), float(C[0]),
                                          float(C[1]), float(C[2]), _d(F), _d(e), _d(sg))
     return F.reshape(3, 3), e.reshape(3, 3), sg.reshape(3, 3), int(st)
+
+
+def bandpass(img, lo, hi):
+    """Pre-filter of a raw pattern: Gaussian low-pass (sigma lo) minus the
+    Gaussian background (sigma hi); 0 turns a filter off."""
+    a = np.ascontiguousarray(img, dtype=np.float32)
+    H, W = a.shape
+    out = np.empty((H, W), np.float64)
+    lib().orc_bandpass(_f(a), H, W, float(lo), float(hi), _d(out))
+    return out
 
 
 def ssim(R, Tw):

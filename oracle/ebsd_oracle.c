@@ -71,6 +71,9 @@ typedef struct {
     int32_t first_pass;                /* 0 = demons (the paper's method), 1 = ROI
                                           cross-correlation of the unremapped
                                           patterns (the conventional first pass) */
+    double bandpass_lo;                /* pre-filter: sigma (px) of the low-pass, 0 = off */
+    double bandpass_hi;                /* pre-filter: sigma (px) of the background
+                                          Gaussian subtracted (high-pass), 0 = off */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -84,11 +87,22 @@ static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v >
  * (section 2); the oracle z-scores each pattern (population std) before
  * every stage.  Returns ORC_DEGENERATE_INPUT (and writes zeros) when the
  * pattern has no contrast, ORC_NONFINITE_INPUT when it holds NaN/Inf.      */
+uint32_t orc_normalize_d(const double* in, int64_t n, double* out);
+
 uint32_t orc_normalize(const float* in, int64_t n, double* out)
+{
+    double* d = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int64_t i = 0; i < n; i++) d[i] = (double)in[i];
+    uint32_t st = orc_normalize_d(d, n, out);
+    free(d);
+    return st;
+}
+
+uint32_t orc_normalize_d(const double* in, int64_t n, double* out)
 {
     double s = 0.0;
     for (int64_t i = 0; i < n; i++) {
-        double v = (double)in[i];
+        double v = in[i];
         if (!isfinite(v)) {
             for (int64_t j = 0; j < n; j++) out[j] = 0.0;
             return ORC_NONFINITE_INPUT;
@@ -98,7 +112,7 @@ uint32_t orc_normalize(const float* in, int64_t n, double* out)
     double mean = s / (double)n;
     double ss = 0.0;
     for (int64_t i = 0; i < n; i++) {
-        double d = (double)in[i] - mean;
+        double d = in[i] - mean;
         ss += d * d;
     }
     double sd = sqrt(ss / (double)n);
@@ -106,7 +120,7 @@ uint32_t orc_normalize(const float* in, int64_t n, double* out)
         for (int64_t i = 0; i < n; i++) out[i] = 0.0;
         return ORC_DEGENERATE_INPUT;
     }
-    for (int64_t i = 0; i < n; i++) out[i] = ((double)in[i] - mean) / sd;
+    for (int64_t i = 0; i < n; i++) out[i] = (in[i] - mean) / sd;
     return 0u;
 }
 
@@ -279,6 +293,28 @@ void orc_smooth(const double* v, int H, int W, double sigma, double* out)
         }
     free(tmp);
     free(w);
+}
+
+/* Pre-filter of a raw pattern (section 3.3: a low-pass filter against
+ * high-frequency noise and a high-pass filter against low-frequency
+ * background gradients, applied before registration; their kernels are not
+ * given).  Reading: Gaussian filters, out = G_lo * p - G_hi * p, where G_lo
+ * is orc_smooth with sigma lo (identity when lo <= 0) and G_hi * p the
+ * background estimate with sigma hi (nothing subtracted when hi <= 0).      */
+void orc_bandpass(const float* in, int H, int W, double lo, double hi, double* out)
+{
+    size_t HW = (size_t)H * W;
+    double* p = (double*)malloc(sizeof(double) * HW);
+    double* t = (double*)malloc(sizeof(double) * HW);
+    for (size_t i = 0; i < HW; i++) p[i] = (double)in[i];
+    if (lo > 0.0) orc_smooth(p, H, W, lo, out);
+    else memcpy(out, p, sizeof(double) * HW);
+    if (hi > 0.0) {
+        orc_smooth(p, H, W, hi, t);
+        for (size_t i = 0; i < HW; i++) out[i] -= t[i];
+    }
+    free(p);
+    free(t);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1290,8 +1326,17 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
     double* ph = (double*)calloc((size_t)nr, sizeof(double));
     int32_t its[ORC_MAX_LEVELS] = {0};
     uint32_t st = 0;
-    st |= orc_normalize(ref, (int64_t)HW, Rn);
-    st |= orc_normalize(test, (int64_t)HW, Tn);
+    if (p->bandpass_lo > 0.0 || p->bandpass_hi > 0.0) {
+        double* f = (double*)malloc(sizeof(double) * HW);
+        orc_bandpass(ref, H, W, p->bandpass_lo, p->bandpass_hi, f);
+        st |= orc_normalize_d(f, (int64_t)HW, Rn);
+        orc_bandpass(test, H, W, p->bandpass_lo, p->bandpass_hi, f);
+        st |= orc_normalize_d(f, (int64_t)HW, Tn);
+        free(f);
+    } else {
+        st |= orc_normalize(ref, (int64_t)HW, Rn);
+        st |= orc_normalize(test, (int64_t)HW, Tn);
+    }
     orc_roi_layout(H, W, p, cx, cy, x0, y0);
     double* a = (double*)malloc(sizeof(double) * N * N);
     double* b = (double*)malloc(sizeof(double) * N * N);

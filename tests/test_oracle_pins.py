@@ -523,6 +523,28 @@ def test_traction_free_matches_scipy_constrained_minimiser(orc):
     assert np.abs(so[2, :]).max() < 1e-12 * NI[0]
 
 
+# -- pre-filter (section 3.3: low-pass against noise, high-pass against background) -----------
+
+def test_bandpass_matches_scipy_gaussian_filters(orc):
+    x = rng(70).normal(size=(40, 52)).astype(np.float32)
+    g = lambda s: ndi.gaussian_filter(x.astype(np.float64), s, truncate=3.0, mode="nearest")
+    np.testing.assert_allclose(orc.bandpass(x, 1.2, 8.0), g(1.2) - g(8.0), atol=1e-12)
+    np.testing.assert_allclose(orc.bandpass(x, 1.2, 0.0), g(1.2), atol=1e-12)
+    np.testing.assert_allclose(orc.bandpass(x, 0.0, 8.0), x - g(8.0), atol=1e-12)
+    np.testing.assert_array_equal(orc.bandpass(x, 0.0, 0.0), x.astype(np.float64))
+
+
+def test_highpass_removes_a_linear_background(orc):
+    # a symmetric kernel reproduces a linear ramp wherever it does not reach the border
+    x = ndi.gaussian_filter(rng(71).normal(size=(64, 80)), 1.0)
+    y, xx = np.mgrid[0:64, 0:80]
+    ramp = 0.05 * xx - 0.08 * y + 3.0
+    r = int(3 * 6.0 + 0.5)
+    a = orc.bandpass((x + ramp).astype(np.float32), 0.0, 6.0)
+    b = orc.bandpass(x.astype(np.float32), 0.0, 6.0)
+    np.testing.assert_allclose(a[r:-r, r:-r], b[r:-r, r:-r], atol=2e-6)  # float32 input rounding
+
+
 # -- structural similarity of the registration (section 3's SSIM) -----------------------------
 
 def _ssim_scipy(a, b, L=6.0):
