@@ -103,6 +103,13 @@ typedef struct ebsd_params {
                                              cross-correlation of the unremapped patterns, no demons run,
                                              the field output is not written and iters are 0; needs
                                              warm_start = 0 */
+    float bandpass_lo_px;                 /* pre-filter of every raw pattern before normalisation (section
+                                             3.3: low-pass against noise, high-pass against background):
+                                             sigma of the Gaussian low-pass, 0 = off, <= 32 */
+    float bandpass_hi_px;                 /* sigma of the Gaussian background estimate subtracted, 0 = off,
+                                             <= 32; the filtered pattern is G_lo * p - G_hi * p (taps
+                                             exp(-j^2 / 2 sigma^2), |j| <= floor(3 sigma + 0.5), unit sum,
+                                             replicated border) */
 } ebsd_params;
 
 /* One scan point.  ref/test: device pointers to H x W fp32 patterns.  Pairs
@@ -362,6 +369,13 @@ int ebsd_set_model(ebsd_handle* h, const ebsd_cnn* c);
  * such patterns are written as zeros. */
 int ebsd_stage_normalize(const float* in, int32_t n, int64_t elems, float* out, uint32_t* flags,
                          void* stream);
+
+/* The pre-filter of ebsd_params (bandpass_lo_px, bandpass_hi_px) on n raw
+ * images in [n][H][W] -> out [n][H][W] (device fp32; 2 <= W <= 16384,
+ * H <= 65535, n <= 65535; both sigmas in [0, 32]).  Allocates a temporary
+ * of 2 n H W floats. */
+int ebsd_stage_bandpass(const float* in, int32_t n, int32_t H, int32_t W, float lo_px, float hi_px, float* out,
+                        void* stream);
 
 /* Factor-2 restriction of n images [n][H][W] -> [n][ceil(H/2)][ceil(W/2)]
  * with the separable [1,3,3,1]/8 filter, clamped borders (H, W >= 2; an odd

@@ -138,6 +138,15 @@ struct Plan {
     }
 };
 
+// A device temporary released when it goes out of scope.
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
 int check_params(const ebsd_params* p)
 {
     if (!p) return EBSD_EINVAL;
@@ -161,6 +170,8 @@ int check_params(const ebsd_params* p)
     if (p->xcf_passes < 1 || p->xcf_passes > 16) return EBSD_EINVAL;
     if (p->first_pass != 0 && p->first_pass != 1) return EBSD_EINVAL;
     if (p->first_pass == 1 && p->warm_start != 0) return EBSD_EINVAL;
+    if (!(p->bandpass_lo_px >= 0.0f && p->bandpass_lo_px <= 32.0f)) return EBSD_EINVAL;
+    if (!(p->bandpass_hi_px >= 0.0f && p->bandpass_hi_px <= 32.0f)) return EBSD_EINVAL;
     return EBSD_OK;
 }
 
@@ -413,6 +424,8 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const size_t o_rv = w.take(sizeof(double) * 3 * nb);
     const size_t o_st = w.take(sizeof(uint32_t) * nb);
     const size_t o_mae = w.take(sizeof(double) * 2 * nb);
+    const bool prefilter = p.bandpass_lo_px > 0.0f || p.bandpass_hi_px > 0.0f;
+    const size_t o_pf = w.take(prefilter ? sizeof(float) * 2 * (size_t)(nb + nref) * H * W : 0);
     const bool want_ssim = mode == Mode::Full && p.first_pass == 0 && out->ssim && !tune_only &&
                            ssim_tiles(H, W) > 0;
     const size_t o_ssim = w.take(want_ssim ? sizeof(double) * (size_t)nb * (1 + ssim_tiles(H, W)) : 0);
@@ -457,6 +470,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.status = reinterpret_cast<uint32_t*>(base + o_st);
     b.mae1 = reinterpret_cast<double*>(base + o_mae);
     b.mae = b.mae1 + nb;
+    b.prefilter = prefilter ? 1 : 0;
     b.ssim = want_ssim ? reinterpret_cast<double*>(base + o_ssim) : nullptr;
     b.ssim_part = want_ssim ? b.ssim + nb : nullptr;
     b.ref_coef = cubic ? reinterpret_cast<float*>(base + o_coef) : nullptr;
@@ -530,6 +544,23 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
 
     const bool tm = h->timing && mode == Mode::Full;
     if (tm) EBSD_TRY(hipEventRecord(h->ev[0], s));
+    if (prefilter) {
+        // pre-filtered raw patterns into level 0, normalised there in place
+        BandIO io;
+        io.src_a = b.test_in;
+        io.src_b = b.ref_in;
+        io.src = nullptr;
+        io.src_stride = 0;
+        io.dst_a = b.test_pyr;
+        io.dst_b = b.ref_pyr;
+        io.dst_stride = pe;
+        io.na = nb;
+        io.npat = nb + nref;
+        io.H = H;
+        io.W = W;
+        io.tmp = reinterpret_cast<float*>(base + o_pf);
+        EBSD_TRY(launch_bandpass(io, make_band_taps(p.bandpass_lo_px, p.bandpass_hi_px), s));
+    }
     EBSD_TRY(launch_stats(d_bk, nb, nref, s));
     EBSD_TRY(launch_pyramids(d_bk, b, s));
     if (tune_only) {
@@ -775,6 +806,8 @@ int ebsd_params_default(ebsd_params* p)
     p->remap_interp = 3;
     p->xcf_passes = 1;
     p->first_pass = 0;
+    p->bandpass_lo_px = 0.0f;
+    p->bandpass_hi_px = 0.0f;
     return EBSD_OK;
 }
 
@@ -998,6 +1031,36 @@ int ebsd_stage_normalize(const float* in, int32_t n, int64_t elems, float* out, 
     if (n < 0 || elems <= 0 || (n > 0 && (!in || !out))) return EBSD_EINVAL;
     if (n == 0) return EBSD_OK;
     return map_err(launch_stage_normalize(in, n, elems, out, flags, (hipStream_t)stream));
+}
+
+int ebsd_stage_bandpass(const float* in, int32_t n, int32_t H, int32_t W, float lo_px, float hi_px, float* out,
+                        void* stream)
+{
+    if (n < 0 || (n > 0 && (!in || !out))) return EBSD_EINVAL;
+    if (!(lo_px >= 0.0f && lo_px <= 32.0f) || !(hi_px >= 0.0f && hi_px <= 32.0f)) return EBSD_EINVAL;
+    if (H < 1 || W < 2 || W > 16384 || H > 65535 || n > 65535) return EBSD_ESHAPE;
+    if (n == 0) return EBSD_OK;
+    DevBuf tmp;
+    if (hipMalloc(&tmp.p, sizeof(float) * 2 * (size_t)n * H * W) != hipSuccess) return EBSD_ENOMEM;
+    BandIO io;
+    io.src_a = nullptr;
+    io.src_b = nullptr;
+    io.src = in;
+    io.src_stride = (int64_t)H * W;
+    io.dst_a = out;
+    io.dst_b = nullptr;
+    io.dst_stride = (int64_t)H * W;
+    io.na = n;
+    io.npat = n;
+    io.H = H;
+    io.W = W;
+    io.tmp = static_cast<float*>(tmp.p);
+    const hipStream_t s = (hipStream_t)stream;
+    const int e = map_err(launch_bandpass(io, make_band_taps(lo_px, hi_px), s));
+    if (e) return e;
+    // the temporary is released after the stream has used it
+    if (hipStreamSynchronize(s) != hipSuccess) return EBSD_EDEVICE;
+    return EBSD_OK;
 }
 
 int ebsd_stage_restrict(const float* in, int32_t n, int32_t H, int32_t W, float* out, void* stream)

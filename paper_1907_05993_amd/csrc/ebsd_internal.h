@@ -93,6 +93,7 @@ struct Bucket {
     uint32_t* status;           // [nb]
     double* mae1;               // [nb] mean angular error of the first fit (F1 to q1), rad
     double* mae;                // [nb] mean angular error of the last fit, rad
+    int32_t prefilter;          // 1: level 0 holds the pre-filtered patterns before normalisation
     double* ssim;               // [nb] structural similarity of the registration (NULL: not computed)
     double* ssim_part;          // [nb][ssim tiles] per-tile sums
     float* ref_coef;            // [nref][H][W] cubic B-spline coefficients of level 0 (NULL: bilinear remap)
@@ -150,6 +151,29 @@ hipError_t launch_xcf_pairs(const Bucket* d_bk, const Bucket& hb, int window, in
 // The conventional first pass: ROI XCF of the unremapped level-0 patterns ->
 // q1, ph.
 hipError_t launch_xcf_first(const Bucket* d_bk, const Bucket& hb, int window, hipStream_t s);
+// Pre-filter (Gaussian low-pass minus Gaussian background) of raw patterns.
+// Pattern p reads src + p src_stride (src != NULL) or src_a[p] (p < na) /
+// src_b[p - na], and writes dst_a + p dst_stride (p < na) or dst_b + (p - na)
+// dst_stride; tmp holds 2 x npat x H x W floats.  Taps: r < 0 turns a filter off.
+constexpr int kBandMaxR = 96;
+struct BandTaps {
+    float lo[2 * kBandMaxR + 1];
+    float hi[2 * kBandMaxR + 1];
+    int rlo, rhi;
+};
+struct BandIO {
+    const float* const* src_a;
+    const float* const* src_b;
+    const float* src;
+    int64_t src_stride;
+    float* dst_a;
+    float* dst_b;
+    int64_t dst_stride;
+    int na, npat, H, W;
+    float* tmp;
+};
+BandTaps make_band_taps(double lo, double hi);
+hipError_t launch_bandpass(const BandIO& io, const BandTaps& tp, hipStream_t s);
 // Structural similarity of the normalised reference and the test warped by the
 // final field (11 x 11 Gaussian window, sigma 1.5; L = 6) -> bk->ssim, via
 // per-tile sums in bk->ssim_part.

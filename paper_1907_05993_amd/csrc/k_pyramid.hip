@@ -4,6 +4,8 @@
 // All of these are HBM-streaming passes that touch each pattern a few times per
 // batch; they are far from the hot loop and are written for coalesced access
 // rather than for peak bandwidth.
+#include <cmath>
+
 #include "dev_util.h"
 
 #include "../../include/ebsd.h"
@@ -72,15 +74,18 @@ __device__ void pattern_stats(const float* __restrict__ p, int64_t n, PatStat* o
     }
 }
 
+// Statistics of each raw pattern, or of its pre-filtered copy in level 0.
 __global__ void __launch_bounds__(kStatThreads) k_stats(const Bucket* __restrict__ bk)
 {
     __shared__ double sh[kStatThreads];
     const int i = blockIdx.x;
     const int64_t n = (int64_t)bk->H * bk->W;
     if (i < bk->nb)
-        pattern_stats(bk->test_in[i], n, &bk->test_stat[i], sh);
+        pattern_stats(bk->prefilter ? bk->test_pyr + (int64_t)i * bk->pyr_elems : bk->test_in[i], n,
+                      &bk->test_stat[i], sh);
     else
-        pattern_stats(bk->ref_in[i - bk->nb], n, &bk->ref_stat[i - bk->nb], sh);
+        pattern_stats(bk->prefilter ? bk->ref_pyr + (int64_t)(i - bk->nb) * bk->pyr_elems : bk->ref_in[i - bk->nb],
+                      n, &bk->ref_stat[i - bk->nb], sh);
 }
 
 // Level 0 of every pyramid: (p - mean) / std, zeros for flagged patterns.
@@ -92,13 +97,13 @@ __global__ void k_normalize_l0(const Bucket* __restrict__ bk)
     float* dst;
     PatStat st;
     if (pat < bk->nb) {
-        src = bk->test_in[pat];
         dst = bk->test_pyr + (int64_t)pat * bk->pyr_elems;
+        src = bk->prefilter ? dst : bk->test_in[pat];  // in place over the pre-filtered copy
         st = bk->test_stat[pat];
     } else {
         int r = pat - bk->nb;
-        src = bk->ref_in[r];
         dst = bk->ref_pyr + (int64_t)r * bk->pyr_elems;
+        src = bk->prefilter ? dst : bk->ref_in[r];
         st = bk->ref_stat[r];
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -241,6 +246,66 @@ __global__ void k_sample_q1(const Bucket* __restrict__ bk)
     float cx = (float)bk->roi_c[2 * j], cy = (float)bk->roi_c[2 * j + 1];
     bk->q1[2 * t] = bilinear_clamped(f, H, W, cx, cy);
     bk->q1[2 * t + 1] = bilinear_clamped(f + (int64_t)H * W, H, W, cx, cy);
+}
+
+// ---- pre-filter -------------------------------------------------------------------
+// Gaussian low-pass minus Gaussian background estimate, separable, replicated
+// border.  Horizontal pass: one workgroup per (row, pattern), the row in LDS,
+// both filters' row sums to tmp; vertical pass: one thread per pixel, the
+// column sums combined into the destination.
+__device__ inline const float* band_src(const BandIO& io, int p)
+{
+    return io.src ? io.src + (int64_t)p * io.src_stride : (p < io.na ? io.src_a[p] : io.src_b[p - io.na]);
+}
+
+__global__ void __launch_bounds__(256) k_band_rows(BandIO io, BandTaps tp)
+{
+    extern __shared__ float row[];
+    const int y = blockIdx.x, p = blockIdx.y, W = io.W;
+    const float* __restrict__ src = band_src(io, p) + (int64_t)y * W;
+    for (int x = threadIdx.x; x < W; x += 256) row[x] = src[x];
+    __syncthreads();
+    const int64_t HW = (int64_t)io.H * W;
+    float* tlo = io.tmp + (2 * (int64_t)p) * HW + (int64_t)y * W;
+    float* thi = tlo + HW;
+    for (int x = threadIdx.x; x < W; x += 256) {
+        if (tp.rlo >= 0) {
+            float acc = 0.0f;
+            for (int j = -tp.rlo; j <= tp.rlo; j++) acc += tp.lo[j + tp.rlo] * row[clampi(x + j, 0, W - 1)];
+            tlo[x] = acc;
+        }
+        if (tp.rhi >= 0) {
+            float acc = 0.0f;
+            for (int j = -tp.rhi; j <= tp.rhi; j++) acc += tp.hi[j + tp.rhi] * row[clampi(x + j, 0, W - 1)];
+            thi[x] = acc;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_band_cols(BandIO io, BandTaps tp)
+{
+    const int p = blockIdx.y, H = io.H, W = io.W;
+    const int64_t HW = (int64_t)H * W;
+    const float* __restrict__ tlo = io.tmp + (2 * (int64_t)p) * HW;
+    const float* __restrict__ thi = tlo + HW;
+    const float* __restrict__ src = band_src(io, p);
+    float* dst = p < io.na ? io.dst_a + (int64_t)p * io.dst_stride : io.dst_b + (int64_t)(p - io.na) * io.dst_stride;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < HW; t += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(t / W), x = (int)(t - (int64_t)W * (t / W));
+        float v;
+        if (tp.rlo >= 0) {
+            v = 0.0f;
+            for (int j = -tp.rlo; j <= tp.rlo; j++) v += tp.lo[j + tp.rlo] * tlo[(int64_t)clampi(y + j, 0, H - 1) * W + x];
+        } else {
+            v = src[t];
+        }
+        if (tp.rhi >= 0) {
+            float b = 0.0f;
+            for (int j = -tp.rhi; j <= tp.rhi; j++) b += tp.hi[j + tp.rhi] * thi[(int64_t)clampi(y + j, 0, H - 1) * W + x];
+            v -= b;
+        }
+        dst[t] = v;
+    }
 }
 
 // ---- structural similarity of the registration -----------------------------------
@@ -428,6 +493,35 @@ hipError_t launch_sample_q1(const Bucket* d_bk, const Bucket& hb, hipStream_t s)
 {
     int n = hb.nb * hb.n_roi;
     hipLaunchKernelGGL(k_sample_q1, dim3((n + 255) / 256), dim3(256), 0, s, d_bk);
+    return hipGetLastError();
+}
+
+BandTaps make_band_taps(double lo, double hi)
+{
+    BandTaps tp;
+    auto fill = [](double sigma, float* w) -> int {
+        if (!(sigma > 0.0)) return -1;
+        const int r = (int)std::floor(3.0 * sigma + 0.5);
+        double t[2 * kBandMaxR + 1], sum = 0.0;
+        for (int j = -r; j <= r; j++) sum += (t[j + r] = std::exp(-(double)(j * j) / (2.0 * sigma * sigma)));
+        for (int j = 0; j <= 2 * r; j++) w[j] = (float)(t[j] / sum);
+        return r;
+    };
+    for (int j = 0; j <= 2 * kBandMaxR; j++) tp.lo[j] = tp.hi[j] = 0.0f;
+    tp.rlo = fill(lo, tp.lo);
+    tp.rhi = fill(hi, tp.hi);
+    return tp;
+}
+
+hipError_t launch_bandpass(const BandIO& io, const BandTaps& tp, hipStream_t s)
+{
+    if (io.npat <= 0) return hipSuccess;
+    if (io.W > 16384 || io.H > 65535 || io.npat > 65535 || tp.rlo > kBandMaxR || tp.rhi > kBandMaxR)
+        return hipErrorInvalidValue;
+    const size_t lds = sizeof(float) * (size_t)io.W;  // <= 64 KiB
+    hipLaunchKernelGGL(k_band_rows, dim3((unsigned)io.H, (unsigned)io.npat), dim3(256), lds, s, io, tp);
+    hipLaunchKernelGGL(k_band_cols, dim3(grid_for((int64_t)io.H * io.W, 256), (unsigned)io.npat), dim3(256), 0, s,
+                       io, tp);
     return hipGetLastError();
 }
 

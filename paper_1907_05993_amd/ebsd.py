@@ -56,6 +56,8 @@ class CParams(C.Structure):
         ("remap_interp", C.c_int32),
         ("xcf_passes", C.c_int32),
         ("first_pass", C.c_int32),
+        ("bandpass_lo_px", C.c_float),
+        ("bandpass_hi_px", C.c_float),
     ]
 
 
@@ -97,7 +99,8 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_get_params", "ebsd_roi_layout", "ebsd_register_batch",
             "ebsd_register_batch_init", "ebsd_second_pass_batch", "ebsd_stage_normalize",
             "ebsd_stage_restrict", "ebsd_stage_demons_iter", "ebsd_stage_prolong",
-            "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_stage_remap", "ebsd_traction_free", "ebsd_set_timing", "ebsd_get_timing",
+            "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_stage_remap", "ebsd_traction_free",
+            "ebsd_stage_bandpass", "ebsd_set_timing", "ebsd_get_timing",
             "ebsd_autotune", "ebsd_get_strip_height", "ebsd_set_strip_height", "ebsd_set_graphs",
             "ebsd_cnn_num_params", "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_set_params",
             "ebsd_cnn_get_params", "ebsd_cnn_get_grads", "ebsd_cnn_load", "ebsd_cnn_save",
@@ -143,6 +146,7 @@ def lib():
                                        vp, vp, vp, vp]
         L.ebsd_stage_remap.argtypes = [vp, i32, i32, i32, vp, C.c_double, C.c_double, C.c_double, i32,
                                        vp, vp, vp]
+        L.ebsd_stage_bandpass.argtypes = [vp, i32, i32, i32, C.c_float, C.c_float, vp, vp]
         L.ebsd_traction_free.argtypes = [vp, i32, i32, vp, vp, C.c_double, C.c_double, C.c_double, vp, vp,
                                          C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double, vp, vp, vp,
                                          vp, vp]
@@ -210,6 +214,7 @@ class Params:
     remap_interp: int = 3
     xcf_passes: int = 1
     first_pass: int = 0
+    bandpass: tuple = (0.0, 0.0)   # pre-filter sigmas (low-pass, background), px; 0 = off
 
     def to_c(self):
         p = CParams()
@@ -232,6 +237,7 @@ class Params:
         p.remap_interp = self.remap_interp
         p.xcf_passes = self.xcf_passes
         p.first_pass = self.first_pass
+        p.bandpass_lo_px, p.bandpass_hi_px = (float(v) for v in self.bandpass)
         return p
 
 
@@ -529,6 +535,17 @@ def stage_normalize(p):
     _check(lib().ebsd_stage_normalize(_ptr(p), n, p[0].numel() if n else 1, _ptr(out), _ptr(flags),
                                       _stream()), "ebsd_stage_normalize")
     return out, flags
+
+
+def stage_bandpass(img, lo, hi):
+    """Pre-filter (Gaussian low-pass sigma lo minus Gaussian background sigma
+    hi, 0 = off) of raw images [n, H, W] float32 device."""
+    img = _dev_f32(img)
+    n, H, W = img.shape
+    out = torch.empty_like(img)
+    _check(lib().ebsd_stage_bandpass(_ptr(img), n, H, W, float(lo), float(hi), _ptr(out), _stream()),
+           "ebsd_stage_bandpass")
+    return out
 
 
 def stage_restrict(img):

@@ -67,7 +67,9 @@ def test_create_validates_before_touching_the_device(E):
                              ("window", 2, -1), ("pc_z", 0.0, -1), ("tol_px", float("nan"), -1),
                              ("warm_start", 3, -1), ("fallback_residual_px", -1.0, -1),
                              ("remap_interp", 2, -1), ("remap_interp", 0, -1), ("xcf_passes", 0, -1),
-                             ("xcf_passes", 17, -1), ("first_pass", 2, -1), ("first_pass", -1, -1)]:
+                             ("xcf_passes", 17, -1), ("first_pass", 2, -1), ("first_pass", -1, -1),
+                             ("bandpass_lo_px", -1.0, -1), ("bandpass_hi_px", 33.0, -1),
+                             ("bandpass_hi_px", float("nan"), -1)]:
         p = E.Params().to_c()
         setattr(p, field, val)
         assert L.ebsd_create(C.byref(p), 0, C.byref(h)) == code, field
@@ -116,6 +118,10 @@ def test_null_arguments_rejected(E):
     assert L.ebsd_stage_remap(fake, 1, 64, 64, fake, 31.5, 31.5, 0.0, 1, None, fake, None) == -1
     assert L.ebsd_stage_remap(fake, 1, 2, 64, fake, 31.5, 31.5, 44.8, 1, None, fake, None) == -2
     assert L.ebsd_stage_remap(None, 0, 64, 64, None, 31.5, 31.5, 44.8, 3, None, None, None) == 0
+    assert L.ebsd_stage_bandpass(None, 1, 64, 64, C.c_float(1.0), C.c_float(8.0), fake, None) == -1
+    assert L.ebsd_stage_bandpass(fake, 1, 64, 64, C.c_float(40.0), C.c_float(8.0), fake, None) == -1
+    assert L.ebsd_stage_bandpass(fake, 1, 64, 20000, C.c_float(1.0), C.c_float(8.0), fake, None) == -2
+    assert L.ebsd_stage_bandpass(None, 0, 64, 64, C.c_float(1.0), C.c_float(8.0), None, None) == 0
     assert L.ebsd_destroy(None) == 0
     # traction-free solve: validation before any launch
     eye = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
