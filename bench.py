@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512, help="pairs timed on the CPU oracle (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "demons_traffic.json"))
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="run the coarse levels one or two iterations per launch instead of one launch per level")
     ap.add_argument("--skip-plain", action="store_true", help="time the warm start only (profiling runs)")
     ap.add_argument("--paper-pairs", type=int, default=256,
                     help="pairs of the paper's own workload (1244 x 1024, 7 levels x 25) to time (0 = skip)")
@@ -119,6 +121,7 @@ def main():
         if warm:
             reg.load_model(WEIGHTS)
         reg.set_graphs(not args.no_graphs)
+        reg.set_resident(not args.no_resident)
         return reg
 
     def timed(reg, label, tune=True):
@@ -297,6 +300,7 @@ def main():
         p1 = ebsd.Params(levels=3, iters=(100, 100, 100), sigma_px=1.0, tol_px=0.0, roi_size=32, n_roi=20)
         reg1 = ebsd.Registrar(p1, device=0)
         reg1.set_graphs(not args.no_graphs)
+        reg1.set_resident(not args.no_resident)
         reg1.autotune(r1, t1)  # strip heights for this one-pair batch
         for _ in range(3):
             reg1.register(r1, t1, want_field=False)

@@ -235,6 +235,16 @@ int ebsd_autotune(ebsd_handle* h, const ebsd_pair* pairs, int32_t n, void* strea
  * Results are identical either way. */
 int ebsd_set_graphs(ebsd_handle* h, int enable);
 
+/* Demons levels of at most 64 x 64 pixels of a size bucket of at most 256
+ * pairs run in one launch per level (default, enable = 1): one workgroup per
+ * pair keeps the level's reference, test and field in LDS and iterates to the
+ * cap or to its own tolerance (multi-resolution demons, section 1).  Larger
+ * buckets, and enable = 0, run them like the finer levels, one or two
+ * iterations per launch.  The fields are bit-identical either way; the squared
+ * update is summed in another order, so a stop on the tolerance can differ
+ * only when the RMS update lies within rounding of it. */
+int ebsd_set_resident(ebsd_handle* h, int enable);
+
 /* Strip height used for a pyramid level of level_h x level_w px (0 if that
  * level uses the 2-D tile kernel, i.e. wider than 512 px): the tuned or
  * forced value, else 64.  Untuned levels of a batch with fewer than 512

@@ -128,6 +128,12 @@ hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, i
 // fused row-marching kernel; cap = the level's iteration cap).
 hipError_t launch_demons_iter2(const Bucket* d_bk, const Bucket& hb, int level, int L, const float* taps,
                                int radius, float tol, int cap, int ty, hipStream_t s);
+// A whole level of at most 64 x 64 pixels in one launch, one workgroup per
+// pair iterating in LDS to the cap or the tolerance; leaves the final field,
+// the iteration count and the pair state as launch_level_end does.
+bool demons_resident_ok(int h, int w);
+hipError_t launch_demons_resident(const Bucket* d_bk, const Bucket& hb, int level, const float* taps, int radius,
+                                  float tol, int cap, hipStream_t s);
 // Close level l: iteration counts, convergence of the last iteration, final buffer.
 hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int cap, float tol,
                             int ty, bool fused, hipStream_t s);

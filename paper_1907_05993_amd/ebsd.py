@@ -102,6 +102,7 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_stage_xcf", "ebsd_stage_solve", "ebsd_stage_remap", "ebsd_traction_free",
             "ebsd_stage_bandpass", "ebsd_set_timing", "ebsd_get_timing",
             "ebsd_autotune", "ebsd_get_strip_height", "ebsd_set_strip_height", "ebsd_set_graphs",
+            "ebsd_set_resident",
             "ebsd_cnn_num_params", "ebsd_cnn_create", "ebsd_cnn_destroy", "ebsd_cnn_set_params",
             "ebsd_cnn_get_params", "ebsd_cnn_get_grads", "ebsd_cnn_load", "ebsd_cnn_save",
             "ebsd_cnn_forward", "ebsd_cnn_train_step", "ebsd_cnn_reset_optimizer",
@@ -131,6 +132,7 @@ def lib():
         L.ebsd_second_pass_batch.argtypes = [vp, C.POINTER(CPair), i32, vp, C.POINTER(COutputs), vp]
         L.ebsd_autotune.argtypes = [vp, C.POINTER(CPair), i32, vp]
         L.ebsd_set_graphs.argtypes = [vp, C.c_int]
+        L.ebsd_set_resident.argtypes = [vp, C.c_int]
         L.ebsd_get_strip_height.argtypes = [vp, i32, i32]
         L.ebsd_set_strip_height.argtypes = [vp, i32, i32, i32]
         L.ebsd_get_fused_height.argtypes = [vp, i32, i32]
@@ -410,6 +412,11 @@ class Registrar:
     def set_graphs(self, on=True):
         """Replay captured HIP graphs (default) or launch every kernel directly."""
         _check(lib().ebsd_set_graphs(self._h, int(bool(on))), "ebsd_set_graphs")
+
+    def set_resident(self, on=True):
+        """Run levels of at most 64 x 64 px in one launch each (default) or like
+        the finer levels."""
+        _check(lib().ebsd_set_resident(self._h, int(bool(on))), "ebsd_set_resident")
 
     def set_strip_height(self, level_h, level_w, rows):
         _check(lib().ebsd_set_strip_height(self._h, level_h, level_w, rows), "ebsd_set_strip_height")
