@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "pattern pairs/sec (demons+XCF, 256² px, 10°) warm-start vs plain; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3  # vector FP32 (256 CUs, 2.4 GHz)
 BYTES_PER_PX_ITER = 24  # read field 8 + ref 4 + test 4 (gather), write field 8
 CNN_FLOP_PER_PAIR = 11.55e9  # network forward pass, 256 x 256 input
 WEIGHTS = os.path.join(ROOT, "paper_1907_05993_amd", "weights", "warm_cnn_256.bin")
@@ -149,7 +150,7 @@ def main():
         if reg.params.first_pass == 0 and not args.skip_comparison:
             # one more (untimed) call for the structural similarity of the registration
             ssim = reg.register(d_refs, d_tests, want_field=False, want_ssim=True)["ssim"].cpu().numpy()
-        return dict(ssim=ssim, elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
+        return dict(R_finite=out["R_finite"], ssim=ssim, elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
                     tuned=tuned, fused=fused, err_first=err_first, mae_first=out["mae_first"].cpu().numpy(),
                     mae=out["mae"].cpu().numpy(), ph=out["peak_height"].cpu().numpy().mean(axis=1))
 
@@ -161,6 +162,35 @@ def main():
     xcf_c = None if args.skip_comparison else timed(make(False, args.cap, first_pass=1), "XCF first pass", tune=False)
     xcf_a = None if args.skip_comparison else timed(make(False, args.cap, first_pass=1, second_pass=0),
                                                    "XCF only", tune=False)
+
+    # the ROI cross-correlation core alone (ebsd_stage_xcf: window, FFTs, product, inverse FFT,
+    # peak fit) on the batch's 20 ROIs per pair, and the whole second pass from the warm run's
+    # R_finite (normalisation, B-spline coefficients, remap + XCF, Eq. (3) solves); HIP events
+    # on torch's stream, which the library launches on
+    Nr = w["roi"]
+    offs = [((H - Nr) * (j % 5) // 4, (W - Nr) * (j // 5) // 3) for j in range(20)]
+    A = torch.stack([d_refs[:, y:y + Nr, x:x + Nr] for y, x in offs], 1).reshape(-1, Nr, Nr).contiguous()
+    Bt = torch.stack([d_tests[:, y:y + Nr, x:x + Nr] for y, x in offs], 1).reshape(-1, Nr, Nr).contiguous()
+    ebsd.stage_xcf(A, Bt)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        ebsd.stage_xcf(A, Bt)
+    e1.record()
+    torch.cuda.synchronize()
+    xcf_ms = e0.elapsed_time(e1) / 3
+    del A, Bt
+    reg2 = make(True, args.cap)
+    rf = warm["R_finite"]
+    reg2.second_pass(d_refs, d_tests, rf)
+    e0.record()
+    for _ in range(3):
+        reg2.second_pass(d_refs, d_tests, rf)
+    e1.record()
+    torch.cuda.synchronize()
+    second_ms = e0.elapsed_time(e1) / 3
+    import math
+    xcf_flop = 20 * 3 * 5 * Nr * Nr * math.log2(Nr * Nr) * n  # three complex 2-D FFTs per ROI
 
     # network forward alone on the same batch (chunks of 256), HIP events on torch's stream
     net = ebsd.Cnn(device=0, max_batch=256)
@@ -264,6 +294,19 @@ def main():
             "frac": round(CNN_FLOP_PER_PAIR * n / (cnn_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
             "traffic": None,
             "forward_ms_per_step": round(cnn_ms, 3),
+        },
+        "roofline_xcf": {
+            "bound": "alu",
+            "kernel": f"k_xcf_stage<{Nr}> (ROI cross-correlation core: Hann window, packed complex FFTs in LDS, "
+                      "product, inverse FFT, argmax and 2-D quadratic peak fit), 20 ROIs per pair",
+            "achieved": round(xcf_flop / (xcf_ms * 1e-3) / 1e12, 2),
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(xcf_flop / (xcf_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+            "traffic": None,
+            "flop_model": "3 complex 2-D FFTs of N^2 points per ROI at 5 N^2 log2 N^2 flop each",
+            "ms_per_step": round(xcf_ms, 3),
+            "second_pass_ms_per_step": round(second_ms, 3),
         },
         "warm": summary(warm),
         "plain": summary(plain) if plain is not None else None,

@@ -62,6 +62,11 @@ def test_scan_map_4096_full_size(E, orc):
     dt = time.perf_counter() - t0
     print(f"{n} pairs in {dt:.2f} s ({n / dt:.0f} pairs/s, first call incl. graph capture)")
     check_all(g, n)
+    its = g["iters"].cpu().numpy()
+    edges = [1, 2, 5, 10, 20, 50, 100, 150, 151]
+    for l in range(its.shape[1]):
+        hist, _ = np.histogram(its[:, l], bins=edges)
+        print("iterations at level %d (bins %s): %s" % (l, edges, hist.tolist()))
     # rotation against the generator's intragranular rotation field
     truth = np.stack([t.extra["rotvec"] for t in tests])
     err = np.linalg.norm(g["rotvec"].cpu().numpy() - truth, axis=1)
