@@ -184,7 +184,7 @@ hipError_t pack_weights(ebsd_cnn* c, hipStream_t s)
 }
 
 hipError_t conv_fwd(ebsd_cnn* c, int l, int n, int H, int W, const bf16_t* x, bf16_t* out, int out_cs,
-                    int out_co, hipStream_t s)
+                    int out_co, hipStream_t s, int mode = 0)
 {
     const LayerDef& d = kLayers[l];
     ConvArgs a;
@@ -197,15 +197,17 @@ hipError_t conv_fwd(ebsd_cnn* c, int l, int n, int H, int W, const bf16_t* x, bf
     a.W = W >> d.lvl;
     a.Cin = d.cinp;
     a.Cout = d.cout;
-    a.mode = 0;
+    a.mode = mode;
     a.out_cs = out_cs;
     a.out_co = out_co;
     return launch_conv3x3(a, s);
 }
 
 // Forward from the packed input x0 (n <= max_batch pairs of H x W) to out
-// [n][H/4][W/4][2].
-hipError_t forward(ebsd_cnn* c, int n, int H, int W, float* out, hipStream_t s)
+// [n][H/4][W/4][2].  infer: the two encoder convolutions whose outputs are
+// only pooled write the pooled activations directly (the training step keeps
+// them for the pooling's backward pass).
+hipError_t forward(ebsd_cnn* c, int n, int H, int W, float* out, hipStream_t s, bool infer = false)
 {
     hipError_t e = pack_weights(c, s);
 #define CK(x)                          \
@@ -215,11 +217,19 @@ hipError_t forward(ebsd_cnn* c, int n, int H, int W, float* out, hipStream_t s)
     } while (0)
     const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
     CK(conv_fwd(c, 0, n, H, W, c->x0, c->a1a, 32, 0, s));
-    CK(conv_fwd(c, 1, n, H, W, c->a1a, c->e1, 32, 0, s));
-    CK(launch_maxpool(c->e1, n, H, W, 32, 32, 0, c->p1, s));
+    if (infer) {
+        CK(conv_fwd(c, 1, n, H, W, c->a1a, c->p1, 32, 0, s, 2));
+    } else {
+        CK(conv_fwd(c, 1, n, H, W, c->a1a, c->e1, 32, 0, s));
+        CK(launch_maxpool(c->e1, n, H, W, 32, 32, 0, c->p1, s));
+    }
     CK(conv_fwd(c, 2, n, H, W, c->p1, c->a2a, 64, 0, s));
-    CK(conv_fwd(c, 3, n, H, W, c->a2a, c->e2, 64, 0, s));
-    CK(launch_maxpool(c->e2, n, H1, W1, 64, 64, 0, c->p2, s));
+    if (infer) {
+        CK(conv_fwd(c, 3, n, H, W, c->a2a, c->p2, 64, 0, s, 2));
+    } else {
+        CK(conv_fwd(c, 3, n, H, W, c->a2a, c->e2, 64, 0, s));
+        CK(launch_maxpool(c->e2, n, H1, W1, 64, 64, 0, c->p2, s));
+    }
     CK(conv_fwd(c, 4, n, H, W, c->p2, c->a3a, 128, 0, s));
     CK(conv_fwd(c, 5, n, H, W, c->a3a, c->cat, kCatC, 256, s));  // e3 = channels 256..383 of cat
     CK(launch_maxpool(c->cat, n, H2, W2, 128, kCatC, 256, c->p3, s));
@@ -342,7 +352,7 @@ int cnn_forward_from(ebsd_cnn* c, const float* ref_base, int64_t ref_stride, con
                              : launch_pack_input(ref_base, ref_stride, ref_slot, test_base, test_stride, n, kRes,
                                                  kRes, c->x0, s);
     if (e != hipSuccess) return EBSD_EDEVICE;
-    return forward(c, n, kRes, kRes, out, s) == hipSuccess ? EBSD_OK : EBSD_EDEVICE;
+    return forward(c, n, kRes, kRes, out, s, true) == hipSuccess ? EBSD_OK : EBSD_EDEVICE;
 }
 
 }  // namespace ebsd
@@ -477,7 +487,7 @@ int ebsd_cnn_forward(ebsd_cnn* c, const float* ref, const float* test, int32_t n
     hipStream_t s = static_cast<hipStream_t>(stream);
     int e = normalize_pack(c, ref, test, n, H, W, s);
     if (e != EBSD_OK) return e;
-    return forward(c, n, H, W, out, s) == hipSuccess ? EBSD_OK : EBSD_EDEVICE;
+    return forward(c, n, H, W, out, s, true) == hipSuccess ? EBSD_OK : EBSD_EDEVICE;
 }
 
 int ebsd_cnn_train_step(ebsd_cnn* c, const float* ref, const float* test, const float* label, int32_t n,

@@ -20,7 +20,8 @@ struct ConvArgs {
     const float* bias; // [Cout] (mode 0)
     void* out;         // mode 0: bf16, mode 1: fp32
     int32_t n, H, W, Cin, Cout;
-    int32_t mode;      // 0: bf16(relu(acc + bias)); 1: fp32 acc (input gradients)
+    int32_t mode;      // 0: bf16(relu(acc + bias)); 1: fp32 acc (input gradients); 2: as 0, then the
+                       // 2 x 2 max-pool (out is [n][H/2][W/2][out_cs], the result of k_maxpool)
     int32_t out_cs;    // channels per output pixel (>= Cout)
     int32_t out_co;    // channel offset of this output inside the output pixel
 };

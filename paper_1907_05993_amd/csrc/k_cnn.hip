@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
 
     // epilogue (the K loop ended with a barrier: LDS is free)
-    if (a.mode == 0) {
+    if (a.mode == 0 || a.mode == 2) {
         constexpr int RP = BN + 8;  // staging row pitch (bf16)
         bf16_t* stg = reinterpret_cast<bf16_t*>(smem) + wave * 64 * RP;
         for (int j = 0; j < NT; j++) {
@@ -177,12 +177,36 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         }
         __syncthreads();
         bf16_t* out = static_cast<bf16_t*>(a.out);
-        for (int v = lane; v < 64 * (BN / 8); v += 64) {
-            const int px = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
-            const int yy = y0 + 2 * wave + (px >> 5), xx = x0 + (px & 31);
-            const int64_t p = ((int64_t)img * a.H + yy) * a.W + xx;
-            *reinterpret_cast<uint4*>(out + p * a.out_cs + a.out_co + co0 + 8 * g) =
-                *reinterpret_cast<const uint4*>(stg + px * RP + 8 * g);
+        if (a.mode == 0) {
+            for (int v = lane; v < 64 * (BN / 8); v += 64) {
+                const int px = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
+                const int yy = y0 + 2 * wave + (px >> 5), xx = x0 + (px & 31);
+                const int64_t p = ((int64_t)img * a.H + yy) * a.W + xx;
+                *reinterpret_cast<uint4*>(out + p * a.out_cs + a.out_co + co0 + 8 * g) =
+                    *reinterpret_cast<const uint4*>(stg + px * RP + 8 * g);
+            }
+        } else {
+            // 2 x 2 max-pool of the wave's two rows (the selection of k_maxpool: first
+            // of the largest in the order (0,0), (0,1), (1,0), (1,1)) into the
+            // half-size output, pooled row y0 / 2 + wave, columns x0 / 2 .. + 15
+            const int Hp = a.H / 2, Wp = a.W / 2;
+            for (int v = lane; v < 16 * (BN / 8); v += 64) {
+                const int q = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
+                const bf16_t* s0 = stg + (2 * q) * RP + 8 * g;
+                const bf16_t* s1 = s0 + RP;
+                const bf16_t* s2 = s0 + 32 * RP;
+                const bf16_t* s3 = s2 + RP;
+                u16x8 o;
+                for (int e = 0; e < 8; e++) {
+                    uint16_t m = s0[e];
+                    if (bf2f(s1[e]) > bf2f(m)) m = s1[e];
+                    if (bf2f(s2[e]) > bf2f(m)) m = s2[e];
+                    if (bf2f(s3[e]) > bf2f(m)) m = s3[e];
+                    o[e] = m;
+                }
+                const int64_t p = ((int64_t)img * Hp + (y0 >> 1) + wave) * Wp + (x0 >> 1) + q;
+                *reinterpret_cast<u16x8*>(out + p * a.out_cs + a.out_co + co0 + 8 * g) = o;
+            }
         }
     } else {
         constexpr int RP = BN + 4;  // staging row pitch (fp32)
