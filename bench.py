@@ -112,6 +112,8 @@ def main():
     d_refs, d_tests, _ = ebsd.gen_pairs(specs, labels=False)
     torch.cuda.synchronize()
     rv_true = np.array([rotvec_of(rotation_of(s.F)) for s in specs])
+    Fiso = np.stack([s.F / np.cbrt(np.linalg.det(s.F)) for s in specs])
+    eps_true = 0.5 * (Fiso @ np.transpose(Fiso, (0, 2, 1)) - np.eye(3))
     log(f"[bench] generated {n} pairs of {H}x{W} on the GPU in {time.time() - t0:.1f} s")
 
     def make(warm, cap, first_pass=0, second_pass=1):
@@ -150,7 +152,14 @@ def main():
         if reg.params.first_pass == 0 and not args.skip_comparison:
             # one more (untimed) call for the structural similarity of the registration
             ssim = reg.register(d_refs, d_tests, want_field=False, want_ssim=True)["ssim"].cpu().numpy()
-        return dict(R_finite=out["R_finite"], ssim=ssim, elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
+        # isochoric strain error of the final and of the first fit: (F F^T - I) / 2 of F / det(F)^(1/3)
+        def strain_err(Fs):
+            Fs = Fs / np.cbrt(np.linalg.det(Fs))[:, None, None]
+            e = 0.5 * (Fs @ np.transpose(Fs, (0, 2, 1)) - np.eye(3))
+            return np.abs(e - eps_true).max(axis=(1, 2))
+        serr = strain_err(out["F"].cpu().numpy())
+        serr1 = strain_err(out["F_first"].cpu().numpy())
+        return dict(R_finite=out["R_finite"], ssim=ssim, serr=serr, serr1=serr1, elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
                     tuned=tuned, fused=fused, err_first=err_first, mae_first=out["mae_first"].cpu().numpy(),
                     mae=out["mae"].cpu().numpy(), ph=out["peak_height"].cpu().numpy().mean(axis=1))
 
@@ -317,8 +326,10 @@ def main():
         def method(r, first, ph=True):
             e = r["err_first"] if first else r["err"]
             m = r["mae_first"] if first else r["mae"]
+            se = r["serr1"] if first else r["serr"]
             d = {"rotation_error_rad": {"median": float(np.median(e)), "p95": float(np.percentile(e, 95))},
-                 "mean_angular_error_rad": {"median": float(np.median(m)), "p95": float(np.percentile(m, 95))}}
+                 "mean_angular_error_rad": {"median": float(np.median(m)), "p95": float(np.percentile(m, 95))},
+                 "strain_error": {"median": float(np.median(se)), "p95": float(np.percentile(se, 95))}}
             if ph:
                 d["peak_height_mean"] = float(np.mean(r["ph"]))
             if first and r.get("ssim") is not None:
