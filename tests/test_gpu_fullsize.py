@@ -89,7 +89,8 @@ def test_scan_map_4096_full_size(E, orc):
 def test_mixed_size_stream_16384(E, orc):
     """c5: 16384 pairs of 128, 256 and 512 px (40/40/20 %, 0-12 deg, strain
     +-2e-3) in three uneven calls of mixed sizes, warm start on (fitted
-    field, fallback at 0.5 px), per-pair stopping at 1e-4 px, 20 ROIs of 32."""
+    field, fallback at 0.5 px), per-pair stopping at 1e-4 px, 20 ROIs of 32;
+    64 sampled pairs against the oracle."""
     import os
     from paper_1907_05993_amd import synth as S
     rng = np.random.default_rng(55)
@@ -130,13 +131,20 @@ def test_mixed_size_stream_16384(E, orc):
         e = err[sizes == N]
         print("N=%d: %d pairs, warm start used %.0f%%, rotation error median %.2e p95 %.2e"
               % (N, e.size, 100 * used[sizes == N].mean(), np.median(e), np.percentile(e, 95)))
-    # sampled pairs of each size against the oracle from the same R_finite
-    for N in (128, 256, 512):
-        idx = list(np.nonzero(sizes == N)[0][[0, 1, -1]])
+    # 64 sampled pairs (26 / 26 / 12 of 128 / 256 / 512 px, seeded) against the oracle from the
+    # same R_finite: the distribution of the deformation-gradient differences
+    rs = np.random.default_rng(56)
+    dFs = []
+    for N, k in ((128, 26), (256, 26), (512, 12)):
+        idx = sorted(rs.choice(np.nonzero(sizes == N)[0], size=k, replace=False).tolist())
         r = np.stack([refs[i].cpu().numpy() for i in idx])
         t = np.stack([tests[i].cpu().numpy() for i in idx])
         op = orc.make_params(levels=3, iters=150, sigma=1.0, tol=1e-4, roi_size=32, n_roi=20)
         o2 = orc.register_batch(r, t, op, rfin=g["R_finite"][idx].cpu().numpy(), want_field=False)
-        dF = np.abs(g["F"][idx].cpu().numpy() - o2["F"]).max()
-        print("N=%d sampled %s: max |dF| from a common R_finite %.2e" % (N, idx, dF))
-        assert dF <= 1e-6
+        d = np.abs(g["F"][idx].cpu().numpy() - o2["F"]).max(axis=(1, 2))
+        print("N=%d, %d sampled pairs: |dF| from a common R_finite median %.1e, max %.1e" % (N, k, np.median(d), d.max()))
+        dFs.append(d)
+    dFs = np.concatenate(dFs)
+    print("64 sampled pairs: |dF| median %.1e, p95 %.1e, max %.1e"
+          % (np.median(dFs), np.percentile(dFs, 95), dFs.max()))
+    assert dFs.max() <= 1e-6
