@@ -45,6 +45,9 @@ class Params(C.Structure):
         ("first_pass", C.c_int32),
         ("bandpass_lo", C.c_double),
         ("bandpass_hi", C.c_double),
+        ("background_static", C.c_int32),
+        ("background_dynamic", C.c_double),
+        ("background", C.c_void_p),
     ]
 
 
@@ -69,7 +72,7 @@ class _Outputs(C.Structure):
 
 def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_roi=20,
                 roi_size=32, roi_radius_frac=0.3, window=1, second_pass=1, remap_interp=3,
-                xcf_passes=1, first_pass=0, bandpass=(0.0, 0.0)):
+                xcf_passes=1, first_pass=0, bandpass=(0.0, 0.0), background=(0, 0.0)):
     p = Params()
     p.levels = levels
     its = [iters] * MAX_LEVELS if np.isscalar(iters) else list(iters) + [0] * (MAX_LEVELS - len(iters))
@@ -87,6 +90,8 @@ def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_r
     p.xcf_passes = xcf_passes
     p.first_pass = first_pass
     p.bandpass_lo, p.bandpass_hi = bandpass
+    p.background_static, p.background_dynamic = int(background[0]), float(background[1])
+    p.background = None
     return p
 
 
@@ -127,6 +132,8 @@ def lib():
         L.orc_solve_F_traction_free.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d, d,
                                                 d, C.c_double, C.c_double, C.c_double, d, d, d]
         L.orc_bandpass.argtypes = [f, C.c_int, C.c_int, C.c_double, C.c_double, d]
+        L.orc_background.argtypes = [f, C.c_int, C.c_int, d, C.c_double, d]
+        L.orc_mean_pattern.argtypes = [f, C.c_int, C.c_int, C.c_int, d]
         L.orc_ssim.restype = C.c_double
         L.orc_ssim.argtypes = [d, d, C.c_int, C.c_int]
         L.orc_mae.restype = C.c_double
@@ -348,6 +355,26 @@ def bandpass(img, lo, hi):
     return out
 
 
+def background(img, bg=None, dyn=0.0):
+    """Background correction of a raw pattern: divided by the static
+    background bg (None = off), then by its own Gaussian blur of sigma dyn."""
+    a = np.ascontiguousarray(img, dtype=np.float32)
+    H, W = a.shape
+    out = np.empty((H, W), np.float64)
+    b = _f64(bg) if bg is not None else None
+    lib().orc_background(_f(a), H, W, _d(b) if b is not None else None, float(dyn), _d(out))
+    return out
+
+
+def mean_pattern(p):
+    """Pixelwise mean of patterns [n, H, W] (the static background)."""
+    a = np.ascontiguousarray(p, dtype=np.float32)
+    n, H, W = a.shape
+    out = np.empty((H, W), np.float64)
+    lib().orc_mean_pattern(_f(a), n, H, W, _d(out))
+    return out
+
+
 def ssim(R, Tw):
     """Mean structural similarity of R and Tw (11 x 11 Gaussian window of
     sigma 1.5, L = 6 for z-scored patterns, pixels whose window fits)."""
@@ -490,6 +517,11 @@ def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None)
     else:
         ui = _f64(u_init)
         used = 1
+        bgm = None
+        if params.background_static and not params.background:
+            # the static background of the whole call, as orc_register_batch forms it
+            bgm = mean_pattern(tests)
+            params.background = bgm.ctypes.data
         for i in range(n):
             oi = _Outputs()
             for k in _OUT_KEYS:
@@ -501,5 +533,7 @@ def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None)
             lib().orc_register_pair(_f(r_i), _f(t_i), H, W, C.byref(params), _d(u_i),
                                     _d(np.ascontiguousarray(rf[i])) if rf is not None else None,
                                     C.byref(oi))
+        if bgm is not None:
+            params.background = None
     out["threads"] = used
     return out

@@ -74,6 +74,10 @@ typedef struct {
     double bandpass_lo;                /* pre-filter: sigma (px) of the low-pass, 0 = off */
     double bandpass_hi;                /* pre-filter: sigma (px) of the background
                                           Gaussian subtracted (high-pass), 0 = off */
+    int32_t background_static;         /* 1 = divide by the static background */
+    double background_dynamic;         /* sigma (px) of the dynamic background, 0 = off */
+    const double* background;          /* static background [H][W]; orc_register_batch
+                                          sets it to the mean of its test patterns */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -301,20 +305,59 @@ void orc_smooth(const double* v, int H, int W, double sigma, double* out)
  * given).  Reading: Gaussian filters, out = G_lo * p - G_hi * p, where G_lo
  * is orc_smooth with sigma lo (identity when lo <= 0) and G_hi * p the
  * background estimate with sigma hi (nothing subtracted when hi <= 0).      */
-void orc_bandpass(const float* in, int H, int W, double lo, double hi, double* out)
+void orc_bandpass_d(const double* p, int H, int W, double lo, double hi, double* out)
 {
     size_t HW = (size_t)H * W;
-    double* p = (double*)malloc(sizeof(double) * HW);
     double* t = (double*)malloc(sizeof(double) * HW);
-    for (size_t i = 0; i < HW; i++) p[i] = (double)in[i];
     if (lo > 0.0) orc_smooth(p, H, W, lo, out);
     else memcpy(out, p, sizeof(double) * HW);
     if (hi > 0.0) {
         orc_smooth(p, H, W, hi, t);
         for (size_t i = 0; i < HW; i++) out[i] -= t[i];
     }
-    free(p);
     free(t);
+}
+
+void orc_bandpass(const float* in, int H, int W, double lo, double hi, double* out)
+{
+    size_t HW = (size_t)H * W;
+    double* p = (double*)malloc(sizeof(double) * HW);
+    for (size_t i = 0; i < HW; i++) p[i] = (double)in[i];
+    orc_bandpass_d(p, H, W, lo, hi, out);
+    free(p);
+}
+
+/* Background correction (section 3.3 applies a dynamic and a static
+ * background correction to the experimental patterns; their forms are not
+ * given).  Reading: static, divide by the scan's mean pattern bg (the
+ * pixelwise mean of the call's test patterns); dynamic, then divide by the
+ * pattern's own Gaussian blur of sigma dyn (orc_smooth).  A non-positive
+ * divisor gives 0.  bg may be NULL, dyn <= 0 turns the dynamic step off.   */
+void orc_background(const float* in, int H, int W, const double* bg, double dyn, double* out)
+{
+    size_t HW = (size_t)H * W;
+    for (size_t i = 0; i < HW; i++) {
+        double v = (double)in[i];
+        if (bg) v = bg[i] > 0.0 ? v / bg[i] : 0.0;
+        out[i] = v;
+    }
+    if (dyn > 0.0) {
+        double* b = (double*)malloc(sizeof(double) * HW);
+        orc_smooth(out, H, W, dyn, b);
+        for (size_t i = 0; i < HW; i++) out[i] = b[i] > 0.0 ? out[i] / b[i] : 0.0;
+        free(b);
+    }
+}
+
+/* Pixelwise mean of n patterns [n][H][W] (the static background). */
+void orc_mean_pattern(const float* p, int n, int H, int W, double* out)
+{
+    size_t HW = (size_t)H * W;
+    for (size_t i = 0; i < HW; i++) {
+        double s = 0.0;
+        for (int k = 0; k < n; k++) s += (double)p[(size_t)k * HW + i];
+        out[i] = s / (double)n;
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1326,13 +1369,18 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
     double* ph = (double*)calloc((size_t)nr, sizeof(double));
     int32_t its[ORC_MAX_LEVELS] = {0};
     uint32_t st = 0;
-    if (p->bandpass_lo > 0.0 || p->bandpass_hi > 0.0) {
+    const double* bg = p->background_static ? p->background : NULL;
+    if (bg || p->background_dynamic > 0.0 || p->bandpass_lo > 0.0 || p->bandpass_hi > 0.0) {
+        /* background correction, then the pre-filter, then the z-score */
         double* f = (double*)malloc(sizeof(double) * HW);
-        orc_bandpass(ref, H, W, p->bandpass_lo, p->bandpass_hi, f);
-        st |= orc_normalize_d(f, (int64_t)HW, Rn);
-        orc_bandpass(test, H, W, p->bandpass_lo, p->bandpass_hi, f);
-        st |= orc_normalize_d(f, (int64_t)HW, Tn);
+        double* g = (double*)malloc(sizeof(double) * HW);
+        for (int k = 0; k < 2; k++) {
+            orc_background(k == 0 ? ref : test, H, W, bg, p->background_dynamic, f);
+            orc_bandpass_d(f, H, W, p->bandpass_lo, p->bandpass_hi, g);
+            st |= orc_normalize_d(g, (int64_t)HW, k == 0 ? Rn : Tn);
+        }
         free(f);
+        free(g);
     } else {
         st |= orc_normalize(ref, (int64_t)HW, Rn);
         st |= orc_normalize(test, (int64_t)HW, Tn);
@@ -1446,6 +1494,14 @@ int orc_register_batch(const float* refs, const float* tests, int n, int H, int 
     size_t HW = (size_t)H * W;
     int nr = p->n_roi;
     int used = 1;
+    orc_params pb = *p;
+    double* bgm = NULL;
+    if (p->background_static && !p->background) {
+        bgm = (double*)malloc(sizeof(double) * HW);
+        orc_mean_pattern(tests, n, H, W, bgm);
+        pb.background = bgm;
+    }
+    p = &pb;
 #pragma omp parallel
     {
 #ifdef _OPENMP
@@ -1473,5 +1529,6 @@ int orc_register_batch(const float* refs, const float* tests, int n, int H, int 
                               rfin_in ? rfin_in + (size_t)i * 9 : NULL, &oi);
         }
     }
+    free(bgm);
     return used;
 }

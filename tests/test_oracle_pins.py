@@ -545,6 +545,30 @@ def test_highpass_removes_a_linear_background(orc):
     np.testing.assert_allclose(a[r:-r, r:-r], b[r:-r, r:-r], atol=2e-6)  # float32 input rounding
 
 
+def test_background_correction(orc):
+    r = rng(72)
+    H, W = 30, 44
+    y, x = np.mgrid[0:H, 0:W]
+    vignette = 1.0 + 0.5 * np.exp(-((x - 20.0) ** 2 + (y - 12.0) ** 2) / 300.0)
+    s = 1.0 + 0.2 * np.abs(r.normal(size=(5, H, W)))
+    scan = (s * vignette).astype(np.float32)
+    # the mean pattern is the pixelwise mean
+    np.testing.assert_allclose(orc.mean_pattern(scan), scan.astype(np.float64).mean(axis=0), rtol=1e-13)
+    # static: dividing by the scan's mean removes a common multiplicative profile
+    bg = orc.mean_pattern(scan)
+    sd = scan.astype(np.float64)
+    expect = sd / (sd.mean(axis=0))
+    for i in range(5):
+        np.testing.assert_allclose(orc.background(scan[i], bg), expect[i], rtol=1e-12)
+    # dynamic: the pattern over its own Gaussian blur (scipy's filter, radius int(3 sigma + 0.5))
+    g = ndi.gaussian_filter(sd[0], 4.0, truncate=3.0, mode="nearest")
+    np.testing.assert_allclose(orc.background(scan[0], None, 4.0), sd[0] / g, rtol=1e-12)
+    # both, in that order; a constant pattern becomes exactly 1 under the dynamic step
+    g2 = ndi.gaussian_filter(expect[1], 4.0, truncate=3.0, mode="nearest")
+    np.testing.assert_allclose(orc.background(scan[1], bg, 4.0), expect[1] / g2, rtol=1e-12)
+    np.testing.assert_allclose(orc.background(np.full((9, 9), 7.0, np.float32), None, 2.0), 1.0, atol=2e-15)
+
+
 # -- structural similarity of the registration (section 3's SSIM) -----------------------------
 
 def _ssim_scipy(a, b, L=6.0):
