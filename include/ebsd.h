@@ -110,6 +110,12 @@ typedef struct ebsd_params {
                                              <= 32; the filtered pattern is G_lo * p - G_hi * p (taps
                                              exp(-j^2 / 2 sigma^2), |j| <= floor(3 sigma + 0.5), unit sum,
                                              replicated border) */
+    int32_t background_static;            /* background correction before the pre-filter (section 3.3):
+                                             1 = divide every raw pattern by the static background, the
+                                             pixelwise mean of the size bucket's test patterns; 0 = off */
+    float background_dynamic_px;          /* then divide by the pattern's own Gaussian blur of this sigma
+                                             (the pre-filter's taps; 0 = off, <= 32); a non-positive
+                                             divisor gives 0 */
 } ebsd_params;
 
 /* One scan point.  ref/test: device pointers to H x W fp32 patterns.  Pairs

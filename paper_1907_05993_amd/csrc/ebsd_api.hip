@@ -173,6 +173,8 @@ int check_params(const ebsd_params* p)
     if (p->first_pass == 1 && p->warm_start != 0) return EBSD_EINVAL;
     if (!(p->bandpass_lo_px >= 0.0f && p->bandpass_lo_px <= 32.0f)) return EBSD_EINVAL;
     if (!(p->bandpass_hi_px >= 0.0f && p->bandpass_hi_px <= 32.0f)) return EBSD_EINVAL;
+    if (p->background_static != 0 && p->background_static != 1) return EBSD_EINVAL;
+    if (!(p->background_dynamic_px >= 0.0f && p->background_dynamic_px <= 32.0f)) return EBSD_EINVAL;
     return EBSD_OK;
 }
 
@@ -429,8 +431,13 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const size_t o_rv = w.take(sizeof(double) * 3 * nb);
     const size_t o_st = w.take(sizeof(uint32_t) * nb);
     const size_t o_mae = w.take(sizeof(double) * 2 * nb);
-    const bool prefilter = p.bandpass_lo_px > 0.0f || p.bandpass_hi_px > 0.0f;
-    const size_t o_pf = w.take(prefilter ? sizeof(float) * 2 * (size_t)(nb + nref) * H * W : 0);
+    const bool bandpass = p.bandpass_lo_px > 0.0f || p.bandpass_hi_px > 0.0f;
+    const bool bg_static = p.background_static != 0, bg_dyn = p.background_dynamic_px > 0.0f;
+    const bool prefilter = bandpass || bg_static || bg_dyn;
+    const size_t npat_hw = (size_t)(nb + nref) * H * W;
+    const size_t o_pf = w.take(prefilter ? sizeof(float) * 2 * npat_hw : 0);  // band row sums
+    const size_t o_blur = w.take(bg_dyn ? sizeof(float) * npat_hw : 0);       // dynamic background
+    const size_t o_bgs = w.take(bg_static ? sizeof(float) * (size_t)H * W : 0);  // static background
     const bool want_ssim = mode == Mode::Full && p.first_pass == 0 && out->ssim && !tune_only &&
                            ssim_tiles(H, W) > 0;
     const size_t o_ssim = w.take(want_ssim ? sizeof(double) * (size_t)nb * (1 + ssim_tiles(H, W)) : 0);
@@ -550,12 +557,12 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const bool tm = h->timing && mode == Mode::Full;
     if (tm) EBSD_TRY(hipEventRecord(h->ev[0], s));
     if (prefilter) {
-        // pre-filtered raw patterns into level 0, normalised there in place
+        // background-corrected, pre-filtered raw patterns into level 0, normalised
+        // there in place: static background, dynamic background, band-pass
         BandIO io;
+        std::memset(&io, 0, sizeof io);
         io.src_a = b.test_in;
         io.src_b = b.ref_in;
-        io.src = nullptr;
-        io.src_stride = 0;
         io.dst_a = b.test_pyr;
         io.dst_b = b.ref_pyr;
         io.dst_stride = pe;
@@ -564,7 +571,26 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         io.H = H;
         io.W = W;
         io.tmp = reinterpret_cast<float*>(base + o_pf);
-        EBSD_TRY(launch_bandpass(io, make_band_taps(p.bandpass_lo_px, p.bandpass_hi_px), s));
+        float* bgs = bg_static ? reinterpret_cast<float*>(base + o_bgs) : nullptr;
+        if (bg_static) EBSD_TRY(launch_mean_pattern(b.test_in, nb, (int64_t)H * W, bgs, s));
+        EBSD_TRY(launch_bg_static(io, bgs, s));  // a copy into level 0 without the static step
+        // from here on level 0 is the source
+        BandIO lv = io;
+        lv.src_a = nullptr;
+        lv.src_b = nullptr;
+        lv.srcb_a = b.test_pyr;
+        lv.srcb_b = b.ref_pyr;
+        lv.srcb_stride = pe;
+        if (bg_dyn) {
+            float* blur = reinterpret_cast<float*>(base + o_blur);
+            BandIO bl = lv;  // the blur of every pattern into a contiguous buffer
+            bl.dst_a = blur;
+            bl.dst_b = blur + (size_t)nb * H * W;
+            bl.dst_stride = (int64_t)H * W;
+            EBSD_TRY(launch_bandpass(bl, make_band_taps(p.background_dynamic_px, 0.0), s));
+            EBSD_TRY(launch_bg_dynamic(lv, blur, s));
+        }
+        if (bandpass) EBSD_TRY(launch_bandpass(lv, make_band_taps(p.bandpass_lo_px, p.bandpass_hi_px), s));
     }
     EBSD_TRY(launch_stats(d_bk, nb, nref, s));
     EBSD_TRY(launch_pyramids(d_bk, b, s));
@@ -822,6 +848,8 @@ int ebsd_params_default(ebsd_params* p)
     p->first_pass = 0;
     p->bandpass_lo_px = 0.0f;
     p->bandpass_hi_px = 0.0f;
+    p->background_static = 0;
+    p->background_dynamic_px = 0.0f;
     return EBSD_OK;
 }
 
@@ -1064,8 +1092,7 @@ int ebsd_stage_bandpass(const float* in, int32_t n, int32_t H, int32_t W, float 
     DevBuf tmp;
     if (hipMalloc(&tmp.p, sizeof(float) * 2 * (size_t)n * H * W) != hipSuccess) return EBSD_ENOMEM;
     BandIO io;
-    io.src_a = nullptr;
-    io.src_b = nullptr;
+    std::memset(&io, 0, sizeof io);
     io.src = in;
     io.src_stride = (int64_t)H * W;
     io.dst_a = out;

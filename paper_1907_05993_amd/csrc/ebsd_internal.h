@@ -172,6 +172,11 @@ struct BandIO {
     const float* const* src_b;
     const float* src;
     int64_t src_stride;
+    // src == NULL and src_a == NULL: pattern p reads srcb_a + p srcb_stride (p < na)
+    // or srcb_b + (p - na) srcb_stride (in place over a pyramid's level 0, say)
+    const float* srcb_a;
+    const float* srcb_b;
+    int64_t srcb_stride;
     float* dst_a;
     float* dst_b;
     int64_t dst_stride;
@@ -180,6 +185,12 @@ struct BandIO {
 };
 BandTaps make_band_taps(double lo, double hi);
 hipError_t launch_bandpass(const BandIO& io, const BandTaps& tp, hipStream_t s);
+// Background correction: bg [H][W] = pixelwise mean of the nb patterns src_a[0..nb)
+// (the static background); dst(p) = src(p) / bg (bg == NULL: a copy); dst(p) /=
+// blur + p H W (the dynamic step, in place).  A non-positive divisor gives 0.
+hipError_t launch_mean_pattern(const float* const* src, int nb, int64_t hw, float* bg, hipStream_t s);
+hipError_t launch_bg_static(const BandIO& io, const float* bg, hipStream_t s);
+hipError_t launch_bg_dynamic(const BandIO& io, const float* blur, hipStream_t s);
 // Structural similarity of the normalised reference and the test warped by the
 // final field (11 x 11 Gaussian window, sigma 1.5; L = 6) -> bk->ssim, via
 // per-tile sums in bk->ssim_part.

@@ -255,7 +255,52 @@ __global__ void k_sample_q1(const Bucket* __restrict__ bk)
 // column sums combined into the destination.
 __device__ inline const float* band_src(const BandIO& io, int p)
 {
-    return io.src ? io.src + (int64_t)p * io.src_stride : (p < io.na ? io.src_a[p] : io.src_b[p - io.na]);
+    if (io.src) return io.src + (int64_t)p * io.src_stride;
+    if (io.src_a) return p < io.na ? io.src_a[p] : io.src_b[p - io.na];
+    return p < io.na ? io.srcb_a + (int64_t)p * io.srcb_stride : io.srcb_b + (int64_t)(p - io.na) * io.srcb_stride;
+}
+
+__device__ inline float* band_dst(const BandIO& io, int p)
+{
+    return p < io.na ? io.dst_a + (int64_t)p * io.dst_stride : io.dst_b + (int64_t)(p - io.na) * io.dst_stride;
+}
+
+// static background: pixelwise mean of the nb patterns (double sums in order)
+__global__ void k_mean_pattern(const float* const* __restrict__ src, int nb, int64_t hw, float* __restrict__ bg)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hw; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < nb; k++) s += (double)src[k][i];
+        bg[i] = (float)(s / (double)nb);
+    }
+}
+
+__global__ void k_bg_static(BandIO io, const float* __restrict__ bg)
+{
+    const int p = blockIdx.y;
+    const int64_t hw = (int64_t)io.H * io.W;
+    const float* __restrict__ src = band_src(io, p);
+    float* dst = band_dst(io, p);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hw; i += (int64_t)gridDim.x * blockDim.x) {
+        float v = src[i];
+        if (bg) {
+            const float d = bg[i];
+            v = d > 0.0f ? v / d : 0.0f;
+        }
+        dst[i] = v;
+    }
+}
+
+__global__ void k_bg_dynamic(BandIO io, const float* __restrict__ blur)
+{
+    const int p = blockIdx.y;
+    const int64_t hw = (int64_t)io.H * io.W;
+    float* dst = band_dst(io, p);
+    const float* __restrict__ b = blur + (int64_t)p * hw;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hw; i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = b[i];
+        dst[i] = d > 0.0f ? dst[i] / d : 0.0f;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_band_rows(BandIO io, BandTaps tp)
@@ -288,8 +333,8 @@ __global__ void __launch_bounds__(256) k_band_cols(BandIO io, BandTaps tp)
     const int64_t HW = (int64_t)H * W;
     const float* __restrict__ tlo = io.tmp + (2 * (int64_t)p) * HW;
     const float* __restrict__ thi = tlo + HW;
-    const float* __restrict__ src = band_src(io, p);
-    float* dst = p < io.na ? io.dst_a + (int64_t)p * io.dst_stride : io.dst_b + (int64_t)(p - io.na) * io.dst_stride;
+    const float* src = band_src(io, p);  // may be dst (in place): read before the write of each element
+    float* dst = band_dst(io, p);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < HW; t += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(t / W), x = (int)(t - (int64_t)W * (t / W));
         float v;
@@ -522,6 +567,29 @@ hipError_t launch_bandpass(const BandIO& io, const BandTaps& tp, hipStream_t s)
     hipLaunchKernelGGL(k_band_rows, dim3((unsigned)io.H, (unsigned)io.npat), dim3(256), lds, s, io, tp);
     hipLaunchKernelGGL(k_band_cols, dim3(grid_for((int64_t)io.H * io.W, 256), (unsigned)io.npat), dim3(256), 0, s,
                        io, tp);
+    return hipGetLastError();
+}
+
+hipError_t launch_mean_pattern(const float* const* src, int nb, int64_t hw, float* bg, hipStream_t s)
+{
+    if (nb <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mean_pattern, dim3(grid_for(hw, 4096)), dim3(256), 0, s, src, nb, hw, bg);
+    return hipGetLastError();
+}
+
+hipError_t launch_bg_static(const BandIO& io, const float* bg, hipStream_t s)
+{
+    if (io.npat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bg_static, dim3(grid_for((int64_t)io.H * io.W, 256), (unsigned)io.npat), dim3(256), 0, s,
+                       io, bg);
+    return hipGetLastError();
+}
+
+hipError_t launch_bg_dynamic(const BandIO& io, const float* blur, hipStream_t s)
+{
+    if (io.npat <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bg_dynamic, dim3(grid_for((int64_t)io.H * io.W, 256), (unsigned)io.npat), dim3(256), 0, s,
+                       io, blur);
     return hipGetLastError();
 }
 

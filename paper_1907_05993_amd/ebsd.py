@@ -58,6 +58,8 @@ class CParams(C.Structure):
         ("first_pass", C.c_int32),
         ("bandpass_lo_px", C.c_float),
         ("bandpass_hi_px", C.c_float),
+        ("background_static", C.c_int32),
+        ("background_dynamic_px", C.c_float),
     ]
 
 
@@ -217,6 +219,7 @@ class Params:
     xcf_passes: int = 1
     first_pass: int = 0
     bandpass: tuple = (0.0, 0.0)   # pre-filter sigmas (low-pass, background), px; 0 = off
+    background: tuple = (0, 0.0)   # background correction: (static 0/1, dynamic sigma px)
 
     def to_c(self):
         p = CParams()
@@ -240,6 +243,7 @@ class Params:
         p.xcf_passes = self.xcf_passes
         p.first_pass = self.first_pass
         p.bandpass_lo_px, p.bandpass_hi_px = (float(v) for v in self.bandpass)
+        p.background_static, p.background_dynamic_px = int(self.background[0]), float(self.background[1])
         return p
 
 

@@ -74,3 +74,32 @@ def test_whole_path_with_prefilter(E, orc, iters, strict):
     g0 = E.Registrar(E.Params(levels=3, iters=(iters,) * 3, roi_size=64)).register(cuda(refs), cuda(tests))
     torch.cuda.synchronize()
     assert np.abs(g0["field"].cpu().numpy() - gf).max() > 1e-3
+
+
+@pytest.mark.parametrize("background", [(1, 0.0), (0, 8.0), (1, 8.0)])
+def test_whole_path_with_background_correction(E, orc, background):
+    """A batch whose patterns share a strong multiplicative vignette: static
+    (the bucket's mean test pattern) and dynamic (own blur) background
+    correction ahead of the pre-filter, against the oracle (5 iterations per
+    level: field RMS 1e-3 px; F from a common R_finite 1e-6)."""
+    from paper_1907_05993_amd import synth as S
+    specs = S.workload_specs("batch_256", n=4)
+    refs, tests = S.render_batch(specs)
+    y, x = np.mgrid[0:256, 0:256]
+    vig = (1.0 + 0.6 * np.exp(-((x - 100.0) ** 2 + (y - 150.0) ** 2) / 8000.0)).astype(np.float32)
+    refs, tests = refs * vig, tests * vig
+    print(f"whole path with background correction {background} and the pre-filter (1, 12)", flush=True)
+    gp = E.Params(levels=3, iters=(5, 5, 5), roi_size=64, bandpass=(1.0, 12.0), background=background)
+    op = orc.make_params(levels=3, iters=5, roi_size=64, n_roi=20, bandpass=(1.0, 12.0), background=background)
+    g = E.Registrar(gp).register(cuda(refs), cuda(tests))
+    torch.cuda.synchronize()
+    o = orc.register_batch(refs, tests, op)
+    gf = g["field"].cpu().numpy()
+    for i in range(4):
+        rms = float(np.sqrt(((gf[i] - o["field"][i]) ** 2).sum(0).mean()))
+        print("  pair %d: field RMS diff %.1e px" % (i, rms))
+        assert rms <= 1e-3
+    o2 = orc.register_batch(refs, tests, op, rfin=g["R_finite"].cpu().numpy(), want_field=False)
+    dF = np.abs(g["F"].cpu().numpy() - o2["F"]).max()
+    print("  from the GPU's R_finite: max |dF| %.2e" % dF)
+    assert dF <= 1e-6
