@@ -75,7 +75,11 @@ def main():
     ap.add_argument("--paper-pairs", type=int, default=256,
                     help="pairs of the paper's own workload (1244 x 1024, 7 levels x 25) to time (0 = skip)")
     ap.add_argument("--skip-comparison", action="store_true",
-                    help="skip the conventional-first-pass comparison (section 3's four methods)")
+                    help="skip the conventional-first-pass comparison (section 3's four methods) and the "
+                         "iterations-to-tolerance runs")
+    ap.add_argument("--stop-tols", default="0.1,0.05",
+                    help="tolerances (full-res px) at which iterations-to-tolerance are reported, warm and plain "
+                         "('' = skip)")
     ap.add_argument("--latency-reps", type=int, default=20,
                     help="also time the single-pair configuration (128^2, 3 x 100) this many times (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -116,8 +120,9 @@ def main():
     eps_true = 0.5 * (Fiso @ np.transpose(Fiso, (0, 2, 1)) - np.eye(3))
     log(f"[bench] generated {n} pairs of {H}x{W} on the GPU in {time.time() - t0:.1f} s")
 
-    def make(warm, cap, first_pass=0, second_pass=1):
-        p = ebsd.Params(levels=3, iters=(cap,) * 3, sigma_px=1.0, tol_px=args.tol, roi_size=w["roi"], n_roi=20,
+    def make(warm, cap, first_pass=0, second_pass=1, tol=None):
+        p = ebsd.Params(levels=3, iters=(cap,) * 3, sigma_px=1.0, tol_px=args.tol if tol is None else tol,
+                        roi_size=w["roi"], n_roi=20,
                         warm_start=2 if warm else 0, fallback_residual_px=args.fallback,
                         first_pass=first_pass, second_pass=second_pass)
         reg = ebsd.Registrar(p, device=0)
@@ -127,7 +132,7 @@ def main():
         reg.set_resident(not args.no_resident)
         return reg
 
-    def timed(reg, label, tune=True):
+    def timed(reg, label, tune=True, extras=True):
         # strip heights per level, outside the timed region
         tuned = reg.autotune(d_refs, d_tests) if tune else {}
         fused = reg.fused_heights(H, W)
@@ -149,7 +154,7 @@ def main():
         err_first = np.linalg.norm(np.stack([rotvec_of(r) for r in rf]) - rv_true, axis=1)
         log(f"[bench] {label}: {args.steps} steps in {el:.3f} s, median rotation error {np.median(err):.2e} rad")
         ssim = None
-        if reg.params.first_pass == 0 and not args.skip_comparison:
+        if reg.params.first_pass == 0 and not args.skip_comparison and extras:
             # one more (untimed) call for the structural similarity of the registration
             ssim = reg.register(d_refs, d_tests, want_field=False, want_ssim=True)["ssim"].cpu().numpy()
         # isochoric strain error of the final and of the first fit: (F F^T - I) / 2 of F / det(F)^(1/3)
@@ -171,6 +176,12 @@ def main():
     xcf_c = None if args.skip_comparison else timed(make(False, args.cap, first_pass=1), "XCF first pass", tune=False)
     xcf_a = None if args.skip_comparison else timed(make(False, args.cap, first_pass=1, second_pass=0),
                                                    "XCF only", tune=False)
+    # iterations to a tolerance that stops pairs (the configured 1e-4 px stops none on these
+    # noisy patterns), with and without the warm start
+    stop = {}
+    for tol in ([] if args.skip_comparison else [float(x) for x in args.stop_tols.split(",") if x.strip()]):
+        stop[tol] = {m: timed(make(m == "warm", args.cap, tol=tol), f"{m}, tolerance {tol} px", extras=False)
+                     for m in ("warm", "plain")}
 
     # the ROI cross-correlation core alone (ebsd_stage_xcf: window, FFTs, product, inverse FFT,
     # peak fit) on the batch's 20 ROIs per pair, and the whole second pass from the warm run's
@@ -322,6 +333,16 @@ def main():
     }
     if short is not None:
         rec["warm_short_cap"] = dict(summary(short), cap=args.short_cap)
+    if stop:
+        def stopped(r):
+            d = summary(r)
+            d["median_iters_per_level"] = [float(x) for x in np.median(r["iters"], axis=0)]
+            d["at_cap_per_level"] = [round(float(x), 4) for x in (r["iters"] >= args.cap).mean(axis=0)]
+            return d
+        rec["iters_to_tolerance"] = {
+            "levels": "finest first; iterations of each level until 2^level x RMS update < tolerance, cap "
+                      + str(args.cap),
+            **{f"{tol:g}px": {m: stopped(r) for m, r in v.items()} for tol, v in stop.items()}}
     if xcf_c is not None:
         def method(r, first, ph=True):
             e = r["err_first"] if first else r["err"]

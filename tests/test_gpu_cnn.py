@@ -299,7 +299,10 @@ def test_trained_network_gain(E):
     against the generator's ground truth at least five-fold at the same
     iteration budget (3 x 150), falls back on at most 10% of the pairs, and
     with 3 x 10 iterations is still at least five-fold more accurate than the
-    plain method with 3 x 150."""
+    plain method with 3 x 150.  At a tolerance that stops pairs (0.1 px; the
+    configured 1e-4 px stops none on these noisy patterns) the warm start
+    needs at most 0.7 times the plain method's mean iterations over the three
+    levels, and is again five-fold more accurate."""
     import os
     from paper_1907_05993_amd import synth as S
     print("case: trained network gain", flush=True)
@@ -317,8 +320,8 @@ def test_trained_network_gain(E):
             errs.append(np.linalg.norm(rv - wv * th / np.linalg.norm(wv)))
         return np.array(errs)
 
-    def run(warm, cap):
-        p = E.Params(levels=3, iters=(cap,) * 3, sigma_px=1.0, tol_px=1e-4, roi_size=64, n_roi=20,
+    def run(warm, cap, tol=1e-4):
+        p = E.Params(levels=3, iters=(cap,) * 3, sigma_px=1.0, tol_px=tol, roi_size=64, n_roi=20,
                      warm_start=2 if warm else 0, fallback_residual_px=0.5)
         reg = E.Registrar(p)
         if warm:
@@ -336,6 +339,14 @@ def test_trained_network_gain(E):
     assert fb <= 12
     assert np.median(e_warm) * 5 <= np.median(e_plain)
     assert np.median(e_short) * 5 <= np.median(e_plain)
+    tp, e_tp = run(False, 150, tol=0.1)
+    tw, e_tw = run(True, 150, tol=0.1)
+    ip = tp["iters"].cpu().numpy().astype(np.float64)
+    iw = tw["iters"].cpu().numpy().astype(np.float64)
+    print("iterations to 0.1 px (mean per level, finest first): plain %s, warm %s; median error plain %.2e, "
+          "warm %.2e rad" % (ip.mean(0).round(1), iw.mean(0).round(1), np.median(e_tp), np.median(e_tw)))
+    assert iw.sum(1).mean() <= 0.7 * ip.sum(1).mean()
+    assert np.median(e_tw) * 5 <= np.median(e_tp)
 
 
 def test_warm_start_needs_a_model_and_a_supported_size(E):
