@@ -157,13 +157,9 @@ __global__ void __launch_bounds__(kResThreads)
 template <int RAD>
 hipError_t launch_rad(const Bucket* d_bk, int nb, int level, const Taps& tp, float tol, int cap, hipStream_t s)
 {
-    static bool attr_set = false;  // a host attribute, set once (not a stream operation)
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_demons_resident<RAD>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResLdsBytes);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> attr_done{0};
+    const hipError_t e = ensure_dynamic_lds((const void*)k_demons_resident<RAD>, (int)kResLdsBytes, attr_done);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_demons_resident<RAD>, dim3((unsigned)nb), dim3(kResThreads), kResLdsBytes, s, d_bk, level,
                        tp, tol, cap);
     return hipGetLastError();

@@ -228,13 +228,10 @@ hipError_t launch_coef_images(const float* src, int64_t src_stride, int n, int H
     const int nr = std::max(1, std::min(kCoefRows, kCoefLdsWords / (2 * (W + 1))));
     if (2 * nr * (W + 1) > kCoefLdsWords) return hipErrorInvalidValue;  // rows longer than 20479 samples
     const size_t lds = sizeof(float) * 2 * nr * (size_t)(W + 1);
-    static bool attr_set = false;  // a host attribute, set once (not a stream operation)
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_bspline_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(sizeof(float) * kCoefLdsWords));
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> attr_done{0};
+    const hipError_t e =
+        ensure_dynamic_lds((const void*)k_bspline_rows, (int)(sizeof(float) * kCoefLdsWords), attr_done);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bspline_rows, dim3((unsigned)((H + nr - 1) / nr), (unsigned)n), dim3(256), lds, s, src,
                        src_stride, tmp, H, W, nr);
     hipLaunchKernelGGL(k_bspline_cols, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, s, tmp, dst, n, H, W);
@@ -570,13 +567,9 @@ template <int N, int INTERP>
 hipError_t launch_pairs_n(const Bucket* d_bk, int blocks, int window, int pass, hipStream_t s)
 {
     const size_t sm = sizeof(XcfShared<N>);
-    static bool attr_set = false;  // a host attribute, set once (not a stream operation)
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_xcf_pairs<N, INTERP>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> attr_done{0};
+    const hipError_t e = ensure_dynamic_lds((const void*)k_xcf_pairs<N, INTERP>, (int)sm, attr_done);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_xcf_pairs<N, INTERP>), dim3(blocks), dim3(NT), sm, s, d_bk, window, pass);
     return hipGetLastError();
 }
@@ -598,8 +591,8 @@ hipError_t launch_stage_n(const float* A, const float* B, int n, int window, flo
                           hipStream_t s)
 {
     const size_t sm = sizeof(XcfShared<N>);
-    hipError_t e = hipFuncSetAttribute((const void*)k_xcf_stage<N>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    static std::atomic<uint64_t> attr_done{0};
+    const hipError_t e = ensure_dynamic_lds((const void*)k_xcf_stage<N>, (int)sm, attr_done);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_xcf_stage<N>, dim3(n), dim3(NT), sm, s, A, B, window, q, ph);
     return hipGetLastError();
