@@ -63,3 +63,38 @@ def test_resident_tolerance_matches_oracle(E, orc):
         print("  iterations GPU", g["iters"].tolist(), "oracle", o["iters"].tolist())
         assert np.array_equal(g["iters"], o["iters"])
         assert np.array_equal(g["status"].astype(np.uint32), o["status"])
+
+
+def test_resident_bucket_boundary_and_shared_references(E):
+    """The resident levels serve buckets of at most 256 pairs: 257 pairs of
+    128 px in one call (every level on the row kernels) against the same pairs
+    as 256 + 1 (levels of 64 and 32 px resident), with references shared in
+    groups of three (one pyramid per distinct reference) and a tolerance that
+    stops some pairs early.  Fields, iteration counts, status and F agree bit
+    for bit, except where a stop decision sits within rounding of the
+    tolerance (the two paths sum the squared update in different orders):
+    then only that pair's counts may differ by one, and there are none here."""
+    from paper_1907_05993_amd import synth as S
+    n = 257
+    specs = S.workload_specs("single_128", n=n)
+    ref, test, _ = E.gen_pairs(specs, labels=False)
+    ref_ids = [i // 3 for i in range(n)]
+    refs = [ref[3 * (i // 3)] for i in range(n)]
+    tests = [test[i] for i in range(n)]
+    p = E.Params(levels=3, iters=(60,) * 3, sigma_px=1.0, tol_px=0.05, roi_size=32)
+    print(f"resident bucket boundary: {n} pairs of 128 px, references shared in threes", flush=True)
+
+    def call(lo, hi):
+        reg = E.Registrar(p)
+        g = reg.register(refs[lo:hi], tests[lo:hi], ref_ids=ref_ids[lo:hi])
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in g.items() if torch.is_tensor(v)}
+
+    whole = call(0, n)
+    parts = [call(0, 256), call(256, n)]
+    split = {k: np.concatenate([parts[0][k], parts[1][k]]) for k in whole}
+    print("  mean iterations per level", whole["iters"].mean(axis=0).round(2).tolist(),
+          "stopped early", int((whole["iters"] < 60).any(axis=1).sum()))
+    assert (whole["iters"] < 60).any()
+    for k in ("field", "iters", "status", "F", "q1", "q2"):
+        assert np.array_equal(whole[k], split[k]), k
