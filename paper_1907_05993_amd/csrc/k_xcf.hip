@@ -9,8 +9,9 @@
 //            coefficients from k_bspline_rows / k_bspline_cols) or bilinearly, and test ROI,
 //            packed as z = a + i b (one complex FFT serves both);
 //   window   per-ROI mean removed, symmetric Hann window h (x) h;
-//   FFT      2-D radix-2 in LDS: decimation-in-frequency forward (natural in,
-//            bit-reversed out), so no explicit permutation is needed;
+//   FFT      2-D radix-2 in LDS, three stages per pass in registers:
+//            decimation-in-frequency forward (natural in, bit-reversed out),
+//            so no explicit permutation is needed;
 //   product  P(k) = B(k) conj A(k) with A = (Z(k) + conj Z(-k))/2 and
 //            B = (Z(k) - conj Z(-k))/(2i), computed in the bit-reversed domain;
 //   inverse  decimation-in-time (bit-reversed in, natural out), scaled 1/N^2;
@@ -288,75 +289,92 @@ __device__ inline void block_sum4(float v[4], float (*red)[NT / 64], int k)
     __syncthreads();
 }
 
-template <int N>
-__device__ void fft_rows_dif(XcfShared<N>& S)
+// Radix-2 butterflies, up to three stages per pass held in registers: a pass
+// takes the stages of half-size s, 2s, .., s 2^(R-1) (s = 2^SL); each task owns
+// the 2^R elements base + m s of one row (ROWS) or column, base = g 2^R s + t,
+// t < s.  Every butterfly is the one the stage-by-stage transform computes
+// (same operands, same twiddle tw[(i0 mod h) N / 2h]), so the values are
+// those of one LDS pass per stage, with a third of the LDS traffic and
+// barriers.  Forward: decimation in frequency (stages from N/2 down to 1);
+// inverse: decimation in time with conjugate twiddles (from 1 up to N/2).
+// Consecutive threads take consecutive lines, so a wavefront's accesses of
+// one element fall in distinct banks (row pitch N + 1) or are contiguous.
+template <int N, bool DIF, bool ROWS, int SL, int R>
+__device__ void fft_pass(XcfShared<N>& S)
 {
-    for (int h = N / 2; h >= 1; h >>= 1) {
-        const int step = N / (2 * h);
-        for (int c = threadIdx.x; c < N * N / 2; c += NT) {
-            const int row = c / (N / 2), j = c - row * (N / 2);
-            const int t = j & (h - 1), g = j / h;
-            const int i0 = g * 2 * h + t, i1 = i0 + h;
-            float2 a = S.z[row][i0], b = S.z[row][i1];
-            S.z[row][i0] = make_float2(a.x + b.x, a.y + b.y);
-            S.z[row][i1] = cmul(make_float2(a.x - b.x, a.y - b.y), S.tw[t * step]);
+    constexpr int s = 1 << SL, M = 1 << R, span = M * s;
+    constexpr int per_line = N / M;
+    for (int c = threadIdx.x; c < N * per_line; c += NT) {
+        const int line = c % N, k = c / N;
+        const int t = k % s, g = k / s;
+        const int base = g * span + t;
+        float2 v[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) v[m] = ROWS ? S.z[line][base + m * s] : S.z[base + m * s][line];
+        // every loop below is unrolled: stage sizes and element indices are constants
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int e = DIF ? R - 1 - r : r;
+            const int hs = 1 << e;  // h / s
+            const int h = hs * s;
+            const int step = N / (2 * h);
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                if (m & hs) continue;
+                const float2 w = S.tw[(t + (m * s) % h) * step];
+                const float2 a = v[m];
+                if (DIF) {
+                    const float2 b = v[m + hs];
+                    v[m] = make_float2(a.x + b.x, a.y + b.y);
+                    v[m + hs] = cmul(make_float2(a.x - b.x, a.y - b.y), w);
+                } else {
+                    const float2 b = cmulc(v[m + hs], w);
+                    v[m] = make_float2(a.x + b.x, a.y + b.y);
+                    v[m + hs] = make_float2(a.x - b.x, a.y - b.y);
+                }
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            if (ROWS) S.z[line][base + m * s] = v[m];
+            else S.z[base + m * s][line] = v[m];
+        }
     }
+    __syncthreads();
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// Forward stages E .. 0 (half-size 2^E down to 1), three per pass.
+template <int N, bool ROWS, int E>
+__device__ void fft_dif_from(XcfShared<N>& S)
+{
+    constexpr int R = E + 1 < 3 ? E + 1 : 3;
+    fft_pass<N, true, ROWS, E - R + 1, R>(S);
+    if constexpr (E - R >= 0) fft_dif_from<N, ROWS, E - R>(S);
+}
+
+// Inverse stages E .. log2(N) - 1 (half-size 2^E up to N / 2), three per pass.
+template <int N, bool ROWS, int E>
+__device__ void fft_dit_from(XcfShared<N>& S)
+{
+    constexpr int LOGN = ilog2(N);
+    constexpr int R = LOGN - E < 3 ? LOGN - E : 3;
+    fft_pass<N, false, ROWS, E, R>(S);
+    if constexpr (E + R < LOGN) fft_dit_from<N, ROWS, E + R>(S);
 }
 
 template <int N>
-__device__ void fft_cols_dif(XcfShared<N>& S)
-{
-    for (int h = N / 2; h >= 1; h >>= 1) {
-        const int step = N / (2 * h);
-        for (int c = threadIdx.x; c < N * N / 2; c += NT) {
-            const int col = c % N, j = c / N;
-            const int t = j & (h - 1), g = j / h;
-            const int i0 = g * 2 * h + t, i1 = i0 + h;
-            float2 a = S.z[i0][col], b = S.z[i1][col];
-            S.z[i0][col] = make_float2(a.x + b.x, a.y + b.y);
-            S.z[i1][col] = cmul(make_float2(a.x - b.x, a.y - b.y), S.tw[t * step]);
-        }
-        __syncthreads();
-    }
-}
+__device__ void fft_rows_dif(XcfShared<N>& S) { fft_dif_from<N, true, ilog2(N) - 1>(S); }
 
 template <int N>
-__device__ void ifft_cols_dit(XcfShared<N>& S)
-{
-    for (int h = 1; h <= N / 2; h <<= 1) {
-        const int step = N / (2 * h);
-        for (int c = threadIdx.x; c < N * N / 2; c += NT) {
-            const int col = c % N, j = c / N;
-            const int t = j & (h - 1), g = j / h;
-            const int i0 = g * 2 * h + t, i1 = i0 + h;
-            float2 a = S.z[i0][col];
-            float2 b = cmulc(S.z[i1][col], S.tw[t * step]);
-            S.z[i0][col] = make_float2(a.x + b.x, a.y + b.y);
-            S.z[i1][col] = make_float2(a.x - b.x, a.y - b.y);
-        }
-        __syncthreads();
-    }
-}
+__device__ void fft_cols_dif(XcfShared<N>& S) { fft_dif_from<N, false, ilog2(N) - 1>(S); }
 
 template <int N>
-__device__ void ifft_rows_dit(XcfShared<N>& S)
-{
-    for (int h = 1; h <= N / 2; h <<= 1) {
-        const int step = N / (2 * h);
-        for (int c = threadIdx.x; c < N * N / 2; c += NT) {
-            const int row = c / (N / 2), j = c - row * (N / 2);
-            const int t = j & (h - 1), g = j / h;
-            const int i0 = g * 2 * h + t, i1 = i0 + h;
-            float2 a = S.z[row][i0];
-            float2 b = cmulc(S.z[row][i1], S.tw[t * step]);
-            S.z[row][i0] = make_float2(a.x + b.x, a.y + b.y);
-            S.z[row][i1] = make_float2(a.x - b.x, a.y - b.y);
-        }
-        __syncthreads();
-    }
-}
+__device__ void ifft_cols_dit(XcfShared<N>& S) { fft_dit_from<N, false, 0>(S); }
+
+template <int N>
+__device__ void ifft_rows_dit(XcfShared<N>& S) { fft_dit_from<N, true, 0>(S); }
 
 // The whole correlation for one ROI.  `load(x, y)` returns (reference, test)
 // at ROI pixel (x, y).  Writes q (x, y) and ph from thread 0.
