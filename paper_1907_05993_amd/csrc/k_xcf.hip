@@ -299,8 +299,14 @@ __device__ inline void block_sum4(float v[4], float (*red)[NT / 64], int k)
 // inverse: decimation in time with conjugate twiddles (from 1 up to N/2).
 // Consecutive threads take consecutive lines, so a wavefront's accesses of
 // one element fall in distinct banks (row pitch N + 1) or are contiguous.
-template <int N, bool DIF, bool ROWS, int SL, int R>
-__device__ void fft_pass(XcfShared<N>& S)
+struct NoHook {
+    __device__ void operator()(int, int, float2&) const {}
+};
+
+// pre(line, index, v) runs on each element after it is loaded, post(line,
+// index, v) on each result before it is stored (index along the line).
+template <int N, bool DIF, bool ROWS, int SL, int R, class Pre = NoHook, class Post = NoHook>
+__device__ void fft_pass(XcfShared<N>& S, Pre pre = Pre(), Post post = Post())
 {
     constexpr int s = 1 << SL, M = 1 << R, span = M * s;
     constexpr int per_line = N / M;
@@ -310,7 +316,10 @@ __device__ void fft_pass(XcfShared<N>& S)
         const int base = g * span + t;
         float2 v[M];
 #pragma unroll
-        for (int m = 0; m < M; m++) v[m] = ROWS ? S.z[line][base + m * s] : S.z[base + m * s][line];
+        for (int m = 0; m < M; m++) {
+            v[m] = ROWS ? S.z[line][base + m * s] : S.z[base + m * s][line];
+            pre(line, base + m * s, v[m]);
+        }
         // every loop below is unrolled: stage sizes and element indices are constants
 #pragma unroll
         for (int r = 0; r < R; r++) {
@@ -336,6 +345,7 @@ __device__ void fft_pass(XcfShared<N>& S)
         }
 #pragma unroll
         for (int m = 0; m < M; m++) {
+            post(line, base + m * s, v[m]);
             if (ROWS) S.z[line][base + m * s] = v[m];
             else S.z[base + m * s][line] = v[m];
         }
@@ -345,36 +355,30 @@ __device__ void fft_pass(XcfShared<N>& S)
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// Forward stages E .. 0 (half-size 2^E down to 1), three per pass.
-template <int N, bool ROWS, int E>
-__device__ void fft_dif_from(XcfShared<N>& S)
+// Forward stages E .. 0 (half-size 2^E down to 1), three per pass; `pre`
+// runs in the first pass only.
+template <int N, bool ROWS, int E, class Pre = NoHook>
+__device__ void fft_dif_from(XcfShared<N>& S, Pre pre = Pre())
 {
     constexpr int R = E + 1 < 3 ? E + 1 : 3;
-    fft_pass<N, true, ROWS, E - R + 1, R>(S);
+    fft_pass<N, true, ROWS, E - R + 1, R>(S, pre);
     if constexpr (E - R >= 0) fft_dif_from<N, ROWS, E - R>(S);
 }
 
-// Inverse stages E .. log2(N) - 1 (half-size 2^E up to N / 2), three per pass.
-template <int N, bool ROWS, int E>
-__device__ void fft_dit_from(XcfShared<N>& S)
+// Inverse stages E .. log2(N) - 1 (half-size 2^E up to N / 2), three per pass;
+// `post` runs in the last pass only.
+template <int N, bool ROWS, int E, class Post = NoHook>
+__device__ void fft_dit_from(XcfShared<N>& S, Post post = Post())
 {
     constexpr int LOGN = ilog2(N);
     constexpr int R = LOGN - E < 3 ? LOGN - E : 3;
-    fft_pass<N, false, ROWS, E, R>(S);
-    if constexpr (E + R < LOGN) fft_dit_from<N, ROWS, E + R>(S);
+    if constexpr (E + R < LOGN) {
+        fft_pass<N, false, ROWS, E, R>(S);
+        fft_dit_from<N, ROWS, E + R>(S, post);
+    } else {
+        fft_pass<N, false, ROWS, E, R, NoHook, Post>(S, NoHook(), post);
+    }
 }
-
-template <int N>
-__device__ void fft_rows_dif(XcfShared<N>& S) { fft_dif_from<N, true, ilog2(N) - 1>(S); }
-
-template <int N>
-__device__ void fft_cols_dif(XcfShared<N>& S) { fft_dif_from<N, false, ilog2(N) - 1>(S); }
-
-template <int N>
-__device__ void ifft_cols_dit(XcfShared<N>& S) { fft_dit_from<N, false, 0>(S); }
-
-template <int N>
-__device__ void ifft_rows_dit(XcfShared<N>& S) { fft_dit_from<N, true, 0>(S); }
 
 // The whole correlation for one ROI.  `load(x, y)` returns (reference, test)
 // at ROI pixel (x, y).  Writes q (x, y) and ph from thread 0.
@@ -402,22 +406,17 @@ __device__ void xcf_core(XcfShared<N>& S, Loader load, int window, float* q, flo
     block_sum4(acc, S.red, 2);
     const float ma = acc[0] / (float)(N * N), mb = acc[1] / (float)(N * N);
 
-    // zero mean, window, energies
-    float en[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int p = tid; p < N * N; p += NT) {
-        const int y = p / N, x = p - y * N;
+    // forward transform; its first pass removes the means, applies the window
+    // and sums the energies of the windowed ROIs
+    float en0 = 0.0f, en1 = 0.0f;
+    fft_dif_from<N, true, ilog2(N) - 1>(S, [&](int y, int x, float2& ab) {
         const float wgt = S.win[y] * S.win[x];
-        float2 ab = S.z[y][x];
-        float a = (ab.x - ma) * wgt, b = (ab.y - mb) * wgt;
-        S.z[y][x] = make_float2(a, b);
-        en[0] += a * a;
-        en[1] += b * b;
-    }
-    block_sum4(en, S.red, 2);
-    const float ea = en[0], eb = en[1];
-
-    fft_rows_dif<N>(S);
-    fft_cols_dif<N>(S);
+        const float a = (ab.x - ma) * wgt, b = (ab.y - mb) * wgt;
+        ab = make_float2(a, b);
+        en0 += a * a;
+        en1 += b * b;
+    });
+    fft_dif_from<N, false, ilog2(N) - 1>(S);
 
     // cross-power spectrum in the bit-reversed domain
     const float scale = 1.0f / (float)(N * N);
@@ -443,20 +442,18 @@ __device__ void xcf_core(XcfShared<N>& S, Loader load, int window, float* q, flo
     }
     __syncthreads();
 
-    ifft_cols_dit<N>(S);
-    ifft_rows_dit<N>(S);
-
-    // argmax, ties to the lowest row-major index
+    // inverse transform; its last pass also takes each thread's argmax of Re C
+    // (ties to the lowest row-major index; NaNs never win)
     float bv = -INFINITY;
     int bi = 0x7fffffff;
-    for (int p = tid; p < N * N; p += NT) {
-        const int y = p / N, x = p - y * N;
-        float v = S.z[y][x].x;
-        if (v > bv) {
-            bv = v;
+    fft_dit_from<N, false, 0>(S);
+    fft_dit_from<N, true, 0>(S, [&](int y, int x, float2& c) {
+        const int p = y * N + x;
+        if (c.x > bv || (c.x == bv && p < bi)) {
+            bv = c.x;
             bi = p;
         }
-    }
+    });
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         float ov = __shfl_xor(bv, off, 64);
@@ -465,14 +462,24 @@ __device__ void xcf_core(XcfShared<N>& S, Loader load, int window, float* q, flo
             bv = ov;
             bi = oi;
         }
+        en0 += __shfl_xor(en0, off, 64);
+        en1 += __shfl_xor(en1, off, 64);
     }
     const int lane = tid & 63, wv = tid >> 6;
     if (lane == 0) {
         S.bv[wv] = bv;
         S.bi[wv] = bi;
+        S.red[0][wv] = en0;
+        S.red[1][wv] = en1;
     }
     __syncthreads();
     if (tid == 0) {
+        float ea = 0.0f, eb = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NT / 64; i++) {
+            ea += S.red[0][i];
+            eb += S.red[1][i];
+        }
         bv = S.bv[0];
         bi = S.bi[0];
         for (int i = 1; i < NT / 64; i++)
