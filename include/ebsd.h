@@ -408,7 +408,8 @@ int ebsd_stage_demons_iter(const float* R, const float* T, int32_t n, int32_t H,
                            void* stream);
 
 /* Field prolongation [n][2][h][w] -> [n][2][2h][2w]: bilinear with the
- * half-pixel-centre map, values doubled. */
+ * half-pixel-centre map, values doubled.  EBSD_ESHAPE unless 1 <= h, w <= 8192
+ * (outputs of at most 16384 px a side) and n <= 65535. */
 int ebsd_stage_prolong(const float* u, int32_t n, int32_t h, int32_t w, float* out, void* stream);
 
 /* ROI cross-correlation of n ROI pairs (section 2): A (reference) and B

@@ -1147,7 +1147,7 @@ int ebsd_stage_demons_iter(const float* R, const float* T, int32_t n, int32_t H,
 int ebsd_stage_prolong(const float* u, int32_t n, int32_t h, int32_t w, float* out, void* stream)
 {
     if (n < 0 || (n > 0 && (!u || !out))) return EBSD_EINVAL;
-    if (h < 1 || w < 1 || n > 65535) return EBSD_ESHAPE;
+    if (h < 1 || w < 1 || h > 8192 || w > 8192 || n > 65535) return EBSD_ESHAPE;
     if (n == 0) return EBSD_OK;
     return map_err(launch_stage_prolong(u, n, h, w, out, (hipStream_t)stream));
 }

@@ -142,9 +142,10 @@ __global__ void k_restrict_level(const Bucket* __restrict__ bk, int level)
     const int h = bk->lh[level], w = bk->lw[level];
     const float* in = base + bk->lvl_off[level - 1];
     float* out = base + bk->lvl_off[level];
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)h * w;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        int j = (int)(t / w), i = (int)(t % w);
+    // per-pattern indices fit in 32 bits (sides of at most 16384 px)
+    const int n = h * w;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const int j = t / w, i = t - j * w;
         out[t] = restrict_at(in, Hi, Wi, j, i);
     }
 }
@@ -156,24 +157,26 @@ __global__ void k_restrict_plain(const float* __restrict__ in, int H, int W,
     const int h = (H + 1) / 2, w = (W + 1) / 2;
     const float* src = in + (int64_t)pat * H * W;
     float* dst = out + (int64_t)pat * h * w;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)h * w;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        int j = (int)(t / w), i = (int)(t % w);
+    const int n = h * w;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const int j = t / w, i = t - j * w;
         dst[t] = restrict_at(src, H, W, j, i);
     }
 }
 
 // Prolongation u_{l-1}(x) = 2 bilinear(u_l, (x - 0.5)/2): half-pixel centres;
 // the finer level is H2 x W2 (2h x 2w, or one less where it was odd).
+// Output t of the two channels (t < 2 H2 W2, which fits in 32 bits for sides
+// of at most 16384 px).
 __device__ inline void prolong_one(const float* __restrict__ src, int h, int w, int H2, int W2,
-                                   float* __restrict__ dst, int64_t t)
+                                   float* __restrict__ dst, int t)
 {
-    const int64_t hw2 = (int64_t)H2 * W2;
-    int c = (int)(t / hw2);
-    int64_t r = t - (int64_t)c * hw2;
-    int y = (int)(r / W2), x = (int)(r % W2);
+    const int hw2 = H2 * W2;
+    const int c = t >= hw2 ? 1 : 0;
+    const int r = t - c * hw2;
+    const int y = r / W2, x = r - y * W2;
     float sx = ((float)x - 0.5f) * 0.5f, sy = ((float)y - 0.5f) * 0.5f;
-    dst[t] = 2.0f * bilinear_clamped(src + (int64_t)c * h * w, h, w, sx, sy);
+    dst[t] = 2.0f * bilinear_clamped(src + c * h * w, h, w, sx, sy);
 }
 
 __global__ void k_prolong_level(const Bucket* __restrict__ bk, int level)
@@ -185,9 +188,8 @@ __global__ void k_prolong_level(const Bucket* __restrict__ bk, int level)
     const int64_t slot = (int64_t)b * 2 * bk->H * bk->W;
     const float* src = bk->field[cur] + slot;
     float* dst = bk->field[cur ^ 1] + slot;
-    const int64_t n = (int64_t)2 * H2 * W2;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x)
+    const int n = 2 * H2 * W2;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
         prolong_one(src, h, w, H2, W2, dst, t);
 }
 
@@ -206,9 +208,8 @@ __global__ void k_prolong_plain(const float* __restrict__ u, int h, int w, float
     const int b = blockIdx.y;
     const float* src = u + (int64_t)b * 2 * h * w;
     float* dst = out + (int64_t)b * 2 * 4 * h * w;
-    const int64_t n = (int64_t)2 * 4 * h * w;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x)
+    const int n = 2 * 4 * h * w;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
         prolong_one(src, h, w, 2 * h, 2 * w, dst, t);
 }
 

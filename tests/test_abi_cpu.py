@@ -122,6 +122,8 @@ def test_null_arguments_rejected(E):
     assert L.ebsd_stage_bandpass(fake, 1, 64, 64, C.c_float(40.0), C.c_float(8.0), fake, None) == -1
     assert L.ebsd_stage_bandpass(fake, 1, 64, 20000, C.c_float(1.0), C.c_float(8.0), fake, None) == -2
     assert L.ebsd_stage_bandpass(None, 0, 64, 64, C.c_float(1.0), C.c_float(8.0), None, None) == 0
+    assert L.ebsd_stage_prolong(fake, 1, 64, 8193, fake, None) == -2  # output over 16384 px a side
+    assert L.ebsd_stage_prolong(None, 1, 64, 64, fake, None) == -1
     assert L.ebsd_destroy(None) == 0
     # traction-free solve: validation before any launch
     eye = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
