@@ -406,6 +406,7 @@ def main():
             regp = ebsd.Registrar(pp, device=0)
             regp.set_graphs(not args.no_graphs)
             regp.autotune(p_refs, p_tests)
+            regp.set_timing(True)
             for _ in range(max(args.warmup, 1)):
                 regp.register(p_refs, p_tests, want_field=False)
             torch.cuda.synchronize()
@@ -414,6 +415,7 @@ def main():
                 po = regp.register(p_refs, p_tests, want_field=False)
             torch.cuda.synchronize()
             el = time.perf_counter() - ts
+            p_level_ms, p_total_ms = regp.timing()
             e = np.linalg.norm(po["rotvec"].cpu().numpy() - rv_p, axis=1)
             e1 = np.linalg.norm(np.stack([rotvec_of(r) for r in po["R_finite"].cpu().numpy()]) - rv_p, axis=1)
             lat = []
@@ -426,6 +428,8 @@ def main():
                 "pairs_per_s": round(args.paper_pairs * args.steps / el, 1),
                 "ms_per_pair_batched": round(el * 1e3 / (args.paper_pairs * args.steps), 4),
                 "single_pair_ms": round(float(np.median(lat)), 2),
+                "demons_level_ms": [round(float(x), 3) for x in p_level_ms],
+                "call_ms": round(float(p_total_ms), 3),
                 "rotation_error_rad": {"median": float(np.median(e)), "p95": float(np.percentile(e, 95))},
                 "first_pass_rotation_error_rad": {"median": float(np.median(e1)), "p95": float(np.percentile(e1, 95))},
                 "peak_height_mean": float(po["peak_height"].float().mean()),
