@@ -224,7 +224,8 @@ int ebsd_second_pass_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
 /* Autotuner for the demons kernel: on this batch (same validation as
  * ebsd_register_batch), times every supported strip height (rows per
  * workgroup: 16, 32, 64, 128) of the row-marching demons kernel for each
- * pyramid level up to 512 px wide, and keeps the fastest per level size for
+ * pyramid level (wider than 512 px: column segments, and also the 2-D tile
+ * kernel as strip height 0), and keeps the fastest per level size for
  * later calls of this handle.  If the environment variable EBSD_TUNE_CACHE
  * named a file when the handle was created, the table is read from it then
  * and written back here (lines "gfx950 <h> <w> <rows>").  Synchronises
@@ -251,13 +252,16 @@ int ebsd_set_graphs(ebsd_handle* h, int enable);
  * only when the RMS update lies within rounding of it. */
 int ebsd_set_resident(ebsd_handle* h, int enable);
 
-/* Strip height used for a pyramid level of level_h x level_w px (0 if that
- * level uses the 2-D tile kernel, i.e. wider than 512 px): the tuned or
- * forced value, else 64.  Untuned levels of a batch with fewer than 512
+/* Strip height used for a pyramid level of level_h x level_w px (levels
+ * wider than 512 px run in column segments of 256 or 512 lanes, each
+ * recomputing 9 columns on either side, or, at strip height 0, on the 2-D
+ * tile kernel when the autotuner found that faster): the tuned or forced
+ * value, else 64.  Untuned levels of a batch with fewer than 512
  * strips of 64 rows use 32 or 16 rows (more workgroups for small batches). */
 int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w);
 
-/* Force the strip height (16, 32, 64 or 128) for a level size. */
+/* Force the strip height (16, 32, 64 or 128; 0 = the 2-D tile kernel, for
+ * levels wider than 512 px only) for a level size. */
 int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t rows);
 
 /* Two demons iterations per launch (temporal blocking): the row-marching
@@ -271,7 +275,7 @@ int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int3
  * this kernel against the single-iteration kernel and keeps it for a level
  * size where it is faster.  ebsd_get_fused_height returns the strip height
  * used for a level size (0 = one iteration per launch); ebsd_set_fused_height
- * forces it (0, 16, 32, 64 or 128; levels up to 512 px wide). */
+ * forces it (0, 16, 32, 64 or 128). */
 int ebsd_get_fused_height(const ebsd_handle* h, int32_t level_h, int32_t level_w);
 int ebsd_set_fused_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t rows);
 

@@ -1,11 +1,15 @@
 // Row-marching demons iteration for gfx950 (kernel templates; each
 // k_demons_rows_w<NW>.hip instantiates one row width) (multi-resolution demons of
-// arXiv:1907.05993 section 1, Eq. (1) force), used for levels up to 512 px wide.
+// arXiv:1907.05993 section 1, Eq. (1) force).
 //
 // One workgroup of 64 NW threads (NW = 8 wavefronts for 512 px, 4 for 256 px,
 // 2 for 128 px, 1 for 64 px) owns a strip of TY output rows of one pair; thread t owns column
 // t, so a workgroup spans a whole row and every memory instruction is
-// contiguous across the lanes.
+// contiguous across the lanes.  A level wider than 512 px is cut into column
+// segments: lane t owns column sx0 + t, the kSegHalo lanes at either end
+// recompute their neighbours' columns (their own gradients and taps reach
+// past the segment and are wrong, which two iterations of radius r carry at
+// most 2r + 1 lanes inward), and only columns [ws, we) are written.
 // Marching down the strip, for each row y = y0 - r .. y0 + TY - 1 + r:
 //   v = u + a grad R / (|grad R|^2 + a^2),  a = R - T(x + u)  (bilinear, clamped;
 //       central differences inside, one-sided on the border);
@@ -109,7 +113,7 @@ __device__ inline void taps_h(float2* rows, unsigned rb, const Taps& tp, float& 
 template <int NW, int RAD, int TY>
 __device__ float demons_strip(const float* __restrict__ Rg, const float* __restrict__ Tg,
                               const float* __restrict__ ug, float* __restrict__ ung, int h, int w,
-                              int y0, const Taps& tp, bool want_ss)
+                              int y0, int sx0, int ws, int we, const Taps& tp, bool want_ss)
 {
     const unsigned img_bytes = 4u * (unsigned)h * (unsigned)w;
     const __amdgpu_buffer_rsrc_t R = make_rsrc(Rg, img_bytes);
@@ -121,8 +125,9 @@ __device__ float demons_strip(const float* __restrict__ Rg, const float* __restr
     __shared__ StripRows<NW, RAD> L;
     __shared__ float red[NW];
     const int c = threadIdx.x;
-    const bool in = c < w;
-    const int x = in ? c : w - 1;
+    const int gx = sx0 + c;  // the lane's column; written when inside [ws, we)
+    const bool in = gx >= ws && gx < we;
+    const int x = clampi(gx, 0, w - 1);
     const int xm = max(x - 1, 0), xp = min(x + 1, w - 1);
     const float sx = (xp - xm == 2) ? 0.5f : 1.0f;
     const BilGeom gg = bil_geom(h, w);
@@ -131,7 +136,7 @@ __device__ float demons_strip(const float* __restrict__ Rg, const float* __restr
     // byte offset of channel 1 of the field
     const unsigned ch1 = img_bytes;
     RowBase cur, oth;
-    row_bases<NW, RAD>(x, cur, oth);
+    row_bases<NW, RAD>(x - sx0, cur, oth);
 
     // Pipeline state at the start of step s (row y = y0 - RAD + s):
     //   r_m, r_c, r_p   R rows ym, yc, yp of row y (registers)
@@ -149,7 +154,7 @@ __device__ float demons_strip(const float* __restrict__ Rg, const float* __restr
     float ux1 = bload_s(U, x4, (unsigned)yc1 * uw4);
     float uy1 = bload_s(U, x4, ch1 + (unsigned)yc1 * uw4);
     Bilin g = bilinear_issue_g(T, gg, (float)x + ux, (float)yc + uy);
-    put_r(L.r, cur.r, c, w, r_c);
+    put_r(L.r, cur.r, gx, w, r_c);
     __syncthreads();
 
     float ring_x[NR], ring_y[NR], ring_ux[NR], ring_uy[NR];
@@ -193,8 +198,8 @@ __device__ float demons_strip(const float* __restrict__ Rg, const float* __restr
                 vx = fmaf(q, gxr, ux);
                 vy = fmaf(q, gyr, uy);
             }
-            put_v<RAD>(L.v, cur.v, c, w, vx, vy);
-            if (more) put_r(L.r, oth.r, c, w, n_rc);
+            put_v<RAD>(L.v, cur.v, gx, w, vx, vy);
+            if (more) put_r(L.r, oth.r, gx, w, n_rc);
             ring_ux[s] = ux;
             ring_uy[s] = uy;
             __syncthreads();
@@ -280,7 +285,7 @@ struct Strip2Ctx {
     __amdgpu_buffer_rsrc_t R, T, U, UN;
     BilGeom gg;
     unsigned uw4, x4, ch1;
-    int c, x, h, w, y0;
+    int c, gx, x, h, w, y0;
     bool in, want_ss;
     float sx;
     StripRows<NW, RAD>* L1;
@@ -350,8 +355,8 @@ __device__ __forceinline__ void strip2_step(const Strip2Ctx<NW, RAD>& k, const T
             vx = fmaf(q, gxr, st.ux);
             vy = fmaf(q, gyr, st.uy);
         }
-        put_v<RAD>(k.L1->v, st.cur1.v, k.c, k.w, vx, vy);
-        put_r(k.L1->r, st.oth1.r, k.c, k.w, n_rc);
+        put_v<RAD>(k.L1->v, st.cur1.v, k.gx, k.w, vx, vy);
+        put_r(k.L1->r, st.oth1.r, k.gx, k.w, n_rc);
         st.ring_ux[SL1] = st.ux;
         st.ring_uy[SL1] = st.uy;
     }
@@ -390,8 +395,8 @@ __device__ __forceinline__ void strip2_step(const Strip2Ctx<NW, RAD>& k, const T
             vx = fmaf(q, gxr, st.v1x);
             vy = fmaf(q, gyr, st.v1y);
         }
-        put_v<RAD>(k.L2->v, st.cur2.v, k.c, k.w, vx, vy);
-        put_r(k.L2->r, st.oth2.r, k.c, k.w, n_qc);
+        put_v<RAD>(k.L2->v, st.cur2.v, k.gx, k.w, vx, vy);
+        put_r(k.L2->r, st.oth2.r, k.gx, k.w, n_qc);
     }
     __syncthreads();
     // ---- stage 1, after the barrier: taps, u1 row y - r into the history ----
@@ -470,7 +475,7 @@ __device__ __forceinline__ void strip2_step(const Strip2Ctx<NW, RAD>& k, const T
 template <int NW, int RAD, int TY>
 __device__ float2 demons_strip2(const float* __restrict__ Rg, const float* __restrict__ Tg,
                                 const float* __restrict__ ug, float* __restrict__ ung, int h, int w,
-                                int y0, const Taps& tp, bool want_ss)
+                                int y0, int sx0, int ws, int we, const Taps& tp, bool want_ss)
 {
     constexpr int NR = 2 * RAD + 1;  // ring rows
     constexpr int S1 = TY + 4 * RAD; // stage-1 input rows
@@ -495,8 +500,9 @@ __device__ float2 demons_strip2(const float* __restrict__ Rg, const float* __res
     k.U = make_rsrc(ug, 2u * img_bytes);
     k.UN = make_rsrc(ung, 2u * img_bytes);
     k.c = threadIdx.x;
-    k.in = k.c < w;
-    k.x = k.in ? k.c : w - 1;
+    k.gx = sx0 + k.c;  // the lane's column; written when inside [ws, we)
+    k.in = k.gx >= ws && k.gx < we;
+    k.x = clampi(k.gx, 0, w - 1);
     k.h = h;
     k.w = w;
     k.y0 = y0;
@@ -513,9 +519,9 @@ __device__ float2 demons_strip2(const float* __restrict__ Rg, const float* __res
 
     Strip2State<RAD> st;
     // LDS bases: stage 1 uses parity S & 1 at step S, stage 2 parity (S - D) & 1
-    row_bases<NW, RAD>(k.x, st.cur1, st.oth1);
-    if (D & 1) row_bases<NW, RAD>(k.x, st.oth2, st.cur2);
-    else row_bases<NW, RAD>(k.x, st.cur2, st.oth2);
+    row_bases<NW, RAD>(k.x - sx0, st.cur1, st.oth1);
+    if (D & 1) row_bases<NW, RAD>(k.x - sx0, st.oth2, st.cur2);
+    else row_bases<NW, RAD>(k.x - sx0, st.cur2, st.oth2);
     const unsigned uw4 = k.uw4, x4 = k.x4, ch1 = k.ch1;
     // stage 1 pipeline state (as in demons_strip), starting at input row y0 - 2r
     st.yc = k.rowc(y0 - 2 * RAD);
@@ -530,7 +536,7 @@ __device__ float2 demons_strip2(const float* __restrict__ Rg, const float* __res
     st.ux1 = bload_s(k.U, x4, (unsigned)yc1 * uw4);
     st.uy1 = bload_s(k.U, x4, ch1 + (unsigned)yc1 * uw4);
     st.g = bilinear_issue_g(k.T, k.gg, (float)k.x + st.ux, (float)st.yc + st.uy);
-    put_r(L1.r, st.cur1.r, k.c, w, st.r_c);
+    put_r(L1.r, st.cur1.r, k.gx, w, st.r_c);
     // stage 2 state: R rows of its first input row y0 - r; its u1 and gathers
     // are taken from the history one step before its first step
     st.zc = k.rowc(y0 - RAD);
@@ -539,7 +545,7 @@ __device__ float2 demons_strip2(const float* __restrict__ Rg, const float* __res
     st.q_m = bload_s(k.R, x4, (unsigned)st.zm * uw4);
     st.q_c = bload_s(k.R, x4, (unsigned)st.zc * uw4);
     st.q_p = bload_s(k.R, x4, (unsigned)st.zp * uw4);
-    put_r(L2.r, (D & 1) ? st.oth2.r : st.cur2.r, k.c, w, st.q_c);  // parity 0 of stage 2
+    put_r(L2.r, (D & 1) ? st.oth2.r : st.cur2.r, k.gx, w, st.q_c);  // parity 0 of stage 2
     st.v1x = st.v1y = 0.0f;
     st.g2 = st.g;
     st.ss1 = st.ss2 = 0.0f;
@@ -597,24 +603,29 @@ __device__ float2 demons_strip2(const float* __restrict__ Rg, const float* __res
     return make_float2(t1, t2);
 }
 
-template <int NW, int RAD, int TY>
+// SEG: the level is cut into column segments (levels wider than 64 NW px);
+// without it nsegs is 1 and every lane's column is its index.
+template <int NW, int RAD, int TY, bool SEG>
 __global__ void __launch_bounds__(64 * NW)
-    k_demons_rows(const Bucket* __restrict__ bk, int level, int k, Taps tp, float tol, int nstrips)
+    k_demons_rows(const Bucket* __restrict__ bk, int level, int k, Taps tp, float tol, int nstrips, int nsegs_arg)
 {
     __shared__ double sh_sum;
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int b = lb / nstrips;
-    const int strip = lb - b * nstrips;
+    const int nsegs = SEG ? nsegs_arg : 1;
+    const int nunits = nstrips * nsegs;  // units of a pair: strips x column segments
+    const int b = lb / nunits;
+    const int unit = lb - b * nunits;
+    const int strip = unit / nsegs, seg = unit - strip * nsegs;
     const PairState st = bk->state[b];
     if (st.stop >= 0) return;  // uniform
     const int h = bk->lh[level], w = bk->lw[level];
     const int64_t npart = (int64_t)bk->nb * bk->max_tiles;
     if (tol > 0.0f && k > 0) {
         const float* prev = bk->partial + ((k - 1) & 1) * npart + (int64_t)b * bk->max_tiles;
-        const double ss = pair_sum(prev, nstrips, &sh_sum);
+        const double ss = pair_sum(prev, nunits, &sh_sum);
         const double delta = sqrt(ss / ((double)h * (double)w)) * (double)(1 << level);
         if (delta < (double)tol) {
-            if (strip == 0 && threadIdx.x == 0) {
+            if (unit == 0 && threadIdx.x == 0) {
                 bk->state[b].stop = k;
                 bk->state[b].convmask = st.convmask | (1u << level);
             }
@@ -626,9 +637,11 @@ __global__ void __launch_bounds__(64 * NW)
     const float* T = bk->test_pyr + (int64_t)b * bk->pyr_elems + bk->lvl_off[level];
     const float* u = bk->field[(st.base + k) & 1] + slot;
     float* un = bk->field[(st.base + k + 1) & 1] + slot;
-    const float ss = demons_strip<NW, RAD, TY>(R, T, u, un, h, w, strip * TY, tp, tol > 0.0f);
+    int sx0 = 0, ws = 0, we = w;
+    if constexpr (SEG) rows_seg_cols(seg, nsegs, w, NW, sx0, ws, we);
+    const float ss = demons_strip<NW, RAD, TY>(R, T, u, un, h, w, strip * TY, sx0, ws, we, tp, tol > 0.0f);
     if (tol > 0.0f && threadIdx.x == 0)
-        bk->partial[(k & 1) * npart + (int64_t)b * bk->max_tiles + strip] = ss;
+        bk->partial[(k & 1) * npart + (int64_t)b * bk->max_tiles + unit] = ss;
 }
 
 // Launch L of a level run two iterations at a time: iterations k = 2L and
@@ -644,14 +657,18 @@ __global__ void __launch_bounds__(64 * NW)
 // A launch with k >= cap only takes these decisions; one with k + 1 == cap
 // runs a single iteration.  The final field of a pair that ran n iterations
 // is in buffer (base + ceil(n / 2)) & 1.
-template <int NW, int RAD, int TY>
+template <int NW, int RAD, int TY, bool SEG>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)))
-    k_demons_rows2(const Bucket* __restrict__ bk, int level, int L, Taps tp, float tol, int nstrips, int cap)
+    k_demons_rows2(const Bucket* __restrict__ bk, int level, int L, Taps tp, float tol, int nstrips, int nsegs_arg,
+                   int cap)
 {
     __shared__ double sh_sum;
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int b = lb / nstrips;
-    const int strip = lb - b * nstrips;
+    const int nsegs = SEG ? nsegs_arg : 1;
+    const int nunits = nstrips * nsegs;  // units of a pair: strips x column segments
+    const int b = lb / nunits;
+    const int unit = lb - b * nunits;
+    const int strip = unit / nsegs, seg = unit - strip * nsegs;
     const PairState st = bk->state[b];
     if (st.stop >= 0) return;  // uniform
     const int h = bk->lh[level], w = bk->lw[level];
@@ -661,13 +678,13 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
     bool recompute = false;
     if (tol > 0.0f && L > 0) {
         const double hw = (double)h * (double)w, sc = (double)(1 << level);
-        const double ssa = pair_sum(bk->partial + ((k - 2) & 3) * npart + pofs, nstrips, &sh_sum);
+        const double ssa = pair_sum(bk->partial + ((k - 2) & 3) * npart + pofs, nunits, &sh_sum);
         if (sqrt(ssa / hw) * sc < (double)tol) {
             recompute = true;
         } else {
-            const double ssb = pair_sum(bk->partial + ((k - 1) & 3) * npart + pofs, nstrips, &sh_sum);
+            const double ssb = pair_sum(bk->partial + ((k - 1) & 3) * npart + pofs, nunits, &sh_sum);
             if (sqrt(ssb / hw) * sc < (double)tol) {
-                if (strip == 0 && threadIdx.x == 0) {
+                if (unit == 0 && threadIdx.x == 0) {
                     bk->state[b].stop = k;
                     bk->state[b].convmask = st.convmask | (1u << level);
                 }
@@ -680,24 +697,26 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
     const float* T = bk->test_pyr + (int64_t)b * bk->pyr_elems + bk->lvl_off[level];
     float* fa = bk->field[(st.base + L) & 1] + slot;
     float* fb = bk->field[(st.base + L + 1) & 1] + slot;
+    int sx0 = 0, ws = 0, we = w;
+    if constexpr (SEG) rows_seg_cols(seg, nsegs, w, NW, sx0, ws, we);
     if (recompute) {
-        if (strip == 0 && threadIdx.x == 0) {
+        if (unit == 0 && threadIdx.x == 0) {
             bk->state[b].stop = k - 1;
             bk->state[b].convmask = st.convmask | (1u << level);
         }
-        demons_strip<NW, RAD, TY>(R, T, fb, fa, h, w, strip * TY, tp, false);
+        demons_strip<NW, RAD, TY>(R, T, fb, fa, h, w, strip * TY, sx0, ws, we, tp, false);
         return;
     }
     if (k >= cap) return;
     if (k + 1 < cap) {
-        const float2 ss = demons_strip2<NW, RAD, TY>(R, T, fa, fb, h, w, strip * TY, tp, tol > 0.0f);
+        const float2 ss = demons_strip2<NW, RAD, TY>(R, T, fa, fb, h, w, strip * TY, sx0, ws, we, tp, tol > 0.0f);
         if (tol > 0.0f && threadIdx.x == 0) {
-            bk->partial[(k & 3) * npart + pofs + strip] = ss.x;
-            bk->partial[((k + 1) & 3) * npart + pofs + strip] = ss.y;
+            bk->partial[(k & 3) * npart + pofs + unit] = ss.x;
+            bk->partial[((k + 1) & 3) * npart + pofs + unit] = ss.y;
         }
     } else {
-        const float ss = demons_strip<NW, RAD, TY>(R, T, fa, fb, h, w, strip * TY, tp, tol > 0.0f);
-        if (tol > 0.0f && threadIdx.x == 0) bk->partial[(k & 3) * npart + pofs + strip] = ss;
+        const float ss = demons_strip<NW, RAD, TY>(R, T, fa, fb, h, w, strip * TY, sx0, ws, we, tp, tol > 0.0f);
+        if (tol > 0.0f && threadIdx.x == 0) bk->partial[(k & 3) * npart + pofs + unit] = ss;
     }
 }
 
@@ -713,78 +732,92 @@ __global__ void __launch_bounds__(64 * NW)
     double acc = 0.0;
     for (int y0 = 0; y0 < h; y0 += TY)
         acc += (double)demons_strip<NW, RAD, TY>(R + b * hw, T + b * hw, u + 2 * b * hw,
-                                                  un + 2 * b * hw, h, w, y0, tp, true);
+                                                  un + 2 * b * hw, h, w, y0, 0, 0, w, tp, true);
     if (rms && threadIdx.x == 0) rms[b] = sqrt(acc / (double)hw);
 }
 
 template <int CPL, int RAD, int TY>
-void launch_rows(const Bucket* d_bk, int nb, int h, int level, int k, const Taps& tp, float tol,
+void launch_rows(const Bucket* d_bk, int nb, int h, int w, int level, int k, const Taps& tp, float tol,
                  hipStream_t s)
 {
-    const int nstrips = (h + TY - 1) / TY;
-    hipLaunchKernelGGL((k_demons_rows<CPL, RAD, TY>), dim3(nb * nstrips), dim3(64 * CPL), 0, s, d_bk,
-                       level, k, tp, tol, nstrips);
+    const int nstrips = (h + TY - 1) / TY, nsegs = rows_segs(w, CPL);
+    if constexpr (CPL >= 4) {
+        if (nsegs > 1) {
+            hipLaunchKernelGGL((k_demons_rows<CPL, RAD, TY, true>), dim3(nb * nstrips * nsegs), dim3(64 * CPL), 0,
+                               s, d_bk, level, k, tp, tol, nstrips, nsegs);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_demons_rows<CPL, RAD, TY, false>), dim3(nb * nstrips), dim3(64 * CPL), 0, s, d_bk,
+                       level, k, tp, tol, nstrips, 1);
 }
 
 template <int CPL, int RAD>
-bool dispatch_ty(const Bucket* d_bk, int nb, int h, int level, int k, const Taps& tp, float tol,
+bool dispatch_ty(const Bucket* d_bk, int nb, int h, int w, int level, int k, const Taps& tp, float tol,
                  int ty, hipStream_t s)
 {
     switch (ty) {
-    case 16: launch_rows<CPL, RAD, 16>(d_bk, nb, h, level, k, tp, tol, s); return true;
-    case 32: launch_rows<CPL, RAD, 32>(d_bk, nb, h, level, k, tp, tol, s); return true;
-    case 64: launch_rows<CPL, RAD, 64>(d_bk, nb, h, level, k, tp, tol, s); return true;
-    case 128: launch_rows<CPL, RAD, 128>(d_bk, nb, h, level, k, tp, tol, s); return true;
+    case 16: launch_rows<CPL, RAD, 16>(d_bk, nb, h, w, level, k, tp, tol, s); return true;
+    case 32: launch_rows<CPL, RAD, 32>(d_bk, nb, h, w, level, k, tp, tol, s); return true;
+    case 64: launch_rows<CPL, RAD, 64>(d_bk, nb, h, w, level, k, tp, tol, s); return true;
+    case 128: launch_rows<CPL, RAD, 128>(d_bk, nb, h, w, level, k, tp, tol, s); return true;
     default: return false;
     }
 }
 
 template <int CPL>
-bool dispatch_rad(const Bucket* d_bk, int nb, int h, int level, int k, const Taps& tp, int radius,
+bool dispatch_rad(const Bucket* d_bk, int nb, int h, int w, int level, int k, const Taps& tp, int radius,
                   float tol, int ty, hipStream_t s)
 {
     switch (radius) {
-    case 0: return dispatch_ty<CPL, 0>(d_bk, nb, h, level, k, tp, tol, ty, s);
-    case 1: return dispatch_ty<CPL, 1>(d_bk, nb, h, level, k, tp, tol, ty, s);
-    case 2: return dispatch_ty<CPL, 2>(d_bk, nb, h, level, k, tp, tol, ty, s);
-    case 3: return dispatch_ty<CPL, 3>(d_bk, nb, h, level, k, tp, tol, ty, s);
-    case 4: return dispatch_ty<CPL, 4>(d_bk, nb, h, level, k, tp, tol, ty, s);
+    case 0: return dispatch_ty<CPL, 0>(d_bk, nb, h, w, level, k, tp, tol, ty, s);
+    case 1: return dispatch_ty<CPL, 1>(d_bk, nb, h, w, level, k, tp, tol, ty, s);
+    case 2: return dispatch_ty<CPL, 2>(d_bk, nb, h, w, level, k, tp, tol, ty, s);
+    case 3: return dispatch_ty<CPL, 3>(d_bk, nb, h, w, level, k, tp, tol, ty, s);
+    case 4: return dispatch_ty<CPL, 4>(d_bk, nb, h, w, level, k, tp, tol, ty, s);
     default: return false;
     }
 }
 
 template <int CPL, int RAD, int TY>
-void launch_rows2(const Bucket* d_bk, int nb, int h, int level, int L, const Taps& tp, float tol, int cap,
+void launch_rows2(const Bucket* d_bk, int nb, int h, int w, int level, int L, const Taps& tp, float tol, int cap,
                   hipStream_t s)
 {
-    const int nstrips = (h + TY - 1) / TY;
-    hipLaunchKernelGGL((k_demons_rows2<CPL, RAD, TY>), dim3(nb * nstrips), dim3(64 * CPL), 0, s, d_bk, level, L,
-                       tp, tol, nstrips, cap);
+    const int nstrips = (h + TY - 1) / TY, nsegs = rows_segs(w, CPL);
+    if constexpr (CPL >= 4) {
+        if (nsegs > 1) {
+            hipLaunchKernelGGL((k_demons_rows2<CPL, RAD, TY, true>), dim3(nb * nstrips * nsegs), dim3(64 * CPL), 0,
+                               s, d_bk, level, L, tp, tol, nstrips, nsegs, cap);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_demons_rows2<CPL, RAD, TY, false>), dim3(nb * nstrips), dim3(64 * CPL), 0, s, d_bk,
+                       level, L, tp, tol, nstrips, 1, cap);
 }
 
 template <int CPL, int RAD>
-bool dispatch_ty2(const Bucket* d_bk, int nb, int h, int level, int L, const Taps& tp, float tol, int cap, int ty,
+bool dispatch_ty2(const Bucket* d_bk, int nb, int h, int w, int level, int L, const Taps& tp, float tol, int cap, int ty,
                   hipStream_t s)
 {
     switch (ty) {
-    case 16: launch_rows2<CPL, RAD, 16>(d_bk, nb, h, level, L, tp, tol, cap, s); return true;
-    case 32: launch_rows2<CPL, RAD, 32>(d_bk, nb, h, level, L, tp, tol, cap, s); return true;
-    case 64: launch_rows2<CPL, RAD, 64>(d_bk, nb, h, level, L, tp, tol, cap, s); return true;
-    case 128: launch_rows2<CPL, RAD, 128>(d_bk, nb, h, level, L, tp, tol, cap, s); return true;
+    case 16: launch_rows2<CPL, RAD, 16>(d_bk, nb, h, w, level, L, tp, tol, cap, s); return true;
+    case 32: launch_rows2<CPL, RAD, 32>(d_bk, nb, h, w, level, L, tp, tol, cap, s); return true;
+    case 64: launch_rows2<CPL, RAD, 64>(d_bk, nb, h, w, level, L, tp, tol, cap, s); return true;
+    case 128: launch_rows2<CPL, RAD, 128>(d_bk, nb, h, w, level, L, tp, tol, cap, s); return true;
     default: return false;
     }
 }
 
 template <int CPL>
-bool dispatch_rad2(const Bucket* d_bk, int nb, int h, int level, int L, const Taps& tp, int radius, float tol,
+bool dispatch_rad2(const Bucket* d_bk, int nb, int h, int w, int level, int L, const Taps& tp, int radius, float tol,
                    int cap, int ty, hipStream_t s)
 {
     switch (radius) {
-    case 0: return dispatch_ty2<CPL, 0>(d_bk, nb, h, level, L, tp, tol, cap, ty, s);
-    case 1: return dispatch_ty2<CPL, 1>(d_bk, nb, h, level, L, tp, tol, cap, ty, s);
-    case 2: return dispatch_ty2<CPL, 2>(d_bk, nb, h, level, L, tp, tol, cap, ty, s);
-    case 3: return dispatch_ty2<CPL, 3>(d_bk, nb, h, level, L, tp, tol, cap, ty, s);
-    case 4: return dispatch_ty2<CPL, 4>(d_bk, nb, h, level, L, tp, tol, cap, ty, s);
+    case 0: return dispatch_ty2<CPL, 0>(d_bk, nb, h, w, level, L, tp, tol, cap, ty, s);
+    case 1: return dispatch_ty2<CPL, 1>(d_bk, nb, h, w, level, L, tp, tol, cap, ty, s);
+    case 2: return dispatch_ty2<CPL, 2>(d_bk, nb, h, w, level, L, tp, tol, cap, ty, s);
+    case 3: return dispatch_ty2<CPL, 3>(d_bk, nb, h, w, level, L, tp, tol, cap, ty, s);
+    case 4: return dispatch_ty2<CPL, 4>(d_bk, nb, h, w, level, L, tp, tol, cap, ty, s);
     default: return false;
     }
 }

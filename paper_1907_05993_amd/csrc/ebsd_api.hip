@@ -97,7 +97,7 @@ void load_tune_cache(ebsd_handle* h)
         if (!(is >> arch >> lh >> lw >> ty) || arch != "gfx950") continue;
         if (!(is >> fty)) fty = 0;
         const auto key = std::make_pair(lh, lw);
-        if (rows_ty_supported(ty)) h->strip_ty[key] = ty;
+        if (strip_ty_ok(lw, ty)) h->strip_ty[key] = ty;
         if (rows2_ty_supported(fty)) h->fused_ty[key] = fty;
         else h->fused_ty.erase(key);
     }
@@ -390,6 +390,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         pe += (int64_t)b.lh[l] * b.lw[l];
         pe = (pe + 63) / 64 * 64;  // every level 256 B aligned
         max_units = std::max(max_units, demons_units(b.lh[l], b.lw[l], kMinStripTY));
+        if (b.lw[l] > 512) max_units = std::max(max_units, demons_tiles(b.lh[l], b.lw[l]));
     }
     b.pyr_elems = pe;
     b.max_tiles = max_units;
@@ -605,7 +606,8 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
             if (!rows_cpl(lw)) continue;
             float best = 1e30f;
             int best_ty = kDefaultStripTY;
-            for (int ty : {16, 32, 64, 128}) {
+            for (int ty : {0, 16, 32, 64, 128}) {
+                if (!strip_ty_ok(lw, ty)) continue;  // 0: the 2-D tile kernel, levels wider than 512 px
                 for (int it = 0; it < 2; it++)
                     EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, 0.0f, ty, s));
                 EBSD_TRY(hipEventRecord(e0, s));
@@ -944,7 +946,7 @@ int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w
 
 int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t ty)
 {
-    if (!h || level_h <= 0 || level_w <= 0 || !rows_ty_supported(ty)) return EBSD_EINVAL;
+    if (!h || level_h <= 0 || level_w <= 0 || !strip_ty_ok(level_w, ty)) return EBSD_EINVAL;
     h->strip_ty[std::make_pair((int)level_h, (int)level_w)] = ty;
     return EBSD_OK;
 }

@@ -260,10 +260,33 @@ inline int demons_tiles(int h, int w)
     return ((w + kDemonsTX - 1) / kDemonsTX) * ((h + kDemonsTY - 1) / kDemonsTY);
 }
 
-// Row-marching kernel (levels up to 512 px wide): wavefronts per row (0 = not
-// applicable), supported strip heights, number of strips, and its launchers
-// (false if not applicable).
+// Row-marching kernel: wavefronts per row (0 = not applicable), supported
+// strip heights, number of strips, and its launchers (false if not
+// applicable).  Levels wider than 512 px run in column segments of 512
+// lanes: each segment recomputes kSegHalo columns on either side (enough for
+// two iterations of the widest smoothing) and writes the 512 - 2 kSegHalo
+// columns between them.
 int rows_cpl(int w);
+constexpr int kSegHalo = 2 * kMaxRadius + 1;
+__host__ __device__ inline int rows_segs(int w, int nw)
+{
+    const int lanes = 64 * nw, ww = lanes - 2 * kSegHalo;
+    return w <= lanes ? 1 : (w + ww - 1) / ww;
+}
+// Columns of segment `seg`: lanes start at column sx0; columns [ws, we) are written.
+__host__ __device__ inline void rows_seg_cols(int seg, int nsegs, int w, int nw, int& sx0, int& ws, int& we)
+{
+    if (nsegs == 1) {
+        sx0 = 0;
+        ws = 0;
+        we = w;
+        return;
+    }
+    const int ww = 64 * nw - 2 * kSegHalo;
+    ws = seg * ww;
+    we = ws + ww < w ? ws + ww : w;
+    sx0 = ws - kSegHalo;
+}
 bool rows_ty_supported(int ty);
 // Two iterations per launch (temporal blocking) at strip heights 16, 32, 64, 128:
 // launch L of a level runs iterations 2L and 2L + 1 (see k_demons_rows2);
@@ -281,10 +304,14 @@ constexpr int kDefaultStripTY = 64;
 constexpr int kMinStripTY = 16;
 
 // Work units (and per-pair partial sums) of one demons iteration at h x w
-// with strip height ty (row-marching kernel) or 2-D tiles.
+// with strip height ty (row-marching kernel: strips x column segments) or
+// 2-D tiles (ty = 0, which levels wider than 512 px may select).
 inline int demons_units(int h, int w, int ty)
 {
-    return rows_cpl(w) ? rows_units(h, ty) : demons_tiles(h, w);
+    const int nw = rows_cpl(w);
+    return nw && ty > 0 ? rows_units(h, ty) * rows_segs(w, nw) : demons_tiles(h, w);
 }
+// Strip heights a level accepts: the row kernel's, and 0 (2-D tiles) above 512 px.
+inline bool strip_ty_ok(int w, int ty) { return rows_ty_supported(ty) || (ty == 0 && w > 512); }
 
 }  // namespace ebsd
