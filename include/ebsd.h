@@ -58,7 +58,7 @@ enum {
     EBSD_EROI = -3,     /* a ROI falls outside the pattern, or ROI size is not 32/64/128 */
     EBSD_ENOMEM = -4,   /* device or pinned allocation failed */
     EBSD_EDEVICE = -5,  /* a HIP runtime call failed */
-    EBSD_ENOTSUP = -6,  /* feature not available in this build */
+    EBSD_ENOTSUP = -6,  /* feature not available in this library */
     EBSD_ENOMODEL = -7, /* warm start requested but no network parameters loaded */
     EBSD_EVERSION = -8, /* ebsd_params.struct_size does not match this library */
     EBSD_EIO = -9       /* a parameter file could not be read or written */

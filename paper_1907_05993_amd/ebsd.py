@@ -118,7 +118,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
-                               "(run paper_1907_05993_amd/build.py or __graft_entry__.build())")
+                               "(run paper_1907_05993_amd/build.py)")
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.ebsd_version.restype = C.c_int
