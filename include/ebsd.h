@@ -226,7 +226,9 @@ int ebsd_second_pass_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
  * workgroup: 16, 32, 64, 128) of the row-marching demons kernel for each
  * pyramid level (wider than 512 px: column segments, and also the 2-D tile
  * kernel as strip height 0), and keeps the fastest per level size for
- * later calls of this handle.  If the environment variable EBSD_TUNE_CACHE
+ * later calls of this handle whose size bucket holds at least a quarter as
+ * many pairs as the tuned batch (smaller batches use the default rule of
+ * ebsd_get_strip_height).  If the environment variable EBSD_TUNE_CACHE
  * named a file when the handle was created, the table is read from it then
  * and written back here (lines "gfx950 <h> <w> <rows>").  Synchronises
  * `stream`.  Demons results are unaffected (the strip height only changes the
