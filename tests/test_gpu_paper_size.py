@@ -81,19 +81,22 @@ def test_odd_level_sizes_match_oracle(E, orc, iters, strict):
     _compare(E, orc, refs, tests, gp, op, strict=strict)
 
 
-@pytest.mark.parametrize("strip", [64, 16, 0])
-def test_wide_level_segments_and_tiles_match_oracle(E, orc, strip):
+@pytest.mark.parametrize("strip,tol", [(64, 0.0), (16, 0.0), (0, 0.0), (64, 0.05)])
+def test_wide_level_segments_and_tiles_match_oracle(E, orc, strip, tol):
     """A 700 px wide level 0 (600 x 700 px, 3 levels): the row kernels cut it
     into three column segments of 256 lanes (each writing 238 columns), at
     strips of 64 and 16 rows, or the 2-D tile kernel runs it (strip height 0).
     Every variant meets the oracle's field to the 1e-3 px RMS bar at a depth
-    where the FP32 and FP64 iterations stay together."""
+    where the FP32 and FP64 iterations stay together.  With a tolerance the
+    stop decisions sum the squared update over strips and segments, and the
+    iteration counts equal the oracle's."""
     from paper_1907_05993_amd import synth as S
     specs = [S.make_spec(9, i, 600, 700, mis_deg=(0.0, 3.0)) for i in range(2)]
     refs, tests = S.render_batch(specs)
-    print(f"wide level: 2 pairs of 600 x 700, 3 levels x 10, level-0 strip height {strip}", flush=True)
-    gp = E.Params(levels=3, iters=(10,) * 3, sigma_px=1.0, roi_size=64, n_roi=20)
-    op = orc.make_params(levels=3, iters=10, sigma=1.0, roi_size=64, n_roi=20)
+    print(f"wide level: 2 pairs of 600 x 700, 3 levels x 10, level-0 strip height {strip}, tolerance {tol}",
+          flush=True)
+    gp = E.Params(levels=3, iters=(10,) * 3, sigma_px=1.0, tol_px=tol, roi_size=64, n_roi=20)
+    op = orc.make_params(levels=3, iters=10, sigma=1.0, tol=tol, roi_size=64, n_roi=20)
     _compare(E, orc, refs, tests, gp, op, strict=True, strips={(600, 700): strip})
 
 
