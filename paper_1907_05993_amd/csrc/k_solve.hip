@@ -81,14 +81,17 @@ struct LMat {
 };
 
 // The same cyclic Jacobi iteration (same operation order, hence the same
-// results) on LDS matrices.
-template <int n>
+// results) on LDS matrices.  WANT_V = false skips the eigenvectors (the
+// eigenvalues do not depend on them).
+template <int n, bool WANT_V = true>
 __device__ void jacobi_eigen_l(LMat<n> A, double (&ev)[n], LMat<n> V)
 {
+    if constexpr (WANT_V) {
 #pragma unroll
-    for (int i = 0; i < n; i++)
+        for (int i = 0; i < n; i++)
 #pragma unroll
-        for (int j = 0; j < n; j++) V(i, j) = i == j ? 1.0 : 0.0;
+            for (int j = 0; j < n; j++) V(i, j) = i == j ? 1.0 : 0.0;
+    }
     for (int sweep = 0; sweep < 60; sweep++) {
         double off = 0.0, diag = 0.0;
 #pragma unroll
@@ -129,15 +132,17 @@ __device__ void jacobi_eigen_l(LMat<n> A, double (&ev)[n], LMat<n> V)
                     A(p, k) = c * lp[k] - s * lq[k];
                     A(q, k) = s * lp[k] + c * lq[k];
                 }
+                if constexpr (WANT_V) {
 #pragma unroll
-                for (int k = 0; k < n; k++) {
-                    lp[k] = V(k, p);
-                    lq[k] = V(k, q);
-                }
+                    for (int k = 0; k < n; k++) {
+                        lp[k] = V(k, p);
+                        lq[k] = V(k, q);
+                    }
 #pragma unroll
-                for (int k = 0; k < n; k++) {
-                    V(k, p) = c * lp[k] - s * lq[k];
-                    V(k, q) = s * lp[k] + c * lq[k];
+                    for (int k = 0; k < n; k++) {
+                        V(k, p) = c * lp[k] - s * lq[k];
+                        V(k, q) = s * lp[k] + c * lq[k];
+                    }
                 }
             }
     }
@@ -312,7 +317,7 @@ __device__ uint32_t solve_F(const RoiSet& rs, double* F, double* pool)
         for (int a = 0; a < 8; a++)
 #pragma unroll
             for (int b = 0; b < 8; b++) A8(a, b) = JtJ[a][b];
-        jacobi_eigen_l<8>(A8, e8, V8);
+        jacobi_eigen_l<8, false>(A8, e8, V8);  // eigenvalues only: the conditioning
     }
     double lo = e8[0], hi = e8[0];
     for (int a = 1; a < 8; a++) {
