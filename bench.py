@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 METRIC = "pattern pairs/sec (demons+XCF, 256² px, 10°) warm-start vs plain; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
-FP32_PEAK_TFLOPS = 157.3  # vector FP32 (256 CUs, 2.4 GHz)
+FP32_NOPK_TFLOPS = 78.6  # vector FP32 without packed instructions: 256 CUs x 128 flop/clk x 2.4 GHz
+LDS_PEAK_TBS = 78.6  # LDS: 256 CUs x 128 B/clk x 2.4 GHz
 BYTES_PER_PX_ITER = 24  # read field 8 + ref 4 + test 4 (gather), write field 8
 CNN_FLOP_PER_PAIR = 11.55e9  # network forward pass, 256 x 256 input
 WEIGHTS = os.path.join(ROOT, "paper_1907_05993_amd", "weights", "warm_cnn_256.bin")
@@ -67,6 +68,8 @@ def main():
                     help="also time the warm start with this iteration cap per level (0 = skip)")
     ap.add_argument("--fallback", type=float, default=0.5, help="fallback misfit threshold, coarse-grid px")
     ap.add_argument("--cpu-sample", type=int, default=512, help="pairs timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--parity-pairs", type=int, default=16,
+                    help="sampled pairs of the timed batch compared with the oracle in the CPU leg (0 = skip)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "demons_traffic.json"))
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly")
     ap.add_argument("--no-resident", action="store_true",
@@ -114,6 +117,14 @@ def main():
     t0 = time.time()
     specs = S.workload_specs(args.workload, n=n)
     d_refs, d_tests, _ = ebsd.gen_pairs(specs, labels=False)
+    # pairs whose outputs the CPU leg compares with the oracle: rendered by the CPU generator
+    # (same specs, the same distribution), so that the oracle's inputs do not come from the library
+    par_idx = np.linspace(0, n - 1, min(args.parity_pairs, n)).round().astype(int) if args.parity_pairs > 0 else None
+    par_in = None
+    if par_idx is not None:
+        par_in = S.render_batch([specs[i] for i in par_idx])
+        d_refs[par_idx] = torch.from_numpy(par_in[0]).cuda()
+        d_tests[par_idx] = torch.from_numpy(par_in[1]).cuda()
     torch.cuda.synchronize()
     rv_true = np.array([rotvec_of(rotation_of(s.F)) for s in specs])
     Fiso = np.stack([s.F / np.cbrt(np.linalg.det(s.F)) for s in specs])
@@ -132,18 +143,20 @@ def main():
         reg.set_resident(not args.no_resident)
         return reg
 
-    def timed(reg, label, tune=True, extras=True):
+    def timed(reg, label, tune=True, extras=True, parity_idx=None):
         # strip heights per level, outside the timed region
         tuned = reg.autotune(d_refs, d_tests) if tune else {}
         fused = reg.fused_heights(H, W)
         reg.set_timing(True)
+        # every timed call writes the displacement field of every pair (the registration's
+        # first output), as well as F, R, the rotation vector and the per-ROI shifts
         for i in range(args.warmup):
-            reg.register(d_refs, d_tests, want_field=False)
+            reg.register(d_refs, d_tests, want_field=True)
             torch.cuda.synchronize()
         torch.cuda.synchronize()
         ts = time.perf_counter()
         for i in range(args.steps):
-            out = reg.register(d_refs, d_tests, want_field=False)
+            out = reg.register(d_refs, d_tests, want_field=True)
         torch.cuda.synchronize()
         el = time.perf_counter() - ts
         level_ms, total_ms = reg.timing()
@@ -164,12 +177,20 @@ def main():
             return np.abs(e - eps_true).max(axis=(1, 2))
         serr = strain_err(out["F"].cpu().numpy())
         serr1 = strain_err(out["F_first"].cpu().numpy())
-        return dict(R_finite=out["R_finite"], ssim=ssim, serr=serr, serr1=serr1, elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
+        keep = None
+        if parity_idx is not None:
+            # the sampled pairs' outputs, checked against the oracle in the CPU leg below
+            sel = torch.as_tensor(parity_idx, device=out["F"].device)
+            keep = {k: out[k][sel].cpu().numpy() for k in ("field", "F", "R_finite", "iters", "status")}
+            if "warm_field" in out:
+                keep["warm_field"] = out["warm_field"][sel].cpu().numpy()
+        out.pop("field", None)
+        return dict(parity=keep, R_finite=out["R_finite"], ssim=ssim, serr=serr, serr1=serr1, elapsed=el, level_ms=level_ms, total_ms=total_ms, iters=iters, status=st, err=err,
                     tuned=tuned, fused=fused, err_first=err_first, mae_first=out["mae_first"].cpu().numpy(),
                     mae=out["mae"].cpu().numpy(), ph=out["peak_height"].cpu().numpy().mean(axis=1))
 
-    warm = timed(make(True, args.cap), "warm start")
-    plain = None if args.skip_plain else timed(make(False, args.cap), "plain")
+    warm = timed(make(True, args.cap), "warm start", parity_idx=par_idx)
+    plain = None if args.skip_plain else timed(make(False, args.cap), "plain", parity_idx=par_idx)
     short = timed(make(True, args.short_cap), f"warm start, cap {args.short_cap}") if args.short_cap > 0 else None
     # the conventional first pass (ROI cross-correlation of the unremapped patterns), with and
     # without the remap + second pass: methods (c) and (a) of section 3's comparison
@@ -210,7 +231,13 @@ def main():
     torch.cuda.synchronize()
     second_ms = e0.elapsed_time(e1) / 3
     import math
-    xcf_flop = 20 * 3 * 5 * Nr * Nr * math.log2(Nr * Nr) * n  # three complex 2-D FFTs per ROI
+    # two complex 2-D FFTs executed per ROI: the forward transform of the packed pair
+    # z = a + i b and the inverse transform of the cross-power spectrum
+    xcf_flop = 20 * 2 * 5 * Nr * Nr * math.log2(Nr * Nr) * n
+    # LDS traffic per ROI: the gather writes the N x N complex tile once, every FFT pass (three
+    # radix-2 stages in registers) reads and writes it, the cross-power step reads and writes it
+    xcf_passes = 2 * 2 * -(-int(math.log2(Nr)) // 3)  # rows and columns, forward and inverse
+    xcf_lds_bytes = 20 * n * 8 * Nr * Nr * (1 + 2 * xcf_passes + 2)
 
     # network forward alone on the same batch (chunks of 256), HIP events on torch's stream
     net = ebsd.Cnn(device=0, max_batch=256)
@@ -316,15 +343,21 @@ def main():
             "forward_ms_per_step": round(cnn_ms, 3),
         },
         "roofline_xcf": {
-            "bound": "alu",
+            "bound": "lds",
             "kernel": f"k_xcf_stage<{Nr}> (ROI cross-correlation core: Hann window, packed complex FFTs in LDS, "
                       "product, inverse FFT, argmax and 2-D quadratic peak fit), 20 ROIs per pair",
-            "achieved": round(xcf_flop / (xcf_ms * 1e-3) / 1e12, 2),
-            "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(xcf_flop / (xcf_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+            "achieved": round(xcf_lds_bytes / (xcf_ms * 1e-3) / 1e12, 2),
+            "peak": LDS_PEAK_TBS,
+            "unit": "TB/s",
+            "frac": round(xcf_lds_bytes / (xcf_ms * 1e-3) / 1e12 / LDS_PEAK_TBS, 4),
             "traffic": None,
-            "flop_model": "3 complex 2-D FFTs of N^2 points per ROI at 5 N^2 log2 N^2 flop each",
+            "lds_model": f"8 N^2 bytes per tile sweep; per ROI the gather's write, {xcf_passes} FFT passes "
+                         "(read + write) and the cross-power step (read + write)",
+            "flop": {"achieved_tflops": round(xcf_flop / (xcf_ms * 1e-3) / 1e12, 2), "peak_tflops": FP32_NOPK_TFLOPS,
+                     "frac": round(xcf_flop / (xcf_ms * 1e-3) / 1e12 / FP32_NOPK_TFLOPS, 4),
+                     "model": "2 complex 2-D FFTs of N^2 points per ROI (packed forward, inverse) at "
+                              "5 N^2 log2 N^2 flop each; peak without packed FP32 instructions (the build "
+                              "disables them): 256 CUs x 128 flop/clk x 2.4 GHz"},
             "ms_per_step": round(xcf_ms, 3),
             "second_pass_ms_per_step": round(second_ms, 3),
         },
@@ -446,12 +479,14 @@ def main():
         }
         del p_refs, p_tests
 
-    if args.cpu_sample > 0:
+    if args.cpu_sample > 0 or par_idx is not None:
         import oracle
-        m = min(args.cpu_sample, n)
-        refs = d_refs[:m].cpu().numpy()
-        tests = d_tests[:m].cpu().numpy()
         op = oracle.make_params(levels=3, iters=args.cap, sigma=1.0, tol=args.tol, roi_size=w["roi"], n_roi=20)
+    if args.cpu_sample > 0:
+        m = min(args.cpu_sample, n)
+        tr = time.perf_counter()
+        refs, tests = S.render_batch(specs[:m])  # the CPU generator: the oracle's inputs
+        log(f"[bench] rendered {m} pairs on the CPU in {time.perf_counter() - tr:.1f} s")
         tc = time.perf_counter()
         o = oracle.register_batch(refs, tests, op, want_field=False)
         dt = time.perf_counter() - tc
@@ -460,10 +495,51 @@ def main():
             "unit": "pairs/s",
             "cores": int(o["threads"]),
             "kind": "oracle",
-            "sample": f"first {m} pairs of the same workload, plain path (the oracle has no network), "
-                      f"FP64 C oracle, OpenMP one pair per thread ({dt:.1f} s wall)",
+            "sample": f"first {m} pairs of the same workload (rendered by the CPU generator), plain path (the "
+                      f"oracle has no network), FP64 C oracle, OpenMP one pair per thread ({dt:.1f} s wall)",
         }
         log(f"[bench] cpu oracle: {m} pairs in {dt:.1f} s on {o['threads']} threads")
+    if par_idx is not None:
+        # the timed calls' outputs of the sampled pairs against the oracle: field differences
+        # (median and 95th percentile of |du| per pair; the iteration is chaotic at full depth in
+        # noise-dominated pixels), iteration counts, and F from the GPU's R_finite (the oracle's
+        # second pass) to 1e-6.  The warm run's oracle starts from the same initial field (the
+        # network field fitted to Eq. (2), or zero where the GPU fell back).
+        from oracle import cnn as ocnn
+        pcs = (0.5 * W - 0.5, 0.5 * H - 0.5, 0.7 * W)
+        par = {"pairs": [int(i) for i in par_idx],
+               "bars": {"field_median_px": 2e-3, "field_p95_px": 0.05, "F_common_R_finite": 1e-6,
+                        "iters": "equal"}}
+        ok_all = True
+        for name, r in (("warm", warm), ("plain", plain)):
+            if r is None or r["parity"] is None:
+                continue
+            g = r["parity"]
+            tp = time.perf_counter()
+            if name == "warm":
+                u0 = np.stack([ocnn.warm_init_field(g["warm_field"][k].astype(np.float64), H, W, pcs, 2,
+                                                    bool(g["status"][k] & ebsd.WARM_USED))
+                               for k in range(len(par_idx))])
+                o = oracle.register_batch(par_in[0], par_in[1], op, u_init=u0)
+            else:
+                o = oracle.register_batch(par_in[0], par_in[1], op)
+            d = np.sqrt(((g["field"].astype(np.float64) - o["field"]) ** 2).sum(axis=1)).reshape(len(par_idx), -1)
+            med = np.median(d, axis=1)
+            p95 = np.percentile(d, 95, axis=1)
+            rms = np.sqrt((d ** 2).mean(axis=1))
+            o2 = oracle.register_batch(par_in[0], par_in[1], op, rfin=g["R_finite"], want_field=False)
+            dF = np.abs(g["F"] - o2["F"]).max(axis=(1, 2))
+            iters_eq = bool(np.array_equal(g["iters"], o["iters"]))
+            ok = bool((med <= 2e-3).all() and (p95 <= 0.05).all() and (dF <= 1e-6).all() and iters_eq)
+            ok_all = ok_all and ok
+            par[name] = {"field_median_px_max": float(med.max()), "field_p95_px_max": float(p95.max()),
+                         "field_rms_px_median": float(np.median(rms)), "F_common_R_finite_max": float(dF.max()),
+                         "iters_equal": iters_eq, "pass": ok}
+            log(f"[bench] parity {name}: {len(par_idx)} pairs, field median <= {med.max():.1e} px, "
+                f"p95 <= {p95.max():.1e} px, |dF| <= {dF.max():.1e}, iterations equal {iters_eq} "
+                f"({time.perf_counter() - tp:.1f} s)")
+        par["pass"] = ok_all
+        rec["parity"] = par
     print(json.dumps(rec), flush=True)
 
 

@@ -148,6 +148,8 @@ def lib():
         L.orc_fft1.argtypes = [d, d, C.c_int, C.c_int]
         L.orc_fft2.argtypes = [d, d, C.c_int, C.c_int]
         L.orc_xcf.argtypes = [d, d, C.c_int, C.c_int, d, d, d]
+        L.orc_peak_subpixel.restype = C.c_int
+        L.orc_peak_subpixel.argtypes = [d, d]
         L.orc_register_pair.restype = C.c_int
         L.orc_register_pair.argtypes = [f, f, C.c_int, C.c_int, C.POINTER(Params), d, d,
                                         C.POINTER(_Outputs)]
@@ -463,6 +465,17 @@ def xcf(A, B, window=1):
     ph = np.empty(1)
     lib().orc_xcf(_d(A), _d(B), N, int(window), _d(Cm), _d(q), _d(ph))
     return q, float(ph[0]), Cm
+
+
+def peak_subpixel(nb):
+    """Sub-pixel offset (dx, dy) of a correlation peak from its 3 x 3
+    neighbourhood nb[dy + 1, dx + 1] (section 2's interpolated peak: the
+    quadratic surface through the neighbourhood, its stationary point when
+    negative definite, each component clamped to +-1).  Returns (d, ok)."""
+    nb = np.ascontiguousarray(np.asarray(nb, np.float64).reshape(9))
+    d = np.zeros(2)
+    ok = lib().orc_peak_subpixel(_d(nb), _d(d))
+    return d, bool(ok)
 
 
 def pc_pixels(H, W, params):

@@ -284,3 +284,27 @@ def warm_fallback(field, H, W, pcs, radius_frac=0.3, threshold=0.5, levels=3):
     d2 = (px - cx - q[:, 0]) ** 2 + (py - cy - q[:, 1]) ** 2
     rms = float(np.sqrt(d2.mean()))
     return rms / 2 ** (levels - 1) <= threshold, rms, F
+
+
+def warm_init_field(field, H, W, pcs, mode, use, levels=3):
+    """Coarsest-level initial field of the warm start (units: coarsest-level px).
+
+    field: [H/4, W/4, 2] predicted shifts (full-resolution px); mode 1 starts
+    demons from the prediction itself, mode 2 from the Eq. (2) model fitted to
+    it (warm_fallback's F evaluated at the grid points); use = False gives the
+    zero field of the fallback.  Returns [2, H/4, W/4].
+    """
+    f = np.asarray(field, np.float64)
+    u0 = np.zeros((2, H // 4, W // 4))
+    if not use:
+        return u0
+    if mode == 1:
+        u0[:] = np.moveaxis(f, -1, 0)
+    else:
+        _, _, Ff = warm_fallback(f, H, W, pcs, threshold=np.inf, levels=levels)
+        gx, gy = grid_points(H, W)
+        r = np.stack([gx - pcs[0], gy - pcs[1], np.full_like(gx, pcs[2])])
+        v = np.einsum("ij,jhw->ihw", Ff, r)
+        u0[0] = pcs[0] + pcs[2] * v[0] / v[2] - gx
+        u0[1] = pcs[1] + pcs[2] * v[1] / v[2] - gy
+    return u0 / 2 ** (levels - 1)

@@ -1201,6 +1201,34 @@ void orc_fft2(double* re, double* im, int N, int inverse)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Sub-pixel offset of a correlation peak (section 2 interpolates the peak of
+ * the cross-correlation): the quadratic surface through the 3 x 3
+ * neighbourhood nb[(dy + 1) * 3 + (dx + 1)], dx, dy in {-1, 0, 1}, around the
+ * integer maximum.  Central differences give its gradient g = (Cx, Cy) and
+ * Hessian Hs = [[Cxx, Cxy], [Cxy, Cyy]] at the centre, exactly for a
+ * quadratic; its stationary point d = -Hs^-1 g is the peak when Hs is
+ * negative definite (Cxx < 0 and det Hs > 0).  Each component is clamped to
+ * +-1; a surface that is not negative definite gives d = 0 (return 0).      */
+int orc_peak_subpixel(const double* nb, double* d)
+{
+#define NB(dy, dx) nb[((dy) + 1) * 3 + ((dx) + 1)]
+    const double c0 = NB(0, 0);
+    const double gx = 0.5 * (NB(0, 1) - NB(0, -1));
+    const double gy = 0.5 * (NB(1, 0) - NB(-1, 0));
+    const double hxx = NB(0, 1) - 2.0 * c0 + NB(0, -1);
+    const double hyy = NB(1, 0) - 2.0 * c0 + NB(-1, 0);
+    const double hxy = 0.25 * (NB(1, 1) - NB(1, -1) - NB(-1, 1) + NB(-1, -1));
+#undef NB
+    const double det = hxx * hyy - hxy * hxy;
+    d[0] = 0.0;
+    d[1] = 0.0;
+    if (!(hxx < 0.0 && det > 0.0)) return 0;
+    d[0] = clampd(-(hyy * gx - hxy * gy) / det, -1.0, 1.0);
+    d[1] = clampd(-(hxx * gy - hxy * gx) / det, -1.0, 1.0);
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
 /* ROI cross-correlation and its peak (section 2).
  *   A = reference ROI, B = test ROI (N x N); each loses its own mean, is
  *   multiplied by the symmetric Hann window h (x) h, h[n] = 0.5 - 0.5
@@ -1260,23 +1288,15 @@ void orc_xcf(const double* A, const double* B, int N, int window, double* C, dou
         if (br[i] > br[best]) best = i;
     int ky = (int)(best / N), kx = (int)(best % N);
     double c0 = br[best];
-#define CAT(dy, dx) br[(size_t)((ky + (dy) + N) % N) * N + (size_t)((kx + (dx) + N) % N)]
-    double gx = 0.5 * (CAT(0, 1) - CAT(0, -1));
-    double gy = 0.5 * (CAT(1, 0) - CAT(-1, 0));
-    double hxx = CAT(0, 1) - 2.0 * c0 + CAT(0, -1);
-    double hyy = CAT(1, 0) - 2.0 * c0 + CAT(-1, 0);
-    double hxy = 0.25 * (CAT(1, 1) - CAT(1, -1) - CAT(-1, 1) + CAT(-1, -1));
-#undef CAT
-    double det = hxx * hyy - hxy * hxy;
-    double dx = 0.0, dy = 0.0;
-    if (hxx < 0.0 && det > 0.0) {
-        dx = clampd(-(hyy * gx - hxy * gy) / det, -1.0, 1.0);
-        dy = clampd(-(hxx * gy - hxy * gx) / det, -1.0, 1.0);
-    }
+    double nb[9], d[2];
+    for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++)
+            nb[(dy + 1) * 3 + (dx + 1)] = br[(size_t)((ky + dy + N) % N) * N + (size_t)((kx + dx + N) % N)];
+    orc_peak_subpixel(nb, d);
     int sx = kx < N / 2 ? kx : kx - N;
     int sy = ky < N / 2 ? ky : ky - N;
-    q[0] = sx + dx;
-    q[1] = sy + dy;
+    q[0] = sx + d[0];
+    q[1] = sy + d[1];
     double nrm = sqrt(ea * eb);
     *ph = nrm > 0.0 ? c0 / nrm : 0.0;
     if (C) memcpy(C, br, sizeof(double) * NN);

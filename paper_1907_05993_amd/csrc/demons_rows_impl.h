@@ -670,11 +670,17 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
     const int unit = lb - b * nunits;
     const int strip = unit / nsegs, seg = unit - strip * nsegs;
     const PairState st = bk->state[b];
-    if (st.stop >= 0) return;  // uniform
+    const int k = 2 * L;
+    // A stop at k - 1 can only have been written by unit 0 of this launch
+    // (earlier launches record stops at most k - 2); the other units of the
+    // pair still owe the recompute of their strips below, and each reaches
+    // that decision again from the same partial sums.  Any unit may start
+    // after unit 0 has written the state when the grid exceeds one dispatch
+    // wave, so the early exit must not take that stop.
+    if (st.stop >= 0 && st.stop != k - 1) return;  // uniform
     const int h = bk->lh[level], w = bk->lw[level];
     const int64_t npart = (int64_t)bk->nb * bk->max_tiles;
     const int64_t pofs = (int64_t)b * bk->max_tiles;
-    const int k = 2 * L;
     bool recompute = false;
     if (tol > 0.0f && L > 0) {
         const double hw = (double)h * (double)w, sc = (double)(1 << level);

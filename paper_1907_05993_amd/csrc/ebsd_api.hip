@@ -48,8 +48,10 @@ struct ebsd_handle {
     // strip height of the two-iterations-per-launch kernel per level size; a
     // level size absent here (or 0) runs one iteration per launch
     std::map<std::pair<int, int>, int> fused_ty;
-    // batch size each level size was tuned on (absent: forced or read from the cache file)
-    std::map<std::pair<int, int>, int> tuned_nb;
+    // batch size each level size's strip height and two-iteration strip
+    // height were tuned on (absent: forced or read from the cache file); kept
+    // apart so that forcing one of them leaves the other's record in place
+    std::map<std::pair<int, int>, int> tuned_nb_strip, tuned_nb_fused;
     std::string tune_cache;  // EBSD_TUNE_CACHE at create time (may be empty)
     // captured launch sequences per bucket configuration (replayed with
     // hipGraphLaunch); the capture itself runs on a private stream
@@ -70,16 +72,16 @@ namespace {
 // A tuned entry is not used for a batch under a quarter of the one it was
 // tuned on: the fastest decomposition of a large batch starves a small one
 // of workgroups.
-bool tuned_applies(const ebsd_handle* h, int lh, int lw, int nb)
+bool tuned_applies(const std::map<std::pair<int, int>, int>& rec, int lh, int lw, int nb)
 {
-    auto it = h->tuned_nb.find(std::make_pair(lh, lw));
-    return it == h->tuned_nb.end() || 4 * (int64_t)nb >= it->second;
+    auto it = rec.find(std::make_pair(lh, lw));
+    return it == rec.end() || 4 * (int64_t)nb >= it->second;
 }
 
 int strip_ty_for(const ebsd_handle* h, int lh, int lw, int nb = 1 << 20)
 {
     auto it = h->strip_ty.find(std::make_pair(lh, lw));
-    if (it != h->strip_ty.end() && tuned_applies(h, lh, lw, nb)) return it->second;
+    if (it != h->strip_ty.end() && tuned_applies(h->tuned_nb_strip, lh, lw, nb)) return it->second;
     constexpr int kFill = 512;
     for (int ty = kDefaultStripTY; ty > kMinStripTY; ty /= 2)
         if ((int64_t)nb * ((lh + ty - 1) / ty) >= kFill) return ty;
@@ -88,7 +90,7 @@ int strip_ty_for(const ebsd_handle* h, int lh, int lw, int nb = 1 << 20)
 
 int fused_ty_for(const ebsd_handle* h, int lh, int lw, int nb = 1 << 20)
 {
-    if (!rows_cpl(lw) || !tuned_applies(h, lh, lw, nb)) return 0;
+    if (!rows_cpl(lw) || !tuned_applies(h->tuned_nb_fused, lh, lw, nb)) return 0;
     auto it = h->fused_ty.find(std::make_pair(lh, lw));
     return it == h->fused_ty.end() ? 0 : it->second;
 }
@@ -634,7 +636,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
                 }
             }
             h->strip_ty[std::make_pair(lh, lw)] = best_ty;
-            h->tuned_nb[std::make_pair(lh, lw)] = nb;
+            h->tuned_nb_strip[std::make_pair(lh, lw)] = nb;
             // two iterations per launch: 3 launches (6 iterations) against the best 6 single launches
             int best_fty = 0;
             for (int fty : {16, 32, 64, 128}) {
@@ -653,6 +655,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
             }
             if (best_fty) h->fused_ty[std::make_pair(lh, lw)] = best_fty;
             else h->fused_ty.erase(std::make_pair(lh, lw));
+            h->tuned_nb_fused[std::make_pair(lh, lw)] = nb;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -960,7 +963,7 @@ int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int3
 {
     if (!h || level_h <= 0 || level_w <= 0 || !strip_ty_ok(level_w, ty)) return EBSD_EINVAL;
     h->strip_ty[std::make_pair((int)level_h, (int)level_w)] = ty;
-    h->tuned_nb.erase(std::make_pair((int)level_h, (int)level_w));  // forced: applies to every batch
+    h->tuned_nb_strip.erase(std::make_pair((int)level_h, (int)level_w));  // forced: applies to every batch
     return EBSD_OK;
 }
 
@@ -977,7 +980,7 @@ int ebsd_set_fused_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int3
     const auto key = std::make_pair((int)level_h, (int)level_w);
     if (rows) h->fused_ty[key] = rows;
     else h->fused_ty.erase(key);
-    h->tuned_nb.erase(key);  // forced: applies to every batch
+    h->tuned_nb_fused.erase(key);  // forced: applies to every batch
     return EBSD_OK;
 }
 

@@ -1,0 +1,137 @@
+"""The oracle's multi-resolution demons iteration with FP32 storage and FP32
+arithmetic (NumPy float32), for the test suite only.
+
+The FP64 oracle (oracle/ebsd_oracle.c) takes each step of section 1's
+multi-resolution demons and Eq. (1) in the paper's order; this module takes
+the same steps in the same order, but every image, field and intermediate is
+a float32 and every operation rounds to float32 (normalisation statistics
+excepted: they are FP64, as on the GPU).  It shares no code with the library.
+
+Its purpose is the size of the difference that FP32 rounding alone makes after
+many iterations: Eq. (1)'s update is ill-conditioned in noise-dominated pixels
+(|R - T(x + u)| and |grad R| both small), so two correct implementations that
+round differently drift apart with depth.  The GPU's difference from the FP64
+oracle at full depth is judged against this module's difference from it.
+"""
+import numpy as np
+
+f32 = np.float32
+
+
+def normalize(p):
+    """z-score with FP64 statistics (population std), stored as float32."""
+    d = np.asarray(p, np.float64)
+    m = d.mean()
+    sd = np.sqrt(((d - m) ** 2).mean())
+    return ((d - m) / sd).astype(f32)
+
+
+def restrict(img):
+    """Factor-2 [1,3,3,1]/8 restriction with clamped borders (sizes halve rounding up)."""
+    def along(a, axis):
+        n = a.shape[axis]
+        i = np.arange((n + 1) // 2)
+        take = lambda k: np.take(a, np.clip(k, 0, n - 1), axis=axis)
+        return (take(2 * i - 1) + f32(3) * take(2 * i) + f32(3) * take(2 * i + 1) + take(2 * i + 2)) / f32(8)
+    return along(along(img, 1), 0)
+
+
+def gradient(f):
+    """Central differences, one-sided on the border (numpy.gradient's rule)."""
+    gx = np.empty_like(f)
+    gy = np.empty_like(f)
+    gx[:, 1:-1] = (f[:, 2:] - f[:, :-2]) / f32(2)
+    gx[:, 0] = f[:, 1] - f[:, 0]
+    gx[:, -1] = f[:, -1] - f[:, -2]
+    gy[1:-1] = (f[2:] - f[:-2]) / f32(2)
+    gy[0] = f[1] - f[0]
+    gy[-1] = f[-1] - f[-2]
+    return gx, gy
+
+
+def bilinear(img, x, y):
+    """Bilinear samples at (x, y), coordinates clamped to the image before the floor."""
+    H, W = img.shape
+    xc = np.clip(x, f32(0), f32(W - 1))
+    yc = np.clip(y, f32(0), f32(H - 1))
+    x0 = np.floor(xc).astype(np.int64)
+    y0 = np.floor(yc).astype(np.int64)
+    fx = xc - x0.astype(f32)
+    fy = yc - y0.astype(f32)
+    x1 = np.minimum(x0 + 1, W - 1)
+    y1 = np.minimum(y0 + 1, H - 1)
+    one = f32(1)
+    top = (one - fx) * img[y0, x0] + fx * img[y0, x1]
+    bot = (one - fx) * img[y1, x0] + fx * img[y1, x1]
+    return (one - fy) * top + fy * bot
+
+
+def taps(sigma):
+    r = int(np.floor(3.0 * sigma + 0.5))
+    w = np.exp(-np.arange(-r, r + 1, dtype=np.float64) ** 2 / (2.0 * sigma * sigma))
+    return (w / w.sum()).astype(f32), r
+
+
+def smooth(v, w, r):
+    """Separable Gaussian with replicated borders: rows, then columns."""
+    H, W = v.shape
+    acc = np.zeros_like(v)
+    for j in range(-r, r + 1):
+        acc = acc + w[j + r] * v[:, np.clip(np.arange(W) + j, 0, W - 1)]
+    out = np.zeros_like(v)
+    for j in range(-r, r + 1):
+        out = out + w[j + r] * acc[np.clip(np.arange(H) + j, 0, H - 1), :]
+    return out
+
+
+def demons_iter(R, T, gx, gy, u, w, r):
+    """One Eq. (1) step on the accumulated field, then its smoothing; returns
+    (u_new, RMS of the update)."""
+    H, W = R.shape
+    ys, xs = np.mgrid[0:H, 0:W]
+    wv = bilinear(T, xs.astype(f32) + u[0], ys.astype(f32) + u[1])
+    a = R - wv
+    den = gx * gx + gy * gy + a * a
+    ok = den > f32(1e-9)
+    safe = np.where(ok, den, f32(1))
+    dux = np.where(ok, a * gx / safe, f32(0))
+    duy = np.where(ok, a * gy / safe, f32(0))
+    v = np.stack([u[0] + dux, u[1] + duy])
+    un = np.stack([smooth(v[0], w, r), smooth(v[1], w, r)]) if r > 0 else v
+    d = (un - u).astype(np.float64)
+    return un, float(np.sqrt((d ** 2).sum(axis=0).mean()))
+
+
+def prolong(u, H, W):
+    """x2 bilinear on the half-pixel map (fine i -> coarse (i - 0.5) / 2), values doubled."""
+    ys, xs = np.mgrid[0:H, 0:W]
+    x = (xs.astype(f32) - f32(0.5)) / f32(2)
+    y = (ys.astype(f32) - f32(0.5)) / f32(2)
+    return np.stack([f32(2) * bilinear(u[c], x, y) for c in range(2)])
+
+
+def demons(ref, test, levels=3, iters=150, sigma=1.0, tol=0.0, u_init=None):
+    """Multi-resolution demons of one pair; returns (field [2, H, W] float32,
+    iteration counts per level, finest first)."""
+    R = [normalize(ref)]
+    T = [normalize(test)]
+    for _ in range(1, levels):
+        R.append(restrict(R[-1]))
+        T.append(restrict(T[-1]))
+    w, r = taps(sigma) if sigma > 0 else (None, 0)
+    hc, wc = R[-1].shape
+    u = np.zeros((2, hc, wc), f32) if u_init is None else np.asarray(u_init, f32).copy()
+    its = [0] * levels
+    caps = [iters] * levels if np.isscalar(iters) else list(iters)
+    for l in range(levels - 1, -1, -1):
+        gx, gy = gradient(R[l])
+        k = 0
+        while k < caps[l]:
+            u, rms = demons_iter(R[l], T[l], gx, gy, u, w, r)
+            k += 1
+            if tol > 0 and (1 << l) * rms < tol:
+                break
+        its[l] = k
+        if l > 0:
+            u = prolong(u, *R[l - 1].shape)
+    return u, its

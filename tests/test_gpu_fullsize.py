@@ -21,6 +21,10 @@ def E():
     return ebsd
 
 
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
 def check_all(g, n, levels=3):
     """Properties of every pair: det F = 1, R orthonormal with det 1, the
     rotation vector of R, finite outputs, one of CONVERGED / HIT_CAP."""
@@ -50,7 +54,12 @@ def test_scan_map_4096_full_size(E, orc):
     print(f"case: scan map {n} points at 400x400", flush=True)
     _, d_tests, _ = E.gen_pairs(tests, labels=False)
     grains = sorted(refs)
-    d_ref, _, _ = E.gen_pairs([refs[k] for k in grains], labels=False)
+    # the references and the sampled test patterns checked against the oracle come from the
+    # CPU generator (the oracle's inputs never come from the library); the rest from the GPU's
+    idx = [0, 1337, 2048, 4095]
+    d_ref = cuda(np.stack([S.render_pair(refs[k])[0] for k in grains]))
+    for i in idx:
+        d_tests[i] = cuda(S.render_pair(tests[i])[1])
     slot = {gg: i for i, gg in enumerate(grains)}
     ref_list = [d_ref[slot[gg]] for gg in ref_ids]
     p = E.Params(levels=3, iters=(150,) * 3, sigma_px=1.0, tol_px=1e-4, roi_size=128, n_roi=20)
@@ -76,7 +85,6 @@ def test_scan_map_4096_full_size(E, orc):
           % (np.median(err), np.percentile(err, 95), np.median(err[small]), small.sum()))
     assert np.median(err[small]) < 5e-3
     # sampled pairs against the oracle from the same R_finite
-    idx = [0, 1337, 2048, 4095]
     r = np.stack([d_ref[slot[ref_ids[i]]].cpu().numpy() for i in idx])
     t = d_tests[idx].cpu().numpy()
     op = orc.make_params(levels=3, iters=150, sigma=1.0, tol=1e-4, roi_size=128, n_roi=20)
@@ -106,6 +114,17 @@ def test_mixed_size_stream_16384(E, orc):
         for k, i in enumerate(idx):
             refs[i] = r[k]
             tests[i] = t[k]
+    # 64 sampled pairs (26 / 26 / 12 of 128 / 256 / 512 px, seeded) are checked against the
+    # oracle below; they come from the CPU generator (the oracle's inputs never come from the
+    # library)
+    rs = np.random.default_rng(56)
+    sampled = []
+    for N, k in ((128, 26), (256, 26), (512, 12)):
+        idx = sorted(rs.choice(np.nonzero(sizes == N)[0], size=k, replace=False).tolist())
+        for i in idx:
+            r1, t1 = S.render_pair(specs[i])
+            refs[i], tests[i] = cuda(r1), cuda(t1)
+        sampled.append((N, k, idx))
     weights = os.path.join(os.path.dirname(E.__file__), "weights", "warm_cnn_256.bin")
     p = E.Params(levels=3, iters=(150,) * 3, sigma_px=1.0, tol_px=1e-4, roi_size=32, n_roi=20, warm_start=2)
     reg = E.Registrar(p)
@@ -133,10 +152,8 @@ def test_mixed_size_stream_16384(E, orc):
               % (N, e.size, 100 * used[sizes == N].mean(), np.median(e), np.percentile(e, 95)))
     # 64 sampled pairs (26 / 26 / 12 of 128 / 256 / 512 px, seeded) against the oracle from the
     # same R_finite: the distribution of the deformation-gradient differences
-    rs = np.random.default_rng(56)
     dFs = []
-    for N, k in ((128, 26), (256, 26), (512, 12)):
-        idx = sorted(rs.choice(np.nonzero(sizes == N)[0], size=k, replace=False).tolist())
+    for N, k, idx in sampled:
         r = np.stack([refs[i].cpu().numpy() for i in idx])
         t = np.stack([tests[i].cpu().numpy() for i in idx])
         op = orc.make_params(levels=3, iters=150, sigma=1.0, tol=1e-4, roi_size=32, n_roi=20)

@@ -47,7 +47,7 @@ def test_fused_equals_single(E, name, H, iters, tol):
     n = 4 if H == 256 else 1
     refs, tests = gen(name, n)
     a = run(E, refs, tests, H, H, iters, tol, 0)
-    for rows in (16, 32, 64):
+    for rows in (16, 32, 64, 128):
         b = run(E, refs, tests, H, H, iters, tol, rows)
         print("iters per level (single):", a["iters"].tolist(), "status", a["status"].tolist())
         for k in ("field", "iters", "status", "F", "q1", "q2", "R_finite"):
@@ -67,7 +67,7 @@ def test_fused_equals_single_wide(E, N):
     refs, tests = S.render_batch(specs)
     for iters, tol in ((9, 0.0), (60, 0.1)):
         a = run(E, refs, tests, N, N, iters, tol, 0)
-        for rows in (16, 64):
+        for rows in (16, 64, 128):
             b = run(E, refs, tests, N, N, iters, tol, rows)
             for k in ("field", "iters", "status", "F", "q1", "q2", "R_finite"):
                 assert np.array_equal(a[k], b[k]), (k, rows, iters)
@@ -80,7 +80,7 @@ def test_fused_stops_on_odd_and_even_iterations(E):
     refs, tests = gen("batch_256", 4)
     seen = set()
     for tol in (0.15, 0.05, 0.03):
-        a = run(E, refs, tests, 256, 256, 150, tol, 64)
+        a = run(E, refs, tests, 256, 256, 150, tol, 128)
         its = a["iters"]
         for v in its[its < 150].ravel():
             seen.add(int(v) % 2)

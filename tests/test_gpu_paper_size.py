@@ -97,7 +97,12 @@ def test_wide_level_segments_and_tiles_match_oracle(E, orc, strip, tol):
           flush=True)
     gp = E.Params(levels=3, iters=(10,) * 3, sigma_px=1.0, tol_px=tol, roi_size=64, n_roi=20)
     op = orc.make_params(levels=3, iters=10, sigma=1.0, tol=tol, roi_size=64, n_roi=20)
-    _compare(E, orc, refs, tests, gp, op, strict=True, strips={(600, 700): strip})
+    g, _ = _compare(E, orc, refs, tests, gp, op, strict=True, strips={(600, 700): strip})
+    its = g["iters"].cpu().numpy()
+    print("  iterations per level (finest first):", its.tolist())
+    if tol > 0:
+        # a stop on the segmented level itself (level 0), decided from the segment sums
+        assert (its[:, 0] < 10).any()
 
 
 @pytest.mark.parametrize("sigma,iters", [(1.0, 10), (0.0, 25)])
@@ -108,8 +113,11 @@ def test_paper_workload_matches_oracle(E, orc, sigma, iters):
     25 iterations per level) unsmoothed demons is chaotic on these patterns:
     the oracle's own field moves by 0.29 px RMS (24 px at worst) when its
     input is perturbed by 1e-7 relative after only 10 iterations per level,
-    so only the field's median (2e-3 px) is compared, and the second pass from
-    a common R_finite (1e-6)."""
+    so the field is judged against the envelope of FP32 rounding alone: the
+    oracle's iteration with FP32 storage and arithmetic (tests/fp32_demons.py)
+    on the same pair, whose median, 95th percentile and RMS of |du| against
+    the FP64 oracle bound the GPU's to within 4 times; and the second pass
+    from a common R_finite (1e-6)."""
     from paper_1907_05993_amd import synth as S
     w = S.WORKLOADS["paper_1244"]
     specs = S.workload_specs("paper_1244", n=1)
@@ -125,6 +133,12 @@ def test_paper_workload_matches_oracle(E, orc, sigma, iters):
     assert med <= 2e-3
     if sigma > 0:
         assert p95 <= 0.05
+    else:
+        import fp32_demons
+        u32, _ = fp32_demons.demons(refs[0], tests[0], levels=7, iters=iters, sigma=0.0)
+        erms, emed, ep95, _ = field_stats(u32, o["field"][0])
+        print("  FP32 envelope |du|: rms %.1e, median %.1e, p95 %.1e" % (erms, emed, ep95))
+        assert med <= 4.0 * emed and p95 <= 4.0 * ep95 and rms <= 4.0 * erms
     assert np.array_equal(g["iters"].cpu().numpy(), o["iters"])
     o2 = orc.register_batch(refs, tests, op, rfin=g["R_finite"].cpu().numpy(), want_field=False)
     dF = np.abs(g["F"].cpu().numpy() - o2["F"]).max()

@@ -133,10 +133,33 @@ def test_batch_256_stable_depth(E, orc):
 
 
 def test_batch_256_full_depth(E, orc):
-    """256^2 pairs, 3 x 150 (the batch workload's settings) on 4 pairs."""
+    """256^2 pairs, 3 x 150 (the batch workload's settings) on 4 pairs.
+
+    At this depth the field's difference from the FP64 oracle is bounded by
+    what FP32 rounding alone produces: the oracle's iteration with FP32
+    storage and arithmetic (tests/fp32_demons.py, the same steps in the same
+    order) run on the same pairs gives the envelope.  Per statistic of |du|
+    (median, 95th percentile, RMS over the pixels), the GPU's value on each
+    pair stays within 4 times the envelope's (two FP32 orderings of the same
+    iteration differ from the FP64 oracle by up to 3x from each other in RMS),
+    and the median over the pairs within 2 times."""
+    import fp32_demons
     refs, tests, _ = gen("batch_256", 4)
     gp, op = params_pair(E, orc, iters=150, roi=64)
-    compare(E, orc, refs, tests, gp, op, strict=False)
+    g, o = compare(E, orc, refs, tests, gp, op, strict=False)
+    gf = g["field"].cpu().numpy()
+    gs, es = [], []
+    for i in range(4):
+        u32, its = fp32_demons.demons(refs[i], tests[i], levels=3, iters=150, sigma=1.0)
+        grms, gmed, gp95, _ = field_stats(gf[i], o["field"][i])
+        erms, emed, ep95, _ = field_stats(u32, o["field"][i])
+        gs.append((gmed, gp95, grms))
+        es.append((emed, ep95, erms))
+        print("pair %d  |du| GPU vs FP64: median %.1e p95 %.1e rms %.1e;  FP32 envelope: median %.1e p95 %.1e "
+              "rms %.1e" % (i, gmed, gp95, grms, emed, ep95, erms), flush=True)
+    gs, es = np.array(gs), np.array(es)
+    assert np.all(gs <= 4.0 * es), (gs / es).round(2).tolist()
+    assert np.all(np.median(gs, axis=0) <= 2.0 * np.median(es, axis=0)), (np.median(gs, 0), np.median(es, 0))
 
 
 def test_full_batch_1024_sampled(E, orc):

@@ -284,6 +284,78 @@ def test_xcf_subpixel_shift_of_smooth_texture(orc):
     assert np.all(np.abs(q - s) < 0.05)
 
 
+def _quadratic_nb(c, H, p0):
+    """The 3 x 3 samples nb[dy + 1, dx + 1] of f(p) = c + (p - p0)^T H (p - p0) / 2."""
+    nb = np.empty((3, 3))
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            v = np.array([dx, dy], np.float64) - p0
+            nb[dy + 1, dx + 1] = c + 0.5 * v @ H @ v
+    return nb
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_peak_subpixel_exact_on_tilted_quadratic(orc, seed):
+    """Central differences are exact on a quadratic surface, so the fitted
+    peak is its stationary point exactly; tilted surfaces (a large mixed term,
+    of either sign) pin the mixed term's sign and weight."""
+    r = rng(300 + seed)
+    ang = r.uniform(0, np.pi)
+    Q = np.array([[np.cos(ang), -np.sin(ang)], [np.sin(ang), np.cos(ang)]])
+    H = -Q @ np.diag([r.uniform(0.05, 0.3), r.uniform(1.0, 3.0)]) @ Q.T  # negative definite, anisotropic
+    assert abs(H[0, 1]) > 0.05 * abs(H[0, 0])
+    p0 = r.uniform(-0.9, 0.9, size=2)
+    d, ok = orc.peak_subpixel(_quadratic_nb(r.normal(), H, p0))
+    assert ok
+    np.testing.assert_allclose(d, p0, atol=1e-12)
+
+
+def test_peak_subpixel_mixed_term_sign(orc):
+    """The same surface with the mixed term negated has its peak reflected
+    about an axis: a fit that ignores or flips the mixed term fails one of the
+    two."""
+    H = np.array([[-1.0, 0.8], [0.8, -1.0]])
+    p0 = np.array([0.4, 0.1])
+    d, _ = orc.peak_subpixel(_quadratic_nb(0.0, H, p0))
+    np.testing.assert_allclose(d, p0, atol=1e-12)
+    Hm = np.array([[-1.0, -0.8], [-0.8, -1.0]])
+    d, _ = orc.peak_subpixel(_quadratic_nb(0.0, Hm, p0))
+    np.testing.assert_allclose(d, p0, atol=1e-12)
+
+
+@pytest.mark.parametrize("H", [np.array([[-1.0, 1.5], [1.5, -1.0]]),   # saddle (det < 0)
+                               np.array([[1.0, 0.0], [0.0, 2.0]]),     # minimum
+                               np.array([[0.5, 0.0], [0.0, -1.0]]),    # Cxx > 0
+                               np.array([[-1.0, 1.0], [1.0, -1.0]])])  # degenerate (det = 0)
+def test_peak_subpixel_not_negative_definite_gives_zero(orc, H):
+    d, ok = orc.peak_subpixel(_quadratic_nb(1.0, H, np.array([0.3, -0.2])))
+    assert not ok and np.all(d == 0.0)
+
+
+def test_peak_subpixel_clamps_each_component(orc):
+    H = np.diag([-1.0, -2.0])
+    d, ok = orc.peak_subpixel(_quadratic_nb(0.0, H, np.array([1.6, -0.3])))
+    assert ok
+    np.testing.assert_allclose(d, [1.0, -0.3], atol=1e-12)
+    d, ok = orc.peak_subpixel(_quadratic_nb(0.0, H, np.array([-0.25, -4.0])))
+    np.testing.assert_allclose(d, [-0.25, -1.0], atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_xcf_shift_is_integer_peak_plus_fit(orc, seed):
+    """The XCF's shift is the wrapped integer maximum of its correlation plus
+    the fit of that maximum's circular 3 x 3 neighbourhood (x = column)."""
+    A = ndi.gaussian_filter(rng(310 + seed).normal(size=(64, 64)), (1.0, 3.0))
+    B = ndi.shift(A, (-2.3, 4.6), order=3, mode="wrap")
+    q, _, C = orc.xcf(A, B, 1)
+    ky, kx = np.unravel_index(np.argmax(C), C.shape)
+    nb = np.array([[C[(ky + dy) % 64, (kx + dx) % 64] for dx in (-1, 0, 1)] for dy in (-1, 0, 1)])
+    d, _ = orc.peak_subpixel(nb)
+    s = np.array([kx if kx < 32 else kx - 64, ky if ky < 32 else ky - 64], np.float64)
+    np.testing.assert_allclose(q, s + d, atol=1e-12)
+    assert np.all(np.abs(q - (4.6, -2.3)) < 0.5)  # the right integer cell (the quadratic under-reads)
+
+
 # -- F solve (Eq. 2-3), polar (Eq. 4-5), rotation vector -------------------------------------
 
 def _project(F, cx, cy, xs, ys, zs):
