@@ -254,6 +254,29 @@ int ebsd_set_graphs(ebsd_handle* h, int enable);
  * only when the RMS update lies within rounding of it. */
 int ebsd_set_resident(ebsd_handle* h, int enable);
 
+/* Per-pair convergence across launches (multi-resolution demons, section 1,
+ * run to a tolerance per pair).  Every demons launch skips the pairs that
+ * have stopped, but a level's launches up to the cap would still be issued.
+ * With a tolerance (tol_px > 0) and chunk_launches > 0 (default 8), a
+ * level's launches are issued in chunks of chunk_launches; after each chunk
+ * a one-workgroup kernel writes the number of pairs still iterating into
+ * pinned host memory.  With chunks c - 1 and c queued behind it, the host
+ * waits for chunk c - 2's count and issues no further chunk once it is
+ * zero, so a level ends within two chunks of its last pair's stop and the
+ * device never waits for the host.  The call then
+ * returns only after the gated levels have been issued (the host thread
+ * waits on the stream between chunks); a stream being captured by the
+ * caller is never gated.  chunk_launches = 0 issues every launch and never
+ * waits.  Results are identical either way (a skipped launch would have
+ * exited at once for every pair).  EBSD_EINVAL for a negative value. */
+int ebsd_set_gating(ebsd_handle* h, int32_t chunk_launches);
+
+/* Demons launches of the last registration call per pyramid level, summed
+ * over its size buckets (host arrays of EBSD_MAX_LEVELS, either may be NULL):
+ * issued[l] were issued, planned[l] is the full sequence to the cap (one or
+ * two iterations per launch).  Levels run level-resident count neither. */
+int ebsd_get_launch_counts(const ebsd_handle* h, int32_t* issued, int32_t* planned);
+
 /* Strip height used for a pyramid level of level_h x level_w px (levels
  * wider than 512 px run in column segments of 256 or 512 lanes, each
  * recomputing 9 columns on either side, or, at strip height 0, on the 2-D
@@ -378,6 +401,14 @@ int ebsd_cnn_train_step(ebsd_cnn* c, const float* ref, const float* test, const 
 /* Restart Adam (moments zero, step count 0). */
 int ebsd_cnn_reset_optimizer(ebsd_cnn* c);
 
+/* Adam's state, for checkpointing a training run: first and second moments
+ * (HOST, n = ebsd_cnn_num_params() floats each, parameter layout) and the
+ * step count that sets the bias corrections.  get: any of m, v, step may be
+ * NULL (zero moments before the first training step); set: m and v are
+ * required, step >= 0.  EBSD_EINVAL for a wrong n or a negative step. */
+int ebsd_cnn_get_optimizer(const ebsd_cnn* c, float* m, float* v, int64_t n, int64_t* step);
+int ebsd_cnn_set_optimizer(ebsd_cnn* c, const float* m, const float* v, int64_t n, int64_t step);
+
 /* Parameters used by the warm start of a registration handle: from a file
  * (ebsd_load_model) or copied from a network object (ebsd_set_model). */
 int ebsd_load_model(ebsd_handle* h, const char* path);
@@ -436,6 +467,12 @@ int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t
  * 1: bilinear; coef is not used (may be NULL).  H, W >= 3, n <= 65535. */
 int ebsd_stage_remap(const float* img, int32_t n, int32_t H, int32_t W, const double* R, double xs,
                      double ys, double zs, int32_t interp, float* coef, float* out, void* stream);
+
+/* Eq. (13)'s detector-to-sample rotation R_tilt for a tilt of theta rad, as
+ * printed (a rotation about z): S = [[cos, sin, 0], [-sin, cos, 0], [0, 0, 1]],
+ * written to S (HOST, 9 fp64, row-major).  EBSD_EINVAL for a NULL S or a
+ * theta that is not finite. */
+int ebsd_tilt_rotation(double theta, double* S);
 
 /* Eq. (3) under the traction-free equality constraint, with the strain and
  * stress it implies (section 2; Eq. (13)-(16); supplementary Eq. (2.1)-(2.11)).

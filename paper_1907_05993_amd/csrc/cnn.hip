@@ -530,6 +530,39 @@ int ebsd_cnn_train_step(ebsd_cnn* c, const float* ref, const float* test, const 
     return EBSD_OK;
 }
 
+int ebsd_cnn_get_optimizer(const ebsd_cnn* c, float* m, float* v, int64_t n, int64_t* step)
+{
+    if (!c || n != kNumParams) return EBSD_EINVAL;
+    if (step) *step = c->step;
+    DevGuard g(c->device);
+    if (!g.ok || hipDeviceSynchronize() != hipSuccess) return EBSD_EDEVICE;
+    for (int k = 0; k < 2; k++) {
+        float* dst = k == 0 ? m : v;
+        if (!dst) continue;
+        const float* src = k == 0 ? c->adam_m : c->adam_v;
+        if (!c->have_bwd) {
+            std::memset(dst, 0, kNumParams * sizeof(float));
+        } else if (hipMemcpy(dst, src, kNumParams * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
+            return EBSD_EDEVICE;
+        }
+    }
+    return EBSD_OK;
+}
+
+int ebsd_cnn_set_optimizer(ebsd_cnn* c, const float* m, const float* v, int64_t n, int64_t step)
+{
+    if (!c || !m || !v || n != kNumParams || step < 0) return EBSD_EINVAL;
+    DevGuard g(c->device);
+    if (!g.ok) return EBSD_EDEVICE;
+    if (!alloc_backward(c)) return EBSD_ENOMEM;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(c->adam_m, m, kNumParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->adam_v, v, kNumParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return EBSD_EDEVICE;
+    c->step = step;
+    return EBSD_OK;
+}
+
 int ebsd_cnn_reset_optimizer(ebsd_cnn* c)
 {
     if (!c) return EBSD_EINVAL;

@@ -59,6 +59,20 @@ struct ebsd_handle {
     bool resident = true;  // levels of at most 64 x 64 px iterate in one launch
     hipStream_t cap_stream = nullptr;
     std::map<std::string, hipGraphExec_t> graph_cache;
+    // With a tolerance, a level's launches go out in chunks of gate_chunk; after
+    // each chunk a kernel writes the number of pairs still iterating into
+    // pinned host memory, and the host stops issuing chunks once a chunk has
+    // left none.  It reads chunk c - 2's count while chunks c - 1 and c are
+    // queued, so the device never waits for the host.  0: every launch of
+    // every level is issued and the call never waits on the stream.
+    int gate_chunk = 8;
+    int32_t* gate_host = nullptr;  // pinned, device-visible [4]
+    int32_t* gate_dev = nullptr;   // the same memory as the device addresses it
+    hipEvent_t gate_ev[4] = {};
+    // launches of the last call per level (summed over size buckets): issued,
+    // and the full sequence up to the cap
+    int32_t launches_issued[EBSD_MAX_LEVELS] = {};
+    int32_t launches_planned[EBSD_MAX_LEVELS] = {};
     // warm-start network (created by ebsd_load_model / ebsd_set_model)
     ebsd_cnn* cnn = nullptr;
 };
@@ -663,27 +677,30 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     }
     // The demons iterations of one level (up to a few hundred launches) are a
     // static sequence for a given configuration: captured once into a graph
-    // and replayed; the few other launches and the timing events stay on the
-    // stream.
+    // (per chunk of launches when the level is gated) and replayed; the few
+    // other launches and the timing events stay on the stream.
     // fty > 0: two iterations per launch (ceil(cap / 2) launches, plus the
     // decision-only launch that follows an even cap when a tolerance is set)
-    auto level_iters = [&](int l, int ty, int fty, hipStream_t st) -> int {
+    auto n_launches = [&](int l, int fty) -> int {
         const int cap = p.max_iters[l];
-        if (fty) {
-            const int nl = (cap + 1) / 2 + ((p.tol_px > 0.0f && cap > 0 && cap % 2 == 0) ? 1 : 0);
-            for (int L2 = 0; L2 < nl; L2++)
-                EBSD_TRY(launch_demons_iter2(d_bk, b, l, L2, h->taps, h->radius, p.tol_px, cap, fty, st));
-            return EBSD_OK;
+        if (fty) return (cap + 1) / 2 + ((p.tol_px > 0.0f && cap > 0 && cap % 2 == 0) ? 1 : 0);
+        return cap;
+    };
+    auto launch_range = [&](int l, int ty, int fty, int a, int e, hipStream_t st) -> int {
+        for (int k = a; k < e; k++) {
+            if (fty)
+                EBSD_TRY(launch_demons_iter2(d_bk, b, l, k, h->taps, h->radius, p.tol_px, p.max_iters[l], fty, st));
+            else
+                EBSD_TRY(launch_demons_iter(d_bk, b, l, k, h->taps, h->radius, p.tol_px, ty, st));
         }
-        for (int it = 0; it < cap; it++)
-            EBSD_TRY(launch_demons_iter(d_bk, b, l, it, h->taps, h->radius, p.tol_px, ty, st));
         return EBSD_OK;
     };
-    auto run_level = [&](int l, int ty, int fty) -> int {
-        if (h->graphs && p.max_iters[l] > 0) {
+    auto run_range = [&](int l, int ty, int fty, int a, int e) -> int {
+        if (h->graphs && e > a) {
             std::ostringstream key;
             key << H << ' ' << W << ' ' << nb << ' ' << nref << ' ' << l << ' ' << p.max_iters[l]
-                << ' ' << p.tol_px << ' ' << h->radius << ' ' << ty << ' ' << fty << ' ' << (void*)base;
+                << ' ' << p.tol_px << ' ' << h->radius << ' ' << ty << ' ' << fty << ' ' << a << ' ' << e
+                << ' ' << (void*)base;
             auto it = h->graph_cache.find(key.str());
             hipGraphExec_t exec = nullptr;
             if (it != h->graph_cache.end()) {
@@ -695,9 +712,9 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
                 hipGraph_t graph = nullptr;
                 if (h->cap_stream &&
                     hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
-                    const int e = level_iters(l, ty, fty, h->cap_stream);
+                    const int e2 = launch_range(l, ty, fty, a, e, h->cap_stream);
                     const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
-                    if (e == EBSD_OK && ec == hipSuccess && graph &&
+                    if (e2 == EBSD_OK && ec == hipSuccess && graph &&
                         hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
                         exec = nullptr;
                     if (graph) (void)hipGraphDestroy(graph);
@@ -710,7 +727,53 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
                 return EBSD_OK;
             }
         }
-        return level_iters(l, ty, fty, s);
+        return launch_range(l, ty, fty, a, e, s);
+    };
+    // gating needs a stream the host may wait on: not while the caller captures it
+    bool gate = p.tol_px > 0.0f && h->gate_chunk > 0 && mode == Mode::Full;
+    if (gate) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) gate = false;
+        (void)hipGetLastError();
+    }
+    if (gate && !h->gate_host) {
+        if (hipHostMalloc((void**)&h->gate_host, sizeof(int32_t) * 4, hipHostMallocMapped) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&h->gate_dev, h->gate_host, 0) != hipSuccess) {
+            if (h->gate_host) (void)hipHostFree(h->gate_host);
+            h->gate_host = nullptr;
+            h->gate_dev = nullptr;
+            (void)hipGetLastError();
+            return EBSD_ENOMEM;
+        }
+        for (auto& ev : h->gate_ev)
+            EBSD_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    auto run_level = [&](int l, int ty, int fty) -> int {
+        const int nl = n_launches(l, fty);
+        h->launches_planned[l] += nl;
+        const int chunk = gate ? h->gate_chunk : 0;
+        if (chunk <= 0 || nl <= chunk) {
+            h->launches_issued[l] += nl;
+            return run_range(l, ty, fty, 0, nl);
+        }
+        int done = 0;
+        for (int c = 0, a = 0; a < nl; c++, a += chunk) {
+            const int e = std::min(nl, a + chunk);
+            const int r = run_range(l, ty, fty, a, e);
+            if (r) return r;
+            done = e;
+            if (e == nl) break;
+            EBSD_TRY(launch_count_active(d_bk, h->gate_dev + (c & 3), s));
+            EBSD_TRY(hipEventRecord(h->gate_ev[c & 3], s));
+            if (c >= 2) {
+                // chunks c - 1 and c are queued behind chunk c - 2's count: the device
+                // stays busy while the host waits for it and reads it
+                EBSD_TRY(hipEventSynchronize(h->gate_ev[(c - 2) & 3]));
+                if (reinterpret_cast<volatile int32_t*>(h->gate_host)[(c - 2) & 3] == 0) break;
+            }
+        }
+        h->launches_issued[l] += done;
+        return EBSD_OK;
     };
     if (warm) {
         // network field at the coarse grid, chunk by chunk, then the Eq. (2)
@@ -818,6 +881,9 @@ int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u
     DeviceGuard g(h->device);
     if (!g.ok) return EBSD_EDEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!tune_only) {
+        for (int l = 0; l < EBSD_MAX_LEVELS; l++) h->launches_issued[l] = h->launches_planned[l] = 0;
+    }
     size_t need = 0;
     for (auto& hb : buckets) need += desc_upper_bound(hb, h->p.n_roi);
     e = ensure_pin(h, need);
@@ -952,6 +1018,32 @@ int ebsd_set_resident(ebsd_handle* h, int enable)
     return EBSD_OK;
 }
 
+int ebsd_tilt_rotation(double theta, double* S)
+{
+    if (!S || !std::isfinite(theta)) return EBSD_EINVAL;
+    const double c = std::cos(theta), sn = std::sin(theta);
+    const double m[9] = {c, sn, 0.0, -sn, c, 0.0, 0.0, 0.0, 1.0};
+    for (int i = 0; i < 9; i++) S[i] = m[i];
+    return EBSD_OK;
+}
+
+int ebsd_set_gating(ebsd_handle* h, int32_t chunk_launches)
+{
+    if (!h || chunk_launches < 0 || chunk_launches > 1000000) return EBSD_EINVAL;
+    h->gate_chunk = chunk_launches;
+    return EBSD_OK;
+}
+
+int ebsd_get_launch_counts(const ebsd_handle* h, int32_t* issued, int32_t* planned)
+{
+    if (!h) return EBSD_EINVAL;
+    for (int l = 0; l < EBSD_MAX_LEVELS; l++) {
+        if (issued) issued[l] = h->launches_issued[l];
+        if (planned) planned[l] = h->launches_planned[l];
+    }
+    return EBSD_OK;
+}
+
 int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w)
 {
     if (!h || level_h <= 0 || level_w <= 0) return EBSD_EINVAL;
@@ -995,6 +1087,9 @@ int ebsd_destroy(ebsd_handle* h)
         if (h->pin_free) (void)hipEventDestroy(h->pin_free);
         clear_graphs(h);
         if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+        if (h->gate_host) (void)hipHostFree(h->gate_host);
+        for (auto& e : h->gate_ev)
+            if (e) (void)hipEventDestroy(e);
         for (auto& e : h->ev)
             if (e) (void)hipEventDestroy(e);
     }

@@ -151,6 +151,9 @@ hipError_t launch_demons_iter2(const Bucket* d_bk, const Bucket& hb, int level, 
 bool demons_resident_ok(int h, int w);
 hipError_t launch_demons_resident(const Bucket* d_bk, const Bucket& hb, int level, const float* taps, int radius,
                                   float tol, int cap, hipStream_t s);
+// *out = number of pairs whose demons state has not recorded a stop (out may
+// be pinned host memory mapped into the device's address space).
+hipError_t launch_count_active(const Bucket* d_bk, int32_t* out, hipStream_t s);
 // Close level l: iteration counts, convergence of the last iteration, final buffer.
 hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int cap, float tol,
                             int ty, bool fused, hipStream_t s);

@@ -280,6 +280,25 @@ hipError_t launch_demons_iter(const Bucket* d_bk, const Bucket& hb, int level, i
     return hipGetLastError();
 }
 
+// One workgroup: the pairs that have not recorded a stop (fixed-order sum).
+__global__ void __launch_bounds__(256) k_count_active(const Bucket* __restrict__ bk, int32_t* out)
+{
+    __shared__ int part[4];
+    int c = 0;
+    for (int b = threadIdx.x; b < bk->nb; b += 256) c += bk->state[b].stop < 0 ? 1 : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = part[0] + part[1] + part[2] + part[3];
+}
+
+hipError_t launch_count_active(const Bucket* d_bk, int32_t* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, d_bk, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_level_end(const Bucket* d_bk, const Bucket& hb, int level, int cap, float tol,
                             int ty, bool fused, hipStream_t s)
 {

@@ -109,7 +109,9 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_cnn_get_params", "ebsd_cnn_get_grads", "ebsd_cnn_load", "ebsd_cnn_save",
             "ebsd_cnn_forward", "ebsd_cnn_train_step", "ebsd_cnn_reset_optimizer",
             "ebsd_load_model", "ebsd_set_model", "ebsd_stage_conv3x3", "ebsd_stage_conv3x3_dgrad",
-            "ebsd_stage_conv3x3_wgrad", "ebsd_gen_pairs", "ebsd_get_fused_height", "ebsd_set_fused_height"]
+            "ebsd_stage_conv3x3_wgrad", "ebsd_gen_pairs", "ebsd_get_fused_height", "ebsd_set_fused_height",
+            "ebsd_set_gating", "ebsd_get_launch_counts", "ebsd_tilt_rotation", "ebsd_cnn_get_optimizer",
+            "ebsd_cnn_set_optimizer"]
 
 
 def lib():
@@ -139,6 +141,9 @@ def lib():
         L.ebsd_set_strip_height.argtypes = [vp, i32, i32, i32]
         L.ebsd_get_fused_height.argtypes = [vp, i32, i32]
         L.ebsd_set_fused_height.argtypes = [vp, i32, i32, i32]
+        L.ebsd_set_gating.argtypes = [vp, i32]
+        L.ebsd_tilt_rotation.argtypes = [C.c_double, C.POINTER(C.c_double)]
+        L.ebsd_get_launch_counts.argtypes = [vp, vp, vp]
         L.ebsd_set_timing.argtypes = [vp, C.c_int]
         L.ebsd_get_timing.argtypes = [vp, vp, vp]
         L.ebsd_stage_normalize.argtypes = [vp, i32, i64, vp, vp, vp]
@@ -166,6 +171,8 @@ def lib():
         L.ebsd_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, C.c_float, i32,
                                           C.POINTER(C.c_float), vp]
         L.ebsd_cnn_reset_optimizer.argtypes = [vp]
+        L.ebsd_cnn_get_optimizer.argtypes = [vp, vp, vp, i64, vp]
+        L.ebsd_cnn_set_optimizer.argtypes = [vp, vp, vp, i64, i64]
         L.ebsd_load_model.argtypes = [vp, C.c_char_p]
         L.ebsd_set_model.argtypes = [vp, vp]
         L.ebsd_gen_pairs.argtypes = [C.POINTER(CGenSpec), i32, i32, i32, C.c_double, C.c_double, C.c_double,
@@ -422,6 +429,20 @@ class Registrar:
         the finer levels."""
         _check(lib().ebsd_set_resident(self._h, int(bool(on))), "ebsd_set_resident")
 
+    def set_gating(self, chunk_launches=8):
+        """With a tolerance, issue each level's launches in chunks of this many
+        and stop once no pair is left iterating (0 = issue every launch)."""
+        _check(lib().ebsd_set_gating(self._h, int(chunk_launches)), "ebsd_set_gating")
+
+    def launch_counts(self):
+        """(issued, planned) demons launches per level of the last call."""
+        import numpy as np
+        issued = np.zeros(MAX_LEVELS, np.int32)
+        planned = np.zeros(MAX_LEVELS, np.int32)
+        _check(lib().ebsd_get_launch_counts(self._h, issued.ctypes.data, planned.ctypes.data),
+               "ebsd_get_launch_counts")
+        return issued[:self.params.levels], planned[:self.params.levels]
+
     def set_strip_height(self, level_h, level_w, rows):
         _check(lib().ebsd_set_strip_height(self._h, level_h, level_w, rows), "ebsd_set_strip_height")
 
@@ -524,6 +545,24 @@ class Cnn:
                                          float(lr), int(bool(update)), C.byref(loss), _stream()),
                "ebsd_cnn_train_step")
         return float(loss.value)
+
+    def get_optimizer(self):
+        """Adam's state: (m, v, step) with m, v float32 host arrays."""
+        import numpy as np
+        m = np.zeros(CNN_PARAMS, np.float32)
+        v = np.zeros(CNN_PARAMS, np.float32)
+        st = C.c_int64(0)
+        _check(lib().ebsd_cnn_get_optimizer(self._h, m.ctypes.data, v.ctypes.data, CNN_PARAMS, C.byref(st)),
+               "ebsd_cnn_get_optimizer")
+        return m, v, int(st.value)
+
+    def set_optimizer(self, m, v, step):
+        """Restore Adam's state (moments and step count)."""
+        import numpy as np
+        m = np.ascontiguousarray(m, np.float32)
+        v = np.ascontiguousarray(v, np.float32)
+        _check(lib().ebsd_cnn_set_optimizer(self._h, m.ctypes.data, v.ctypes.data, CNN_PARAMS, int(step)),
+               "ebsd_cnn_set_optimizer")
 
     def reset_optimizer(self):
         _check(lib().ebsd_cnn_reset_optimizer(self._h), "ebsd_cnn_reset_optimizer")
@@ -629,10 +668,11 @@ NICKEL_STIFFNESS = (2.76e11, 1.59e11, 1.32e11)
 
 
 def r_tilt(theta):
-    """Eq. (13)'s detector-to-sample rotation for a tilt theta (rad), as printed."""
-    import math
-    c, s = math.cos(theta), math.sin(theta)
-    return ((c, s, 0.0), (-s, c, 0.0), (0.0, 0.0, 1.0))
+    """Eq. (13)'s detector-to-sample rotation for a tilt theta (rad), from
+    ebsd_tilt_rotation; a 3 x 3 tuple of rows."""
+    S = (C.c_double * 9)()
+    _check(lib().ebsd_tilt_rotation(float(theta), S), "ebsd_tilt_rotation")
+    return tuple(tuple(S[3 * i + j] for j in range(3)) for i in range(3))
 
 
 def traction_free(q, cx, cy, pcs, g, S, stiffness=NICKEL_STIFFNESS, M=None):

@@ -11,6 +11,13 @@ Every step runs in the library (ebsd_gen_pairs, ebsd_cnn_train_step); this
 script only schedules them.
 
     python -m paper_1907_05993_amd.train_cnn --pairs 200000 --out weights.bin
+
+A run can be cut into pieces (--time-limit) and continued (--resume): the
+checkpoint (--checkpoint, NumPy .npz written with allow_pickle off) holds the
+parameters, Adam's moments and step count, the global step and the position
+in the epoch's shuffled order; the learning-rate schedule is a function of the
+global step (cosine from --lr to --lr-final over --total-steps), so a resumed
+run continues the same schedule.
 """
 from __future__ import annotations
 
@@ -64,6 +71,22 @@ def evaluate(net, specs, batch, E):
             "p95_epe_px": float(np.percentile(e, 95)), "pairs_rms_gt_0.5px": float((per_pair > 0.5).mean())}
 
 
+def save_checkpoint(path, net, step, epoch, pos):
+    params = net.get_params()
+    m, v, adam_step = net.get_optimizer()
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, params=params, adam_m=m, adam_v=v, adam_step=np.int64(adam_step), step=np.int64(step),
+             epoch=np.int64(epoch), pos=np.int64(pos))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path, net):
+    with np.load(path, allow_pickle=False) as z:
+        net.set_params(z["params"])
+        net.set_optimizer(z["adam_m"], z["adam_v"], int(z["adam_step"]))
+        return int(z["step"]), int(z["epoch"]), int(z["pos"])
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--pairs", type=int, default=200000, help="training pairs per epoch")
@@ -71,9 +94,14 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-final", type=float, default=None,
-                    help="cosine decay of the learning rate to this value over the run (default: constant)")
+                    help="cosine decay of the learning rate to this value over --total-steps (default: constant)")
+    ap.add_argument("--total-steps", type=int, default=0,
+                    help="length of the cosine schedule in steps (default: all epochs)")
     ap.add_argument("--eval", type=int, default=2048)
-    ap.add_argument("--init", default=None, help="start from a parameter file")
+    ap.add_argument("--init", default=None, help="start from a parameter file (fresh optimizer)")
+    ap.add_argument("--resume", default=None, help="continue from a checkpoint (.npz)")
+    ap.add_argument("--checkpoint", default=None, help="checkpoint file written during and after the run")
+    ap.add_argument("--checkpoint-every", type=float, default=120.0, help="seconds between checkpoints")
     ap.add_argument("--out", required=True)
     ap.add_argument("--time-limit", type=float, default=0.0, help="stop training after this many seconds")
     ap.add_argument("--log-every", type=float, default=20.0, help="seconds between progress lines")
@@ -87,7 +115,11 @@ def main(argv=None):
     import torch
     from . import ebsd as E
     net = E.Cnn(max_batch=args.batch)
-    if args.init:
+    step, ep0, pos0 = 0, 0, 0
+    if args.resume:
+        step, ep0, pos0 = load_checkpoint(args.resume, net)
+        log(f"[train] resumed {args.resume}: step {step}, epoch {ep0}, position {pos0}")
+    elif args.init:
         net.load(args.init)
     else:
         net.set_params(init_params(0))
@@ -95,22 +127,23 @@ def main(argv=None):
     log(f"[train] before: {ev0}")
 
     steps_per_epoch = args.pairs // args.batch
+    total = args.total_steps or steps_per_epoch * args.epochs
     t_train = time.time()
-    last = t_train
-    step = 0
+    last = last_ck = t_train
     losses = []
     stop = False
-    for ep in range(args.epochs):
+    step0 = step
+    ep, pos = ep0, pos0
+    for ep in range(ep0, args.epochs):
         order = np.random.default_rng(1000 + ep).permutation(steps_per_epoch)
-        for b in order:
+        start_pos = pos0 if ep == ep0 else 0
+        for pos in range(start_pos, steps_per_epoch):
+            b = order[pos]
             specs = train_specs[b * args.batch:(b + 1) * args.batch]
             ref, test, label = E.gen_pairs(specs)
             lr = args.lr
             if args.lr_final is not None:
-                if args.time_limit:
-                    frac = min(1.0, (time.time() - t_train) / args.time_limit)
-                else:
-                    frac = step / max(1, steps_per_epoch * args.epochs)
+                frac = min(1.0, step / max(1, total))
                 lr = args.lr_final + 0.5 * (args.lr - args.lr_final) * (1.0 + math.cos(math.pi * frac))
             losses.append(net.train_step(ref, test, label, lr=lr))
             step += 1
@@ -118,14 +151,22 @@ def main(argv=None):
             if now - last >= args.log_every:
                 last = now
                 log(f"[train] epoch {ep} step {step} loss(last 50) {np.mean(losses[-50:]):.4f} lr {lr:.2e} "
-                    f"{step / (now - t_train):.1f} steps/s")
-            if args.time_limit and now - t_train > args.time_limit:
+                    f"{(step - step0) / (now - t_train):.1f} steps/s")
+            if args.checkpoint and now - last_ck >= args.checkpoint_every:
+                last_ck = now
+                save_checkpoint(args.checkpoint, net, step, ep, pos + 1)
+            if (args.time_limit and now - t_train > args.time_limit) or (args.total_steps and step >= total):
                 stop = True
                 break
         if stop:
             break
+    else:
+        ep, pos = args.epochs, -1
     dt = time.time() - t_train
-    log(f"[train] {step} steps ({step * args.batch} pairs) in {dt:.1f} s, {step / max(dt, 1e-9):.2f} steps/s")
+    log(f"[train] {step - step0} steps ({(step - step0) * args.batch} pairs) in {dt:.1f} s, "
+        f"{(step - step0) / max(dt, 1e-9):.2f} steps/s; global step {step}")
+    if args.checkpoint:
+        save_checkpoint(args.checkpoint, net, step, ep, pos + 1)
     net.save(args.out)
     ev = evaluate(net, eval_specs, args.batch, E)
     log(f"[train] after: {ev}")

@@ -58,11 +58,13 @@ def bilinear(img, x, y):
     y0 = np.floor(yc).astype(np.int64)
     fx = xc - x0.astype(f32)
     fy = yc - y0.astype(f32)
-    x1 = np.minimum(x0 + 1, W - 1)
-    y1 = np.minimum(y0 + 1, H - 1)
+    dx = (x0 + 1 < W).astype(np.int64)  # the right neighbour, clamped
+    dy = np.where(y0 + 1 < H, W, 0)
+    flat = img.ravel()
+    i00 = y0 * W + x0
     one = f32(1)
-    top = (one - fx) * img[y0, x0] + fx * img[y0, x1]
-    bot = (one - fx) * img[y1, x0] + fx * img[y1, x1]
+    top = (one - fx) * flat.take(i00) + fx * flat.take(i00 + dx)
+    bot = (one - fx) * flat.take(i00 + dy) + fx * flat.take(i00 + dy + dx)
     return (one - fy) * top + fy * bot
 
 
@@ -72,24 +74,34 @@ def taps(sigma):
     return (w / w.sum()).astype(f32), r
 
 
-def smooth(v, w, r):
-    """Separable Gaussian with replicated borders: rows, then columns."""
+def smooth(v, w, r, cols_first=False):
+    """Separable Gaussian with replicated borders: rows, then columns (or the
+    other way round: the same sum rounded in another order)."""
     H, W = v.shape
-    acc = np.zeros_like(v)
-    for j in range(-r, r + 1):
-        acc = acc + w[j + r] * v[:, np.clip(np.arange(W) + j, 0, W - 1)]
-    out = np.zeros_like(v)
-    for j in range(-r, r + 1):
-        out = out + w[j + r] * acc[np.clip(np.arange(H) + j, 0, H - 1), :]
-    return out
+
+    def along(a, axis):
+        # a[.., clamp(i + j), ..] for j = -r..r as slices of the edge-replicated array
+        pad = [(0, 0), (0, 0)]
+        pad[axis] = (r, r)
+        ap = np.pad(a, pad, mode="edge")
+        n = a.shape[axis]
+        acc = np.zeros_like(a)
+        for j in range(-r, r + 1):
+            sl = ap[:, r + j:r + j + n] if axis == 1 else ap[r + j:r + j + n, :]
+            acc = acc + w[j + r] * sl
+        return acc
+
+    if cols_first:
+        return along(along(v, 0), 1)
+    return along(along(v, 1), 0)
 
 
-def demons_iter(R, T, gx, gy, u, w, r):
+def demons_iter(R, T, gx, gy, u, w, r, cols_first=False):
     """One Eq. (1) step on the accumulated field, then its smoothing; returns
     (u_new, RMS of the update)."""
     H, W = R.shape
-    ys, xs = np.mgrid[0:H, 0:W]
-    wv = bilinear(T, xs.astype(f32) + u[0], ys.astype(f32) + u[1])
+    ys, xs = np.mgrid[0:H, 0:W].astype(f32)
+    wv = bilinear(T, xs + u[0], ys + u[1])
     a = R - wv
     den = gx * gx + gy * gy + a * a
     ok = den > f32(1e-9)
@@ -97,7 +109,7 @@ def demons_iter(R, T, gx, gy, u, w, r):
     dux = np.where(ok, a * gx / safe, f32(0))
     duy = np.where(ok, a * gy / safe, f32(0))
     v = np.stack([u[0] + dux, u[1] + duy])
-    un = np.stack([smooth(v[0], w, r), smooth(v[1], w, r)]) if r > 0 else v
+    un = np.stack([smooth(v[0], w, r, cols_first), smooth(v[1], w, r, cols_first)]) if r > 0 else v
     d = (un - u).astype(np.float64)
     return un, float(np.sqrt((d ** 2).sum(axis=0).mean()))
 
@@ -110,9 +122,11 @@ def prolong(u, H, W):
     return np.stack([f32(2) * bilinear(u[c], x, y) for c in range(2)])
 
 
-def demons(ref, test, levels=3, iters=150, sigma=1.0, tol=0.0, u_init=None):
+def demons(ref, test, levels=3, iters=150, sigma=1.0, tol=0.0, u_init=None, cols_first=False):
     """Multi-resolution demons of one pair; returns (field [2, H, W] float32,
-    iteration counts per level, finest first)."""
+    iteration counts per level, finest first).  u_init: coarsest-level
+    initial field [2, h, w] in that level's px.  cols_first: smooth columns
+    before rows (another FP32 rounding order of the same iteration)."""
     R = [normalize(ref)]
     T = [normalize(test)]
     for _ in range(1, levels):
@@ -127,7 +141,7 @@ def demons(ref, test, levels=3, iters=150, sigma=1.0, tol=0.0, u_init=None):
         gx, gy = gradient(R[l])
         k = 0
         while k < caps[l]:
-            u, rms = demons_iter(R[l], T[l], gx, gy, u, w, r)
+            u, rms = demons_iter(R[l], T[l], gx, gy, u, w, r, cols_first)
             k += 1
             if tol > 0 and (1 << l) * rms < tol:
                 break
@@ -135,3 +149,22 @@ def demons(ref, test, levels=3, iters=150, sigma=1.0, tol=0.0, u_init=None):
         if l > 0:
             u = prolong(u, *R[l - 1].shape)
     return u, its
+
+
+def field_stats(a, b):
+    """(median, 95th percentile, RMS) over the pixels of |a - b| (field vectors)."""
+    d = np.sqrt(((np.asarray(a, np.float64) - b) ** 2).sum(0))
+    return float(np.median(d)), float(np.percentile(d, 95)), float(np.sqrt((d ** 2).mean()))
+
+
+def envelope(refs, tests, fields64, u_init=None, **kw):
+    """Per pair, the largest (median, p95, RMS) of |u32 - u64| over the two
+    FP32 rounding orders (rows or columns smoothed first), against the FP64
+    fields fields64 [n, 2, H, W].  Returns an [n, 3] array."""
+    n = len(refs)
+    out = np.zeros((n, 3))
+    for i in range(n):
+        for cf in (False, True):
+            u, _ = demons(refs[i], tests[i], u_init=None if u_init is None else u_init[i], cols_first=cf, **kw)
+            out[i] = np.maximum(out[i], field_stats(u, fields64[i]))
+    return out

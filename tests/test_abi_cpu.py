@@ -125,6 +125,9 @@ def test_null_arguments_rejected(E):
     assert L.ebsd_stage_prolong(fake, 1, 64, 8193, fake, None) == -2  # output over 16384 px a side
     assert L.ebsd_stage_prolong(None, 1, 64, 64, fake, None) == -1
     assert L.ebsd_destroy(None) == 0
+    assert L.ebsd_set_gating(None, 8) == -1
+    assert L.ebsd_tilt_rotation(0.1, None) == -1
+    assert L.ebsd_get_launch_counts(None, None, None) == -1
     # traction-free solve: validation before any launch
     eye = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
     bad = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, -1)  # a reflection
@@ -159,3 +162,14 @@ def test_network_entry_points_validate_without_a_gpu(E):
     assert L.ebsd_cnn_load(None, b"x") == -1
     assert L.ebsd_load_model(None, b"x") == -1
     assert L.ebsd_set_model(None, None) == -1
+
+
+def test_tilt_rotation_is_eq13_as_printed(E, orc):
+    """ebsd_tilt_rotation (host) against the tests' own transcription of Eq. (13)."""
+    import math
+    import test_oracle_pins as pins
+    for th in (0.0, math.radians(70.0), -1.3):
+        np.testing.assert_allclose(np.array(E.r_tilt(th)), np.array(pins._r_tilt(th)), atol=1e-15)
+    S = np.array(E.r_tilt(0.7))
+    np.testing.assert_allclose(S @ S.T, np.eye(3), atol=1e-15)
+    assert abs(np.linalg.det(S) - 1.0) < 1e-15

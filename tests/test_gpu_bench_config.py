@@ -11,11 +11,19 @@
   the plain method; tolerance 1e-4 px, cap 150 per level, graph replay on,
   strip heights autotuned on the 1024-pair batch of exactly 10 degrees)
   against the FP64 oracle on 16 sampled pairs: the deformation gradient from
-  a common R_finite to 1e-6, the field's median and 95th percentile
-  difference (2e-3 and 0.05 px: the iteration is chaotic at full depth in the
-  noise-dominated pixels, see test_gpu_pipeline.py) and equal iteration
-  counts.  The oracle starts from the same initial field as the GPU (the
-  fitted network field, or zero where the GPU fell back).
+  a common R_finite to 1e-6, equal iteration counts, and the field.  At this
+  depth (3 x 150) the iteration is chaotic in the noise-dominated pixels, so
+  the field's difference is judged against what FP32 rounding alone does:
+  the oracle's iteration in float32 (tests/fp32_demons.py, two rounding
+  orders, the larger difference per statistic) on the same pairs from the
+  same initial field.  Per statistic of |du| (median, 95th percentile, RMS)
+  the median over the 16 pairs of the GPU's difference is at most 2 times
+  the envelope's, and no pair's median or 95th percentile is above 10 times
+  its own envelope's (a single pair's RMS is set by the few pixels where the
+  iteration diverged and scatters by more than an order of magnitude between
+  FP32 realisations, so it is compared over the pairs only).  The
+  oracle starts from the same initial field as the GPU (the fitted network
+  field, or zero where the GPU fell back).
 Needs an MI355X.
 """
 import numpy as np
@@ -108,14 +116,18 @@ def test_bench_registrar_matches_oracle_on_16_sampled_pairs(E, orc, batch, warm)
         o = orc.register_batch(refs[SAMPLE], tests[SAMPLE], op, u_init=u0)
         print("warm used on", int((st & E.WARM_USED != 0).sum()), "of 16 sampled pairs", flush=True)
     else:
+        u0 = None
         o = orc.register_batch(refs[SAMPLE], tests[SAMPLE], op)
+    import fp32_demons
     gf = g["field"].cpu().numpy()[SAMPLE]
+    env = fp32_demons.envelope(refs[SAMPLE], tests[SAMPLE], o["field"], u_init=u0, iters=150, tol=1e-4)
+    gs = np.array([fp32_demons.field_stats(gf[k], o["field"][k]) for k in range(16)])
     for k in range(16):
-        d = np.sqrt(((gf[k].astype(np.float64) - o["field"][k]) ** 2).sum(0))
-        med, p95 = float(np.median(d)), float(np.percentile(d, 95))
-        print("pair %4d field |du| median %.1e p95 %.1e rms %.1e" % (SAMPLE[k], med, p95,
-                                                                   float(np.sqrt((d ** 2).mean()))))
-        assert med <= 2e-3 and p95 <= 0.05, (SAMPLE[k], med, p95)
+        print("pair %4d |du| median %.1e p95 %.1e rms %.1e;  FP32 envelope %.1e %.1e %.1e"
+              % ((SAMPLE[k],) + tuple(gs[k]) + tuple(env[k])))
+    print("median over pairs: GPU", np.median(gs, 0), "envelope", np.median(env, 0))
+    assert np.all(np.median(gs, 0) <= 2.0 * np.median(env, 0))
+    assert np.all(gs[:, :2] <= 10.0 * env[:, :2]), (gs / env).round(2).tolist()
     gi = g["iters"].cpu().numpy()[SAMPLE]
     assert np.array_equal(gi, o["iters"])
     rf = g["R_finite"].cpu().numpy()[SAMPLE]

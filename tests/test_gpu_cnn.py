@@ -452,3 +452,35 @@ def test_mixed_size_stream_with_warm_start(E, orc):
         dF = np.abs(mixed["F"][idx].cpu().numpy() - o2["F"]).max()
         print("N=%d: max |dF| from a common R_finite %.2e, status %s" % (N, dF, mixed["status"][idx].tolist()))
         assert dF <= 1e-6
+
+
+def test_optimizer_checkpoint_resume_is_exact(E):
+    """Adam's moments and step count round-trip through ebsd_cnn_get_optimizer /
+    ebsd_cnn_set_optimizer: two steps after a restore equal two more steps of
+    the uninterrupted run bit for bit."""
+    from paper_1907_05993_amd import synth as S
+    print("case: optimizer checkpoint", flush=True)
+    specs = [S.make_spec(62, i, 256, 256, mis_deg=(0.0, 12.0), strain=2e-3) for i in range(2)]
+    ref, test, label = E.gen_pairs(specs)
+    a = E.Cnn(max_batch=2)
+    a.set_params(cnn.flatten(random_params(8)).astype(np.float32))
+    for _ in range(3):
+        a.train_step(ref, test, label, lr=1e-3)
+    params = a.get_params()
+    m, v, step = a.get_optimizer()
+    assert step == 3 and np.abs(m).max() > 0 and v.min() >= 0
+    for _ in range(2):
+        a.train_step(ref, test, label, lr=1e-3)
+    b = E.Cnn(max_batch=2)
+    b.set_params(params)
+    b.set_optimizer(m, v, step)
+    for _ in range(2):
+        b.train_step(ref, test, label, lr=1e-3)
+    assert np.array_equal(a.get_params(), b.get_params())
+    assert b.get_optimizer()[2] == 5
+    # a fresh optimizer (set_params restarts Adam) takes a different path
+    c = E.Cnn(max_batch=2)
+    c.set_params(params)
+    for _ in range(2):
+        c.train_step(ref, test, label, lr=1e-3)
+    assert not np.array_equal(a.get_params(), c.get_params())
