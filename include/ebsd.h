@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define EBSD_ABI_VERSION 4
+#define EBSD_ABI_VERSION 5
 #define EBSD_MAX_LEVELS 8
 
 /* return codes */
@@ -55,7 +55,7 @@ enum {
     EBSD_OK = 0,
     EBSD_EINVAL = -1,   /* bad argument (NULL pointer, n < 0, bad parameter value) */
     EBSD_ESHAPE = -2,   /* pattern size not supported (coarsest level under 4 x 4, over 16384) */
-    EBSD_EROI = -3,     /* a ROI falls outside the pattern, or ROI size is not 32/64/128 */
+    EBSD_EROI = -3,     /* a ROI falls outside the pattern, or ROI size is not 32/64/128/256 */
     EBSD_ENOMEM = -4,   /* device or pinned allocation failed */
     EBSD_EDEVICE = -5,  /* a HIP runtime call failed */
     EBSD_ENOTSUP = -6,  /* feature not available in this library */
@@ -85,7 +85,7 @@ typedef struct ebsd_params {
     float tol_px;                         /* stop a level when 2^l RMS|u_new - u| < tol (full-res px); 0 = fixed count */
     double pc_x, pc_y, pc_z;              /* pattern centre fractions */
     int32_t n_roi;                        /* ROIs: 1 at the pattern centre + (n_roi - 1) on a ring, 5..256 */
-    int32_t roi_size;                     /* 32, 64 or 128 */
+    int32_t roi_size;                     /* 32, 64, 128 or 256 (the paper's size) */
     double roi_radius_frac;               /* ring radius / W */
     int32_t window;                       /* 1 = Hann window on each ROI (section 2), 0 = none */
     int32_t second_pass;                  /* 1 = remap + XCF second pass (Eq. (12)); 0 = demons only */
@@ -156,6 +156,9 @@ typedef struct ebsd_outputs {
                                    C1 = (0.01 L)^2, C2 = (0.03 L)^2, L = 6 (z-scored patterns); NaN with
                                    the XCF first pass or a pattern of 10 px or less; computed only when
                                    this pointer is set */
+    double* omega;              /* [n][9] Eq. (6)'s rotation tensor of rotvec (theta):
+                                   omega_ij = -eps_ijk theta_k, row-major, rad (the cross-product
+                                   matrix of theta, the logarithm of R) */
 } ebsd_outputs;
 
 /* Library ABI version (EBSD_ABI_VERSION). */
@@ -450,10 +453,13 @@ int ebsd_stage_demons_iter(const float* R, const float* T, int32_t n, int32_t H,
 int ebsd_stage_prolong(const float* u, int32_t n, int32_t h, int32_t w, float* out, void* stream);
 
 /* ROI cross-correlation of n ROI pairs (section 2): A (reference) and B
- * (test), [n][N][N] fp32, N in {32, 64, 128}; per-ROI zero mean, optional
+ * (test), [n][N][N] fp32, N in {32, 64, 128, 256}; per-ROI zero mean, optional
  * Hann window, C = IFFT(FFT(B w) conj FFT(A w)), integer peak (ties to the
  * lowest row-major index), 2-D quadratic sub-pixel fit.  q: [n][2] (x, y)
- * shift of B relative to A; ph: [n] normalised peak height (may be NULL). */
+ * shift of B relative to A; ph: [n] normalised peak height (may be NULL).
+ * N = 256 (the paper's ROI size) allocates a device temporary of 768 KiB per
+ * ROI in flight (at most 512 ROIs: 384 MiB) and waits on the stream before
+ * it returns; smaller N run in LDS and never wait. */
 int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t window, float* q,
                    float* ph, void* stream);
 

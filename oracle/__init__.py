@@ -68,6 +68,7 @@ class _Outputs(C.Structure):
         ("mae1", C.c_void_p),
         ("mae", C.c_void_p),
         ("ssim", C.c_void_p),
+        ("omega", C.c_void_p),
     ]
 
 
@@ -141,6 +142,7 @@ def lib():
         L.orc_mae.argtypes = [d, d, d, C.c_int, C.c_double, C.c_double, C.c_double, d]
         L.orc_polar.argtypes = [d, d]
         L.orc_rotvec.argtypes = [d, d]
+        L.orc_omega.argtypes = [d, d]
         L.orc_remap.argtypes = [d, C.c_int, C.c_int, d, C.c_double, C.c_double, C.c_double, C.c_int, d]
         L.orc_bspline_coeffs.argtypes = [d, C.c_int, C.c_int, d]
         L.orc_bspline_at.restype = C.c_double
@@ -402,6 +404,14 @@ def rotvec(R):
     return out
 
 
+def omega(rotvec):
+    """Eq. (6): omega_ij = -eps_ijk theta_k of a rotation vector theta (3 x 3)."""
+    th = _f64(rotvec).reshape(3)
+    om = np.empty(9)
+    lib().orc_omega(_d(th), _d(om))
+    return om.reshape(3, 3)
+
+
 def det_normalize(F):
     F = _f64(F).reshape(9).copy()
     lib().orc_det_normalize(_d(F))
@@ -485,7 +495,7 @@ def pc_pixels(H, W, params):
 
 
 _OUT_KEYS = ("field", "q1", "F1", "Rfin", "q2", "ph", "F", "R", "rotvec", "iters", "status", "mae1", "mae",
-             "ssim")
+             "ssim", "omega")
 
 
 def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None):
@@ -518,6 +528,7 @@ def register_batch(refs, tests, params, rfin=None, want_field=True, u_init=None)
         "mae1": np.empty(n),
         "mae": np.empty(n),
         "ssim": np.empty(n),
+        "omega": np.empty((n, 3, 3)),
     }
     o = _Outputs()
     for k in _OUT_KEYS:

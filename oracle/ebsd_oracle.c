@@ -1004,6 +1004,23 @@ void orc_polar(const double* F, double* R)
 /* Axis-angle of R (the passage after Eq. (5)), written with atan2 so small
  * angles keep their digits: w = (R32-R23, R13-R31, R21-R12)/2 = sin(theta) m,
  * theta = atan2(|w|, (tr R - 1)/2), rotation vector theta_k = theta m_k.   */
+/* Eq. (6): the rotation tensor of a rotation vector theta (the axis times
+ * the angle), omega_ij = -eps_ijk theta_k (eps the permutation symbol),
+ * row-major 3 x 3.                                                         */
+void orc_omega(const double* th, double* om)
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double v = 0.0;
+            for (int k = 0; k < 3; k++) {
+                /* eps_ijk = (i - j)(j - k)(k - i) / 2 for indices 0..2 */
+                const int e = (i - j) * (j - k) * (k - i) / 2;
+                v -= (double)e * th[k];
+            }
+            om[3 * i + j] = v;
+        }
+}
+
 void orc_rotvec(const double* R, double* rv)
 {
     double w0 = 0.5 * (R[7] - R[5]);
@@ -1365,6 +1382,7 @@ typedef struct {
     double* mae1;    /* [1] */
     double* mae;     /* [1] */
     double* ssim;    /* [1] orc_ssim of the final field (NaN with the XCF first pass) */
+    double* omega;   /* [9] Eq. (6)'s rotation tensor of rotvec */
 } orc_outputs;
 
 static void store(double* dst, const double* src, size_t n)
@@ -1486,6 +1504,7 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
     store(o->F, F, 9);
     store(o->R, R, 9);
     store(o->rotvec, rv, 3);
+    if (o->omega) orc_omega(rv, o->omega);
     if (o->iters) memcpy(o->iters, its, sizeof(int32_t) * p->levels);
     if (o->status) *o->status = st;
     store(o->mae1, &mae1, 1);
@@ -1545,6 +1564,7 @@ int orc_register_batch(const float* refs, const float* tests, int n, int H, int 
             oi.mae1 = o->mae1 ? o->mae1 + i : NULL;
             oi.mae = o->mae ? o->mae + i : NULL;
             oi.ssim = o->ssim ? o->ssim + i : NULL;
+            oi.omega = o->omega ? o->omega + (size_t)i * 9 : NULL;
             orc_register_pair(refs + (size_t)i * HW, tests + (size_t)i * HW, H, W, p, NULL,
                               rfin_in ? rfin_in + (size_t)i * 9 : NULL, &oi);
         }

@@ -188,7 +188,7 @@ int check_params(const ebsd_params* p)
         !std::isfinite(p->pc_z))
         return EBSD_EINVAL;
     if (p->n_roi < 5 || p->n_roi > 256) return EBSD_EINVAL;
-    if (p->roi_size != 32 && p->roi_size != 64 && p->roi_size != 128) return EBSD_EROI;
+    if (p->roi_size != 32 && p->roi_size != 64 && p->roi_size != 128 && p->roi_size != 256) return EBSD_EROI;
     if (!(p->roi_radius_frac >= 0.0) || !std::isfinite(p->roi_radius_frac)) return EBSD_EINVAL;
     if (p->window != 0 && p->window != 1) return EBSD_EINVAL;
     if (p->second_pass != 0 && p->second_pass != 1) return EBSD_EINVAL;
@@ -473,6 +473,9 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     const bool cubic = xcf && p.remap_interp == 3 && !tune_only;
     const size_t o_coef = w.take(cubic ? sizeof(float) * (size_t)nref * H * W : 0);
     const size_t o_coef_tmp = w.take(cubic ? sizeof(float) * (size_t)nref * H * W : 0);
+    const bool xcf_any = (xcf || (mode == Mode::Full && p.first_pass == 1)) && !tune_only;
+    const size_t o_xscr = w.take(xcf_any ? sizeof(float) * (size_t)xcf_scratch_floats(p.roi_size, (int64_t)nb * nr)
+                                         : 0);
     const bool warm = mode == Mode::Full && !tune_only && !u_init && p.warm_start;
     const int64_t gcell = (int64_t)(H >> 2) * (W >> 2);  // coarse grid of the pattern
     const int64_t ncell = (int64_t)(kWarmRes / 4) * (kWarmRes / 4);  // the network's output grid
@@ -515,6 +518,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.ssim_part = want_ssim ? b.ssim + nb : nullptr;
     b.ref_coef = cubic ? reinterpret_cast<float*>(base + o_coef) : nullptr;
     b.coef_tmp = cubic ? reinterpret_cast<float*>(base + o_coef_tmp) : nullptr;
+    b.xcf_scratch = xcf_any && p.roi_size == 256 ? reinterpret_cast<float*>(base + o_xscr) : nullptr;
 
     const bool xcf_first = mode == Mode::Full && p.first_pass == 1;
     bool want_field = mode == Mode::Full && out->field && !xcf_first;
@@ -531,6 +535,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
     b.out.mae1 = mode == Mode::Full ? out->mae_first : nullptr;
     b.out.mae = out->mae;
     b.out.ssim = mode == Mode::Full ? out->ssim : nullptr;
+    b.out.omega = out->omega;
     b.u_init = warm ? reinterpret_cast<const float*>(base + o_uinit) : u_init;
     if (warm) {
         b.warm_field = reinterpret_cast<const float*>(base + o_wfield);
@@ -1270,10 +1275,21 @@ int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t
                    float* ph, void* stream)
 {
     if (n < 0 || (n > 0 && (!A || !B || !q))) return EBSD_EINVAL;
-    if (N != 32 && N != 64 && N != 128) return EBSD_EROI;
+    if (N != 32 && N != 64 && N != 128 && N != 256) return EBSD_EROI;
     if (window != 0 && window != 1) return EBSD_EINVAL;
     if (n == 0) return EBSD_OK;
-    return map_err(launch_stage_xcf(A, B, n, N, window, q, ph, (hipStream_t)stream));
+    const hipStream_t s = (hipStream_t)stream;
+    if (N < 256) return map_err(launch_stage_xcf(A, B, n, N, window, q, ph, nullptr, s));
+    DevBuf scr;
+    if (hipMalloc(&scr.p, sizeof(float) * (size_t)xcf_scratch_floats(N, n)) != hipSuccess) {
+        (void)hipGetLastError();
+        return EBSD_ENOMEM;
+    }
+    const int e = map_err(launch_stage_xcf(A, B, n, N, window, q, ph, static_cast<float*>(scr.p), s));
+    if (e) return e;
+    // the scratch is released after the stream has used it
+    if (hipStreamSynchronize(s) != hipSuccess) return EBSD_EDEVICE;
+    return EBSD_OK;
 }
 
 int ebsd_stage_remap(const float* img, int32_t n, int32_t H, int32_t W, const double* R, double xs,

@@ -71,6 +71,7 @@ struct OutPtrs {
     double* mae1;        // [n] mean angular error of the first fit
     double* mae;         // [n] mean angular error of the last fit
     double* ssim;        // [n] structural similarity of the registration
+    double* omega;       // [n][9] Eq. (6)'s rotation tensor of rotvec
 };
 // Everything a bucket's kernels need, in device memory (one copy per bucket).
 struct Bucket {
@@ -115,6 +116,7 @@ struct Bucket {
     double* ssim_part;          // [nb][ssim tiles] per-tile sums
     float* ref_coef;            // [nref][H][W] cubic B-spline coefficients of level 0 (NULL: bilinear remap)
     float* coef_tmp;            // [nref][H][W] row pass of the coefficients
+    float* xcf_scratch;         // ROIs of 256: xcf_scratch_floats(256, nb n_roi) floats (else NULL)
     // per-call caller pointers (so that a bucket's launch sequence is static
     // and can be replayed from a captured graph)
     OutPtrs out;                // results, scattered by pair_index
@@ -237,8 +239,11 @@ hipError_t launch_stage_demons_iter(const float* R, const float* T, int n, int H
                                     const float* u_in, const float* taps, int radius,
                                     float* u_out, double* rms, hipStream_t s);
 hipError_t launch_stage_prolong(const float* u, int n, int h, int w, float* out, hipStream_t s);
+// N in {32, 64, 128}: LDS-resident; N = 256: scratch holds xcf_scratch_floats(256, n) floats.
 hipError_t launch_stage_xcf(const float* A, const float* B, int n, int N, int window, float* q,
-                            float* ph, hipStream_t s);
+                            float* ph, float* scratch, hipStream_t s);
+// Global scratch the XCF of `rois` ROIs of N x N needs (0 below N = 256).
+int64_t xcf_scratch_floats(int N, int64_t rois);
 hipError_t launch_stage_remap(const float* ref, int n, int H, int W, const double* R, double xs, double ys,
                               double zs, int interp, float* coef, float* out, hipStream_t s);
 hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx,

@@ -730,6 +730,20 @@ __global__ void k_scatter(const Bucket* __restrict__ bk)
     }
     if (o.rotvec)
         for (int i = 0; i < 3; i++) o.rotvec[3 * g + i] = bk->rotvec[3 * (int64_t)b + i];
+    if (o.omega) {
+        // Eq. (6): omega_ij = -eps_ijk theta_k
+        const double* th = bk->rotvec + 3 * (int64_t)b;
+        double* om = o.omega + 9 * g;
+        om[0] = 0.0;
+        om[1] = -th[2];
+        om[2] = th[1];
+        om[3] = th[2];
+        om[4] = 0.0;
+        om[5] = -th[0];
+        om[6] = -th[1];
+        om[7] = th[0];
+        om[8] = 0.0;
+    }
     for (int j = 0; j < 2 * nr; j++) {
         if (o.q1) o.q1[2 * nr * g + j] = bk->q1[2 * nr * (int64_t)b + j];
         if (o.q2) o.q2[2 * nr * g + j] = bk->q2[2 * nr * (int64_t)b + j];

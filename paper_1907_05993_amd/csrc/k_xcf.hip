@@ -382,6 +382,34 @@ __device__ void fft_dit_from(XcfShared<N>& S, Post post = Post())
 
 // The whole correlation for one ROI.  `load(x, y)` returns (reference, test)
 // at ROI pixel (x, y).  Writes q (x, y) and ph from thread 0.
+// 2-D quadratic fit of the correlation peak from its circular 3 x 3
+// neighbourhood, C(dy, dx) around the integer maximum (ky, kx); q = wrapped
+// integer shift plus the fit, ph = C0 / sqrt(ea eb).
+template <int N, class At>
+__device__ void peak_fit(At C, int ky, int kx, float ea, float eb, float* q, float* ph)
+{
+    const double c0 = C(0, 0);
+    const double gx = 0.5 * (C(0, 1) - C(0, -1));
+    const double gy = 0.5 * (C(1, 0) - C(-1, 0));
+    const double hxx = C(0, 1) - 2.0 * c0 + C(0, -1);
+    const double hyy = C(1, 0) - 2.0 * c0 + C(-1, 0);
+    const double hxy = 0.25 * (C(1, 1) - C(1, -1) - C(-1, 1) + C(-1, -1));
+    const double det = hxx * hyy - hxy * hxy;
+    double dx = 0.0, dy = 0.0;
+    if (hxx < 0.0 && det > 0.0) {
+        dx = fmin(fmax(-(hyy * gx - hxy * gy) / det, -1.0), 1.0);
+        dy = fmin(fmax(-(hxx * gy - hxy * gx) / det, -1.0), 1.0);
+    }
+    const int sx = kx < N / 2 ? kx : kx - N;
+    const int sy = ky < N / 2 ? ky : ky - N;
+    q[0] = (float)((double)sx + dx);
+    q[1] = (float)((double)sy + dy);
+    if (ph) {
+        const double nrm = sqrt((double)ea * (double)eb);
+        *ph = nrm > 0.0 ? (float)(c0 / nrm) : 0.0f;
+    }
+}
+
 template <int N, class Loader>
 __device__ void xcf_core(XcfShared<N>& S, Loader load, int window, float* q, float* ph)
 {
@@ -492,72 +520,336 @@ __device__ void xcf_core(XcfShared<N>& S, Loader load, int window, float* q, flo
         auto C = [&](int dy, int dx) -> double {
             return (double)S.z[(ky + dy + N) & (N - 1)][(kx + dx + N) & (N - 1)].x;
         };
-        const double c0 = C(0, 0);
-        const double gx = 0.5 * (C(0, 1) - C(0, -1));
-        const double gy = 0.5 * (C(1, 0) - C(-1, 0));
-        const double hxx = C(0, 1) - 2.0 * c0 + C(0, -1);
-        const double hyy = C(1, 0) - 2.0 * c0 + C(-1, 0);
-        const double hxy = 0.25 * (C(1, 1) - C(1, -1) - C(-1, 1) + C(-1, -1));
-        const double det = hxx * hyy - hxy * hxy;
-        double dx = 0.0, dy = 0.0;
-        if (hxx < 0.0 && det > 0.0) {
-            dx = fmin(fmax(-(hyy * gx - hxy * gy) / det, -1.0), 1.0);
-            dy = fmin(fmax(-(hxx * gy - hxy * gx) / det, -1.0), 1.0);
+        peak_fit<N>(C, ky, kx, ea, eb, q, ph);
+    }
+}
+
+// ---- ROIs of 256 x 256 (the paper's ROI size) ----------------------------------
+// The 256 x 256 complex tile (512 KiB) does not fit in LDS, so one workgroup
+// per ROI keeps it in a slot of global scratch (L2 / MALL resident while the
+// workgroup works on it) and moves 32 lines at a time through an LDS tile:
+//   gather   z = a + i b of the ROI (remapped reference, test) into the slot,
+//            natural order, and the two means;
+//   rows     per 32 rows: mean removed, Hann window, energies, forward
+//            transform along x (decimation in frequency: bit-reversed out),
+//            written back in that order;
+//   columns  per 32 physical columns: forward transform along y, the cross
+//            power spectrum P(k) = B(k) conj A(k) (A, B separated from Z(k)
+//            and Z(-k) as for the smaller ROIs), inverse transform along y;
+//            the physical columns of a chunk are two blocks of 16 chosen so
+//            that the partner -k of every element lies in the same chunk (bit
+//            reversal of 8 bits maps the block of physical columns 16 j .. 16 j + 15 of
+//            logical kx = 16 rev4(i) + rev4(j) onto the block rev4((16 -
+//            rev4(j)) mod 16) of the partners -kx; blocks 0 and 1 are their own
+//            partners, the others pair up);
+//   inverse  per 32 rows: inverse transform along x (bit-reversed in, natural
+//            out), the real part into the slot's correlation plane, each
+//            thread's argmax (ties to the lowest row-major index);
+// then the block's argmax and the 2-D quadratic fit of its neighbourhood.
+// Every butterfly is the one the LDS-resident kernels compute for N = 256.
+constexpr int kX2 = 256, kX2Lines = 32, kX2Pitch = kX2 + 1;
+constexpr int64_t kX2SlotFloats = (int64_t)2 * kX2 * kX2 + (int64_t)kX2 * kX2;  // complex tile + real plane
+constexpr int kX2Slots = 512;  // workgroups (two per compute unit at 68 KiB of LDS each)
+
+struct Xcf256Shared {
+    float2 t[kX2Lines][kX2Pitch];
+    float2 tw[kX2 / 2];
+    float win[kX2];
+    float red[4][NT / 64];
+    float bv[NT / 64];
+    int bi[NT / 64];
+};
+
+__device__ inline int rev4(int v) { return (int)(__brev((unsigned)v) >> 28); }
+__device__ inline int rev8(int v) { return (int)(__brev((unsigned)v) >> 24); }
+
+// Radix-2 butterflies over the kX2Lines lines of the LDS tile (length 256),
+// up to three stages per pass in registers; the same butterflies and twiddles
+// as fft_pass.  Consecutive threads take consecutive lines.
+template <bool DIF, int SL, int R>
+__device__ void line_pass(Xcf256Shared& S)
+{
+    constexpr int N = kX2;
+    constexpr int s = 1 << SL, M = 1 << R, span = M * s;
+    constexpr int per_line = N / M;
+    for (int c = threadIdx.x; c < kX2Lines * per_line; c += NT) {
+        const int line = c % kX2Lines, k = c / kX2Lines;
+        const int t = k % s, g = k / s;
+        const int base = g * span + t;
+        float2 v[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) v[m] = S.t[line][base + m * s];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int e = DIF ? R - 1 - r : r;
+            const int hs = 1 << e;
+            const int h = hs * s;
+            const int step = N / (2 * h);
+#pragma unroll
+            for (int m = 0; m < M; m++) {
+                if (m & hs) continue;
+                const float2 w = S.tw[(t + (m * s) % h) * step];
+                const float2 a = v[m];
+                if (DIF) {
+                    const float2 b = v[m + hs];
+                    v[m] = make_float2(a.x + b.x, a.y + b.y);
+                    v[m + hs] = cmul(make_float2(a.x - b.x, a.y - b.y), w);
+                } else {
+                    const float2 b = cmulc(v[m + hs], w);
+                    v[m] = make_float2(a.x + b.x, a.y + b.y);
+                    v[m + hs] = make_float2(a.x - b.x, a.y - b.y);
+                }
+            }
         }
-        const int sx = kx < N / 2 ? kx : kx - N;
-        const int sy = ky < N / 2 ? ky : ky - N;
-        q[0] = (float)((double)sx + dx);
-        q[1] = (float)((double)sy + dy);
-        if (ph) {
-            const double nrm = sqrt((double)ea * (double)eb);
-            *ph = nrm > 0.0 ? (float)(c0 / nrm) : 0.0f;
+#pragma unroll
+        for (int m = 0; m < M; m++) S.t[line][base + m * s] = v[m];
+    }
+    __syncthreads();
+}
+
+// forward: stages 7 .. 0 (half-sizes 128 down to 1) in passes of 3, 3, 2
+__device__ inline void lines_dif(Xcf256Shared& S)
+{
+    line_pass<true, 5, 3>(S);
+    line_pass<true, 2, 3>(S);
+    line_pass<true, 0, 2>(S);
+}
+// inverse: stages 0 .. 7 in passes of 3, 3, 2
+__device__ inline void lines_dit(Xcf256Shared& S)
+{
+    line_pass<false, 0, 3>(S);
+    line_pass<false, 3, 3>(S);
+    line_pass<false, 6, 2>(S);
+}
+
+// The physical column blocks of column chunk c (0..7): (0, 1), then the pairs
+// (j, partner(j)) with j < partner(j) in increasing j.
+__device__ inline void x2_chunk_blocks(int c, int& ba, int& bb)
+{
+    if (c == 0) {
+        ba = 0;
+        bb = 1;
+        return;
+    }
+    int seen = 0;
+    for (int j = 2; j < 16; j++) {
+        const int pj = rev4((16 - rev4(j)) & 15);
+        if (j < pj && ++seen == c) {
+            ba = j;
+            bb = pj;
+            return;
         }
     }
+    ba = bb = 0;  // not reached for c < 8
+}
+
+template <class Loader>
+__device__ void xcf256_core(Xcf256Shared& S, float2* __restrict__ Z, float* __restrict__ Cr, Loader load,
+                            int window, float* q, float* ph)
+{
+    constexpr int N = kX2, L = kX2Lines;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < N / 2; k += NT) {
+        double sn, cs;
+        sincospi(-2.0 * (double)k / (double)N, &sn, &cs);
+        S.tw[k] = make_float2((float)cs, (float)sn);
+    }
+    for (int n = tid; n < N; n += NT)
+        S.win[n] = window ? (float)(0.5 - 0.5 * cospi(2.0 * (double)n / (double)(N - 1))) : 1.0f;
+
+    // gather + means
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p = tid; p < N * N; p += NT) {
+        const float2 ab = load(p & (N - 1), p >> 8);
+        Z[p] = ab;
+        acc[0] += ab.x;
+        acc[1] += ab.y;
+    }
+    block_sum4(acc, S.red, 2);  // its barriers also order the slot's writes before the reads below
+    const float ma = acc[0] / (float)(N * N), mb = acc[1] / (float)(N * N);
+
+    // rows: window, energies, forward transform
+    float en0 = 0.0f, en1 = 0.0f;
+    for (int r0 = 0; r0 < N; r0 += L) {
+        for (int i = tid; i < L * N; i += NT) {
+            const int line = i >> 8, x = i & (N - 1);
+            const float2 ab = Z[(r0 + line) * N + x];
+            const float wgt = S.win[r0 + line] * S.win[x];
+            const float a = (ab.x - ma) * wgt, b = (ab.y - mb) * wgt;
+            en0 += a * a;
+            en1 += b * b;
+            S.t[line][x] = make_float2(a, b);
+        }
+        __syncthreads();
+        lines_dif(S);
+        for (int i = tid; i < L * N; i += NT) {
+            const int line = i >> 8, x = i & (N - 1);
+            Z[(r0 + line) * N + x] = S.t[line][x];
+        }
+        __syncthreads();
+    }
+
+    // columns: forward transform, cross power spectrum, inverse transform
+    const float scale = 1.0f / (float)(N * N);
+    for (int c = 0; c < 8; c++) {
+        int ba, bb;
+        x2_chunk_blocks(c, ba, bb);
+        for (int i = tid; i < L * N; i += NT) {
+            const int y = i >> 5, l = i & (L - 1);
+            const int px = (l < 16 ? ba : bb) * 16 + (l & 15);
+            S.t[l][y] = Z[y * N + px];
+        }
+        __syncthreads();
+        lines_dif(S);
+        for (int i = tid; i < L * N; i += NT) {
+            const int l = i >> 8, py = i & (N - 1);
+            const int px = (l < 16 ? ba : bb) * 16 + (l & 15);
+            const int ky = rev8(py), kx = rev8(px);
+            const int qy = rev8((N - ky) & (N - 1)), qx = rev8((N - kx) & (N - 1));
+            const int ql = ((qx >> 4) == ba ? 0 : 16) + (qx & 15);
+            if (ql * N + qy < i) continue;  // each pair once
+            const float2 z1 = S.t[l][py], z2 = S.t[ql][qy];
+            const float2 A = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+            const float2 B = make_float2(0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x));
+            float2 P = cmulc(B, A);
+            P.x *= scale;
+            P.y *= scale;
+            if (ql * N + qy == i) {
+                S.t[l][py] = make_float2(P.x, 0.0f);
+            } else {
+                S.t[l][py] = P;
+                S.t[ql][qy] = make_float2(P.x, -P.y);
+            }
+        }
+        __syncthreads();
+        lines_dit(S);
+        for (int i = tid; i < L * N; i += NT) {
+            const int y = i >> 5, l = i & (L - 1);
+            const int px = (l < 16 ? ba : bb) * 16 + (l & 15);
+            Z[y * N + px] = S.t[l][y];
+        }
+        __syncthreads();
+    }
+
+    // rows: inverse transform, real part, argmax (NaNs never win)
+    float bv = -INFINITY;
+    int bi = 0x7fffffff;
+    for (int r0 = 0; r0 < N; r0 += L) {
+        for (int i = tid; i < L * N; i += NT) {
+            const int line = i >> 8, x = i & (N - 1);
+            S.t[line][x] = Z[(r0 + line) * N + x];
+        }
+        __syncthreads();
+        lines_dit(S);
+        for (int i = tid; i < L * N; i += NT) {
+            const int line = i >> 8, x = i & (N - 1);
+            const int p = (r0 + line) * N + x;
+            const float v = S.t[line][x].x;
+            Cr[p] = v;
+            if (v > bv || (v == bv && p < bi)) {
+                bv = v;
+                bi = p;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+        en0 += __shfl_xor(en0, off, 64);
+        en1 += __shfl_xor(en1, off, 64);
+    }
+    const int lane = tid & 63, wv = tid >> 6;
+    if (lane == 0) {
+        S.bv[wv] = bv;
+        S.bi[wv] = bi;
+        S.red[0][wv] = en0;
+        S.red[1][wv] = en1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float ea = 0.0f, eb = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NT / 64; i++) {
+            ea += S.red[0][i];
+            eb += S.red[1][i];
+        }
+        bv = S.bv[0];
+        bi = S.bi[0];
+        for (int i = 1; i < NT / 64; i++)
+            if (S.bv[i] > bv || (S.bv[i] == bv && S.bi[i] < bi)) {
+                bv = S.bv[i];
+                bi = S.bi[i];
+            }
+        if (bi < 0 || bi >= N * N) bi = 0;  // all-NaN correlation
+        const int ky = bi >> 8, kx = bi & (N - 1);
+        auto C = [&](int dy, int dx) -> double { return (double)Cr[((ky + dy) & (N - 1)) * N + ((kx + dx) & (N - 1))]; };
+        peak_fit<N>(C, ky, kx, ea, eb, q, ph);
+    }
+    __syncthreads();  // the slot is reused by the workgroup's next ROI
 }
 
 // One workgroup per (pair, ROI).  INTERP 3 / 1: the second pass, the
 // reference remapped (cubic B-spline / bilinear) -> q2; INTERP 0: the
 // conventional first pass, the unremapped reference ROI -> q1.  Both write
 // the peak height.
-template <int N, int INTERP>
-__global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk, int window, int pass)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    XcfShared<N>& S = *reinterpret_cast<XcfShared<N>*>(smem);
-    const int b = blockIdx.x / bk->n_roi;
-    const int j = blockIdx.x - b * bk->n_roi;
-    const int H = bk->H, W = bk->W;
-    const float* Rn = bk->ref_pyr + (int64_t)bk->ref_slot[b] * bk->pyr_elems;
-    const float* Tn = bk->test_pyr + (int64_t)b * bk->pyr_elems;
-    const int x0 = bk->roi_xy[2 * j], y0 = bk->roi_xy[2 * j + 1];
-    // pass 0 remaps by R_finite: source direction R^T r; a later pass by the
-    // previous pass's F: source direction F^-1 r, i.e. the same map with
-    // (F^-1)^T = cofactor(F) / det F in place of R
-    const float* Cf = INTERP == 3 ? bk->ref_coef + (int64_t)bk->ref_slot[b] * H * W : nullptr;
-    double m[9];
-    if (INTERP == 0) {
-        for (int i = 0; i < 9; i++) m[i] = 0.0;  // unused
-    } else if (pass == 0) {
-        const double* Rf = bk->Rfin + 9 * (int64_t)b;
-        for (int i = 0; i < 9; i++) m[i] = Rf[i];
-    } else {
-        const double* A = bk->F + 9 * (int64_t)b;
-        m[0] = A[4] * A[8] - A[5] * A[7];
-        m[1] = A[5] * A[6] - A[3] * A[8];
-        m[2] = A[3] * A[7] - A[4] * A[6];
-        m[3] = A[2] * A[7] - A[1] * A[8];
-        m[4] = A[0] * A[8] - A[2] * A[6];
-        m[5] = A[1] * A[6] - A[0] * A[7];
-        m[6] = A[1] * A[5] - A[2] * A[4];
-        m[7] = A[2] * A[3] - A[0] * A[5];
-        m[8] = A[0] * A[4] - A[1] * A[3];
-        const double det = A[0] * m[0] + A[1] * m[1] + A[2] * m[2];
-        for (int i = 0; i < 9; i++) m[i] /= det;
+// The (reference, test) sample at pixel (x, y) of ROI j of pair b.  INTERP 3 /
+// 1: the reference remapped (cubic B-spline / bilinear); pass 0 remaps by
+// R_finite (source direction R^T r), a later pass by the previous pass's F
+// (source direction F^-1 r: the same map with (F^-1)^T = cofactor(F) / det F
+// in place of R).  INTERP 0: the unremapped reference.
+template <int INTERP>
+struct RoiLoader {
+    const float* Rn;
+    const float* Tn;
+    const float* Cf;
+    int H, W, x0, y0;
+    double r00, r01, r02, r10, r11, r12, r20, r21, r22, xs, ys, zs;
+
+    __device__ RoiLoader(const Bucket* __restrict__ bk, int b, int j, int pass)
+    {
+        H = bk->H;
+        W = bk->W;
+        Rn = bk->ref_pyr + (int64_t)bk->ref_slot[b] * bk->pyr_elems;
+        Tn = bk->test_pyr + (int64_t)b * bk->pyr_elems;
+        x0 = bk->roi_xy[2 * j];
+        y0 = bk->roi_xy[2 * j + 1];
+        Cf = INTERP == 3 ? bk->ref_coef + (int64_t)bk->ref_slot[b] * H * W : nullptr;
+        double m[9];
+        if (INTERP == 0) {
+            for (int i = 0; i < 9; i++) m[i] = 0.0;  // unused
+        } else if (pass == 0) {
+            const double* Rf = bk->Rfin + 9 * (int64_t)b;
+            for (int i = 0; i < 9; i++) m[i] = Rf[i];
+        } else {
+            const double* A = bk->F + 9 * (int64_t)b;
+            m[0] = A[4] * A[8] - A[5] * A[7];
+            m[1] = A[5] * A[6] - A[3] * A[8];
+            m[2] = A[3] * A[7] - A[4] * A[6];
+            m[3] = A[2] * A[7] - A[1] * A[8];
+            m[4] = A[0] * A[8] - A[2] * A[6];
+            m[5] = A[1] * A[6] - A[0] * A[7];
+            m[6] = A[1] * A[5] - A[2] * A[4];
+            m[7] = A[2] * A[3] - A[0] * A[5];
+            m[8] = A[0] * A[4] - A[1] * A[3];
+            const double det = A[0] * m[0] + A[1] * m[1] + A[2] * m[2];
+            for (int i = 0; i < 9; i++) m[i] /= det;
+        }
+        r00 = m[0]; r01 = m[1]; r02 = m[2];
+        r10 = m[3]; r11 = m[4]; r12 = m[5];
+        r20 = m[6]; r21 = m[7]; r22 = m[8];
+        xs = bk->xs;
+        ys = bk->ys;
+        zs = bk->zs;
     }
-    const double r00 = m[0], r01 = m[1], r02 = m[2], r10 = m[3], r11 = m[4], r12 = m[5],
-                 r20 = m[6], r21 = m[7], r22 = m[8];
-    const double xs = bk->xs, ys = bk->ys, zs = bk->zs;
-    auto load = [&](int x, int y) -> float2 {
+
+    __device__ float2 operator()(int x, int y) const
+    {
         const int X = x0 + x, Y = y0 + y;
         if (INTERP == 0) return make_float2(Rn[(int64_t)Y * W + X], Tn[(int64_t)Y * W + X]);
         const double p0 = (double)X - xs, p1 = (double)Y - ys, p2 = zs;
@@ -567,11 +859,56 @@ __global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk,
         const double v2 = r02 * p0 + r12 * p1 + r22 * p2;
         const double sx = xs + zs * v0 / v2, sy = ys + zs * v1 / v2;
         const float a = INTERP == 3 ? bspline_d(Cf, H, W, sx, sy) : bilinear_d(Rn, H, W, sx, sy);
-        const float t = Tn[(int64_t)Y * W + X];
-        return make_float2(a, t);
-    };
+        return make_float2(a, Tn[(int64_t)Y * W + X]);
+    }
+};
+
+// One workgroup per (pair, ROI).  INTERP 3 / 1: the second pass -> q2;
+// INTERP 0: the conventional first pass -> q1.  Both write the peak height.
+template <int N, int INTERP>
+__global__ void __launch_bounds__(NT) k_xcf_pairs(const Bucket* __restrict__ bk, int window, int pass)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    XcfShared<N>& S = *reinterpret_cast<XcfShared<N>*>(smem);
+    const int b = blockIdx.x / bk->n_roi;
+    const int j = blockIdx.x - b * bk->n_roi;
+    const RoiLoader<INTERP> load(bk, b, j, pass);
     const int64_t o = (int64_t)b * bk->n_roi + j;
     xcf_core<N>(S, load, window, (INTERP == 0 ? bk->q1 : bk->q2) + 2 * o, bk->ph + o);
+}
+
+// ROIs of 256: a grid of at most kX2Slots workgroups walks the (pair, ROI)
+// list; workgroup g works in scratch slot g.
+template <int INTERP>
+__global__ void __launch_bounds__(NT) k_xcf256_pairs(const Bucket* __restrict__ bk, int window, int pass,
+                                                     float* __restrict__ scratch)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    Xcf256Shared& S = *reinterpret_cast<Xcf256Shared*>(smem);
+    float* slot = scratch + (int64_t)blockIdx.x * kX2SlotFloats;
+    const int total = bk->nb * bk->n_roi;
+    for (int r = blockIdx.x; r < total; r += gridDim.x) {
+        const int b = r / bk->n_roi, j = r - (r / bk->n_roi) * bk->n_roi;
+        const RoiLoader<INTERP> load(bk, b, j, pass);
+        xcf256_core(S, reinterpret_cast<float2*>(slot), slot + 2 * kX2 * kX2, load, window,
+                    (INTERP == 0 ? bk->q1 : bk->q2) + 2 * (int64_t)r, bk->ph + r);
+    }
+}
+
+__global__ void __launch_bounds__(NT)
+    k_xcf256_stage(const float* __restrict__ A, const float* __restrict__ B, int n, int window,
+                   float* __restrict__ q, float* __restrict__ ph, float* __restrict__ scratch)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    Xcf256Shared& S = *reinterpret_cast<Xcf256Shared*>(smem);
+    float* slot = scratch + (int64_t)blockIdx.x * kX2SlotFloats;
+    for (int r = blockIdx.x; r < n; r += gridDim.x) {
+        const float* a = A + (int64_t)r * kX2 * kX2;
+        const float* bb = B + (int64_t)r * kX2 * kX2;
+        auto load = [&](int x, int y) -> float2 { return make_float2(a[y * kX2 + x], bb[y * kX2 + x]); };
+        xcf256_core(S, reinterpret_cast<float2*>(slot), slot + 2 * kX2 * kX2, load, window, q + 2 * (int64_t)r,
+                    ph ? ph + r : nullptr);
+    }
 }
 
 template <int N>
@@ -600,6 +937,20 @@ hipError_t launch_pairs_n(const Bucket* d_bk, int blocks, int window, int pass, 
 }
 
 template <int INTERP>
+hipError_t launch_pairs256(const Bucket* d_bk, const Bucket& hb, int window, int pass, hipStream_t s)
+{
+    const int total = hb.nb * hb.n_roi;
+    if (!hb.xcf_scratch || total <= 0) return hipErrorInvalidValue;
+    const size_t sm = sizeof(Xcf256Shared);
+    static std::atomic<uint64_t> attr_done{0};
+    const hipError_t e = ensure_dynamic_lds((const void*)k_xcf256_pairs<INTERP>, (int)sm, attr_done);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_xcf256_pairs<INTERP>), dim3(std::min(total, kX2Slots)), dim3(NT), sm, s, d_bk, window,
+                       pass, hb.xcf_scratch);
+    return hipGetLastError();
+}
+
+template <int INTERP>
 hipError_t launch_pairs_i(const Bucket* d_bk, const Bucket& hb, int window, int pass, hipStream_t s)
 {
     const int blocks = hb.nb * hb.n_roi;
@@ -607,6 +958,7 @@ hipError_t launch_pairs_i(const Bucket* d_bk, const Bucket& hb, int window, int 
     case 32: return launch_pairs_n<32, INTERP>(d_bk, blocks, window, pass, s);
     case 64: return launch_pairs_n<64, INTERP>(d_bk, blocks, window, pass, s);
     case 128: return launch_pairs_n<128, INTERP>(d_bk, blocks, window, pass, s);
+    case 256: return launch_pairs256<INTERP>(d_bk, hb, window, pass, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -665,14 +1017,30 @@ hipError_t launch_stage_remap(const float* ref, int n, int H, int W, const doubl
 }
 
 hipError_t launch_stage_xcf(const float* A, const float* B, int n, int N, int window, float* q,
-                            float* ph, hipStream_t s)
+                            float* ph, float* scratch, hipStream_t s)
 {
     switch (N) {
     case 32: return launch_stage_n<32>(A, B, n, window, q, ph, s);
     case 64: return launch_stage_n<64>(A, B, n, window, q, ph, s);
     case 128: return launch_stage_n<128>(A, B, n, window, q, ph, s);
+    case 256: {
+        if (!scratch) return hipErrorInvalidValue;
+        const size_t sm = sizeof(Xcf256Shared);
+        static std::atomic<uint64_t> attr_done{0};
+        const hipError_t e = ensure_dynamic_lds((const void*)k_xcf256_stage, (int)sm, attr_done);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_xcf256_stage, dim3(std::min(n, kX2Slots)), dim3(NT), sm, s, A, B, n, window, q, ph,
+                           scratch);
+        return hipGetLastError();
+    }
     default: return hipErrorInvalidValue;
     }
+}
+
+int64_t xcf_scratch_floats(int N, int64_t rois)
+{
+    if (N != kX2 || rois <= 0) return 0;
+    return std::min<int64_t>(rois, kX2Slots) * kX2SlotFloats;
 }
 
 }  // namespace ebsd

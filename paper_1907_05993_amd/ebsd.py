@@ -92,6 +92,7 @@ class COutputs(C.Structure):
         ("mae_first", C.c_void_p),
         ("mae", C.c_void_p),
         ("ssim", C.c_void_p),
+        ("omega", C.c_void_p),
     ]
 
 
@@ -298,6 +299,9 @@ class Registrar:
             pass
 
     def _pairs(self, refs, tests, ref_ids):
+        if (isinstance(refs, torch.Tensor) and isinstance(tests, torch.Tensor) and refs.dim() == 3
+                and tests.dim() == 3 and refs.shape == tests.shape):
+            return self._pairs_batched(refs, tests, ref_ids)
         if isinstance(refs, torch.Tensor):
             refs = list(refs.unbind(0)) if refs.dim() == 3 else [refs]
             tests = list(tests.unbind(0)) if tests.dim() == 3 else [tests]
@@ -315,6 +319,32 @@ class Registrar:
             arr[i].ref_id = -1 if ref_ids is None else int(ref_ids[i])
             keep += [r, t]
         return arr, n, [(t.shape[-2], t.shape[-1]) for t in tests], keep
+
+    @staticmethod
+    def _pairs_batched(refs, tests, ref_ids):
+        """The pair table of two [n, H, W] tensors, filled without a Python
+        object per pair (pair i: base pointer + i H W floats)."""
+        import numpy as np
+        for x in (refs, tests):
+            if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+                raise ValueError("patterns must be contiguous float32 device tensors")
+        n, H, W = tests.shape
+        arr = (CPair * max(n, 1))()
+        if n:
+            view = np.frombuffer(arr, dtype=np.dtype({"names": ["ref", "test", "H", "W", "ref_id"],
+                                                       "formats": [np.uint64, np.uint64, np.int32, np.int32,
+                                                                   np.int32],
+                                                       "offsets": [CPair.ref.offset, CPair.test.offset,
+                                                                   CPair.H.offset, CPair.W.offset,
+                                                                   CPair.ref_id.offset],
+                                                       "itemsize": C.sizeof(CPair)}), count=max(n, 1))
+            step = np.arange(n, dtype=np.uint64) * np.uint64(4 * H * W)
+            view["ref"][:n] = np.uint64(refs.data_ptr()) + step
+            view["test"][:n] = np.uint64(tests.data_ptr()) + step
+            view["H"][:n] = H
+            view["W"][:n] = W
+            view["ref_id"][:n] = -1 if ref_ids is None else np.asarray(ref_ids, np.int32)
+        return arr, n, [(H, W)] * n, [refs, tests]
 
     def _outputs(self, shapes, want_field, dev, want_ssim=False):
         n = len(shapes)
@@ -334,6 +364,7 @@ class Registrar:
             "status": torch.empty(n, dtype=torch.int32, device=dev),
             "mae_first": torch.empty(n, **f64),
             "mae": torch.empty(n, **f64),
+            "omega": torch.empty(n, 3, 3, **f64),
         }
         if want_ssim:
             out["ssim"] = torch.empty(n, **f64)
@@ -354,7 +385,7 @@ class Registrar:
         co.field = out["_field_flat"].data_ptr() if want_field else None
         co.field_offset = offs.ctypes.data if want_field else None
         for k in ("F", "R", "rotvec", "R_finite", "F_first", "q1", "q2", "peak_height", "iters",
-                  "status", "warm_field", "warm_misfit", "mae_first", "mae", "ssim"):
+                  "status", "warm_field", "warm_misfit", "mae_first", "mae", "ssim", "omega"):
             if k in out:
                 setattr(co, k, out[k].data_ptr())
         return out, co
@@ -364,11 +395,10 @@ class Registrar:
         if "_field_flat" not in out:
             return out
         flat, offs = out.pop("_field_flat"), out.pop("_field_offsets")
-        fields = [flat[int(o):int(o) + 2 * h * w].view(2, h, w) for o, (h, w) in zip(offs, shapes)]
-        if len(set(shapes)) == 1 and fields:
+        if shapes and len(set(shapes)) == 1:
             out["field"] = flat.view(len(shapes), 2, shapes[0][0], shapes[0][1])
         else:
-            out["field"] = fields
+            out["field"] = [flat[int(o):int(o) + 2 * h * w].view(2, h, w) for o, (h, w) in zip(offs, shapes)]
         return out
 
     def register(self, refs, tests, ref_ids=None, want_field=True, u_init=None, want_ssim=False):

@@ -343,9 +343,9 @@ WORKLOADS = {
     "scan_400": dict(config_id=3, n=4096, H=400, W=400, strain=0.0, iters=150, roi=128, tol=1e-4),
     # the paper's own pattern size and settings (section 3.1): 1244 x 1024 px (width x height),
     # pattern centre (0.5, 0.5, 0.5), 7 levels x 25 iterations, no field smoothing; 10 deg;
-    # 100 ROIs on a ring plus one at the centre (128 px here, 256 in the paper)
+    # 100 ROIs of 256 x 256 on a ring plus one at the centre (the paper's test set 1)
     "paper_1244": dict(config_id=7, n=256, H=1024, W=1244, exact_angle=10.0, strain=2e-3, iters=25,
-                       levels=7, sigma=0.0, roi=128, n_roi=101, pc=(0.5, 0.5, 0.5)),
+                       levels=7, sigma=0.0, roi=256, n_roi=101, pc=(0.5, 0.5, 0.5)),
 }
 
 

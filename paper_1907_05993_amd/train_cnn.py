@@ -57,18 +57,28 @@ def init_params(seed=0):
 
 
 def evaluate(net, specs, batch, E):
-    """Endpoint errors of the network field against the labels (px, full res)."""
+    """Endpoint errors of the network field against the labels (px, full res),
+    and the misfit of the Eq. (2) fit to it that decides the warm start's
+    fallback (RMS over the grid points inside the ROI ring, full-res px)."""
     import torch
-    errs = []
+    errs, mis = [], []
+    reg = E.Registrar(E.Params(levels=3, iters=(0, 0, 0), sigma_px=1.0, roi_size=64, n_roi=20, warm_start=2,
+                               fallback_residual_px=1e9))
+    reg.set_model(net)
     for i in range(0, len(specs), batch):
         ref, test, label = E.gen_pairs(specs[i:i + batch])
         out = net.forward(ref, test)
         d = (out - label).double()
         errs.append(torch.sqrt((d ** 2).sum(-1)).reshape(d.shape[0], -1).cpu().numpy())
+        mis.append(reg.register(ref, test, want_field=False)["warm_misfit"].cpu().numpy())
+    reg.close()
     e = np.concatenate(errs)
+    m = np.concatenate(mis)
     per_pair = np.sqrt((e ** 2).mean(axis=1))
     return {"rms_epe_px": float(np.sqrt((e ** 2).mean())), "median_epe_px": float(np.median(e)),
-            "p95_epe_px": float(np.percentile(e, 95)), "pairs_rms_gt_0.5px": float((per_pair > 0.5).mean())}
+            "p95_epe_px": float(np.percentile(e, 95)), "pairs_rms_gt_0.5px": float((per_pair > 0.5).mean()),
+            "misfit_median_px": float(np.median(m)), "misfit_p95_px": float(np.percentile(m, 95)),
+            "pairs_misfit_le_0.5px": float((m <= 0.5).mean())}
 
 
 def save_checkpoint(path, net, step, epoch, pos):

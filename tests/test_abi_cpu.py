@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(E):
 
 def test_version_defaults_strerror(E):
     L = E.lib()
-    assert L.ebsd_version() == 4
+    assert L.ebsd_version() == 5
     p = E.CParams()
     assert L.ebsd_params_default(C.byref(p)) == 0
     assert p.struct_size == C.sizeof(E.CParams)

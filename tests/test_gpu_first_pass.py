@@ -63,7 +63,7 @@ def test_xcf_first_pass_integer_shift(E, orc):
     assert g["mae_first"].cpu().numpy().max() < 1e-6
 
 
-@pytest.mark.parametrize("roi,H", [(64, 256), (32, 128)])
+@pytest.mark.parametrize("roi,H", [(64, 256), (32, 128), (256, 1024)])
 def test_xcf_first_pass_parity(E, orc, roi, H):
     from paper_1907_05993_amd import synth as S
     specs = [S.make_spec(7, i, H, H, mis_deg=(0.0, 2.0)) for i in range(4)]

@@ -108,6 +108,11 @@ def compare(E, orc, refs, tests, gp, op, strict=True, F_tol=1e-6):
         print("second-pass response to the R_finite difference:", ["%.1e" % v for v in sens])
         assert (dF_e2e <= np.maximum(1e-4, 3.0 * sens + 1e-6)).all()
     assert np.array_equal(g["status"].cpu().numpy().astype(np.uint32), o["status"])
+    # Eq. (6): the rotation tensor of the GPU's own rotation vector, as the oracle forms it
+    om = g["omega"].cpu().numpy()
+    rv = g["rotvec"].cpu().numpy()
+    for i in range(n):
+        np.testing.assert_array_equal(om[i], orc.omega(rv[i]))
     return g, o
 
 

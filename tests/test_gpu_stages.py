@@ -99,7 +99,7 @@ def test_stage_prolong(E, orc, hw):
         np.testing.assert_allclose(out[i], orc.prolong(u[i].astype(np.float64)), atol=2e-6)
 
 
-@pytest.mark.parametrize("N", [32, 64, 128])
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
 def test_stage_xcf_random_textures(E, orc, N):
     n = 6
     A = np.empty((n, N, N), np.float32)
@@ -119,7 +119,7 @@ def test_stage_xcf_random_textures(E, orc, N):
             assert abs(ph[i] - pho) < 1e-5
 
 
-@pytest.mark.parametrize("N", [32, 64, 128])
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
 def test_stage_xcf_integer_shift_and_identical(E, N):
     A = ndi.gaussian_filter(rng(30).normal(size=(N, N)), 1.5, mode="wrap").astype(np.float32)
     shifts = [(0, 0), (3, -5), (-N // 4, N // 4 - 1), (7, 2)]
@@ -128,6 +128,33 @@ def test_stage_xcf_integer_shift_and_identical(E, N):
     q, ph = E.stage_xcf(cuda(As), cuda(Bs), 0)
     np.testing.assert_allclose(q.cpu().numpy(), np.array(shifts, np.float64), atol=1e-4)
     assert abs(ph[0].item() - 1.0) < 1e-5
+
+
+def test_stage_xcf_256_more_rois_than_workgroups(E, orc):
+    """ROIs of 256 x 256 go through global scratch, one slot per workgroup; with
+    more ROIs than workgroups (600 > 512) a workgroup reuses its slot for a
+    second ROI.  Sampled ROIs against the oracle (first and second round of
+    the slots), and every ROI against the same ROI correlated alone."""
+    N, n = 256, 600
+    print(f"case: XCF N=256, {n} ROIs", flush=True)
+    base = ndi.gaussian_filter(rng(40).normal(size=(N + 32, N + 32)), (1.5, 3.0))
+    A = np.empty((n, N, N), np.float32)
+    B = np.empty((n, N, N), np.float32)
+    sh = rng(41).uniform(-6, 6, size=(n, 2))
+    off = rng(42).integers(0, 32, size=(n, 2))
+    for i in range(n):
+        big = np.roll(base, shift=(int(off[i, 0]), int(off[i, 1])), axis=(0, 1))
+        A[i] = big[16:16 + N, 16:16 + N]
+        B[i] = ndi.shift(big, (sh[i, 1], sh[i, 0]), order=3, mode="wrap")[16:16 + N, 16:16 + N]
+    q, ph = E.stage_xcf(cuda(A), cuda(B), 1)
+    q, ph = q.cpu().numpy(), ph.cpu().numpy()
+    for i in (0, 1, 255, 511, 512, 513, 599):
+        qo, pho, _ = orc.xcf(A[i].astype(np.float64), B[i].astype(np.float64), 1)
+        np.testing.assert_allclose(q[i], qo, atol=1e-3)
+        assert abs(ph[i] - pho) < 1e-5
+    for i in (3, 300, 512, 599):
+        q1, ph1 = E.stage_xcf(cuda(A[i:i + 1]), cuda(B[i:i + 1]), 1)
+        assert np.array_equal(q1.cpu().numpy()[0], q[i]) and ph1.item() == ph[i]
 
 
 def test_stage_solve(E, orc):

@@ -694,6 +694,27 @@ def test_rotvec_matches_scipy(orc, rv):
     np.testing.assert_allclose(orc.rotvec(R), Rotation.from_matrix(R).as_rotvec(), atol=1e-14)
 
 
+@pytest.mark.parametrize("rv", [[0, 0, 0], [1e-7, -2e-7, 3e-7], [0.01, 0.02, -0.03], [0.5, -1.0, 1.2]])
+def test_omega_is_the_rotation_logarithm(orc, rv):
+    """Eq. (6)'s omega_ij = -eps_ijk theta_k is the cross-product matrix of
+    theta (omega v = theta x v), i.e. the matrix logarithm of R = exp(theta)."""
+    from scipy.linalg import logm
+    R = Rotation.from_rotvec(rv).as_matrix()
+    om = orc.omega(orc.rotvec(R))
+    np.testing.assert_allclose(om, np.real(logm(R)), atol=1e-12)
+    np.testing.assert_allclose(om, -om.T, atol=0)
+    v = np.array([0.3, -0.7, 1.1])
+    np.testing.assert_allclose(om @ v, np.cross(rv, v), atol=1e-15)
+
+
+def test_omega_output_of_the_pipeline(orc):
+    from paper_1907_05993_amd import synth as S
+    refs, tests = S.render_batch([S.make_spec(2, i, 128, 128, mis_deg=(0.0, 2.0)) for i in range(2)])
+    o = orc.register_batch(refs, tests, orc.make_params(levels=3, iters=5, roi_size=32), want_field=False)
+    for i in range(2):
+        np.testing.assert_array_equal(o["omega"][i], orc.omega(o["rotvec"][i]))
+
+
 def test_det_normalize(orc):
     F = np.diag([1.1, 0.9, 1.05])
     Fn = orc.det_normalize(F)
