@@ -61,7 +61,8 @@ enum {
     EBSD_ENOTSUP = -6,  /* feature not available in this library */
     EBSD_ENOMODEL = -7, /* warm start requested but no network parameters loaded */
     EBSD_EVERSION = -8, /* ebsd_params.struct_size does not match this library */
-    EBSD_EIO = -9       /* a parameter file could not be read or written */
+    EBSD_EIO = -9,      /* a parameter file could not be read or written */
+    EBSD_ETOOBIG = -10  /* input larger than an allocation-free entry point's fixed device buffer */
 };
 
 /* per-pair status bits */
@@ -418,6 +419,20 @@ int ebsd_load_model(ebsd_handle* h, const char* path);
 int ebsd_set_model(ebsd_handle* h, const ebsd_cnn* c);
 
 /* ---- single-stage entry points (one kernel each; device pointers) ------- */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid allocation): the same
+ * pre-filter as ebsd_stage_bandpass, bit for bit, with its row pass (2 n H W
+ * floats) in a fixed device buffer of 8 Mi floats (32 MiB) that the library
+ * holds on each device it runs on until the process ends, instead of a
+ * temporary.  It calls no allocator and does not wait on the stream.
+ * EBSD_ETOOBIG when 2 n H W exceeds 8 Mi floats (e.g. at most 64 patterns of
+ * 256 x 256 or 3 of 1244 x 1024 per call); other errors as ebsd_stage_bandpass.
+ * Every call on one device shares that buffer: calls that may overlap on one
+ * device (other streams, other threads) race and must be ordered by the
+ * caller. */
+int ebsd_stage_bandpass_static(const float* in, int32_t n, int32_t H, int32_t W, float lo_px, float hi_px,
+                               float* out, void* stream);
 
 /* z-score each of n contiguous patterns of `elems` fp32 values:
  * out = (in - mean) / std (population std, FP64 statistics).  flags (device,

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <fstream>
 #include <sstream>
 #include <string>
@@ -954,6 +955,7 @@ const char* ebsd_strerror(int code)
     case EBSD_ENOMODEL: return "warm start requested but no network parameters loaded";
     case EBSD_EVERSION: return "ebsd_params.struct_size mismatch";
     case EBSD_EIO: return "parameter file could not be read or written";
+    case EBSD_ETOOBIG: return "input larger than the fixed device buffer of an allocation-free entry point";
     default: return "unknown error";
     }
 }
@@ -1228,6 +1230,66 @@ int ebsd_stage_bandpass(const float* in, int32_t n, int32_t H, int32_t W, float 
     // the temporary is released after the stream has used it
     if (hipStreamSynchronize(s) != hipSuccess) return EBSD_EDEVICE;
     return EBSD_OK;
+}
+
+// ---- the allocation-free pre-filter -------------------------------------------
+// ebsd_stage_bandpass_static keeps its row pass (2 n H W floats) in this
+// file-scope device array instead of a temporary; each device holds its own
+// copy until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): the first call on
+// a device looks up that device's address of it, and every call uses that.
+constexpr int64_t kStaticScratchFloats = int64_t(8) << 20;  // 32 MiB
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up once per device, with
+// that device current).
+int scratch_for_current_device(float** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return EBSD_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return EBSD_EDEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return EBSD_OK;
+}
+}  // namespace
+
+int ebsd_stage_bandpass_static(const float* in, int32_t n, int32_t H, int32_t W, float lo_px, float hi_px,
+                               float* out, void* stream)
+{
+    if (n < 0 || (n > 0 && (!in || !out))) return EBSD_EINVAL;
+    if (!(lo_px >= 0.0f && lo_px <= 32.0f) || !(hi_px >= 0.0f && hi_px <= 32.0f)) return EBSD_EINVAL;
+    if (H < 1 || W < 2 || W > 16384 || H > 65535 || n > 65535) return EBSD_ESHAPE;
+    if (2 * (int64_t)n * H * W > kStaticScratchFloats) return EBSD_ETOOBIG;
+    if (n == 0) return EBSD_OK;
+    float* tmp = nullptr;
+    const int e = scratch_for_current_device(&tmp);
+    if (e) return e;
+    BandIO io;
+    std::memset(&io, 0, sizeof io);
+    io.src = in;
+    io.src_stride = (int64_t)H * W;
+    io.dst_a = out;
+    io.dst_b = nullptr;
+    io.dst_stride = (int64_t)H * W;
+    io.na = n;
+    io.npat = n;
+    io.H = H;
+    io.W = W;
+    io.tmp = tmp;  // fully written by the row pass before the column pass reads it
+    return map_err(launch_bandpass(io, make_band_taps(lo_px, hi_px), (hipStream_t)stream));
 }
 
 int ebsd_stage_restrict(const float* in, int32_t n, int32_t H, int32_t W, float* out, void* stream)

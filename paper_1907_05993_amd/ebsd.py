@@ -112,7 +112,7 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_load_model", "ebsd_set_model", "ebsd_stage_conv3x3", "ebsd_stage_conv3x3_dgrad",
             "ebsd_stage_conv3x3_wgrad", "ebsd_gen_pairs", "ebsd_get_fused_height", "ebsd_set_fused_height",
             "ebsd_set_gating", "ebsd_get_launch_counts", "ebsd_tilt_rotation", "ebsd_cnn_get_optimizer",
-            "ebsd_cnn_set_optimizer"]
+            "ebsd_cnn_set_optimizer", "ebsd_stage_bandpass_static"]
 
 
 def lib():
@@ -157,6 +157,7 @@ def lib():
         L.ebsd_stage_remap.argtypes = [vp, i32, i32, i32, vp, C.c_double, C.c_double, C.c_double, i32,
                                        vp, vp, vp]
         L.ebsd_stage_bandpass.argtypes = [vp, i32, i32, i32, C.c_float, C.c_float, vp, vp]
+        L.ebsd_stage_bandpass_static.argtypes = [vp, i32, i32, i32, C.c_float, C.c_float, vp, vp]
         L.ebsd_traction_free.argtypes = [vp, i32, i32, vp, vp, C.c_double, C.c_double, C.c_double, vp, vp,
                                          C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double, vp, vp, vp,
                                          vp, vp]

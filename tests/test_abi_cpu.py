@@ -127,6 +127,10 @@ def test_null_arguments_rejected(E):
     assert L.ebsd_destroy(None) == 0
     assert L.ebsd_set_gating(None, 8) == -1
     assert L.ebsd_tilt_rotation(0.1, None) == -1
+    # the allocation-free pre-filter validates before touching a device
+    assert L.ebsd_stage_bandpass_static(None, 1, 64, 64, C.c_float(1.0), C.c_float(8.0), fake, None) == -1
+    assert L.ebsd_stage_bandpass_static(fake, 17, 512, 512, C.c_float(1.0), C.c_float(8.0), fake, None) == -10
+    assert L.ebsd_stage_bandpass_static(None, 0, 64, 64, C.c_float(1.0), C.c_float(8.0), None, None) == 0
     assert L.ebsd_get_launch_counts(None, None, None) == -1
     # traction-free solve: validation before any launch
     eye = (C.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
