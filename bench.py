@@ -66,7 +66,9 @@ def main():
     ap.add_argument("--cap", type=int, default=150)
     ap.add_argument("--short-cap", type=int, default=10,
                     help="also time the warm start with this iteration cap per level (0 = skip)")
-    ap.add_argument("--fallback", type=float, default=0.5, help="fallback misfit threshold, coarse-grid px")
+    ap.add_argument("--fallback", type=float, default=1.0,
+                    help="fallback threshold: RMS misfit of the Eq. (2) fit to the network field, full-res px "
+                         "(the warm legs; one more leg runs the library's default 0.5 px)")
     ap.add_argument("--cpu-sample", type=int, default=512, help="pairs timed on the CPU oracle (0 = skip)")
     ap.add_argument("--parity-pairs", type=int, default=16,
                     help="sampled pairs of the timed batch compared with the oracle in the CPU leg (0 = skip)")
@@ -91,7 +93,18 @@ def main():
                     help="the stopping tolerance of the scan-map and mixed-stream legs (full-res px)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (counter calibration) and exit")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("COPY_FETCH", "COPY_WRITE", "FETCH", "WRITE"),
+                    help="write the HBM traffic record (--traffic-json) from four rocprofv3 --pmc output "
+                         "folders (FETCH_SIZE and WRITE_SIZE of --copy-probe, then of a bench run) and exit")
+    ap.add_argument("--strip-rows", type=int, default=64,
+                    help="with --summarize-pmc: the level-0 strip height the profiled run used")
+    ap.add_argument("--two-iteration-rows", type=int, default=128,
+                    help="with --summarize-pmc: the level-0 two-iteration strip height the profiled run used")
     args = ap.parse_args()
+
+    if args.summarize_pmc:
+        summarize_pmc(args)
+        return
 
     if args.copy_probe:
         import torch
@@ -135,10 +148,10 @@ def main():
     eps_true = 0.5 * (Fiso @ np.transpose(Fiso, (0, 2, 1)) - np.eye(3))
     log(f"[bench] generated {n} pairs of {H}x{W} on the GPU in {time.time() - t0:.1f} s")
 
-    def make(warm, cap, first_pass=0, second_pass=1, tol=None):
+    def make(warm, cap, first_pass=0, second_pass=1, tol=None, fallback=None):
         p = ebsd.Params(levels=3, iters=(cap,) * 3, sigma_px=1.0, tol_px=args.tol if tol is None else tol,
-                        roi_size=w["roi"], n_roi=20,
-                        warm_start=2 if warm else 0, fallback_residual_px=args.fallback,
+                        roi_size=w["roi"], n_roi=20, warm_start=2 if warm else 0,
+                        fallback_residual_px=args.fallback if fallback is None else fallback,
                         first_pass=first_pass, second_pass=second_pass)
         reg = ebsd.Registrar(p, device=0)
         if warm:
@@ -196,6 +209,9 @@ def main():
     warm = timed(make(True, args.cap), "warm start", parity_idx=par_idx)
     plain = None if args.skip_plain else timed(make(False, args.cap), "plain", parity_idx=par_idx)
     short = timed(make(True, args.short_cap), f"warm start, cap {args.short_cap}") if args.short_cap > 0 else None
+    # the library's default fallback threshold (0.5 full-res px of fit misfit)
+    strict = None if args.skip_comparison else timed(make(True, args.cap, fallback=0.5),
+                                                    "warm start, fallback at 0.5 px", extras=False)
     # the conventional first pass (ROI cross-correlation of the unremapped patterns), with and
     # without the remap + second pass: methods (c) and (a) of section 3's comparison
     xcf_c = None if args.skip_comparison else timed(make(False, args.cap, first_pass=1), "XCF first pass", tune=False)
@@ -313,7 +329,7 @@ def main():
             "strain": w["strain"], "counts": 1e4,
             "levels": 3, "iters_cap": args.cap, "tol_px": args.tol, "sigma_px": 1.0,
             "n_roi": 20, "roi": w["roi"], "mode": "warm start (network field fitted to Eq. 2), bf16 network",
-            "fallback_residual_coarse_px": args.fallback,
+            "fallback_residual_px": args.fallback,
             "strip_rows": {f"{k[0]}x{k[1]}": v for k, v in warm["tuned"].items()},
             "two_iteration_strip_rows": {f"{k[0]}x{k[1]}": v for k, v in warm["fused"].items()},
             "launch": "direct" if args.no_graphs else "hipGraph replay",
@@ -370,6 +386,10 @@ def main():
     }
     if short is not None:
         rec["warm_short_cap"] = dict(summary(short), cap=args.short_cap)
+    if strict is not None:
+        rec["warm_fallback_0.5px"] = dict(summary(strict), fallback_residual_px=0.5,
+                                          note="the library's default threshold; the other warm legs use "
+                                               f"{args.fallback} px")
     if stop:
         def stopped(r):
             d = summary(r)
@@ -628,6 +648,55 @@ def main():
         par["pass"] = ok_all
         rec["parity"] = par
     print(json.dumps(rec), flush=True)
+
+
+def _pmc_rows(folder, counter):
+    """(kernel name, value) per dispatch of a rocprofv3 --pmc csv output folder."""
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_pmc(args):
+    """HBM bytes per launch of the demons kernels: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) scaled by what the same counters read for a copy of known size."""
+    cf = [v for k, v in _pmc_rows(args.summarize_pmc[0], "FETCH_SIZE") if "copyBuffer" in k]
+    cw = [v for k, v in _pmc_rows(args.summarize_pmc[1], "WRITE_SIZE") if "copyBuffer" in k]
+    if not cf or not cw:
+        sys.exit("no copy dispatches in the calibration folders")
+    nbytes = float(1 << 30)
+    fetch_factor = nbytes / (1024.0 * float(np.median(cf)))
+    write_factor = nbytes / (1024.0 * float(np.median(cw)))
+    fetch = _pmc_rows(args.summarize_pmc[2], "FETCH_SIZE")
+    write = _pmc_rows(args.summarize_pmc[3], "WRITE_SIZE")
+    out = {}
+    for kn in sorted({k for k, _ in fetch if "k_demons_rows2" in k}):
+        # median over the dispatches that ran two iterations (the decision-only launch at a
+        # level's end moves almost nothing)
+        nf = [v * 1024.0 * fetch_factor for k, v in fetch if k == kn]
+        nw = [v * 1024.0 * write_factor for k, v in write if k == kn]
+        if not nf or not nw:
+            continue
+        big_f = [v for v in nf if v > 0.1 * max(nf)]
+        big_w = [v for v in nw if v > 0.1 * max(nw)]
+        name = kn.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0].replace("ebsd::", "")
+        out[name] = int(np.median(big_f) + np.median(big_w))
+    level0 = [k for k in out if "<4, 3, " in k]
+    rec = {"workload": args.workload, "kernel_source_sha": kernel_sha(), "bytes_per_launch": out,
+           "calibration": {"fetch_factor": fetch_factor, "write_factor": write_factor}}
+    if level0:
+        rec["levels"] = {"0": {"kernel": level0[0], "strip_rows": args.strip_rows,
+                               "two_iteration_rows": args.two_iteration_rows,
+                               "bytes_per_launch": out[level0[0]]}}
+    with open(args.traffic_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
 
 
 def kernel_sha():

@@ -92,8 +92,8 @@ typedef struct ebsd_params {
     int32_t second_pass;                  /* 1 = remap + XCF second pass (Eq. (12)); 0 = demons only */
     int32_t warm_start;                   /* square 128, 256 or 512 px, 3 levels: 1 = start demons from the
                                              network's field, 2 = from the Eq. (2) field fitted to it; 0 = zero */
-    float fallback_residual_px;           /* warm start: largest RMS misfit of the Eq. (2) fit, in px of the
-                                             coarsest level (the grid the field initialises) */
+    float fallback_residual_px;           /* warm start: largest RMS misfit of the Eq. (2) fit, in
+                                             full-resolution px of the registered pattern (0.5) */
     int32_t remap_interp;                 /* remap before the XCF (section 2, before Eq. (12)): 3 = cubic
                                              B-spline interpolation (the paper's cubic scheme), 1 = bilinear */
     int32_t xcf_passes;                   /* remap + XCF + Eq. (12) passes, 1..16: pass 1 remaps by R_finite
@@ -353,8 +353,9 @@ int ebsd_get_timing(ebsd_handle* h, double* level_ms, double* total_ms);
  * Fallback rule (warm start inside ebsd_register_batch): the Eq. (2) model is
  * fitted (Eq. (3): direct linear start, Gauss-Newton, det F = 1) to the
  * predicted field at the grid points within roi_radius_frac * W of the
- * pattern centre; if the RMS endpoint misfit, expressed in px of the coarse
- * grid (full-resolution misfit / 4), exceeds fallback_residual_px the pair
+ * pattern centre; if the RMS endpoint misfit, in full-resolution px of the
+ * registered pattern (the 256-px frame's misfit times N / 256 for an N-px
+ * pattern), exceeds fallback_residual_px the pair
  * starts from zero (EBSD_WARM_FALLBACK), otherwise (EBSD_WARM_USED) from
  * the predicted field (warm_start = 1) or from the field of the fitted model
  * (warm_start = 2: the network's estimate projected onto Eq. (2)).

@@ -259,17 +259,17 @@ def grid_points(H, W):
     return 4.0 * xs + 1.5, 4.0 * ys + 1.5
 
 
-def warm_fallback(field, H, W, pcs, radius_frac=0.3, threshold=0.5, levels=3):
+def warm_fallback(field, H, W, pcs, radius_frac=0.3, threshold=0.5, px_scale=1.0):
     """Fit the Eq. (2) model to a predicted coarse field and decide its use.
 
     field: [H/4, W/4, 2] (x, y) shifts in full-resolution px at the grid points.
     The fit uses the grid points within radius_frac * W of the pattern centre
     and the Eq. (3) solver (DLT start, Gauss-Newton, det F = 1).  The RMS
     distance between the fitted model's shifts and the predicted shifts is
-    the misfit (full-resolution px); the field is used when the misfit,
-    expressed in px of the coarsest pyramid level (the grid the field
-    initialises, 2^(levels-1) full-resolution px), is at most threshold.
-    Returns (use, rms_misfit_px, F).
+    the misfit (px of H x W); the field is used when the misfit in
+    full-resolution px of the registered pattern (misfit x px_scale: the
+    pattern's size over H when the fit runs in a resampled frame) is at most
+    threshold.  Returns (use, rms_misfit_px, F).
     """
     import oracle
     xs, ys = grid_points(H, W)
@@ -283,7 +283,7 @@ def warm_fallback(field, H, W, pcs, radius_frac=0.3, threshold=0.5, levels=3):
     py = pcs[1] + pcs[2] * v[1] / v[2]
     d2 = (px - cx - q[:, 0]) ** 2 + (py - cy - q[:, 1]) ** 2
     rms = float(np.sqrt(d2.mean()))
-    return rms / 2 ** (levels - 1) <= threshold, rms, F
+    return rms * px_scale <= threshold, rms, F
 
 
 def warm_init_field(field, H, W, pcs, mode, use, levels=3):
@@ -301,7 +301,7 @@ def warm_init_field(field, H, W, pcs, mode, use, levels=3):
     if mode == 1:
         u0[:] = np.moveaxis(f, -1, 0)
     else:
-        _, _, Ff = warm_fallback(f, H, W, pcs, threshold=np.inf, levels=levels)
+        _, _, Ff = warm_fallback(f, H, W, pcs, threshold=np.inf)
         gx, gy = grid_points(H, W)
         r = np.stack([gx - pcs[0], gy - pcs[1], np.full_like(gx, pcs[2])])
         v = np.einsum("ij,jhw->ihw", Ff, r)

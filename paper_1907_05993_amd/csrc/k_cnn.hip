@@ -231,6 +231,196 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
 }
 
+// Row-blocked variant (Cin a multiple of 16, H of 16; used for 32 output
+// channels, where it is faster than k_conv3x3): output tile 16 rows x
+// 32 columns x (32 NT) channels, wave w computes rows 4w .. 4w + 3.  Input
+// chunks of 16 channels (one 16-wide MFMA step per tap: lanes 0..31 carry
+// channels 0..7 of the chunk, lanes 32..63 channels 8..15).  For each kx the
+// wave reads the six input rows its four output rows need once and uses each
+// for up to three ky taps; for each ky it reads the NT weight fragments once
+// and uses them for the four rows: 6 + 3 NT fragment reads per 12 NT MFMAs
+// (against 2 + NT per 2 NT in k_conv3x3), so the LDS read port no longer sets
+// the pace.  Pixel rows in LDS are padded to 48 bytes (conflict-free 16-byte
+// reads); the next chunk's global loads are in flight during the current
+// chunk's MFMAs, as in k_conv3x3.
+constexpr int kR4TH = 16;
+
+template <int NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_conv3x3_r4(ConvArgs a)
+{
+    constexpr int CK = 16, PS = 24;
+    constexpr int HP = kR4TH + 2, WP = kConvTW + 2;
+    constexpr int BN = 32 * NT;
+    constexpr int SA = HP * WP * PS, SB = 9 * BN * PS;  // bf16 elements
+    constexpr int RP0 = BN + 8, RP1 = BN + 4;           // staging row pitches (bf16, fp32)
+    constexpr int ST0 = 4 * 128 * RP0 * 2;              // bf16 output tiles, bytes
+    constexpr int ST1 = 4 * 32 * RP1 * 4;               // fp32 output rows, bytes
+    constexpr int SMEM0 = 2 * (SA + SB);
+    constexpr int SMEM = SMEM0 > ST0 ? (SMEM0 > ST1 ? SMEM0 : ST1) : (ST0 > ST1 ? ST0 : ST1);
+    __shared__ __attribute__((aligned(16))) char smem[SMEM];
+    bf16_t* const sA = reinterpret_cast<bf16_t*>(smem);
+    bf16_t* const sB = sA + SA;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    int b = blockIdx.x;
+    const int nbk = a.Cout / BN, txn = a.W / kConvTW, tyn = a.H / kR4TH;
+    const int nb = b % nbk;
+    b /= nbk;
+    const int tx = b % txn;
+    b /= txn;
+    const int ty = b % tyn;
+    const int img = b / tyn;
+    const int x0 = tx * kConvTW, y0 = ty * kR4TH, co0 = nb * BN;
+    const int Cin = a.Cin;
+    const bf16_t* __restrict__ xin = a.x + (int64_t)img * a.H * a.W * Cin;
+
+    f32x16 acc[4][NT];
+    for (int r = 0; r < 4; r++)
+        for (int j = 0; j < NT; j++)
+            for (int i = 0; i < 16; i++) acc[r][j][i] = 0.0f;
+
+    constexpr int NA_TOT = HP * WP * 2, NB_TOT = 9 * BN * 2;
+    constexpr int NA = (NA_TOT + 255) / 256, NB = (NB_TOT + 255) / 256;
+    uint4 pa[NA], pb[NB];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int k = 0; k < NA; k++) {
+            const int i = tid + 256 * k;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (i < NA_TOT) {
+                const int g = i & 1, p = i >> 1;
+                const int hx = p % WP, hy = p / WP;
+                const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    v = *reinterpret_cast<const uint4*>(xin + ((int64_t)yy * a.W + xx) * Cin + c0 + 8 * g);
+            }
+            pa[k] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < NB; k++) {
+            const int i = tid + 256 * k;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (i < NB_TOT) {
+                const int g = i & 1, r = i >> 1;
+                const int co = r % BN, t = r / BN;
+                v = *reinterpret_cast<const uint4*>(a.w + ((int64_t)(co0 + co) * 9 + t) * Cin + c0 + 8 * g);
+            }
+            pb[k] = v;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int k = 0; k < NA; k++) {
+            const int i = tid + 256 * k;
+            if (i < NA_TOT) *reinterpret_cast<uint4*>(sA + (i >> 1) * PS + 8 * (i & 1)) = pa[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; k++) {
+            const int i = tid + 256 * k;
+            if (i < NB_TOT) *reinterpret_cast<uint4*>(sB + (i >> 1) * PS + 8 * (i & 1)) = pb[k];
+        }
+    };
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int c0 = 0; c0 < Cin; c0 += CK) {
+        const bool next = c0 + CK < Cin;
+        if (next) fetch(c0 + CK);
+#pragma unroll
+        for (int kx = 0; kx < 3; kx++) {
+            bf16x8 av[6];
+#pragma unroll
+            for (int i = 0; i < 6; i++)
+                av[i] = *reinterpret_cast<const bf16x8*>(sA + ((4 * wave + i) * WP + l32 + kx) * PS + 8 * h);
+#pragma unroll
+            for (int ky = 0; ky < 3; ky++) {
+                const int t = 3 * ky + kx;
+                bf16x8 bv[NT];
+#pragma unroll
+                for (int j = 0; j < NT; j++)
+                    bv[j] = *reinterpret_cast<const bf16x8*>(sB + (t * BN + 32 * j + l32) * PS + 8 * h);
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+#pragma unroll
+                    for (int j = 0; j < NT; j++) acc[r][j] = mfma16(av[r + ky], bv[j], acc[r][j]);
+            }
+        }
+        __syncthreads();
+        if (next) {
+            stash();
+            __syncthreads();
+        }
+    }
+
+    // epilogue (the K loop ended with a barrier: LDS is free)
+    if (a.mode == 0 || a.mode == 2) {
+        bf16_t* stg = reinterpret_cast<bf16_t*>(smem) + wave * 128 * RP0;
+        for (int j = 0; j < NT; j++) {
+            const int col = 32 * j + l32;
+            const float bias = a.bias[co0 + col];
+            for (int r = 0; r < 4; r++)
+                for (int i = 0; i < 16; i++) {
+                    const int px = 32 * r + 8 * (i >> 2) + 4 * h + (i & 3);
+                    stg[px * RP0 + col] = f2bf(fmaxf(acc[r][j][i] + bias, 0.0f));
+                }
+        }
+        __syncthreads();
+        bf16_t* out = static_cast<bf16_t*>(a.out);
+        if (a.mode == 0) {
+            for (int v = lane; v < 128 * (BN / 8); v += 64) {
+                const int px = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
+                const int yy = y0 + 4 * wave + (px >> 5), xx = x0 + (px & 31);
+                const int64_t p = ((int64_t)img * a.H + yy) * a.W + xx;
+                *reinterpret_cast<uint4*>(out + p * a.out_cs + a.out_co + co0 + 8 * g) =
+                    *reinterpret_cast<const uint4*>(stg + px * RP0 + 8 * g);
+            }
+        } else {
+            // 2 x 2 max-pool of the wave's rows (the selection of k_maxpool: first of the
+            // largest in the order (0,0), (0,1), (1,0), (1,1)): pooled rows y0 / 2 + 2 wave
+            // and + 1, columns x0 / 2 .. + 15
+            const int Hp = a.H / 2, Wp = a.W / 2;
+            for (int v = lane; v < 32 * (BN / 8); v += 64) {
+                const int q = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
+                const int pr = q >> 4, qc = q & 15;
+                const bf16_t* s0 = stg + (64 * pr + 2 * qc) * RP0 + 8 * g;
+                const bf16_t* s1 = s0 + RP0;
+                const bf16_t* s2 = s0 + 32 * RP0;
+                const bf16_t* s3 = s2 + RP0;
+                u16x8 o;
+                for (int e = 0; e < 8; e++) {
+                    uint16_t m = s0[e];
+                    if (bf2f(s1[e]) > bf2f(m)) m = s1[e];
+                    if (bf2f(s2[e]) > bf2f(m)) m = s2[e];
+                    if (bf2f(s3[e]) > bf2f(m)) m = s3[e];
+                    o[e] = m;
+                }
+                const int64_t p = ((int64_t)img * Hp + (y0 >> 1) + 2 * wave + pr) * Wp + (x0 >> 1) + qc;
+                *reinterpret_cast<u16x8*>(out + p * a.out_cs + a.out_co + co0 + 8 * g) = o;
+            }
+        }
+    } else {
+        float* stg = reinterpret_cast<float*>(smem) + wave * 32 * RP1;
+        float* out = static_cast<float*>(a.out);
+        for (int r = 0; r < 4; r++) {
+            for (int j = 0; j < NT; j++)
+                for (int i = 0; i < 16; i++) {
+                    const int px = 8 * (i >> 2) + 4 * h + (i & 3);
+                    stg[px * RP1 + 32 * j + l32] = acc[r][j][i];
+                }
+            __syncthreads();
+            const int yy = y0 + 4 * wave + r;
+            for (int v = lane; v < 32 * (BN / 4); v += 64) {
+                const int px = v / (BN / 4), g = v - (BN / 4) * (v / (BN / 4));
+                const int64_t p = ((int64_t)img * a.H + yy) * a.W + x0 + px;
+                *reinterpret_cast<float4*>(out + p * a.out_cs + a.out_co + co0 + 4 * g) =
+                    *reinterpret_cast<const float4*>(stg + px * RP1 + 4 * g);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---- 3x3 weight gradient -------------------------------------------------------
 //
 // Workgroup: 3 waves; wave w owns the three taps of kernel row ky = w for a
@@ -674,8 +864,16 @@ hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t s)
 {
     if (!conv3x3_supported(a.H, a.W, a.Cin, a.Cout) || a.n <= 0) return hipErrorInvalidValue;
     const int nt = a.Cout % 64 == 0 ? 2 : 1;
+    const dim3 block(256);
+    // 32 output channels (one N tile): the row-blocked kernel (c1b of the network: 553 against
+    // 599 us per 256 pairs); with two N tiles both kernels take the same time (measured per layer)
+    if (nt == 1 && a.Cin % 16 == 0 && a.H % kR4TH == 0) {
+        const int64_t tiles4 = (int64_t)a.n * (a.H / kR4TH) * (a.W / kConvTW) * (a.Cout / 32);
+        hipLaunchKernelGGL((k_conv3x3_r4<1>), dim3((unsigned)tiles4), block, 0, s, a);
+        return hipGetLastError();
+    }
     const int64_t tiles = (int64_t)a.n * (a.H / kConvTH) * (a.W / kConvTW) * (a.Cout / (32 * nt));
-    const dim3 grid((unsigned)tiles), block(256);
+    const dim3 grid((unsigned)tiles);
     if (a.Cin == 8) {
         if (nt == 2) hipLaunchKernelGGL((k_conv3x3<8, 2>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_conv3x3<8, 1>), grid, block, 0, s, a);

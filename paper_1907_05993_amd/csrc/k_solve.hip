@@ -930,8 +930,10 @@ k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys
     }
     fit_block_sum<1>(ss, sh);
     const double rms = sqrt(ss[0] / npts);
-    // the decision is taken in px of the coarse grid the field initialises
-    const bool use = rms * 0.25 <= threshold;
+    // the decision is taken in full-resolution px of the registered pattern:
+    // the fit ran in the network's frame (a grid of gw points a side), the
+    // pattern's coarse grid has go points a side
+    const bool use = rms * (double)go / (double)gw <= threshold;
     if (threadIdx.x == 0) {
         misfit[b] = (float)rms;
         flag[b] = use ? (uint32_t)EBSD_WARM_USED : (uint32_t)EBSD_WARM_FALLBACK;

@@ -231,10 +231,12 @@ def test_warm_fallback_accepts_model_fields_and_rejects_others():
     np.testing.assert_allclose(Ff, Fn_, atol=1e-9)
     # independent N(0, s^2) noise on both components: the RMS endpoint misfit
     # is s*sqrt(2) (less a negligible share for the 8 fitted parameters); the
-    # decision compares misfit / 4 (coarse-grid px) with the threshold
+    # decision compares the misfit (full-resolution px) with the threshold
     noise = np.random.default_rng(8).normal(0, 1.0, size=field.shape)
-    use2, rms2, _ = cnn.warm_fallback(field + 2.0 * noise, H, W, pcs)
-    assert not use2 and abs(rms2 - 2.0 * np.sqrt(2)) < 0.12
-    use3, rms3, _ = cnn.warm_fallback(field + 1.0 * noise, H, W, pcs)
-    assert use3 and abs(rms3 - np.sqrt(2)) < 0.06
-    assert not cnn.warm_fallback(field + 1.0 * noise, H, W, pcs, threshold=0.3)[0]
+    use2, rms2, _ = cnn.warm_fallback(field + 0.5 * noise, H, W, pcs)
+    assert not use2 and abs(rms2 - 0.5 * np.sqrt(2)) < 0.03
+    use3, rms3, _ = cnn.warm_fallback(field + 0.25 * noise, H, W, pcs)
+    assert use3 and abs(rms3 - 0.25 * np.sqrt(2)) < 0.015
+    assert not cnn.warm_fallback(field + 0.25 * noise, H, W, pcs, threshold=0.3)[0]
+    # in a resampled frame the misfit is scaled to the registered pattern's px
+    assert cnn.warm_fallback(field + 0.25 * noise, H, W, pcs, threshold=0.3, px_scale=0.5)[0]
