@@ -687,7 +687,7 @@ def summarize_pmc(args):
         big_w = [v for v in nw if v > 0.1 * max(nw)]
         name = kn.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0].replace("ebsd::", "")
         out[name] = int(np.median(big_f) + np.median(big_w))
-    level0 = [k for k in out if "<4, 3, " in k]
+    level0 = [k for k in out if k.startswith("k_demons_rows2<4, 3, %d," % args.two_iteration_rows)]
     rec = {"workload": args.workload, "kernel_source_sha": kernel_sha(), "bytes_per_launch": out,
            "calibration": {"fetch_factor": fetch_factor, "write_factor": write_factor}}
     if level0:
