@@ -49,6 +49,7 @@ class Params(C.Structure):
         ("background_static", C.c_int32),
         ("background_dynamic", C.c_double),
         ("background", C.c_void_p),
+        ("peak_fit", C.c_int32),
     ]
 
 
@@ -74,7 +75,7 @@ class _Outputs(C.Structure):
 
 def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_roi=20,
                 roi_size=32, roi_radius_frac=0.3, window=1, second_pass=1, remap_interp=3,
-                xcf_passes=1, first_pass=0, bandpass=(0.0, 0.0), background=(0, 0.0)):
+                xcf_passes=1, first_pass=0, bandpass=(0.0, 0.0), background=(0, 0.0), peak_fit=0):
     p = Params()
     p.levels = levels
     its = [iters] * MAX_LEVELS if np.isscalar(iters) else list(iters) + [0] * (MAX_LEVELS - len(iters))
@@ -94,6 +95,7 @@ def make_params(levels=3, iters=100, sigma=1.0, tol=0.0, pc=(0.5, 0.5, 0.7), n_r
     p.bandpass_lo, p.bandpass_hi = bandpass
     p.background_static, p.background_dynamic = int(background[0]), float(background[1])
     p.background = None
+    p.peak_fit = peak_fit
     return p
 
 
@@ -151,6 +153,9 @@ def lib():
         L.orc_fft1.argtypes = [d, d, C.c_int, C.c_int]
         L.orc_fft2.argtypes = [d, d, C.c_int, C.c_int]
         L.orc_xcf.argtypes = [d, d, C.c_int, C.c_int, d, d, d]
+        L.orc_xcf_fit.argtypes = [d, d, C.c_int, C.c_int, C.c_int, d, d, d]
+        L.orc_peak_fourier.restype = C.c_int
+        L.orc_peak_fourier.argtypes = [d, d, C.c_int, C.c_int, C.c_int, d, d]
         L.orc_peak_subpixel.restype = C.c_int
         L.orc_peak_subpixel.argtypes = [d, d]
         L.orc_register_pair.restype = C.c_int
@@ -466,16 +471,33 @@ def fft2(x, inverse=False):
     return re + 1j * im
 
 
-def xcf(A, B, window=1):
-    """ROI cross-correlation (section 2).  Returns (q, ph, C)."""
+def xcf(A, B, window=1, peak_fit=0):
+    """ROI cross-correlation (section 2).  peak_fit 0: the 2-D quadratic fit
+    of the peak's 3 x 3 neighbourhood; 1: the maximum of the correlation's
+    band-limited interpolant.  Returns (q, ph, C)."""
     A = _f64(A)
     B = _f64(B)
     N = A.shape[0]
     Cm = np.empty((N, N))
     q = np.empty(2)
     ph = np.empty(1)
-    lib().orc_xcf(_d(A), _d(B), N, int(window), _d(Cm), _d(q), _d(ph))
+    lib().orc_xcf_fit(_d(A), _d(B), N, int(window), int(peak_fit), _d(Cm), _d(q), _d(ph))
     return q, float(ph[0]), Cm
+
+
+def peak_fourier(P, start, integer_peak):
+    """Maximum of the band-limited interpolant of C = IFFT2(P) near `start`
+    (x, y), starting integer peak (sx, sy) in signed coordinates.  Returns
+    ((x, y), ok)."""
+    P = np.asarray(P, np.complex128)
+    N = P.shape[0]
+    re = np.ascontiguousarray(P.real)
+    im = np.ascontiguousarray(P.imag)
+    x = C.c_double(start[0])
+    y = C.c_double(start[1])
+    ok = lib().orc_peak_fourier(_d(re), _d(im), N, int(integer_peak[0]), int(integer_peak[1]), C.byref(x),
+                                C.byref(y))
+    return (x.value, y.value), bool(ok)
 
 
 def peak_subpixel(nb):

@@ -78,6 +78,9 @@ typedef struct {
     double background_dynamic;         /* sigma (px) of the dynamic background, 0 = off */
     const double* background;          /* static background [H][W]; orc_register_batch
                                           sets it to the mean of its test patterns */
+    int32_t peak_fit;                  /* sub-pixel peak of each XCF: 0 = 2-D quadratic
+                                          through the 3 x 3 neighbourhood, 1 = maximum of
+                                          the band-limited interpolant of C */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -1246,6 +1249,77 @@ int orc_peak_subpixel(const double* nb, double* d)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Maximum of the band-limited interpolant of a correlation (a reading of
+ * section 2's interpolated peak).  C is the inverse DFT of the cross-power
+ * spectrum P (N x N, k = 0..N-1, row = k_y); between the samples C is
+ * continued by its Fourier series,
+ *   C(x, y) = Re (1/N^2) sum_k P(k) exp(2 pi i (k_x' x + k_y' y) / N),
+ * with signed frequencies k' = k for k < N/2, k - N otherwise, which agrees
+ * with C at every integer point.  Newton's method on grad C = 0 with the
+ * exact gradient and Hessian of the series, from (x, y) (the quadratic
+ * estimate in signed shift coordinates), until the step is below 1e-12 px
+ * (at most 30 steps).  Returns 0 and leaves (x, y) when a Hessian is not
+ * negative definite or the iterate leaves the unit square around the
+ * starting integer peak (kx, ky), 1 on success.                            */
+int orc_peak_fourier(const double* Pre, const double* Pim, int N, int sx, int sy, double* x, double* y)
+{
+    const double pi = 3.14159265358979323846;
+    double cx = *x, cy = *y;
+    double* ex_re = (double*)malloc(sizeof(double) * N);
+    double* ex_im = (double*)malloc(sizeof(double) * N);
+    double* ey_re = (double*)malloc(sizeof(double) * N);
+    double* ey_im = (double*)malloc(sizeof(double) * N);
+    int ok = 0;
+    for (int it = 0; it < 30; it++) {
+        for (int k = 0; k < N; k++) {
+            const int ks = k < N / 2 ? k : k - N;
+            ex_re[k] = cos(2.0 * pi * ks * cx / N);
+            ex_im[k] = sin(2.0 * pi * ks * cx / N);
+            ey_re[k] = cos(2.0 * pi * ks * cy / N);
+            ey_im[k] = sin(2.0 * pi * ks * cy / N);
+        }
+        double gx = 0.0, gy = 0.0, hxx = 0.0, hxy = 0.0, hyy = 0.0;
+        for (int ky = 0; ky < N; ky++) {
+            const double fy = 2.0 * pi * (ky < N / 2 ? ky : ky - N) / N;
+            for (int kx = 0; kx < N; kx++) {
+                const double fx = 2.0 * pi * (kx < N / 2 ? kx : kx - N) / N;
+                const size_t i = (size_t)ky * N + kx;
+                /* e = exp(i (fx x + fy y)) */
+                const double er = ex_re[kx] * ey_re[ky] - ex_im[kx] * ey_im[ky];
+                const double ei = ex_re[kx] * ey_im[ky] + ex_im[kx] * ey_re[ky];
+                const double tr = Pre[i] * er - Pim[i] * ei; /* Re(P e) */
+                const double ti = Pre[i] * ei + Pim[i] * er; /* Im(P e) */
+                gx -= fx * ti;
+                gy -= fy * ti;
+                hxx -= fx * fx * tr;
+                hxy -= fx * fy * tr;
+                hyy -= fy * fy * tr;
+            }
+        }
+        const double det = hxx * hyy - hxy * hxy;
+        if (!(hxx < 0.0 && det > 0.0)) break;
+        const double dx = -(hyy * gx - hxy * gy) / det;
+        const double dy = -(hxx * gy - hxy * gx) / det;
+        cx += dx;
+        cy += dy;
+        if (fabs(cx - sx) > 1.0 || fabs(cy - sy) > 1.0) break;
+        if (sqrt(dx * dx + dy * dy) < 1e-12) {
+            ok = 1;
+            break;
+        }
+    }
+    free(ex_re);
+    free(ex_im);
+    free(ey_re);
+    free(ey_im);
+    if (ok) {
+        *x = cx;
+        *y = cy;
+    }
+    return ok;
+}
+
+/* ------------------------------------------------------------------------ */
 /* ROI cross-correlation and its peak (section 2).
  *   A = reference ROI, B = test ROI (N x N); each loses its own mean, is
  *   multiplied by the symmetric Hann window h (x) h, h[n] = 0.5 - 0.5
@@ -1262,8 +1336,18 @@ int orc_peak_subpixel(const double* nb, double* d)
  *   are tilted ridges, which per-axis fits mislocate;
  *   peak height PH = C_max / sqrt(sum (A w)^2 sum (B w)^2).
  * C (optional) receives the N x N correlation.  q = (x shift, y shift).   */
-void orc_xcf(const double* A, const double* B, int N, int window, double* C, double* q,
-             double* ph)
+void orc_xcf_fit(const double* A, const double* B, int N, int window, int peak_fit, double* C, double* q,
+                 double* ph);
+
+void orc_xcf(const double* A, const double* B, int N, int window, double* C, double* q, double* ph)
+{
+    orc_xcf_fit(A, B, N, window, 0, C, q, ph);
+}
+
+/* peak_fit 0: the 2-D quadratic fit of the 3 x 3 neighbourhood; 1: then the
+ * maximum of the band-limited interpolant (orc_peak_fourier) from there. */
+void orc_xcf_fit(const double* A, const double* B, int N, int window, int peak_fit, double* C, double* q,
+                 double* ph)
 {
     const double pi = 3.14159265358979323846;
     size_t NN = (size_t)N * N;
@@ -1299,6 +1383,9 @@ void orc_xcf(const double* A, const double* B, int N, int window, double* C, dou
         br[i] = pr;
         bi[i] = pi_;
     }
+    /* the spectrum, kept for the interpolant (ar, ai are free from here) */
+    memcpy(ar, br, sizeof(double) * NN);
+    memcpy(ai, bi, sizeof(double) * NN);
     orc_fft2(br, bi, N, 1);
     size_t best = 0;
     for (size_t i = 1; i < NN; i++)
@@ -1314,6 +1401,14 @@ void orc_xcf(const double* A, const double* B, int N, int window, double* C, dou
     int sy = ky < N / 2 ? ky : ky - N;
     q[0] = sx + d[0];
     q[1] = sy + d[1];
+    if (peak_fit == 1) {
+        /* C = IFFT(P) carries the 1/N^2 of the inverse transform */
+        for (size_t i = 0; i < NN; i++) {
+            ar[i] /= (double)NN;
+            ai[i] /= (double)NN;
+        }
+        orc_peak_fourier(ar, ai, N, sx, sy, &q[0], &q[1]);
+    }
     double nrm = sqrt(ea * eb);
     *ph = nrm > 0.0 ? c0 / nrm : 0.0;
     if (C) memcpy(C, br, sizeof(double) * NN);
@@ -1435,7 +1530,7 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
                     a[y * N + x] = Rn[(size_t)(y0[j] + y) * W + x0[j] + x];
                     b[y * N + x] = Tn[(size_t)(y0[j] + y) * W + x0[j] + x];
                 }
-            orc_xcf(a, b, N, p->window, NULL, q1 + 2 * j, ph + j);
+            orc_xcf_fit(a, b, N, p->window, p->peak_fit, NULL, q1 + 2 * j, ph + j);
         }
     } else {
         st |= orc_demons(Rn, Tn, H, W, p, u_init, field, its);
@@ -1477,7 +1572,7 @@ int orc_register_pair(const float* ref, const float* test, int H, int W, const o
                         a[y * N + x] = Rm[(size_t)(y0[j] + y) * W + x0[j] + x];
                         b[y * N + x] = Tn[(size_t)(y0[j] + y) * W + x0[j] + x];
                     }
-                orc_xcf(a, b, N, p->window, NULL, q2 + 2 * j, ph + j);
+                orc_xcf_fit(a, b, N, p->window, p->peak_fit, NULL, q2 + 2 * j, ph + j);
             }
             double Finf[9];
             st |= orc_solve_F(q2, cx, cy, nr, xs, ys, zs, Finf);

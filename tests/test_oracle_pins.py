@@ -356,6 +356,44 @@ def test_xcf_shift_is_integer_peak_plus_fit(orc, seed):
     assert np.all(np.abs(q - (4.6, -2.3)) < 0.5)  # the right integer cell (the quadratic under-reads)
 
 
+def _circular_shift(A, s):
+    """A (real, N x N) shifted by s = (sx, sy) px as a band-limited periodic
+    signal: phase ramp on the spectrum, Nyquist rows/columns zeroed first so
+    that the shifted signal stays real."""
+    N = A.shape[0]
+    FA = np.fft.fft2(A)
+    FA[N // 2, :] = 0.0
+    FA[:, N // 2] = 0.0
+    k = np.fft.fftfreq(N) * N
+    ramp = np.exp(-2j * np.pi * (k[None, :] * s[0] + k[:, None] * s[1]) / N)
+    return np.real(np.fft.ifft2(FA)), np.real(np.fft.ifft2(FA * ramp))
+
+
+@pytest.mark.parametrize("s", [(0.37, -0.21), (-2.8, 4.45), (5.5, -0.5)])
+def test_xcf_interpolant_peak_exact_for_band_limited_shift(orc, s):
+    """Without a window, the correlation of a band-limited periodic pattern
+    with its copy shifted by s is its autocorrelation shifted by s, whose
+    band-limited interpolant peaks exactly at s: the interpolant fit recovers
+    s to rounding, where the 3 x 3 quadratic fit is biased."""
+    A0 = ndi.gaussian_filter(rng(320).normal(size=(64, 64)), 2.0, mode="wrap")
+    A, B = _circular_shift(A0, s)
+    q, _, _ = orc.xcf(A, B, 0, peak_fit=1)
+    np.testing.assert_allclose(q, s, atol=1e-9)
+    q0, _, _ = orc.xcf(A, B, 0, peak_fit=0)
+    assert np.abs(q0 - s).max() > 1e-4
+
+
+def test_peak_fourier_start_independent(orc):
+    """Newton's method on the interpolant converges to the same maximum from
+    any start in the peak's cell."""
+    A0 = ndi.gaussian_filter(rng(321).normal(size=(32, 32)), 1.5, mode="wrap")
+    A, B = _circular_shift(A0, (1.3, -0.6))
+    P = np.fft.fft2(B) * np.conj(np.fft.fft2(A)) / 32 ** 2
+    ends = [orc.peak_fourier(P, st, (1, -1))[0] for st in [(1.0, -1.0), (1.4, -0.7), (0.8, -0.55)]]
+    for e in ends:
+        np.testing.assert_allclose(e, (1.3, -0.6), atol=1e-9)
+
+
 # -- F solve (Eq. 2-3), polar (Eq. 4-5), rotation vector -------------------------------------
 
 def _project(F, cx, cy, xs, ys, zs):
@@ -909,7 +947,25 @@ def test_pipeline_recovers_known_small_rotation(orc, kind, angle, seed):
     print(f"{kind} {angle:.1e}: rotation error {err:.2e} rad, max |dF| {dF:.2e}")
     assert err < 1e-5, err
     assert dF < 2e-5, dF
-    # a single pass leaves more (the sub-pixel fit under-reads the residual)
+    # a single pass leaves more (the windowed correlation of each ROI under-reads its residual shift)
     one = orc.register_batch(ref, test, orc.make_params(levels=3, iters=50, sigma=1.0, roi_size=64,
                                                         n_roi=20), want_field=False)
     assert np.linalg.norm(one["rotvec"][0] - truth) > err
+
+
+@pytest.mark.parametrize("kind,angle,seed", KNOWN_ROTATION_CASES[1:3] + KNOWN_ROTATION_CASES[4:5])
+def test_single_pass_shortfall_is_not_the_peak_interpolation(orc, kind, angle, seed):
+    """The paper's single remap pass leaves 1e-4 rad here, and the maximum of
+    the correlation's band-limited interpolant (exact for a pure shift, pinned
+    above) instead of the 3 x 3 quadratic removes at most half of it: the
+    under-read comes from the windowed correlation of ROIs that still differ
+    by more than a shift after the first-pass remap, which only a further
+    remap of the whole pattern removes (the 8-pass case above)."""
+    ref, test, F = known_rotation_pair(kind, angle, seed)
+    truth = Rotation.from_matrix(scipy.linalg.polar(F)[0]).as_rotvec()
+    errs = []
+    for pf in (0, 1):
+        p = orc.make_params(levels=3, iters=50, sigma=1.0, roi_size=64, n_roi=20, peak_fit=pf)
+        errs.append(np.linalg.norm(orc.register_batch(ref, test, p, want_field=False)["rotvec"][0] - truth))
+    print(f"{kind} {angle:.1e}: single pass, quadratic peak {errs[0]:.2e} rad, interpolant peak {errs[1]:.2e} rad")
+    assert 5e-5 < errs[1] < errs[0] < 2.5 * errs[1]
