@@ -604,18 +604,22 @@ def main():
         }
         log(f"[bench] cpu oracle: {m} pairs in {dt:.1f} s on {o['threads']} threads")
     if par_idx is not None:
-        # the timed calls' outputs of the sampled pairs against the oracle: field differences
-        # (median and 95th percentile of |du| per pair; the iteration is chaotic at full depth in
-        # noise-dominated pixels), iteration counts, and F from the GPU's R_finite (the oracle's
-        # second pass) to 1e-6.  The warm run's oracle starts from the same initial field (the
-        # network field fitted to Eq. (2), or zero where the GPU fell back).
+        # the timed calls' outputs of the sampled pairs against the oracle: iteration counts, F from
+        # the GPU's R_finite (the oracle's second pass) to 1e-6, and the field.  At 3 x 150 the
+        # iteration is chaotic in noise-dominated pixels, so the field's difference is judged
+        # against what FP32 rounding alone does there: the oracle's iteration in float32 (two
+        # rounding orders) on the same pairs from the same initial field.  Per statistic of |du|
+        # (median, 95th percentile, RMS) the median over the pairs is at most 2 x the envelope's,
+        # and no pair's median or 95th percentile is above 10 x its own envelope's.  The warm
+        # run's oracle starts from the same initial field as the GPU (the network field fitted to
+        # Eq. (2), or zero where the GPU fell back).
         from oracle import cnn as ocnn
+        from oracle import fp32_demons
         pcs = (0.5 * W - 0.5, 0.5 * H - 0.5, 0.7 * W)
         par = {"pairs": [int(i) for i in par_idx],
-               "bars": {"field_median_px": 2e-3, "F_common_R_finite": 1e-6, "iters": "equal",
-                        "note": "the field's 95th percentile and RMS are reported, not gated: at 3 x 150 the "
-                                "iteration is chaotic in noise-dominated pixels, and the tests bound them by "
-                                "the envelope of the oracle's iteration in float32 on the same pairs"}}
+               "bars": {"field_stats_median_over_pairs": "<= 2 x FP32 envelope",
+                        "field_median_p95_per_pair": "<= 10 x own FP32 envelope",
+                        "F_common_R_finite": 1e-6, "iters": "equal"}}
         ok_all = True
         for name, r in (("warm", warm), ("plain", plain)):
             if r is None or r["parity"] is None:
@@ -626,25 +630,31 @@ def main():
                 u0 = np.stack([ocnn.warm_init_field(g["warm_field"][k].astype(np.float64), H, W, pcs, 2,
                                                     bool(g["status"][k] & ebsd.WARM_USED))
                                for k in range(len(par_idx))])
-                o = oracle.register_batch(par_in[0], par_in[1], op, u_init=u0)
             else:
-                o = oracle.register_batch(par_in[0], par_in[1], op)
+                u0 = None
+            o = oracle.register_batch(par_in[0], par_in[1], op, u_init=u0)
             d = np.sqrt(((g["field"].astype(np.float64) - o["field"]) ** 2).sum(axis=1)).reshape(len(par_idx), -1)
-            med = np.median(d, axis=1)
-            p95 = np.percentile(d, 95, axis=1)
-            rms = np.sqrt((d ** 2).mean(axis=1))
+            gs = np.stack([np.median(d, axis=1), np.percentile(d, 95, axis=1), np.sqrt((d ** 2).mean(axis=1))], 1)
+            env = fp32_demons.envelope(par_in[0], par_in[1], o["field"], u_init=u0, workers=8,
+                                       levels=3, iters=args.cap, sigma=1.0, tol=args.tol)
             o2 = oracle.register_batch(par_in[0], par_in[1], op, rfin=g["R_finite"], want_field=False)
             dF = np.abs(g["F"] - o2["F"]).max(axis=(1, 2))
             iters_eq = bool(np.array_equal(g["iters"], o["iters"]))
-            ok = bool((med <= 2e-3).all() and (dF <= 1e-6).all() and iters_eq)
+            gm, em = np.median(gs, 0), np.median(env, 0)
+            env_ok = bool(np.all(gm <= 2.0 * em) and np.all(gs[:, :2] <= 10.0 * env[:, :2]))
+            ok = bool(env_ok and (dF <= 1e-6).all() and iters_eq)
             ok_all = ok_all and ok
-            par[name] = {"field_median_px_max": float(med.max()), "field_p95_px_median": float(np.median(p95)),
-                         "field_p95_px_max": float(p95.max()), "field_rms_px_median": float(np.median(rms)),
+            par[name] = {"field_px_median_over_pairs": {"median": float(gm[0]), "p95": float(gm[1]), "rms": float(gm[2])},
+                         "fp32_envelope_median_over_pairs": {"median": float(em[0]), "p95": float(em[1]),
+                                                             "rms": float(em[2])},
+                         "field_median_px_max": float(gs[:, 0].max()), "field_p95_px_max": float(gs[:, 1].max()),
+                         "max_ratio_to_own_envelope": float((gs[:, :2] / env[:, :2]).max()),
                          "F_common_R_finite_max": float(dF.max()),
                          "iters_equal": iters_eq, "pass": ok}
-            log(f"[bench] parity {name}: {len(par_idx)} pairs, field median <= {med.max():.1e} px, "
-                f"p95 <= {p95.max():.1e} px, |dF| <= {dF.max():.1e}, iterations equal {iters_eq} "
-                f"({time.perf_counter() - tp:.1f} s)")
+            log(f"[bench] parity {name}: {len(par_idx)} pairs, |du| median/p95/rms median over pairs "
+                f"{gm[0]:.1e}/{gm[1]:.1e}/{gm[2]:.1e} px vs FP32 envelope {em[0]:.1e}/{em[1]:.1e}/{em[2]:.1e}, "
+                f"worst pair {(gs[:, :2] / env[:, :2]).max():.2f} x its envelope, |dF| <= {dF.max():.1e}, "
+                f"iterations equal {iters_eq} ({time.perf_counter() - tp:.1f} s)")
         par["pass"] = ok_all
         rec["parity"] = par
     print(json.dumps(rec), flush=True)

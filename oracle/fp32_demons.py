@@ -1,5 +1,8 @@
 """The oracle's multi-resolution demons iteration with FP32 storage and FP32
-arithmetic (NumPy float32), for the test suite only.
+arithmetic (NumPy float32).
+
+TEST INFRASTRUCTURE, like the rest of this package: the test suite and the
+benchmark's parity check use it; the product never does.
 
 The FP64 oracle (oracle/ebsd_oracle.c) takes each step of section 1's
 multi-resolution demons and Eq. (1) in the paper's order; this module takes
@@ -13,6 +16,8 @@ many iterations: Eq. (1)'s update is ill-conditioned in noise-dominated pixels
 round differently drift apart with depth.  The GPU's difference from the FP64
 oracle at full depth is judged against this module's difference from it.
 """
+import os
+
 import numpy as np
 
 f32 = np.float32
@@ -157,14 +162,91 @@ def field_stats(a, b):
     return float(np.median(d)), float(np.percentile(d, 95)), float(np.sqrt((d ** 2).mean()))
 
 
-def envelope(refs, tests, fields64, u_init=None, **kw):
+def _cases(refs, tests, fields64, u_init, cases, kw):
+    """field_stats of the FP32 run for each (pair, cols_first) case."""
+    out = []
+    for i, cf in cases:
+        u, _ = demons(refs[i], tests[i], u_init=None if u_init is None else u_init[i], cols_first=bool(cf), **kw)
+        out.append(field_stats(u, fields64[i]))
+    return out
+
+
+def _cases_in_processes(refs, tests, fields64, u_init, cases, kw, workers, timeout_s=900):
+    """The cases split over `workers` child interpreters (python -m oracle.fp32_demons),
+    inputs and results through .npz/.npy files in a temporary folder; None when a
+    child cannot be started or fails."""
+    import json
+    import shutil
+    import subprocess
+    import sys
+    import tempfile
+    pkg_parent = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    d = tempfile.mkdtemp(prefix="fp32_envelope_")
+    procs = []
+    try:
+        arrays = {"refs": np.asarray(refs), "tests": np.asarray(tests), "fields": np.asarray(fields64)}
+        if u_init is not None:
+            arrays["u_init"] = np.asarray(u_init)
+        np.savez(os.path.join(d, "in.npz"), **arrays)
+        env = dict(os.environ)
+        env["PYTHONPATH"] = pkg_parent + (os.pathsep + env["PYTHONPATH"] if env.get("PYTHONPATH") else "")
+        for w in range(workers):
+            mine = cases[w::workers]
+            if not mine:
+                continue
+            job = os.path.join(d, "job%d.json" % w)
+            with open(job, "w") as f:
+                json.dump({"cases": [[int(i), bool(cf)] for i, cf in mine], "kw": kw}, f)
+            procs.append((w, subprocess.Popen([sys.executable, "-m", "oracle.fp32_demons", d, job],
+                                              env=env, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)))
+        stats = [None] * len(cases)
+        for w, pr in procs:
+            _, err = pr.communicate(timeout=timeout_s)
+            if pr.returncode != 0:
+                return None
+            res = np.load(os.path.join(d, "job%d.npy" % w), allow_pickle=False)
+            for k, j in enumerate(range(w, len(cases), workers)):
+                stats[j] = tuple(res[k])
+        return stats
+    except (OSError, subprocess.SubprocessError):
+        return None
+    finally:
+        for _, pr in procs:
+            if pr.poll() is None:
+                pr.kill()
+                pr.wait()
+        shutil.rmtree(d, ignore_errors=True)
+
+
+def envelope(refs, tests, fields64, u_init=None, workers=1, **kw):
     """Per pair, the largest (median, p95, RMS) of |u32 - u64| over the two
     FP32 rounding orders (rows or columns smoothed first), against the FP64
-    fields fields64 [n, 2, H, W].  Returns an [n, 3] array."""
+    fields fields64 [n, 2, H, W].  Returns an [n, 3] array.  workers > 1
+    runs the (pair, order) cases in that many child interpreters (falling
+    back to this process if they cannot run); kw: demons() arguments."""
     n = len(refs)
+    cases = [(i, cf) for i in range(n) for cf in (False, True)]
+    stats = None
+    if workers > 1 and len(cases) > 1:
+        stats = _cases_in_processes(refs, tests, fields64, u_init, cases, kw, min(workers, len(cases)))
+    if stats is None:
+        stats = _cases(refs, tests, fields64, u_init, cases, kw)
     out = np.zeros((n, 3))
-    for i in range(n):
-        for cf in (False, True):
-            u, _ = demons(refs[i], tests[i], u_init=None if u_init is None else u_init[i], cols_first=cf, **kw)
-            out[i] = np.maximum(out[i], field_stats(u, fields64[i]))
+    for (i, _), st in zip(cases, stats):
+        out[i] = np.maximum(out[i], st)
     return out
+
+
+def _child(folder, job):
+    import json
+    with open(job) as f:
+        spec = json.load(f)
+    with np.load(os.path.join(folder, "in.npz"), allow_pickle=False) as z:
+        u_init = z["u_init"] if "u_init" in z.files else None
+        res = _cases(z["refs"], z["tests"], z["fields"], u_init, [tuple(c) for c in spec["cases"]], spec["kw"])
+    np.save(job[:-5] + ".npy", np.array(res, dtype=np.float64))
+
+
+if __name__ == "__main__":
+    import sys
+    _child(sys.argv[1], sys.argv[2])

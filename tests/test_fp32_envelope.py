@@ -1,6 +1,6 @@
 """The FP32 envelope of the demons iteration at depth (CPU only).
 
-tests/fp32_demons.py runs the oracle's multi-resolution demons with FP32
+oracle/fp32_demons.py runs the oracle's multi-resolution demons with FP32
 storage and arithmetic.  At shallow depth it equals the FP64 oracle to FP32
 rounding (the same algorithm: a dropped term, a wrong sign or index would
 show here), and at the batch workload's depth (3 levels x 150 iterations at
@@ -12,7 +12,7 @@ difference from the oracle is judged against this envelope
 import numpy as np
 import pytest
 
-import fp32_demons
+from oracle import fp32_demons
 
 
 def _stats(a, b):
@@ -58,3 +58,20 @@ def test_fp32_envelope_at_full_depth(orc, pairs):
         # far above one step's rounding (the shallow case), within the robust bars of the GPU tests
         assert rms >= 1e-4
         assert med <= 2e-3 and p95 <= 0.05
+
+
+def test_envelope_in_child_processes_equals_in_process(orc, pairs):
+    """The envelope computed by child interpreters (as the benchmark's parity
+    check runs it) equals the same cases run in this process, with and
+    without an initial field."""
+    refs, tests = pairs
+    op = orc.make_params(levels=3, iters=5, sigma=1.0, roi_size=64, n_roi=20)
+    o = orc.register_batch(refs, tests, op)
+    u0 = np.zeros((2, 2, 64, 64))
+    u0[:, 0] = 0.25
+    u0[1, 1] = -0.5
+    for init in (None, u0):
+        a = fp32_demons.envelope(refs, tests, o["field"], u_init=init, levels=3, iters=5, sigma=1.0)
+        b = fp32_demons.envelope(refs, tests, o["field"], u_init=init, workers=3, levels=3, iters=5, sigma=1.0)
+        assert a.shape == (2, 3) and np.all(a > 0)
+        assert np.array_equal(a, b)
