@@ -614,7 +614,8 @@ def main():
         # run's oracle starts from the same initial field as the GPU (the network field fitted to
         # Eq. (2), or zero where the GPU fell back).
         from oracle import cnn as ocnn
-        from oracle import fp32_demons
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        import fp32_demons  # the oracle's iteration in float32 (test infrastructure)
         pcs = (0.5 * W - 0.5, 0.5 * H - 0.5, 0.7 * W)
         par = {"pairs": [int(i) for i in par_idx],
                "bars": {"field_stats_median_over_pairs": "<= 2 x FP32 envelope",

@@ -1,8 +1,8 @@
 """The oracle's multi-resolution demons iteration with FP32 storage and FP32
 arithmetic (NumPy float32).
 
-TEST INFRASTRUCTURE, like the rest of this package: the test suite and the
-benchmark's parity check use it; the product never does.
+Test infrastructure: the test suite and the benchmark's parity check use it;
+the product never does.  It is kept apart from the FP64 oracle on purpose.
 
 The FP64 oracle (oracle/ebsd_oracle.c) takes each step of section 1's
 multi-resolution demons and Eq. (1) in the paper's order; this module takes
@@ -172,7 +172,7 @@ def _cases(refs, tests, fields64, u_init, cases, kw):
 
 
 def _cases_in_processes(refs, tests, fields64, u_init, cases, kw, workers, timeout_s=900):
-    """The cases split over `workers` child interpreters (python -m oracle.fp32_demons),
+    """The cases split over `workers` child interpreters running this file,
     inputs and results through .npz/.npy files in a temporary folder; None when a
     child cannot be started or fails."""
     import json
@@ -180,7 +180,6 @@ def _cases_in_processes(refs, tests, fields64, u_init, cases, kw, workers, timeo
     import subprocess
     import sys
     import tempfile
-    pkg_parent = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     d = tempfile.mkdtemp(prefix="fp32_envelope_")
     procs = []
     try:
@@ -188,8 +187,6 @@ def _cases_in_processes(refs, tests, fields64, u_init, cases, kw, workers, timeo
         if u_init is not None:
             arrays["u_init"] = np.asarray(u_init)
         np.savez(os.path.join(d, "in.npz"), **arrays)
-        env = dict(os.environ)
-        env["PYTHONPATH"] = pkg_parent + (os.pathsep + env["PYTHONPATH"] if env.get("PYTHONPATH") else "")
         for w in range(workers):
             mine = cases[w::workers]
             if not mine:
@@ -197,8 +194,8 @@ def _cases_in_processes(refs, tests, fields64, u_init, cases, kw, workers, timeo
             job = os.path.join(d, "job%d.json" % w)
             with open(job, "w") as f:
                 json.dump({"cases": [[int(i), bool(cf)] for i, cf in mine], "kw": kw}, f)
-            procs.append((w, subprocess.Popen([sys.executable, "-m", "oracle.fp32_demons", d, job],
-                                              env=env, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)))
+            procs.append((w, subprocess.Popen([sys.executable, os.path.abspath(__file__), d, job],
+                                              stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)))
         stats = [None] * len(cases)
         for w, pr in procs:
             _, err = pr.communicate(timeout=timeout_s)

@@ -1,6 +1,6 @@
 """The FP32 envelope of the demons iteration at depth (CPU only).
 
-oracle/fp32_demons.py runs the oracle's multi-resolution demons with FP32
+tests/fp32_demons.py runs the oracle's multi-resolution demons with FP32
 storage and arithmetic.  At shallow depth it equals the FP64 oracle to FP32
 rounding (the same algorithm: a dropped term, a wrong sign or index would
 show here), and at the batch workload's depth (3 levels x 150 iterations at
@@ -12,7 +12,7 @@ difference from the oracle is judged against this envelope
 import numpy as np
 import pytest
 
-from oracle import fp32_demons
+import fp32_demons
 
 
 def _stats(a, b):

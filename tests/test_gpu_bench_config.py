@@ -14,7 +14,7 @@
   a common R_finite to 1e-6, equal iteration counts, and the field.  At this
   depth (3 x 150) the iteration is chaotic in the noise-dominated pixels, so
   the field's difference is judged against what FP32 rounding alone does:
-  the oracle's iteration in float32 (oracle/fp32_demons.py, two rounding
+  the oracle's iteration in float32 (tests/fp32_demons.py, two rounding
   orders, the larger difference per statistic) on the same pairs from the
   same initial field.  Per statistic of |du| (median, 95th percentile, RMS)
   the median over the 16 pairs of the GPU's difference is at most 2 times
@@ -118,7 +118,7 @@ def test_bench_registrar_matches_oracle_on_16_sampled_pairs(E, orc, batch, warm)
     else:
         u0 = None
         o = orc.register_batch(refs[SAMPLE], tests[SAMPLE], op)
-    from oracle import fp32_demons
+    import fp32_demons
     gf = g["field"].cpu().numpy()[SAMPLE]
     env = fp32_demons.envelope(refs[SAMPLE], tests[SAMPLE], o["field"], u_init=u0, workers=8, iters=150, tol=1e-4)
     gs = np.array([fp32_demons.field_stats(gf[k], o["field"][k]) for k in range(16)])

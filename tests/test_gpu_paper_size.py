@@ -114,7 +114,7 @@ def test_paper_workload_matches_oracle(E, orc, sigma, iters):
     the oracle's own field moves by 0.29 px RMS (24 px at worst) when its
     input is perturbed by 1e-7 relative after only 10 iterations per level,
     so the field is judged against the envelope of FP32 rounding alone: the
-    oracle's iteration with FP32 storage and arithmetic (oracle/fp32_demons.py)
+    oracle's iteration with FP32 storage and arithmetic (tests/fp32_demons.py)
     on the same pair, whose median, 95th percentile and RMS of |du| against
     the FP64 oracle (two rounding orders, the larger) bound the GPU's median
     and 95th percentile to within 10 times (one pair: a single realisation of
@@ -137,7 +137,7 @@ def test_paper_workload_matches_oracle(E, orc, sigma, iters):
     if sigma > 0:
         assert p95 <= 0.05
     else:
-        from oracle import fp32_demons
+        import fp32_demons
         emed, ep95, erms = fp32_demons.envelope(refs, tests, o["field"], levels=7, iters=iters, sigma=0.0)[0]
         print("  FP32 envelope |du|: rms %.1e, median %.1e, p95 %.1e" % (erms, emed, ep95))
         assert med <= 10.0 * emed and p95 <= 10.0 * ep95

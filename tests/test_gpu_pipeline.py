@@ -142,7 +142,7 @@ def test_batch_256_full_depth(E, orc):
 
     At this depth the field's difference from the FP64 oracle is bounded by
     what FP32 rounding alone produces: the oracle's iteration with FP32
-    storage and arithmetic (oracle/fp32_demons.py, the same steps in the same
+    storage and arithmetic (tests/fp32_demons.py, the same steps in the same
     order, two rounding orders, the larger difference per statistic) run on
     the same pairs gives the envelope.  Per statistic of |du| (median, 95th
     percentile, RMS over the pixels), the median over the pairs of the GPU's
@@ -150,7 +150,7 @@ def test_batch_256_full_depth(E, orc):
     95th percentile is above 10 times its own envelope's (a single pair's RMS
     is set by the few pixels where the iteration diverged and scatters by
     more than an order of magnitude between FP32 realisations)."""
-    from oracle import fp32_demons
+    import fp32_demons
     refs, tests, _ = gen("batch_256", 4)
     gp, op = params_pair(E, orc, iters=150, roi=64)
     g, o = compare(E, orc, refs, tests, gp, op, strict=False)
