@@ -403,6 +403,14 @@ int ebsd_cnn_train_step(ebsd_cnn* c, const float* ref, const float* test, const 
                         int32_t n, int32_t H, int32_t W, float lr, int32_t update, float* loss,
                         void* stream);
 
+/* Kernels of the inference forward pass (ebsd_cnn_forward and the warm
+ * start): on = 1 (the default) runs fused kernels (the first block's two
+ * convolutions and pooling in one pass, activations kept on chip); on = 0
+ * runs one kernel per layer, as the training step does.  Both give the same
+ * output bit for bit; the switch exists to measure and test the fusion.
+ * EBSD_EINVAL unless on is 0 or 1. */
+int ebsd_cnn_set_fusion(ebsd_cnn* c, int32_t on);
+
 /* Restart Adam (moments zero, step count 0). */
 int ebsd_cnn_reset_optimizer(ebsd_cnn* c);
 

@@ -45,6 +45,7 @@ struct ebsd_cnn {
     int64_t step = 0;
     bool have_params = false;
     bool packed = false;
+    bool fused = true;  // inference: fused kernels (equal bit for bit to the per-layer ones)
     int64_t off_w[10], off_b[10], off_hw, off_hb;
     bf16_t* wf[10] = {};
     bf16_t* wd[10] = {};
@@ -184,7 +185,8 @@ hipError_t pack_weights(ebsd_cnn* c, hipStream_t s)
 }
 
 hipError_t conv_fwd(ebsd_cnn* c, int l, int n, int H, int W, const bf16_t* x, bf16_t* out, int out_cs,
-                    int out_co, hipStream_t s, int mode = 0)
+                    int out_co, hipStream_t s, int mode = 0, bf16_t* out2 = nullptr, int out2_cs = 0,
+                    const bf16_t* x2 = nullptr, int c2 = 0)
 {
     const LayerDef& d = kLayers[l];
     ConvArgs a;
@@ -200,6 +202,10 @@ hipError_t conv_fwd(ebsd_cnn* c, int l, int n, int H, int W, const bf16_t* x, bf
     a.mode = mode;
     a.out_cs = out_cs;
     a.out_co = out_co;
+    a.out2 = out2;
+    a.out2_cs = out2_cs;
+    a.x2 = x2;
+    a.c2 = c2;
     return launch_conv3x3(a, s);
 }
 
@@ -216,10 +222,14 @@ hipError_t forward(ebsd_cnn* c, int n, int H, int W, float* out, hipStream_t s, 
         e = (x);                       \
     } while (0)
     const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
-    CK(conv_fwd(c, 0, n, H, W, c->x0, c->a1a, 32, 0, s));
-    if (infer) {
+    if (infer && c->fused) {
+        CK(launch_conv_stem(c->x0, c->wf[0], c->params + c->off_b[0], c->wf[1], c->params + c->off_b[1], n, H, W,
+                            c->p1, s));
+    } else if (infer) {
+        CK(conv_fwd(c, 0, n, H, W, c->x0, c->a1a, 32, 0, s));
         CK(conv_fwd(c, 1, n, H, W, c->a1a, c->p1, 32, 0, s, 2));
     } else {
+        CK(conv_fwd(c, 0, n, H, W, c->x0, c->a1a, 32, 0, s));
         CK(conv_fwd(c, 1, n, H, W, c->a1a, c->e1, 32, 0, s));
         CK(launch_maxpool(c->e1, n, H, W, 32, 32, 0, c->p1, s));
     }
@@ -231,12 +241,21 @@ hipError_t forward(ebsd_cnn* c, int n, int H, int W, float* out, hipStream_t s, 
         CK(launch_maxpool(c->e2, n, H1, W1, 64, 64, 0, c->p2, s));
     }
     CK(conv_fwd(c, 4, n, H, W, c->p2, c->a3a, 128, 0, s));
-    CK(conv_fwd(c, 5, n, H, W, c->a3a, c->cat, kCatC, 256, s));  // e3 = channels 256..383 of cat
-    CK(launch_maxpool(c->cat, n, H2, W2, 128, kCatC, 256, c->p3, s));
+    const bool fuse = infer && c->fused;
+    if (fuse) {  // e3 into channels 256..383 of cat and, pooled, into p3
+        CK(conv_fwd(c, 5, n, H, W, c->a3a, c->cat, kCatC, 256, s, 3, c->p3, 128));
+    } else {
+        CK(conv_fwd(c, 5, n, H, W, c->a3a, c->cat, kCatC, 256, s));  // e3 = channels 256..383 of cat
+        CK(launch_maxpool(c->cat, n, H2, W2, 128, kCatC, 256, c->p3, s));
+    }
     CK(conv_fwd(c, 6, n, H, W, c->p3, c->a4a, 256, 0, s));
     CK(conv_fwd(c, 7, n, H, W, c->a4a, c->e4, 256, 0, s));
-    CK(launch_upsample_into(c->e4, n, H3, W3, 256, c->cat, kCatC, s));
-    CK(conv_fwd(c, 8, n, H, W, c->cat, c->a5, 128, 0, s));
+    if (fuse) {  // d1 reads channels 0..255 (e4 upsampled) from e4 itself
+        CK(conv_fwd(c, 8, n, H, W, c->cat, c->a5, 128, 0, s, 0, nullptr, 0, c->e4, 256));
+    } else {
+        CK(launch_upsample_into(c->e4, n, H3, W3, 256, c->cat, kCatC, s));
+        CK(conv_fwd(c, 8, n, H, W, c->cat, c->a5, 128, 0, s));
+    }
     CK(conv_fwd(c, 9, n, H, W, c->a5, c->a6, 128, 0, s));
     CK(launch_head_fwd(c->a6, (int64_t)n * H2 * W2, kHeadC, c->params + c->off_hw, c->params + c->off_hb, out,
                        s));
@@ -560,6 +579,13 @@ int ebsd_cnn_set_optimizer(ebsd_cnn* c, const float* m, const float* v, int64_t 
         hipMemcpy(c->adam_v, v, kNumParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         return EBSD_EDEVICE;
     c->step = step;
+    return EBSD_OK;
+}
+
+int ebsd_cnn_set_fusion(ebsd_cnn* c, int32_t on)
+{
+    if (!c || (on != 0 && on != 1)) return EBSD_EINVAL;
+    c->fused = on != 0;
     return EBSD_OK;
 }
 

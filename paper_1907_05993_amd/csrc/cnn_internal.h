@@ -21,13 +21,29 @@ struct ConvArgs {
     void* out;         // mode 0: bf16, mode 1: fp32
     int32_t n, H, W, Cin, Cout;
     int32_t mode;      // 0: bf16(relu(acc + bias)); 1: fp32 acc (input gradients); 2: as 0, then the
-                       // 2 x 2 max-pool (out is [n][H/2][W/2][out_cs], the result of k_maxpool)
+                       // 2 x 2 max-pool (out is [n][H/2][W/2][out_cs], the result of k_maxpool);
+                       // 3: as 0, and also the pooled result into out2
     int32_t out_cs;    // channels per output pixel (>= Cout)
     int32_t out_co;    // channel offset of this output inside the output pixel
+    // mode 3: pooled output [n][H/2][W/2][out2_cs], channels [0, Cout)
+    bf16_t* out2 = nullptr;
+    int32_t out2_cs = 0;
+    // input channels [0, c2) read from x2 [n][H/2][W/2][c2] upsampled x2 (nearest) instead of x
+    // (whose channels [0, c2) are then not read); c2 a multiple of 32, 0: not used
+    const bf16_t* x2 = nullptr;
+    int32_t c2 = 0;
 };
 // Requirements: W % 32 == 0, H % 8 == 0, Cin % 32 == 0 or Cin == 8, Cout % 32 == 0.
 bool conv3x3_supported(int H, int W, int Cin, int Cout);
 hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t s);
+
+// The network's first block for inference in one pass: c1a (input packed as
+// 8 bf16 channels [n][H][W][8], weights w1a [32][9][8]) and c1b (w1b
+// [32][9][32]), each with bias and ReLU, then the 2 x 2 max-pool into p1
+// [n][H/2][W/2][32]; equal bit for bit to the two convolutions (mode 0, then
+// mode 2).  H % 16 == 0, W % 32 == 0.
+hipError_t launch_conv_stem(const bf16_t* x0, const bf16_t* w1a, const float* b1a, const bf16_t* w1b,
+                            const float* b1b, int n, int H, int W, bf16_t* p1, hipStream_t s);
 
 // Weight gradient of a 3x3 convolution: dW[t][ci][co] = sum over pixels of
 // x[p + off(t)][ci] * dz[p][co], split over pixel ranges into fp32 partial

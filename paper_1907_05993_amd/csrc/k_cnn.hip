@@ -44,7 +44,7 @@ __device__ inline f32x16 mfma16(const bf16x8& a, const bf16x8& b, const f32x16& 
 // cover all banks.
 constexpr int kConvTH = 8, kConvTW = 32;
 
-template <int CK, int NT>
+template <int CK, int NT, bool UP = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_conv3x3(ConvArgs a)
 {
     constexpr int HP = kConvTH + 2, WP = kConvTW + 2;
@@ -78,6 +78,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const int x0 = tx * kConvTW, y0 = ty * kConvTH, co0 = nb * BN;
     const int Cin = a.Cin;
     const bf16_t* __restrict__ xin = a.x + (int64_t)img * a.H * a.W * Cin;
+    const bf16_t* __restrict__ x2in = UP ? a.x2 + (int64_t)img * (a.H >> 1) * (a.W >> 1) * a.c2 : nullptr;
 
     f32x16 acc[2][NT];
     for (int r = 0; r < 2; r++)
@@ -88,30 +89,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     // matrix-core loop and written to LDS after it (registers pa, pb).
     constexpr int NA_TOT = HP * WP * G, NB_TOT = 9 * BN * G;
     constexpr int NA = (NA_TOT + 255) / 256, NB = (NB_TOT + 255) / 256;
+    static_assert(NA <= 32, "halo mask");
     uint4 pa[NA], pb[NB];
+    uint32_t amask = 0;  // bit k: pa[k] lies inside the image (else the halo value is zero)
+    // Halo loads without branches (addresses clamped into the image; the zero of the padding
+    // is selected when the chunk is stored): with the loads under branches the compiler waited
+    // for them in the middle of the prefetch, before the current chunk's matrix-core loop.
     auto fetch = [&](int c0) {
+        amask = 0;
+        const bool up = UP && c0 < a.c2;  // uniform: the chunk lies in the upsampled source
 #pragma unroll
         for (int k = 0; k < NA; k++) {
-            const int i = tid + 256 * k;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (i < NA_TOT) {
-                const int g = i % G, p = i / G;
-                const int hx = p % WP, hy = p / WP;
-                const int yy = y0 + hy - 1, xx = x0 + hx - 1;
-                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                    v = *reinterpret_cast<const uint4*>(xin + ((int64_t)yy * a.W + xx) * Cin + c0 + 8 * g);
-            }
-            pa[k] = v;
+            const int i = min(tid + 256 * k, NA_TOT - 1);
+            const int g = i % G, p = i / G;
+            const int hx = p % WP, hy = p / WP;
+            const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+            const bool in = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+            const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
+            const bf16_t* src = up ? x2in + ((int64_t)(yc >> 1) * (a.W >> 1) + (xc >> 1)) * a.c2
+                                   : xin + ((int64_t)yc * a.W + xc) * Cin;
+            pa[k] = *reinterpret_cast<const uint4*>(src + c0 + 8 * g);
+            amask |= (in ? 1u : 0u) << k;
         }
 #pragma unroll
         for (int k = 0; k < NB; k++) {
+            // (a guarded load here: the clamped form makes the compiler keep pb in scratch)
             const int i = tid + 256 * k;
+            const int g = i % G, r = i / G;
+            const int co = r % BN, t = r / BN;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (i < NB_TOT) {
-                const int g = i % G, r = i / G;
-                const int co = r % BN, t = r / BN;
+            if (i < NB_TOT)
                 v = *reinterpret_cast<const uint4*>(a.w + ((int64_t)(co0 + co) * 9 + t) * Cin + c0 + 8 * g);
-            }
             pb[k] = v;
         }
     };
@@ -119,7 +127,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
         for (int k = 0; k < NA; k++) {
             const int i = tid + 256 * k;
-            if (i < NA_TOT) *reinterpret_cast<uint4*>(sA + (i / G) * PS + 8 * (i % G)) = pa[k];
+            const uint4 v = (amask >> k) & 1u ? pa[k] : make_uint4(0u, 0u, 0u, 0u);
+            if (i < NA_TOT) *reinterpret_cast<uint4*>(sA + (i / G) * PS + 8 * (i % G)) = v;
         }
 #pragma unroll
         for (int k = 0; k < NB; k++) {
@@ -163,7 +172,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
 
     // epilogue (the K loop ended with a barrier: LDS is free)
-    if (a.mode == 0 || a.mode == 2) {
+    if (a.mode != 1) {
         constexpr int RP = BN + 8;  // staging row pitch (bf16)
         bf16_t* stg = reinterpret_cast<bf16_t*>(smem) + wave * 64 * RP;
         for (int j = 0; j < NT; j++) {
@@ -177,7 +186,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         }
         __syncthreads();
         bf16_t* out = static_cast<bf16_t*>(a.out);
-        if (a.mode == 0) {
+        if (a.mode != 2) {
             for (int v = lane; v < 64 * (BN / 8); v += 64) {
                 const int px = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
                 const int yy = y0 + 2 * wave + (px >> 5), xx = x0 + (px & 31);
@@ -185,10 +194,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                 *reinterpret_cast<uint4*>(out + p * a.out_cs + a.out_co + co0 + 8 * g) =
                     *reinterpret_cast<const uint4*>(stg + px * RP + 8 * g);
             }
-        } else {
+        }
+        if (a.mode != 0) {
             // 2 x 2 max-pool of the wave's two rows (the selection of k_maxpool: first
             // of the largest in the order (0,0), (0,1), (1,0), (1,1)) into the
             // half-size output, pooled row y0 / 2 + wave, columns x0 / 2 .. + 15
+            // (mode 3: into out2, channels from 0)
+            bf16_t* const pout = a.mode == 3 ? a.out2 : out;
+            const int pcs = a.mode == 3 ? a.out2_cs : a.out_cs, pco = a.mode == 3 ? 0 : a.out_co;
             const int Hp = a.H / 2, Wp = a.W / 2;
             for (int v = lane; v < 16 * (BN / 8); v += 64) {
                 const int q = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
@@ -205,7 +218,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                     o[e] = m;
                 }
                 const int64_t p = ((int64_t)img * Hp + (y0 >> 1) + wave) * Wp + (x0 >> 1) + q;
-                *reinterpret_cast<u16x8*>(out + p * a.out_cs + a.out_co + co0 + 8 * g) = o;
+                *reinterpret_cast<u16x8*>(pout + p * pcs + pco + co0 + 8 * g) = o;
             }
         }
     } else {
@@ -231,8 +244,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
 }
 
-// Row-blocked variant (Cin a multiple of 16, H of 16; used for 32 output
-// channels, where it is faster than k_conv3x3): output tile 16 rows x
+// Row-blocked variant (Cin a multiple of 16, H of 16; see launch_conv3x3 for
+// where it is used): output tile 16 rows x
 // 32 columns x (32 NT) channels, wave w computes rows 4w .. 4w + 3.  Input
 // chunks of 16 channels (one 16-wide MFMA step per tap: lanes 0..31 carry
 // channels 0..7 of the chunk, lanes 32..63 channels 8..15).  For each kx the
@@ -283,19 +296,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     constexpr int NA_TOT = HP * WP * 2, NB_TOT = 9 * BN * 2;
     constexpr int NA = (NA_TOT + 255) / 256, NB = (NB_TOT + 255) / 256;
     uint4 pa[NA], pb[NB];
+    uint32_t amask = 0;  // bit k: pa[k] lies inside the image
     auto fetch = [&](int c0) {
+        amask = 0;
 #pragma unroll
         for (int k = 0; k < NA; k++) {
-            const int i = tid + 256 * k;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (i < NA_TOT) {
-                const int g = i & 1, p = i >> 1;
-                const int hx = p % WP, hy = p / WP;
-                const int yy = y0 + hy - 1, xx = x0 + hx - 1;
-                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                    v = *reinterpret_cast<const uint4*>(xin + ((int64_t)yy * a.W + xx) * Cin + c0 + 8 * g);
-            }
-            pa[k] = v;
+            const int i = min(tid + 256 * k, NA_TOT - 1);
+            const int g = i & 1, p = i >> 1;
+            const int hx = p % WP, hy = p / WP;
+            const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+            const bool in = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+            const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
+            pa[k] = *reinterpret_cast<const uint4*>(xin + ((int64_t)yc * a.W + xc) * Cin + c0 + 8 * g);
+            amask |= (in ? 1u : 0u) << k;
         }
 #pragma unroll
         for (int k = 0; k < NB; k++) {
@@ -313,7 +326,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
         for (int k = 0; k < NA; k++) {
             const int i = tid + 256 * k;
-            if (i < NA_TOT) *reinterpret_cast<uint4*>(sA + (i >> 1) * PS + 8 * (i & 1)) = pa[k];
+            const uint4 v = (amask >> k) & 1u ? pa[k] : make_uint4(0u, 0u, 0u, 0u);
+            if (i < NA_TOT) *reinterpret_cast<uint4*>(sA + (i >> 1) * PS + 8 * (i & 1)) = v;
         }
 #pragma unroll
         for (int k = 0; k < NB; k++) {
@@ -417,6 +431,199 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                     *reinterpret_cast<const float4*>(stg + px * RP1 + 4 * g);
             }
             __syncthreads();
+        }
+    }
+}
+
+// ---- fused first encoder block (inference) ---------------------------------------
+//
+// c1a (2 -> 32 channels, input packed as 8 channels) and c1b (32 -> 32), each a
+// 3x3 convolution with bias and ReLU, then the 2 x 2 max-pool, for one 16 x 32
+// tile of c1b's output per workgroup.  c1a is evaluated on the 18 x 34 halo
+// that c1b reads and kept in LDS as bf16 (zero outside the image: c1b's zero
+// padding), so the full-resolution activations never reach HBM.
+//
+// Both products run transposed (A = weights, B = activations: a lane's
+// accumulators hold 16 channels, 8 q + 4 h + e, of one pixel), so that each
+// lane converts and stores whole groups of channels and the pooling is a
+// maximum over its own two rows and its neighbour lane's.  The bf16 rounding
+// (round to nearest even) is monotonic, as are the bias and the ReLU, so the
+// pooled value bf16(relu(max of the four sums + bias)) is the value that the
+// per-layer kernels select after rounding each of the four.  Each sum is the
+// same matrix-core dot product in the same order as in the per-layer kernels
+// (c1a: one tap per half wave and k step, as k_conv3x3<8, 1>; c1b: 16-channel
+// halves, kx, ky, as k_conv3x3_r4<1>), so the output equals theirs bit for bit.
+constexpr int kStemTH = 16, kStemTW = 32;
+
+// two floats to packed bf16, round to nearest even (v_cvt_pk_bf16_f32)
+__device__ inline uint32_t pack_bf16x2(float lo, float hi)
+{
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){lo, hi}, b2));
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_conv_stem(const bf16_t* __restrict__ x0, const bf16_t* __restrict__ w1a, const float* __restrict__ b1a,
+            const bf16_t* __restrict__ w1b, const float* __restrict__ b1b, int H, int W, bf16_t* __restrict__ p1)
+{
+    constexpr int XH = kStemTH + 4, XW = kStemTW + 4;  // c1a input halo
+    constexpr int AH = kStemTH + 2, AW = kStemTW + 2;  // c1a output = c1b input halo
+    constexpr int NPX = AH * AW, MT = (NPX + 31) / 32;
+    constexpr int PS = 40;                             // bf16 per pixel row in LDS (80 B)
+    constexpr int SXB = XH * XW * 4, SAB = NPX * PS * 2, SBB = 9 * 32 * PS * 2;
+    __shared__ __attribute__((aligned(16))) char smem[SXB + SAB + SBB];
+    uint32_t* const sX = reinterpret_cast<uint32_t*>(smem);
+    bf16_t* const sA = reinterpret_cast<bf16_t*>(smem + SXB);
+    bf16_t* const sB = reinterpret_cast<bf16_t*>(smem + SXB + SAB);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    int b = blockIdx.x;
+    const int txn = W / kStemTW, tyn = H / kStemTH;
+    const int tx = b % txn;
+    b /= txn;
+    const int ty = b % tyn;
+    const int img = b / tyn;
+    const int x0t = tx * kStemTW, y0t = ty * kStemTH;
+
+    // every global load in flight at once (registers), then the LDS stores: the packed
+    // input's first two channels (ref, test) on the c1a halo, zero outside; c1b's weights
+    // [co][t][ci] (to sB[t][co][ci]); c1a's A fragments: tap f = 2 s + h of output channel
+    // l32 (8 packed channels), zero past tap 8.  Addresses are clamped into the buffers and
+    // the values selected afterwards, so that no load sits under a branch that waits for it.
+    constexpr int NXL = (XH * XW + 255) / 256, NWL = (9 * 32 * 4 + 255) / 256;
+    uint32_t xv[NXL];
+    uint4 wv[NWL];
+    u16x8 wa[5];
+#pragma unroll
+    for (int k = 0; k < NXL; k++) {
+        const int i = tid + 256 * k;
+        const int iy = i / XW, ix = i - XW * (i / XW);
+        const int yy = y0t - 2 + iy, xx = x0t - 2 + ix;
+        const bool in = i < XH * XW && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const int yc = min(max(yy, 0), H - 1), xc = min(max(xx, 0), W - 1);
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(x0 + (((int64_t)img * H + yc) * W + xc) * 8);
+        xv[k] = in ? v : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < NWL; k++) {
+        const int i = min(tid + 256 * k, 9 * 32 * 4 - 1);
+        const int g = i & 3, r = i >> 2;
+        const int co = r % 32, t = r / 32;
+        wv[k] = *reinterpret_cast<const uint4*>(w1b + ((int64_t)co * 9 + t) * 32 + 8 * g);
+    }
+#pragma unroll
+    for (int s = 0; s < 5; s++) {
+        const int f = 2 * s + h;
+        const u16x8 v = *reinterpret_cast<const u16x8*>(w1a + ((int64_t)l32 * 9 + min(f, 8)) * 8);
+        wa[s] = f < 9 ? v : (u16x8){0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    // biases of this lane's channels 8 q + 4 h + e
+    float4 bias_a[4], bias_b[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        bias_a[q] = *reinterpret_cast<const float4*>(b1a + 8 * q + 4 * h);
+        bias_b[q] = *reinterpret_cast<const float4*>(b1b + 8 * q + 4 * h);
+    }
+    // the weight values pass through an empty asm here, which pins their loads ahead of it
+    // (the compiler would otherwise sink each load to its store and wait for it there)
+#pragma unroll
+    for (int k = 0; k < NWL; k++) {
+        uint32_t q0 = wv[k].x, q1 = wv[k].y, q2 = wv[k].z, q3 = wv[k].w;
+        asm volatile("" : "+v"(q0), "+v"(q1), "+v"(q2), "+v"(q3));
+        wv[k] = make_uint4(q0, q1, q2, q3);
+    }
+#pragma unroll
+    for (int k = 0; k < NXL; k++) {
+        const int i = tid + 256 * k;
+        if (i < XH * XW) sX[i] = xv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NWL; k++) {
+        const int i = tid + 256 * k;
+        const int g = i & 3, r = i >> 2;
+        const int co = r % 32, t = r / 32;
+        if (i < 9 * 32 * 4) *reinterpret_cast<uint4*>(sB + (t * 32 + co) * PS + 8 * g) = wv[k];
+    }
+    __syncthreads();
+
+    // c1a on the halo, 32 consecutive halo pixels per product (this lane: pixel 32 m + l32),
+    // wave w taking products w, w + 4, ...
+    for (int m = wave; m < MT; m += 4) {
+        const int p = 32 * m + l32;
+        const int pa = min(p, NPX - 1);  // lanes past the halo compute a copy, never stored
+        const int ay = pa / AW, ax = pa - AW * (pa / AW);
+        f32x16 acc;
+        for (int i = 0; i < 16; i++) acc[i] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 5; s++) {
+            const int f = 2 * s + h;
+            const int t = f < 9 ? f : 0;  // the padding step reads tap 0 against zero weights
+            const int ky = t / 3, kx = t - 3 * (t / 3);
+            const uint32_t v = sX[(ay + ky) * XW + ax + kx];
+            const u16x8 raw = (u16x8){(uint16_t)(v & 0xFFFFu), (uint16_t)(v >> 16), 0, 0, 0, 0, 0, 0};
+            acc = mfma16(__builtin_bit_cast(bf16x8, wa[s]), __builtin_bit_cast(bf16x8, raw), acc);
+        }
+        const int yy = y0t - 1 + ay, xx = x0t - 1 + ax;
+        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        if (p < NPX) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const float4 bq = bias_a[q];
+                uint2 o;
+                o.x = pack_bf16x2(fmaxf(acc[4 * q] + bq.x, 0.0f), fmaxf(acc[4 * q + 1] + bq.y, 0.0f));
+                o.y = pack_bf16x2(fmaxf(acc[4 * q + 2] + bq.z, 0.0f), fmaxf(acc[4 * q + 3] + bq.w, 0.0f));
+                if (!in) o = make_uint2(0u, 0u);
+                *reinterpret_cast<uint2*>(sA + p * PS + 8 * q + 4 * h) = o;
+            }
+        }
+    }
+    __syncthreads();
+
+    // c1b: wave w computes output rows 4w .. 4w + 3 of the tile (this lane: column l32)
+    f32x16 acc[4];
+    for (int r = 0; r < 4; r++)
+        for (int i = 0; i < 16; i++) acc[r][i] = 0.0f;
+#pragma unroll
+    for (int c16 = 0; c16 < 2; c16++) {
+#pragma unroll
+        for (int kx = 0; kx < 3; kx++) {
+            bf16x8 av[6];
+#pragma unroll
+            for (int i = 0; i < 6; i++)
+                av[i] = *reinterpret_cast<const bf16x8*>(sA + ((4 * wave + i) * AW + l32 + kx) * PS + 16 * c16 + 8 * h);
+#pragma unroll
+            for (int ky = 0; ky < 3; ky++) {
+                const bf16x8 bv =
+                    *reinterpret_cast<const bf16x8*>(sB + ((3 * ky + kx) * 32 + l32) * PS + 16 * c16 + 8 * h);
+#pragma unroll
+                for (int r = 0; r < 4; r++) acc[r] = mfma16(bv, av[r + ky], acc[r]);
+            }
+        }
+    }
+
+    // epilogue: 2 x 2 max of the sums (rows 2 pr, 2 pr + 1 of this lane and of the neighbour
+    // lane l32 ^ 1), then bias, ReLU and bf16; even lanes hold pooled column l32 / 2
+    const int Hp = H / 2, Wp = W / 2;
+#pragma unroll
+    for (int pr = 0; pr < 2; pr++) {
+        float mx[16];
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            const float v = fmaxf(acc[2 * pr][i], acc[2 * pr + 1][i]);
+            mx[i] = fmaxf(v, __shfl_xor(v, 1));
+        }
+        if ((l32 & 1) == 0) {
+            const int64_t po = ((int64_t)img * Hp + (y0t >> 1) + 2 * wave + pr) * Wp + (x0t >> 1) + (l32 >> 1);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const float4 bq = bias_b[q];
+                uint2 o;
+                o.x = pack_bf16x2(fmaxf(mx[4 * q] + bq.x, 0.0f), fmaxf(mx[4 * q + 1] + bq.y, 0.0f));
+                o.y = pack_bf16x2(fmaxf(mx[4 * q + 2] + bq.z, 0.0f), fmaxf(mx[4 * q + 3] + bq.w, 0.0f));
+                *reinterpret_cast<uint2*>(p1 + po * 32 + 8 * q + 4 * h) = o;
+            }
         }
     }
 }
@@ -863,13 +1070,19 @@ bool conv3x3_supported(int H, int W, int Cin, int Cout)
 hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t s)
 {
     if (!conv3x3_supported(a.H, a.W, a.Cin, a.Cout) || a.n <= 0) return hipErrorInvalidValue;
+    if (a.mode < 0 || a.mode > 3 || (a.mode == 3 && (!a.out2 || a.out2_cs < a.Cout)) ||
+        (a.c2 != 0 && (a.c2 < 0 || a.c2 % 32 != 0 || a.c2 > a.Cin || !a.x2 || a.Cin == 8)))
+        return hipErrorInvalidValue;
     const int nt = a.Cout % 64 == 0 ? 2 : 1;
     const dim3 block(256);
-    // 32 output channels (one N tile): the row-blocked kernel (c1b of the network: 553 against
-    // 599 us per 256 pairs); with two N tiles both kernels take the same time (measured per layer)
-    if (nt == 1 && a.Cin % 16 == 0 && a.H % kR4TH == 0) {
-        const int64_t tiles4 = (int64_t)a.n * (a.H / kR4TH) * (a.W / kConvTW) * (a.Cout / 32);
-        hipLaunchKernelGGL((k_conv3x3_r4<1>), dim3((unsigned)tiles4), block, 0, s, a);
+    // The row-blocked kernel (16-row tiles, half the LDS fragment reads per product, input
+    // chunks of 16 channels) for 32 output channels, and for two N tiles when the input has
+    // only 32 channels (one 32-channel chunk in k_conv3x3: nothing to overlap the loads with);
+    // elsewhere both take the same time (measured per layer of the network).
+    if (a.Cin % 16 == 0 && a.H % kR4TH == 0 && a.mode != 3 && a.c2 == 0 && (nt == 1 || a.Cin == 32)) {
+        const int64_t tiles4 = (int64_t)a.n * (a.H / kR4TH) * (a.W / kConvTW) * (a.Cout / (32 * nt));
+        if (nt == 2) hipLaunchKernelGGL((k_conv3x3_r4<2>), dim3((unsigned)tiles4), block, 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3_r4<1>), dim3((unsigned)tiles4), block, 0, s, a);
         return hipGetLastError();
     }
     const int64_t tiles = (int64_t)a.n * (a.H / kConvTH) * (a.W / kConvTW) * (a.Cout / (32 * nt));
@@ -877,10 +1090,22 @@ hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t s)
     if (a.Cin == 8) {
         if (nt == 2) hipLaunchKernelGGL((k_conv3x3<8, 2>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_conv3x3<8, 1>), grid, block, 0, s, a);
+    } else if (a.c2 != 0) {
+        if (nt == 2) hipLaunchKernelGGL((k_conv3x3<32, 2, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3<32, 1, true>), grid, block, 0, s, a);
     } else {
         if (nt == 2) hipLaunchKernelGGL((k_conv3x3<32, 2>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_conv3x3<32, 1>), grid, block, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_stem(const bf16_t* x0, const bf16_t* w1a, const float* b1a, const bf16_t* w1b,
+                            const float* b1b, int n, int H, int W, bf16_t* p1, hipStream_t s)
+{
+    if (n <= 0 || H <= 0 || W <= 0 || H % kStemTH != 0 || W % kStemTW != 0) return hipErrorInvalidValue;
+    const int64_t tiles = (int64_t)n * (H / kStemTH) * (W / kStemTW);
+    hipLaunchKernelGGL(k_conv_stem, dim3((unsigned)tiles), dim3(256), 0, s, x0, w1a, b1a, w1b, b1b, H, W, p1);
     return hipGetLastError();
 }
 

@@ -31,30 +31,52 @@ __device__ double block_sum(double v, double* sh)
     return r;
 }
 
+// Sum over one pattern of f(v) for every value v, per thread in a fixed order:
+// 16-byte loads, four in flight per thread (one workgroup per pattern leaves
+// few waves per CU, so the loads' latency has to be covered by the thread's
+// own outstanding loads), and a scalar tail.  Requires 16-byte alignment for
+// the vector part (else all scalar).
+template <class F>
+__device__ double pattern_sum(const float* __restrict__ p, int64_t n, F f)
+{
+    constexpr int T = kStatThreads;
+    double acc = 0.0;
+    const int64_t nv = ((uintptr_t)p & 15) == 0 ? n / 4 : 0;
+    const float4* __restrict__ p4 = reinterpret_cast<const float4*>(p);
+    int64_t i = threadIdx.x;
+    for (; i + 3 * T < nv; i += 4 * T) {
+        const float4 a = p4[i], b = p4[i + T], c = p4[i + 2 * T], d = p4[i + 3 * T];
+        acc += f(a.x) + f(a.y) + f(a.z) + f(a.w);
+        acc += f(b.x) + f(b.y) + f(b.z) + f(b.w);
+        acc += f(c.x) + f(c.y) + f(c.z) + f(c.w);
+        acc += f(d.x) + f(d.y) + f(d.z) + f(d.w);
+    }
+    for (; i < nv; i += T) {
+        const float4 a = p4[i];
+        acc += f(a.x) + f(a.y) + f(a.z) + f(a.w);
+    }
+    for (int64_t j = 4 * nv + threadIdx.x; j < n; j += T) acc += f(p[j]);
+    return acc;
+}
+
 // Mean and 1/std of one pattern in FP64 (two passes: mean, then centred sum
 // of squares).  Non-finite values or zero contrast are flagged.
 __device__ void pattern_stats(const float* __restrict__ p, int64_t n, PatStat* out, double* sh)
 {
-    double s = 0.0;
-    int bad = 0;
-    for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
-        float v = p[i];
-        if (!isfinite(v)) bad = 1;
-        s += (double)v;
-    }
-    double badsum = block_sum((double)bad, sh);
-    double tot = block_sum(s, sh);
+    // the FP64 sum of finite floats cannot overflow (n < 2^40), so it is finite exactly
+    // when every value is
+    double tot = block_sum(pattern_sum(p, n, [](float v) { return (double)v; }), sh);
+    const bool bad = !isfinite(tot);
     double mean = tot / (double)n;
-    double ss = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
-        double d = (double)p[i] - mean;
-        ss += d * d;
-    }
+    double ss = bad ? 0.0 : pattern_sum(p, n, [mean](float v) {
+        const double d = (double)v - mean;
+        return d * d;
+    });
     double var = block_sum(ss, sh) / (double)n;
     if (threadIdx.x == 0) {
         PatStat st;
         st.pad = 0;
-        if (badsum > 0.0) {
+        if (bad) {
             st.mean = 0.0;
             st.inv_std = 0.0;
             st.flags = EBSD_NONFINITE_INPUT;
@@ -487,8 +509,21 @@ __global__ void __launch_bounds__(kStatThreads)
     pattern_stats(src, elems, &st, sh);
     __syncthreads();
     const PatStat s = st;
-    for (int64_t i = threadIdx.x; i < elems; i += kStatThreads)
-        dst[i] = s.flags ? 0.0f : (float)(((double)src[i] - s.mean) * s.inv_std);
+    const int64_t nv = (((uintptr_t)src | (uintptr_t)dst) & 15) == 0 ? elems / 4 : 0;
+    const float4* __restrict__ s4 = reinterpret_cast<const float4*>(src);
+    float4* __restrict__ d4 = reinterpret_cast<float4*>(dst);
+    auto nz = [&s](float v) { return s.flags ? 0.0f : (float)(((double)v - s.mean) * s.inv_std); };
+    int64_t i = threadIdx.x;
+    for (; i + kStatThreads < nv; i += 2 * kStatThreads) {
+        const float4 a = s4[i], b = s4[i + kStatThreads];
+        d4[i] = make_float4(nz(a.x), nz(a.y), nz(a.z), nz(a.w));
+        d4[i + kStatThreads] = make_float4(nz(b.x), nz(b.y), nz(b.z), nz(b.w));
+    }
+    for (; i < nv; i += kStatThreads) {
+        const float4 a = s4[i];
+        d4[i] = make_float4(nz(a.x), nz(a.y), nz(a.z), nz(a.w));
+    }
+    for (int64_t j = 4 * nv + threadIdx.x; j < elems; j += kStatThreads) dst[j] = nz(src[j]);
     if (flags && threadIdx.x == 0) flags[p] = s.flags;
 }
 

@@ -112,7 +112,7 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_load_model", "ebsd_set_model", "ebsd_stage_conv3x3", "ebsd_stage_conv3x3_dgrad",
             "ebsd_stage_conv3x3_wgrad", "ebsd_gen_pairs", "ebsd_get_fused_height", "ebsd_set_fused_height",
             "ebsd_set_gating", "ebsd_get_launch_counts", "ebsd_tilt_rotation", "ebsd_cnn_get_optimizer",
-            "ebsd_cnn_set_optimizer", "ebsd_stage_bandpass_static"]
+            "ebsd_cnn_set_optimizer", "ebsd_stage_bandpass_static", "ebsd_cnn_set_fusion"]
 
 
 def lib():
@@ -173,6 +173,7 @@ def lib():
         L.ebsd_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, C.c_float, i32,
                                           C.POINTER(C.c_float), vp]
         L.ebsd_cnn_reset_optimizer.argtypes = [vp]
+        L.ebsd_cnn_set_fusion.argtypes = [vp, i32]
         L.ebsd_cnn_get_optimizer.argtypes = [vp, vp, vp, i64, vp]
         L.ebsd_cnn_set_optimizer.argtypes = [vp, vp, vp, i64, i64]
         L.ebsd_load_model.argtypes = [vp, C.c_char_p]
@@ -597,6 +598,11 @@ class Cnn:
 
     def reset_optimizer(self):
         _check(lib().ebsd_cnn_reset_optimizer(self._h), "ebsd_cnn_reset_optimizer")
+
+    def set_fusion(self, on):
+        """Inference forward with the fused kernels (True, the default) or one
+        kernel per layer (False); equal outputs."""
+        _check(lib().ebsd_cnn_set_fusion(self._h, 1 if on else 0), "ebsd_cnn_set_fusion")
 
 
 # -- single-stage entry points -------------------------------------------------------

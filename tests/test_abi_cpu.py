@@ -166,6 +166,7 @@ def test_network_entry_points_validate_without_a_gpu(E):
     assert L.ebsd_cnn_load(None, b"x") == -1
     assert L.ebsd_load_model(None, b"x") == -1
     assert L.ebsd_set_model(None, None) == -1
+    assert L.ebsd_cnn_set_fusion(None, 1) == -1
 
 
 def test_tilt_rotation_is_eq13_as_printed(E, orc):

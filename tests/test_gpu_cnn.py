@@ -142,6 +142,34 @@ def test_forward_matches_oracle(E, orc, n, H, W):
     assert r <= 5e-3 and mx <= 1.5e-2
 
 
+@pytest.mark.parametrize("n,H,W", [(1, 256, 256), (3, 64, 256), (5, 128, 256), (2, 64, 512), (64, 256, 256)])
+def test_fused_forward_equals_per_layer_kernels(E, n, H, W):
+    """The inference forward with its fused kernels (first block's two
+    convolutions and pooling in one pass; the third block's pooling in its
+    second convolution's epilogue; the decoder's first convolution reading
+    the upsampled channels from the half-size activation) equals the
+    per-layer kernels bit for bit, with random and with trained parameters."""
+    print(f"case: fused forward n={n} {H}x{W}", flush=True)
+    net = E.Cnn(max_batch=64)
+    refs, tests, _ = pairs(n, H, W, seed=3)
+    r, t = cuda(refs), cuda(tests)
+    for params in ("random", "trained"):
+        if params == "random":
+            net.set_params(cnn.flatten(random_params(5)))
+        else:
+            net.load("paper_1907_05993_amd/weights/warm_cnn_256.bin")
+        net.set_fusion(True)
+        a = net.forward(r, t).cpu().numpy()
+        net.set_fusion(False)
+        b = net.forward(r, t).cpu().numpy()
+        net.set_fusion(True)
+        c = net.forward(r, t).cpu().numpy()
+        assert a.shape == (n, H // 4, W // 4, 2)
+        assert np.isfinite(a).all() and np.abs(a).max() > 0
+        assert np.array_equal(a, b), (params, np.abs(a - b).max())
+        assert np.array_equal(a, c)
+
+
 def test_gradients_loss_and_adam_match_oracle(E, orc):
     print("case: train step n=2 64x256", flush=True)
     n, H, W = 2, 64, 256
