@@ -93,6 +93,10 @@ def main():
                     help="the stopping tolerance of the scan-map and mixed-stream legs (full-res px)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (counter calibration) and exit")
+    ap.add_argument("--network-probe", type=int, default=0, metavar="REPS",
+                    help="only run the warm-start network's forward pass on the workload's batch (chunks "
+                         "of 256 pairs, after one untimed pass) REPS times, print the times and exit "
+                         "(for per-layer traces and counters)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("COPY_FETCH", "COPY_WRITE", "FETCH", "WRITE"),
                     help="write the HBM traffic record (--traffic-json) from four rocprofv3 --pmc output "
                          "folders (FETCH_SIZE and WRITE_SIZE of --copy-probe, then of a bench run) and exit")
@@ -116,6 +120,29 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
                           "launches": 3}))
+        return
+
+    if args.network_probe > 0:
+        import torch
+        from paper_1907_05993_amd import ebsd, synth as S
+        specs = S.workload_specs(args.workload, n=args.pairs) if args.pairs else S.workload_specs(args.workload)
+        r, t, _ = ebsd.gen_pairs(specs, labels=False)
+        net = ebsd.Cnn(device=0, max_batch=256)
+        net.load(WEIGHTS)
+        n = r.shape[0]
+        for c0 in range(0, n, 256):
+            net.forward(r[c0:c0 + 256], t[c0:c0 + 256])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(args.network_probe):
+            e0.record()
+            for c0 in range(0, n, 256):
+                net.forward(r[c0:c0 + 256], t[c0:c0 + 256])
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        print(json.dumps({"network_probe_pairs": int(n), "forward_ms": [round(x, 3) for x in times],
+                          "tflops_best": round(CNN_FLOP_PER_PAIR * n / (min(times) * 1e-3) / 1e12, 1)}))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
