@@ -29,6 +29,105 @@ constexpr int kResRows = kResThreads / 64;  // rows per pass
 constexpr int kResMaxPx = 64 * 64;
 constexpr size_t kResLdsBytes = sizeof(float) * 8 * kResMaxPx;  // R, T, u (2), v (2), row taps (2)
 
+// The three phases of an iteration over the rows a thread owns (y0, y0 + 8, ...), as
+// functions whose LDS operands are restrict-qualified: the arrays are disjoint parts of
+// the level's LDS, and with that known the compiler issues the reads of a group of four
+// rows together instead of waiting for each row's stores before the next row's reads (an
+// empty asm with a memory clobber between the two groups bounds the registers this takes).
+constexpr int kResMaxRows = 64 / kResRows;
+constexpr int kResGroup = kResMaxRows / 2;  // rows whose reads are issued together
+
+__device__ __forceinline__ void res_force(const float* __restrict__ sR, const float* __restrict__ sT,
+                                          const float* __restrict__ ux, const float* __restrict__ uy,
+                                          float* __restrict__ vx, float* __restrict__ vy, int h, int w, int x,
+                                          int y0, bool col, int xm, int xp, float sx, float wm1, float hm1,
+                                          float wm2, float hm2, float wf, int ddx, int ddy)
+{
+#pragma unroll
+    for (int j = 0; j < kResMaxRows; j++) {
+        if (j == kResGroup) asm volatile("" ::: "memory");  // two groups of rows: bounded registers
+        const int y = y0 + kResRows * j;
+        if (y < h && col) {
+            const int i = y * w + x;
+            const int ym = max(y - 1, 0), yp = min(y + 1, h - 1);
+            const float sy = (yp - ym == 2) ? 0.5f : 1.0f;
+            const float gxr = (sR[y * w + xp] - sR[y * w + xm]) * sx;
+            const float gyr = (sR[yp * w + x] - sR[ym * w + x]) * sy;
+            const float u0 = ux[i], u1 = uy[i];
+            const float xc = fminf(fmaxf((float)x + u0, 0.0f), wm1);
+            const float yc = fminf(fmaxf((float)y + u1, 0.0f), hm1);
+            const float xf = fminf(floorf(xc), wm2), yf = fminf(floorf(yc), hm2);
+            const float fx = xc - xf, fy = yc - yf;
+            const int o = (int)fmaf(yf, wf, xf);
+            const float wv =
+                lerp_ends(lerp_ends(sT[o], sT[o + ddx], fx), lerp_ends(sT[o + ddy], sT[o + ddx + ddy], fx), fy);
+            const float a = sR[i] - wv;
+            const float den = fmaf(gxr, gxr, fmaf(gyr, gyr, a * a));
+            float v0 = u0, v1 = u1;
+            if (den > 1e-9f) {
+                const float q = a * __builtin_amdgcn_rcpf(den);
+                v0 = fmaf(q, gxr, u0);
+                v1 = fmaf(q, gyr, u1);
+            }
+            vx[i] = v0;
+            vy[i] = v1;
+        }
+    }
+}
+
+template <int RAD>
+__device__ __forceinline__ void res_taps_h(const float* __restrict__ vx, const float* __restrict__ vy,
+                                           float* __restrict__ hx, float* __restrict__ hy, const Taps& tp, int h,
+                                           int w, int x, int y0, bool col)
+{
+#pragma unroll
+    for (int j = 0; j < kResMaxRows; j++) {
+        if (j == kResGroup) asm volatile("" ::: "memory");  // two groups of rows: bounded registers
+        const int y = y0 + kResRows * j;
+        if (y < h && col) {
+            const int i = y * w + x;
+            float ax = 0.0f, ay = 0.0f;
+#pragma unroll
+            for (int t = 0; t <= 2 * RAD; t++) {
+                const int c = y * w + clampi(x - RAD + t, 0, w - 1);
+                ax = fmaf(tp.w[t], vx[c], ax);
+                ay = fmaf(tp.w[t], vy[c], ay);
+            }
+            hx[i] = ax;
+            hy[i] = ay;
+        }
+    }
+}
+
+// returns this thread's sum of squared updates
+template <int RAD>
+__device__ __forceinline__ float res_taps_v(const float* __restrict__ hx, const float* __restrict__ hy,
+                                            float* __restrict__ ux, float* __restrict__ uy, const Taps& tp, int h,
+                                            int w, int x, int y0, bool col)
+{
+    float ss = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kResMaxRows; j++) {
+        if (j == kResGroup) asm volatile("" ::: "memory");  // two groups of rows: bounded registers
+        const int y = y0 + kResRows * j;
+        if (y < h && col) {
+            const int i = y * w + x;
+            float ox = 0.0f, oy = 0.0f;
+#pragma unroll
+            for (int t = 0; t <= 2 * RAD; t++) {
+                const int r = clampi(y - RAD + t, 0, h - 1) * w + x;
+                ox = fmaf(tp.w[t], hx[r], ox);
+                oy = fmaf(tp.w[t], hy[r], oy);
+            }
+            const float dx = ox - ux[i], dy = oy - uy[i];
+            ss = fmaf(dx, dx, fmaf(dy, dy, ss));
+            ux[i] = ox;
+            uy[i] = oy;
+        }
+    }
+    return ss;
+}
+
 template <int RAD>
 __global__ void __launch_bounds__(kResThreads)
     k_demons_resident(const Bucket* __restrict__ bk, int level, Taps tp, float tol, int cap)
@@ -70,63 +169,15 @@ __global__ void __launch_bounds__(kResThreads)
     int k = 0;
     bool conv = false;
     while (k < cap) {
-        // 1. force
-        for (int y = y0; y < h && col; y += kResRows) {
-            const int i = y * w + x;
-            const int ym = max(y - 1, 0), yp = min(y + 1, h - 1);
-            const float sy = (yp - ym == 2) ? 0.5f : 1.0f;
-            const float gxr = (sR[y * w + xp] - sR[y * w + xm]) * sx;
-            const float gyr = (sR[yp * w + x] - sR[ym * w + x]) * sy;
-            const float u0 = ux[i], u1 = uy[i];
-            const float xc = fminf(fmaxf((float)x + u0, 0.0f), wm1);
-            const float yc = fminf(fmaxf((float)y + u1, 0.0f), hm1);
-            const float xf = fminf(floorf(xc), wm2), yf = fminf(floorf(yc), hm2);
-            const float fx = xc - xf, fy = yc - yf;
-            const int o = (int)fmaf(yf, wf, xf);
-            const float wv = lerp_ends(lerp_ends(sT[o], sT[o + ddx], fx), lerp_ends(sT[o + ddy], sT[o + ddx + ddy], fx),
-                                       fy);
-            const float a = sR[i] - wv;
-            const float den = fmaf(gxr, gxr, fmaf(gyr, gyr, a * a));
-            float v0 = u0, v1 = u1;
-            if (den > 1e-9f) {
-                const float q = a * __builtin_amdgcn_rcpf(den);
-                v0 = fmaf(q, gxr, u0);
-                v1 = fmaf(q, gyr, u1);
-            }
-            vx[i] = v0;
-            vy[i] = v1;
-        }
+        // the column index passes through an empty asm once per iteration, so that the compiler
+        // recomputes the rows' LDS addresses in each iteration instead of keeping them all live
+        int xi = x;
+        asm volatile("" : "+v"(xi));
+        res_force(sR, sT, ux, uy, vx, vy, h, w, xi, y0, col, xm, xp, sx, wm1, hm1, wm2, hm2, wf, ddx, ddy);
         __syncthreads();
-        // 2. horizontal taps
-        for (int y = y0; y < h && col; y += kResRows) {
-            const int i = y * w + x;
-            float ax = 0.0f, ay = 0.0f;
-#pragma unroll
-            for (int j = 0; j <= 2 * RAD; j++) {
-                const int c = y * w + clampi(x - RAD + j, 0, w - 1);
-                ax = fmaf(tp.w[j], vx[c], ax);
-                ay = fmaf(tp.w[j], vy[c], ay);
-            }
-            hx[i] = ax;
-            hy[i] = ay;
-        }
+        res_taps_h<RAD>(vx, vy, hx, hy, tp, h, w, xi, y0, col);
         __syncthreads();
-        // 3. vertical taps into u, squared update
-        float ss = 0.0f;
-        for (int y = y0; y < h && col; y += kResRows) {
-            const int i = y * w + x;
-            float ox = 0.0f, oy = 0.0f;
-#pragma unroll
-            for (int j = 0; j <= 2 * RAD; j++) {
-                const int r = clampi(y - RAD + j, 0, h - 1) * w + x;
-                ox = fmaf(tp.w[j], hx[r], ox);
-                oy = fmaf(tp.w[j], hy[r], oy);
-            }
-            const float dx = ox - ux[i], dy = oy - uy[i];
-            ss = fmaf(dx, dx, fmaf(dy, dy, ss));
-            ux[i] = ox;
-            uy[i] = oy;
-        }
+        float ss = res_taps_v<RAD>(hx, hy, ux, uy, tp, h, w, xi, y0, col);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
