@@ -251,43 +251,44 @@ __device__ uint32_t solve_F(const RoiSet& rs, double* F, double* pool)
 {
     const int n = rs.n;
     uint32_t st = 0;
-    // direct linear start: null vector of the stacked constraints
-    double Mu[9][9];
+    // Linear start: Eq. (2) multiplied through by its denominator is linear in F, and with
+    // F33 = 1 (the normalisation the Gauss-Newton iteration keeps) in the 8 other entries; their
+    // least-squares solution (8 x 8 normal equations, Cholesky) starts the iteration, which
+    // converges to the same minimiser as from the unit-norm null vector of the 9-column system
+    // and takes none of its eigen-decomposition.  A singular system flags the pair and starts
+    // from the identity.
+    double f[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    {
+        double A[8][8], rhs[8], sol[8];
 #pragma unroll
-    for (int a = 0; a < 9; a++)
+        for (int a = 0; a < 8; a++) {
+            rhs[a] = 0.0;
 #pragma unroll
-        for (int b = 0; b < 9; b++) Mu[a][b] = 0.0;
-    for (int i = 0; i < n; i++) {
-        double rx, ry, px, py;
-        rs.get(i, rx, ry, px, py);
-        const double ra[9] = {rx, ry, 1.0, 0.0, 0.0, 0.0, -px * rx, -px * ry, -px};
-        const double rb[9] = {0.0, 0.0, 0.0, rx, ry, 1.0, -py * rx, -py * ry, -py};
+            for (int c = 0; c < 8; c++) A[a][c] = 0.0;
+        }
+        for (int i = 0; i < n; i++) {
+            double rx, ry, px, py;
+            rs.get(i, rx, ry, px, py);
+            const double ra[8] = {rx, ry, 1.0, 0.0, 0.0, 0.0, -px * rx, -px * ry};
+            const double rb[8] = {0.0, 0.0, 0.0, rx, ry, 1.0, -py * rx, -py * ry};
 #pragma unroll
-        for (int a = 0; a < 9; a++)
+            for (int a = 0; a < 8; a++) {
+                rhs[a] += ra[a] * px + rb[a] * py;
 #pragma unroll
-            for (int b = a; b < 9; b++) Mu[a][b] += ra[a] * ra[b] + rb[a] * rb[b];
+                for (int c = a; c < 8; c++) A[a][c] += ra[a] * ra[c] + rb[a] * rb[c];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 8; a++)
+#pragma unroll
+            for (int c = 0; c < a; c++) A[a][c] = A[c][a];
+        if (cholesky_solve8(A, rhs, sol)) {
+#pragma unroll
+            for (int a = 0; a < 8; a++) f[a] = sol[a];
+        } else {
+            st |= EBSD_SOLVE_ILLCOND;
+        }
     }
-    const LMat<9> M{pool}, V{pool + 81 * kSolveThreads};
-#pragma unroll
-    for (int a = 0; a < 9; a++)
-#pragma unroll
-        for (int b = 0; b < 9; b++) M(a, b) = b >= a ? Mu[a][b] : Mu[b][a];
-    double ev[9];
-    jacobi_eigen_l<9>(M, ev, V);
-    int k = 0;
-#pragma unroll
-    for (int i = 1; i < 9; i++)
-        if (ev[i] < ev[k]) k = i;
-    double f[9];
-#pragma unroll
-    for (int i = 0; i < 9; i++) f[i] = V(i, k);
-    if (f[8] == 0.0) {
-        st |= EBSD_SOLVE_ILLCOND;
-        f[8] = 1.0;
-    }
-    const double s8 = f[8];
-    for (int i = 0; i < 9; i++) f[i] /= s8;
-    f[8] = 1.0;
 
     double JtJ[8][8], Jte[8];
     for (int it = 0; it < 100; it++) {
