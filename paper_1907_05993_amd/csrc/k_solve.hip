@@ -791,11 +791,13 @@ template <int NV>
 __device__ void fit_block_sum(double (&v)[NV], double* sh)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
     for (int k = 0; k < NV; k++) {
         const double w = wave_sum_d(v[k]);
         if (lane == 0) sh[wave * NV + k] = w;
     }
     __syncthreads();
+#pragma unroll
     for (int k = 0; k < NV; k++) v[k] = ((sh[k] + sh[NV + k]) + sh[2 * NV + k]) + sh[3 * NV + k];
     __syncthreads();
 }
@@ -839,6 +841,7 @@ k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys
     double npts;
     {
         double t[45];
+#pragma unroll
         for (int k = 0; k < 45; k++) t[k] = 0.0;
         for (int g = threadIdx.x; g < ng; g += kFitThreads) {
             double x, y;
@@ -849,8 +852,11 @@ k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys
             const double ra[8] = {rx, ry, 1.0, 0.0, 0.0, 0.0, -px * rx, -px * ry};
             const double rb[8] = {0.0, 0.0, 0.0, rx, ry, 1.0, -py * rx, -py * ry};
             int k = 0;
+#pragma unroll
             for (int a = 0; a < 8; a++)
+#pragma unroll
                 for (int c = a; c < 8; c++) t[k++] += ra[a] * ra[c] + rb[a] * rb[c];
+#pragma unroll
             for (int a = 0; a < 8; a++) t[36 + a] += ra[a] * px + rb[a] * py;
             t[44] += 1.0;
         }
@@ -872,6 +878,7 @@ k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys
     // Gauss-Newton on the 8 free entries (|step| < 1e-12 or 100 steps)
     for (int it = 0; it < 100; it++) {
         double t[44];
+#pragma unroll
         for (int k = 0; k < 44; k++) t[k] = 0.0;
         for (int g = threadIdx.x; g < ng; g += kFitThreads) {
             double x, y;
@@ -888,8 +895,11 @@ k_warm_fit(const float* __restrict__ field, int gh, int gw, double xs, double ys
             const double ju[8] = {r0 * id, r1 * id, id, 0.0, 0.0, 0.0, -u * r0 * id, -u * r1 * id};
             const double jv[8] = {0.0, 0.0, 0.0, r0 * id, r1 * id, id, -v * r0 * id, -v * r1 * id};
             int k = 0;
+#pragma unroll
             for (int a = 0; a < 8; a++)
+#pragma unroll
                 for (int c = a; c < 8; c++) t[k++] += ju[a] * ju[c] + jv[a] * jv[c];
+#pragma unroll
             for (int a = 0; a < 8; a++) t[36 + a] += ju[a] * ex + jv[a] * ey;
         }
         fit_block_sum<44>(t, sh);
