@@ -6,10 +6,12 @@
 //   R = F (F^T F)^(-1/2), composition F = F_inf R_finite (Eq. (12)) and the
 //   rotation vector theta m (axis-angle after Eq. (5)) with theta from atan2 so
 //   small angles keep their digits.
-// One thread per pair.  The dense algebra with data-dependent indices (the
-// Jacobi eigen-solvers of the 9 x 9 and 8 x 8 systems) works on matrices in
-// LDS, one column of words per thread, so that no array goes to scratch
-// memory; the small fixed-index algebra stays in registers.
+// One wavefront per pair for the registration's solves (the sums over the ROIs
+// on the lanes, see solve_F_wave); one thread per pair for the traction-free
+// solve, whose dense algebra with data-dependent indices (the Jacobi
+// eigen-solver, the 12 x 13 Lagrange-Newton system) works on matrices in LDS,
+// one column of words per thread, so that no array goes to scratch memory; the
+// small fixed-index algebra stays in registers.
 #include "ebsd_internal.h"
 #include "cnn_internal.h"
 
@@ -337,6 +339,227 @@ __device__ uint32_t solve_F(const RoiSet& rs, double* F, double* pool)
     return st;
 }
 
+// ---- Eq. (3) with one wavefront per pair -----------------------------------------
+//
+// The solve above with its sums over the ROIs spread over the lanes of one
+// wavefront (a workgroup of 64 threads per pair).  Lane t < 36 accumulates the
+// upper-triangle element (a, c) of the 8 x 8 normal matrix and lane 36 + a the
+// right-hand side's element a, each over the ROIs in order and with its products
+// grouped as in solve_F, so that every element, and hence F, the status and the
+// conditioning, is the same bit for bit.  The 8 x 8 Cholesky solves then run on
+// every lane alike (uniform values in registers), and each Jacobi rotation of the
+// conditioning check updates its row and column elements on lanes 0..7.  The
+// workgroup is one wavefront, so __syncthreads orders the lanes' LDS accesses
+// without coupling pairs; every loop bound and branch outside the per-lane
+// element work is uniform (computed alike from the same LDS values).
+constexpr int kWaveSolveMaxRoi = 256;  // the largest ROI count the entry points accept
+
+struct WaveSolveLds {
+    double roi[4][kWaveSolveMaxRoi];  // r0, r1, p0, p1 of each ROI (units of Z*)
+    double M[8][8];                   // normal matrix (symmetric)
+    double rhs[8];
+    double term[kWaveSolveMaxRoi];    // per-ROI terms of the mean angular error
+};
+
+// 0 -> x, 1 -> y, 2 -> 1
+__device__ inline double sel3(int k, double x, double y) { return k == 0 ? x : (k == 1 ? y : 1.0); }
+
+// Lane t's task: (a, c), a <= c, of the matrix for t < 36 (row-major upper
+// triangle), row a of the right-hand side for 36 <= t < 44; idle above.
+__device__ inline void wave_task(int t, int& a, int& c)
+{
+    if (t >= 36) {
+        a = t - 36;
+        c = -1;
+        return;
+    }
+    a = 0;
+    int rem = t;
+    while (rem >= 8 - a) {
+        rem -= 8 - a;
+        a++;
+    }
+    c = a + rem;
+}
+
+// Fill the ROI table (lanes over ROIs).
+__device__ void wave_rois(const RoiSet& rs, WaveSolveLds& L)
+{
+    for (int i = threadIdx.x; i < rs.n; i += 64) {
+        double r0, r1, p0, p1;
+        rs.get(i, r0, r1, p0, p1);
+        L.roi[0][i] = r0;
+        L.roi[1][i] = r1;
+        L.roi[2][i] = p0;
+        L.roi[3][i] = p1;
+    }
+    __syncthreads();
+}
+
+// Store lane results (matrix element or right-hand side element), then every
+// lane reads the whole system into registers.
+__device__ void wave_gather(double acc, int ta, int tc, WaveSolveLds& L, double (&A)[8][8], double (&r)[8])
+{
+    if (threadIdx.x < 36) {
+        L.M[ta][tc] = acc;
+        L.M[tc][ta] = acc;
+    } else if (threadIdx.x < 44) {
+        L.rhs[ta] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+        r[a] = L.rhs[a];
+#pragma unroll
+        for (int c = 0; c < 8; c++) A[a][c] = L.M[a][c];
+    }
+    __syncthreads();
+}
+
+// gn_terms on the lanes: the lane's element of J^T J (tc >= 0) or of J^T e (tc < 0).
+__device__ double gn_term_lane(const double (&f)[9], int n, const WaveSolveLds& L, int ta, int tc)
+{
+    double acc = 0.0;
+    for (int i = 0; i < n; i++) {
+        const double r0 = L.roi[0][i], r1 = L.roi[1][i], pxi = L.roi[2][i], pyi = L.roi[3][i];
+        const double n1 = f[0] * r0 + f[1] * r1 + f[2];
+        const double n2 = f[3] * r0 + f[4] * r1 + f[5];
+        const double d = f[6] * r0 + f[7] * r1 + f[8];
+        const double id = 1.0 / d;
+        const double u = n1 * id, v = n2 * id;
+        const double ex = u - pxi, ey = v - pyi;
+        // d(u)/d theta_k and d(v)/d theta_k as in gn_terms
+        auto ju = [&](int k) {
+            return k < 3 ? sel3(k, r0, r1) * id : (k < 6 ? 0.0 : (-u * sel3(k - 6, r0, r1)) * id);
+        };
+        auto jv = [&](int k) {
+            return k < 3 ? 0.0 : (k < 6 ? sel3(k - 3, r0, r1) * id : (-v * sel3(k - 6, r0, r1)) * id);
+        };
+        const double ua = ju(ta), va = jv(ta);
+        const double ub = tc < 0 ? ex : ju(tc), vb = tc < 0 ? ey : jv(tc);
+        acc += ua * ub + va * vb;
+    }
+    return acc;
+}
+
+// Eigenvalues of the symmetric 8 x 8 matrix in L.M (destroyed): jacobi_eigen_l's
+// rotations and convergence test in the same order, the element updates of a
+// rotation on lanes 0..7.
+__device__ void wave_jacobi8(WaveSolveLds& L, double (&ev)[8])
+{
+    const int k = threadIdx.x;
+    for (int sweep = 0; sweep < 60; sweep++) {
+        double off = 0.0, diag = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            diag += L.M[i][i] * L.M[i][i];
+#pragma unroll
+            for (int j = i + 1; j < 8; j++) off += 2.0 * L.M[i][j] * L.M[i][j];
+        }
+        if (off == 0.0 || off <= 1e-30 * (off + diag)) break;
+        for (int p = 0; p < 7; p++)
+            for (int q = p + 1; q < 8; q++) {
+                const double apq = L.M[p][q];
+                if (apq == 0.0) continue;
+                const double tau = (L.M[q][q] - L.M[p][p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = rsqrt(1.0 + t * t), s = t * c;
+                __syncthreads();  // every lane has read the rotation's inputs
+                if (k < 8) {
+                    const double lp = L.M[k][p], lq = L.M[k][q];
+                    L.M[k][p] = c * lp - s * lq;
+                    L.M[k][q] = s * lp + c * lq;
+                }
+                __syncthreads();
+                if (k < 8) {
+                    const double lp = L.M[p][k], lq = L.M[q][k];
+                    L.M[p][k] = c * lp - s * lq;
+                    L.M[q][k] = s * lp + c * lq;
+                }
+                __syncthreads();
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++) ev[i] = L.M[i][i];
+    __syncthreads();
+}
+
+// solve_F on one wavefront (see above); every lane returns the same F and status.
+__device__ uint32_t solve_F_wave(const RoiSet& rs, double* F, WaveSolveLds& L)
+{
+    const int n = rs.n;
+    uint32_t st = 0;
+    int ta, tc;
+    wave_task(threadIdx.x < 44 ? threadIdx.x : 0, ta, tc);
+    wave_rois(rs, L);
+    // linear start (see solve_F)
+    double f[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    {
+        double acc = 0.0;
+        for (int i = 0; i < n; i++) {
+            const double rx = L.roi[0][i], ry = L.roi[1][i], px = L.roi[2][i], py = L.roi[3][i];
+            auto ra = [&](int k) { return k < 3 ? sel3(k, rx, ry) : (k < 6 ? 0.0 : -px * sel3(k - 6, rx, ry)); };
+            auto rb = [&](int k) { return k < 3 ? 0.0 : (k < 6 ? sel3(k - 3, rx, ry) : -py * sel3(k - 6, rx, ry)); };
+            const double ua = ra(ta), va = rb(ta);
+            const double ub = tc < 0 ? px : ra(tc), vb = tc < 0 ? py : rb(tc);
+            acc += ua * ub + va * vb;
+        }
+        double A[8][8], rhs[8], sol[8];
+        wave_gather(acc, ta, tc, L, A, rhs);
+        if (cholesky_solve8(A, rhs, sol)) {
+#pragma unroll
+            for (int a = 0; a < 8; a++) f[a] = sol[a];
+        } else {
+            st |= EBSD_SOLVE_ILLCOND;
+        }
+    }
+    double JtJ[8][8], Jte[8];
+    for (int it = 0; it < 100; it++) {
+        wave_gather(gn_term_lane(f, n, L, ta, tc), ta, tc, L, JtJ, Jte);
+        double rhs[8], dlt[8];
+        for (int a = 0; a < 8; a++) rhs[a] = -Jte[a];
+        if (!cholesky_solve8(JtJ, rhs, dlt)) {
+            st |= EBSD_SOLVE_ILLCOND;
+            break;
+        }
+        double nrm = 0.0;
+        for (int a = 0; a < 8; a++) {
+            f[a] += dlt[a];
+            nrm += dlt[a] * dlt[a];
+        }
+        if (!isfinite(nrm)) {
+            st |= EBSD_SOLVE_ILLCOND;
+            break;
+        }
+        if (sqrt(nrm) < 1e-14) break;
+    }
+    {
+        const double acc = gn_term_lane(f, n, L, ta, tc);
+        if (threadIdx.x < 36) {
+            L.M[ta][tc] = acc;
+            L.M[tc][ta] = acc;
+        }
+        __syncthreads();
+    }
+    double e8[8];
+    wave_jacobi8(L, e8);  // eigenvalues only: the conditioning
+    double lo = e8[0], hi = e8[0];
+    for (int a = 1; a < 8; a++) {
+        lo = fmin(lo, e8[a]);
+        hi = fmax(hi, e8[a]);
+    }
+    if (!(lo > 0.0) || hi > 1e12 * lo) st |= EBSD_SOLVE_ILLCOND;
+    const double d = det3(f);
+    if (d > 0.0) {
+        const double s = cbrt(d);
+        for (int i = 0; i < 9; i++) f[i] /= s;
+    } else {
+        st |= EBSD_SOLVE_ILLCOND;
+    }
+    for (int i = 0; i < 9; i++) F[i] = f[i];
+    return st;
+}
+
 // R = F (F^T F)^(-1/2): the rotation of the polar decomposition.
 __device__ void polar_rot(const double* F, double* R)
 {
@@ -377,11 +600,11 @@ __device__ void rotation_vector(const double* R, double* rv)
 // compares remapping methods by; its formula is not given, this reading is
 // used): the mean over the ROIs of the angle between F r_i and r_i + q_i,
 // atan2(|a x b|, a . b).  Both vectors are in units of Z*, which leaves the
-// angles unchanged.
-__device__ double mean_angular_error(const RoiSet& rs, const double* F)
+// angles unchanged.  The angles on the lanes of the pair's wavefront, their sum
+// in ROI order.
+__device__ double mean_angular_error_wave(const RoiSet& rs, const double* F, WaveSolveLds& L)
 {
-    double sum = 0.0;
-    for (int i = 0; i < rs.n; i++) {
+    for (int i = threadIdx.x; i < rs.n; i += 64) {
         double r0, r1, p0, p1;
         rs.get(i, r0, r1, p0, p1);
         const double a0 = F[0] * r0 + F[1] * r1 + F[2];
@@ -389,8 +612,12 @@ __device__ double mean_angular_error(const RoiSet& rs, const double* F)
         const double a2 = F[6] * r0 + F[7] * r1 + F[8];
         // b = (p0, p1, 1)
         const double c0 = a1 - a2 * p1, c1 = a2 * p0 - a0, c2 = a0 * p1 - a1 * p0;
-        sum += atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), a0 * p0 + a1 * p1 + a2);
+        L.term[i] = atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), a0 * p0 + a1 * p1 + a2);
     }
+    __syncthreads();
+    double sum = 0.0;
+    for (int i = 0; i < rs.n; i++) sum += L.term[i];
+    __syncthreads();
     return rs.n > 0 ? sum / rs.n : 0.0;
 }
 
@@ -408,11 +635,12 @@ __device__ RoiSet bucket_rois(const Bucket* bk, const float* q)
     return rs;
 }
 
-__global__ void __launch_bounds__(kSolveThreads) k_solve_first(const Bucket* __restrict__ bk, float tol)
+// One wavefront per pair (workgroup b).
+__global__ void __launch_bounds__(64) k_solve_first(const Bucket* __restrict__ bk, float tol)
 {
-    __shared__ double pool[kSolvePool * kSolveThreads];
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= bk->nb) return;
+    __shared__ WaveSolveLds L;
+    const int b = blockIdx.x;
+    if (b >= bk->nb) return;  // uniform
     uint32_t st = bk->test_stat[b].flags | bk->ref_stat[bk->ref_slot[b]].flags;
     if (bk->warm_flag) st |= bk->warm_flag[b];
     if (tol > 0.0f) {
@@ -420,12 +648,19 @@ __global__ void __launch_bounds__(kSolveThreads) k_solve_first(const Bucket* __r
         if ((bk->state[b].convmask & all) == all) st |= EBSD_CONVERGED;
         else st |= EBSD_HIT_CAP;
     }
-    double* F1 = bk->F1 + 9 * (int64_t)b;
     const RoiSet rs = bucket_rois(bk, bk->q1 + 2 * (int64_t)b * bk->n_roi);
-    st |= solve_F(rs, F1, pool + threadIdx.x);
-    bk->mae1[b] = mean_angular_error(rs, F1);
-    polar_rot(F1, bk->Rfin + 9 * (int64_t)b);
-    bk->status[b] = st;
+    double F1[9], R[9];
+    st |= solve_F_wave(rs, F1, L);
+    const double mae = mean_angular_error_wave(rs, F1, L);
+    polar_rot(F1, R);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 9; i++) {
+            bk->F1[9 * (int64_t)b + i] = F1[i];
+            bk->Rfin[9 * (int64_t)b + i] = R[i];
+        }
+        bk->mae1[b] = mae;
+        bk->status[b] = st;
+    }
 }
 
 // Status for the second-pass-only entry: input flags only.
@@ -437,23 +672,25 @@ __global__ void k_status_inputs(const Bucket* __restrict__ bk)
 }
 
 // pass 0 composes with R_finite (Eq. (12)); pass k > 0 with the F the
-// previous pass left in F (read before F is overwritten).
-__global__ void __launch_bounds__(kSolveThreads)
-    k_solve_second(const Bucket* __restrict__ bk, int second_pass, int pass)
+// previous pass left in F (read before F is overwritten).  One wavefront per
+// pair (workgroup b); lane 0 writes the results.
+__global__ void __launch_bounds__(64) k_solve_second(const Bucket* __restrict__ bk, int second_pass, int pass)
 {
-    __shared__ double pool[kSolvePool * kSolveThreads];
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= bk->nb) return;
+    __shared__ WaveSolveLds L;
+    const int b = blockIdx.x;
+    if (b >= bk->nb) return;  // uniform
     double Rf[9];
     const double* Rsrc = (pass == 0 ? bk->Rfin : bk->F) + 9 * (int64_t)b;
     for (int i = 0; i < 9; i++) Rf[i] = Rsrc[i];
-    double* F = bk->F + 9 * (int64_t)b;
+    double F[9];
     uint32_t st = bk->status[b];
+    double mae;
+    __syncthreads();  // every lane has read F before lane 0 overwrites it
     if (second_pass) {
         double Fi[9];
         const RoiSet rs = bucket_rois(bk, bk->q2 + 2 * (int64_t)b * bk->n_roi);
-        st |= solve_F(rs, Fi, pool + threadIdx.x);
-        bk->mae[b] = mean_angular_error(rs, Fi);
+        st |= solve_F_wave(rs, Fi, L);
+        mae = mean_angular_error_wave(rs, Fi, L);
         double Ft[9];
         for (int i = 0; i < 3; i++)
             for (int j = 0; j < 3; j++)
@@ -467,22 +704,31 @@ __global__ void __launch_bounds__(kSolveThreads)
     } else {
         const double* F1 = bk->F1 + 9 * (int64_t)b;
         for (int i = 0; i < 9; i++) F[i] = F1[i];
-        bk->mae[b] = bk->mae1[b];
+        mae = bk->mae1[b];
     }
-    double* R = bk->R + 9 * (int64_t)b;
+    double R[9], rv[3];
     polar_rot(F, R);
-    rotation_vector(R, bk->rotvec + 3 * (int64_t)b);
-    bk->status[b] = st;
+    rotation_vector(R, rv);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 9; i++) {
+            bk->F[9 * (int64_t)b + i] = F[i];
+            bk->R[9 * (int64_t)b + i] = R[i];
+        }
+        for (int i = 0; i < 3; i++) bk->rotvec[3 * (int64_t)b + i] = rv[i];
+        bk->mae[b] = mae;
+        bk->status[b] = st;
+    }
 }
 
-__global__ void __launch_bounds__(kSolveThreads) k_stage_solve(const float* __restrict__ q, int n, int n_roi,
+// One wavefront per shift set (workgroup b).
+__global__ void __launch_bounds__(64) k_stage_solve(const float* __restrict__ q, int n, int n_roi,
                               const double* __restrict__ cx, const double* __restrict__ cy,
                               double xs, double ys, double zs, double* __restrict__ F,
                               double* __restrict__ R, uint32_t* __restrict__ status)
 {
-    __shared__ double pool[kSolvePool * kSolveThreads];
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n) return;
+    __shared__ WaveSolveLds L;
+    const int b = blockIdx.x;
+    if (b >= n) return;  // uniform
     RoiSet rs;
     rs.q = q + 2 * (int64_t)b * n_roi;
     rs.cx = cx;
@@ -492,9 +738,16 @@ __global__ void __launch_bounds__(kSolveThreads) k_stage_solve(const float* __re
     rs.xs = xs;
     rs.ys = ys;
     rs.iz = 1.0 / zs;
-    uint32_t st = solve_F(rs, F + 9 * (int64_t)b, pool + threadIdx.x);
-    if (R) polar_rot(F + 9 * (int64_t)b, R + 9 * (int64_t)b);
-    if (status) status[b] = st;
+    double Fb[9], Rb[9];
+    const uint32_t st = solve_F_wave(rs, Fb, L);
+    polar_rot(Fb, Rb);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 9; i++) {
+            F[9 * (int64_t)b + i] = Fb[i];
+            if (R) R[9 * (int64_t)b + i] = Rb[i];
+        }
+        if (status) status[b] = st;
+    }
 }
 
 // ---- traction-free constraint, strain and stress ----------------------------------
@@ -1030,8 +1283,7 @@ hipError_t launch_scatter_warm(const Bucket* d_bk, const Bucket& hb, hipStream_t
 
 hipError_t launch_solve_first(const Bucket* d_bk, const Bucket& hb, float tol, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_solve_first, dim3((hb.nb + kSolveThreads - 1) / kSolveThreads), dim3(kSolveThreads), 0, s,
-                       d_bk, tol);
+    hipLaunchKernelGGL(k_solve_first, dim3(hb.nb), dim3(64), 0, s, d_bk, tol);
     return hipGetLastError();
 }
 
@@ -1044,8 +1296,7 @@ hipError_t launch_status_inputs(const Bucket* d_bk, const Bucket& hb, hipStream_
 hipError_t launch_solve_second(const Bucket* d_bk, const Bucket& hb, int second_pass, int pass,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_solve_second, dim3((hb.nb + kSolveThreads - 1) / kSolveThreads), dim3(kSolveThreads), 0,
-                       s, d_bk, second_pass, pass);
+    hipLaunchKernelGGL(k_solve_second, dim3(hb.nb), dim3(64), 0, s, d_bk, second_pass, pass);
     return hipGetLastError();
 }
 
@@ -1053,9 +1304,8 @@ hipError_t launch_stage_solve(const float* q, int n, int n_roi, const double* cx
                               double xs, double ys, double zs, double* F, double* R,
                               uint32_t* status, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stage_solve, dim3((n + kSolveThreads - 1) / kSolveThreads), dim3(kSolveThreads), 0, s, q,
-                       n, n_roi, cx, cy, xs,
-                       ys, zs, F, R, status);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stage_solve, dim3(n), dim3(64), 0, s, q, n, n_roi, cx, cy, xs, ys, zs, F, R, status);
     return hipGetLastError();
 }
 
