@@ -185,6 +185,44 @@ def test_stage_solve(E, orc):
         assert st[k].item() == sto
 
 
+@pytest.mark.parametrize("n_roi,roi,size", [(5, 64, 256), (101, 32, 256), (256, 32, 512)])
+def test_stage_solve_roi_counts(E, orc, n_roi, roi, size):
+    """The solve (one wavefront per shift set, sums over the ROIs on its lanes)
+    at the fewest ROIs the entry accepts, more ROIs than lanes, and the most it
+    accepts; plus an exact identity (zero shifts) and a shift set the fit
+    cannot explain (one ROI moved by 1e6 px), against the oracle's F and status."""
+    from scipy.spatial.transform import Rotation
+    p = orc.make_params(n_roi=n_roi, roi_size=roi)
+    cx, cy, _, _, bad = orc.roi_layout(size, size, p)
+    assert not bad
+    pcs = (0.5 * size - 0.5, 0.5 * size - 0.5, 0.7 * size)
+    qs = []
+    for k in range(6):
+        eps = rng(140 + k).uniform(-2e-3, 2e-3, size=(3, 3))
+        eps = 0.5 * (eps + eps.T)
+        F = (np.eye(3) + eps) @ Rotation.from_rotvec(rng(150 + k).normal(scale=0.08, size=3)).as_matrix()
+        r = np.stack([cx - pcs[0], cy - pcs[1], np.full_like(cx, pcs[2])])
+        v = F @ r
+        q = np.stack([pcs[0] + pcs[2] * v[0] / v[2] - cx, pcs[1] + pcs[2] * v[1] / v[2] - cy], 1)
+        qs.append((q + rng(160 + k).normal(scale=0.05, size=q.shape)).astype(np.float32))
+    qs.append(np.zeros((n_roi, 2), np.float32))
+    far = qs[0].copy()
+    far[0, 0] = 1e6
+    qs.append(far)
+    qs = np.stack(qs)
+    F, R, st = E.stage_solve(cuda(qs), cx, cy, pcs)
+    F, R, st = F.cpu().numpy(), R.cpu().numpy(), st.cpu().numpy()
+    for k in range(7):
+        Fo, sto = orc.solve_F(qs[k].astype(np.float64), cx, cy, pcs)
+        assert st[k].item() == sto == 0, k
+        np.testing.assert_allclose(F[k], Fo, atol=1e-11)
+        np.testing.assert_allclose(R[k], orc.polar(Fo), atol=1e-11)
+    np.testing.assert_allclose(F[6], np.eye(3), atol=1e-13)
+    # the 1e6 px outlier: both sides flag the fit (the values of F differ, both meaningless)
+    _, sto = orc.solve_F(qs[7].astype(np.float64), cx, cy, pcs)
+    assert sto == E.SOLVE_ILLCOND and st[7].item() & E.SOLVE_ILLCOND
+
+
 def test_teacher_forced_full_depth(E, orc):
     """150 GPU iterations at 256^2 (level 0 of a real 10-degree pair, field
     started from the oracle's prolonged level-1 field); every 15th step the
