@@ -218,6 +218,41 @@ int ebsd_register_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
 int ebsd_register_batch_init(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
                              const float* u_init, const ebsd_outputs* out, void* stream);
 
+/* Pipelined registration (throughput of a stream of batches).  A pipeline
+ * owns `depth` (1..8) registration handles created with the same parameters,
+ * each with its own stream, workspace, captured graphs and host thread.
+ * Batches submitted in turn go to the handles round-robin.  While the
+ * pipeline fills, batch k + 1 (k + 1 < depth) is issued once batch k has begun
+ * its finest demons level (its stream waits for an event recorded there); from
+ * then on each handle runs its batches back to back, so the streams stay offset
+ * and one batch's network forward, coarse levels and second pass overlap
+ * another's finest level instead of the same phases running in lockstep.  Each
+ * batch is an ebsd_register_batch call on its handle: outputs are identical
+ * bit for bit.
+ * The pipeline's memory is depth times one handle's.
+ *
+ * ebsd_pipeline_create: EBSD_EINVAL unless 1 <= depth <= 8 (and as
+ * ebsd_create).  ebsd_pipeline_handle: the handle of slot 0 <= slot < depth,
+ * owned by the pipeline, for configuration (ebsd_load_model, ebsd_autotune,
+ * ebsd_set_graphs, ...) while no batch is pending; do not destroy it or call
+ * its registration functions directly.  ebsd_pipeline_submit: validates as
+ * ebsd_register_batch, copies `pairs` and `*out` (and the host field_offset
+ * array) and returns without waiting; the batch starts after the work already
+ * on `stream`; the caller keeps the patterns and outputs alive and unchanged
+ * until ebsd_pipeline_wait returns.  Errors of a submitted batch are reported
+ * by the next ebsd_pipeline_wait.  ebsd_pipeline_wait: blocks until every
+ * submitted batch has been issued, then makes `stream` wait for their
+ * completion; returns the first error since the previous wait.
+ * ebsd_pipeline_destroy: waits for the submitted batches (host side), then
+ * frees everything; NULL is a no-op. */
+typedef struct ebsd_pipeline ebsd_pipeline;
+int ebsd_pipeline_create(const ebsd_params* p, int device, int32_t depth, ebsd_pipeline** out);
+int ebsd_pipeline_handle(ebsd_pipeline* pl, int32_t slot, ebsd_handle** h);
+int ebsd_pipeline_submit(ebsd_pipeline* pl, const ebsd_pair* pairs, int32_t n, const ebsd_outputs* out,
+                         void* stream);
+int ebsd_pipeline_wait(ebsd_pipeline* pl, void* stream);
+int ebsd_pipeline_destroy(ebsd_pipeline* pl);
+
 /* Second pass only (section 2, Eq. (12)): remap each reference by the
  * caller's R_finite (device, [n][9] fp64, row-major), ROI XCF against the
  * test, F_inf by Eq. (3), F = F_inf R_finite, det F = 1, R, rotation vector.

@@ -25,6 +25,7 @@ inline hipError_t ensure_dynamic_lds(const void* fn, int bytes, std::atomic<uint
 }
 
 constexpr int kMaxLevels = 8;
+constexpr int kMaxPipelineDepth = 8;  // handles (streams) of one ebsd_pipeline
 constexpr int kMaxRadius = 4;     // Gaussian half-width supported by the demons kernel
 constexpr int kDemonsTX = 64;     // demons output tile: 64 columns (one wavefront per row)
 constexpr int kDemonsTY = 16;     // ... x 16 rows

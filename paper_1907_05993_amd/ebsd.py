@@ -112,7 +112,9 @@ EXPORTED = ["ebsd_version", "ebsd_params_default", "ebsd_strerror", "ebsd_create
             "ebsd_load_model", "ebsd_set_model", "ebsd_stage_conv3x3", "ebsd_stage_conv3x3_dgrad",
             "ebsd_stage_conv3x3_wgrad", "ebsd_gen_pairs", "ebsd_get_fused_height", "ebsd_set_fused_height",
             "ebsd_set_gating", "ebsd_get_launch_counts", "ebsd_tilt_rotation", "ebsd_cnn_get_optimizer",
-            "ebsd_cnn_set_optimizer", "ebsd_stage_bandpass_static", "ebsd_cnn_set_fusion"]
+            "ebsd_cnn_set_optimizer", "ebsd_stage_bandpass_static", "ebsd_cnn_set_fusion",
+            "ebsd_pipeline_create", "ebsd_pipeline_handle", "ebsd_pipeline_submit", "ebsd_pipeline_wait",
+            "ebsd_pipeline_destroy"]
 
 
 def lib():
@@ -133,6 +135,11 @@ def lib():
         L.ebsd_get_params.argtypes = [vp, C.POINTER(CParams)]
         L.ebsd_roi_layout.argtypes = [C.POINTER(CParams), i32, i32, vp, vp, vp, vp]
         L.ebsd_register_batch.argtypes = [vp, C.POINTER(CPair), i32, C.POINTER(COutputs), vp]
+        L.ebsd_pipeline_create.argtypes = [C.POINTER(CParams), C.c_int, i32, C.POINTER(vp)]
+        L.ebsd_pipeline_handle.argtypes = [vp, i32, C.POINTER(vp)]
+        L.ebsd_pipeline_submit.argtypes = [vp, C.POINTER(CPair), i32, C.POINTER(COutputs), vp]
+        L.ebsd_pipeline_wait.argtypes = [vp, vp]
+        L.ebsd_pipeline_destroy.argtypes = [vp]
         L.ebsd_register_batch_init.argtypes = [vp, C.POINTER(CPair), i32, vp, C.POINTER(COutputs), vp]
         L.ebsd_second_pass_batch.argtypes = [vp, C.POINTER(CPair), i32, vp, C.POINTER(COutputs), vp]
         L.ebsd_autotune.argtypes = [vp, C.POINTER(CPair), i32, vp]
@@ -281,17 +288,22 @@ def roi_layout(params: Params, H, W):
 class Registrar:
     """A library handle bound to one device with fixed parameters."""
 
-    def __init__(self, params: Params | None = None, device: int = 0):
+    def __init__(self, params: Params | None = None, device: int = 0, _handle=None):
         self.params = params or Params()
         self._p = self.params.to_c()
         self.device = device
-        h = C.c_void_p()
-        _check(lib().ebsd_create(C.byref(self._p), device, C.byref(h)), "ebsd_create")
-        self._h = h
+        self._owned = _handle is None
+        if _handle is None:
+            h = C.c_void_p()
+            _check(lib().ebsd_create(C.byref(self._p), device, C.byref(h)), "ebsd_create")
+            self._h = h
+        else:
+            self._h = _handle
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().ebsd_destroy(self._h)
+            if self._owned:
+                lib().ebsd_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -510,6 +522,79 @@ class Registrar:
         for k in ("F_first", "q1", "iters", "mae_first"):
             out.pop(k)
         return out
+
+
+class Pipeline:
+    """Pipelined registration (ebsd_pipeline_*): batches submitted in turn run on
+    `depth` library handles with their own streams and host threads; batch k + 1
+    is issued once batch k has begun its finest demons level, so that its network
+    forward and coarse levels overlap that level.  Outputs equal
+    Registrar.register's bit for bit.  `slots` are Registrar views of the handles
+    for configuration (load_model, autotune, set_graphs, ...) while nothing is
+    pending."""
+
+    def __init__(self, params: Params | None = None, depth: int = 2, device: int = 0):
+        self.params = params or Params()
+        self.device = device
+        self.depth = depth
+        h = C.c_void_p()
+        _check(lib().ebsd_pipeline_create(C.byref(self.params.to_c()), device, depth, C.byref(h)),
+               "ebsd_pipeline_create")
+        self._pl = h
+        self.slots = []
+        for k in range(depth):
+            hk = C.c_void_p()
+            _check(lib().ebsd_pipeline_handle(self._pl, k, C.byref(hk)), "ebsd_pipeline_handle")
+            self.slots.append(Registrar(self.params, device, _handle=hk))
+        self._pending = []
+
+    def load_model(self, path):
+        for r in self.slots:
+            r.load_model(path)
+
+    def set_graphs(self, on=True):
+        for r in self.slots:
+            r.set_graphs(on)
+
+    def set_resident(self, on=True):
+        for r in self.slots:
+            r.set_resident(on)
+
+    def autotune(self, refs, tests, ref_ids=None):
+        return [r.autotune(refs, tests, ref_ids) for r in self.slots]
+
+    def submit(self, refs, tests, ref_ids=None, want_field=True):
+        """Queue one batch (as Registrar.register, on torch's current stream);
+        returns its output dict, valid after wait()."""
+        r0 = self.slots[0]
+        arr, n, shapes, keep = r0._pairs(refs, tests, ref_ids)
+        dev = keep[0].device if keep else torch.device("cuda", self.device)
+        want_field = want_field and self.params.first_pass == 0
+        out, co = r0._outputs(shapes, want_field, dev)
+        _check(lib().ebsd_pipeline_submit(self._pl, arr, n, C.byref(co), _stream()), "ebsd_pipeline_submit")
+        out["_keep"] = (keep, co, arr)
+        self._pending.append(out)
+        return r0._unflatten_field(out, shapes)
+
+    def wait(self):
+        """Make torch's current stream wait for every submitted batch."""
+        rc = lib().ebsd_pipeline_wait(self._pl, _stream())
+        self._pending.clear()
+        _check(rc, "ebsd_pipeline_wait")
+
+    def close(self):
+        if getattr(self, "_pl", None):
+            for r in self.slots:
+                r._h = None
+            lib().ebsd_pipeline_destroy(self._pl)
+            self._pl = None
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Cnn:

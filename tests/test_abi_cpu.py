@@ -169,6 +169,24 @@ def test_network_entry_points_validate_without_a_gpu(E):
     assert L.ebsd_cnn_set_fusion(None, 1) == -1
 
 
+def test_pipeline_entry_points_validate_without_a_gpu(E):
+    import torch
+    L = E.lib()
+    h = C.c_void_p()
+    p = E.Params().to_c()
+    assert L.ebsd_pipeline_create(C.byref(p), 0, 0, C.byref(h)) == -1
+    assert L.ebsd_pipeline_create(C.byref(p), 0, 9, C.byref(h)) == -1
+    assert L.ebsd_pipeline_create(C.byref(p), 0, 2, None) == -1
+    bad = E.Params(sigma_px=-1.0).to_c()
+    assert L.ebsd_pipeline_create(C.byref(bad), 0, 2, C.byref(h)) == -1
+    if not torch.cuda.is_available():
+        assert L.ebsd_pipeline_create(C.byref(p), 0, 2, C.byref(h)) == -5
+    assert L.ebsd_pipeline_handle(None, 0, C.byref(h)) == -1
+    assert L.ebsd_pipeline_submit(None, None, 0, None, None) == -1
+    assert L.ebsd_pipeline_wait(None, None) == -1
+    assert L.ebsd_pipeline_destroy(None) == 0
+
+
 def test_tilt_rotation_is_eq13_as_printed(E, orc):
     """ebsd_tilt_rotation (host) against the tests' own transcription of Eq. (13)."""
     import math

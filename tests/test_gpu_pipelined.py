@@ -1,0 +1,76 @@
+"""Pipelined registration (ebsd_pipeline_*): batches submitted in turn run on
+two or three handles with their own streams, each batch issued once the
+previous one has begun its finest demons level.  Every output of every batch
+equals a plain ebsd_register_batch call on the same batch bit for bit: the
+warm-started path on the benchmark's patterns (256 x 256, 10 degrees, trained
+network), and the plain path with a tolerance that stops pairs (gated level
+launches, counts and stop decisions included).  Needs an MI355X."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = "paper_1907_05993_amd/weights/warm_cnn_256.bin"
+KEYS = ("field", "F", "R", "rotvec", "R_finite", "F_first", "q1", "q2", "peak_height", "iters", "status",
+        "mae_first", "mae", "omega", "warm_field", "warm_misfit")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1907_05993_amd import ebsd
+    ebsd.lib()
+    return ebsd
+
+
+@pytest.fixture(scope="module")
+def batches(E):
+    from paper_1907_05993_amd import synth as S
+    specs = S.workload_specs("batch_256_10deg", n=3 * 192)
+    refs, tests, _ = E.gen_pairs(specs, labels=False)
+    return [(refs[k * 192:(k + 1) * 192].contiguous(), tests[k * 192:(k + 1) * 192].contiguous()) for k in range(3)]
+
+
+def host(out):
+    return {k: out[k].cpu().numpy() for k in KEYS if k in out}
+
+
+@pytest.mark.parametrize("depth,warm,tol", [(2, True, 1e-4), (3, False, 0.1)])
+def test_pipelined_batches_equal_single_calls(E, batches, depth, warm, tol):
+    p = E.Params(levels=3, iters=(40,) * 3, sigma_px=1.0, tol_px=tol, roi_size=64, n_roi=20,
+                 warm_start=2 if warm else 0, fallback_residual_px=1.0)
+    print(f"case: pipeline depth {depth}, warm={warm}, tol {tol}, 3 batches of 192", flush=True)
+    reg = E.Registrar(p)
+    if warm:
+        reg.load_model(WEIGHTS)
+    want = [host(reg.register(r, t)) for r, t in batches]
+    torch.cuda.synchronize()
+    reg.close()
+    pl = E.Pipeline(p, depth=depth)
+    if warm:
+        pl.load_model(WEIGHTS)
+    for rep in range(2):  # the second round replays the captured graphs
+        outs = [pl.submit(r, t) for r, t in batches]
+        pl.wait()
+        torch.cuda.synchronize()
+        for k, o in enumerate(outs):
+            got = host(o)
+            assert got.keys() == want[k].keys()
+            for key in got:
+                assert np.array_equal(got[key], want[k][key], equal_nan=True), (rep, k, key)
+    if tol > 0.01:
+        its = np.concatenate([w["iters"] for w in want])
+        print("pairs stopped before the cap per level:", (its < 40).sum(axis=0).tolist(), flush=True)
+        assert (its < 40).any()
+    pl.close()
+
+
+def test_pipeline_rejects_bad_batches_at_submission(E, batches):
+    pl = E.Pipeline(E.Params(levels=3, iters=(5,) * 3), depth=2)
+    r, t = batches[0]
+    with pytest.raises(E.EbsdError):
+        pl.submit(r[:, :3, :3].contiguous(), t[:, :3, :3].contiguous())  # coarsest level under 4 x 4
+    out = pl.submit(r[:4], t[:4])
+    pl.wait()
+    assert out["F"].shape == (4, 3, 3)
+    pl.close()
