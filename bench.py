@@ -239,12 +239,13 @@ def main():
 
     warm = timed(make(True, args.cap), "warm start", parity_idx=par_idx)
 
-    def timed_pipeline(depth, ref_out):
+    def timed_pipeline(depth, ref_out, warm_start=True):
         # the same registration on a stream of batches: `depth` handles with their own streams,
-        # batch k + 1 issued once batch k has begun its finest demons level (ebsd_pipeline)
-        p = make(True, args.cap).params
+        # the first batches staggered at the previous one's finest demons level (ebsd_pipeline)
+        p = make(warm_start, args.cap).params
         pl = ebsd.Pipeline(p, depth=depth, device=0)
-        pl.load_model(WEIGHTS)
+        if warm_start:
+            pl.load_model(WEIGHTS)
         pl.set_graphs(not args.no_graphs)
         pl.set_resident(not args.no_resident)
         pl.autotune(d_refs, d_tests)
@@ -261,7 +262,7 @@ def main():
         el = time.perf_counter() - ts
         last = outs[-1]
         same = all(torch.equal(last[k], ref_out[k]) for k in ("F", "iters", "status", "q2"))
-        log(f"[bench] warm start, {depth} batches in flight: {args.steps} steps in {el:.3f} s "
+        log(f"[bench] {'warm start' if warm_start else 'plain'}, {depth} batches in flight: {args.steps} steps in {el:.3f} s "
             f"(outputs equal to one call at a time: {same})")
         del outs, last
         pl.close()
@@ -271,6 +272,10 @@ def main():
     pipelined = timed_pipeline(args.streams, warm["out_ref"]) if args.streams > 1 else None
     warm.pop("out_ref", None)
     plain = None if args.skip_plain else timed(make(False, args.cap), "plain", parity_idx=par_idx)
+    plain_pipelined = (timed_pipeline(args.streams, plain["out_ref"], warm_start=False)
+                       if plain is not None and args.streams > 1 else None)
+    if plain is not None:
+        plain.pop("out_ref", None)
     short = timed(make(True, args.short_cap), f"warm start, cap {args.short_cap}") if args.short_cap > 0 else None
     # the library's default fallback threshold (0.5 full-res px of fit misfit)
     strict = None if args.skip_comparison else timed(make(True, args.cap, fallback=0.5),
@@ -457,6 +462,7 @@ def main():
         "warm": summary(warm),
         "plain": summary(plain) if plain is not None else None,
         "warm_pipelined": pipelined,
+        "plain_pipelined": plain_pipelined,
     }
     if short is not None:
         rec["warm_short_cap"] = dict(summary(short), cap=args.short_cap)

@@ -239,7 +239,9 @@ int ebsd_register_batch_init(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
  * ebsd_register_batch, copies `pairs` and `*out` (and the host field_offset
  * array) and returns without waiting; the batch starts after the work already
  * on `stream`; the caller keeps the patterns and outputs alive and unchanged
- * until ebsd_pipeline_wait returns.  Errors of a submitted batch are reported
+ * until `stream` has passed the point at which a later ebsd_pipeline_wait made
+ * it wait (work enqueued on `stream` after that call sees the results).
+ * Errors of a submitted batch are reported
  * by the next ebsd_pipeline_wait.  ebsd_pipeline_wait: blocks until every
  * submitted batch has been issued, then makes `stream` wait for their
  * completion; returns the first error since the previous wait.
