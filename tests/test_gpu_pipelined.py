@@ -74,3 +74,35 @@ def test_pipeline_rejects_bad_batches_at_submission(E, batches):
     pl.wait()
     assert out["F"].shape == (4, 3, 3)
     pl.close()
+
+
+def test_bench_pipeline_configuration_on_1024_pairs(E):
+    """The headline's configuration: two handles, each autotuned on the 1024-pair
+    batch (256 x 256, exactly 10 degrees), graph replay, warm start, 3 x 150
+    iterations at 1e-4 px; four batches in flight equal one call at a time."""
+    from paper_1907_05993_amd import synth as S
+    specs = S.workload_specs("batch_256_10deg", n=1024)
+    refs, tests, _ = E.gen_pairs(specs, labels=False)
+    p = E.Params(levels=3, iters=(150,) * 3, sigma_px=1.0, tol_px=1e-4, roi_size=64, n_roi=20, warm_start=2,
+                 fallback_residual_px=1.0)
+    print("case: pipeline depth 2, 1024 pairs, bench configuration", flush=True)
+    reg = E.Registrar(p)
+    reg.load_model(WEIGHTS)
+    reg.set_graphs(True)
+    reg.autotune(refs, tests)
+    want = host(reg.register(refs, tests))
+    torch.cuda.synchronize()
+    reg.close()
+    pl = E.Pipeline(p, depth=2)
+    pl.load_model(WEIGHTS)
+    pl.set_graphs(True)
+    tuned = pl.autotune(refs, tests)
+    print("strip heights per handle:", tuned, flush=True)
+    outs = [pl.submit(refs, tests) for _ in range(4)]
+    pl.wait()
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        got = host(o)
+        for key in got:
+            assert np.array_equal(got[key], want[key], equal_nan=True), (k, key)
+    pl.close()
