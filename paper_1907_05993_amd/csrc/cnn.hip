@@ -206,6 +206,7 @@ hipError_t conv_fwd(ebsd_cnn* c, int l, int n, int H, int W, const bf16_t* x, bf
     a.out2_cs = out2_cs;
     a.x2 = x2;
     a.c2 = c2;
+    a.lds_dma = c->fused ? 1 : 0;  // the per-layer setting (tests) keeps k_conv3x3 throughout
     return launch_conv3x3(a, s);
 }
 

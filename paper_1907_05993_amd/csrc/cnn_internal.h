@@ -32,6 +32,10 @@ struct ConvArgs {
     // (whose channels [0, c2) are then not read); c2 a multiple of 32, 0: not used
     const bf16_t* x2 = nullptr;
     int32_t c2 = 0;
+    // bf16-output modes: k_conv3x3_lds (input chunks moved into LDS by the buffer unit, 16-row
+    // tiles, the same sums in the same order, so the same outputs) for layers with at least 256
+    // input channels (and H % 16 == 0); 0: k_conv3x3 throughout
+    int32_t lds_dma = 0;
 };
 // Requirements: W % 32 == 0, H % 8 == 0, Cin % 32 == 0 or Cin == 8, Cout % 32 == 0.
 bool conv3x3_supported(int H, int W, int Cin, int Cout);

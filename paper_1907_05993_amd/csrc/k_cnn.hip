@@ -7,6 +7,7 @@
 // and column l % 32 of B with the same 8 k values; it receives the 16
 // accumulator values C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32], i = 0..15.
 #include "cnn_internal.h"
+#include "dev_util.h"
 
 #include "../../include/ebsd.h"
 
@@ -240,6 +241,187 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                     *reinterpret_cast<const float4*>(stg + px * RP + 4 * g);
             }
             __syncthreads();
+        }
+    }
+}
+
+// 16 bytes per lane from a buffer resource into LDS at dst + 16 * lane (dst
+// wave-uniform); offsets past the resource's end deliver zeros.  (Kept out of the
+// kernel templates: called from a template body directly, the builtin makes the
+// host pass drop the kernel's launch stub.)
+typedef __attribute__((address_space(3))) char lds_char;
+__device__ inline void lds_load16(__amdgpu_buffer_rsrc_t r, lds_char* dst, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)dst, 16, voff, soff, 0, 0);
+}
+
+// Inference variant of k_conv3x3<32, NT, UP> with the input chunks moved into
+// LDS by the buffer unit (buffer_load_dwordx4 ... lds): no staging registers
+// and no store phase, two LDS buffers so that chunk c + 1 loads while chunk c
+// is multiplied, one barrier per chunk.  16 x 32 output pixels per workgroup of
+// 8 waves (wave w on rows 2w, 2w + 1), one workgroup per CU (2 x 74 KiB of
+// buffers).  The K loop is k_conv3x3's for CK = 32 (the same products in the
+// same order), so the outputs are equal bit for bit.  A pixel's (or a weight
+// row's) four 16-byte quarters sit in LDS rotated by bits 1..2 of its index
+// (16-byte slot 4p + (g ^ ((p >> 1) & 3))), so that the 16-byte reads of eight
+// consecutive lanes fall in eight different bank groups; each lane's buffer
+// load fetches the quarter that lands in its slot (the buffer unit writes lane
+// l's 16 bytes at the instruction's LDS base + 16 l).  Halo pixels outside the
+// image get an offset past the end of the resource, which reads as zeros.
+constexpr int kLdsTH = 16;
+
+template <int NT, bool UP>
+__global__ void __launch_bounds__(512) k_conv3x3_lds(ConvArgs a)
+{
+    constexpr int HP = kLdsTH + 2, WP = kConvTW + 2;
+    constexpr int BN = 32 * NT;
+    constexpr int G = 4;              // 8-channel groups of a 32-channel chunk
+    constexpr int NA = HP * WP * G;   // 16-byte pieces of a chunk's halo
+    constexpr int NB = 9 * BN * G;    // and of its weights
+    constexpr int KA = (NA + 511) / 512, KB = (NB + 511) / 512;
+    constexpr int BUF = (NA + NB) * 16;  // bytes of one buffer
+    constexpr int RP = BN + 8;           // epilogue staging row pitch (bf16)
+    constexpr int ST = 8 * 64 * RP * 2;
+    constexpr int SMEM = 2 * BUF > ST ? 2 * BUF : ST;
+    __shared__ __attribute__((aligned(16))) char smem[SMEM];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    int b = blockIdx.x;
+    const int nbk = a.Cout / BN, txn = a.W / kConvTW, tyn = a.H / kLdsTH;
+    const int nb = b % nbk;
+    b /= nbk;
+    const int tx = b % txn;
+    b /= txn;
+    const int ty = b % tyn;
+    const int img = b / tyn;
+    const int x0 = tx * kConvTW, y0 = ty * kLdsTH, co0 = nb * BN;
+    const int Cin = a.Cin;
+    constexpr unsigned kOut = 0x80000000u;  // past the end of every resource: reads as zero
+    const __amdgpu_buffer_rsrc_t rx =
+        make_rsrc(a.x + (int64_t)img * a.H * a.W * Cin, 2u * (unsigned)a.H * (unsigned)a.W * (unsigned)Cin);
+    const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.w, 2u * (unsigned)a.Cout * 9u * (unsigned)Cin);
+    __amdgpu_buffer_rsrc_t rx2 = rx;
+    if constexpr (UP)
+        rx2 = make_rsrc(a.x2 + (int64_t)img * (a.H >> 1) * (a.W >> 1) * a.c2,
+                        2u * (unsigned)(a.H >> 1) * (unsigned)(a.W >> 1) * (unsigned)a.c2);
+
+    // this thread's byte offsets of its pieces, before the chunk's channel offset
+    unsigned oa[KA], oa2[KA], ob[KB];
+#pragma unroll
+    for (int k = 0; k < KA; k++) {
+        const int i = k * 512 + tid;
+        const int p = i >> 2, g = (i & 3) ^ ((p >> 1) & 3);
+        const int hy = p / WP, hx = p - WP * (p / WP);
+        const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+        const bool in = i < NA && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        oa[k] = in ? 2u * ((unsigned)(yy * a.W + xx) * (unsigned)Cin + 8u * g) : kOut;
+        oa2[k] = (UP && in) ? 2u * ((unsigned)((yy >> 1) * (a.W >> 1) + (xx >> 1)) * (unsigned)a.c2 + 8u * g)
+                            : kOut;
+    }
+#pragma unroll
+    for (int k = 0; k < KB; k++) {
+        const int i = k * 512 + tid;
+        const int r = i >> 2, g = (i & 3) ^ ((r >> 1) & 3);
+        const int t = r / BN, co = r - BN * (r / BN);
+        ob[k] = i < NB ? 2u * ((unsigned)((co0 + co) * 9 + t) * (unsigned)Cin + 8u * g) : kOut;
+    }
+    auto fetch = [&](int c0, int buf) {
+        lds_char* base = (lds_char*)smem + buf * BUF;
+        const bool up = UP && c0 < a.c2;  // uniform: the chunk lies in the upsampled source
+        const unsigned so = 2u * (unsigned)c0;
+#pragma unroll
+        for (int k = 0; k < KA; k++) {
+            if (k * 512 + wave * 64 >= NA) continue;  // uniform: nothing of this wave's block is needed
+            lds_char* dst = base + (k * 512 + wave * 64) * 16;
+            if (k * 512 + tid < NA) {
+                if (up) lds_load16(rx2, dst, oa2[k], so);
+                else lds_load16(rx, dst, oa[k], so);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; k++) {
+            if (k * 512 + wave * 64 >= NB) continue;
+            lds_char* dst = base + NA * 16 + (k * 512 + wave * 64) * 16;
+            if (k * 512 + tid < NB) lds_load16(rw, dst, ob[k], so);
+        }
+    };
+
+    f32x16 acc[2][NT];
+    for (int r = 0; r < 2; r++)
+        for (int j = 0; j < NT; j++)
+            for (int i = 0; i < 16; i++) acc[r][j][i] = 0.0f;
+
+    const int nck = Cin / 32;
+    fetch(0, 0);
+    for (int c = 0; c < nck; c++) {
+        __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of chunk c are in LDS
+        __syncthreads();                // everyone's, and chunk c - 1's buffer is free again
+        if (c + 1 < nck) fetch(32 * (c + 1), (c + 1) & 1);
+        const char* sA = smem + (c & 1) * BUF;
+        const char* sB = sA + NA * 16;
+        // k_conv3x3's K loop: step s takes (tap, group) pairs 2s (lanes 0..31) and 2s + 1 (32..63)
+        for (int s = 0; s < 9 * G / 2; s++) {
+            const int f = 2 * s + h;
+            const int t = f / G, g = f - G * (f / G);
+            const int ky = t / 3, kx = t - 3 * (t / 3);
+            bf16x8 av[2], bv[NT];
+            for (int r = 0; r < 2; r++) {
+                const int p = (2 * wave + r + ky) * WP + l32 + kx;
+                av[r] = *reinterpret_cast<const bf16x8*>(sA + (4 * p + (g ^ ((p >> 1) & 3))) * 16);
+            }
+            for (int j = 0; j < NT; j++) {
+                const int rr = t * BN + 32 * j + l32;
+                bv[j] = *reinterpret_cast<const bf16x8*>(sB + (4 * rr + (g ^ ((rr >> 1) & 3))) * 16);
+            }
+            for (int r = 0; r < 2; r++)
+                for (int j = 0; j < NT; j++) acc[r][j] = mfma16(av[r], bv[j], acc[r][j]);
+        }
+    }
+    __syncthreads();  // the buffers become the epilogue's staging area
+
+    // epilogue of k_conv3x3 (modes 0, 2, 3)
+    bf16_t* stg = reinterpret_cast<bf16_t*>(smem) + wave * 64 * RP;
+    for (int j = 0; j < NT; j++) {
+        const int col = 32 * j + l32;
+        const float bias = a.bias[co0 + col];
+        for (int r = 0; r < 2; r++)
+            for (int i = 0; i < 16; i++) {
+                const int px = 32 * r + 8 * (i >> 2) + 4 * h + (i & 3);
+                stg[px * RP + col] = f2bf(fmaxf(acc[r][j][i] + bias, 0.0f));
+            }
+    }
+    __syncthreads();
+    bf16_t* out = static_cast<bf16_t*>(a.out);
+    if (a.mode != 2) {
+        for (int v = lane; v < 64 * (BN / 8); v += 64) {
+            const int px = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
+            const int yy = y0 + 2 * wave + (px >> 5), xx = x0 + (px & 31);
+            const int64_t p = ((int64_t)img * a.H + yy) * a.W + xx;
+            *reinterpret_cast<uint4*>(out + p * a.out_cs + a.out_co + co0 + 8 * g) =
+                *reinterpret_cast<const uint4*>(stg + px * RP + 8 * g);
+        }
+    }
+    if (a.mode != 0) {
+        bf16_t* const pout = a.mode == 3 ? a.out2 : out;
+        const int pcs = a.mode == 3 ? a.out2_cs : a.out_cs, pco = a.mode == 3 ? 0 : a.out_co;
+        const int Hp = a.H / 2, Wp = a.W / 2;
+        for (int v = lane; v < 16 * (BN / 8); v += 64) {
+            const int q = v / (BN / 8), g = v - (BN / 8) * (v / (BN / 8));
+            const bf16_t* s0 = stg + (2 * q) * RP + 8 * g;
+            const bf16_t* s1 = s0 + RP;
+            const bf16_t* s2 = s0 + 32 * RP;
+            const bf16_t* s3 = s2 + RP;
+            u16x8 o;
+            for (int e = 0; e < 8; e++) {
+                uint16_t m = s0[e];
+                if (bf2f(s1[e]) > bf2f(m)) m = s1[e];
+                if (bf2f(s2[e]) > bf2f(m)) m = s2[e];
+                if (bf2f(s3[e]) > bf2f(m)) m = s3[e];
+                o[e] = m;
+            }
+            const int64_t p = ((int64_t)img * Hp + (y0 >> 1) + wave) * Wp + (x0 >> 1) + q;
+            *reinterpret_cast<u16x8*>(pout + p * pcs + pco + co0 + 8 * g) = o;
         }
     }
 }
@@ -1083,6 +1265,23 @@ hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t s)
         const int64_t tiles4 = (int64_t)a.n * (a.H / kR4TH) * (a.W / kConvTW) * (a.Cout / (32 * nt));
         if (nt == 2) hipLaunchKernelGGL((k_conv3x3_r4<2>), dim3((unsigned)tiles4), block, 0, s, a);
         else hipLaunchKernelGGL((k_conv3x3_r4<1>), dim3((unsigned)tiles4), block, 0, s, a);
+        return hipGetLastError();
+    }
+    // k_conv3x3_lds where the input has at least 8 chunks of 32 channels: measured per layer of
+    // the network (256 pairs), 256 -> 256 at 32 x 32 px 287 -> 261 us and the decoder's 384-channel
+    // layer 805 -> 699 us; with 128 input channels both kernels take the same time, with 64 the
+    // register-staged one is faster (350 against 376 us: two chunks leave the loads nothing to
+    // overlap)
+    if (a.lds_dma && a.mode != 1 && a.Cin % 32 == 0 && a.Cin >= 256 && a.H % kLdsTH == 0) {
+        const int64_t t16 = (int64_t)a.n * (a.H / kLdsTH) * (a.W / kConvTW) * (a.Cout / (32 * nt));
+        const dim3 g16((unsigned)t16), b512(512);
+        if (a.c2 != 0) {
+            if (nt == 2) hipLaunchKernelGGL((k_conv3x3_lds<2, true>), g16, b512, 0, s, a);
+            else hipLaunchKernelGGL((k_conv3x3_lds<1, true>), g16, b512, 0, s, a);
+        } else {
+            if (nt == 2) hipLaunchKernelGGL((k_conv3x3_lds<2, false>), g16, b512, 0, s, a);
+            else hipLaunchKernelGGL((k_conv3x3_lds<1, false>), g16, b512, 0, s, a);
+        }
         return hipGetLastError();
     }
     const int64_t tiles = (int64_t)a.n * (a.H / kConvTH) * (a.W / kConvTW) * (a.Cout / (32 * nt));
