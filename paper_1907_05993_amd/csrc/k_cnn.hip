@@ -262,9 +262,11 @@ __device__ inline void lds_load16(__amdgpu_buffer_rsrc_t r, lds_char* dst, unsig
 // 8 waves (wave w on rows 2w, 2w + 1), one workgroup per CU (2 x 74 KiB of
 // buffers).  The K loop is k_conv3x3's for CK = 32 (the same products in the
 // same order), so the outputs are equal bit for bit.  A pixel's (or a weight
-// row's) four 16-byte quarters sit in LDS rotated by bits 1..2 of its index
-// (16-byte slot 4p + (g ^ ((p >> 1) & 3))), so that the 16-byte reads of eight
-// consecutive lanes fall in eight different bank groups; each lane's buffer
+// row's) four 16-byte quarters sit in LDS rotated by bits 2..3 of its index
+// (16-byte slot 4p + (g ^ ((p >> 2) & 3))), so that the 16-byte reads of 16
+// consecutive lanes fall in 16 different 16-byte groups of the 256 bytes the
+// LDS serves per cycle (rotating by bits 1..2 left pixels p and p + 8 in the
+// same group: twice the bank-conflict cycles, measured); each lane's buffer
 // load fetches the quarter that lands in its slot (the buffer unit writes lane
 // l's 16 bytes at the instruction's LDS base + 16 l).  Halo pixels outside the
 // image get an offset past the end of the resource, which reads as zeros.
@@ -311,7 +313,7 @@ __global__ void __launch_bounds__(512) k_conv3x3_lds(ConvArgs a)
 #pragma unroll
     for (int k = 0; k < KA; k++) {
         const int i = k * 512 + tid;
-        const int p = i >> 2, g = (i & 3) ^ ((p >> 1) & 3);
+        const int p = i >> 2, g = (i & 3) ^ ((p >> 2) & 3);
         const int hy = p / WP, hx = p - WP * (p / WP);
         const int yy = y0 + hy - 1, xx = x0 + hx - 1;
         const bool in = i < NA && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
@@ -322,7 +324,7 @@ __global__ void __launch_bounds__(512) k_conv3x3_lds(ConvArgs a)
 #pragma unroll
     for (int k = 0; k < KB; k++) {
         const int i = k * 512 + tid;
-        const int r = i >> 2, g = (i & 3) ^ ((r >> 1) & 3);
+        const int r = i >> 2, g = (i & 3) ^ ((r >> 2) & 3);
         const int t = r / BN, co = r - BN * (r / BN);
         ob[k] = i < NB ? 2u * ((unsigned)((co0 + co) * 9 + t) * (unsigned)Cin + 8u * g) : kOut;
     }
@@ -368,11 +370,11 @@ __global__ void __launch_bounds__(512) k_conv3x3_lds(ConvArgs a)
             bf16x8 av[2], bv[NT];
             for (int r = 0; r < 2; r++) {
                 const int p = (2 * wave + r + ky) * WP + l32 + kx;
-                av[r] = *reinterpret_cast<const bf16x8*>(sA + (4 * p + (g ^ ((p >> 1) & 3))) * 16);
+                av[r] = *reinterpret_cast<const bf16x8*>(sA + (4 * p + (g ^ ((p >> 2) & 3))) * 16);
             }
             for (int j = 0; j < NT; j++) {
                 const int rr = t * BN + 32 * j + l32;
-                bv[j] = *reinterpret_cast<const bf16x8*>(sB + (4 * rr + (g ^ ((rr >> 1) & 3))) * 16);
+                bv[j] = *reinterpret_cast<const bf16x8*>(sB + (4 * rr + (g ^ ((rr >> 2) & 3))) * 16);
             }
             for (int r = 0; r < 2; r++)
                 for (int j = 0; j < NT; j++) acc[r][j] = mfma16(av[r], bv[j], acc[r][j]);
