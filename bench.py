@@ -431,7 +431,7 @@ def main():
         "roofline_network": {
             "bound": "mfma",
             "kernel": "network forward through ebsd_cnn_forward: z-scoring of both inputs, packing, the fused "
-                      "first block (k_conv_stem), k_conv3x3 / k_conv3x3_r4 bf16 MFMA implicit GEMMs with pooling "
+                      "first block (k_conv_stem), k_conv3x3 / k_conv3x3_r4 / k_conv3x3_lds bf16 MFMA implicit GEMMs with pooling "
                       "and upsampling folded in, head",
             "achieved": round(CNN_FLOP_PER_PAIR * n / (cnn_ms * 1e-3) / 1e12, 1),
             "peak": BF16_PEAK_TFLOPS,
