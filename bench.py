@@ -240,8 +240,8 @@ def main():
     warm = timed(make(True, args.cap), "warm start", parity_idx=par_idx)
 
     def timed_pipeline(depth, ref_out, warm_start=True):
-        # the same registration on a stream of batches: `depth` handles with their own streams,
-        # the first batches staggered at the previous one's finest demons level (ebsd_pipeline)
+        # the same registration on a stream of batches: `depth` handles with their own streams and
+        # host threads, `depth` batches in flight (ebsd_pipeline)
         p = make(warm_start, args.cap).params
         pl = ebsd.Pipeline(p, depth=depth, device=0)
         if warm_start:
@@ -406,9 +406,8 @@ def main():
             "launch": "direct" if args.no_graphs else "hipGraph replay",
             "batches_in_flight": args.streams if pipelined is not None else 1,
             "step": f"one batch of {n} pairs through the whole path; with several batches in flight "
-                    "(ebsd_pipeline) consecutive steps overlap, each batch starting once the previous one has "
-                    "begun its finest demons level; value = steps x pairs / the time from the first "
-                    "submission to the last batch's completion",
+                    "(ebsd_pipeline) consecutive steps overlap on separate handles and streams; value = steps "
+                    "x pairs / the time from the first submission to the last batch's completion",
         },
         "roofline": {
             "bound": "hbm",

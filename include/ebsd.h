@@ -221,14 +221,11 @@ int ebsd_register_batch_init(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
 /* Pipelined registration (throughput of a stream of batches).  A pipeline
  * owns `depth` (1..8) registration handles created with the same parameters,
  * each with its own stream, workspace, captured graphs and host thread.
- * Batches submitted in turn go to the handles round-robin.  While the
- * pipeline fills, batch k + 1 (k + 1 < depth) is issued once batch k has begun
- * its finest demons level (its stream waits for an event recorded there); from
- * then on each handle runs its batches back to back, so the streams stay offset
- * and one batch's network forward, coarse levels and second pass overlap
- * another's finest level instead of the same phases running in lockstep.  Each
- * batch is an ebsd_register_batch call on its handle: outputs are identical
- * bit for bit.
+ * Batches submitted in turn go to the handles round-robin and run back to back
+ * on each, so `depth` batches are in flight at once: one batch's network
+ * forward, coarse levels and second pass overlap another's finest demons
+ * level.  Each batch is an ebsd_register_batch call on its handle: outputs
+ * are identical bit for bit.
  * The pipeline's memory is depth times one handle's.
  *
  * ebsd_pipeline_create: EBSD_EINVAL unless 1 <= depth <= 8 (and as

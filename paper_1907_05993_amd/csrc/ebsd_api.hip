@@ -14,7 +14,6 @@
 #include <algorithm>
 #include <condition_variable>
 #include <deque>
-#include <functional>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -80,9 +79,6 @@ struct ebsd_handle {
     int32_t launches_planned[EBSD_MAX_LEVELS] = {};
     // warm-start network (created by ebsd_load_model / ebsd_set_model)
     ebsd_cnn* cnn = nullptr;
-    // set by a pipeline (ebsd_pipeline_*) around its calls: invoked with the call's
-    // stream when the finest demons level of a size bucket is about to be issued
-    std::function<void(hipStream_t)> on_finest_level;
 };
 
 namespace {
@@ -825,7 +821,6 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
             // per-iteration launches (measured: single pair 5.1 -> 3.6 ms; 1024 pairs at
             // 64 x 64 px 4.0 -> 4.5 ms, so large batches keep the row kernels)
             const bool res = h->resident && nb <= kResidentMaxPairs && demons_resident_ok(b.lh[l], b.lw[l]);
-            if (l == 0 && h->on_finest_level) h->on_finest_level(s);
             if (tm) EBSD_TRY(hipEventRecord(h->ev[2 + 2 * l], s));
             if (res) {
                 EBSD_TRY(launch_demons_resident(d_bk, b, l, h->taps, h->radius, p.tol_px, p.max_iters[l], s));
@@ -1424,12 +1419,10 @@ int ebsd_traction_free(const float* q, int32_t n, int32_t n_roi, const double* c
 // Batches submitted one after another run on `depth` registration handles, each
 // with its own stream, workspace, captured graphs and network, from one host
 // thread per handle (a call blocks its thread while a gated level waits for
-// its counts).  While the pipeline fills, batch k + 1 (k + 1 < depth) is issued
-// once batch k has reached its finest demons level, and its stream waits for an
-// event recorded there; from then on every handle runs its batches back to
-// back, so the streams stay offset from one another instead of running the same
-// phase (network, coarse levels, finest level) in lockstep.  Each batch is a
-// plain ebsd_register_batch call on its handle: results are the same bit for bit.
+// its counts), so `depth` batches are in flight at once.  Their phases drift
+// apart within a few batches, and one batch's network forward, coarse levels
+// and second pass then overlap another's finest level.  Each batch is a plain
+// ebsd_register_batch call on its handle: results are the same bit for bit.
 struct ebsd_pipeline {
     struct Job {
         std::vector<ebsd_pair> pairs;
@@ -1437,20 +1430,17 @@ struct ebsd_pipeline {
         std::vector<int64_t> offs;  // copy of out.field_offset (host array)
         bool has_offs = false;
         hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
-        uint64_t seq = 0;
     };
     int depth = 0;
     int device = 0;
     std::vector<ebsd_handle*> h;
     std::vector<hipStream_t> st;
-    std::vector<hipEvent_t> ev_stagger;  // per slot: the finest level of its last batch began
     std::vector<hipEvent_t> ev_done;     // per slot: its last batch is complete
     std::vector<std::deque<Job>> queue;  // per slot
     std::vector<std::thread> workers;
     std::mutex mu;
     std::condition_variable cv;
     uint64_t submitted = 0;  // batches submitted
-    uint64_t started = 0;    // 1 + the last batch that reached its finest level (or ended)
     uint64_t finished = 0;   // batches whose calls have returned
     int error = 0;
     bool stop = false;
@@ -1468,34 +1458,17 @@ void pipeline_worker(ebsd_pipeline* pl, int slot)
             if (pl->queue[slot].empty()) return;  // stop requested and nothing left
             job = std::move(pl->queue[slot].front());
             pl->queue[slot].pop_front();
-            // filling: batch seq - 1 must have reached its finest level (or ended)
-            if (job.seq < (uint64_t)pl->depth) pl->cv.wait(lk, [&] { return pl->started >= job.seq; });
         }
         DeviceGuard g(pl->device);
         int rc = g.ok ? EBSD_OK : EBSD_EDEVICE;
         hipStream_t s = pl->st[slot];
-        if (rc == EBSD_OK && job.seq > 0 && job.seq < (uint64_t)pl->depth &&
-            hipStreamWaitEvent(s, pl->ev_stagger[(job.seq - 1) % pl->depth], 0) != hipSuccess)
-            rc = EBSD_EDEVICE;
         if (rc == EBSD_OK && hipStreamWaitEvent(s, job.ready, 0) != hipSuccess) rc = EBSD_EDEVICE;
         (void)hipEventDestroy(job.ready);
-        bool signalled = false;
-        auto signal = [&](hipStream_t es) {
-            if (signalled) return;
-            signalled = true;
-            (void)hipEventRecord(pl->ev_stagger[slot], es);
-            std::lock_guard<std::mutex> lk(pl->mu);
-            pl->started = std::max(pl->started, job.seq + 1);
-            pl->cv.notify_all();
-        };
         if (rc == EBSD_OK) {
             if (job.has_offs) job.out.field_offset = job.offs.data();
-            pl->h[slot]->on_finest_level = signal;
             rc = run(pl->h[slot], job.pairs.data(), (int)job.pairs.size(), Mode::Full, nullptr, nullptr, &job.out,
                      s);
-            pl->h[slot]->on_finest_level = nullptr;
         }
-        signal(s);  // a batch that ran no demons level (or failed) releases its successor here
         if (hipEventRecord(pl->ev_done[slot], s) != hipSuccess && rc == EBSD_OK) rc = EBSD_EDEVICE;
         std::lock_guard<std::mutex> lk(pl->mu);
         if (rc != EBSD_OK && pl->error == EBSD_OK) pl->error = rc;
@@ -1517,8 +1490,6 @@ void pipeline_free(ebsd_pipeline* pl)
         DeviceGuard g(pl->device);
         for (hipStream_t s : pl->st)
             if (s) (void)hipStreamSynchronize(s);
-        for (hipEvent_t e : pl->ev_stagger)
-            if (e) (void)hipEventDestroy(e);
         for (hipEvent_t e : pl->ev_done)
             if (e) (void)hipEventDestroy(e);
         for (hipStream_t s : pl->st)
@@ -1545,7 +1516,6 @@ int ebsd_pipeline_create(const ebsd_params* p, int device, int32_t depth, ebsd_p
     pl->device = device;
     pl->h.assign(depth, nullptr);
     pl->st.assign(depth, nullptr);
-    pl->ev_stagger.assign(depth, nullptr);
     pl->ev_done.assign(depth, nullptr);
     pl->queue.resize(depth);
     for (int k = 0; k < depth; k++) {
@@ -1560,7 +1530,6 @@ int ebsd_pipeline_create(const ebsd_params* p, int device, int32_t depth, ebsd_p
         bool ok = g.ok;
         for (int k = 0; ok && k < depth; k++)
             ok = hipStreamCreateWithFlags(&pl->st[k], hipStreamNonBlocking) == hipSuccess &&
-                 hipEventCreateWithFlags(&pl->ev_stagger[k], hipEventDisableTiming) == hipSuccess &&
                  hipEventCreateWithFlags(&pl->ev_done[k], hipEventDisableTiming) == hipSuccess;
         if (!ok) {
             pipeline_free(pl);
@@ -1609,8 +1578,8 @@ int ebsd_pipeline_submit(ebsd_pipeline* pl, const ebsd_pair* pairs, int32_t n, c
         }
     }
     std::lock_guard<std::mutex> lk(pl->mu);
-    job.seq = pl->submitted++;
-    pl->queue[job.seq % pl->depth].push_back(std::move(job));
+    const uint64_t seq = pl->submitted++;
+    pl->queue[seq % pl->depth].push_back(std::move(job));
     pl->cv.notify_all();
     return EBSD_OK;
 }

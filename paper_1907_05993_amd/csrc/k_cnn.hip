@@ -1269,21 +1269,15 @@ hipError_t launch_conv3x3(const ConvArgs& a, hipStream_t s)
         else hipLaunchKernelGGL((k_conv3x3_r4<1>), dim3((unsigned)tiles4), block, 0, s, a);
         return hipGetLastError();
     }
-    // k_conv3x3_lds where the input has at least 8 chunks of 32 channels: measured per layer of
+    // k_conv3x3_lds (two N tiles) where the input has at least 8 chunks of 32 channels: measured per layer of
     // the network (256 pairs), 256 -> 256 at 32 x 32 px 287 -> 261 us and the decoder's 384-channel
     // layer 805 -> 699 us; with 128 input channels both kernels take the same time, with 64 the
     // register-staged one is faster (350 against 376 us: two chunks leave the loads nothing to
     // overlap)
-    if (a.lds_dma && a.mode != 1 && a.Cin % 32 == 0 && a.Cin >= 256 && a.H % kLdsTH == 0) {
-        const int64_t t16 = (int64_t)a.n * (a.H / kLdsTH) * (a.W / kConvTW) * (a.Cout / (32 * nt));
-        const dim3 g16((unsigned)t16), b512(512);
-        if (a.c2 != 0) {
-            if (nt == 2) hipLaunchKernelGGL((k_conv3x3_lds<2, true>), g16, b512, 0, s, a);
-            else hipLaunchKernelGGL((k_conv3x3_lds<1, true>), g16, b512, 0, s, a);
-        } else {
-            if (nt == 2) hipLaunchKernelGGL((k_conv3x3_lds<2, false>), g16, b512, 0, s, a);
-            else hipLaunchKernelGGL((k_conv3x3_lds<1, false>), g16, b512, 0, s, a);
-        }
+    if (a.lds_dma && a.mode != 1 && nt == 2 && a.Cin % 32 == 0 && a.Cin >= 256 && a.H % kLdsTH == 0) {
+        const int64_t t16 = (int64_t)a.n * (a.H / kLdsTH) * (a.W / kConvTW) * (a.Cout / 64);
+        if (a.c2 != 0) hipLaunchKernelGGL((k_conv3x3_lds<2, true>), dim3((unsigned)t16), dim3(512), 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3_lds<2, false>), dim3((unsigned)t16), dim3(512), 0, s, a);
         return hipGetLastError();
     }
     const int64_t tiles = (int64_t)a.n * (a.H / kConvTH) * (a.W / kConvTW) * (a.Cout / (32 * nt));

@@ -526,10 +526,10 @@ class Registrar:
 
 class Pipeline:
     """Pipelined registration (ebsd_pipeline_*): batches submitted in turn run on
-    `depth` library handles with their own streams and host threads; batch k + 1
-    is issued once batch k has begun its finest demons level, so that its network
-    forward and coarse levels overlap that level.  Outputs equal
-    Registrar.register's bit for bit.  `slots` are Registrar views of the handles
+    `depth` library handles with their own streams and host threads, back to back
+    on each, so that `depth` batches are in flight and one batch's network
+    forward and coarse levels overlap another's finest demons level.  Outputs
+    equal Registrar.register's bit for bit.  `slots` are Registrar views of the handles
     for configuration (load_model, autotune, set_graphs, ...) while nothing is
     pending."""
 

@@ -1,6 +1,6 @@
 """Pipelined registration (ebsd_pipeline_*): batches submitted in turn run on
-two or three handles with their own streams, each batch issued once the
-previous one has begun its finest demons level.  Every output of every batch
+two or three handles with their own streams, several batches in flight at
+once.  Every output of every batch
 equals a plain ebsd_register_batch call on the same batch bit for bit: the
 warm-started path on the benchmark's patterns (256 x 256, 10 degrees, trained
 network), and the plain path with a tolerance that stops pairs (gated level
