@@ -334,11 +334,12 @@ int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int3
  * decision on the first is known; the next launch takes the decisions in
  * iteration order and recomputes the field of a pair that should have
  * stopped in between, so iteration counts, status and fields are identical to
- * one iteration per launch.  ebsd_autotune times strip heights 32, 64, 128 of
- * this kernel against the single-iteration kernel and keeps it for a level
- * size where it is faster.  ebsd_get_fused_height returns the strip height
- * used for a level size (0 = one iteration per launch); ebsd_set_fused_height
- * forces it (0, 16, 32, 64 or 128). */
+ * one iteration per launch.  ebsd_autotune times strip heights 8 (levels at
+ * most 128 px wide), 16, 32, 64, 128 of this kernel against the
+ * single-iteration kernel and keeps it for a level size where it is faster.
+ * ebsd_get_fused_height returns the strip height used for a level size (0 =
+ * one iteration per launch); ebsd_set_fused_height forces it (0, 16, 32, 64 or
+ * 128, or 8 for levels at most 128 px wide; EBSD_EINVAL otherwise). */
 int ebsd_get_fused_height(const ebsd_handle* h, int32_t level_h, int32_t level_w);
 int ebsd_set_fused_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t rows);
 

@@ -806,6 +806,12 @@ bool dispatch_ty2(const Bucket* d_bk, int nb, int h, int w, int level, int L, co
                   hipStream_t s)
 {
     switch (ty) {
+    case 8:  // rows of at most 128 px only (a single small pair's latency)
+        if constexpr (CPL <= 2) {
+            launch_rows2<CPL, RAD, 8>(d_bk, nb, h, w, level, L, tp, tol, cap, s);
+            return true;
+        }
+        return false;
     case 16: launch_rows2<CPL, RAD, 16>(d_bk, nb, h, w, level, L, tp, tol, cap, s); return true;
     case 32: launch_rows2<CPL, RAD, 32>(d_bk, nb, h, w, level, L, tp, tol, cap, s); return true;
     case 64: launch_rows2<CPL, RAD, 64>(d_bk, nb, h, w, level, L, tp, tol, cap, s); return true;

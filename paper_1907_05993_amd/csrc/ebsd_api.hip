@@ -129,7 +129,7 @@ void load_tune_cache(ebsd_handle* h)
         if (!(is >> fty)) fty = 0;
         const auto key = std::make_pair(lh, lw);
         if (strip_ty_ok(lw, ty)) h->strip_ty[key] = ty;
-        if (rows2_ty_supported(fty)) h->fused_ty[key] = fty;
+        if (rows2_ty_ok(lw, fty)) h->fused_ty[key] = fty;
         else h->fused_ty.erase(key);
     }
 }
@@ -420,7 +420,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         b.lvl_off[l] = (int32_t)pe;
         pe += (int64_t)b.lh[l] * b.lw[l];
         pe = (pe + 63) / 64 * 64;  // every level 256 B aligned
-        max_units = std::max(max_units, demons_units(b.lh[l], b.lw[l], kMinStripTY));
+        max_units = std::max(max_units, demons_units(b.lh[l], b.lw[l], kMinStripTY2));
         if (b.lw[l] > 512) max_units = std::max(max_units, demons_tiles(b.lh[l], b.lw[l]));
     }
     b.pyr_elems = pe;
@@ -662,7 +662,8 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
             h->tuned_nb_strip[std::make_pair(lh, lw)] = nb;
             // two iterations per launch: 3 launches (6 iterations) against the best 6 single launches
             int best_fty = 0;
-            for (int fty : {16, 32, 64, 128}) {
+            for (int fty : {8, 16, 32, 64, 128}) {
+                if (!rows2_ty_ok(lw, fty)) continue;
                 EBSD_TRY(launch_demons_iter2(d_bk, b, l, 0, h->taps, h->radius, 0.0f, 1 << 20, fty, s));
                 EBSD_TRY(hipEventRecord(e0, s));
                 for (int L2 = 1; L2 <= 3; L2++)
@@ -1078,7 +1079,7 @@ int ebsd_get_fused_height(const ebsd_handle* h, int32_t level_h, int32_t level_w
 int ebsd_set_fused_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t rows)
 {
     if (!h || level_h <= 0 || level_w <= 0) return EBSD_EINVAL;
-    if (rows != 0 && (!rows2_ty_supported(rows) || !rows_cpl(level_w))) return EBSD_EINVAL;
+    if (rows != 0 && !rows2_ty_ok(level_w, rows)) return EBSD_EINVAL;
     const auto key = std::make_pair((int)level_h, (int)level_w);
     if (rows) h->fused_ty[key] = rows;
     else h->fused_ty.erase(key);

@@ -297,10 +297,12 @@ __host__ __device__ inline void rows_seg_cols(int seg, int nsegs, int w, int nw,
     sx0 = ws - kSegHalo;
 }
 bool rows_ty_supported(int ty);
-// Two iterations per launch (temporal blocking) at strip heights 16, 32, 64, 128:
+// Two iterations per launch (temporal blocking) at strip heights 16, 32, 64, 128 (and 8 on
+// levels at most 128 px wide):
 // launch L of a level runs iterations 2L and 2L + 1 (see k_demons_rows2);
 // ceil(cap / 2) launches, plus one more when tol > 0 and cap is even.
 bool rows2_ty_supported(int ty);
+bool rows2_ty_ok(int w, int ty);  // ty supported for a level w px wide (8 only up to 128 px)
 bool launch_demons_rows2(const Bucket* d_bk, const Bucket& hb, int level, int L, const Taps& tp, int radius,
                          float tol, int cap, int ty, hipStream_t s);
 int rows_units(int h, int ty);
@@ -311,6 +313,7 @@ bool launch_demons_rows_stage(const float* R, const float* T, int n, int h, int 
 
 constexpr int kDefaultStripTY = 64;
 constexpr int kMinStripTY = 16;
+constexpr int kMinStripTY2 = 8;  // two-iteration kernel on rows of at most 128 px (latency of small batches)
 
 // Work units (and per-pair partial sums) of one demons iteration at h x w
 // with strip height ty (row-marching kernel: strips x column segments) or

@@ -45,7 +45,9 @@ int rows_cpl(int w)
 
 bool rows_ty_supported(int ty) { return ty == 16 || ty == 32 || ty == 64 || ty == 128; }
 
-bool rows2_ty_supported(int ty) { return ty == 16 || ty == 32 || ty == 64 || ty == 128; }
+bool rows2_ty_supported(int ty) { return ty == 8 || ty == 16 || ty == 32 || ty == 64 || ty == 128; }
+
+bool rows2_ty_ok(int w, int ty) { return rows2_ty_supported(ty) && rows_cpl(w) && (ty != 8 || rows_cpl(w) <= 2); }
 
 bool launch_demons_rows2(const Bucket* d_bk, const Bucket& hb, int level, int L, const Taps& tp, int radius,
                          float tol, int cap, int ty, hipStream_t s)
