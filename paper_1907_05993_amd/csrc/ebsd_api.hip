@@ -870,8 +870,8 @@ size_t desc_upper_bound(const HostBucket& hb, int nr)
            sizeof(int32_t) * 2 * nb + sizeof(double) * 2 * nr + sizeof(int32_t) * 2 * nr;
 }
 
-int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u_init,
-        const double* rfin_in, const ebsd_outputs* out, void* stream, bool tune_only = false)
+int run_body(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u_init,
+             const double* rfin_in, const ebsd_outputs* out, void* stream, bool tune_only)
 {
     if (!h || !out) return EBSD_EINVAL;
     int e = check_pairs(h->p, pairs, n);
@@ -909,6 +909,18 @@ int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u
     h->pin_pending = true;
     if (tune_only) save_tune_cache(h);
     return EBSD_OK;
+}
+
+// A call's host-side containers (buckets, descriptors, the tuned tables) can
+// throw std::bad_alloc; no exception leaves the C ABI or a pipeline's thread.
+int run(ebsd_handle* h, const ebsd_pair* pairs, int n, Mode mode, const float* u_init,
+        const double* rfin_in, const ebsd_outputs* out, void* stream, bool tune_only = false)
+{
+    try {
+        return run_body(h, pairs, n, mode, u_init, rfin_in, out, stream, tune_only);
+    } catch (const std::bad_alloc&) {
+        return EBSD_ENOMEM;
+    }
 }
 
 }  // namespace
@@ -997,8 +1009,13 @@ int ebsd_create(const ebsd_params* p, int device, ebsd_handle** out)
         delete h;
         return EBSD_EDEVICE;
     }
-    if (const char* c = std::getenv("EBSD_TUNE_CACHE")) h->tune_cache = c;
-    load_tune_cache(h);
+    try {
+        if (const char* c = std::getenv("EBSD_TUNE_CACHE")) h->tune_cache = c;
+        load_tune_cache(h);
+    } catch (const std::bad_alloc&) {
+        (void)ebsd_destroy(h);
+        return EBSD_ENOMEM;
+    }
     *out = h;
     return EBSD_OK;
 }
@@ -1065,7 +1082,11 @@ int ebsd_get_strip_height(const ebsd_handle* h, int32_t level_h, int32_t level_w
 int ebsd_set_strip_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int32_t ty)
 {
     if (!h || level_h <= 0 || level_w <= 0 || !strip_ty_ok(level_w, ty)) return EBSD_EINVAL;
-    h->strip_ty[std::make_pair((int)level_h, (int)level_w)] = ty;
+    try {
+        h->strip_ty[std::make_pair((int)level_h, (int)level_w)] = ty;
+    } catch (const std::bad_alloc&) {
+        return EBSD_ENOMEM;
+    }
     h->tuned_nb_strip.erase(std::make_pair((int)level_h, (int)level_w));  // forced: applies to every batch
     return EBSD_OK;
 }
@@ -1081,8 +1102,12 @@ int ebsd_set_fused_height(ebsd_handle* h, int32_t level_h, int32_t level_w, int3
     if (!h || level_h <= 0 || level_w <= 0) return EBSD_EINVAL;
     if (rows != 0 && !rows2_ty_ok(level_w, rows)) return EBSD_EINVAL;
     const auto key = std::make_pair((int)level_h, (int)level_w);
-    if (rows) h->fused_ty[key] = rows;
-    else h->fused_ty.erase(key);
+    try {
+        if (rows) h->fused_ty[key] = rows;
+        else h->fused_ty.erase(key);
+    } catch (const std::bad_alloc&) {
+        return EBSD_ENOMEM;
+    }
     h->tuned_nb_fused.erase(key);  // forced: applies to every batch
     return EBSD_OK;
 }
@@ -1579,8 +1604,14 @@ int ebsd_pipeline_submit(ebsd_pipeline* pl, const ebsd_pair* pairs, int32_t n, c
         }
     }
     std::lock_guard<std::mutex> lk(pl->mu);
-    const uint64_t seq = pl->submitted++;
-    pl->queue[seq % pl->depth].push_back(std::move(job));
+    try {
+        pl->queue[pl->submitted % pl->depth].push_back(std::move(job));
+    } catch (const std::bad_alloc&) {  // the queue is unchanged and job still owns its event
+        DeviceGuard g(pl->device);
+        (void)hipEventDestroy(job.ready);
+        return EBSD_ENOMEM;
+    }
+    pl->submitted++;
     pl->cv.notify_all();
     return EBSD_OK;
 }
