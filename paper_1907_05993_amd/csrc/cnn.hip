@@ -91,7 +91,12 @@ bool dalloc(ebsd_cnn* c, T** p, int64_t elems)
         (void)hipGetLastError();
         return false;
     }
-    c->allocs.push_back(q);
+    try {
+        c->allocs.push_back(q);
+    } catch (const std::bad_alloc&) {
+        (void)hipFree(q);
+        return false;
+    }
     *p = static_cast<T*>(q);
     return true;
 }
@@ -462,15 +467,19 @@ int ebsd_cnn_get_grads(const ebsd_cnn* c, float* host, int64_t n)
 int ebsd_cnn_load(ebsd_cnn* c, const char* path)
 {
     if (!c || !path) return EBSD_EINVAL;
+    std::vector<float> buf;
+    try {
+        buf.resize((size_t)kNumParams);
+    } catch (const std::bad_alloc&) {
+        return EBSD_ENOMEM;
+    }
     FILE* f = fopen(path, "rb");
     if (!f) return EBSD_EIO;
     char magic[8];
     int64_t cnt = 0;
-    std::vector<float> buf;
     bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "EBSDCNN1", 8) == 0 &&
               fread(&cnt, sizeof(cnt), 1, f) == 1 && cnt == kNumParams;
     if (ok) {
-        buf.resize((size_t)kNumParams);
         ok = fread(buf.data(), sizeof(float), (size_t)kNumParams, f) == (size_t)kNumParams;
     }
     fclose(f);
@@ -483,7 +492,12 @@ int ebsd_cnn_load(ebsd_cnn* c, const char* path)
 int ebsd_cnn_save(const ebsd_cnn* c, const char* path)
 {
     if (!c || !path) return EBSD_EINVAL;
-    std::vector<float> buf((size_t)kNumParams);
+    std::vector<float> buf;
+    try {
+        buf.resize((size_t)kNumParams);
+    } catch (const std::bad_alloc&) {
+        return EBSD_ENOMEM;
+    }
     int e = ebsd_cnn_get_params(c, buf.data(), kNumParams);
     if (e != EBSD_OK) return e;
     FILE* f = fopen(path, "wb");
