@@ -145,6 +145,30 @@ def test_demons_1d_ramp_closed_form(orc):
     assert not u_new[1].any()
 
 
+def test_demons_ramp_trajectory_two_levels_closed_form(orc):
+    # R(x) = x, T(x) = x - s on two levels without smoothing.  Away from the borders the field is
+    # uniform and follows Eq. (1) for a linear pattern step by step: the restricted ramp has slope 2
+    # (R1(x') = 2 x' + 0.5, T1 = R1 - s), so with U the displacement in full-resolution px,
+    # a = s - U and the coarse step is U += 4 a / (4 + a^2); prolongation doubles the coarse field
+    # (U unchanged); the fine step is U += a / (1 + a^2).  Checks the accumulation over iterations,
+    # the level order, the coarse-px scaling and the prolongation together.
+    s, k1, k0 = 6.0, 3, 4
+    H, W = 16, 64
+    x = np.tile(np.arange(W, dtype=np.float64), (H, 1))
+    f, its, _ = orc.demons(x, x - s, orc.make_params(levels=2, iters=[k0, k1], sigma=0.0))
+    assert list(its) == [k0, k1]
+    U = 0.0
+    for _ in range(k1):
+        a = s - U
+        U += 4.0 * a / (4.0 + a * a)
+    for _ in range(k0):
+        a = s - U
+        U += a / (1.0 + a * a)
+    assert 2.0 < U < s - 2.0  # far from converged: every step moves the field
+    np.testing.assert_allclose(f[0][:, 8:51], U, rtol=0, atol=1e-12)
+    assert not f[1].any()
+
+
 def test_demons_force_sign_drives_toward_shift(orc):
     # T(x) = R(x - s) with a smooth R: after iterations u -> s in the interior
     y, x = np.mgrid[0:64, 0:64].astype(np.float64)
