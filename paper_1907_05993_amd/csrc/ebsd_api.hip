@@ -1199,7 +1199,12 @@ int ebsd_set_model(ebsd_handle* h, const ebsd_cnn* c)
         const int e = ebsd_cnn_create(h->device, kWarmBatch, &h->cnn);
         if (e) return e;
     }
-    std::vector<float> buf((size_t)EBSD_CNN_PARAMS);
+    std::vector<float> buf;
+    try {
+        buf.resize((size_t)EBSD_CNN_PARAMS);
+    } catch (const std::bad_alloc&) {
+        return EBSD_ENOMEM;
+    }
     int e = ebsd_cnn_get_params(c, buf.data(), EBSD_CNN_PARAMS);
     if (e) return e;
     return ebsd_cnn_set_params(h->cnn, buf.data(), EBSD_CNN_PARAMS);
@@ -1540,10 +1545,16 @@ int ebsd_pipeline_create(const ebsd_params* p, int device, int32_t depth, ebsd_p
     if (!pl) return EBSD_ENOMEM;
     pl->depth = depth;
     pl->device = device;
-    pl->h.assign(depth, nullptr);
-    pl->st.assign(depth, nullptr);
-    pl->ev_done.assign(depth, nullptr);
-    pl->queue.resize(depth);
+    try {
+        pl->h.assign(depth, nullptr);
+        pl->st.assign(depth, nullptr);
+        pl->ev_done.assign(depth, nullptr);
+        pl->queue.resize(depth);
+        pl->workers.reserve(depth);
+    } catch (const std::bad_alloc&) {
+        pipeline_free(pl);
+        return EBSD_ENOMEM;
+    }
     for (int k = 0; k < depth; k++) {
         e = ebsd_create(p, device, &pl->h[k]);
         if (e) {

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <new>
 #include <set>
 #include <tuple>
 #include <vector>
@@ -284,7 +285,14 @@ extern "C" int ebsd_gen_pairs(const ebsd_gen_spec* specs, int32_t n, int32_t H, 
     if (H < 8 || W < 8 || H > 4096 || W > 4096 || (label && (H % 4 || W % 4))) return EBSD_ESHAPE;
     if (!(pc_z > 0.0) || !std::isfinite(pc_x) || !std::isfinite(pc_y) || !std::isfinite(pc_z)) return EBSD_EINVAL;
     if (n == 0) return EBSD_OK;
-    std::vector<GenPair> hp((size_t)n);
+    std::vector<GenPair> hp;
+    BandTable bt;
+    try {
+        hp.resize((size_t)n);
+        bt = fcc_bands();
+    } catch (const std::bad_alloc&) {
+        return EBSD_ENOMEM;
+    }
     for (int i = 0; i < n; i++) {
         const ebsd_gen_spec& s = specs[i];
         GenPair& g = hp[(size_t)i];
@@ -303,7 +311,6 @@ extern "C" int ebsd_gen_pairs(const ebsd_gen_spec* specs, int32_t n, int32_t H, 
         g.noise = s.noise != 0;
         g.bands = s.bands != 0;
     }
-    const BandTable bt = fcc_bands();
     hipStream_t st = static_cast<hipStream_t>(stream);
     DevMem dpairs, dbt, dpart;
     if (hipMalloc(&dpairs.p, sizeof(GenPair) * (size_t)n) != hipSuccess ||
