@@ -90,6 +90,38 @@ def test_stage_demons_identical_images_exact(E):
     assert not un.any().item() and rms.item() == 0.0
 
 
+@pytest.mark.parametrize("sigma", [0.0, 1.0])
+def test_stage_demons_ramp_trajectory_closed_form(E, sigma):
+    """R(x) = x, T(x) = x - s through the stage kernels: restriction, 3 coarse
+    steps, prolongation, 4 fine steps.  Away from the borders the field is
+    uniform (smoothing keeps it so) and follows the scalar recurrences of
+    Eq. (1) for a linear pattern, U += 4 a / (4 + a^2) on the coarse level
+    (full-resolution px, slope 2) and U += a / (1 + a^2) on the fine one,
+    a = s - U; no oracle involved.  FP32 bar 1e-4 px (intensities up to 127)."""
+    s, k1, k0, H, W = 6.0, 3, 4, 16, 128
+    x = np.tile(np.arange(W, dtype=np.float32), (1, H, 1))
+    R, T = cuda(x), cuda(x - np.float32(s))
+    R1, T1 = E.stage_restrict(R), E.stage_restrict(T)
+    u = torch.zeros(1, 2, H // 2, W // 2, device="cuda")
+    for _ in range(k1):
+        u, _ = E.stage_demons_iter(R1, T1, u, sigma)
+    u = E.stage_prolong(u)
+    for _ in range(k0):
+        u, _ = E.stage_demons_iter(R, T, u, sigma)
+    U = 0.0
+    for _ in range(k1):
+        a = s - U
+        U += 4.0 * a / (4.0 + a * a)
+    for _ in range(k0):
+        a = s - U
+        U += a / (1.0 + a * a)
+    f = u.cpu().numpy()[0].astype(np.float64)
+    lo, hi = (8, 112) if sigma == 0 else (24, 100)  # border effects spread 3 columns per smoothed step
+    print("closed form U = %.6f; GPU interior min %.6f max %.6f" % (U, f[0][:, lo:hi].min(), f[0][:, lo:hi].max()))
+    np.testing.assert_allclose(f[0][:, lo:hi], U, rtol=0, atol=1e-4)
+    assert np.abs(f[1]).max() <= 1e-6
+
+
 @pytest.mark.parametrize("hw", [(8, 8), (16, 32), (64, 64), (5, 7)])
 def test_stage_prolong(E, orc, hw):
     h, w = hw
