@@ -32,7 +32,9 @@
  *     synchronises the device first.
  *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
  *     stream): outputs are valid once the stream has completed.  A handle is
- *     used by one host thread at a time.
+ *     used by one host thread at a time; different handles may run in
+ *     different threads at once (the library keeps its graph captures apart
+ *     from its device-wide waits, workspace growth and frees).
  *   - Errors: every call validates all of its arguments before anything is
  *     enqueued and returns a negative EBSD_E* code (outputs untouched).
  *     Numerical outcomes never fail a batch: they are reported per pair in

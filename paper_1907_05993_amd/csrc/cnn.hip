@@ -159,6 +159,7 @@ int64_t wgrad_part_floats(int n)
 bool alloc_backward(ebsd_cnn* c)
 {
     if (c->have_bwd) return true;
+    DeviceWideLock lk(capture_mutex());
     const int64_t n = c->max_batch;
     const int64_t g = n * px(256) * 32;  // largest gradient tensor
     const int64_t bp = (int64_t)mask_blocks(n * px(256), 32) * 32;
@@ -399,6 +400,7 @@ int ebsd_cnn_create(int device, int32_t max_batch, ebsd_cnn** out)
     }
     DevGuard g(device);
     if (!g.ok) return EBSD_EDEVICE;
+    DeviceWideLock lk(capture_mutex());
     ebsd_cnn* c = new (std::nothrow) ebsd_cnn();
     if (!c) return EBSD_ENOMEM;
     c->device = device;
@@ -418,6 +420,7 @@ int ebsd_cnn_destroy(ebsd_cnn* c)
     if (!c) return EBSD_OK;
     {
         DevGuard g(c->device);
+        DeviceWideLock lk(capture_mutex());
         (void)hipDeviceSynchronize();
         free_all(c);
     }
@@ -429,6 +432,7 @@ int ebsd_cnn_set_params(ebsd_cnn* c, const float* host, int64_t n)
 {
     if (!c || !host || n != kNumParams) return EBSD_EINVAL;
     DevGuard g(c->device);
+    DeviceWideLock lk(capture_mutex());
     if (!g.ok) return EBSD_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return EBSD_EDEVICE;
     if (hipMemcpy(c->params, host, kNumParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
@@ -448,6 +452,7 @@ int ebsd_cnn_get_params(const ebsd_cnn* c, float* host, int64_t n)
 {
     if (!c || !host || n != kNumParams) return EBSD_EINVAL;
     DevGuard g(c->device);
+    DeviceWideLock lk(capture_mutex());
     if (!g.ok || hipDeviceSynchronize() != hipSuccess) return EBSD_EDEVICE;
     return hipMemcpy(host, c->params, kNumParams * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess
                ? EBSD_OK
@@ -458,6 +463,7 @@ int ebsd_cnn_get_grads(const ebsd_cnn* c, float* host, int64_t n)
 {
     if (!c || !host || n != kNumParams || !c->have_bwd) return EBSD_EINVAL;
     DevGuard g(c->device);
+    DeviceWideLock lk(capture_mutex());
     if (!g.ok || hipDeviceSynchronize() != hipSuccess) return EBSD_EDEVICE;
     return hipMemcpy(host, c->grads, kNumParams * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess
                ? EBSD_OK
@@ -569,6 +575,7 @@ int ebsd_cnn_get_optimizer(const ebsd_cnn* c, float* m, float* v, int64_t n, int
     if (!c || n != kNumParams) return EBSD_EINVAL;
     if (step) *step = c->step;
     DevGuard g(c->device);
+    DeviceWideLock lk(capture_mutex());
     if (!g.ok || hipDeviceSynchronize() != hipSuccess) return EBSD_EDEVICE;
     for (int k = 0; k < 2; k++) {
         float* dst = k == 0 ? m : v;
@@ -589,6 +596,7 @@ int ebsd_cnn_set_optimizer(ebsd_cnn* c, const float* m, const float* v, int64_t 
     DevGuard g(c->device);
     if (!g.ok) return EBSD_EDEVICE;
     if (!alloc_backward(c)) return EBSD_ENOMEM;
+    DeviceWideLock lk(capture_mutex());
     if (hipDeviceSynchronize() != hipSuccess ||
         hipMemcpy(c->adam_m, m, kNumParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->adam_v, v, kNumParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
@@ -610,6 +618,7 @@ int ebsd_cnn_reset_optimizer(ebsd_cnn* c)
     c->step = 0;
     if (!c->have_bwd) return EBSD_OK;
     DevGuard g(c->device);
+    DeviceWideLock lk(capture_mutex());
     if (!g.ok || hipDeviceSynchronize() != hipSuccess) return EBSD_EDEVICE;
     if (hipMemset(c->adam_m, 0, kNumParams * sizeof(float)) != hipSuccess ||
         hipMemset(c->adam_v, 0, kNumParams * sizeof(float)) != hipSuccess)
@@ -647,6 +656,7 @@ int ebsd_stage_conv3x3(const uint16_t* x, int32_t n, int32_t H, int32_t W, int32
     if (!x || !w || !out || (mode != 0 && mode != 1) || (mode == 0 && !bias)) return EBSD_EINVAL;
     if (!conv_shape_ok(n, H, W, Cin, Cout)) return EBSD_ESHAPE;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceWideLock lk(capture_mutex());
     TempBuf wf;
     if (hipMalloc(&wf.p, sizeof(bf16_t) * 9 * Cin * Cout) != hipSuccess) return EBSD_ENOMEM;
     if (launch_pack_weights(w, Cin, Cin, Cout, static_cast<bf16_t*>(wf.p), nullptr, s) != hipSuccess)
@@ -674,6 +684,7 @@ int ebsd_stage_conv3x3_dgrad(const uint16_t* dz, int32_t n, int32_t H, int32_t W
     if (!dz || !w || !dx) return EBSD_EINVAL;
     if (!conv_shape_ok(n, H, W, Cout, Cin)) return EBSD_ESHAPE;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceWideLock lk(capture_mutex());
     TempBuf wf, wd;
     if (hipMalloc(&wf.p, sizeof(bf16_t) * 9 * Cin * Cout) != hipSuccess ||
         hipMalloc(&wd.p, sizeof(bf16_t) * 9 * Cin * Cout) != hipSuccess)
@@ -714,6 +725,7 @@ int ebsd_stage_conv3x3_wgrad(const uint16_t* x, const uint16_t* dz, int32_t n, i
     a.Cout = Cout;
     a.cin_keep = Cin;
     a.splits = wgrad_splits(n, H, W, Cin, Cout, &a.tiles_per_split);
+    DeviceWideLock lk(capture_mutex());
     TempBuf part, tmp;
     const int64_t tmp_floats = (int64_t)((a.splits + 511) / 512) * 9 * Cin * Cout;
     if (hipMalloc(&part.p, sizeof(float) * (size_t)a.splits * 9 * Cin * Cout) != hipSuccess ||

@@ -298,6 +298,7 @@ void clear_graphs(ebsd_handle* h)
 int ensure_ws(ebsd_handle* h, size_t bytes)
 {
     if (bytes <= h->ws_bytes) return EBSD_OK;
+    DeviceWideLock lk(capture_mutex());
     if (hipDeviceSynchronize() != hipSuccess) return EBSD_EDEVICE;
     clear_graphs(h);  // captured kernels point into the old workspace
     if (h->ws) (void)hipFree(h->ws);
@@ -322,6 +323,7 @@ int ensure_pin(ebsd_handle* h, size_t bytes)
         h->pin_pending = false;
     }
     if (bytes <= h->pin_bytes) return EBSD_OK;
+    DeviceWideLock lk(capture_mutex());
     if (h->pin) (void)hipHostFree(h->pin);
     h->pin = nullptr;
     h->pin_bytes = 0;
@@ -720,6 +722,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
                     hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
                     h->cap_stream = nullptr;
                 hipGraph_t graph = nullptr;
+                std::shared_lock<std::shared_mutex> cap_lk(capture_mutex());
                 if (h->cap_stream &&
                     hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
                     const int e2 = launch_range(l, ty, fty, a, e, h->cap_stream);
@@ -747,6 +750,7 @@ int run_bucket(ebsd_handle* h, const HostBucket& hbk, Mode mode, const float* u_
         (void)hipGetLastError();
     }
     if (gate && !h->gate_host) {
+        DeviceWideLock lk(capture_mutex());
         if (hipHostMalloc((void**)&h->gate_host, sizeof(int32_t) * 4, hipHostMallocMapped) != hipSuccess ||
             hipHostGetDevicePointer((void**)&h->gate_dev, h->gate_host, 0) != hipSuccess) {
             if (h->gate_host) (void)hipHostFree(h->gate_host);
@@ -1117,6 +1121,7 @@ int ebsd_destroy(ebsd_handle* h)
     if (!h) return EBSD_OK;
     {
         DeviceGuard g(h->device);
+        DeviceWideLock lk(capture_mutex());
         (void)hipDeviceSynchronize();
         if (h->ws) (void)hipFree(h->ws);
         if (h->pin) (void)hipHostFree(h->pin);
@@ -1244,6 +1249,7 @@ int ebsd_stage_bandpass(const float* in, int32_t n, int32_t H, int32_t W, float 
     if (!(lo_px >= 0.0f && lo_px <= 32.0f) || !(hi_px >= 0.0f && hi_px <= 32.0f)) return EBSD_EINVAL;
     if (H < 1 || W < 2 || W > 16384 || H > 65535 || n > 65535) return EBSD_ESHAPE;
     if (n == 0) return EBSD_OK;
+    DeviceWideLock lk(capture_mutex());  // the temporary's free waits for the device
     DevBuf tmp;
     if (hipMalloc(&tmp.p, sizeof(float) * 2 * (size_t)n * H * W) != hipSuccess) return EBSD_ENOMEM;
     BandIO io;
@@ -1376,6 +1382,7 @@ int ebsd_stage_xcf(const float* A, const float* B, int32_t n, int32_t N, int32_t
     if (n == 0) return EBSD_OK;
     const hipStream_t s = (hipStream_t)stream;
     if (N < 256) return map_err(launch_stage_xcf(A, B, n, N, window, q, ph, nullptr, s));
+    DeviceWideLock lk(capture_mutex());  // the temporary's free waits for the device
     DevBuf scr;
     if (hipMalloc(&scr.p, sizeof(float) * (size_t)xcf_scratch_floats(N, n)) != hipSuccess) {
         (void)hipGetLastError();

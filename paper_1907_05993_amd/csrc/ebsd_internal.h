@@ -6,8 +6,24 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <mutex>
+#include <shared_mutex>
 
 namespace ebsd {
+
+// Stream capture in one host thread and a call that waits for the whole device
+// in another (hipDeviceSynchronize, and the frees and pinned allocations that
+// synchronise implicitly) must not overlap: the wait would take in the stream
+// being captured, which fails the call or invalidates the capture.  Several
+// handles run in their own threads in a pipeline, so captures hold this lock
+// shared and every device-wide wait or (de)allocation of the library holds it
+// exclusively.
+inline std::shared_mutex& capture_mutex()
+{
+    static std::shared_mutex m;
+    return m;
+}
+using DeviceWideLock = std::unique_lock<std::shared_mutex>;
 
 // Raises a kernel's dynamic LDS limit on the current device, once per device:
 // a host-side function attribute (not a stream operation).  `done` holds one

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/ebsd.h"
+#include "ebsd_internal.h"
 
 namespace {
 
@@ -312,6 +313,7 @@ extern "C" int ebsd_gen_pairs(const ebsd_gen_spec* specs, int32_t n, int32_t H, 
         g.bands = s.bands != 0;
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
+    ebsd::DeviceWideLock lk(ebsd::capture_mutex());  // the buffers' frees wait for the device
     DevMem dpairs, dbt, dpart;
     if (hipMalloc(&dpairs.p, sizeof(GenPair) * (size_t)n) != hipSuccess ||
         hipMalloc(&dbt.p, sizeof(BandTable)) != hipSuccess ||

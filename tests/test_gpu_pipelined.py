@@ -65,6 +65,68 @@ def test_pipelined_batches_equal_single_calls(E, batches, depth, warm, tol):
     pl.close()
 
 
+@pytest.mark.parametrize("depth,warm,tol", [(2, False, 0.1), (3, True, 0.05)])
+def test_pipelined_mixed_size_batches_equal_single_calls(E, depth, warm, tol):
+    """Batches that each hold 128 x 128 and 256 x 256 pairs in an interleaved
+    order (two size buckets per call, the warm start resampling the 128 px
+    pairs), several in flight: every output equals a single call's."""
+    from paper_1907_05993_amd import synth as S
+    p = E.Params(levels=3, iters=(30,) * 3, sigma_px=1.0, tol_px=tol, roi_size=32, n_roi=20,
+                 warm_start=2 if warm else 0, fallback_residual_px=1.0)
+    print(f"case: pipeline depth {depth}, warm={warm}, tol {tol}, 3 mixed batches of 24 x 128^2 + 16 x 256^2",
+          flush=True)
+    small = E.gen_pairs([S.make_spec(31, i, 128, 128, mis_deg=(0.0, 12.0)) for i in range(72)], labels=False)
+    large = E.gen_pairs([S.make_spec(32, i, 256, 256, mis_deg=(0.0, 12.0)) for i in range(48)], labels=False)
+    batches = []
+    ns = nl = 0
+    for k in range(3):
+        refs, tests = [], []
+        for j in range(40):  # 3 small, 2 large, repeated
+            if j % 5 < 3:
+                src, i, ns = small, ns, ns + 1
+            else:
+                src, i, nl = large, nl, nl + 1
+            refs.append(src[0][i])
+            tests.append(src[1][i])
+        batches.append((refs, tests))
+    assert ns == 72 and nl == 48
+
+    def host_mixed(out):
+        got = {k: out[k].cpu().numpy() for k in KEYS if k in out and k != "field"}
+        got["field"] = [f.cpu().numpy() for f in out["field"]]
+        return got
+
+    reg = E.Registrar(p)
+    if warm:
+        reg.load_model(WEIGHTS)
+    want = [host_mixed(reg.register(r, t)) for r, t in batches]
+    torch.cuda.synchronize()
+    reg.close()
+    pl = E.Pipeline(p, depth=depth)
+    if warm:
+        pl.load_model(WEIGHTS)
+    outs = [pl.submit(r, t) for r, t in batches]
+    pl.wait()
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        got = host_mixed(o)
+        assert got.keys() == want[k].keys()
+        for key in got:
+            if key == "field":
+                assert len(got[key]) == 40
+                for j in range(40):
+                    assert np.array_equal(got[key][j], want[k][key][j]), (k, j)
+            else:
+                assert np.array_equal(got[key], want[k][key], equal_nan=True), (k, key)
+    its = np.concatenate([w["iters"] for w in want])
+    print("pairs stopped before the cap per level:", (its < 30).sum(axis=0).tolist(), flush=True)
+    assert (its < 30).any()
+    if warm:
+        st = np.concatenate([w["status"] for w in want])
+        print("warm start used on", int((st & E.WARM_USED != 0).sum()), "of", st.size, flush=True)
+    pl.close()
+
+
 def test_pipeline_rejects_bad_batches_at_submission(E, batches):
     pl = E.Pipeline(E.Params(levels=3, iters=(5,) * 3), depth=2)
     r, t = batches[0]
