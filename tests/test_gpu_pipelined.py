@@ -4,7 +4,9 @@ once.  Every output of every batch
 equals a plain ebsd_register_batch call on the same batch bit for bit: the
 warm-started path on the benchmark's patterns (256 x 256, 10 degrees, trained
 network), and the plain path with a tolerance that stops pairs (gated level
-launches, counts and stop decisions included).  Needs an MI355X."""
+launches, counts and stop decisions included), batches of two pattern sizes
+(plain and warm-started), and scan batches whose grains share references.
+Needs an MI355X."""
 import numpy as np
 import pytest
 import torch
@@ -124,6 +126,50 @@ def test_pipelined_mixed_size_batches_equal_single_calls(E, depth, warm, tol):
     if warm:
         st = np.concatenate([w["status"] for w in want])
         print("warm start used on", int((st & E.WARM_USED != 0).sum()), "of", st.size, flush=True)
+    pl.close()
+
+
+def test_pipelined_scan_batches_with_shared_references_equal_single_calls(E):
+    """Scan points at 400 x 400 whose grains share one reference each (ref_ids:
+    one reference pyramid per grain), ROIs of 128, two batches in flight on two
+    handles with a stopping tolerance: every output equals a single call's."""
+    from paper_1907_05993_amd import synth as S
+    m = S.scan_map()
+    gid = m["gid"].ravel()
+    batches = []
+    for pick in ([0, 7, 19, 40], [1, 8, 20, 39]):
+        idx = []
+        for g in (0, 6, 9):
+            idx += [int(i) for i in np.nonzero(gid == g)[0][pick]]
+        tests, refs, ref_ids = S.scan_specs(400, 400, idx, smap=m)
+        ref_img, test_img = S.render_scan(tests, refs, ref_ids)
+        d_ref = {g: torch.from_numpy(r).cuda() for g, r in ref_img.items()}
+        batches.append(([d_ref[g] for g in ref_ids], [torch.from_numpy(t).cuda() for t in test_img], list(ref_ids)))
+    print("case: pipeline depth 2, 2 scan batches of 12 points at 400^2, 3 shared references each", flush=True)
+    p = E.Params(levels=3, iters=(20,) * 3, sigma_px=1.0, tol_px=0.1, roi_size=128, n_roi=20)
+
+    def host_list(out):
+        got = {k: out[k].cpu().numpy() for k in KEYS if k in out and k != "field"}
+        f = out["field"]
+        got["field"] = f.cpu().numpy() if isinstance(f, torch.Tensor) else np.stack([x.cpu().numpy() for x in f])
+        return got
+
+    reg = E.Registrar(p)
+    want = [host_list(reg.register(r, t, ref_ids=ids)) for r, t, ids in batches]
+    torch.cuda.synchronize()
+    reg.close()
+    pl = E.Pipeline(p, depth=2)
+    for rep in range(2):
+        outs = [pl.submit(r, t, ref_ids=ids) for r, t, ids in batches]
+        pl.wait()
+        torch.cuda.synchronize()
+        for k, o in enumerate(outs):
+            got = host_list(o)
+            assert got.keys() == want[k].keys()
+            for key in got:
+                assert np.array_equal(got[key], want[k][key], equal_nan=True), (rep, k, key)
+    its = np.concatenate([w["iters"] for w in want])
+    print("pairs stopped before the cap per level:", (its < 20).sum(axis=0).tolist(), flush=True)
     pl.close()
 
 
