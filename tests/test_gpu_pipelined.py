@@ -173,6 +173,29 @@ def test_pipelined_scan_batches_with_shared_references_equal_single_calls(E):
     pl.close()
 
 
+def test_pipelined_growing_batches_equal_single_calls(E, batches):
+    """Batches of 8, 48, 192, 16 and 96 pairs in turn on two handles: each
+    handle's workspace grows while the other captures and replays graphs for
+    new batch sizes; every output equals a single call's."""
+    r, t = batches[0]
+    sizes = (8, 48, 192, 16, 96)
+    p = E.Params(levels=3, iters=(12,) * 3, sigma_px=1.0, tol_px=0.05, roi_size=64, n_roi=20)
+    print("case: pipeline depth 2, batches of", sizes, flush=True)
+    reg = E.Registrar(p)
+    want = [host(reg.register(r[:n].contiguous(), t[:n].contiguous())) for n in sizes]
+    torch.cuda.synchronize()
+    reg.close()
+    pl = E.Pipeline(p, depth=2)
+    outs = [pl.submit(r[:n].contiguous(), t[:n].contiguous()) for n in sizes]
+    pl.wait()
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        got = host(o)
+        for key in got:
+            assert np.array_equal(got[key], want[k][key], equal_nan=True), (sizes[k], key)
+    pl.close()
+
+
 def test_pipeline_rejects_bad_batches_at_submission(E, batches):
     pl = E.Pipeline(E.Params(levels=3, iters=(5,) * 3), depth=2)
     r, t = batches[0]
