@@ -196,6 +196,48 @@ def test_pipelined_growing_batches_equal_single_calls(E, batches):
     pl.close()
 
 
+def test_registrars_in_two_threads_equal_serial_calls(E, batches):
+    """Two registrars used at once from two host threads, each on its own
+    stream (first calls: workspace growth and graph capture in both threads
+    at the same time); each thread's outputs equal a serial call's."""
+    import threading
+    p = E.Params(levels=3, iters=(15,) * 3, sigma_px=1.0, tol_px=0.05, roi_size=64, n_roi=20)
+    print("case: two registrars in two threads, 3 calls each", flush=True)
+    want = []
+    reg = E.Registrar(p)
+    for r, t in batches[:2]:
+        want.append(host(reg.register(r, t)))
+    torch.cuda.synchronize()
+    reg.close()
+    got = [[], []]
+    errors = []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            rg = E.Registrar(p)
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    out = rg.register(*batches[k])
+                    s.synchronize()
+                    got[k].append(host(out))
+            rg.close()
+        except Exception as e:  # reported by the main thread
+            errors.append(repr(e))
+
+    th = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join(timeout=120)
+    assert not errors, errors
+    for k in range(2):
+        assert len(got[k]) == 3
+        for rep, g in enumerate(got[k]):
+            for key in g:
+                assert np.array_equal(g[key], want[k][key], equal_nan=True), (k, rep, key)
+
+
 def test_pipeline_rejects_bad_batches_at_submission(E, batches):
     pl = E.Pipeline(E.Params(levels=3, iters=(5,) * 3), depth=2)
     r, t = batches[0]
