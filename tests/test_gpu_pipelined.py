@@ -244,8 +244,10 @@ def test_pipeline_rejects_bad_batches_at_submission(E, batches):
     with pytest.raises(E.EbsdError):
         pl.submit(r[:, :3, :3].contiguous(), t[:, :3, :3].contiguous())  # coarsest level under 4 x 4
     out = pl.submit(r[:4], t[:4])
+    empty = pl.submit(r[:0], t[:0])  # an empty batch is a no-op in the queue
     pl.wait()
     assert out["F"].shape == (4, 3, 3)
+    assert empty["F"].shape[0] == 0
     pl.close()
 
 
