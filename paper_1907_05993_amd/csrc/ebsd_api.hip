@@ -24,6 +24,8 @@
 #include <utility>
 #include <vector>
 
+#include <unistd.h>
+
 #include "../../include/ebsd.h"
 #include "ebsd_internal.h"
 #include "cnn_internal.h"
@@ -134,13 +136,30 @@ void load_tune_cache(ebsd_handle* h)
     }
 }
 
+// Written to a temporary file in the same folder and renamed over the cache, so
+// a handle created meanwhile (here or in another process) reads either the old
+// table or the new one, never a partial file; writers in this process take
+// turns.  Best effort: a cache that cannot be written is left as it was.
 void save_tune_cache(const ebsd_handle* h)
 {
     if (h->tune_cache.empty()) return;
-    std::ofstream f(h->tune_cache, std::ios::trunc);
-    for (auto& kv : h->strip_ty)
-        f << "gfx950 " << kv.first.first << " " << kv.first.second << " " << kv.second << " "
-          << fused_ty_for(h, kv.first.first, kv.first.second) << "\n";
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    std::ostringstream tmp;
+    tmp << h->tune_cache << ".tmp." << (unsigned long)getpid();
+    {
+        std::ofstream f(tmp.str(), std::ios::trunc);
+        for (auto& kv : h->strip_ty)
+            f << "gfx950 " << kv.first.first << " " << kv.first.second << " " << kv.second << " "
+              << fused_ty_for(h, kv.first.first, kv.first.second) << "\n";
+        f.flush();
+        if (!f) {
+            f.close();
+            std::remove(tmp.str().c_str());
+            return;
+        }
+    }
+    if (std::rename(tmp.str().c_str(), h->tune_cache.c_str()) != 0) std::remove(tmp.str().c_str());
 }
 
 struct DeviceGuard {

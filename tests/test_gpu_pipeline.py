@@ -354,3 +354,29 @@ def test_graph_replay_matches_eager(E, orc):
             torch.cuda.synchronize()
             for k in ("field", "F", "R", "q1", "q2", "peak_height", "iters", "status"):
                 assert torch.equal(a[k], b[k]), (rep, k)
+
+
+def test_tune_cache_file_written_whole_and_read_back(E, tmp_path, monkeypatch):
+    """With EBSD_TUNE_CACHE set, an autotune writes the tuned table through a
+    temporary file renamed over the cache (no partial file, no temporary left
+    behind), and a handle created afterwards starts from that table."""
+    from paper_1907_05993_amd import synth as S
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("EBSD_TUNE_CACHE", str(path))
+    specs = S.workload_specs("batch_256_10deg", n=64)
+    r, t, _ = E.gen_pairs(specs, labels=False)
+    p = E.Params(levels=3, iters=(10,) * 3, sigma_px=1.0, roi_size=64, n_roi=20)
+    print("case: tune cache, 64 pairs 256^2", flush=True)
+    reg = E.Registrar(p)
+    tuned = reg.autotune(r, t)
+    fused = reg.fused_heights(256, 256)
+    reg.close()
+    lines = path.read_text().splitlines()
+    print("cache:", lines, "tuned:", tuned, "fused:", fused, flush=True)
+    assert lines and all(x.split()[0] == "gfx950" and len(x.split()) == 5 for x in lines)
+    assert not [q.name for q in tmp_path.iterdir() if q.name != "tune.txt"]
+    reg2 = E.Registrar(p)
+    for (h, w), ty in tuned.items():
+        assert E.lib().ebsd_get_strip_height(reg2._h, h, w) == ty, (h, w)
+    assert reg2.fused_heights(256, 256) == fused
+    reg2.close()
