@@ -270,7 +270,9 @@ int ebsd_second_pass_batch(ebsd_handle* h, const ebsd_pair* pairs, int32_t n,
  * many pairs as the tuned batch (smaller batches use the default rule of
  * ebsd_get_strip_height).  If the environment variable EBSD_TUNE_CACHE
  * named a file when the handle was created, the table is read from it then
- * and written back here (lines "gfx950 <h> <w> <rows>").  Synchronises
+ * and written back here (lines "gfx950 <h> <w> <rows> <two-iteration rows>",
+ * through a temporary file renamed over the cache, so a reader never sees a
+ * partial table).  Synchronises
  * `stream`.  Demons results are unaffected (the strip height only changes the
  * work decomposition). */
 int ebsd_autotune(ebsd_handle* h, const ebsd_pair* pairs, int32_t n, void* stream);
