@@ -238,6 +238,31 @@ def test_registrars_in_two_threads_equal_serial_calls(E, batches):
                 assert np.array_equal(g[key], want[k][key], equal_nan=True), (k, rep, key)
 
 
+@pytest.mark.parametrize("opts", [dict(first_pass=1), dict(bandpass=(1.0, 20.0), background=(1, 0.0)),
+                                  dict(background=(0, 15.0), xcf_passes=2, remap_interp=1)])
+def test_pipelined_options_equal_single_calls(E, batches, opts):
+    """The path's options through the pipeline: the conventional XCF first pass,
+    the pre-filter with the static background correction (the bucket's mean
+    test pattern), the dynamic background with two bilinear remap passes."""
+    p = E.Params(levels=3, iters=(12,) * 3, sigma_px=1.0, roi_size=64, n_roi=20, **opts)
+    print("case: pipeline depth 2, options", opts, flush=True)
+    bs = [(r[:64].contiguous(), t[:64].contiguous()) for r, t in batches]
+    reg = E.Registrar(p)
+    want = [host(reg.register(r, t)) for r, t in bs]
+    torch.cuda.synchronize()
+    reg.close()
+    pl = E.Pipeline(p, depth=2)
+    outs = [pl.submit(r, t) for r, t in bs]
+    pl.wait()
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        got = host(o)
+        assert got.keys() == want[k].keys()
+        for key in got:
+            assert np.array_equal(got[key], want[k][key], equal_nan=True), (k, key)
+    pl.close()
+
+
 def test_pipeline_rejects_bad_batches_at_submission(E, batches):
     pl = E.Pipeline(E.Params(levels=3, iters=(5,) * 3), depth=2)
     r, t = batches[0]
