@@ -380,3 +380,31 @@ def test_tune_cache_file_written_whole_and_read_back(E, tmp_path, monkeypatch):
         assert E.lib().ebsd_get_strip_height(reg2._h, h, w) == ty, (h, w)
     assert reg2.fused_heights(256, 256) == fused
     reg2.close()
+
+
+def test_autotune_on_mixed_sizes_leaves_results_unchanged(E):
+    """An autotune over a batch of 128 x 128 and 256 x 256 pairs (two size
+    buckets, every level of both timed) changes only the work decomposition:
+    the registration afterwards equals an untuned handle's bit for bit."""
+    from paper_1907_05993_amd import synth as S
+    small = E.gen_pairs([S.make_spec(33, i, 128, 128, mis_deg=(0.0, 8.0)) for i in range(48)], labels=False)
+    large = E.gen_pairs([S.make_spec(34, i, 256, 256, mis_deg=(0.0, 8.0)) for i in range(32)], labels=False)
+    refs = [small[0][i] for i in range(48)] + [large[0][i] for i in range(32)]
+    tests = [small[1][i] for i in range(48)] + [large[1][i] for i in range(32)]
+    p = E.Params(levels=3, iters=(20,) * 3, sigma_px=1.0, tol_px=0.05, roi_size=32, n_roi=20)
+    print("case: autotune on 48 x 128^2 + 32 x 256^2", flush=True)
+    plain = E.Registrar(p)
+    a = plain.register(refs, tests)
+    tuned = E.Registrar(p)
+    tuned.autotune(refs, tests)
+    heights = {k: E.lib().ebsd_get_strip_height(tuned._h, *k) for k in [(128, 128), (64, 64), (32, 32), (256, 256)]}
+    print("tuned strip heights:", heights, "two-iteration:", tuned.fused_heights(256, 256), tuned.fused_heights(128, 128),
+          flush=True)
+    b = tuned.register(refs, tests)
+    torch.cuda.synchronize()
+    for k in ("F", "R", "iters", "status", "q1", "q2", "R_finite"):
+        assert np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy()), k
+    for fa, fb in zip(a["field"], b["field"]):
+        assert torch.equal(fa, fb)
+    plain.close()
+    tuned.close()
